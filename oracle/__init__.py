@@ -1,0 +1,6 @@
+"""FP64 CPU oracle of the differentiable splatting path (test infrastructure only).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the HIP library.
+"""
+from .oracle import *  # noqa: F401,F403
