@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Forward+backward throughput of the differentiable splatting path on one MI355X.
+
+Workload (the batched-uneven configuration): 64 views (2 cameras x 32 frames) of
+1408x376 along a 300 m synthetic drive anchored at 2,000,000 LiDAR Gaussians,
+visible counts varying strongly per view.  One step = pose interpolation ->
+projection -> tile binning + radix sort -> forward compositing -> L1 loss ->
+backward compositing -> projection adjoint -> pose adjoint, for all 64 views, with
+inputs resident in HBM.  The targets are the same scene rendered at a slightly
+different calibration, so every covered pixel carries a loss gradient.
+
+Prints ONE JSON line: Mpixels/s (fwd+bwd) of the batched persistent path, with
+the per-view plain launch, the hipGraph replay, the ALU roofline of the dominant
+render kernel (HIP events around its launches in the timed region) and the FP64
+CPU oracle on a one-view sample as context.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# ALU roofline (see the design notes): FP32 flops per unit, FMA = 2.
+FWD_FLOP_PER_EVAL, FWD_FLOP_PER_BLEND = 13, 10
+BWD_FLOP_PER_EVAL, BWD_FLOP_PER_CONTRIB = 13, 50
+# 256 CUs x 64 FP32 lanes x 2 flops (FMA) x 2.4 GHz, without packed-FP32 issue
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--per-view-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--small", action="store_true", help="tiny smoke workload instead of the 64-view drive")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding of this "
+              "path is a design note, not a measured configuration.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2403_11577_amd import pipeline as pl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda"
+    t0 = time.time()
+    if args.small:
+        scene = synth.small_drive(0, n_points=3000, W=256, H=96, f=120.0, n_frames=4)
+        workload = "small_drive_8v_3k_256x96"
+    else:
+        scene = synth.batched64(seed=0)
+        workload = "batched_uneven_64v_2M_1408x376"
+    log(f"[bench] scene {workload}: {scene.gauss.n} Gaussians, {scene.views.n} views, "
+        f"{time.time() - t0:.1f}s to generate")
+    ds = pl.DeviceScene.from_scene(scene, device=dev)
+    V, W, H = ds.n_views, ds.W, ds.H
+    xi = torch.zeros((ds.n_cams, 6), dtype=torch.float64, device=dev)
+    delta = torch.zeros(ds.n_cams, dtype=torch.float64, device=dev)
+    tw, th = (int(x) for x in args.tile.split("x"))
+    settings = pl.make_settings(tile=(tw, th), batch=args.batch, persistent=True)
+
+    # targets: the scene at a slightly different calibration (untimed)
+    xi_t = xi.clone()
+    xi_t[:, 3:] = 0.01   # ~0.6 degree
+    xi_t[:, :3] = 0.05
+    fr0 = pl.fit_frame(ds, xi_t, delta, settings)
+    img_t, _, _ = pl.forward(fr0, ds, xi_t, delta)
+    targets = img_t.clone()
+    del fr0
+    torch.cuda.synchronize()
+
+    step = pl.BatchedStep(ds, xi, delta, targets, settings)
+    step.run()
+    torch.cuda.synchronize()
+    ns, ni = step.fr.counts()
+    view_off = step.fr.buf("view_off", torch.int32, V + 1).cpu().numpy().astype(np.int64)
+    vis = np.diff(view_off)
+    log(f"[bench] slots {ns}, instances {ni}, visible/view min {vis.min()} median {int(np.median(vis))} "
+        f"max {vis.max()}")
+
+    for _ in range(args.warmup):
+        step.run()
+    torch.cuda.synchronize()
+
+    # ---- timed region: K eager steps, HIP events around the two render kernels ----
+    evs = [{"fwd": (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)),
+            "bwd": (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))}
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        step.events = evs[k]
+        step.run()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    step.events = None
+    ms_step = 1e3 * t_total / args.steps
+    fwd_ms = float(np.mean([e["fwd"][0].elapsed_time(e["fwd"][1]) for e in evs]))
+    bwd_ms = float(np.mean([e["bwd"][0].elapsed_time(e["bwd"][1]) for e in evs]))
+    mpx = V * W * H * args.steps / t_total / 1e6
+    log(f"[bench] batched: {ms_step:.3f} ms/step, {mpx:.1f} Mpx/s; render_fwd {fwd_ms:.3f} ms, "
+        f"render_bwd {bwd_ms:.3f} ms")
+    loss = float(step.loss.item())
+
+    # ---- roofline of the dominant render kernel (pair counts from the instrumented variant) ----
+    stt = step.stats()
+    fwd_flop = FWD_FLOP_PER_EVAL * stt["fwd_eval"] + FWD_FLOP_PER_BLEND * stt["fwd_blend"]
+    bwd_flop = BWD_FLOP_PER_EVAL * stt["bwd_eval"] + BWD_FLOP_PER_CONTRIB * stt["bwd_contrib"]
+    if bwd_ms >= fwd_ms:
+        kern, dur_ms, flop = "render_bwd", bwd_ms, bwd_flop
+    else:
+        kern, dur_ms, flop = "render_fwd", fwd_ms, fwd_flop
+    achieved = flop / (dur_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": kern, "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
+                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
+                "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
+                "fwd_tflops": round(fwd_flop / (fwd_ms * 1e-3) / 1e12, 3),
+                "bwd_tflops": round(bwd_flop / (bwd_ms * 1e-3) / 1e12, 3), "pairs": stt}
+
+    # ---- hipGraph replay of the same step ----
+    graph = None
+    if not args.no_graph:
+        step.capture()
+        for _ in range(args.warmup):
+            step.replay()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            step.replay()
+        torch.cuda.synchronize()
+        g_ms = 1e3 * (time.perf_counter() - tg) / args.steps
+        graph = {"ms_per_step": round(g_ms, 3), "mpx_s": round(V * W * H / (g_ms * 1e-3) / 1e6, 2)}
+        log(f"[bench] graph replay: {g_ms:.3f} ms/step")
+
+    # ---- per-view plain launch (same kernels, one view at a time, host syncs) ----
+    per_view = None
+    if not args.no_per_view:
+        pv = pl.PerViewPlain(ds, xi, delta, settings)
+        gr = pl.alloc_grads(ds)
+        pv.step(xi, delta, targets, gr)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for _ in range(args.per_view_steps):
+            pl.zero_grads(gr)
+            pv.step(xi, delta, targets, gr)
+        torch.cuda.synchronize()
+        p_ms = 1e3 * (time.perf_counter() - tp) / args.per_view_steps
+        per_view = {"ms_per_step": round(p_ms, 3), "mpx_s": round(V * W * H / (p_ms * 1e-3) / 1e6, 2)}
+        log(f"[bench] per-view plain: {p_ms:.3f} ms/step")
+        del pv
+
+    # ---- FP64 CPU oracle on a bounded sample: the median-visible view, fwd + bwd ----
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nthreads = min(16, os.cpu_count() or 1)
+        os.environ.setdefault("OMP_NUM_THREADS", str(nthreads))
+        v = int(np.argsort(vis)[len(vis) // 2])
+        sub = synth.Views(scene.views.cam[v:v + 1], scene.views.t[v:v + 1])
+        w2c, _, _ = oracle.pose(scene.traj, scene.rig, np.zeros((2, 6)), np.zeros(2), sub)
+        intr = oracle.view_intr(scene.rig, sub)
+        tc = time.perf_counter()
+        r = oracle.render(scene.gauss, w2c, intr, W, H)
+        tgt = targets[v:v + 1].cpu().numpy().astype(np.float64)
+        _, dimg = oracle.l1_loss(r["img"], tgt)
+        oracle.grad(scene.gauss, w2c, intr, W, H, dimg)
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": round(W * H / tcpu / 1e6, 4), "unit": "Mpixels/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": f"view {v} of {V} (median visible, {int(vis[v])} Gaussians), "
+                                           f"fwd+bwd, {W}x{H}, {tcpu:.1f}s"}
+        log(f"[bench] cpu oracle: {tcpu:.1f}s for one view")
+
+    out = {
+        "metric": "fwd+bwd Mpixels/s (batched persistent, 64 views)",
+        "value": round(mpx, 2),
+        "unit": "Mpixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "views": V, "width": W, "height": H, "gaussians": int(scene.gauss.n),
+                   "tile": args.tile, "batch": args.batch, "persistent": True,
+                   "visible_per_view": {"min": int(vis.min()), "median": int(np.median(vis)), "max": int(vis.max())}},
+        "loss": loss,
+        "graph": graph,
+        "per_view_plain": per_view,
+        "speedup_vs_per_view": (round(per_view["ms_per_step"] / ms_step, 3) if per_view else None),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

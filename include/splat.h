@@ -1,0 +1,272 @@
+/*
+ * splat.h -- C ABI of the MI355X (gfx950) differentiable splatting library.
+ *
+ * The library renders LiDAR-anchored 3-D Gaussians into many camera views and
+ * back-propagates an image-space loss gradient to the Gaussian parameters, to
+ * the camera->LiDAR extrinsic correction and to the per-camera time offset, as
+ * the calibration method of 3DGS-Calib (arXiv 2403.11577) requires.
+ *
+ * Call order of one calibration step (every call is asynchronous on `stream`):
+ *   splat_pose_interp_fwd -> splat_project -> splat_bin_sort -> splat_render_fwd
+ *   (loss gradient by the caller) -> splat_render_bwd -> splat_project_bwd
+ *   -> splat_pose_interp_bwd
+ *
+ * Memory.  Every pointer argument that is not a `const splat_plan *` or a
+ * `const splat_gaussians *` / `const splat_settings *` (host structs) is a
+ * DEVICE pointer owned by the caller.  The library never allocates, frees,
+ * copies to the host or synchronises, so a whole step can be captured in a HIP
+ * graph.  Intermediate per-step state lives in one caller-allocated device
+ * workspace `ws` whose size and internal layout `splat_plan_make` computes.
+ *
+ * Errors.  Arguments are checked on the host before anything is launched;
+ * a bad argument returns a negative code, launches nothing, and leaves a text
+ * message for splat_last_error() (thread local).  Data-dependent conditions
+ * found on the device are OR-ed into the status word at ws + plan->off_status:
+ *   SPLAT_ST_CAPACITY  slot or instance capacity exceeded (outputs undefined;
+ *                      grow the capacities and run again),
+ *   SPLAT_ST_NONFINITE a Gaussian with a non-finite parameter (culled),
+ *   SPLAT_ST_DEGENERATE a Gaussian with |q| < 1e-12 (culled),
+ *   SPLAT_ST_EXTRAPOLATED a camera time outside the trajectory (informational).
+ * The library never clears the status word; the caller zeroes it when it wants.
+ *
+ * Threading.  Re-entrant; no global mutable state except the thread-local
+ * error text.  Calls that share a workspace must be ordered on one stream.
+ */
+#ifndef SPLAT_H
+#define SPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define SPLAT_API __attribute__((visibility("default")))
+#else
+#define SPLAT_API
+#endif
+
+#define SPLAT_OK 0
+#define SPLAT_EINVAL (-1)       /* invalid argument: nothing launched */
+#define SPLAT_EUNSUPPORTED (-2) /* valid but unsupported (e.g. key wider than 64 bits) */
+#define SPLAT_ELAUNCH (-3)      /* the HIP runtime refused a launch */
+
+#define SPLAT_ST_CAPACITY 1u
+#define SPLAT_ST_NONFINITE 2u
+#define SPLAT_ST_DEGENERATE 4u
+#define SPLAT_ST_EXTRAPOLATED 8u
+
+/*
+ * Renderer constants.  The paper fixes none of them (it defers the splatting
+ * function to EWA splatting and the loss to the original 3DGS work); these are
+ * the library's readings, identical to the reference renderer's defaults:
+ *   near_z 0.2 m, far_z 256 m   depth window on the FP32 depth key (culls)
+ *   eps2d 0.3 px^2               screen-space low-pass added to the 2-D covariance
+ *   alpha_min 1/255, alpha_max 0.99, t_min 1e-4   compositing thresholds
+ *   guard 0.15                   Jacobian guard band, fraction of the image size
+ *   bg                           background colour
+ *   pad_px 0.1, pad_rel 1e-4     footprint padding (absolute px, relative)
+ * Launch shape (results do not depend on it):
+ *   tile_w x tile_h in {8x8, 16x16, 16x32, 32x16}; batch = Gaussians per LDS
+ *   batch in [16, 256], multiple of 16; persistent = 1 runs the render kernels
+ *   as persistent workgroups over a cost-ordered (view, tile) queue, 0 launches
+ *   one workgroup per (view, tile).
+ */
+typedef struct splat_settings {
+    double near_z, far_z, eps2d, alpha_min, alpha_max, t_min, guard;
+    double bg[3];
+    double pad_px, pad_rel;
+    int32_t tile_w, tile_h, batch, persistent;
+} splat_settings;
+
+/* Gaussian parameters: device SoA planes of length n (float32).
+ * mean[3][n] world position (fixed LiDAR points, Sec. III-B), quat[4][n]
+ * rotation (w,x,y,z; normalised inside), scale[3][n] (> 0), opacity[n] in (0,1)
+ * (activated), color[3][n] view-independent RGB (Sec. III-B). */
+typedef struct splat_gaussians {
+    const float *mean, *quat, *scale, *opacity, *color;
+    int64_t n;
+} splat_gaussians;
+
+/* Workspace layout for one (settings, views, Gaussians, image, capacity) shape.
+ * All off_* are byte offsets into the workspace; every region is 256-byte
+ * aligned.  Filled by splat_plan_make; treat as read-only. */
+typedef struct splat_plan {
+    splat_settings s;
+    int32_t n_views, width, height;
+    int32_t tiles_x, tiles_y, tiles_per_view;
+    int32_t depth_bits, tile_bits;   /* sort key = (view*T + tile) << depth_bits | depth */
+    int32_t n_blocks_proj;           /* project blocks per view (256 Gaussians each) */
+    int32_t n_sort_blocks;           /* radix-sort partitions */
+    int64_t n_gauss, slot_cap, inst_cap;
+    size_t ws_bytes;
+    size_t off_status;      /* u32                                                      */
+    size_t off_counts;      /* u32[8]: 0 slots, 1 instances, 2 work counter, 3..7 spare  */
+    size_t off_view_off;    /* u32[V+1] first slot of every view                          */
+    size_t off_blockcnt;    /* u32[V*n_blocks_proj] visible count per project block      */
+    size_t off_rec;         /* float4[3][slot_cap]: (mx,my,lx,ly) (a,b,c,o) (r,g,b,depth) */
+    size_t off_meta;        /* int2[slot_cap]: (Gaussian id, view)                       */
+    size_t off_rect;        /* u16x4[slot_cap]: tile rect (x0,x1,y0,y1) inclusive         */
+    size_t off_ntiles;      /* u32[slot_cap+1]: tiles per slot, scanned to offsets       */
+    size_t off_keys;        /* u64[2][inst_cap]                                          */
+    size_t off_vals;        /* u32[2][inst_cap]                                          */
+    size_t off_ranges;      /* u32x2[V*T]: [start,end) of every (view, tile) list         */
+    size_t off_queue;       /* u32[V*T]: (view, tile) work items, most expensive first    */
+    size_t off_hist;        /* u32[256*n_sort_blocks + 1024] radix / queue histograms     */
+    size_t off_scan;        /* u32[scan partials]                                        */
+    size_t off_grad2d;      /* float[slot_cap][9]: d(mu x,y; conic a,b,c; o; r,g,b)       */
+    int32_t sorted_buf;     /* which of the two key/value buffers holds the sorted result */
+    int32_t reserved;
+} splat_plan;
+
+/* Fill `s` with the default settings listed above (16x16 tiles, batch 64,
+ * persistent). */
+SPLAT_API void splat_default_settings(splat_settings *s);
+
+/*
+ * Compute the workspace layout.  n_views >= 1, n_gauss >= 0, width and height
+ * in [1, 16384], slot_cap >= 1 (visible (view, Gaussian) pairs, at most
+ * n_views*n_gauss is ever needed), inst_cap >= 1 ((Gaussian, tile) pairs);
+ * both capacities below 2^31.  Returns SPLAT_EUNSUPPORTED when the sort key
+ * (tile bits + depth bits) would exceed 64 bits.
+ */
+SPLAT_API int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, int32_t width,
+                    int32_t height, int64_t slot_cap, int64_t inst_cap, splat_plan *plan);
+
+/*
+ * Camera poses (paper Sec. III-A, Eq. 1 and Eq. 2).  The LiDAR trajectory is
+ * the piecewise interpolation of K >= 2 timestamped poses: linear in the
+ * translation and SLERP in the rotation (shortest arc); the camera pose of view
+ * v at camera time t_v is T_L(t_v + delta_c) * T_c with the camera->LiDAR
+ * extrinsic T_c = (R0_c Exp(phi_c), t0_c + rho_c), and the output is its
+ * inverse (world->camera).  Segments are left-closed; times before the first
+ * or after the last knot extrapolate the end segment and set
+ * SPLAT_ST_EXTRAPOLATED.
+ *   knot_t[K] (strictly increasing, seconds), knot_q[K][4] (w,x,y,z, LiDAR->
+ *   world), knot_p[K][3]; R0[C][9] row-major, t0[C][3]; xi[C][6] = (rho, phi);
+ *   delta[C] seconds; view_cam[V] in [0,C); view_t[V] seconds.
+ *   Output w2c[V][12] float64, row-major [W | w] with x_cam = W x_world + w.
+ * Monotonicity of knot_t is the caller's contract (checked by the binding).
+ */
+SPLAT_API int splat_pose_interp_fwd(int32_t K, const double *knot_t, const double *knot_q,
+                          const double *knot_p, int32_t C, const double *R0, const double *t0,
+                          const double *xi, const double *delta, int32_t V,
+                          const int32_t *view_cam, const double *view_t, double *w2c,
+                          uint32_t *status, void *stream);
+
+/*
+ * Adjoint of splat_pose_interp_fwd: given dL/dw2c[V][12] (float64) it ADDS
+ * dL/dxi[C][6] and dL/ddelta[C] (float64, caller zeroes).  The rotation part
+ * uses the right Jacobian of SO(3); d/ddelta goes through the interpolation
+ * (translation velocity of the segment and its angular velocity).  Views of
+ * one camera are summed in view order (deterministic).
+ */
+SPLAT_API int splat_pose_interp_bwd(int32_t K, const double *knot_t, const double *knot_q,
+                          const double *knot_p, int32_t C, const double *R0, const double *t0,
+                          const double *xi, const double *delta, int32_t V,
+                          const int32_t *view_cam, const double *view_t, const double *dw2c,
+                          double *dxi, double *ddelta, void *stream);
+
+/*
+ * Projection (paper Eq. 2 and Eq. 3 folded into W Sigma W^T, then EWA):
+ * for every (view, Gaussian) the float32 depth key depth32 =
+ * fma(W20, x, fma(W21, y, fma(W22, z, w2))) on float32-rounded row 2 of w2c;
+ * cull when depth32 <= near_z or > far_z, opacity < alpha_min, |q| < 1e-12, a
+ * non-finite parameter, or an empty on-screen footprint; otherwise (in float64)
+ * the camera-frame covariance, the perspective Jacobian with the guard band,
+ * the 2-D covariance + eps2d, its inverse (conic), the pixel mean and the
+ * opacity-aware footprint (alpha >= alpha_min inside an axis-aligned box of
+ * half-widths sqrt(2 ln(o/alpha_min) Sigma2_ii), padded).  Visible pairs are
+ * compacted per view in Gaussian order into slots.
+ *   g: Gaussians (device planes); w2c[V][12] float64 (device);
+ *   intr[V][4] float64 (fx, fy, cx, cy) per view (device).
+ * Writes counts, view_off, rec, meta, rect, ntiles in the workspace.
+ */
+SPLAT_API int splat_project(const splat_plan *plan, void *ws, const splat_gaussians *g, const double *w2c,
+                  const double *intr, void *stream);
+
+/*
+ * Tile binning: one instance per (slot, covered tile) with key
+ * ((view*T + tile) << depth_bits) | (bits(depth32) - bits(near_z)) and value =
+ * slot, emitted in (view, Gaussian, tile row-major) order, then a stable LSD
+ * radix sort on the used key bits, so every tile list is in (depth32, Gaussian
+ * id) order.  Writes the sorted values, per-(view, tile) ranges and the
+ * cost-ordered work queue in the workspace; plan->sorted_buf names the buffer
+ * that holds the sorted result (it is a function of the plan only).
+ */
+SPLAT_API int splat_bin_sort(const splat_plan *plan, void *ws, void *stream);
+
+/*
+ * Forward compositing (the splatting function Phi of Eq. 5): every pixel
+ * (sampled at its centre, +0.5) walks its tile list front to back, alpha =
+ * min(alpha_max, o exp(-d^T Q d / 2)), skips alpha < alpha_min, stops before a
+ * blend that would take T below t_min, and accumulates C += c alpha T.
+ * Outputs (device, float32/int32): img[V][3][H][W] = C + T bg,
+ * T_final[V][H][W], last_pos[V][H][W] = instance index of the last blended
+ * Gaussian (into the sorted value buffer) or -1.
+ */
+SPLAT_API int splat_render_fwd(const splat_plan *plan, void *ws, float *img, float *T_final,
+                     int32_t *last_pos, void *stream);
+
+/*
+ * Backward compositing (the adjoint of splat_render_fwd): every pixel walks
+ * its list in reverse from last_pos, recovering T by division and the suffix
+ * colour sum, and accumulates d(loss)/d(mean2d, conic, opacity, colour) of
+ * every slot with wave-reduced atomics into the workspace gradient buffer
+ * (zeroed here first).  dL_dimg[V][3][H][W], T_final and last_pos are the
+ * caller's (last two from splat_render_fwd).
+ */
+SPLAT_API int splat_render_bwd(const splat_plan *plan, void *ws, const float *dL_dimg, const float *T_final,
+                     const int32_t *last_pos, void *stream);
+
+/*
+ * Adjoint of splat_project: from the slot gradients it ADDS d(loss)/d quat,
+ * scale, opacity, colour and (if dmean != NULL) mean of every Gaussian
+ * (float32 device planes of the parameter shapes; the caller zeroes them), and
+ * ADDS d(loss)/d w2c[V][12] (float64, reduced in float64; caller zeroes).
+ * g, w2c and intr must be the ones given to splat_project.
+ */
+SPLAT_API int splat_project_bwd(const splat_plan *plan, void *ws, const splat_gaussians *g,
+                      const double *w2c, const double *intr, float *dquat, float *dscale,
+                      float *dopacity, float *dcolor, float *dmean, double *dw2c, void *stream);
+
+/*
+ * The L1 term of the photometric loss (paper Eq. 4): with N = V*3*H*W,
+ * dL_dimg = sign(img - target)/N (sign(0) = 0) and *loss += sum |img - target|/N
+ * (float64, caller zeroes it; NULL to skip).  img, target, dL_dimg are
+ * [V][3][H][W] float32 device arrays; mask (nullable) is uint8 [V][H][W] and
+ * removes the pixels where it is non-zero (e.g. outside a region of interest).
+ */
+SPLAT_API int splat_l1_loss_grad(const float *img, const float *target, const uint8_t *mask, int32_t n_views,
+                                 int32_t width, int32_t height, float *dL_dimg, double *loss, void *stream);
+
+/*
+ * Instrumented variants of splat_render_fwd / splat_render_bwd: identical
+ * outputs, plus pair counters ADDED into stats (uint64 device array, caller
+ * zeroes): [0] forward evaluated (pixel, Gaussian) pairs, [1] forward blended
+ * pairs, [2] backward evaluated pairs, [3] backward contributing pairs,
+ * [4] backward wave-reduced atomic groups (9 atomics each).  Used to turn
+ * kernel durations into achieved work; slower than the plain calls.
+ */
+SPLAT_API int splat_render_fwd_stats(const splat_plan *plan, void *ws, float *img, float *T_final,
+                                     int32_t *last_pos, uint64_t *stats, void *stream);
+SPLAT_API int splat_render_bwd_stats(const splat_plan *plan, void *ws, const float *dL_dimg,
+                                     const float *T_final, const int32_t *last_pos, uint64_t *stats,
+                                     void *stream);
+
+/* Text of the last synchronous error on this thread ("" if none). */
+SPLAT_API const char *splat_last_error(void);
+
+/* Library version string. */
+SPLAT_API const char *splat_version(void);
+
+/* sizeof of the ABI structs, for bindings to check their mirrors:
+ * which = 0 splat_settings, 1 splat_gaussians, 2 splat_plan; else 0. */
+SPLAT_API size_t splat_struct_size(int32_t which);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPLAT_H */

@@ -1,0 +1,192 @@
+"""ctypes binding of libsplat.so with the names of include/splat.h.
+
+Argument marshalling only: every function takes torch device tensors (or ints
+for sizes), passes their data pointers and the current HIP stream to the C ABI
+and raises on a negative return code.  No arithmetic of the method happens here.
+The library is loaded from this package directory; if it is missing the import
+fails loudly (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsplat.so")
+
+ST_CAPACITY, ST_NONFINITE, ST_DEGENERATE, ST_EXTRAPOLATED = 1, 2, 4, 8
+
+
+class SplatError(RuntimeError):
+    pass
+
+
+class splat_settings(C.Structure):
+    _fields_ = [("near_z", C.c_double), ("far_z", C.c_double), ("eps2d", C.c_double),
+                ("alpha_min", C.c_double), ("alpha_max", C.c_double), ("t_min", C.c_double),
+                ("guard", C.c_double), ("bg", C.c_double * 3), ("pad_px", C.c_double),
+                ("pad_rel", C.c_double), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
+                ("batch", C.c_int32), ("persistent", C.c_int32)]
+
+
+class splat_gaussians(C.Structure):
+    _fields_ = [("mean", C.c_void_p), ("quat", C.c_void_p), ("scale", C.c_void_p),
+                ("opacity", C.c_void_p), ("color", C.c_void_p), ("n", C.c_int64)]
+
+
+_PLAN_OFFS = ["ws_bytes", "off_status", "off_counts", "off_view_off", "off_blockcnt", "off_rec",
+              "off_meta", "off_rect", "off_ntiles", "off_keys", "off_vals", "off_ranges",
+              "off_queue", "off_hist", "off_scan", "off_grad2d"]
+
+
+class splat_plan(C.Structure):
+    _fields_ = ([("s", splat_settings)] +
+                [(n, C.c_int32) for n in ("n_views", "width", "height", "tiles_x", "tiles_y",
+                                          "tiles_per_view", "depth_bits", "tile_bits",
+                                          "n_blocks_proj", "n_sort_blocks")] +
+                [(n, C.c_int64) for n in ("n_gauss", "slot_cap", "inst_cap")] +
+                [(n, C.c_size_t) for n in _PLAN_OFFS] +
+                [("sorted_buf", C.c_int32), ("reserved", C.c_int32)])
+
+
+_lib = None
+
+
+def lib():
+    """Load libsplat.so once and declare the signatures of include/splat.h."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SplatError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                         "or python -m paper_2403_11577_amd.build")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+    L.splat_default_settings.argtypes = [C.POINTER(splat_settings)]
+    L.splat_default_settings.restype = None
+    L.splat_plan_make.argtypes = [C.POINTER(splat_settings), I32, I64, I32, I32, I64, I64,
+                                  C.POINTER(splat_plan)]
+    L.splat_pose_interp_fwd.argtypes = [I32, P, P, P, I32, P, P, P, P, I32, P, P, P, P, P]
+    L.splat_pose_interp_bwd.argtypes = [I32, P, P, P, I32, P, P, P, P, I32, P, P, P, P, P, P]
+    L.splat_project.argtypes = [C.POINTER(splat_plan), P, C.POINTER(splat_gaussians), P, P, P]
+    L.splat_bin_sort.argtypes = [C.POINTER(splat_plan), P, P]
+    L.splat_render_fwd.argtypes = [C.POINTER(splat_plan), P, P, P, P, P]
+    L.splat_render_bwd.argtypes = [C.POINTER(splat_plan), P, P, P, P, P]
+    L.splat_project_bwd.argtypes = [C.POINTER(splat_plan), P, C.POINTER(splat_gaussians), P, P,
+                                    P, P, P, P, P, P, P]
+    L.splat_render_fwd_stats.argtypes = [C.POINTER(splat_plan), P, P, P, P, P, P]
+    L.splat_render_bwd_stats.argtypes = [C.POINTER(splat_plan), P, P, P, P, P, P]
+    L.splat_l1_loss_grad.argtypes = [P, P, P, I32, I32, I32, P, P, P]
+    L.splat_last_error.restype = C.c_char_p
+    L.splat_version.restype = C.c_char_p
+    L.splat_struct_size.argtypes = [I32]
+    L.splat_struct_size.restype = C.c_size_t
+    for w, st in ((0, splat_settings), (1, splat_gaussians), (2, splat_plan)):
+        if L.splat_struct_size(w) != C.sizeof(st):
+            raise SplatError(f"ABI mismatch: {st.__name__} is {L.splat_struct_size(w)} bytes in the "
+                             f"library, {C.sizeof(st)} in the binding")
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().splat_last_error().decode()
+        raise SplatError(f"{what} failed ({rc}): {msg}")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def default_settings(**overrides) -> splat_settings:
+    s = splat_settings()
+    lib().splat_default_settings(C.byref(s))
+    for k, v in overrides.items():
+        if k == "bg":
+            s.bg = (C.c_double * 3)(*v)
+        else:
+            setattr(s, k, v)
+    return s
+
+
+def splat_plan_make(settings: splat_settings, n_views: int, n_gauss: int, width: int, height: int,
+                    slot_cap: int, inst_cap: int) -> splat_plan:
+    p = splat_plan()
+    _check(lib().splat_plan_make(C.byref(settings), int(n_views), int(n_gauss), int(width),
+                                 int(height), int(slot_cap), int(inst_cap), C.byref(p)),
+           "splat_plan_make")
+    return p
+
+
+def gaussians_struct(mean, quat, scale, opacity, color) -> splat_gaussians:
+    return splat_gaussians(_ptr(mean), _ptr(quat), _ptr(scale), _ptr(opacity), _ptr(color),
+                           int(opacity.shape[0]))
+
+
+def splat_pose_interp_fwd(knot_t, knot_q, knot_p, R0, t0, xi, delta, view_cam, view_t, w2c,
+                          status=None, stream=None):
+    _check(lib().splat_pose_interp_fwd(int(knot_t.shape[0]), _ptr(knot_t), _ptr(knot_q), _ptr(knot_p),
+                                       int(R0.shape[0]), _ptr(R0), _ptr(t0), _ptr(xi), _ptr(delta),
+                                       int(view_cam.shape[0]), _ptr(view_cam), _ptr(view_t), _ptr(w2c),
+                                       _ptr(status), _stream(stream)), "splat_pose_interp_fwd")
+
+
+def splat_pose_interp_bwd(knot_t, knot_q, knot_p, R0, t0, xi, delta, view_cam, view_t, dw2c, dxi,
+                          ddelta, stream=None):
+    _check(lib().splat_pose_interp_bwd(int(knot_t.shape[0]), _ptr(knot_t), _ptr(knot_q), _ptr(knot_p),
+                                       int(R0.shape[0]), _ptr(R0), _ptr(t0), _ptr(xi), _ptr(delta),
+                                       int(view_cam.shape[0]), _ptr(view_cam), _ptr(view_t), _ptr(dw2c),
+                                       _ptr(dxi), _ptr(ddelta), _stream(stream)), "splat_pose_interp_bwd")
+
+
+def splat_project(plan, ws, gauss: splat_gaussians, w2c, intr, stream=None):
+    _check(lib().splat_project(C.byref(plan), _ptr(ws), C.byref(gauss), _ptr(w2c), _ptr(intr),
+                               _stream(stream)), "splat_project")
+
+
+def splat_bin_sort(plan, ws, stream=None):
+    _check(lib().splat_bin_sort(C.byref(plan), _ptr(ws), _stream(stream)), "splat_bin_sort")
+
+
+def splat_render_fwd(plan, ws, img, T_final, last_pos, stream=None):
+    _check(lib().splat_render_fwd(C.byref(plan), _ptr(ws), _ptr(img), _ptr(T_final), _ptr(last_pos),
+                                  _stream(stream)), "splat_render_fwd")
+
+
+def splat_render_bwd(plan, ws, dL_dimg, T_final, last_pos, stream=None):
+    _check(lib().splat_render_bwd(C.byref(plan), _ptr(ws), _ptr(dL_dimg), _ptr(T_final), _ptr(last_pos),
+                                  _stream(stream)), "splat_render_bwd")
+
+
+def splat_project_bwd(plan, ws, gauss: splat_gaussians, w2c, intr, dquat, dscale, dopacity, dcolor,
+                      dmean, dw2c, stream=None):
+    _check(lib().splat_project_bwd(C.byref(plan), _ptr(ws), C.byref(gauss), _ptr(w2c), _ptr(intr),
+                                   _ptr(dquat), _ptr(dscale), _ptr(dopacity), _ptr(dcolor), _ptr(dmean),
+                                   _ptr(dw2c), _stream(stream)), "splat_project_bwd")
+
+
+def splat_render_fwd_stats(plan, ws, img, T_final, last_pos, stats, stream=None):
+    _check(lib().splat_render_fwd_stats(C.byref(plan), _ptr(ws), _ptr(img), _ptr(T_final), _ptr(last_pos),
+                                        _ptr(stats), _stream(stream)), "splat_render_fwd_stats")
+
+
+def splat_render_bwd_stats(plan, ws, dL_dimg, T_final, last_pos, stats, stream=None):
+    _check(lib().splat_render_bwd_stats(C.byref(plan), _ptr(ws), _ptr(dL_dimg), _ptr(T_final), _ptr(last_pos),
+                                        _ptr(stats), _stream(stream)), "splat_render_bwd_stats")
+
+
+def splat_l1_loss_grad(img, target, mask, dL_dimg, loss=None, stream=None):
+    V, _, H, W = img.shape
+    _check(lib().splat_l1_loss_grad(_ptr(img), _ptr(target), _ptr(mask), int(V), int(W), int(H), _ptr(dL_dimg),
+                                    _ptr(loss), _stream(stream)), "splat_l1_loss_grad")
+
+
+def splat_version() -> str:
+    return lib().splat_version().decode()

@@ -1,0 +1,324 @@
+// api.hip -- the C ABI of the splatting library: host-side argument checks, the
+// workspace plan, and dispatch to the kernels.  Nothing here allocates device
+// memory or synchronises; every check happens before the first launch.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+
+#include "common.hpp"
+
+namespace splat {
+
+static thread_local char g_err[512];
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+int launch_status(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("%s: HIP launch failed: %s", what, hipGetErrorString(e));
+        return SPLAT_ELAUNCH;
+    }
+    return SPLAT_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int bit_length(uint64_t x) {
+    int b = 0;
+    while (x) {
+        ++b;
+        x >>= 1;
+    }
+    return b;
+}
+
+static uint32_t fbits(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    return u;
+}
+
+static bool tile_supported(int tw, int th) {
+    return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 16 && th == 32) || (tw == 32 && th == 16);
+}
+
+static int check_settings(const splat_settings *s) {
+    if (!s) { set_error("settings is NULL"); return SPLAT_EINVAL; }
+    if (!(s->near_z > 0.0) || !(s->far_z > s->near_z) || !std::isfinite(s->far_z)) {
+        set_error("need 0 < near_z < far_z < inf (got %g, %g)", s->near_z, s->far_z); return SPLAT_EINVAL;
+    }
+    if (!(s->alpha_min > 0.0 && s->alpha_min < 1.0) || !(s->alpha_max > s->alpha_min && s->alpha_max < 1.0)) {
+        set_error("need 0 < alpha_min < alpha_max < 1 (got %g, %g)", s->alpha_min, s->alpha_max); return SPLAT_EINVAL;
+    }
+    if (!(s->t_min > 0.0 && s->t_min < 1.0)) { set_error("need 0 < t_min < 1 (got %g)", s->t_min); return SPLAT_EINVAL; }
+    if (!(s->eps2d >= 0.0) || !(s->guard >= 0.0) || !(s->pad_px >= 0.0) || !(s->pad_rel >= 0.0)) {
+        set_error("eps2d, guard, pad_px and pad_rel must be >= 0"); return SPLAT_EINVAL;
+    }
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(s->bg[i])) { set_error("background must be finite"); return SPLAT_EINVAL; }
+    if (!tile_supported(s->tile_w, s->tile_h)) {
+        set_error("unsupported tile %dx%d (8x8, 16x16, 16x32, 32x16)", s->tile_w, s->tile_h); return SPLAT_EINVAL;
+    }
+    if (s->batch < 16 || s->batch > 256 || (s->batch % 16)) {
+        set_error("batch must be a multiple of 16 in [16, 256] (got %d)", s->batch); return SPLAT_EINVAL;
+    }
+    if (s->persistent != 0 && s->persistent != 1) { set_error("persistent must be 0 or 1"); return SPLAT_EINVAL; }
+    return SPLAT_OK;
+}
+
+static int check_plan(const splat_plan *p, const void *ws, const char *who) {
+    if (!p) { set_error("%s: plan is NULL", who); return SPLAT_EINVAL; }
+    if (!ws) { set_error("%s: workspace is NULL", who); return SPLAT_EINVAL; }
+    if (p->n_views < 1 || p->ws_bytes == 0 || p->tiles_per_view < 1 || check_settings(&p->s)) {
+        set_error("%s: plan is not initialised by splat_plan_make", who); return SPLAT_EINVAL;
+    }
+    return SPLAT_OK;
+}
+
+static int check_gauss(const splat_gaussians *g, const splat_plan *p, const char *who) {
+    if (!g) { set_error("%s: gaussians is NULL", who); return SPLAT_EINVAL; }
+    if (g->n != p->n_gauss) {
+        set_error("%s: %lld Gaussians but the plan was made for %lld", who, (long long)g->n, (long long)p->n_gauss);
+        return SPLAT_EINVAL;
+    }
+    if (g->n > 0 && (!g->mean || !g->quat || !g->scale || !g->opacity || !g->color)) {
+        set_error("%s: a Gaussian parameter plane is NULL", who); return SPLAT_EINVAL;
+    }
+    return SPLAT_OK;
+}
+
+static int check_pose_args(int32_t K, const double *kt, const double *kq, const double *kp, int32_t C,
+                           const double *R0, const double *t0, const double *xi, const double *delta,
+                           int32_t V, const int32_t *vcam, const double *vt, const char *who) {
+    if (K < 2) { set_error("%s: need at least 2 trajectory knots (got %d)", who, K); return SPLAT_EINVAL; }
+    if (C < 1 || V < 1) { set_error("%s: need C >= 1 and V >= 1 (got %d, %d)", who, C, V); return SPLAT_EINVAL; }
+    if (!kt || !kq || !kp || !R0 || !t0 || !xi || !delta || !vcam || !vt) {
+        set_error("%s: NULL pointer argument", who); return SPLAT_EINVAL;
+    }
+    return SPLAT_OK;
+}
+
+}  // namespace splat
+
+using namespace splat;
+
+extern "C" {
+
+const char *splat_last_error(void) { return g_err; }
+
+const char *splat_version(void) { return "splat-gfx950 0.1"; }
+
+size_t splat_struct_size(int32_t which) {
+    switch (which) {
+        case 0: return sizeof(splat_settings);
+        case 1: return sizeof(splat_gaussians);
+        case 2: return sizeof(splat_plan);
+        default: return 0;
+    }
+}
+
+void splat_default_settings(splat_settings *s) {
+    if (!s) return;
+    s->near_z = 0.2;
+    s->far_z = 256.0;
+    s->eps2d = 0.3;
+    s->alpha_min = 1.0 / 255.0;
+    s->alpha_max = 0.99;
+    s->t_min = 1e-4;
+    s->guard = 0.15;
+    s->bg[0] = s->bg[1] = s->bg[2] = 0.0;
+    s->pad_px = 0.1;
+    s->pad_rel = 1e-4;
+    s->tile_w = 16;
+    s->tile_h = 16;
+    s->batch = 64;
+    s->persistent = 1;
+}
+
+int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, int32_t width, int32_t height,
+                    int64_t slot_cap, int64_t inst_cap, splat_plan *plan) {
+    g_err[0] = 0;
+    if (!plan) { set_error("plan is NULL"); return SPLAT_EINVAL; }
+    int rc = check_settings(s);
+    if (rc) return rc;
+    if (n_views < 1 || n_views > 1023) { set_error("n_views must be in [1, 1023] (got %d)", n_views); return SPLAT_EINVAL; }
+    if (n_gauss < 0 || n_gauss >= ((int64_t)1 << 31)) { set_error("n_gauss must be in [0, 2^31)"); return SPLAT_EINVAL; }
+    if (width < 1 || height < 1 || width > 16384 || height > 16384) {
+        set_error("image size %dx%d outside [1, 16384]", width, height); return SPLAT_EINVAL;
+    }
+    if (slot_cap < 1 || slot_cap >= ((int64_t)1 << 31) || inst_cap < 1 || inst_cap >= ((int64_t)1 << 31)) {
+        set_error("capacities must be in [1, 2^31) (got %lld, %lld)", (long long)slot_cap, (long long)inst_cap);
+        return SPLAT_EINVAL;
+    }
+    splat_plan p;
+    memset(&p, 0, sizeof p);
+    p.s = *s;
+    p.n_views = n_views;
+    p.width = width;
+    p.height = height;
+    p.tiles_x = (width + s->tile_w - 1) / s->tile_w;
+    p.tiles_y = (height + s->tile_h - 1) / s->tile_h;
+    p.tiles_per_view = p.tiles_x * p.tiles_y;
+    if (p.tiles_x > 65535 || p.tiles_y > 65535) { set_error("too many tiles"); return SPLAT_EUNSUPPORTED; }
+    uint32_t nb = fbits((float)s->near_z), fb = fbits((float)s->far_z);
+    if (!(fb > nb)) { set_error("far_z and near_z round to the same float"); return SPLAT_EINVAL; }
+    p.depth_bits = bit_length(fb - nb);
+    uint64_t ntiles_all = (uint64_t)n_views * (uint64_t)p.tiles_per_view;
+    p.tile_bits = ntiles_all > 1 ? bit_length(ntiles_all - 1) : 1;
+    if (p.depth_bits + p.tile_bits > 64) {
+        set_error("sort key needs %d + %d bits > 64", p.tile_bits, p.depth_bits); return SPLAT_EUNSUPPORTED;
+    }
+    if (ntiles_all >= ((uint64_t)1 << 31)) { set_error("too many (view, tile) items"); return SPLAT_EUNSUPPORTED; }
+    p.n_blocks_proj = (int32_t)((n_gauss + 255) / 256);
+    if (p.n_blocks_proj < 1) p.n_blocks_proj = 1;
+    if (p.n_blocks_proj > 65535) { set_error("too many Gaussians for one projection grid row"); return SPLAT_EUNSUPPORTED; }
+    int64_t nsb = (inst_cap + 8191) / 8192;
+    p.n_sort_blocks = (int32_t)(nsb < 1 ? 1 : (nsb > 2048 ? 2048 : nsb));
+    p.n_gauss = n_gauss;
+    p.slot_cap = slot_cap;
+    p.inst_cap = inst_cap;
+    int bits = p.depth_bits + p.tile_bits;
+    int passes = (bits + 7) / 8;
+    p.sorted_buf = passes & 1;
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + (bytes ? bytes : 1));
+        return o;
+    };
+    int64_t nproj = (int64_t)n_views * p.n_blocks_proj + 1;
+    size_t nparts = scan_partials(slot_cap + 1);
+    size_t np2 = scan_partials(nproj);
+    size_t np3 = scan_partials((int64_t)256 * p.n_sort_blocks);
+    if (np2 > nparts) nparts = np2;
+    if (np3 > nparts) nparts = np3;
+    p.off_status = take(4);
+    p.off_counts = take(8 * 4);
+    p.off_view_off = take((size_t)(n_views + 1) * 4);
+    p.off_blockcnt = take((size_t)nproj * 4);
+    p.off_rec = take((size_t)slot_cap * 48);
+    p.off_meta = take((size_t)slot_cap * 8);
+    p.off_rect = take((size_t)slot_cap * 8);
+    p.off_ntiles = take((size_t)(slot_cap + 1) * 4);
+    p.off_keys = take((size_t)inst_cap * 16);
+    p.off_vals = take((size_t)inst_cap * 8);
+    p.off_ranges = take((size_t)ntiles_all * 8);
+    p.off_queue = take((size_t)ntiles_all * 4);
+    p.off_hist = take(((size_t)256 * p.n_sort_blocks + 1 + 128) * 4);
+    p.off_scan = take(nparts * 4);
+    p.off_grad2d = take((size_t)slot_cap * 36);
+    p.ws_bytes = off;
+    *plan = p;
+    return SPLAT_OK;
+}
+
+int splat_pose_interp_fwd(int32_t K, const double *knot_t, const double *knot_q, const double *knot_p, int32_t C,
+                          const double *R0, const double *t0, const double *xi, const double *delta, int32_t V,
+                          const int32_t *view_cam, const double *view_t, double *w2c, uint32_t *status,
+                          void *stream) {
+    g_err[0] = 0;
+    int rc = check_pose_args(K, knot_t, knot_q, knot_p, C, R0, t0, xi, delta, V, view_cam, view_t, "pose_interp_fwd");
+    if (rc) return rc;
+    if (!w2c) { set_error("pose_interp_fwd: w2c is NULL"); return SPLAT_EINVAL; }
+    return launch_pose_fwd(K, knot_t, knot_q, knot_p, C, R0, t0, xi, delta, V, view_cam, view_t, w2c, status,
+                           (hipStream_t)stream);
+}
+
+int splat_pose_interp_bwd(int32_t K, const double *knot_t, const double *knot_q, const double *knot_p, int32_t C,
+                          const double *R0, const double *t0, const double *xi, const double *delta, int32_t V,
+                          const int32_t *view_cam, const double *view_t, const double *dw2c, double *dxi,
+                          double *ddelta, void *stream) {
+    g_err[0] = 0;
+    int rc = check_pose_args(K, knot_t, knot_q, knot_p, C, R0, t0, xi, delta, V, view_cam, view_t, "pose_interp_bwd");
+    if (rc) return rc;
+    if (!dw2c || !dxi || !ddelta) { set_error("pose_interp_bwd: NULL gradient pointer"); return SPLAT_EINVAL; }
+    return launch_pose_bwd(K, knot_t, knot_q, knot_p, C, R0, t0, xi, delta, V, view_cam, view_t, dw2c, dxi, ddelta,
+                           (hipStream_t)stream);
+}
+
+int splat_project(const splat_plan *plan, void *ws, const splat_gaussians *g, const double *w2c, const double *intr,
+                  void *stream) {
+    g_err[0] = 0;
+    int rc = check_plan(plan, ws, "project");
+    if (rc) return rc;
+    if ((rc = check_gauss(g, plan, "project"))) return rc;
+    if (!w2c || !intr) { set_error("project: w2c or intr is NULL"); return SPLAT_EINVAL; }
+    return launch_project(*plan, ws, *g, w2c, intr, (hipStream_t)stream);
+}
+
+int splat_bin_sort(const splat_plan *plan, void *ws, void *stream) {
+    g_err[0] = 0;
+    int rc = check_plan(plan, ws, "bin_sort");
+    if (rc) return rc;
+    return launch_bin_sort(*plan, ws, (hipStream_t)stream);
+}
+
+int splat_render_fwd(const splat_plan *plan, void *ws, float *img, float *T_final, int32_t *last_pos, void *stream) {
+    g_err[0] = 0;
+    int rc = check_plan(plan, ws, "render_fwd");
+    if (rc) return rc;
+    if (!img || !T_final || !last_pos) { set_error("render_fwd: NULL output"); return SPLAT_EINVAL; }
+    return launch_render_fwd(*plan, ws, img, T_final, last_pos, nullptr, (hipStream_t)stream);
+}
+
+int splat_render_fwd_stats(const splat_plan *plan, void *ws, float *img, float *T_final, int32_t *last_pos,
+                           uint64_t *stats, void *stream) {
+    g_err[0] = 0;
+    int rc = check_plan(plan, ws, "render_fwd_stats");
+    if (rc) return rc;
+    if (!img || !T_final || !last_pos || !stats) { set_error("render_fwd_stats: NULL argument"); return SPLAT_EINVAL; }
+    return launch_render_fwd(*plan, ws, img, T_final, last_pos, stats, (hipStream_t)stream);
+}
+
+int splat_l1_loss_grad(const float *img, const float *target, const uint8_t *mask, int32_t n_views, int32_t width,
+                       int32_t height, float *dL_dimg, double *loss, void *stream) {
+    g_err[0] = 0;
+    if (!img || !target || !dL_dimg) { set_error("l1_loss_grad: NULL argument"); return SPLAT_EINVAL; }
+    if (n_views < 1 || width < 1 || height < 1) { set_error("l1_loss_grad: bad shape"); return SPLAT_EINVAL; }
+    int64_t hw = (int64_t)width * height;
+    double inv_n = 1.0 / (3.0 * (double)n_views * (double)hw);
+    return launch_l1(img, target, mask, n_views, hw, inv_n, dL_dimg, loss, (hipStream_t)stream);
+}
+
+int splat_render_bwd(const splat_plan *plan, void *ws, const float *dL_dimg, const float *T_final,
+                     const int32_t *last_pos, void *stream) {
+    g_err[0] = 0;
+    int rc = check_plan(plan, ws, "render_bwd");
+    if (rc) return rc;
+    if (!dL_dimg || !T_final || !last_pos) { set_error("render_bwd: NULL input"); return SPLAT_EINVAL; }
+    return launch_render_bwd(*plan, ws, dL_dimg, T_final, last_pos, nullptr, (hipStream_t)stream);
+}
+
+int splat_render_bwd_stats(const splat_plan *plan, void *ws, const float *dL_dimg, const float *T_final,
+                           const int32_t *last_pos, uint64_t *stats, void *stream) {
+    g_err[0] = 0;
+    int rc = check_plan(plan, ws, "render_bwd_stats");
+    if (rc) return rc;
+    if (!dL_dimg || !T_final || !last_pos || !stats) { set_error("render_bwd_stats: NULL argument"); return SPLAT_EINVAL; }
+    return launch_render_bwd(*plan, ws, dL_dimg, T_final, last_pos, stats, (hipStream_t)stream);
+}
+
+int splat_project_bwd(const splat_plan *plan, void *ws, const splat_gaussians *g, const double *w2c,
+                      const double *intr, float *dquat, float *dscale, float *dopacity, float *dcolor, float *dmean,
+                      double *dw2c, void *stream) {
+    g_err[0] = 0;
+    int rc = check_plan(plan, ws, "project_bwd");
+    if (rc) return rc;
+    if ((rc = check_gauss(g, plan, "project_bwd"))) return rc;
+    if (!w2c || !intr || !dquat || !dscale || !dopacity || !dcolor || !dw2c) {
+        set_error("project_bwd: NULL argument"); return SPLAT_EINVAL;
+    }
+    return launch_project_bwd(*plan, ws, *g, w2c, intr, dquat, dscale, dopacity, dcolor, dmean, dw2c,
+                              (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,427 @@
+// binsort.hip -- tile binning: scans, instance emission, stable LSD radix sort on
+// 64-bit keys, per-(view, tile) ranges and the cost-ordered work queue.
+//
+// Every (slot, covered tile) pair becomes one instance with key
+//   ((view * T + tile) << depth_bits) | (bits(depth32) - bits(near_z))
+// and value = slot.  Instances are emitted in (view, Gaussian, tile row-major)
+// order and the sort is stable, so inside a tile the order is (depth32,
+// Gaussian id) -- ties on depth are broken by the Gaussian index.
+//
+// Radix sort: reduce-then-scan per 8-bit digit with a fixed number of
+// partitions (the key count lives on the device, so the grid never depends on
+// it); inside a partition keys are ranked 256 at a time with wave64 ballot
+// peer matching, which keeps the order stable without any inter-workgroup
+// waiting.
+#include "common.hpp"
+
+namespace splat {
+namespace {
+
+constexpr int SCAN_T = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_T * SCAN_ITEMS;  // 2048
+
+__device__ inline uint32_t load_n(const uint32_t *n_dev, int64_t n_cap) {
+    if (!n_dev) return (uint32_t)n_cap;
+    uint32_t n = *n_dev;
+    return n < (uint64_t)n_cap ? n : (uint32_t)n_cap;
+}
+
+// inclusive wave scan
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+    int l = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t u = __shfl_up(v, o, kWave);
+        if (l >= o) v += u;
+    }
+    return v;
+}
+
+// exclusive block scan over 256 threads; returns the block total through *tot
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *lds, uint32_t *tot) {
+    uint32_t inc = wave_incl_scan(v);
+    int w = threadIdx.x >> 6;
+    if (__lane_id() == 63) lds[w] = inc;
+    __syncthreads();
+    uint32_t base = 0, total = 0;
+    int nw = blockDim.x >> 6;
+    for (int i = 0; i < nw; ++i) {
+        uint32_t c = lds[i];
+        if (i < w) base += c;
+        total += c;
+    }
+    __syncthreads();
+    *tot = total;
+    return base + inc - v;
+}
+
+__global__ __launch_bounds__(SCAN_T) void scan_reduce_kernel(const uint32_t *in, const uint32_t *n_dev,
+                                                            int64_t n_cap, uint32_t *partials) {
+    __shared__ uint32_t lds[4];
+    uint32_t n = load_n(n_dev, n_cap);
+    uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    if (base >= n) {
+        if (threadIdx.x == 0) partials[blockIdx.x] = 0;
+        return;
+    }
+    uint32_t s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        uint64_t i = base + (uint64_t)k * SCAN_T + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    uint32_t tot;
+    block_excl_scan(s, lds, &tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// single workgroup of 1024 threads: exclusive scan of the partials in place
+__global__ __launch_bounds__(1024) void scan_partials_kernel(uint32_t *partials, int nparts, uint32_t *out,
+                                                            const uint32_t *n_dev, int64_t n_cap,
+                                                            uint32_t *total_dst) {
+    __shared__ uint32_t lds[16];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nparts; base += 1024) {
+        int i = base + threadIdx.x;
+        uint32_t v = i < nparts ? partials[i] : 0u;
+        uint32_t inc = wave_incl_scan(v);
+        int w = threadIdx.x >> 6;
+        if (__lane_id() == 63) lds[w] = inc;
+        __syncthreads();
+        uint32_t wb = 0, tot = 0;
+        for (int k = 0; k < 16; ++k) {
+            uint32_t c = lds[k];
+            if (k < w) wb += c;
+            tot += c;
+        }
+        uint32_t c0 = carry;
+        if (i < nparts) partials[i] = c0 + wb + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c0 + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        uint32_t n = load_n(n_dev, n_cap);
+        out[n] = carry;
+        if (total_dst) *total_dst = carry;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_T) void scan_down_kernel(const uint32_t *in, uint32_t *out, const uint32_t *n_dev,
+                                                          int64_t n_cap, const uint32_t *partials) {
+    __shared__ uint32_t lds[4];
+    uint32_t n = load_n(n_dev, n_cap);
+    uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    if (base >= n) return;
+    // each thread owns SCAN_ITEMS consecutive elements
+    uint64_t t0 = base + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        uint64_t i = t0 + k;
+        v[k] = (i < n) ? in[i] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(s, lds, &tot) + partials[blockIdx.x];
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        uint64_t i = t0 + k;
+        if (i < n) out[i] = ex;
+        ex += v[k];
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// -------------------------------------------------------------------------------------
+// emission
+// -------------------------------------------------------------------------------------
+// Instance count.  On overflow the count is the end of the longest prefix of
+// slots whose instances all fit, so every key below the count is written.
+__global__ void inst_finish_kernel(const uint32_t *offs, int64_t inst_cap, uint32_t *counts, uint32_t *status) {
+    if (threadIdx.x != 0) return;
+    uint32_t ns = counts[CNT_SLOTS];
+    uint32_t tot = offs[ns];
+    uint32_t cap = (uint32_t)inst_cap;
+    if (tot <= cap) {
+        counts[CNT_INST] = tot;
+        return;
+    }
+    uint32_t lo = 0, hi = ns;  // largest k with offs[k] <= cap (offs[0] = 0)
+    while (lo < hi) {
+        uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (offs[mid] <= cap) lo = mid; else hi = mid - 1;
+    }
+    counts[CNT_INST] = offs[lo];
+    atomicOr(status, SPLAT_ST_CAPACITY);
+}
+
+__global__ __launch_bounds__(256) void emit_kernel(const uint32_t *counts, const uint32_t *offs, const Rect16 *rect,
+                                                  const float4 *rec, const int2 *meta, int tiles_x, int T,
+                                                  int depth_bits, float near32,
+                                                  uint64_t *keys, uint32_t *vals) {
+    uint32_t ns = counts[CNT_SLOTS];
+    uint32_t ni = counts[CNT_INST];  // <= capacity; only slots wholly below it emit
+    uint32_t nb = __float_as_uint(near32);
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < ns;
+         s += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t o = offs[s];
+        Rect16 r = rect[s];
+        uint32_t nt = (uint32_t)(r.x1 - r.x0 + 1) * (uint32_t)(r.y1 - r.y0 + 1);
+        if ((uint64_t)o + nt > (uint64_t)ni) continue;
+        uint64_t dkey = (uint64_t)(__float_as_uint(rec[3 * s + 2].w) - nb);
+        uint64_t vbase = (uint64_t)meta[s].y * (uint64_t)T;
+        for (int ty = r.y0; ty <= r.y1; ++ty)
+            for (int tx = r.x0; tx <= r.x1; ++tx) {
+                uint64_t tile = vbase + (uint64_t)(ty * tiles_x + tx);
+                keys[o] = (tile << depth_bits) | dkey;
+                vals[o] = (uint32_t)s;
+                ++o;
+            }
+    }
+}
+
+// -------------------------------------------------------------------------------------
+// radix sort
+// -------------------------------------------------------------------------------------
+constexpr int RS_T = 256;  // threads per partition workgroup = keys per round
+
+__device__ inline void chunk_of(uint32_t n, int nparts, int part, uint32_t &b, uint32_t &e) {
+    uint32_t per = (n + nparts - 1) / nparts;
+    per = (per + RS_T - 1) / RS_T * RS_T;
+    uint64_t bb = (uint64_t)part * per;
+    uint64_t ee = bb + per;
+    b = (uint32_t)(bb < n ? bb : n);
+    e = (uint32_t)(ee < n ? ee : n);
+}
+
+// lanes of the wave holding the same 8-bit digit as this lane
+__device__ inline uint64_t match_digit(uint32_t d, bool act) {
+    uint64_t peers = __ballot(act);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        uint64_t m = __ballot(act && ((d >> b) & 1u));
+        peers &= ((d >> b) & 1u) ? m : ~m;
+    }
+    return act ? peers : 0ull;
+}
+
+__global__ __launch_bounds__(RS_T) void radix_upsweep_kernel(const uint64_t *keys, const uint32_t *counts, int shift,
+                                                            int nparts, uint32_t *hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t n = counts[CNT_INST];
+    uint32_t b, e;
+    chunk_of(n, nparts, blockIdx.x, b, e);
+    for (uint32_t base = b; base < e; base += RS_T) {
+        uint32_t i = base + threadIdx.x;
+        bool act = i < e;
+        uint32_t d = act ? (uint32_t)(keys[i] >> shift) & 255u : 0u;
+        uint64_t peers = match_digit(d, act);
+        if (act && rank_in(peers) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * nparts + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RS_T) void radix_downsweep_kernel(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
+                                                              uint32_t *vout, const uint32_t *counts, int shift,
+                                                              int nparts, const uint32_t *hoff) {
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t wbase[4][256];
+    int t = threadIdx.x;
+    int w = t >> 6;
+    for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
+    uint32_t run = hoff[(size_t)t * nparts + blockIdx.x];  // running offset of digit t
+    __syncthreads();
+    uint32_t n = counts[CNT_INST];
+    uint32_t b, e;
+    chunk_of(n, nparts, blockIdx.x, b, e);
+    for (uint32_t base = b; base < e; base += RS_T) {
+        uint32_t i = base + t;
+        bool act = i < e;
+        uint64_t key = act ? kin[i] : 0ull;
+        uint32_t val = act ? vin[i] : 0u;
+        uint32_t d = (uint32_t)(key >> shift) & 255u;
+        uint64_t peers = match_digit(d, act);
+        uint32_t r = rank_in(peers);
+        if (act && r == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        // thread t owns digit t: per-wave bases inside this round
+        uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
+        wbase[0][t] = run;
+        wbase[1][t] = run + c0;
+        wbase[2][t] = run + c0 + c1;
+        wbase[3][t] = run + c0 + c1 + c2;
+        run += c0 + c1 + c2 + c3;
+        wcnt[0][t] = 0; wcnt[1][t] = 0; wcnt[2][t] = 0; wcnt[3][t] = 0;
+        __syncthreads();
+        if (act) {
+            uint32_t dst = wbase[w][d] + r;
+            if (dst < n) {  // always true when both sweeps saw the same keys
+                kout[dst] = key;
+                vout[dst] = val;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// -------------------------------------------------------------------------------------
+// tile ranges and the work queue
+// -------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void ranges_kernel(const uint64_t *keys, const uint32_t *counts, int depth_bits,
+                                                    uint64_t n_tiles, uint2 *ranges) {
+    uint32_t n = counts[CNT_INST];
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t t = keys[i] >> depth_bits;
+        if (t >= n_tiles) continue;  // cannot happen for emitted keys; keeps the write in bounds
+        if (i == 0 || (keys[i - 1] >> depth_bits) != t) ranges[t].x = (uint32_t)i;
+        if (i + 1 == n || (keys[i + 1] >> depth_bits) != t) ranges[t].y = (uint32_t)(i + 1);
+    }
+}
+
+__device__ inline int cost_bucket(uint2 r) {
+    uint32_t c = r.y - r.x;  // empty tiles have x = y = 0
+    return c == 0 ? 0 : 32 - __clz(c);  // 1..32
+}
+
+// hist[64]: [0..32] bucket counts
+__global__ __launch_bounds__(256) void queue_hist_kernel(const uint2 *ranges, int n, uint32_t *qh) {
+    __shared__ uint32_t h[33];
+    if (threadIdx.x < 33) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        atomicAdd(&h[cost_bucket(ranges[i])], 1u);
+    __syncthreads();
+    if (threadIdx.x < 33 && h[threadIdx.x]) atomicAdd(&qh[threadIdx.x], h[threadIdx.x]);
+}
+
+// descending buckets: cursor[b] = number of items in buckets > b
+__global__ void queue_scan_kernel(uint32_t *qh) {
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int b = 32; b >= 0; --b) {
+            uint32_t c = qh[b];
+            qh[33 + b] = acc;
+            acc += c;
+        }
+    }
+}
+
+// each workgroup reserves one range per bucket with a single global atomic,
+// then places its items with LDS atomics
+__global__ __launch_bounds__(256) void queue_scatter_kernel(const uint2 *ranges, int n, uint32_t *qh,
+                                                           uint32_t *queue) {
+    __shared__ uint32_t cnt[33], base[33];
+    for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
+        if (threadIdx.x < 33) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        int i = i0 + threadIdx.x;
+        int bk = i < n ? cost_bucket(ranges[i]) : 0;
+        uint32_t local = i < n ? atomicAdd(&cnt[bk], 1u) : 0u;
+        __syncthreads();
+        if (threadIdx.x < 33 && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&qh[33 + threadIdx.x], cnt[threadIdx.x]);
+        __syncthreads();
+        if (i < n) queue[base[bk] + local] = (uint32_t)i;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+size_t scan_partials(int64_t n_cap) { return (size_t)((n_cap + SCAN_TILE - 1) / SCAN_TILE) + 1; }
+
+int launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return 0;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)nb), dim3(256), 0, st, p, v, n);
+    return launch_status("fill");
+}
+
+int launch_scan_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, int64_t n_cap, uint32_t *partials,
+                    uint32_t *total_dst, hipStream_t st) {
+    int64_t nparts = (n_cap + SCAN_TILE - 1) / SCAN_TILE;
+    if (nparts < 1) nparts = 1;
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nparts), dim3(SCAN_T), 0, st, in, n_dev, n_cap, partials);
+    int rc = launch_status("scan_reduce");
+    if (rc) return rc;
+    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, st, partials, (int)nparts, out, n_dev, n_cap,
+                       total_dst);
+    rc = launch_status("scan_partials");
+    if (rc) return rc;
+    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nparts), dim3(SCAN_T), 0, st, in, out, n_dev, n_cap, partials);
+    return launch_status("scan_down");
+}
+
+int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
+    uint32_t *status = ws_at<uint32_t>(ws, p.off_status);
+    uint32_t *counts = ws_at<uint32_t>(ws, p.off_counts);
+    uint32_t *ntiles = ws_at<uint32_t>(ws, p.off_ntiles);
+    uint32_t *partials = ws_at<uint32_t>(ws, p.off_scan);
+    uint64_t *keys0 = ws_at<uint64_t>(ws, p.off_keys);
+    uint64_t *keys1 = keys0 + p.inst_cap;
+    uint32_t *vals0 = ws_at<uint32_t>(ws, p.off_vals);
+    uint32_t *vals1 = vals0 + p.inst_cap;
+    uint2 *ranges = ws_at<uint2>(ws, p.off_ranges);
+    uint32_t *queue = ws_at<uint32_t>(ws, p.off_queue);
+    uint32_t *hist = ws_at<uint32_t>(ws, p.off_hist);
+    uint32_t *qh = hist + (size_t)256 * p.n_sort_blocks + 1;
+    int nT = p.n_views * p.tiles_per_view;
+
+    // instance offsets: exclusive scan of the per-slot tile counts
+    int rc = launch_scan_u32(ntiles, ntiles, counts + CNT_SLOTS, p.slot_cap, partials, nullptr, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(inst_finish_kernel, dim3(1), dim3(64), 0, st, ntiles, p.inst_cap, counts, status);
+    if ((rc = launch_status("inst_finish"))) return rc;
+    int eb = (int)((p.slot_cap + 255) / 256);
+    if (eb > 8192) eb = 8192;
+    hipLaunchKernelGGL(emit_kernel, dim3(eb), dim3(256), 0, st, counts, ntiles, ws_at<Rect16>(ws, p.off_rect),
+                       ws_at<float4>(ws, p.off_rec), ws_at<int2>(ws, p.off_meta), p.tiles_x, p.tiles_per_view,
+                       p.depth_bits, (float)p.s.near_z, keys0, vals0);
+    if ((rc = launch_status("emit"))) return rc;
+
+    // LSD radix sort over the used key bits
+    int bits = p.depth_bits + p.tile_bits;
+    int passes = (bits + 7) / 8;
+    uint64_t *ki = keys0, *ko = keys1;
+    uint32_t *vi = vals0, *vo = vals1;
+    int nh = 256 * p.n_sort_blocks;
+    for (int ps = 0; ps < passes; ++ps) {
+        int shift = 8 * ps;
+        hipLaunchKernelGGL(radix_upsweep_kernel, dim3(p.n_sort_blocks), dim3(RS_T), 0, st, ki, counts, shift,
+                           p.n_sort_blocks, hist);
+        if ((rc = launch_status("radix_upsweep"))) return rc;
+        rc = launch_scan_u32(hist, hist, nullptr, nh, partials, nullptr, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(radix_downsweep_kernel, dim3(p.n_sort_blocks), dim3(RS_T), 0, st, ki, vi, ko, vo, counts,
+                           shift, p.n_sort_blocks, hist);
+        if ((rc = launch_status("radix_downsweep"))) return rc;
+        uint64_t *tk = ki; ki = ko; ko = tk;
+        uint32_t *tv = vi; vi = vo; vo = tv;
+    }
+    // ranges of every (view, tile) and the cost-ordered queue
+    if ((rc = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, (int64_t)2 * nT, st))) return rc;
+    int rb = (int)((p.inst_cap + 255) / 256);
+    if (rb > 8192) rb = 8192;
+    hipLaunchKernelGGL(ranges_kernel, dim3(rb), dim3(256), 0, st, ki, counts, p.depth_bits, (uint64_t)nT, ranges);
+    if ((rc = launch_status("ranges"))) return rc;
+    if ((rc = launch_fill_u32(qh, 0u, 66, st))) return rc;
+    int qb = (nT + 255) / 256;
+    if (qb > 1024) qb = 1024;
+    hipLaunchKernelGGL(queue_hist_kernel, dim3(qb), dim3(256), 0, st, ranges, nT, qh);
+    if ((rc = launch_status("queue_hist"))) return rc;
+    hipLaunchKernelGGL(queue_scan_kernel, dim3(1), dim3(64), 0, st, qh);
+    if ((rc = launch_status("queue_scan"))) return rc;
+    hipLaunchKernelGGL(queue_scatter_kernel, dim3(qb), dim3(256), 0, st, ranges, nT, qh, queue);
+    return launch_status("queue_scatter");
+}
+
+}  // namespace splat

@@ -1,0 +1,85 @@
+// common.hpp -- internal helpers of the gfx950 splatting library.
+// Not part of the public ABI (see include/splat.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/splat.h"
+
+namespace splat {
+
+constexpr int kWave = 64;
+
+// workspace views --------------------------------------------------------------
+template <typename T>
+__host__ __device__ inline T *ws_at(void *ws, size_t off) {
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(ws) + off);
+}
+
+struct alignas(8) Rect16 {
+    uint16_t x0, x1, y0, y1;
+};
+
+// counter indices in off_counts
+enum { CNT_SLOTS = 0, CNT_INST = 1, CNT_WORK = 2 };
+
+// float <-> bits
+__device__ inline uint32_t f2u(float f) { return __float_as_uint(f); }
+
+// wave-level helpers -------------------------------------------------------------
+__device__ inline int lane_id() { return __lane_id(); }
+
+__device__ inline uint64_t ballot(bool p) { return __ballot(p); }
+
+// exclusive rank of this lane among the set bits of mask below it
+__device__ inline uint32_t rank_in(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// host side ------------------------------------------------------------------------
+void set_error(const char *fmt, ...);
+int launch_status(const char *what);
+
+// internal launchers (one per translation unit)
+int launch_pose_fwd(int32_t K, const double *kt, const double *kq, const double *kp, int32_t C,
+                    const double *R0, const double *t0, const double *xi, const double *delta,
+                    int32_t V, const int32_t *vcam, const double *vt, double *w2c, uint32_t *status,
+                    hipStream_t st);
+int launch_pose_bwd(int32_t K, const double *kt, const double *kq, const double *kp, int32_t C,
+                    const double *R0, const double *t0, const double *xi, const double *delta,
+                    int32_t V, const int32_t *vcam, const double *vt, const double *dw2c,
+                    double *dxi, double *ddelta, hipStream_t st);
+int launch_project(const splat_plan &p, void *ws, const splat_gaussians &g, const double *w2c,
+                   const double *intr, hipStream_t st);
+int launch_project_bwd(const splat_plan &p, void *ws, const splat_gaussians &g, const double *w2c,
+                       const double *intr, float *dquat, float *dscale, float *dopac,
+                       float *dcolor, float *dmean, double *dw2c, hipStream_t st);
+int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st);
+int launch_render_fwd(const splat_plan &p, void *ws, float *img, float *T, int32_t *last,
+                      uint64_t *stats, hipStream_t st);
+int launch_render_bwd(const splat_plan &p, void *ws, const float *dimg, const float *T,
+                      const int32_t *last, uint64_t *stats, hipStream_t st);
+int launch_l1(const float *img, const float *target, const uint8_t *mask, int64_t n_views, int64_t hw,
+              double inv_n, float *dimg, double *loss, hipStream_t st);
+
+// device exclusive scan of u32 (binsort.hip): out[i] = sum in[0..i), out[n] = total;
+// n is read from *n_dev (clamped to n_cap); partials needs scan_partials(n_cap) u32.
+size_t scan_partials(int64_t n_cap);
+int launch_scan_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, int64_t n_cap,
+                    uint32_t *partials, uint32_t *total_dst, hipStream_t st);
+int launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
+
+}  // namespace splat

@@ -1,0 +1,343 @@
+"""GPU parity of every stage of the HIP path against the FP64 CPU oracle.
+
+Bars: float64 poses to 1e-12; depth keys, visibility, tile lists and sort order
+bit-exact (Gaussians whose footprint edge sits on a rounding step excepted);
+images within 1e-4 per channel and last contributors bit-exact, with the
+oracle's alternatives at threshold-margin pixels; gradients within 1e-3
+relative.  All through the C ABI.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_2403_11577_amd import binding as B
+from paper_2403_11577_amd import pipeline as pl
+
+from gpu_util import compare_images, gpu_render, rel_close, say
+
+pytestmark = pytest.mark.gpu
+
+TILES = [(16, 16), (8, 8), (16, 32), (32, 16)]
+
+
+def _dev(a, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def test_library_loads_and_abi_matches():
+    say("case: abi")
+    assert B.splat_version().startswith("splat")
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_pose_fwd_bwd_vs_oracle(seed):
+    say(f"case: pose seed={seed}")
+    s = synth.small_drive(seed, n_frames=3)
+    ds = pl.DeviceScene.from_scene(s)
+    xi, dl = _dev(s.xi), _dev(s.delta)
+    w2c = torch.empty((s.views.n, 12), dtype=torch.float64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    B.splat_pose_interp_fwd(ds.knot_t, ds.knot_q, ds.knot_p, ds.R0, ds.t0, xi, dl, ds.view_cam, ds.view_t,
+                            w2c, status)
+    ref, _, _ = oracle.pose(s.traj, s.rig, s.xi, s.delta, s.views)
+    np.testing.assert_allclose(w2c.cpu().numpy(), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    assert int(status.item()) == 0
+    G = np.random.default_rng(seed).normal(size=(s.views.n, 12))
+    dxi = torch.zeros((2, 6), dtype=torch.float64, device="cuda")
+    ddl = torch.zeros(2, dtype=torch.float64, device="cuda")
+    B.splat_pose_interp_bwd(ds.knot_t, ds.knot_q, ds.knot_p, ds.R0, ds.t0, xi, dl, ds.view_cam, ds.view_t,
+                            _dev(G), dxi, ddl)
+    rxi, rdl = oracle.pose_bwd(s.traj, s.rig, s.xi, s.delta, s.views, G)
+    np.testing.assert_allclose(dxi.cpu().numpy(), rxi, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(ddl.cpu().numpy(), rdl, rtol=1e-10, atol=1e-12)
+
+
+def test_pose_extrapolation_flag():
+    say("case: pose extrapolation")
+    s = synth.small_drive(0, n_frames=1)
+    ds = pl.DeviceScene.from_scene(s)
+    vt = torch.tensor([s.traj.t[-1] + 0.3, s.traj.t[0] - 0.2], dtype=torch.float64, device="cuda")
+    cam = torch.tensor([0, 1], dtype=torch.int32, device="cuda")
+    w2c = torch.empty((2, 12), dtype=torch.float64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    B.splat_pose_interp_fwd(ds.knot_t, ds.knot_q, ds.knot_p, ds.R0, ds.t0, _dev(s.xi), _dev(s.delta), cam, vt,
+                            w2c, status)
+    views = synth.Views(np.array([0, 1], np.int32), vt.cpu().numpy())
+    ref, _, _ = oracle.pose(s.traj, s.rig, s.xi, s.delta, views)
+    np.testing.assert_allclose(w2c.cpu().numpy(), ref, atol=1e-9)
+    assert int(status.item()) & B.ST_EXTRAPOLATED
+
+
+def _project_check(scene, tile):
+    w2c, _, _ = oracle.pose(scene.traj, scene.rig, scene.xi, scene.delta, scene.views)
+    intr = oracle.view_intr(scene.rig, scene.views)
+    W, H = scene.rig.W, scene.rig.H
+    g = gpu_render(scene, tile=tile, w2c=w2c)
+    fr = g["frame"]
+    ns, ni = g["slots"], g["inst"]
+    proj = oracle.project_all(scene.gauss, w2c, intr, W, H)
+    meta = fr.meta(ns).cpu().numpy()
+    rec = fr.records(ns).cpu().numpy()
+    view_off = fr.buf("view_off", torch.int32, scene.views.n + 1).cpu().numpy()
+    for v in range(scene.views.n):
+        sl = slice(view_off[v], view_off[v + 1])
+        gids = meta[sl, 0]
+        assert np.all(meta[sl, 1] == v)
+        assert np.all(np.diff(gids) > 0)  # compaction keeps Gaussian order
+        vis = np.nonzero(proj["cull"][v] == 0)[0]
+        rm = proj["rect_margin"][v].astype(bool)
+        assert set(gids) ^ set(vis) <= set(np.nonzero(rm)[0])
+        common = np.intersect1d(gids, vis)
+        idx = np.searchsorted(gids, common)
+        r = rec[sl][idx]
+        # depth key: bit-exact by specification
+        assert np.array_equal(r[:, 11].view(np.uint32), proj["depth32"][v][common].view(np.uint32))
+        mu = r[:, 0:2].astype(np.float64) + r[:, 2:4].astype(np.float64)
+        np.testing.assert_allclose(mu, proj["mu"][v][common], rtol=0, atol=1e-5)
+        np.testing.assert_allclose(r[:, 4:7], proj["conic"][v][common], rtol=2e-6,
+                                   atol=2e-6 * np.abs(proj["conic"][v][common]).max())
+    return g, proj, w2c
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_project_vs_oracle(tile):
+    say(f"case: project tile={tile}")
+    _project_check(synth.tiny_scene(0), tile)
+    _project_check(synth.small_drive(1, n_frames=2), tile)
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_bin_sort_vs_oracle(tile):
+    say(f"case: bin_sort tile={tile}")
+    scene = synth.small_drive(2, n_frames=2)
+    g, proj, w2c = _project_check(scene, tile)
+    fr = g["frame"]
+    ns, ni = g["slots"], g["inst"]
+    vals = fr.sorted_vals(ni).cpu().numpy().astype(np.int64)
+    keys = fr.sorted_keys(ni).cpu().numpy().view(np.uint64)
+    meta = fr.meta(ns).cpu().numpy()
+    ranges = fr.ranges().cpu().numpy().astype(np.int64)
+    assert np.all(np.diff(keys) >= 0)
+    T = int(fr.plan.tiles_per_view)
+    W, H = scene.rig.W, scene.rig.H
+    for v in range(scene.views.n):
+        off, gid, margin = oracle.tile_lists(proj, W, H, tile[0], tile[1], view=v)
+        mset = set(gid[margin])
+        for t in range(T):
+            a, b = ranges[v * T + t]
+            mine = [int(x) for x in meta[vals[a:b], 0]] if b > a else []
+            ref = [int(x) for x in gid[off[t]:off[t + 1]]]
+            if mset:
+                mine = [x for x in mine if x not in mset]
+                ref = [x for x in ref if x not in mset]
+            assert mine == ref, (v, t)
+
+
+SCENES = {
+    "tiny": lambda: synth.tiny_scene(0),
+    "tiny_ragged": lambda: synth.tiny_scene(4, n=700, W=100, H=37, f=80.0),
+    "small_drive": lambda: synth.small_drive(3, n_frames=2),
+}
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+@pytest.mark.parametrize("tile", TILES)
+def test_render_fwd_vs_oracle(name, tile):
+    say(f"case: render_fwd scene={name} tile={tile}")
+    scene = SCENES[name]()
+    g = gpu_render(scene, tile=tile)
+    orc = oracle.render(scene.gauss, g["w2c"], oracle.view_intr(scene.rig, scene.views), scene.rig.W,
+                        scene.rig.H, alternatives=True)
+    ref_w2c, _, _ = oracle.pose(scene.traj, scene.rig, scene.xi, scene.delta, scene.views)
+    np.testing.assert_allclose(g["w2c"], ref_w2c, atol=1e-12 * np.abs(ref_w2c).max())
+    nbad, nfl, nex, mx = compare_images(g, orc)
+    say(f"  flagged={nfl} excluded={nex} max_err={mx:.3g} slots={g['slots']} inst={g['inst']}")
+    assert g["status"] == 0
+    assert nbad == 0
+    assert nex <= 0.001 * orc["nflag"].size
+
+
+def test_render_invariant_across_launch_shapes():
+    say("case: launch-shape invariance")
+    scene = synth.small_drive(4, n_frames=2)
+    base = gpu_render(scene, tile=(16, 16), batch=64, persistent=True)
+    for tile in TILES:
+        for batch in (16, 64, 256):
+            for pers in (True, False):
+                o = gpu_render(scene, tile=tile, batch=batch, persistent=pers)
+                assert np.array_equal(o["img"], base["img"]), (tile, batch, pers)
+                assert np.array_equal(o["T"], base["T"])
+                assert np.array_equal(o["last_id"], base["last_id"])
+
+
+def _grad_case(scene, tile, seed=0):
+    w2c_ref, _, _ = oracle.pose(scene.traj, scene.rig, scene.xi, scene.delta, scene.views)
+    target = oracle.render_scene(scene, xi=scene.xi_gt, delta=scene.delta_gt)["img"]
+    g = gpu_render(scene, tile=tile)
+    fr, ds = g["frame"], g["ds"]
+    # pixels with a threshold decision or an alpha_max kink near the margin are left out on both sides
+    mset = oracle.Settings(margin=1e-2)
+    orc_m = oracle.render(scene.gauss, g["w2c"], oracle.view_intr(scene.rig, scene.views), scene.rig.W,
+                          scene.rig.H, mset)
+    mask = (orc_m["nflag"] > 0) | (orc_m["kink"] > 0)
+    L, dimg = oracle.l1_loss(g["img"], target, mask)   # the same dL/dimg for both sides
+    gr = pl.alloc_grads(ds, with_mean=True)
+    pl.backward(fr, ds, g["xi"], g["delta"], torch.as_tensor(dimg, dtype=torch.float32, device="cuda"), gr)
+    torch.cuda.synchronize()
+    ref = oracle.grad(scene.gauss, g["w2c"], oracle.view_intr(scene.rig, scene.views), scene.rig.W, scene.rig.H,
+                      dimg.astype(np.float32).astype(np.float64), mask=mask.astype(np.int8))
+    rxi, rdl = oracle.pose_bwd(scene.traj, scene.rig, scene.xi, scene.delta, scene.views, ref["w2c"])
+    out = {}
+    for name in ("quat", "scale", "opacity", "color", "mean"):
+        ok, err = rel_close(getattr(gr, name).cpu().numpy(), ref[name], 1e-3)
+        out[name] = (ok, err)
+    ok, err = rel_close(gr.w2c.cpu().numpy(), ref["w2c"], 1e-3, floor_frac=0)
+    out["w2c"] = (ok, err)
+    for name, a, b in (("xi", gr.xi.cpu().numpy(), rxi), ("delta", gr.delta.cpu().numpy(), rdl)):
+        e = float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-12)))
+        out[name] = (e <= 1e-3, e)
+    return out, float(mask.mean())
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 32)])
+def test_gradients_vs_oracle(tile):
+    say(f"case: gradients tile={tile}")
+    out, mfrac = _grad_case(synth.small_drive(5, n_frames=2), tile)
+    say("  masked frac %.4f " % mfrac + " ".join(f"{k}={v[1]:.2e}" for k, v in out.items()))
+    for k, (ok, err) in out.items():
+        assert ok, (k, err)
+
+
+def test_gradients_tiny_vs_oracle():
+    say("case: gradients tiny")
+    s = synth.tiny_scene(2)
+    out, _ = _grad_case(s, (16, 16))
+    for k in ("quat", "scale", "opacity", "color", "mean"):
+        assert out[k][0], (k, out[k][1])
+
+
+def test_empty_and_degenerate_inputs():
+    say("case: empty / degenerate")
+    s = synth.tiny_scene(0, n=64)
+    # every Gaussian behind the camera
+    s.gauss.mean[2] = -5.0
+    g = gpu_render(s)
+    assert g["slots"] == 0 and g["inst"] == 0
+    assert np.all(g["img"] == 0) and np.all(g["T"] == 1) and np.all(g["last_pos"] == -1)
+    # a NaN parameter and a zero quaternion are culled and flagged
+    s = synth.tiny_scene(0, n=64)
+    s.gauss.scale[0, 3] = np.nan
+    s.gauss.quat[:, 5] = 0.0
+    g = gpu_render(s)
+    assert g["status"] & B.ST_NONFINITE and g["status"] & B.ST_DEGENERATE
+    orc = oracle.render(s.gauss, g["w2c"], oracle.view_intr(s.rig, s.views), s.rig.W, s.rig.H, alternatives=True)
+    assert compare_images(g, orc)[0] == 0
+
+
+def test_capacity_overflow_is_flagged_not_fatal():
+    say("case: capacity overflow")
+    s = synth.tiny_scene(0)
+    ds = pl.DeviceScene.from_scene(s)
+    xi, dl = _dev(s.xi), _dev(s.delta)
+    fr = pl.Frame(pl.make_settings(), 1, s.gauss.n, s.rig.W, s.rig.H, 100, 200)
+    pl.forward(fr, ds, xi, dl)
+    torch.cuda.synchronize()
+    assert fr.status() & B.ST_CAPACITY
+    ns, ni = fr.counts()
+    assert ns <= 100 and ni <= 200
+
+
+def test_invalid_arguments_rejected():
+    say("case: invalid args")
+    st = pl.make_settings()
+    with pytest.raises(B.SplatError):
+        B.splat_plan_make(st, 0, 10, 64, 64, 10, 10)
+    bad = pl.make_settings(tile=(12, 12))
+    with pytest.raises(B.SplatError):
+        B.splat_plan_make(bad, 1, 10, 64, 64, 10, 10)
+
+
+def test_l1_kernel_vs_numpy():
+    say("case: l1 kernel")
+    rng = np.random.default_rng(0)
+    img = rng.uniform(size=(3, 3, 17, 29)).astype(np.float32)
+    tgt = img.copy()
+    tgt[:, :, ::2] = rng.uniform(size=tgt[:, :, ::2].shape)
+    mask = np.zeros((3, 17, 29), np.uint8)
+    mask[1, 3:7, 2:9] = 1
+    it, tt, mt = (torch.as_tensor(a, device="cuda") for a in (img, tgt, mask))
+    loss, dimg = pl.l1_loss_grad(it, tt, mt.bool())
+    ref_L, ref_d = oracle.l1_loss(img.astype(np.float64), tgt.astype(np.float64), mask)
+    # the kernel subtracts in float32 (exact sign, rounded magnitude) and sums in float64
+    np.testing.assert_allclose(float(loss.item()), ref_L, rtol=1e-6)
+    np.testing.assert_array_equal(dimg.cpu().numpy(), ref_d.astype(np.float32))
+
+
+def _step_for(scene, tile=(16, 16)):
+    ds = pl.DeviceScene.from_scene(scene)
+    xi, dl = _dev(scene.xi), _dev(scene.delta)
+    tgt = torch.as_tensor(oracle.render_scene(scene, xi=scene.xi_gt, delta=scene.delta_gt)["img"],
+                          dtype=torch.float32, device="cuda")
+    return pl.BatchedStep(ds, xi, dl, tgt, pl.make_settings(tile=tile))
+
+
+def test_graph_replay_matches_eager():
+    say("case: hipGraph replay")
+    step = _step_for(synth.small_drive(6, n_frames=2))
+    step.run()
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (step.fr.img, step.gr.quat, step.gr.color, step.gr.xi, step.gr.delta, step.loss)]
+    step.capture()
+    for rep in range(3):
+        step.fr.img.fill_(-1.0)      # eager work between replays
+        step.gr.color.fill_(123.0)
+        torch.cuda.synchronize()
+        step.replay()
+        torch.cuda.synchronize()
+        got = (step.fr.img, step.gr.quat, step.gr.color, step.gr.xi, step.gr.delta, step.loss)
+        assert torch.equal(got[0], ref[0]), rep
+        # float atomics may sum in another order: compare to the gradient bar's metric, 100x tighter
+        for a, b in zip(got[1:], ref[1:]):
+            ok, err = rel_close(a.cpu().numpy(), b.cpu().numpy(), 1e-5)
+            assert ok, (rep, err)
+
+
+def test_autograd_function_matches_kernels():
+    say("case: autograd")
+    scene = synth.small_drive(7, n_frames=2)
+    step = _step_for(scene)
+    step.run()
+    torch.cuda.synchronize()
+    ds = step.ds
+    q = ds.quat.clone().requires_grad_(True)
+    sc = ds.scale.clone().requires_grad_(True)
+    op = ds.opacity.clone().requires_grad_(True)
+    co = ds.color.clone().requires_grad_(True)
+    xi = step.xi.clone().requires_grad_(True)
+    dl = step.delta.clone().requires_grad_(True)
+    img = pl.SplatRender.apply(q, sc, op, co, xi, dl, step.fr, ds)
+    loss = (img - step.targets).abs().mean()
+    loss.backward()
+    for a, b in ((co.grad, step.gr.color), (xi.grad, step.gr.xi), (dl.grad, step.gr.delta), (q.grad, step.gr.quat)):
+        ok, err = rel_close(a.detach().cpu().numpy(), b.cpu().numpy(), 1e-4)
+        assert ok, err
+
+
+def test_per_view_plain_matches_batched():
+    say("case: per-view plain vs batched")
+    scene = synth.small_drive(8, n_frames=2)
+    step = _step_for(scene)
+    step.run()
+    torch.cuda.synchronize()
+    pv = pl.PerViewPlain(step.ds, step.xi, step.delta, pl.make_settings())
+    gr = pl.alloc_grads(step.ds)
+    pv.step(step.xi, step.delta, step.targets, gr)
+    torch.cuda.synchronize()
+    for v, (dv, fr, _) in enumerate(pv.views):
+        assert torch.equal(fr.img[0], step.fr.img[v])
+        assert torch.equal(fr.T[0], step.fr.T[v])
+    for a, b in ((gr.color, step.gr.color), (gr.xi, step.gr.xi), (gr.delta, step.gr.delta)):
+        ok, err = rel_close(a.cpu().numpy(), b.cpu().numpy(), 1e-4)
+        assert ok, err
