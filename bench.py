@@ -48,6 +48,8 @@ def main():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--small", action="store_true", help="tiny smoke workload instead of the 64-view drive")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first copy this many MiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding of this "
@@ -62,6 +64,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda"
+    if args.copy_probe_mb > 0:
+        src = torch.ones(args.copy_probe_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe_mb} MiB device-to-device")
+        del src, dst
     t0 = time.time()
     if args.small:
         scene = synth.small_drive(0, n_points=3000, W=256, H=96, f=120.0, n_frames=4)

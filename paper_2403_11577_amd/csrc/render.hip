@@ -40,41 +40,86 @@ struct RenderArgs {
     const uint32_t *counts;     // device counts (slots, instances)
     unsigned long long *stats;  // pair counters of the instrumented variant
     int n_items, T, tiles_x, W, H, persistent;
-    float amin, amax, tmin;
+    float amin, amax, tmin, lamin2;  // lamin2 = log2(alpha_min)
     float bg0, bg1, bg2;
 };
 
-// one Gaussian as staged for a tile: block-relative mean, conic pre-scaled by
-// -1/2 log2(e) (A, Cc) and -log2(e) (Bc), opacity, colour
+// One Gaussian as staged for a tile: mean relative to the enclosing 32x32
+// block, conic pre-scaled by -1/2 log2(e) (A, Cc) and -log2(e) (Bc), log2 of the
+// opacity (folded into the exponent: alpha = min(alpha_max, 2^(power2 + lo2))),
+// 1/opacity, colour, and the mask of the tile's 8x8 sub-blocks that its
+// alpha >= alpha_min footprint can reach (padded by 1% + 0.6 px; a sub-block
+// outside it only ever evaluates alpha < alpha_min).
 struct Stage {
-    float mx, my, A, Bc, Cc, o, r, g, b;
+    float mx, my, A, Bc, Cc, lo2, io, r, g, b;
+    uint32_t slot, mask;
+};
+
+// The gather of a batch is split so that it can be in flight while the previous
+// batch is evaluated: slot ids two batches ahead, raw records one batch ahead,
+// and the derivation of the staged values after the evaluation loop.
+struct Raw {
+    float4 r0, r1, r2;
     uint32_t slot;
 };
 
-__device__ __forceinline__ Stage stage_load(const RenderArgs &a, uint32_t idx, uint32_t end, uint32_t nslots,
-                                            float xb, float yb) {
+__device__ __forceinline__ uint32_t load_slot(const RenderArgs &a, uint32_t idx, uint32_t end) {
+    uint32_t v = a.vals[idx < end ? idx : 0u];  // vals[0] exists whenever this runs (end > 0)
+    return idx < end ? v : 0xFFFFFFFFu;
+}
+
+// Unconditional gather (a branch here would make the compiler wait for the data
+// to merge registers): an invalid slot reads record 0, which always exists, and
+// is marked invalid.  (A slot id outside the slot count cannot come out of the
+// sort; it is treated as transparent.)
+__device__ __forceinline__ Raw load_raw(const RenderArgs &a, uint32_t slot, uint32_t nslots) {
+    Raw r;
+    bool ok = slot < nslots;
+    size_t s = ok ? (size_t)slot : 0;
+    r.slot = ok ? slot : 0xFFFFFFFFu;
+    r.r0 = a.rec[3 * s + 0];
+    r.r1 = a.rec[3 * s + 1];
+    r.r2 = a.rec[3 * s + 2];
+    return r;
+}
+
+template <int TW, int TH>
+__device__ __forceinline__ Stage derive(const RenderArgs &a, const Raw &raw, float xb, float yb, float ox, float oy) {
+    constexpr int SBX = TW / 8, NSB = TW * TH / 64;
     Stage s;
-    s.mx = s.my = s.A = s.Bc = s.Cc = s.o = s.r = s.g = s.b = 0.f;
-    s.slot = 0xFFFFFFFFu;
-    if (idx < end) {
-        uint32_t slot = a.vals[idx];
-        // (a slot id outside the slot count cannot come out of the sort; it stays transparent)
-        if (slot < nslots) {
-            float4 r0 = a.rec[3 * (size_t)slot + 0];
-            float4 r1 = a.rec[3 * (size_t)slot + 1];
-            float4 r2 = a.rec[3 * (size_t)slot + 2];
-            s.mx = (r0.x - xb) + r0.z;
-            s.my = (r0.y - yb) + r0.w;
-            s.A = -0.5f * LOG2E * r1.x;
-            s.Bc = -LOG2E * r1.y;
-            s.Cc = -0.5f * LOG2E * r1.z;
-            s.o = r1.w;
-            s.r = r2.x;
-            s.g = r2.y;
-            s.b = r2.z;
-            s.slot = slot;
-        }
+    s.slot = raw.slot;
+    s.mx = (raw.r0.x - xb) + raw.r0.z;
+    s.my = (raw.r0.y - yb) + raw.r0.w;
+    s.A = -0.5f * LOG2E * raw.r1.x;
+    s.Bc = -LOG2E * raw.r1.y;
+    s.Cc = -0.5f * LOG2E * raw.r1.z;
+    float o = raw.r1.w;
+    bool valid = raw.slot != 0xFFFFFFFFu && o > 0.f;
+    s.lo2 = valid ? __log2f(o) : -256.f;
+    s.io = valid ? __builtin_amdgcn_rcpf(o) : 0.f;
+    s.r = raw.r2.x;
+    s.g = raw.r2.y;
+    s.b = raw.r2.z;
+    // footprint box: half-widths k sqrt(Sigma2_ii), Sigma2 = conic^-1, k^2 = 2 ln(o / alpha_min)
+    float ca = raw.r1.x, cb = raw.r1.y, cc = raw.r1.z;
+    float idet = __builtin_amdgcn_rcpf(fmaxf(ca * cc - cb * cb, 1e-30f));
+    float k2 = fmaxf(2.f * LN2 * (s.lo2 - a.lamin2), 0.f);
+    float rx = sqrtf(k2 * cc * idet) * 1.01f + 0.6f;
+    float ry = sqrtf(k2 * ca * idet) * 1.01f + 0.6f;
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < NSB; ++k) {
+        float bx = ox + 8.f * (float)(k % SBX) + 0.5f;  // first pixel centre of the sub-block
+        float by = oy + 8.f * (float)(k / SBX) + 0.5f;
+        bool hit = (s.mx + rx >= bx) && (s.mx - rx <= bx + 7.f) && (s.my + ry >= by) && (s.my - ry <= by + 7.f);
+        m |= hit ? (1u << k) : 0u;
     }
+    s.mask = valid ? m : 0u;
+    // keep the derived values materialised here: otherwise the compiler may
+    // recompute them from the raw registers at the top of the next evaluation
+    // loop, after the next gather has been issued, and wait for that gather
+    asm volatile("" : "+v"(s.mx), "+v"(s.my), "+v"(s.A), "+v"(s.Bc), "+v"(s.Cc), "+v"(s.lo2));
+    asm volatile("" : "+v"(s.io), "+v"(s.r), "+v"(s.g), "+v"(s.b), "+v"(s.slot), "+v"(s.mask));
     return s;
 }
 
@@ -82,9 +127,13 @@ __device__ __forceinline__ float bcast(float v, int j) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
 }
 
-// exponent in log2 units: A dx^2 + Bc dx dy + Cc dy^2
-__device__ __forceinline__ float power2(float dx, float dy, float A, float Bc, float Cc) {
-    return __fmaf_rn(dx, __fmaf_rn(A, dx, Bc * dy), (Cc * dy) * dy);
+__device__ __forceinline__ uint32_t bcast_u(uint32_t v, int j) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, j);
+}
+
+// exponent in log2 units including log2(opacity): A dx^2 + Bc dx dy + Cc dy^2 + lo2
+__device__ __forceinline__ float power2(float dx, float dy, float A, float Bc, float Cc, float lo2) {
+    return __fmaf_rn(dx, __fmaf_rn(A, dx, Bc * dy), __fmaf_rn(Cc * dy, dy, lo2));
 }
 
 __device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -127,12 +176,20 @@ __device__ __forceinline__ bool next_item(const RenderArgs &a, int iter, int &it
     return item < a.n_items;
 }
 
+// Pixel layout: lane l covers pixel (l & 7, l >> 3) of every 8x8 sub-block k of
+// the tile (k row-major over the TW/8 x TH/8 sub-blocks).
+//
+// Forward state per pixel: T > 0 while the pixel is still compositing; when a
+// blend would take T below t_min the pixel stops, its T is kept in Tf and T is
+// set to 0, which makes every later pair of that pixel a no-op without a branch.
+//
 // STATS = true is the instrumented variant (pair counters for the roofline);
 // it computes exactly the same outputs.
 template <int TW, int TH, bool STATS>
 __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img, float *Tout, int32_t *lastout) {
-    constexpr int PPT = TW * TH / 64;
+    constexpr int NSB = TW * TH / 64, SBX = TW / 8;
     const int lane = threadIdx.x;
+    const int lx = lane & 7, ly = lane >> 3;
     const size_t HW = (size_t)a.W * a.H;
     const uint32_t nslots = a.counts[CNT_SLOTS];
     unsigned long long n_eval = 0, n_blend = 0;
@@ -144,66 +201,71 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
         int x0 = tx * TW, y0 = ty * TH;
         int xb = x0 & ~31, yb = y0 & ~31;
         uint2 rg = a.ranges[tid];
-        float Tr[PPT], C0[PPT], C1[PPT], C2[PPT], px[PPT], py[PPT];
-        int last[PPT];
-        bool alive[PPT];
+        float T[NSB], Tf[NSB], C0[NSB], C1[NSB], C2[NSB], px[NSB], py[NSB];
+        int last[NSB];
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            int p = lane + 64 * k;
-            int lx = p % TW, ly = p / TW;
-            px[k] = (float)(x0 - xb + lx) + 0.5f;
-            py[k] = (float)(y0 - yb + ly) + 0.5f;
-            Tr[k] = 1.f;
+        for (int k = 0; k < NSB; ++k) {
+            int qx = 8 * (k % SBX) + lx, qy = 8 * (k / SBX) + ly;
+            px[k] = (float)(x0 - xb + qx) + 0.5f;
+            py[k] = (float)(y0 - yb + qy) + 0.5f;
+            T[k] = (x0 + qx < a.W && y0 + qy < a.H) ? 1.f : 0.f;
+            Tf[k] = 1.f;
             C0[k] = C1[k] = C2[k] = 0.f;
             last[k] = -1;
-            alive[k] = (x0 + lx < a.W) && (y0 + ly < a.H);
         }
-        Stage cur = stage_load(a, rg.x + lane, rg.y, nslots, (float)xb, (float)yb);
+        const float fxb = (float)xb, fyb = (float)yb, fox = (float)(x0 - xb), foy = (float)(y0 - yb);
+        Stage cur = derive<TW, TH>(a, load_raw(a, load_slot(a, rg.x + lane, rg.y), nslots), fxb, fyb, fox, foy);
+        uint32_t sl_next = load_slot(a, rg.x + 64 + lane, rg.y);
         for (uint32_t b = rg.x; b < rg.y; b += 64) {
             bool any = false;
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) any |= alive[k];
+            for (int k = 0; k < NSB; ++k) any |= T[k] > 0.f;
             if (__ballot(any) == 0) break;
-            Stage nxt = stage_load(a, b + 64 + lane, rg.y, nslots, (float)xb, (float)yb);
+            Raw raw_next = load_raw(a, sl_next, nslots);              // records of batch b + 64
+            uint32_t sl_after = load_slot(a, b + 128 + lane, rg.y);   // slot ids of batch b + 128
             int n = (int)min(64u, rg.y - b);
             for (int j = 0; j < n; ++j) {
+                uint32_t m = bcast_u(cur.mask, j);
+                if (m == 0u) continue;
                 float mx = bcast(cur.mx, j), my = bcast(cur.my, j);
-                float A = bcast(cur.A, j), Bc = bcast(cur.Bc, j), Cc = bcast(cur.Cc, j);
-                float o = bcast(cur.o, j);
+                float A = bcast(cur.A, j), Bc = bcast(cur.Bc, j), Cc = bcast(cur.Cc, j), lo2 = bcast(cur.lo2, j);
+                float cr = bcast(cur.r, j), cg = bcast(cur.g, j), cb = bcast(cur.b, j);
+                int idx = (int)(b + j);
 #pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    if (!alive[k]) continue;
-                    if (STATS) ++n_eval;
+                for (int k = 0; k < NSB; ++k) {
+                    if (!(m & (1u << k))) continue;  // wave-uniform
+                    if (STATS) n_eval += T[k] > 0.f;
                     float dx = px[k] - mx, dy = py[k] - my;
-                    float al = fminf(a.amax, o * exp2_hw(power2(dx, dy, A, Bc, Cc)));
-                    if (al < a.amin) continue;
-                    float Tn = Tr[k] * (1.f - al);
-                    if (Tn < a.tmin) {
-                        alive[k] = false;
-                        continue;
-                    }
-                    if (STATS) ++n_blend;
-                    float w = al * Tr[k];
-                    C0[k] = __fmaf_rn(bcast(cur.r, j), w, C0[k]);
-                    C1[k] = __fmaf_rn(bcast(cur.g, j), w, C1[k]);
-                    C2[k] = __fmaf_rn(bcast(cur.b, j), w, C2[k]);
-                    Tr[k] = Tn;
-                    last[k] = (int)(b + j);
+                    float al = fminf(a.amax, exp2_hw(power2(dx, dy, A, Bc, Cc, lo2)));
+                    al = al >= a.amin ? al : 0.f;
+                    float w = al * T[k];
+                    float Tn = T[k] - w;
+                    bool stop = (Tn < a.tmin) && (T[k] > 0.f);
+                    Tf[k] = stop ? T[k] : Tf[k];
+                    w = stop ? 0.f : w;
+                    Tn = stop ? 0.f : Tn;
+                    if (STATS) n_blend += w > 0.f;
+                    C0[k] = __fmaf_rn(cr, w, C0[k]);
+                    C1[k] = __fmaf_rn(cg, w, C1[k]);
+                    C2[k] = __fmaf_rn(cb, w, C2[k]);
+                    last[k] = w > 0.f ? idx : last[k];
+                    T[k] = Tn;
                 }
             }
-            cur = nxt;
+            cur = derive<TW, TH>(a, raw_next, fxb, fyb, fox, foy);
+            sl_next = sl_after;
         }
+        size_t vo = (size_t)v * HW;
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            int p = lane + 64 * k;
-            int gx = x0 + p % TW, gy = y0 + p / TW;
+        for (int k = 0; k < NSB; ++k) {
+            int gx = x0 + 8 * (k % SBX) + lx, gy = y0 + 8 * (k / SBX) + ly;
             if (gx >= a.W || gy >= a.H) continue;
             size_t o = (size_t)gy * a.W + gx;
-            size_t vo = (size_t)v * HW;
-            img[3 * vo + o] = __fmaf_rn(Tr[k], a.bg0, C0[k]);
-            img[3 * vo + HW + o] = __fmaf_rn(Tr[k], a.bg1, C1[k]);
-            img[3 * vo + 2 * HW + o] = __fmaf_rn(Tr[k], a.bg2, C2[k]);
-            Tout[vo + o] = Tr[k];
+            float Tfin = T[k] > 0.f ? T[k] : Tf[k];
+            img[3 * vo + o] = __fmaf_rn(Tfin, a.bg0, C0[k]);
+            img[3 * vo + HW + o] = __fmaf_rn(Tfin, a.bg1, C1[k]);
+            img[3 * vo + 2 * HW + o] = __fmaf_rn(Tfin, a.bg2, C2[k]);
+            Tout[vo + o] = Tfin;
             lastout[vo + o] = last[k];
         }
     }
@@ -213,11 +275,19 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
     }
 }
 
+// Backward: each pixel walks from its last contributor towards the list start,
+// recovering T_j = T_{j+1} / (1 - alpha_j) and the suffix colour
+// S_j = sum_{i>j} c_i alpha_i T_i + T_final bg, and forms
+//   dL/dc_j     = alpha_j T_j dL/dC
+//   dL/dalpha_j = dL/dC . (c_j T_j - S_j / (1 - alpha_j))
+// then dL/dpower = alpha dL/dalpha and dL/do = dL/dalpha alpha / o (unless
+// alpha was clamped at alpha_max), dL/d(conic) and dL/d(mean) from the power.
 template <int TW, int TH, bool STATS>
 __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const float *dimg, const float *Tin,
                                                        const int32_t *lastin, float *grad2d) {
-    constexpr int PPT = TW * TH / 64;
+    constexpr int NSB = TW * TH / 64, SBX = TW / 8;
     const int lane = threadIdx.x;
+    const int lx = lane & 7, ly = lane >> 3;
     const size_t HW = (size_t)a.W * a.H;
     const uint32_t nslots = a.counts[CNT_SLOTS];
     unsigned long long n_eval = 0, n_contrib = 0, n_atomic = 0;
@@ -229,96 +299,105 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
         int x0 = tx * TW, y0 = ty * TH;
         int xb = x0 & ~31, yb = y0 & ~31;
         uint2 rg = a.ranges[tid];
-        float Tr[PPT], S0[PPT], S1[PPT], S2[PPT], gc0[PPT], gc1[PPT], gc2[PPT], px[PPT], py[PPT];
-        int last[PPT];
-        int mymax = -1;
+        float T[NSB], S0[NSB], S1[NSB], S2[NSB], gc0[NSB], gc1[NSB], gc2[NSB], px[NSB], py[NSB];
+        int last[NSB], kmax[NSB];
         size_t vo = (size_t)v * HW;
+        int wmax = -1;
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            int p = lane + 64 * k;
-            int lx = p % TW, ly = p / TW;
-            px[k] = (float)(x0 - xb + lx) + 0.5f;
-            py[k] = (float)(y0 - yb + ly) + 0.5f;
-            int gx = x0 + lx, gy = y0 + ly;
+        for (int k = 0; k < NSB; ++k) {
+            int qx = 8 * (k % SBX) + lx, qy = 8 * (k / SBX) + ly;
+            px[k] = (float)(x0 - xb + qx) + 0.5f;
+            py[k] = (float)(y0 - yb + qy) + 0.5f;
+            int gx = x0 + qx, gy = y0 + qy;
             last[k] = -1;
-            Tr[k] = 1.f;
+            T[k] = 1.f;
             gc0[k] = gc1[k] = gc2[k] = 0.f;
             if (gx < a.W && gy < a.H) {
                 size_t o = (size_t)gy * a.W + gx;
                 last[k] = lastin[vo + o];
                 // a position outside this tile's list cannot come from render_fwd; ignore it
                 if (last[k] < (int)rg.x || last[k] >= (int)rg.y) last[k] = -1;
-                Tr[k] = Tin[vo + o];
+                T[k] = Tin[vo + o];
                 gc0[k] = dimg[3 * vo + o];
                 gc1[k] = dimg[3 * vo + HW + o];
                 gc2[k] = dimg[3 * vo + 2 * HW + o];
             }
-            S0[k] = Tr[k] * a.bg0;
-            S1[k] = Tr[k] * a.bg1;
-            S2[k] = Tr[k] * a.bg2;
-            mymax = max(mymax, last[k]);
-        }
-        // walk [rg.x, hi) backwards, hi = 1 + the wave's last contributor
+            S0[k] = T[k] * a.bg0;
+            S1[k] = T[k] * a.bg1;
+            S2[k] = T[k] * a.bg2;
+            int mk = last[k];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) mymax = max(mymax, __shfl_xor(mymax, o, kWave));
-        int hi = mymax + 1;
+            for (int o = 32; o > 0; o >>= 1) mk = max(mk, __shfl_xor(mk, o, kWave));
+            kmax[k] = __builtin_amdgcn_readfirstlane(mk);  // per sub-block: walk no further than this
+            wmax = max(wmax, kmax[k]);
+        }
+        int hi = wmax + 1;  // walk [rg.x, hi) backwards
         if (hi <= (int)rg.x) continue;
+        const float fxb = (float)xb, fyb = (float)yb, fox = (float)(x0 - xb), foy = (float)(y0 - yb);
         int e = hi;
         int bs = max((int)rg.x, e - 64);
-        Stage cur = stage_load(a, (uint32_t)(bs + lane), (uint32_t)e, nslots, (float)xb, (float)yb);
+        Stage cur = derive<TW, TH>(a, load_raw(a, load_slot(a, (uint32_t)(bs + lane), (uint32_t)e), nslots), fxb,
+                                   fyb, fox, foy);
+        int bs2 = max((int)rg.x, bs - 64);
+        uint32_t sl_next = load_slot(a, (uint32_t)(bs2 + lane), (uint32_t)bs);
         while (e > (int)rg.x) {
             int n = e - bs;
-            int e2 = bs, bs2 = max((int)rg.x, bs - 64);
-            Stage nxt = stage_load(a, (uint32_t)(bs2 + lane), (uint32_t)e2, nslots, (float)xb, (float)yb);
+            int e2 = bs;
+            int bs3 = max((int)rg.x, bs2 - 64);
+            Raw raw_next = load_raw(a, sl_next, nslots);                                 // batch [bs2, bs)
+            uint32_t sl_after = load_slot(a, (uint32_t)(bs3 + lane), (uint32_t)bs2);   // batch [bs3, bs2)
             for (int j = n - 1; j >= 0; --j) {
+                uint32_t m = bcast_u(cur.mask, j);
+                if (m == 0u) continue;
                 int idx = bs + j;
                 float mx = bcast(cur.mx, j), my = bcast(cur.my, j);
-                float A = bcast(cur.A, j), Bc = bcast(cur.Bc, j), Cc = bcast(cur.Cc, j);
-                float o = bcast(cur.o, j);
-                float cr = bcast(cur.r, j), cg = bcast(cur.g, j), cb = bcast(cur.b, j);
+                float A = bcast(cur.A, j), Bc = bcast(cur.Bc, j), Cc = bcast(cur.Cc, j), lo2 = bcast(cur.lo2, j);
                 float gmx = 0.f, gmy = 0.f, ga = 0.f, gb = 0.f, gcc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
-                bool hit = false;
+                bool hit_any = false;
 #pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    if (idx > last[k]) continue;
-                    if (STATS) ++n_eval;
+                for (int k = 0; k < NSB; ++k) {
+                    if (!(m & (1u << k)) || idx > kmax[k]) continue;  // wave-uniform
                     float dx = px[k] - mx, dy = py[k] - my;
-                    float ex = exp2_hw(power2(dx, dy, A, Bc, Cc));
-                    float av = o * ex;
-                    float al = fminf(a.amax, av);
-                    if (al < a.amin) continue;
-                    if (STATS) ++n_contrib;
-                    hit = true;
-                    float iom = __builtin_amdgcn_rcpf(1.f - al);
-                    float Tj = Tr[k] * iom;
-                    float w = al * Tj;
-                    gr = __fmaf_rn(w, gc0[k], gr);
-                    gg = __fmaf_rn(w, gc1[k], gg);
-                    gbl = __fmaf_rn(w, gc2[k], gbl);
-                    float dal = gc0[k] * __fmaf_rn(cr, Tj, -S0[k] * iom) + gc1[k] * __fmaf_rn(cg, Tj, -S1[k] * iom) +
-                                gc2[k] * __fmaf_rn(cb, Tj, -S2[k] * iom);
-                    S0[k] = __fmaf_rn(cr, w, S0[k]);
-                    S1[k] = __fmaf_rn(cg, w, S1[k]);
-                    S2[k] = __fmaf_rn(cb, w, S2[k]);
-                    Tr[k] = Tj;
-                    if (av < a.amax) {
-                        go = __fmaf_rn(dal, ex, go);
-                        float dp = dal * al;
-                        float hdx = 0.5f * dx, hdy = 0.5f * dy;
-                        ga = __fmaf_rn(-dp * hdx, dx, ga);
-                        gb = __fmaf_rn(-dp * dx, dy, gb);
-                        gcc = __fmaf_rn(-dp * hdy, dy, gcc);
-                        // d power / d mu = (a dx + b dy, b dx + c dy) with a = -2 ln2 A, b = -ln2 Bc, c = -2 ln2 Cc
-                        gmx = __fmaf_rn(dp, -LN2 * __fmaf_rn(2.f * A, dx, Bc * dy), gmx);
-                        gmy = __fmaf_rn(dp, -LN2 * __fmaf_rn(Bc, dx, 2.f * Cc * dy), gmy);
+                    float al = fminf(a.amax, exp2_hw(power2(dx, dy, A, Bc, Cc, lo2)));
+                    bool hit = (idx <= last[k]) && (al >= a.amin);
+                    if (STATS) n_eval += idx <= last[k];
+                    if (__ballot(hit) == 0) continue;
+                    hit_any = true;
+                    if (hit) {
+                        if (STATS) ++n_contrib;
+                        float cr = bcast(cur.r, j), cg = bcast(cur.g, j), cb = bcast(cur.b, j);
+                        float iom = __builtin_amdgcn_rcpf(1.f - al);
+                        float Tj = T[k] * iom;
+                        float w = al * Tj;
+                        gr = __fmaf_rn(w, gc0[k], gr);
+                        gg = __fmaf_rn(w, gc1[k], gg);
+                        gbl = __fmaf_rn(w, gc2[k], gbl);
+                        float dal = gc0[k] * __fmaf_rn(cr, Tj, -S0[k] * iom) +
+                                    gc1[k] * __fmaf_rn(cg, Tj, -S1[k] * iom) +
+                                    gc2[k] * __fmaf_rn(cb, Tj, -S2[k] * iom);
+                        S0[k] = __fmaf_rn(cr, w, S0[k]);
+                        S1[k] = __fmaf_rn(cg, w, S1[k]);
+                        S2[k] = __fmaf_rn(cb, w, S2[k]);
+                        T[k] = Tj;
+                        if (al < a.amax) {
+                            float dp = dal * al;
+                            go = __fmaf_rn(dp, bcast(cur.io, j), go);
+                            float hdx = 0.5f * dx, hdy = 0.5f * dy;
+                            ga = __fmaf_rn(-dp * hdx, dx, ga);
+                            gb = __fmaf_rn(-dp * dx, dy, gb);
+                            gcc = __fmaf_rn(-dp * hdy, dy, gcc);
+                            // d power / d mu = (a dx + b dy, b dx + c dy), a = -2 ln2 A, b = -ln2 Bc, c = -2 ln2 Cc
+                            gmx = __fmaf_rn(dp, -LN2 * __fmaf_rn(2.f * A, dx, Bc * dy), gmx);
+                            gmy = __fmaf_rn(dp, -LN2 * __fmaf_rn(Bc, dx, 2.f * Cc * dy), gmy);
+                        }
                     }
                 }
-                if (__ballot(hit) == 0) continue;
+                if (!hit_any) continue;
                 float s0 = lane63(wave_sum63(gmx)), s1 = lane63(wave_sum63(gmy));
                 float s2 = lane63(wave_sum63(ga)), s3 = lane63(wave_sum63(gb)), s4 = lane63(wave_sum63(gcc));
                 float s5 = lane63(wave_sum63(go));
                 float s6 = lane63(wave_sum63(gr)), s7 = lane63(wave_sum63(gg)), s8 = lane63(wave_sum63(gbl));
-                uint32_t slot = (uint32_t)__builtin_amdgcn_readlane((int)cur.slot, j);
+                uint32_t slot = bcast_u(cur.slot, j);
                 if (STATS && lane == 0) ++n_atomic;
                 if (lane < 9) {
                     float val = lane == 0 ? s0 : lane == 1 ? s1 : lane == 2 ? s2 : lane == 3 ? s3 :
@@ -326,9 +405,11 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
                     atomicAdd(grad2d + 9 * (size_t)slot + lane, val);
                 }
             }
-            cur = nxt;
+            cur = derive<TW, TH>(a, raw_next, fxb, fyb, fox, foy);
+            sl_next = sl_after;
             e = e2;
             bs = bs2;
+            bs2 = bs3;
         }
     }
     if (STATS) {
@@ -364,6 +445,7 @@ RenderArgs make_args(const splat_plan &p, void *ws, unsigned long long *stats) {
     a.amin = (float)p.s.alpha_min;
     a.amax = (float)p.s.alpha_max;
     a.tmin = (float)p.s.t_min;
+    a.lamin2 = (float)log2(p.s.alpha_min);
     a.bg0 = (float)p.s.bg[0];
     a.bg1 = (float)p.s.bg[1];
     a.bg2 = (float)p.s.bg[2];
@@ -372,7 +454,8 @@ RenderArgs make_args(const splat_plan &p, void *ws, unsigned long long *stats) {
 
 int persistent_grid(int n_items, int wg_per_cu) {
     int dev = 0, ncu = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        ncu = 256;
     int g = ncu * wg_per_cu;
     return g < n_items ? g : n_items;
 }

@@ -33,15 +33,16 @@ __all__ = [
     "Gaussians", "Trajectory", "Rig", "Views", "Scene",
     "tiny_scene", "tiny_target", "kitti_single", "calib16", "batched64",
     "calib_full", "small_drive", "random_rigid", "perturbation",
-    "quat_from_euler", "CONFIG_NAMES",
+    "quat_from_euler", "WORKLOADS",
 ]
 
-CONFIG_NAMES = {
-    0: "tiny_2k_256x64",
-    1: "kitti_single_500k_1408x376",
-    2: "calib_2cam_8frame_500k_1408x376",
-    3: "batched_uneven_64v_2M_1408x376",
-    4: "calib_loop_2cam_100frame_2M_1408x376",
+# workload name of every generator
+WORKLOADS = {
+    "tiny_scene": "tiny_2k_256x64",
+    "kitti_single": "kitti_single_500k_1408x376",
+    "calib16": "calib_2cam_8frame_500k_1408x376",
+    "batched64": "batched_uneven_64v_2M_1408x376",
+    "calib_full": "calib_loop_2cam_100frame_2M_1408x376",
 }
 
 
@@ -187,7 +188,7 @@ def random_rigid(rng, max_angle=math.pi, max_t=10.0):
 
 
 # ----------------------------------------------------------------------------
-# configs[0]-style tiny scene
+# tiny scene: 2,000 Gaussians, one 256x64 camera
 # ----------------------------------------------------------------------------
 def tiny_scene(seed=0, n=2000, W=256, H=64, f=200.0):
     """2,000 Gaussians in front of an identity camera (camera = LiDAR = world).
@@ -471,7 +472,8 @@ def calib16(seed=0, n_points=500_000, W=1408, H=376, f=552.0, deg=5.0, metres=0.
 
 def small_drive(seed=0, n_points=3000, W=96, H=40, f=40.0, n_cams=2, n_frames=2,
                 deg=5.0, metres=0.3, delta=0.05, n_boxes=30, n_rings=16, az_step=1.0):
-    """A configs[2]-shaped calibration problem small enough for CPU finite differences."""
+    """The two-camera calibration problem (arc drive, 10 Hz poses, perturbed extrinsic and
+    time offset) at a size small enough for CPU finite differences."""
     rng = np.random.default_rng(seed)
 
     def arc(s):

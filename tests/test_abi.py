@@ -1,0 +1,110 @@
+"""The C ABI on the host: the library loads without a GPU, exports every symbol that
+include/splat.h declares, its struct mirrors match, and argument checks reject bad
+calls synchronously (nothing is launched, so no device is needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2403_11577_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "splat.h")).read()
+    return sorted(set(re.findall(r"SPLAT_API\s+[\w\s\*]+?\b(splat_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_symbols()
+    assert len(names) >= 15
+    L = B.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_struct_sizes_match_library():
+    L = B.lib()
+    assert L.splat_struct_size(0) == C.sizeof(B.splat_settings)
+    assert L.splat_struct_size(1) == C.sizeof(B.splat_gaussians)
+    assert L.splat_struct_size(2) == C.sizeof(B.splat_plan)
+
+
+def test_default_settings_are_the_documented_readings():
+    s = B.default_settings()
+    assert (s.near_z, s.far_z, s.eps2d, s.alpha_max, s.t_min, s.guard) == (0.2, 256.0, 0.3, 0.99, 1e-4, 0.15)
+    assert abs(s.alpha_min - 1 / 255) < 1e-15
+    assert (s.tile_w, s.tile_h) == (16, 16)
+
+
+def test_plan_layout_is_aligned_and_disjoint():
+    s = B.default_settings()
+    p = B.splat_plan_make(s, 3, 1000, 100, 37, 2000, 9000)
+    offs = sorted((getattr(p, n), n) for n in B._PLAN_OFFS if n != "ws_bytes")
+    assert all(o % 256 == 0 for o, _ in offs)
+    assert offs[-1][0] < p.ws_bytes
+    assert p.tiles_x == 7 and p.tiles_y == 3 and p.tiles_per_view == 21
+    # key = (view*T + tile) << depth_bits | depth: 63 items need 6 bits, the 0.2..256 m window 27
+    assert p.tile_bits == 6 and p.depth_bits == 27
+    assert p.sorted_buf == ((p.tile_bits + p.depth_bits + 7) // 8) % 2
+
+
+@pytest.mark.parametrize("kw, msg", [
+    (dict(n_views=0), "n_views"),
+    (dict(width=0), "image size"),
+    (dict(slot_cap=0), "capacities"),
+    (dict(inst_cap=1 << 31), "capacities"),
+])
+def test_plan_make_rejects_bad_shapes(kw, msg):
+    args = dict(n_views=2, n_gauss=100, width=64, height=48, slot_cap=100, inst_cap=1000)
+    args.update(kw)
+    with pytest.raises(B.SplatError, match=msg):
+        B.splat_plan_make(B.default_settings(), **args)
+
+
+@pytest.mark.parametrize("field, value", [
+    ("tile_w", 12), ("batch", 8), ("batch", 300), ("near_z", 0.0), ("far_z", 0.1),
+    ("alpha_min", 0.0), ("alpha_max", 1.0), ("t_min", 0.0), ("eps2d", -1.0), ("persistent", 2),
+])
+def test_plan_make_rejects_bad_settings(field, value):
+    s = B.default_settings()
+    setattr(s, field, value)
+    with pytest.raises(B.SplatError):
+        B.splat_plan_make(s, 1, 10, 64, 64, 10, 10)
+
+
+def test_too_many_work_items_is_unsupported():
+    # 1023 views of 2048 x 2048 8x8 tiles exceed the 2^31 (view, tile) items the key and queue allow
+    s = B.default_settings()
+    s.far_z = 1e30   # 30 depth bits: with at most 31 tile bits the key stays within 64 bits
+    s.tile_w = s.tile_h = 8
+    rc = B.lib().splat_plan_make(C.byref(s), 1023, 10, 16384, 16384, 10, 10, C.byref(B.splat_plan()))
+    assert rc == -2
+    assert b"too many" in B.lib().splat_last_error()
+    p = B.splat_plan_make(s, 1, 10, 1408, 376, 10, 10)
+    assert p.depth_bits == 30
+
+
+def test_entry_points_reject_null_arguments_without_a_device():
+    L = B.lib()
+    s = B.default_settings()
+    p = B.splat_plan_make(s, 1, 10, 64, 64, 10, 100)
+    g = B.splat_gaussians()
+    g.n = 10
+    assert L.splat_project(None, None, None, None, None, None) == -1
+    assert L.splat_project(C.byref(p), None, C.byref(g), None, None, None) == -1
+    assert L.splat_project(C.byref(p), C.c_void_p(16), C.byref(g), None, None, None) == -1  # NULL planes
+    g.n = 11
+    assert L.splat_project(C.byref(p), C.c_void_p(16), C.byref(g), C.c_void_p(16), C.c_void_p(16), None) == -1
+    assert b"plan was made for" in L.splat_last_error()
+    assert L.splat_bin_sort(C.byref(p), None, None) == -1
+    assert L.splat_render_fwd(C.byref(p), C.c_void_p(16), None, None, None, None) == -1
+    assert L.splat_render_bwd(C.byref(p), C.c_void_p(16), None, None, None, None) == -1
+    assert L.splat_pose_interp_fwd(1, *([None] * 3), 1, *([None] * 4), 1, None, None, None, None, None) == -1
+    assert b"2 trajectory knots" in L.splat_last_error()
+    assert L.splat_l1_loss_grad(None, None, None, 1, 4, 4, None, None, None) == -1
+    bad = B.splat_plan()  # all zeros: not made by splat_plan_make
+    assert L.splat_bin_sort(C.byref(bad), C.c_void_p(16), None) == -1
+    assert b"not initialised" in L.splat_last_error()
