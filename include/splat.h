@@ -105,7 +105,7 @@ typedef struct splat_plan {
     size_t off_status;      /* u32                                                      */
     size_t off_counts;      /* u32[8]: 0 slots, 1 instances, 2 work counter, 3..7 spare  */
     size_t off_view_off;    /* u32[V+1] first slot of every view                          */
-    size_t off_blockcnt;    /* u32[V*n_blocks_proj] visible count per project block      */
+    size_t off_blockcnt;    /* u32[V*n_blocks_proj+1] visible count per project block, scanned in place to slot offsets */
     size_t off_rec;         /* float4[3][slot_cap]: (mx,my,lx,ly) (a,b,c,o) (r,g,b,depth) */
     size_t off_meta;        /* int2[slot_cap]: (Gaussian id, view)                       */
     size_t off_rect;        /* u16x4[slot_cap]: tile rect (x0,x1,y0,y1) inclusive         */
@@ -117,6 +117,7 @@ typedef struct splat_plan {
     size_t off_hist;        /* u32[256*n_sort_blocks + 1024] radix / queue histograms     */
     size_t off_scan;        /* u32[scan partials]                                        */
     size_t off_grad2d;      /* float[slot_cap][9]: d(mu x,y; conic a,b,c; o; r,g,b)       */
+    size_t off_visbits;     /* u64[V*n_blocks_proj*4]: visible (view, Gaussian) bit masks  */
     int32_t sorted_buf;     /* which of the two key/value buffers holds the sorted result */
     int32_t reserved;
 } splat_plan;

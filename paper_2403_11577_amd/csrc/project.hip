@@ -137,7 +137,7 @@ __device__ inline uint32_t block_rank(bool vis, uint32_t *lds4, uint32_t *tot) {
 
 __global__ __launch_bounds__(256) void project_count_kernel(splat_settings S, splat_gaussians g, const double *w2c,
                                                            const double *intr, int W, int H, int nb,
-                                                           uint32_t *blockcnt, uint32_t *status) {
+                                                           uint32_t *blockcnt, uint64_t *visbits, uint32_t *status) {
     __shared__ uint32_t lds4[4];
     int v = blockIdx.y;
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -149,6 +149,8 @@ __global__ __launch_bounds__(256) void project_count_kernel(splat_settings S, sp
         code = project_gauss(S, w2c + 12 * v, intr + 4 * v, W, H, x, q, s, o, P);
     }
     flag_status(status, code);
+    uint64_t m = __ballot(code == PC_OK);
+    if (__lane_id() == 0) visbits[((size_t)v * nb + blockIdx.x) * 4 + (threadIdx.x >> 6)] = m;
     uint32_t tot;
     block_rank(code == PC_OK, lds4, &tot);
     if (threadIdx.x == 0) blockcnt[(size_t)v * nb + blockIdx.x] = tot;
@@ -208,125 +210,145 @@ __global__ void project_finish_kernel(const uint32_t *blockoff, int V, int nb, i
 // ----------------------------------------------------------------------------------
 // adjoint
 // ----------------------------------------------------------------------------------
+// Chain rule of one visible (view, Gaussian) pair from its slot gradient gd[9]
+// = d(mu x, mu y; conic a, b, c; opacity; r, g, b).  Adds the quaternion, scale
+// and mean gradients to gq, gs, gm and returns the W2C gradient in gw[12].
+__device__ void slot_adjoint(const Proj &P, const double *M, const double *K4, const float *x, const float *s,
+                             const float *gd, double *gq, double *gs, double *gm, double *gw) {
+    double gmx = gd[0], gmy = gd[1], ga = gd[2], gb = gd[3], gc = gd[4];
+    // conic -> Sigma2: G2 = -Q GQ Q with GQ = [[ga, gb/2], [gb/2, gc]]
+    double a = P.Q[0], b = P.Q[1], c = P.Q[2];
+    double hb = 0.5 * gb;
+    double m00 = a * ga + b * hb, m01 = a * hb + b * gc;
+    double m10 = b * ga + c * hb, m11 = b * hb + c * gc;
+    double g2xx = -(m00 * a + m01 * b);
+    double g2xy = -(m00 * b + m01 * c);
+    double g2yy = -(m10 * b + m11 * c);
+    // Sigma2 = T T^T + eps I -> dT = 2 G2 T
+    double gT[6];
+    for (int j = 0; j < 3; ++j) {
+        gT[j] = 2.0 * (g2xx * P.T[j] + g2xy * P.T[3 + j]);
+        gT[3 + j] = 2.0 * (g2xy * P.T[j] + g2yy * P.T[3 + j]);
+    }
+    // T = J A -> dJ = gT A^T, dA = J^T gT
+    double gJ[6], gA[9];
+    for (int r = 0; r < 2; ++r)
+        for (int k = 0; k < 3; ++k)
+            gJ[3 * r + k] = gT[3 * r] * P.A[3 * k] + gT[3 * r + 1] * P.A[3 * k + 1] + gT[3 * r + 2] * P.A[3 * k + 2];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) gA[3 * r + k] = P.J[r] * gT[k] + P.J[3 + r] * gT[3 + k];
+    // J(t), mu(t)
+    double fx = K4[0], fy = K4[1];
+    double tx = P.t[0], ty = P.t[1], tz = P.t[2];
+    double iz = 1.0 / tz, iz2 = iz * iz;
+    double gt0 = gmx * fx * iz, gt1 = gmy * fy * iz;
+    double gt2 = -(gmx * fx * tx + gmy * fy * ty) * iz2 - (gJ[0] * fx + gJ[4] * fy) * iz2;
+    if (!P.clx) {
+        gt0 += -gJ[2] * fx * iz2;
+        gt2 += 2.0 * gJ[2] * fx * tx * iz2 * iz;
+    } else {
+        gt2 += gJ[2] * fx * P.xh * iz2;
+    }
+    if (!P.cly) {
+        gt1 += -gJ[5] * fy * iz2;
+        gt2 += 2.0 * gJ[5] * fy * ty * iz2 * iz;
+    } else {
+        gt2 += gJ[5] * fy * P.yh * iz2;
+    }
+    double gt[3] = {gt0, gt1, gt2};
+    // A = W R D: dW += gA (R D)^T ; dR = W^T gA D ; ds_k = ((W R)^T gA)_kk
+    double gR[9];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) {
+            double acc = 0.0;
+            for (int m = 0; m < 3; ++m) acc += M[4 * m + r] * gA[3 * m + k];  // (W^T gA)[r][k]
+            gR[3 * r + k] = acc * (double)s[k];
+            gs[k] += P.R[3 * r + k] * acc;  // ((W R)^T gA)_kk = sum_r R[r][k] (W^T gA)[r][k]
+        }
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) {
+            double acc = 0.0;
+            for (int m = 0; m < 3; ++m) acc += gA[3 * r + m] * P.R[3 * k + m] * (double)s[m];
+            gw[4 * r + k] = acc + gt[r] * (double)x[k];
+        }
+    for (int r = 0; r < 3; ++r) gw[4 * r + 3] = gt[r];
+    for (int k = 0; k < 3; ++k) gm[k] += M[k] * gt[0] + M[4 + k] * gt[1] + M[8 + k] * gt[2];
+    // R(q_hat) -> q_hat -> q
+    double w = P.qh[0], qx = P.qh[1], qy = P.qh[2], qz = P.qh[3];
+    double gq0 = 2.0 * (-qz * gR[1] + qy * gR[2] + qz * gR[3] - qx * gR[5] - qy * gR[6] + qx * gR[7]);
+    double gq1 = 2.0 * (qy * gR[1] + qz * gR[2] + qy * gR[3] - 2.0 * qx * gR[4] - w * gR[5] + qz * gR[6] + w * gR[7] - 2.0 * qx * gR[8]);
+    double gq2 = 2.0 * (-2.0 * qy * gR[0] + qx * gR[1] + w * gR[2] + qx * gR[3] + qz * gR[5] - w * gR[6] + qz * gR[7] - 2.0 * qy * gR[8]);
+    double gq3 = 2.0 * (-2.0 * qz * gR[0] - w * gR[1] + qx * gR[2] + w * gR[3] - 2.0 * qz * gR[4] + qy * gR[5] + qx * gR[6] + qy * gR[7]);
+    double dot = w * gq0 + qx * gq1 + qy * gq2 + qz * gq3;
+    double iq = 1.0 / P.qn;
+    gq[0] += (gq0 - w * dot) * iq;
+    gq[1] += (gq1 - qx * dot) * iq;
+    gq[2] += (gq2 - qy * dot) * iq;
+    gq[3] += (gq3 - qz * dot) * iq;
+}
+
+// One thread per Gaussian walks every view; the visibility mask written by the
+// count pass and the per-block slot offsets give the slot of each visible pair
+// (slots are compacted per view in Gaussian order), so the per-Gaussian
+// gradients are summed in float64 registers and written once, without atomics.
+// The W2C gradient of each view is reduced over the workgroup in float64 and
+// added with one atomic per (workgroup, view, entry).
 __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, splat_gaussians g, const double *w2c,
-                                                         const double *intr, int W, int H,
-                                                         const uint32_t *counts, const int2 *meta,
-                                                         const float *grad2d, float *dquat, float *dscale,
-                                                         float *dopac, float *dcolor, float *dmean,
+                                                         const double *intr, int W, int H, int V, int nb,
+                                                         const uint32_t *blockoff, const uint64_t *visbits,
+                                                         int64_t slot_cap, const float *grad2d, float *dquat,
+                                                         float *dscale, float *dopac, float *dcolor, float *dmean,
                                                          double *dw2c) {
-    uint32_t nslots = counts[CNT_SLOTS];
-    int64_t n = g.n;
-    for (uint64_t base = (uint64_t)blockIdx.x * 256; base < nslots; base += (uint64_t)gridDim.x * 256) {
-        uint64_t slot = base + threadIdx.x;
-        bool act = slot < nslots;
+    __shared__ double red[4][12];
+    const int b = blockIdx.x, wv = threadIdx.x >> 6, lane = __lane_id();
+    const int64_t i = (int64_t)b * 256 + threadIdx.x;
+    const int64_t n = g.n;
+    const bool live = i < n;
+    float x[3] = {0.f, 0.f, 0.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, s[3] = {1.f, 1.f, 1.f}, o = 1.f;
+    if (live) load_gauss(g, i, x, q, s, o);
+    double gq[4] = {0, 0, 0, 0}, gs[3] = {0, 0, 0}, gm[3] = {0, 0, 0}, go = 0.0, gc[3] = {0, 0, 0};
+    for (int v = 0; v < V; ++v) {
+        const uint64_t *vb = visbits + ((size_t)v * nb + b) * 4;
+        uint64_t mask = vb[wv];
+        bool vis = live && ((mask >> lane) & 1ull);
+        if (!__syncthreads_or(vis)) continue;  // nothing of this workgroup visible in view v
         double gw[12];
         for (int k = 0; k < 12; ++k) gw[k] = 0.0;
-        int v = -1;
-        if (act) {
-            int2 mv = meta[slot];
-            int64_t i = mv.x;
-            v = mv.y;
-            const double *M = w2c + 12 * v;
-            const double *K4 = intr + 4 * v;
-            float x[3], q[4], s[3], o;
-            load_gauss(g, i, x, q, s, o);
-            Proj P;
-            project_gauss(S, M, K4, W, H, x, q, s, o, P);
-            const float *gd = grad2d + 9 * slot;
-            double gmx = gd[0], gmy = gd[1], ga = gd[2], gb = gd[3], gc = gd[4];
-            atomicAdd(dopac + i, gd[5]);
-            atomicAdd(dcolor + i, gd[6]);
-            atomicAdd(dcolor + n + i, gd[7]);
-            atomicAdd(dcolor + 2 * n + i, gd[8]);
-            // conic -> Sigma2: G2 = -Q GQ Q with GQ = [[ga, gb/2], [gb/2, gc]]
-            double a = P.Q[0], b = P.Q[1], c = P.Q[2];
-            double hb = 0.5 * gb;
-            double m00 = a * ga + b * hb, m01 = a * hb + b * gc;
-            double m10 = b * ga + c * hb, m11 = b * hb + c * gc;
-            double g2xx = -(m00 * a + m01 * b);
-            double g2xy = -(m00 * b + m01 * c);
-            double g2yy = -(m10 * b + m11 * c);
-            // Sigma2 = T T^T + eps I -> dT = 2 G2 T
-            double gT[6];
-            for (int j = 0; j < 3; ++j) {
-                gT[j] = 2.0 * (g2xx * P.T[j] + g2xy * P.T[3 + j]);
-                gT[3 + j] = 2.0 * (g2xy * P.T[j] + g2yy * P.T[3 + j]);
+        if (vis) {
+            uint32_t before = 0;
+            for (int w2 = 0; w2 < wv; ++w2) before += (uint32_t)__popcll(vb[w2]);
+            uint64_t slot = (uint64_t)blockoff[(size_t)v * nb + b] + before + rank_in(mask);
+            if (slot < (uint64_t)slot_cap) {
+                const double *M = w2c + 12 * v;
+                const double *K4 = intr + 4 * v;
+                Proj P;
+                project_gauss(S, M, K4, W, H, x, q, s, o, P);
+                const float *gd = grad2d + 9 * slot;
+                go += gd[5];
+                gc[0] += gd[6];
+                gc[1] += gd[7];
+                gc[2] += gd[8];
+                slot_adjoint(P, M, K4, x, s, gd, gq, gs, gm, gw);
             }
-            // T = J A -> dJ = gT A^T, dA = J^T gT
-            double gJ[6], gA[9];
-            for (int r = 0; r < 2; ++r)
-                for (int k = 0; k < 3; ++k)
-                    gJ[3 * r + k] = gT[3 * r] * P.A[3 * k] + gT[3 * r + 1] * P.A[3 * k + 1] + gT[3 * r + 2] * P.A[3 * k + 2];
-            for (int r = 0; r < 3; ++r)
-                for (int k = 0; k < 3; ++k) gA[3 * r + k] = P.J[r] * gT[k] + P.J[3 + r] * gT[3 + k];
-            // J(t), mu(t)
-            double fx = K4[0], fy = K4[1];
-            double tx = P.t[0], ty = P.t[1], tz = P.t[2];
-            double iz = 1.0 / tz, iz2 = iz * iz;
-            double gt0 = gmx * fx * iz, gt1 = gmy * fy * iz;
-            double gt2 = -(gmx * fx * tx + gmy * fy * ty) * iz2 - (gJ[0] * fx + gJ[4] * fy) * iz2;
-            if (!P.clx) {
-                gt0 += -gJ[2] * fx * iz2;
-                gt2 += 2.0 * gJ[2] * fx * tx * iz2 * iz;
-            } else {
-                gt2 += gJ[2] * fx * P.xh * iz2;
-            }
-            if (!P.cly) {
-                gt1 += -gJ[5] * fy * iz2;
-                gt2 += 2.0 * gJ[5] * fy * ty * iz2 * iz;
-            } else {
-                gt2 += gJ[5] * fy * P.yh * iz2;
-            }
-            double gt[3] = {gt0, gt1, gt2};
-            // A = W R D: dW += gA (R D)^T ; dR = W^T gA D ; ds_k = ((W R)^T gA)_kk
-            double gR[9], dsv[3] = {0, 0, 0};
-            for (int r = 0; r < 3; ++r)
-                for (int k = 0; k < 3; ++k) {
-                    double acc = 0.0;
-                    for (int m = 0; m < 3; ++m) acc += M[4 * m + r] * gA[3 * m + k];  // (W^T gA)[r][k]
-                    gR[3 * r + k] = acc * (double)s[k];
-                    dsv[k] += P.R[3 * r + k] * acc;  // ((W R)^T gA)_kk = sum_r R[r][k] (W^T gA)[r][k]
-                }
-            for (int r = 0; r < 3; ++r)
-                for (int k = 0; k < 3; ++k) {
-                    double acc = 0.0;
-                    for (int m = 0; m < 3; ++m) acc += gA[3 * r + m] * P.R[3 * k + m] * (double)s[m];
-                    gw[4 * r + k] = acc + gt[r] * (double)x[k];
-                }
-            for (int r = 0; r < 3; ++r) gw[4 * r + 3] = gt[r];
-            for (int k = 0; k < 3; ++k) atomicAdd(dscale + k * n + i, (float)dsv[k]);
-            if (dmean) {
-                for (int k = 0; k < 3; ++k)
-                    atomicAdd(dmean + k * n + i, (float)(M[k] * gt[0] + M[4 + k] * gt[1] + M[8 + k] * gt[2]));
-            }
-            // R(q_hat) -> q_hat -> q
-            double w = P.qh[0], qx = P.qh[1], qy = P.qh[2], qz = P.qh[3];
-            double gq0 = 2.0 * (-qz * gR[1] + qy * gR[2] + qz * gR[3] - qx * gR[5] - qy * gR[6] + qx * gR[7]);
-            double gq1 = 2.0 * (qy * gR[1] + qz * gR[2] + qy * gR[3] - 2.0 * qx * gR[4] - w * gR[5] + qz * gR[6] + w * gR[7] - 2.0 * qx * gR[8]);
-            double gq2 = 2.0 * (-2.0 * qy * gR[0] + qx * gR[1] + w * gR[2] + qx * gR[3] + qz * gR[5] - w * gR[6] + qz * gR[7] - 2.0 * qy * gR[8]);
-            double gq3 = 2.0 * (-2.0 * qz * gR[0] - w * gR[1] + qx * gR[2] + w * gR[3] - 2.0 * qz * gR[4] + qy * gR[5] + qx * gR[6] + qy * gR[7]);
-            double dot = w * gq0 + qx * gq1 + qy * gq2 + qz * gq3;
-            double iq = 1.0 / P.qn;
-            atomicAdd(dquat + i, (float)((gq0 - w * dot) * iq));
-            atomicAdd(dquat + n + i, (float)((gq1 - qx * dot) * iq));
-            atomicAdd(dquat + 2 * n + i, (float)((gq2 - qy * dot) * iq));
-            atomicAdd(dquat + 3 * n + i, (float)((gq3 - qz * dot) * iq));
         }
-        // per-view W2C gradient: float64 wave reduction when the wave sits in one view
-        uint64_t am = __ballot(act);
-        if (am == 0) continue;
-        int first = __ffsll((long long)am) - 1;
-        int v0 = __shfl(v, first, kWave);
-        bool same = __ballot(act && v != v0) == 0;
-        if (same) {
-            for (int k = 0; k < 12; ++k) {
-                double sum = wave_sum(gw[k]);
-                if (__lane_id() == first) atomicAdd(dw2c + 12 * v0 + k, sum);
-            }
-        } else if (act) {
-            for (int k = 0; k < 12; ++k) atomicAdd(dw2c + 12 * v + k, gw[k]);
+        for (int k = 0; k < 12; ++k) {
+            double t = wave_sum(gw[k]);
+            if (lane == 0) red[wv][k] = t;
         }
+        __syncthreads();
+        if (threadIdx.x < 12) {
+            int k = threadIdx.x;
+            atomicAdd(dw2c + 12 * v + k, ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k]);
+        }
+        __syncthreads();
     }
+    if (!live) return;
+    for (int k = 0; k < 4; ++k) dquat[k * n + i] += (float)gq[k];
+    for (int k = 0; k < 3; ++k) dscale[k * n + i] += (float)gs[k];
+    dopac[i] += (float)go;
+    for (int k = 0; k < 3; ++k) dcolor[k * n + i] += (float)gc[k];
+    if (dmean)
+        for (int k = 0; k < 3; ++k) dmean[k * n + i] += (float)gm[k];
 }
 
 }  // namespace
@@ -342,7 +364,7 @@ int launch_project(const splat_plan &p, void *ws, const splat_gaussians &g, cons
         if (rc) return rc;
     } else {
         hipLaunchKernelGGL(project_count_kernel, dim3(nb, V), dim3(256), 0, st, p.s, g, w2c, intr, p.width,
-                           p.height, nb, blockcnt, status);
+                           p.height, nb, blockcnt, ws_at<uint64_t>(ws, p.off_visbits), status);
         int rc = launch_status("project_count");
         if (rc) return rc;
         rc = launch_scan_u32(blockcnt, blockcnt, nullptr, (int64_t)V * nb, ws_at<uint32_t>(ws, p.off_scan),
@@ -362,12 +384,11 @@ int launch_project(const splat_plan &p, void *ws, const splat_gaussians &g, cons
 int launch_project_bwd(const splat_plan &p, void *ws, const splat_gaussians &g, const double *w2c,
                        const double *intr, float *dquat, float *dscale, float *dopac, float *dcolor,
                        float *dmean, double *dw2c, hipStream_t st) {
-    int64_t cap = p.slot_cap;
-    int nblk = (int)((cap + 255) / 256);
-    if (nblk > 8192) nblk = 8192;
-    hipLaunchKernelGGL(project_bwd_kernel, dim3(nblk), dim3(256), 0, st, p.s, g, w2c, intr, p.width, p.height,
-                       ws_at<uint32_t>(ws, p.off_counts), ws_at<int2>(ws, p.off_meta),
-                       ws_at<float>(ws, p.off_grad2d), dquat, dscale, dopac, dcolor, dmean, dw2c);
+    if (g.n == 0) return 0;
+    int nb = p.n_blocks_proj;
+    hipLaunchKernelGGL(project_bwd_kernel, dim3(nb), dim3(256), 0, st, p.s, g, w2c, intr, p.width, p.height,
+                       p.n_views, nb, ws_at<uint32_t>(ws, p.off_blockcnt), ws_at<uint64_t>(ws, p.off_visbits),
+                       p.slot_cap, ws_at<float>(ws, p.off_grad2d), dquat, dscale, dopac, dcolor, dmean, dw2c);
     return launch_status("project_bwd");
 }
 

@@ -352,7 +352,8 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
                 int idx = bs + j;
                 float mx = bcast(cur.mx, j), my = bcast(cur.my, j);
                 float A = bcast(cur.A, j), Bc = bcast(cur.Bc, j), Cc = bcast(cur.Cc, j), lo2 = bcast(cur.lo2, j);
-                float gmx = 0.f, gmy = 0.f, ga = 0.f, gb = 0.f, gcc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
+                // per-lane sums of dp = dL/dpower and its moments in (dx, dy), and of the colour weights
+                float m0 = 0.f, mx1 = 0.f, my1 = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
                 bool hit_any = false;
 #pragma unroll
                 for (int k = 0; k < NSB; ++k) {
@@ -379,24 +380,28 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
                         S1[k] = __fmaf_rn(cg, w, S1[k]);
                         S2[k] = __fmaf_rn(cb, w, S2[k]);
                         T[k] = Tj;
-                        if (al < a.amax) {
-                            float dp = dal * al;
-                            go = __fmaf_rn(dp, bcast(cur.io, j), go);
-                            float hdx = 0.5f * dx, hdy = 0.5f * dy;
-                            ga = __fmaf_rn(-dp * hdx, dx, ga);
-                            gb = __fmaf_rn(-dp * dx, dy, gb);
-                            gcc = __fmaf_rn(-dp * hdy, dy, gcc);
-                            // d power / d mu = (a dx + b dy, b dx + c dy), a = -2 ln2 A, b = -ln2 Bc, c = -2 ln2 Cc
-                            gmx = __fmaf_rn(dp, -LN2 * __fmaf_rn(2.f * A, dx, Bc * dy), gmx);
-                            gmy = __fmaf_rn(dp, -LN2 * __fmaf_rn(Bc, dx, 2.f * Cc * dy), gmy);
-                        }
+                        float dp = al < a.amax ? dal * al : 0.f;  // no gradient through the alpha_max clamp
+                        float tx = dp * dx, tyv = dp * dy;
+                        m0 += dp;
+                        mx1 += tx;
+                        my1 += tyv;
+                        mxx = __fmaf_rn(tx, dx, mxx);
+                        mxy = __fmaf_rn(tx, dy, mxy);
+                        myy = __fmaf_rn(tyv, dy, myy);
                     }
                 }
                 if (!hit_any) continue;
-                float s0 = lane63(wave_sum63(gmx)), s1 = lane63(wave_sum63(gmy));
-                float s2 = lane63(wave_sum63(ga)), s3 = lane63(wave_sum63(gb)), s4 = lane63(wave_sum63(gcc));
-                float s5 = lane63(wave_sum63(go));
+                float M0 = lane63(wave_sum63(m0)), Mx = lane63(wave_sum63(mx1)), My = lane63(wave_sum63(my1));
+                float Mxx = lane63(wave_sum63(mxx)), Mxy = lane63(wave_sum63(mxy)), Myy = lane63(wave_sum63(myy));
                 float s6 = lane63(wave_sum63(gr)), s7 = lane63(wave_sum63(gg)), s8 = lane63(wave_sum63(gbl));
+                // power = -(a dx^2 + 2 b dx dy + c dy^2)/2 with dx = pixel - mean, and
+                // a = -2 ln2 A, b = -ln2 Bc, c = -2 ln2 Cc:
+                //   dL/dmu = (a Mx + b My, b Mx + c My), dL/d(a, b, c) = (-Mxx/2, -Mxy, -Myy/2),
+                //   dL/do = M0 / o
+                float ca = -2.f * LN2 * A, cbv = -LN2 * Bc, ccv = -2.f * LN2 * Cc;
+                float s0 = ca * Mx + cbv * My, s1 = cbv * Mx + ccv * My;
+                float s2 = -0.5f * Mxx, s3 = -Mxy, s4 = -0.5f * Myy;
+                float s5 = M0 * bcast(cur.io, j);
                 uint32_t slot = bcast_u(cur.slot, j);
                 if (STATS && lane == 0) ++n_atomic;
                 if (lane < 9) {
