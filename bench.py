@@ -50,6 +50,9 @@ def main():
     ap.add_argument("--small", action="store_true", help="tiny smoke workload instead of the 64-view drive")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (calibrates HBM byte counters)")
+    ap.add_argument("--no-autotune", action="store_true", help="use --tile instead of the autotuner")
+    ap.add_argument("--calib-steps", type=int, default=3000,
+                    help="steps of the calibration loop (2 cameras x 100 frames, 16 views per step); 0 skips it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding of this "
@@ -97,6 +100,13 @@ def main():
     targets = img_t.clone()
     del fr0
     torch.cuda.synchronize()
+
+    tune = None
+    if not args.no_autotune:
+        from paper_2403_11577_amd import autotune as at
+        settings, tune = at.autotune(ds, xi, delta, targets, use_cache=False)
+        args.tile = "x".join(str(x) for x in tune["best"]["tile"])
+        log(f"[bench] autotune: {tune['best']} of {len(tune['candidates'])} candidates")
 
     step = pl.BatchedStep(ds, xi, delta, targets, settings)
     step.run()
@@ -199,8 +209,30 @@ def main():
                                            f"fwd+bwd, {W}x{H}, {tcpu:.1f}s"}
         log(f"[bench] cpu oracle: {tcpu:.1f}s for one view")
 
+    # ---- the calibration loop: 2 cameras x 100 frames in the same kind of world, 16 views per step ----
+    calib = None
+    if args.calib_steps > 0 and not args.small:
+        del step
+        torch.cuda.empty_cache()
+        from paper_2403_11577_amd import calib as cb
+        tc = time.time()
+        cscene = synth.calib_full(seed=0)
+        cal = cb.Calibrator(cscene, cb.CalibConfig(steps=args.calib_steps, warmup=min(500, args.calib_steps // 6)),
+                            settings=settings)
+        log(f"[bench] calibration setup {time.time() - tc:.1f}s; init rot "
+            f"{[round(x, 2) for x in cal.errors()['rotation_deg']]} deg")
+        res = cal.run(log_every=max(1, args.calib_steps // 6), log=log)
+        calib = {"steps_per_s": round(res["steps_per_s"], 2), "steps": res["steps"], "views_per_step": 16,
+                 "final": {k: [round(x, 4) for x in res[k]] for k in ("rotation_deg", "translation_cm",
+                                                                     "time_offset_ms")},
+                 "init": {"rotation_deg": [round(x, 3) for x in cb.rotation_error_deg(cscene.xi)],
+                          "translation_cm": [round(float(np.linalg.norm(x) * 100), 2) for x in cscene.xi[:, :3]],
+                          "time_offset_ms": [round(float(x) * 1000, 1) for x in cscene.delta]},
+                 "loss": round(res["loss"], 6)}
+        log(f"[bench] calibration: {calib['steps_per_s']} steps/s, final {calib['final']}")
+
     out = {
-        "metric": "fwd+bwd Mpixels/s (batched persistent, 64 views)",
+        "metric": "fwd+bwd Mpixels/s and calib steps/s, batched vs per-view, at <=1e-4 px err",
         "value": round(mpx, 2),
         "unit": "Mpixels/s",
         "n_gpus": 1,
@@ -213,7 +245,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "views": V, "width": W, "height": H, "gaussians": int(scene.gauss.n),
-                   "tile": args.tile, "batch": args.batch, "persistent": True,
+                   "tile": args.tile, "persistent": bool(settings.persistent), "path": "batched",
                    "visible_per_view": {"min": int(vis.min()), "median": int(np.median(vis)), "max": int(vis.max())}},
         "loss": loss,
         "graph": graph,
@@ -221,6 +253,8 @@ def main():
         "speedup_vs_per_view": (round(per_view["ms_per_step"] / ms_step, 3) if per_view else None),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "autotune": tune,
+        "calibration": calib,
     }
     print(json.dumps(out), flush=True)
 

@@ -1,0 +1,246 @@
+"""The calibration loop of 3DGS-Calib on top of the batched differentiable renderer.
+
+Sec. III and IV-B of the paper: Gaussians anchored at the LiDAR points (means
+fixed), view-independent colours initialised at random, scales / rotations /
+opacities initialised as in 3DGS; Adam with learning rates 1e-4 (rotation),
+5e-3 (translation) and 1e-3 (time offset), linearly decayed to 0.1x over the
+run; a warm-up during which the calibration is frozen.  Every step renders a
+batch of views forward and backward through the HIP path (pose interpolation,
+projection, binning, compositing, L1, adjoints); the optimiser and the parameter
+activations (sigmoid opacity, exponential scale) are plain torch.
+
+Learning rates of the Gaussian parameters are not given in the paper; those of
+the original 3DGS implementation are used.  The photometric loss here is the
+L1 term of Eq. (4) only (the D-SSIM term is not part of this build).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import binding as B
+from . import pipeline as pl
+
+
+@dataclasses.dataclass
+class CalibConfig:
+    steps: int = 3000
+    warmup: int = 500
+    batch_views: int = 16
+    lr_rot: float = 1e-4
+    lr_trans: float = 5e-3
+    lr_time: float = 1e-3
+    lr_color: float = 2.5e-3
+    lr_opacity: float = 5e-2
+    lr_scale: float = 5e-3
+    lr_quat: float = 1e-3
+    final_lr_frac: float = 0.1
+    init_opacity: float = 0.1
+    seed: int = 0
+    # "random": colours U[0,1), opacity init_opacity, identity rotations, the scene's scales;
+    # "scene": start from the scene's own Gaussians (pure registration when frozen)
+    gauss_init: str = "random"
+    freeze_gaussians: bool = False
+
+
+def rotation_error_deg(xi):
+    """Geodesic angle of R0 Exp(phi) against the ground truth R0 (phi = 0)."""
+    return np.degrees(np.linalg.norm(np.asarray(xi)[:, 3:], axis=1))
+
+
+class Calibrator:
+    """Optimises Gaussians, extrinsic corrections xi = (rho, phi) and time offsets delta."""
+
+    def __init__(self, scene, cfg: CalibConfig = None, settings=None, device="cuda"):
+        self.cfg = cfg = cfg or CalibConfig()
+        self.scene = scene
+        self.device = device
+        full = pl.DeviceScene.from_scene(scene, device=device)
+        self.full = full
+        V, G, Bv = full.n_views, full.n_gauss, cfg.batch_views
+        self.settings = settings or pl.make_settings()
+        # targets: every view rendered at the ground-truth calibration with the true Gaussians
+        zx = torch.zeros((full.n_cams, 6), dtype=torch.float64, device=device)
+        zd = torch.zeros(full.n_cams, dtype=torch.float64, device=device)
+        self.targets = torch.empty((V, 3, full.H, full.W), dtype=torch.float32, device=device)
+        counts = []
+        for v0 in range(0, V, Bv):
+            sub = self._subscene(full, torch.arange(v0, min(V, v0 + Bv), device=device))
+            fr = pl.fit_frame(sub, zx, zd, self.settings)
+            img, _, _ = pl.forward(fr, sub, zx, zd)
+            self.targets[v0:v0 + sub.n_views] = img
+            counts.append(fr.counts())
+            del fr
+        # capacity: the largest batch seen, with a wide margin for footprints that grow in training
+        ns = max(c[0] for c in counts)
+        ni = max(c[1] for c in counts)
+        self.win = self._subscene(full, torch.arange(Bv, device=device) % V)
+        self.slot_cap = int(min(Bv * G, ns * 2 + 1024))
+        self.inst_cap = int(min((1 << 31) - 1, ni * 3 + 4096))
+        self.fr = pl.Frame(self.settings, Bv, G, full.W, full.H, self.slot_cap, self.inst_cap, device)
+        self.tgt = torch.empty((Bv, 3, full.H, full.W), dtype=torch.float32, device=device)
+        # parameters (raw) and their activations
+        if cfg.gauss_init == "scene":
+            o = full.opacity.clamp(1e-6, 1 - 1e-6)
+            self.color = full.color.clone().requires_grad_(True)
+            self.logit_o = torch.log(o / (1 - o)).requires_grad_(True)
+            self.quat = full.quat.clone().requires_grad_(True)
+        else:
+            g = torch.Generator(device="cpu").manual_seed(cfg.seed)
+            self.color = torch.rand((3, G), generator=g).to(device).requires_grad_(True)
+            self.logit_o = torch.full((G,), math.log(cfg.init_opacity / (1 - cfg.init_opacity)), device=device,
+                                      requires_grad=True)
+            q = torch.zeros((4, G), device=device)
+            q[0] = 1.0
+            self.quat = q.requires_grad_(True)
+        self.log_s = torch.log(full.scale.clone()).requires_grad_(True)
+        self.rho = torch.tensor(scene.xi[:, :3], dtype=torch.float64, device=device).requires_grad_(True)
+        self.phi = torch.tensor(scene.xi[:, 3:], dtype=torch.float64, device=device).requires_grad_(True)
+        self.delta = torch.tensor(scene.delta, dtype=torch.float64, device=device).requires_grad_(True)
+        # two optimisers: the calibration one only starts stepping after the warm-up
+        self.opt_g = torch.optim.Adam([
+            dict(params=[self.color], lr=cfg.lr_color),
+            dict(params=[self.logit_o], lr=cfg.lr_opacity),
+            dict(params=[self.log_s], lr=cfg.lr_scale),
+            dict(params=[self.quat], lr=cfg.lr_quat),
+        ], eps=1e-15)
+        self.opt_c = torch.optim.Adam([
+            dict(params=[self.rho], lr=cfg.lr_trans),
+            dict(params=[self.phi], lr=cfg.lr_rot),
+            dict(params=[self.delta], lr=cfg.lr_time),
+        ], eps=1e-15)
+        self.base_lr = [[grp["lr"] for grp in o.param_groups] for o in (self.opt_g, self.opt_c)]
+        self.xi_t = torch.zeros((full.n_cams, 6), dtype=torch.float64, device=device)
+        self.dl_t = torch.zeros(full.n_cams, dtype=torch.float64, device=device)
+        self.gr = pl.alloc_grads(self.win)
+        self.dimg = torch.empty_like(self.fr.img)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+        self.rng = np.random.default_rng(cfg.seed)
+        self.order = []
+        # status words of the last two steps, copied to pinned memory and read two steps later
+        self._st_host = torch.zeros((2, 1), dtype=torch.int32).pin_memory()
+        self._st_ev = [None, None]
+        self.overflow_steps = []
+        self.replans = 0
+
+    @staticmethod
+    def _subscene(full, idx):
+        return pl.DeviceScene(full.mean, full.quat.clone(), full.scale.clone(), full.opacity.clone(),
+                              full.color.clone(), full.knot_t, full.knot_q, full.knot_p, full.R0, full.t0,
+                              full.view_cam[idx].contiguous(), full.view_t[idx].contiguous(),
+                              full.intr[idx].contiguous(), full.W, full.H)
+
+    def _next_views(self):
+        Bv, V = self.cfg.batch_views, self.full.n_views
+        if len(self.order) < Bv:
+            self.order.extend(self.rng.permutation(V).tolist())
+        sel, self.order = self.order[:Bv], self.order[Bv:]
+        return torch.as_tensor(sel, device=self.device)
+
+    def step(self, k: int):
+        cfg = self.cfg
+        self._poll(k)
+        idx = self._next_views()
+        w, f = self.win, self.full
+        w.view_cam.copy_(f.view_cam[idx])
+        w.view_t.copy_(f.view_t[idx])
+        w.intr.copy_(f.intr[idx])
+        self.tgt.copy_(self.targets[idx])
+        with torch.no_grad():
+            o = torch.sigmoid(self.logit_o)
+            s = torch.exp(self.log_s)
+            w.opacity.copy_(o)
+            w.scale.copy_(s)
+            w.color.copy_(self.color)
+            w.quat.copy_(self.quat)
+            self.xi_t[:, :3].copy_(self.rho)
+            self.xi_t[:, 3:].copy_(self.phi)
+            self.dl_t.copy_(self.delta)
+        fr = self.fr
+        self.loss.zero_()
+        pl.zero_grads(self.gr)
+        pl.forward(fr, w, self.xi_t, self.dl_t)
+        B.splat_l1_loss_grad(fr.img, self.tgt, None, self.dimg, self.loss)
+        pl.backward(fr, w, self.xi_t, self.dl_t, self.dimg, self.gr)
+        # activations and the optimiser (torch)
+        self.color.grad = self.gr.color
+        self.logit_o.grad = self.gr.opacity * o * (1 - o)
+        self.log_s.grad = self.gr.scale * s
+        self.quat.grad = self.gr.quat
+        frac = 1.0 - (1.0 - cfg.final_lr_frac) * min(1.0, k / max(1, cfg.steps - 1))
+        for opt, lrs in zip((self.opt_g, self.opt_c), self.base_lr):
+            for grp, lr0 in zip(opt.param_groups, lrs):
+                grp["lr"] = lr0 * frac
+        if not cfg.freeze_gaussians:
+            self.opt_g.step()
+        if k >= cfg.warmup:
+            self.rho.grad = self.gr.xi[:, :3].contiguous()
+            self.phi.grad = self.gr.xi[:, 3:].contiguous()
+            self.delta.grad = self.gr.delta
+            self.opt_c.step()
+        self._queue_status(k)
+
+    def _poll(self, k: int):
+        """Before step k: read the status word of step k-2, which has finished by now."""
+        j = k & 1
+        ev, self._st_ev[j] = self._st_ev[j], None
+        if ev is not None:
+            ev.synchronize()
+            if int(self._st_host[j, 0]) & B.ST_CAPACITY:
+                self.overflow_steps.append(k - 2)
+                self._grow()
+
+    def _queue_status(self, k: int):
+        """After step k: copy its status word to pinned memory and clear it."""
+        j = k & 1
+        st = self.fr.status_t
+        self._st_host[j].copy_(st, non_blocking=True)
+        st.zero_()
+        e = torch.cuda.Event()
+        e.record()
+        self._st_ev[j] = e
+
+    def _grow(self):
+        """Re-plan with twice the capacities after a step whose instances or slots overflowed."""
+        ns, ni = self.fr.counts()
+        G, Bv = self.full.n_gauss, self.cfg.batch_views
+        self.slot_cap = int(min(Bv * G, max(self.slot_cap, 2 * ns)))
+        self.inst_cap = int(min((1 << 31) - 1, 2 * max(self.inst_cap, ni)))
+        self.fr = pl.Frame(self.settings, Bv, G, self.full.W, self.full.H, self.slot_cap, self.inst_cap,
+                           self.device)
+        self.dimg = torch.empty_like(self.fr.img)
+        self.replans += 1
+
+    def errors(self):
+        xi = np.concatenate([self.rho.detach().cpu().numpy(), self.phi.detach().cpu().numpy()], axis=1)
+        rot = rotation_error_deg(xi - self.scene.xi_gt)
+        trans = np.linalg.norm(xi[:, :3] - self.scene.xi_gt[:, :3], axis=1) * 100.0
+        dt = np.abs(self.delta.detach().cpu().numpy() - self.scene.delta_gt) * 1000.0
+        return dict(rotation_deg=rot.tolist(), translation_cm=trans.tolist(), time_offset_ms=dt.tolist())
+
+    def run(self, steps=None, log_every=0, log=print):
+        steps = self.cfg.steps if steps is None else steps
+        t0 = None
+        for k in range(steps):
+            if k == 10:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            self.step(k)
+            if log_every and (k % log_every == 0 or k == steps - 1):
+                e = self.errors()
+                log(f"[calib] step {k} loss {float(self.loss.item()):.5f} rot {np.round(e['rotation_deg'], 3)} "
+                    f"trans_cm {np.round(e['translation_cm'], 2)} dt_ms {np.round(e['time_offset_ms'], 2)}")
+        torch.cuda.synchronize()
+        sps = (steps - 10) / (time.perf_counter() - t0) if steps > 10 and t0 else float("nan")
+        for k in range(max(0, steps - 2), steps):
+            j = k & 1
+            if self._st_ev[j] is not None and int(self._st_host[j, 0]) & B.ST_CAPACITY:
+                self.overflow_steps.append(k)
+            self._st_ev[j] = None
+        out = dict(steps=steps, steps_per_s=sps, loss=float(self.loss.item()), replans=self.replans,
+                   overflow_steps=len(self.overflow_steps), **self.errors())
+        return out

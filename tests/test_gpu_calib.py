@@ -1,0 +1,51 @@
+"""GPU: the calibration loop and the launch-shape autotuner on small scenes."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from paper_2403_11577_amd import autotune as at
+from paper_2403_11577_amd import calib as cb
+from paper_2403_11577_amd import pipeline as pl
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_calibration_loop_reduces_loss_and_moves_calibration():
+    say("case: calibration loop")
+    s = synth.small_drive(11, n_points=4000, W=160, H=64, f=70.0, n_frames=6, deg=3.0, metres=0.15, delta=0.03)
+    cal = cb.Calibrator(s, cb.CalibConfig(steps=240, warmup=40, batch_views=4, seed=1))
+    e0 = cal.errors()
+    cal.step(0)
+    torch.cuda.synchronize()
+    l0 = float(cal.loss.item())
+    res = cal.run(steps=240)
+    say(f"  loss {l0:.4f} -> {res['loss']:.4f}; rot {e0['rotation_deg']} -> {res['rotation_deg']}; "
+        f"{res['steps_per_s']:.1f} steps/s")
+    assert math.isfinite(res["loss"]) and res["loss"] < 0.8 * l0
+    assert all(math.isfinite(x) for x in res["rotation_deg"] + res["translation_cm"] + res["time_offset_ms"])
+    moved = np.abs(np.array(res["rotation_deg"]) - np.array(e0["rotation_deg"])).max()
+    assert moved > 1e-3
+    assert res["steps_per_s"] > 10
+
+
+def test_autotune_picks_a_candidate_and_results_are_shape_independent():
+    say("case: autotune")
+    s = synth.small_drive(12, n_frames=2)
+    ds = pl.DeviceScene.from_scene(s)
+    xi = torch.as_tensor(s.xi, dtype=torch.float64, device="cuda")
+    dl = torch.as_tensor(s.delta, dtype=torch.float64, device="cuda")
+    tgt = torch.zeros((ds.n_views, 3, ds.H, ds.W), dtype=torch.float32, device="cuda")
+    st, rep = at.autotune(ds, xi, dl, tgt, steps=2, use_cache=False)
+    assert len(rep["candidates"]) == 8
+    assert rep["best"]["ms"] == min(c["ms"] for c in rep["candidates"])
+    a = pl.BatchedStep(ds, xi, dl, tgt, st)
+    b = pl.BatchedStep(ds, xi, dl, tgt, pl.make_settings())
+    a.run()
+    b.run()
+    torch.cuda.synchronize()
+    assert torch.equal(a.fr.img, b.fr.img)
