@@ -275,13 +275,47 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
     }
 }
 
+// Transposed reduction of nine per-lane values over the wave.  Four exchange
+// steps inside each 16-lane row, with partners lane^1, lane^2, lane^7 and
+// lane^15 (quad permutes, half-row mirror, row mirror: one DPP add each), halve
+// the number of values a lane carries at every step; afterwards lane i of every
+// row holds the row sum of value number cls(i) = c0 + 2 c1 + 4 c2 + 8 c3, with
+// c0 = b0^b2, c1 = b1^b2, c2 = b2^b3, c3 = b3 for the bits b of i (the dual
+// basis of {1, 2, 7, 15}, so partners always agree on the bits fixed so far).
+// Two cross-row exchanges then give every lane the wave total of its value.
+// Numbers 9..15 only ever carry padding.  27 VALU operations for nine sums,
+// where nine separate reductions would take about a hundred.
+template <int CTRL>
+__device__ __forceinline__ float xpair(float lo, float hi, bool c) {
+    float keep = c ? hi : lo, send = c ? lo : hi;
+    return keep + dpp_f<CTRL, 0xF>(send);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float xpad(float v) { return v + dpp_f<CTRL, 0xF>(v); }
+
+__device__ __forceinline__ float reduce9(const float (&v)[9], bool c0, bool c1, bool c2, bool c3) {
+    float a0 = xpair<0xB1>(v[0], v[1], c0), a1 = xpair<0xB1>(v[2], v[3], c0);
+    float a2 = xpair<0xB1>(v[4], v[5], c0), a3 = xpair<0xB1>(v[6], v[7], c0);
+    float a4 = xpad<0xB1>(v[8]);
+    float b0 = xpair<0x4E>(a0, a1, c1), b1 = xpair<0x4E>(a2, a3, c1), b2 = xpad<0x4E>(a4);
+    float d0 = xpair<0x141>(b0, b1, c2), d1 = xpad<0x141>(b2);
+    float e = xpair<0x140>(d0, d1, c3);
+    e += __shfl_xor(e, 16, kWave);
+    e += __shfl_xor(e, 32, kWave);
+    return e;
+}
+
 // Backward: each pixel walks from its last contributor towards the list start,
-// recovering T_j = T_{j+1} / (1 - alpha_j) and the suffix colour
-// S_j = sum_{i>j} c_i alpha_i T_i + T_final bg, and forms
+// recovering T_j = T_{j+1} / (1 - alpha_j), and forms
 //   dL/dc_j     = alpha_j T_j dL/dC
-//   dL/dalpha_j = dL/dC . (c_j T_j - S_j / (1 - alpha_j))
-// then dL/dpower = alpha dL/dalpha and dL/do = dL/dalpha alpha / o (unless
-// alpha was clamped at alpha_max), dL/d(conic) and dL/d(mean) from the power.
+//   dL/dalpha_j = dL/dC . (c_j T_j - S_j / (1 - alpha_j)),
+// S_j = sum_{i>j} c_i alpha_i T_i + T_final bg being the colour behind j.  Only
+// the scalar P_j = dL/dC . S_j is kept per pixel (P += w dL/dC . c_j).  Then
+// dL/dpower = alpha dL/dalpha and dL/do = dL/dalpha alpha / o (unless alpha was
+// clamped at alpha_max); dL/d(conic) and dL/d(mean) follow from the power.
+// Lanes that do not blend a Gaussian run the same instructions with alpha = 0,
+// which changes nothing (1 / (1 - 0) = 1 exactly).
 template <int TW, int TH, bool STATS>
 __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const float *dimg, const float *Tin,
                                                        const int32_t *lastin, float *grad2d) {
@@ -290,6 +324,11 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
     const int lx = lane & 7, ly = lane >> 3;
     const size_t HW = (size_t)a.W * a.H;
     const uint32_t nslots = a.counts[CNT_SLOTS];
+    // reduction classes of this lane (see reduce9) and the lanes that write them
+    const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+    const bool c0 = b0 ^ b2, c1 = b1 ^ b2, c2 = b2 ^ b3, c3 = b3;
+    const int cls = (int)c0 | ((int)c1 << 1) | ((int)c2 << 2) | ((int)c3 << 3);
+    const bool writer = lane < 16 && cls < 9;
     unsigned long long n_eval = 0, n_contrib = 0, n_atomic = 0;
     int item;
     for (int iter = 0; next_item(a, iter, item); ++iter) {
@@ -299,7 +338,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
         int x0 = tx * TW, y0 = ty * TH;
         int xb = x0 & ~31, yb = y0 & ~31;
         uint2 rg = a.ranges[tid];
-        float T[NSB], S0[NSB], S1[NSB], S2[NSB], gc0[NSB], gc1[NSB], gc2[NSB], px[NSB], py[NSB];
+        float T[NSB], P[NSB], gc0[NSB], gc1[NSB], gc2[NSB], px[NSB], py[NSB];
         int last[NSB], kmax[NSB];
         size_t vo = (size_t)v * HW;
         int wmax = -1;
@@ -322,9 +361,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
                 gc1[k] = dimg[3 * vo + HW + o];
                 gc2[k] = dimg[3 * vo + 2 * HW + o];
             }
-            S0[k] = T[k] * a.bg0;
-            S1[k] = T[k] * a.bg1;
-            S2[k] = T[k] * a.bg2;
+            P[k] = T[k] * (gc0[k] * a.bg0 + gc1[k] * a.bg1 + gc2[k] * a.bg2);
             int mk = last[k];
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) mk = max(mk, __shfl_xor(mk, o, kWave));
@@ -352,6 +389,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
                 int idx = bs + j;
                 float mx = bcast(cur.mx, j), my = bcast(cur.my, j);
                 float A = bcast(cur.A, j), Bc = bcast(cur.Bc, j), Cc = bcast(cur.Cc, j), lo2 = bcast(cur.lo2, j);
+                float cr = bcast(cur.r, j), cg = bcast(cur.g, j), cb = bcast(cur.b, j);
                 // per-lane sums of dp = dL/dpower and its moments in (dx, dy), and of the colour weights
                 float m0 = 0.f, mx1 = 0.f, my1 = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
                 bool hit_any = false;
@@ -362,53 +400,42 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
                     float al = fminf(a.amax, exp2_hw(power2(dx, dy, A, Bc, Cc, lo2)));
                     bool hit = (idx <= last[k]) && (al >= a.amin);
                     if (STATS) n_eval += idx <= last[k];
-                    if (__ballot(hit) == 0) continue;
+                    if (__ballot(hit) == 0) continue;  // wave-uniform
                     hit_any = true;
-                    if (hit) {
-                        if (STATS) ++n_contrib;
-                        float cr = bcast(cur.r, j), cg = bcast(cur.g, j), cb = bcast(cur.b, j);
-                        float iom = __builtin_amdgcn_rcpf(1.f - al);
-                        float Tj = T[k] * iom;
-                        float w = al * Tj;
-                        gr = __fmaf_rn(w, gc0[k], gr);
-                        gg = __fmaf_rn(w, gc1[k], gg);
-                        gbl = __fmaf_rn(w, gc2[k], gbl);
-                        float dal = gc0[k] * __fmaf_rn(cr, Tj, -S0[k] * iom) +
-                                    gc1[k] * __fmaf_rn(cg, Tj, -S1[k] * iom) +
-                                    gc2[k] * __fmaf_rn(cb, Tj, -S2[k] * iom);
-                        S0[k] = __fmaf_rn(cr, w, S0[k]);
-                        S1[k] = __fmaf_rn(cg, w, S1[k]);
-                        S2[k] = __fmaf_rn(cb, w, S2[k]);
-                        T[k] = Tj;
-                        float dp = al < a.amax ? dal * al : 0.f;  // no gradient through the alpha_max clamp
-                        float tx = dp * dx, tyv = dp * dy;
-                        m0 += dp;
-                        mx1 += tx;
-                        my1 += tyv;
-                        mxx = __fmaf_rn(tx, dx, mxx);
-                        mxy = __fmaf_rn(tx, dy, mxy);
-                        myy = __fmaf_rn(tyv, dy, myy);
-                    }
+                    if (STATS) n_contrib += hit;
+                    float ah = hit ? al : 0.f;
+                    float iom = __builtin_amdgcn_rcpf(1.f - ah);
+                    float Tj = T[k] * iom;
+                    float w = ah * Tj;
+                    float gdc = __fmaf_rn(gc2[k], cb, __fmaf_rn(gc1[k], cg, gc0[k] * cr));
+                    gr = __fmaf_rn(w, gc0[k], gr);
+                    gg = __fmaf_rn(w, gc1[k], gg);
+                    gbl = __fmaf_rn(w, gc2[k], gbl);
+                    float dal = __fmaf_rn(Tj, gdc, -(iom * P[k]));
+                    P[k] = __fmaf_rn(w, gdc, P[k]);
+                    T[k] = Tj;
+                    float dp = al < a.amax ? dal * ah : 0.f;  // no gradient through the alpha_max clamp
+                    float tx = dp * dx, tyv = dp * dy;
+                    m0 += dp;
+                    mx1 += tx;
+                    my1 += tyv;
+                    mxx = __fmaf_rn(tx, dx, mxx);
+                    mxy = __fmaf_rn(tx, dy, mxy);
+                    myy = __fmaf_rn(tyv, dy, myy);
                 }
                 if (!hit_any) continue;
-                float M0 = lane63(wave_sum63(m0)), Mx = lane63(wave_sum63(mx1)), My = lane63(wave_sum63(my1));
-                float Mxx = lane63(wave_sum63(mxx)), Mxy = lane63(wave_sum63(mxy)), Myy = lane63(wave_sum63(myy));
-                float s6 = lane63(wave_sum63(gr)), s7 = lane63(wave_sum63(gg)), s8 = lane63(wave_sum63(gbl));
                 // power = -(a dx^2 + 2 b dx dy + c dy^2)/2 with dx = pixel - mean, and
                 // a = -2 ln2 A, b = -ln2 Bc, c = -2 ln2 Cc:
                 //   dL/dmu = (a Mx + b My, b Mx + c My), dL/d(a, b, c) = (-Mxx/2, -Mxy, -Myy/2),
-                //   dL/do = M0 / o
+                //   dL/do = M0 / o   (applied per lane before the reduction: all linear)
                 float ca = -2.f * LN2 * A, cbv = -LN2 * Bc, ccv = -2.f * LN2 * Cc;
-                float s0 = ca * Mx + cbv * My, s1 = cbv * Mx + ccv * My;
-                float s2 = -0.5f * Mxx, s3 = -Mxy, s4 = -0.5f * Myy;
-                float s5 = M0 * bcast(cur.io, j);
+                float io = bcast(cur.io, j);
                 uint32_t slot = bcast_u(cur.slot, j);
+                float vals[9] = {__fmaf_rn(ca, mx1, cbv * my1), __fmaf_rn(cbv, mx1, ccv * my1), -0.5f * mxx, -mxy,
+                                 -0.5f * myy, m0 * io, gr, gg, gbl};
+                float tot = reduce9(vals, c0, c1, c2, c3);
                 if (STATS && lane == 0) ++n_atomic;
-                if (lane < 9) {
-                    float val = lane == 0 ? s0 : lane == 1 ? s1 : lane == 2 ? s2 : lane == 3 ? s3 :
-                                lane == 4 ? s4 : lane == 5 ? s5 : lane == 6 ? s6 : lane == 7 ? s7 : s8;
-                    atomicAdd(grad2d + 9 * (size_t)slot + lane, val);
-                }
+                if (writer) atomicAdd(grad2d + 9 * (size_t)slot + cls, tot);
             }
             cur = derive<TW, TH>(a, raw_next, fxb, fyb, fox, foy);
             sl_next = sl_after;
