@@ -42,6 +42,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--grid", action="store_true", help="grid dispatch instead of persistent waves (with --no-autotune)")
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--per-view-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -89,7 +90,7 @@ def main():
     xi = torch.zeros((ds.n_cams, 6), dtype=torch.float64, device=dev)
     delta = torch.zeros(ds.n_cams, dtype=torch.float64, device=dev)
     tw, th = (int(x) for x in args.tile.split("x"))
-    settings = pl.make_settings(tile=(tw, th), batch=args.batch, persistent=True)
+    settings = pl.make_settings(tile=(tw, th), batch=args.batch, persistent=not args.grid)
 
     # targets: the scene at a slightly different calibration (untimed)
     xi_t = xi.clone()

@@ -119,7 +119,7 @@ typedef struct splat_plan {
     size_t off_grad2d;      /* float[slot_cap][9]: d(mu x,y; conic a,b,c; o; r,g,b)       */
     size_t off_visbits;     /* u64[V*n_blocks_proj*4]: visible (view, Gaussian) bit masks  */
     int32_t sorted_buf;     /* which of the two key/value buffers holds the sorted result */
-    int32_t reserved;
+    int32_t radix_bits;     /* digit width of the LSD radix sort (passes = ceil(key bits / radix_bits)) */
 } splat_plan;
 
 /* Fill `s` with the default settings listed above (16x16 tiles, batch 64,
@@ -196,6 +196,8 @@ SPLAT_API int splat_project(const splat_plan *plan, void *ws, const splat_gaussi
  * id) order.  Writes the sorted values, per-(view, tile) ranges and the
  * cost-ordered work queue in the workspace; plan->sorted_buf names the buffer
  * that holds the sorted result (it is a function of the plan only).
+ * The per-slot tile counts written by splat_project are turned into instance
+ * offsets in place, so call this exactly once after each splat_project.
  */
 SPLAT_API int splat_bin_sort(const splat_plan *plan, void *ws, void *stream);
 

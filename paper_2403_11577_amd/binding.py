@@ -46,7 +46,7 @@ class splat_plan(C.Structure):
                                           "n_blocks_proj", "n_sort_blocks")] +
                 [(n, C.c_int64) for n in ("n_gauss", "slot_cap", "inst_cap")] +
                 [(n, C.c_size_t) for n in _PLAN_OFFS] +
-                [("sorted_buf", C.c_int32), ("reserved", C.c_int32)])
+                [("sorted_buf", C.c_int32), ("radix_bits", C.c_int32)])
 
 
 _lib = None

@@ -186,7 +186,8 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     p.slot_cap = slot_cap;
     p.inst_cap = inst_cap;
     int bits = p.depth_bits + p.tile_bits;
-    int passes = (bits + 7) / 8;
+    int passes = (bits + kRadixBits - 1) / kRadixBits;
+    p.radix_bits = kRadixBits;
     p.sorted_buf = passes & 1;
 
     size_t off = 0;
@@ -198,7 +199,7 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     int64_t nproj = (int64_t)n_views * p.n_blocks_proj + 1;
     size_t nparts = scan_partials(slot_cap + 1);
     size_t np2 = scan_partials(nproj);
-    size_t np3 = scan_partials((int64_t)256 * p.n_sort_blocks);
+    size_t np3 = scan_partials((int64_t)kRadixDigits * p.n_sort_blocks);
     if (np2 > nparts) nparts = np2;
     if (np3 > nparts) nparts = np3;
     p.off_status = take(4);
@@ -213,7 +214,7 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     p.off_vals = take((size_t)inst_cap * 8);
     p.off_ranges = take((size_t)ntiles_all * 8);
     p.off_queue = take((size_t)ntiles_all * 4);
-    p.off_hist = take(((size_t)256 * p.n_sort_blocks + 1 + 128) * 4);
+    p.off_hist = take(((size_t)kRadixDigits * p.n_sort_blocks + 1 + 128) * 4);
     p.off_scan = take(nparts * 4);
     p.off_grad2d = take((size_t)slot_cap * 36);
     p.off_visbits = take((size_t)n_views * p.n_blocks_proj * 4 * 8);

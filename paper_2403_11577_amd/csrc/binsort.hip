@@ -7,11 +7,11 @@
 // order and the sort is stable, so inside a tile the order is (depth32,
 // Gaussian id) -- ties on depth are broken by the Gaussian index.
 //
-// Radix sort: reduce-then-scan per 8-bit digit with a fixed number of
+// Radix sort: reduce-then-scan per kRadixBits-bit digit with a fixed number of
 // partitions (the key count lives on the device, so the grid never depends on
-// it); inside a partition keys are ranked 256 at a time with wave64 ballot
-// peer matching, which keeps the order stable without any inter-workgroup
-// waiting.
+// it); inside a partition keys are ranked per wave with wave64 ballot peer
+// matching, which keeps the order stable without any inter-workgroup waiting,
+// and leave through an LDS reorder so that the scattered writes coalesce.
 #include "common.hpp"
 
 namespace splat {
@@ -28,14 +28,20 @@ __device__ inline uint32_t load_n(const uint32_t *n_dev, int64_t n_cap) {
 }
 
 // inclusive wave scan
-__device__ inline uint32_t wave_incl_scan(uint32_t v) {
-    int l = __lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t u = __shfl_up(v, o, kWave);
-        if (l >= o) v += u;
-    }
-    return v;
+// inclusive scan over the wave with DPP (row shifts, then row broadcasts)
+template <int CTRL, int ROWS, bool BC>
+__device__ inline uint32_t dpp_add(uint32_t x) {
+    return x + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, BC);
+}
+
+__device__ inline uint32_t wave_incl_scan(uint32_t x) {
+    x = dpp_add<0x111, 0xF, true>(x);  // row_shr:1
+    x = dpp_add<0x112, 0xF, true>(x);  // row_shr:2
+    x = dpp_add<0x114, 0xF, true>(x);  // row_shr:4
+    x = dpp_add<0x118, 0xF, true>(x);  // row_shr:8
+    x = dpp_add<0x142, 0xA, false>(x);  // row_bcast:15 into rows 1, 3
+    x = dpp_add<0x143, 0xC, false>(x);  // row_bcast:31 into rows 2, 3
+    return x;
 }
 
 // exclusive block scan over 256 threads; returns the block total through *tot
@@ -200,21 +206,25 @@ __device__ inline void chunk_of(uint32_t n, int nparts, int part, uint32_t &b, u
     e = (uint32_t)(ee < n ? ee : n);
 }
 
-// lanes of the wave holding the same 8-bit digit as this lane
+// lanes of the wave holding the same digit as this lane
 __device__ inline uint64_t match_digit(uint32_t d, bool act) {
     uint64_t peers = __ballot(act);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < kRadixBits; ++b) {
         uint64_t m = __ballot(act && ((d >> b) & 1u));
         peers &= ((d >> b) & 1u) ? m : ~m;
     }
     return act ? peers : 0ull;
 }
 
+constexpr uint32_t kDigitMask = (uint32_t)kRadixDigits - 1u;
+constexpr int RS_DPT = kRadixDigits / RS_T;  // digits owned per thread
+static_assert(kRadixDigits % RS_T == 0, "digits must be a multiple of the workgroup size");
+
 __global__ __launch_bounds__(RS_T) void radix_upsweep_kernel(const uint64_t *keys, const uint32_t *counts, int shift,
                                                             int nparts, uint32_t *hist) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    __shared__ uint32_t h[kRadixDigits];
+    for (int q = 0; q < RS_DPT; ++q) h[q * RS_T + threadIdx.x] = 0;
     __syncthreads();
     uint32_t n = counts[CNT_INST];
     uint32_t b, e;
@@ -222,53 +232,157 @@ __global__ __launch_bounds__(RS_T) void radix_upsweep_kernel(const uint64_t *key
     for (uint32_t base = b; base < e; base += RS_T) {
         uint32_t i = base + threadIdx.x;
         bool act = i < e;
-        uint32_t d = act ? (uint32_t)(keys[i] >> shift) & 255u : 0u;
+        uint32_t d = act ? (uint32_t)(keys[i] >> shift) & kDigitMask : 0u;
         uint64_t peers = match_digit(d, act);
         if (act && rank_in(peers) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
-    hist[(size_t)threadIdx.x * nparts + blockIdx.x] = h[threadIdx.x];
+    for (int q = 0; q < RS_DPT; ++q) {
+        int d = q * RS_T + threadIdx.x;
+        hist[(size_t)d * nparts + blockIdx.x] = h[d];
+    }
+}
+
+// exclusive scan over the workgroup (RS_T threads, in thread order); *total gets the sum
+__device__ inline uint32_t block_exscan(uint32_t x, uint32_t *wsum, uint32_t *total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t incl = wave_incl_scan(x);
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (int q = 0; q < RS_T / 64; ++q) {
+        uint32_t c = wsum[q];
+        if (q < w) pre += c;
+        tot += c;
+    }
+    *total = tot;
+    return pre + incl - x;
+}
+
+// Downsweep of one pass.  A workgroup walks its chunk in tiles of RS_TILE keys;
+// wave w takes the w-th quarter of the tile (RS_KPT loads of 64 consecutive keys,
+// so position order inside the tile is (wave, round, lane)), and the next tile is
+// loaded while this one is ranked.  Every wave ranks its keys stably on its own
+// with per-wave digit counters in LDS (no workgroup barrier per round); one scan
+// over (digit, wave) then places the tile in digit order in LDS, and the tile
+// leaves in that order: the keys of one digit go out as one contiguous run, so
+// the global stores coalesce.  Thread t owns digits [RS_DPT t, RS_DPT (t + 1)).
+#ifndef SPLAT_RADIX_KPT
+#define SPLAT_RADIX_KPT 16
+#endif
+constexpr int RS_KPT = SPLAT_RADIX_KPT;  // keys per thread per tile
+constexpr int RS_WTILE = 64 * RS_KPT;
+constexpr int RS_TILE = RS_T * RS_KPT;
+
+__device__ inline void rs_load(const uint64_t *kin, const uint32_t *vin, uint32_t base, uint32_t e, int w, int lane,
+                               uint64_t (&key)[RS_KPT], uint32_t (&val)[RS_KPT]) {
+#pragma unroll
+    for (int k = 0; k < RS_KPT; ++k) {
+        uint32_t i = base + w * RS_WTILE + k * 64 + lane;
+        bool act = i < e;
+        key[k] = act ? kin[i] : 0ull;
+        val[k] = act ? vin[i] : 0u;
+    }
 }
 
 __global__ __launch_bounds__(RS_T) void radix_downsweep_kernel(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
                                                               uint32_t *vout, const uint32_t *counts, int shift,
                                                               int nparts, const uint32_t *hoff) {
-    __shared__ uint32_t wcnt[4][256];
-    __shared__ uint32_t wbase[4][256];
-    int t = threadIdx.x;
-    int w = t >> 6;
-    for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
-    uint32_t run = hoff[(size_t)t * nparts + blockIdx.x];  // running offset of digit t
+    __shared__ uint64_t sk[RS_TILE];
+    __shared__ uint32_t sv[RS_TILE];
+    __shared__ uint32_t wc[RS_T / 64][kRadixDigits];  // per-wave running counts, then per-wave bases
+    __shared__ uint32_t tstart[kRadixDigits];         // first LDS position of each digit in the tile
+    __shared__ uint32_t gstart[kRadixDigits];         // global position of the tile's first key of each digit
+    __shared__ uint32_t wsum[2][RS_T / 64];
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    uint32_t gnext[RS_DPT];
+    for (int q = 0; q < RS_DPT; ++q) {
+        int d = RS_DPT * t + q;
+        gnext[q] = hoff[(size_t)d * nparts + blockIdx.x];
+        for (int ww = 0; ww < RS_T / 64; ++ww) wc[ww][d] = 0;
+    }
     __syncthreads();
     uint32_t n = counts[CNT_INST];
     uint32_t b, e;
     chunk_of(n, nparts, blockIdx.x, b, e);
-    for (uint32_t base = b; base < e; base += RS_T) {
-        uint32_t i = base + t;
-        bool act = i < e;
-        uint64_t key = act ? kin[i] : 0ull;
-        uint32_t val = act ? vin[i] : 0u;
-        uint32_t d = (uint32_t)(key >> shift) & 255u;
-        uint64_t peers = match_digit(d, act);
-        uint32_t r = rank_in(peers);
-        if (act && r == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    uint64_t key[RS_KPT];
+    uint32_t val[RS_KPT];
+    if (b < e) rs_load(kin, vin, b, e, w, lane, key, val);
+    int parity = 0;
+    for (uint32_t base = b; base < e; base += RS_TILE) {
+        uint32_t tn = min((uint32_t)RS_TILE, e - base);
+        uint64_t nkey[RS_KPT];
+        uint32_t nval[RS_KPT], rank[RS_KPT];
+        if (base + RS_TILE < e) rs_load(kin, vin, base + RS_TILE, e, w, lane, nkey, nval);
+        // stable rank inside the wave: the peers' leader bumps the wave's counter after all
+        // lanes read it (LDS operations of one wave complete in issue order)
+#pragma unroll
+        for (int k = 0; k < RS_KPT; ++k) {
+            bool act = (uint32_t)(w * RS_WTILE + k * 64 + lane) < tn;
+            uint32_t d = (uint32_t)(key[k] >> shift) & kDigitMask;
+            uint64_t peers = match_digit(d, act);
+            uint32_t r = rank_in(peers);
+            uint32_t bse = act ? wc[w][d] : 0u;
+            if (act && r == 0) wc[w][d] = bse + (uint32_t)__popcll(peers);
+            rank[k] = bse + r;
+        }
         __syncthreads();
-        // thread t owns digit t: per-wave bases inside this round
-        uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
-        wbase[0][t] = run;
-        wbase[1][t] = run + c0;
-        wbase[2][t] = run + c0 + c1;
-        wbase[3][t] = run + c0 + c1 + c2;
-        run += c0 + c1 + c2 + c3;
-        wcnt[0][t] = 0; wcnt[1][t] = 0; wcnt[2][t] = 0; wcnt[3][t] = 0;
+        // digit-major, wave-minor exclusive scan of the counts
+        uint32_t c[RS_DPT][RS_T / 64], seen[RS_DPT], mine = 0;
+        for (int q = 0; q < RS_DPT; ++q) {
+            seen[q] = 0;
+            for (int ww = 0; ww < RS_T / 64; ++ww) {
+                c[q][ww] = wc[ww][RS_DPT * t + q];
+                seen[q] += c[q][ww];
+            }
+            mine += seen[q];
+        }
+        uint32_t tot;
+        uint32_t start = block_exscan(mine, wsum[parity], &tot);
+        for (int q = 0; q < RS_DPT; ++q) {
+            int d = RS_DPT * t + q;
+            tstart[d] = start;
+            gstart[d] = gnext[q];
+            gnext[q] += seen[q];
+            uint32_t run = start;
+            for (int ww = 0; ww < RS_T / 64; ++ww) {
+                wc[ww][d] = run;
+                run += c[q][ww];
+            }
+            start += seen[q];
+        }
         __syncthreads();
-        if (act) {
-            uint32_t dst = wbase[w][d] + r;
-            if (dst < n) {  // always true when both sweeps saw the same keys
-                kout[dst] = key;
-                vout[dst] = val;
+#pragma unroll
+        for (int k = 0; k < RS_KPT; ++k) {
+            if ((uint32_t)(w * RS_WTILE + k * 64 + lane) < tn) {
+                uint32_t d = (uint32_t)(key[k] >> shift) & kDigitMask;
+                uint32_t pos = wc[w][d] + rank[k];
+                sk[pos] = key[k];
+                sv[pos] = val[k];
             }
         }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < RS_KPT; ++k) {
+            uint32_t i = k * RS_T + t;
+            if (i < tn) {
+                uint64_t kk = sk[i];
+                uint32_t d = (uint32_t)(kk >> shift) & kDigitMask;
+                uint32_t dst = gstart[d] + (i - tstart[d]);
+                if (dst < n) {  // always true when both sweeps saw the same keys
+                    kout[dst] = kk;
+                    vout[dst] = sv[i];
+                }
+            }
+        }
+        for (int q = 0; q < RS_DPT; ++q)
+            for (int ww = 0; ww < RS_T / 64; ++ww) wc[ww][RS_DPT * t + q] = 0;
+#pragma unroll
+        for (int k = 0; k < RS_KPT; ++k) {
+            key[k] = nkey[k];
+            val[k] = nval[k];
+        }
+        parity ^= 1;
         __syncthreads();
     }
 }
@@ -373,7 +487,7 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
     uint2 *ranges = ws_at<uint2>(ws, p.off_ranges);
     uint32_t *queue = ws_at<uint32_t>(ws, p.off_queue);
     uint32_t *hist = ws_at<uint32_t>(ws, p.off_hist);
-    uint32_t *qh = hist + (size_t)256 * p.n_sort_blocks + 1;
+    uint32_t *qh = hist + (size_t)kRadixDigits * p.n_sort_blocks + 1;
     int nT = p.n_views * p.tiles_per_view;
 
     // instance offsets: exclusive scan of the per-slot tile counts
@@ -390,12 +504,12 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
 
     // LSD radix sort over the used key bits
     int bits = p.depth_bits + p.tile_bits;
-    int passes = (bits + 7) / 8;
+    int passes = (bits + kRadixBits - 1) / kRadixBits;
     uint64_t *ki = keys0, *ko = keys1;
     uint32_t *vi = vals0, *vo = vals1;
-    int nh = 256 * p.n_sort_blocks;
+    int nh = kRadixDigits * p.n_sort_blocks;
     for (int ps = 0; ps < passes; ++ps) {
-        int shift = 8 * ps;
+        int shift = kRadixBits * ps;
         hipLaunchKernelGGL(radix_upsweep_kernel, dim3(p.n_sort_blocks), dim3(RS_T), 0, st, ki, counts, shift,
                            p.n_sort_blocks, hist);
         if ((rc = launch_status("radix_upsweep"))) return rc;

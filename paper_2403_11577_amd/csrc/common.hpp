@@ -11,6 +11,13 @@ namespace splat {
 
 constexpr int kWave = 64;
 
+// digit width of the LSD radix sort of the instance keys
+#ifndef SPLAT_RADIX_BITS
+#define SPLAT_RADIX_BITS 9
+#endif
+constexpr int kRadixBits = SPLAT_RADIX_BITS;
+constexpr int kRadixDigits = 1 << kRadixBits;
+
 // workspace views --------------------------------------------------------------
 template <typename T>
 __host__ __device__ inline T *ws_at(void *ws, size_t off) {

@@ -48,7 +48,9 @@ def test_plan_layout_is_aligned_and_disjoint():
     assert p.tiles_x == 7 and p.tiles_y == 3 and p.tiles_per_view == 21
     # key = (view*T + tile) << depth_bits | depth: 63 items need 6 bits, the 0.2..256 m window 27
     assert p.tile_bits == 6 and p.depth_bits == 27
-    assert p.sorted_buf == ((p.tile_bits + p.depth_bits + 7) // 8) % 2
+    rb = p.radix_bits
+    assert 4 <= rb <= 12
+    assert p.sorted_buf == ((p.tile_bits + p.depth_bits + rb - 1) // rb) % 2
 
 
 @pytest.mark.parametrize("kw, msg", [
