@@ -179,9 +179,11 @@ __device__ __forceinline__ bool next_item(const RenderArgs &a, int iter, int &it
 // Pixel layout: lane l covers pixel (l & 7, l >> 3) of every 8x8 sub-block k of
 // the tile (k row-major over the TW/8 x TH/8 sub-blocks).
 //
-// Forward state per pixel: T > 0 while the pixel is still compositing; when a
-// blend would take T below t_min the pixel stops, its T is kept in Tf and T is
-// set to 0, which makes every later pair of that pixel a no-op without a branch.
+// Forward state per pixel: the transmittance T and its live copy L, equal to T
+// while the pixel composites and 0 once it has stopped.  The weight of a pair is
+// alpha L, so a stopped pixel runs the same instructions without effect; when a
+// blend would take T below t_min, L drops to 0 and T keeps its value.  Sub-blocks
+// whose 64 pixels have all stopped are skipped from the next batch on.
 //
 // STATS = true is the instrumented variant (pair counters for the roofline);
 // it computes exactly the same outputs.
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
         int x0 = tx * TW, y0 = ty * TH;
         int xb = x0 & ~31, yb = y0 & ~31;
         uint2 rg = a.ranges[tid];
-        float T[NSB], Tf[NSB], C0[NSB], C1[NSB], C2[NSB], px[NSB], py[NSB];
+        float T[NSB], L[NSB], C0[NSB], C1[NSB], C2[NSB], px[NSB], py[NSB];
         int last[NSB];
 #pragma unroll
         for (int k = 0; k < NSB; ++k) {
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
             px[k] = (float)(x0 - xb + qx) + 0.5f;
             py[k] = (float)(y0 - yb + qy) + 0.5f;
             T[k] = (x0 + qx < a.W && y0 + qy < a.H) ? 1.f : 0.f;
-            Tf[k] = 1.f;
+            L[k] = T[k];
             C0[k] = C1[k] = C2[k] = 0.f;
             last[k] = -1;
         }
@@ -217,15 +219,15 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
         Stage cur = derive<TW, TH>(a, load_raw(a, load_slot(a, rg.x + lane, rg.y), nslots), fxb, fyb, fox, foy);
         uint32_t sl_next = load_slot(a, rg.x + 64 + lane, rg.y);
         for (uint32_t b = rg.x; b < rg.y; b += 64) {
-            bool any = false;
+            uint32_t live = 0;  // sub-blocks with a pixel still compositing
 #pragma unroll
-            for (int k = 0; k < NSB; ++k) any |= T[k] > 0.f;
-            if (__ballot(any) == 0) break;
+            for (int k = 0; k < NSB; ++k) live |= __ballot(L[k] > 0.f) ? (1u << k) : 0u;
+            if (live == 0) break;
             Raw raw_next = load_raw(a, sl_next, nslots);              // records of batch b + 64
             uint32_t sl_after = load_slot(a, b + 128 + lane, rg.y);   // slot ids of batch b + 128
             int n = (int)min(64u, rg.y - b);
             for (int j = 0; j < n; ++j) {
-                uint32_t m = bcast_u(cur.mask, j);
+                uint32_t m = bcast_u(cur.mask, j) & live;
                 if (m == 0u) continue;
                 float mx = bcast(cur.mx, j), my = bcast(cur.my, j);
                 float A = bcast(cur.A, j), Bc = bcast(cur.Bc, j), Cc = bcast(cur.Cc, j), lo2 = bcast(cur.lo2, j);
@@ -234,22 +236,21 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
 #pragma unroll
                 for (int k = 0; k < NSB; ++k) {
                     if (!(m & (1u << k))) continue;  // wave-uniform
-                    if (STATS) n_eval += T[k] > 0.f;
+                    if (STATS) n_eval += L[k] > 0.f;
                     float dx = px[k] - mx, dy = py[k] - my;
                     float al = fminf(a.amax, exp2_hw(power2(dx, dy, A, Bc, Cc, lo2)));
                     al = al >= a.amin ? al : 0.f;
-                    float w = al * T[k];
+                    float w = al * L[k];
                     float Tn = T[k] - w;
-                    bool stop = (Tn < a.tmin) && (T[k] > 0.f);
-                    Tf[k] = stop ? T[k] : Tf[k];
+                    bool stop = Tn < a.tmin;  // cannot hold for a stopped pixel: its T stays >= t_min
                     w = stop ? 0.f : w;
-                    Tn = stop ? 0.f : Tn;
+                    T[k] = stop ? T[k] : Tn;
+                    L[k] = stop ? 0.f : L[k] - w;
                     if (STATS) n_blend += w > 0.f;
                     C0[k] = __fmaf_rn(cr, w, C0[k]);
                     C1[k] = __fmaf_rn(cg, w, C1[k]);
                     C2[k] = __fmaf_rn(cb, w, C2[k]);
                     last[k] = w > 0.f ? idx : last[k];
-                    T[k] = Tn;
                 }
             }
             cur = derive<TW, TH>(a, raw_next, fxb, fyb, fox, foy);
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
             int gx = x0 + 8 * (k % SBX) + lx, gy = y0 + 8 * (k / SBX) + ly;
             if (gx >= a.W || gy >= a.H) continue;
             size_t o = (size_t)gy * a.W + gx;
-            float Tfin = T[k] > 0.f ? T[k] : Tf[k];
+            float Tfin = T[k];
             img[3 * vo + o] = __fmaf_rn(Tfin, a.bg0, C0[k]);
             img[3 * vo + HW + o] = __fmaf_rn(Tfin, a.bg1, C1[k]);
             img[3 * vo + 2 * HW + o] = __fmaf_rn(Tfin, a.bg2, C2[k]);
