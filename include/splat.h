@@ -114,10 +114,11 @@ typedef struct splat_plan {
     size_t off_vals;        /* u32[2][inst_cap]                                          */
     size_t off_ranges;      /* u32x2[V*T]: [start,end) of every (view, tile) list         */
     size_t off_queue;       /* u32[V*T]: (view, tile) work items, most expensive first    */
-    size_t off_hist;        /* u32[256*n_sort_blocks + 1024] radix / queue histograms     */
+    size_t off_hist;        /* u32[2^radix_bits*n_sort_blocks + 129] radix / queue histograms */
     size_t off_scan;        /* u32[scan partials]                                        */
     size_t off_grad2d;      /* float[slot_cap][9]: d(mu x,y; conic a,b,c; o; r,g,b)       */
     size_t off_visbits;     /* u64[V*n_blocks_proj*4]: visible (view, Gaussian) bit masks  */
+    size_t off_dwpart;      /* f64[V][n_blocks_proj][12]: per-block W2C gradient partials  */
     int32_t sorted_buf;     /* which of the two key/value buffers holds the sorted result */
     int32_t radix_bits;     /* digit width of the LSD radix sort (passes = ceil(key bits / radix_bits)) */
 } splat_plan;

@@ -37,21 +37,13 @@ struct Proj {
 
 __device__ inline bool finite_f(float v) { return isfinite(v); }
 
-// The projection of one Gaussian into one view.  Returns a cull code (0 = visible).
-__device__ int project_gauss(const splat_settings &S, const double *M, const double *K4, int W, int H,
-                             const float *x, const float *q, const float *s, float o, Proj &P) {
-    if (!(finite_f(x[0]) && finite_f(x[1]) && finite_f(x[2]) && finite_f(q[0]) && finite_f(q[1]) &&
-          finite_f(q[2]) && finite_f(q[3]) && finite_f(s[0]) && finite_f(s[1]) && finite_f(s[2]) &&
-          finite_f(o)))
-        return PC_NONFINITE;
-    // float32 depth key: fma chain on float32-rounded row 2 of W2C
-    P.depth32 = __fmaf_rn((float)M[8], x[0], __fmaf_rn((float)M[9], x[1], __fmaf_rn((float)M[10], x[2], (float)M[11])));
-    if (!(P.depth32 > (float)S.near_z)) return PC_NEAR;
-    if (P.depth32 > (float)S.far_z) return PC_FAR;
-    if ((double)o < S.alpha_min) return PC_OPAC;
+// The geometric part of the projection of one Gaussian into one view (no
+// culling): camera-frame mean, A = W R(q) diag(s), Jacobian with the guard
+// clamp, 2-D covariance, conic and screen mean.
+__device__ inline void project_core(const splat_settings &S, const double *M, const double *K4, int W, int H,
+                                    const float *x, const float *q, const float *s, Proj &P) {
     double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
     double n2 = qw * qw + qx * qx + qy * qy + qz * qz;
-    if (!(n2 >= 1e-24)) return PC_QUAT;
     P.qn = sqrt(n2);
     qw /= P.qn; qx /= P.qn; qy /= P.qn; qz /= P.qn;
     P.qh[0] = qw; P.qh[1] = qx; P.qh[2] = qy; P.qh[3] = qz;
@@ -88,6 +80,26 @@ __device__ int project_gauss(const splat_settings &S, const double *M, const dou
     P.Q[0] = syy * idet; P.Q[1] = -sxy * idet; P.Q[2] = sxx * idet;
     P.mu[0] = fx * ux + cx;
     P.mu[1] = fy * uy + cy;
+}
+
+// The projection of one Gaussian into one view.  Returns a cull code (0 = visible).
+__device__ int project_gauss(const splat_settings &S, const double *M, const double *K4, int W, int H,
+                             const float *x, const float *q, const float *s, float o, Proj &P) {
+    if (!(finite_f(x[0]) && finite_f(x[1]) && finite_f(x[2]) && finite_f(q[0]) && finite_f(q[1]) &&
+          finite_f(q[2]) && finite_f(q[3]) && finite_f(s[0]) && finite_f(s[1]) && finite_f(s[2]) &&
+          finite_f(o)))
+        return PC_NONFINITE;
+    // float32 depth key: fma chain on float32-rounded row 2 of W2C
+    P.depth32 = __fmaf_rn((float)M[8], x[0], __fmaf_rn((float)M[9], x[1], __fmaf_rn((float)M[10], x[2], (float)M[11])));
+    if (!(P.depth32 > (float)S.near_z)) return PC_NEAR;
+    if (P.depth32 > (float)S.far_z) return PC_FAR;
+    if ((double)o < S.alpha_min) return PC_OPAC;
+    {
+        double n2 = (double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3];
+        if (!(n2 >= 1e-24)) return PC_QUAT;
+    }
+    project_core(S, M, K4, W, H, x, q, s, P);
+    double sxx = P.S2[0], syy = P.S2[2];
     double k2 = fmax(2.0 * log((double)o / S.alpha_min), 0.0);
     double ex = sqrt(k2 * sxx) * (1.0 + S.pad_rel) + S.pad_px;
     double ey = sqrt(k2 * syy) * (1.0 + S.pad_rel) + S.pad_px;
@@ -287,20 +299,68 @@ __device__ void slot_adjoint(const Proj &P, const double *M, const double *K4, c
     gq[3] += (gq3 - qz * dot) * iq;
 }
 
+// Transposed FP64 reduction of twelve per-lane values over the wave: four
+// exchange steps inside each 16-lane row with partners lane^1, lane^2, lane^7 and
+// lane^15 (DPP moves of both halves), then two cross-row exchanges.  Lane i ends
+// with the wave total of value number cls(i) = c0 + 2 c1 + 4 c2 + 8 c3, where
+// c0 = b0^b2, c1 = b1^b2, c2 = b2^b3, c3 = b3 for the bits b of i & 15 (numbers
+// 12..15 carry padding).  About 80 VALU operations instead of twelve separate
+// shuffle reductions.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double xpair_d(double lo, double hi, bool c) {
+    double keep = c ? hi : lo, send = c ? lo : hi;
+    return keep + dpp_d<CTRL>(send);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double xpad_d(double v) { return v + dpp_d<CTRL>(v); }
+
+__device__ inline double reduce12(const double (&v)[12], bool c0, bool c1, bool c2, bool c3) {
+    double a0 = xpair_d<0xB1>(v[0], v[1], c0), a1 = xpair_d<0xB1>(v[2], v[3], c0);
+    double a2 = xpair_d<0xB1>(v[4], v[5], c0), a3 = xpair_d<0xB1>(v[6], v[7], c0);
+    double a4 = xpair_d<0xB1>(v[8], v[9], c0), a5 = xpair_d<0xB1>(v[10], v[11], c0);
+    double b0 = xpair_d<0x4E>(a0, a1, c1), b1 = xpair_d<0x4E>(a2, a3, c1), b2 = xpair_d<0x4E>(a4, a5, c1);
+    double d0 = xpair_d<0x141>(b0, b1, c2), d1 = xpad_d<0x141>(b2);
+    double e = xpair_d<0x140>(d0, d1, c3);
+    e += __shfl_xor(e, 16, kWave);
+    e += __shfl_xor(e, 32, kWave);
+    return e;
+}
+
+struct LaneClass {
+    bool c0, c1, c2, c3;
+    int cls;
+    __device__ explicit LaneClass(int lane) {
+        int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+        c0 = b0 ^ b2; c1 = b1 ^ b2; c2 = b2 ^ b3; c3 = b3;
+        cls = (int)c0 | ((int)c1 << 1) | ((int)c2 << 2) | ((int)c3 << 3);
+    }
+};
+
 // One thread per Gaussian walks every view; the visibility mask written by the
 // count pass and the per-block slot offsets give the slot of each visible pair
 // (slots are compacted per view in Gaussian order), so the per-Gaussian
 // gradients are summed in float64 registers and written once, without atomics.
 // The W2C gradient of each view is reduced over the workgroup in float64 and
-// added with one atomic per (workgroup, view, entry).
+// stored as the workgroup's partial; dw2c_reduce_kernel sums the partials of a
+// view in a fixed order (deterministic, no contended float64 atomics).
 __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, splat_gaussians g, const double *w2c,
                                                          const double *intr, int W, int H, int V, int nb,
                                                          const uint32_t *blockoff, const uint64_t *visbits,
                                                          int64_t slot_cap, const float *grad2d, float *dquat,
                                                          float *dscale, float *dopac, float *dcolor, float *dmean,
-                                                         double *dw2c) {
+                                                         double *dwpart) {
     __shared__ double red[4][12];
     const int b = blockIdx.x, wv = threadIdx.x >> 6, lane = __lane_id();
+    const LaneClass lc(lane);
+    const bool writer = lane < 16 && lc.cls < 12;
     const int64_t i = (int64_t)b * 256 + threadIdx.x;
     const int64_t n = g.n;
     const bool live = i < n;
@@ -309,9 +369,13 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
     double gq[4] = {0, 0, 0, 0}, gs[3] = {0, 0, 0}, gm[3] = {0, 0, 0}, go = 0.0, gc[3] = {0, 0, 0};
     for (int v = 0; v < V; ++v) {
         const uint64_t *vb = visbits + ((size_t)v * nb + b) * 4;
+        double *part = dwpart + ((size_t)v * nb + b) * 12;
         uint64_t mask = vb[wv];
         bool vis = live && ((mask >> lane) & 1ull);
-        if (!__syncthreads_or(vis)) continue;  // nothing of this workgroup visible in view v
+        if (!__syncthreads_or(vis)) {  // nothing of this workgroup visible in view v
+            if (threadIdx.x < 12) part[threadIdx.x] = 0.0;
+            continue;
+        }
         double gw[12];
         for (int k = 0; k < 12; ++k) gw[k] = 0.0;
         if (vis) {
@@ -322,7 +386,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
                 const double *M = w2c + 12 * v;
                 const double *K4 = intr + 4 * v;
                 Proj P;
-                project_gauss(S, M, K4, W, H, x, q, s, o, P);
+                project_core(S, M, K4, W, H, x, q, s, P);
                 const float *gd = grad2d + 9 * slot;
                 go += gd[5];
                 gc[0] += gd[6];
@@ -331,14 +395,13 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
                 slot_adjoint(P, M, K4, x, s, gd, gq, gs, gm, gw);
             }
         }
-        for (int k = 0; k < 12; ++k) {
-            double t = wave_sum(gw[k]);
-            if (lane == 0) red[wv][k] = t;
-        }
+        double tot = 0.0;
+        if (mask != 0ull) tot = reduce12(gw, lc.c0, lc.c1, lc.c2, lc.c3);  // wave-uniform
+        if (writer) red[wv][lc.cls] = tot;
         __syncthreads();
         if (threadIdx.x < 12) {
             int k = threadIdx.x;
-            atomicAdd(dw2c + 12 * v + k, ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k]);
+            part[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
         }
         __syncthreads();
     }
@@ -349,6 +412,26 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
     for (int k = 0; k < 3; ++k) dcolor[k * n + i] += (float)gc[k];
     if (dmean)
         for (int k = 0; k < 3; ++k) dmean[k * n + i] += (float)gm[k];
+}
+
+// dw2c[v] += sum over the workgroups of their partials, in a fixed order.
+__global__ __launch_bounds__(256) void dw2c_reduce_kernel(const double *dwpart, int nb, double *dw2c) {
+    __shared__ double red[4][12];
+    const int v = blockIdx.x, wv = threadIdx.x >> 6, lane = __lane_id();
+    const LaneClass lc(lane);
+    double acc[12];
+    for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        const double *p = dwpart + ((size_t)v * nb + b) * 12;
+        for (int k = 0; k < 12; ++k) acc[k] += p[k];
+    }
+    double tot = reduce12(acc, lc.c0, lc.c1, lc.c2, lc.c3);
+    if (lane < 16 && lc.cls < 12) red[wv][lc.cls] = tot;
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        int k = threadIdx.x;
+        dw2c[12 * v + k] += ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    }
 }
 
 }  // namespace
@@ -386,10 +469,14 @@ int launch_project_bwd(const splat_plan &p, void *ws, const splat_gaussians &g, 
                        float *dmean, double *dw2c, hipStream_t st) {
     if (g.n == 0) return 0;
     int nb = p.n_blocks_proj;
+    double *part = ws_at<double>(ws, p.off_dwpart);
     hipLaunchKernelGGL(project_bwd_kernel, dim3(nb), dim3(256), 0, st, p.s, g, w2c, intr, p.width, p.height,
                        p.n_views, nb, ws_at<uint32_t>(ws, p.off_blockcnt), ws_at<uint64_t>(ws, p.off_visbits),
-                       p.slot_cap, ws_at<float>(ws, p.off_grad2d), dquat, dscale, dopac, dcolor, dmean, dw2c);
-    return launch_status("project_bwd");
+                       p.slot_cap, ws_at<float>(ws, p.off_grad2d), dquat, dscale, dopac, dcolor, dmean, part);
+    int rc = launch_status("project_bwd");
+    if (rc) return rc;
+    hipLaunchKernelGGL(dw2c_reduce_kernel, dim3(p.n_views), dim3(256), 0, st, part, nb, dw2c);
+    return launch_status("dw2c_reduce");
 }
 
 }  // namespace splat
