@@ -98,14 +98,14 @@ typedef struct splat_plan {
     int32_t n_views, width, height;
     int32_t tiles_x, tiles_y, tiles_per_view;
     int32_t depth_bits, tile_bits;   /* sort key = (view*T + tile) << depth_bits | depth */
-    int32_t n_blocks_proj;           /* project blocks per view (256 Gaussians each) */
+    int32_t n_blocks_proj;           /* project workgroups (256 Gaussians each, 4 waves) */
     int32_t n_sort_blocks;           /* radix-sort partitions */
     int64_t n_gauss, slot_cap, inst_cap;
     size_t ws_bytes;
     size_t off_status;      /* u32                                                      */
     size_t off_counts;      /* u32[8]: 0 slots, 1 instances, 2 work counter, 3..7 spare  */
     size_t off_view_off;    /* u32[V+1] first slot of every view                          */
-    size_t off_blockcnt;    /* u32[V*n_blocks_proj+1] visible count per project block, scanned in place to slot offsets */
+    size_t off_blockcnt;    /* u32[V*n_blocks_proj*4+1] visible count per (view, wave), scanned in place to slot offsets */
     size_t off_rec;         /* float4[3][slot_cap]: (mx,my,lx,ly) (a,b,c,o) (r,g,b,depth) */
     size_t off_meta;        /* int2[slot_cap]: (Gaussian id, view)                       */
     size_t off_rect;        /* u16x4[slot_cap]: tile rect (x0,x1,y0,y1) inclusive         */
@@ -119,6 +119,7 @@ typedef struct splat_plan {
     size_t off_grad2d;      /* float[slot_cap][9]: d(mu x,y; conic a,b,c; o; r,g,b)       */
     size_t off_visbits;     /* u64[V*n_blocks_proj*4]: visible (view, Gaussian) bit masks  */
     size_t off_dwpart;      /* f64[V][n_blocks_proj][12]: per-block W2C gradient partials  */
+    size_t off_cam;         /* f64[V][8]: per-view camera constants of the projection       */
     int32_t sorted_buf;     /* which of the two key/value buffers holds the sorted result */
     int32_t radix_bits;     /* digit width of the LSD radix sort (passes = ceil(key bits / radix_bits)) */
 } splat_plan;

@@ -36,7 +36,7 @@ class splat_gaussians(C.Structure):
 
 _PLAN_OFFS = ["ws_bytes", "off_status", "off_counts", "off_view_off", "off_blockcnt", "off_rec",
               "off_meta", "off_rect", "off_ntiles", "off_keys", "off_vals", "off_ranges",
-              "off_queue", "off_hist", "off_scan", "off_grad2d", "off_visbits", "off_dwpart"]
+              "off_queue", "off_hist", "off_scan", "off_grad2d", "off_visbits", "off_dwpart", "off_cam"]
 
 
 class splat_plan(C.Structure):

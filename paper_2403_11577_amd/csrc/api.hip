@@ -179,7 +179,6 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     if (ntiles_all >= ((uint64_t)1 << 31)) { set_error("too many (view, tile) items"); return SPLAT_EUNSUPPORTED; }
     p.n_blocks_proj = (int32_t)((n_gauss + 255) / 256);
     if (p.n_blocks_proj < 1) p.n_blocks_proj = 1;
-    if (p.n_blocks_proj > 65535) { set_error("too many Gaussians for one projection grid row"); return SPLAT_EUNSUPPORTED; }
     int64_t nsb = (inst_cap + 8191) / 8192;
     p.n_sort_blocks = (int32_t)(nsb < 1 ? 1 : (nsb > 2048 ? 2048 : nsb));
     p.n_gauss = n_gauss;
@@ -196,7 +195,7 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
         off = align256(off + (bytes ? bytes : 1));
         return o;
     };
-    int64_t nproj = (int64_t)n_views * p.n_blocks_proj + 1;
+    int64_t nproj = (int64_t)n_views * p.n_blocks_proj * 4 + 1;
     size_t nparts = scan_partials(slot_cap + 1);
     size_t np2 = scan_partials(nproj);
     size_t np3 = scan_partials((int64_t)kRadixDigits * p.n_sort_blocks);
@@ -219,6 +218,7 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     p.off_grad2d = take((size_t)slot_cap * 36);
     p.off_visbits = take((size_t)n_views * p.n_blocks_proj * 4 * 8);
     p.off_dwpart = take((size_t)n_views * p.n_blocks_proj * 12 * 8);
+    p.off_cam = take((size_t)n_views * 8 * 8);
     p.ws_bytes = off;
     *plan = p;
     return SPLAT_OK;

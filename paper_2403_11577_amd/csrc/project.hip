@@ -19,6 +19,18 @@ namespace {
 
 enum { PC_OK = 0, PC_NEAR = 1, PC_FAR = 2, PC_OPAC = 4, PC_QUAT = 8, PC_OFF = 16, PC_NONFINITE = 32 };
 
+// View-independent part of a Gaussian: unit quaternion, its rotation and the
+// squared footprint radius k^2 = 2 ln(o / alpha_min) (clamped at 0).
+struct GaussPre {
+    double qh[4], qn, R[9], k2;
+};
+
+// Per-view camera constants: focal lengths, principal point and the clamp bounds
+// of the Jacobian's x/z, y/z ratios.
+struct CamC {
+    double fx, fy, cx, cy, gx0, gx1, gy0, gy1;
+};
+
 struct Proj {
     float depth32;
     double t[3];
@@ -37,38 +49,54 @@ struct Proj {
 
 __device__ inline bool finite_f(float v) { return isfinite(v); }
 
-// The geometric part of the projection of one Gaussian into one view (no
-// culling): camera-frame mean, A = W R(q) diag(s), Jacobian with the guard
-// clamp, 2-D covariance, conic and screen mean.
-__device__ inline void project_core(const splat_settings &S, const double *M, const double *K4, int W, int H,
-                                    const float *x, const float *q, const float *s, Proj &P) {
+__device__ inline void gauss_pre(const splat_settings &S, const float *q, float o, GaussPre &G) {
     double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
     double n2 = qw * qw + qx * qx + qy * qy + qz * qz;
-    P.qn = sqrt(n2);
-    qw /= P.qn; qx /= P.qn; qy /= P.qn; qz /= P.qn;
-    P.qh[0] = qw; P.qh[1] = qx; P.qh[2] = qy; P.qh[3] = qz;
-    double *R = P.R;
+    G.qn = sqrt(n2);
+    qw /= G.qn; qx /= G.qn; qy /= G.qn; qz /= G.qn;
+    G.qh[0] = qw; G.qh[1] = qx; G.qh[2] = qy; G.qh[3] = qz;
+    double *R = G.R;
     R[0] = 1.0 - 2.0 * (qy * qy + qz * qz); R[1] = 2.0 * (qx * qy - qw * qz); R[2] = 2.0 * (qx * qz + qw * qy);
     R[3] = 2.0 * (qx * qy + qw * qz); R[4] = 1.0 - 2.0 * (qx * qx + qz * qz); R[5] = 2.0 * (qy * qz - qw * qx);
     R[6] = 2.0 * (qx * qz - qw * qy); R[7] = 2.0 * (qy * qz + qw * qx); R[8] = 1.0 - 2.0 * (qx * qx + qy * qy);
+    G.k2 = fmax(2.0 * log((double)o / S.alpha_min), 0.0);
+}
+
+__global__ void camconst_kernel(splat_settings S, const double *intr, int V, int W, int H, CamC *cam) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const double *K4 = intr + 4 * v;
+    CamC c;
+    c.fx = K4[0]; c.fy = K4[1]; c.cx = K4[2]; c.cy = K4[3];
+    c.gx0 = (-c.cx - S.guard * W) / c.fx; c.gx1 = (W - c.cx + S.guard * W) / c.fx;
+    c.gy0 = (-c.cy - S.guard * H) / c.fy; c.gy1 = (H - c.cy + S.guard * H) / c.fy;
+    cam[v] = c;
+}
+
+// The geometric part of the projection of one Gaussian into one view (no
+// culling): camera-frame mean, A = W R(q) diag(s), Jacobian with the guard
+// clamp, 2-D covariance, conic (if asked) and screen mean.
+__device__ inline void project_view(const splat_settings &S, const double *M, const CamC &C, const float *x,
+                                    const float *s, const GaussPre &G, bool conic, Proj &P) {
+    for (int k = 0; k < 9; ++k) P.R[k] = G.R[k];
+    for (int k = 0; k < 4; ++k) P.qh[k] = G.qh[k];
+    P.qn = G.qn;
+    const double *R = G.R;
     double xd[3] = {x[0], x[1], x[2]};
     for (int i = 0; i < 3; ++i) P.t[i] = M[4 * i] * xd[0] + M[4 * i + 1] * xd[1] + M[4 * i + 2] * xd[2] + M[4 * i + 3];
     // A = W R diag(s)
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             P.A[3 * i + j] = (M[4 * i] * R[j] + M[4 * i + 1] * R[3 + j] + M[4 * i + 2] * R[6 + j]) * (double)s[j];
-    double fx = K4[0], fy = K4[1], cx = K4[2], cy = K4[3];
     double tz = P.t[2];
     double ux = P.t[0] / tz, uy = P.t[1] / tz;
-    double gx0 = (-cx - S.guard * W) / fx, gx1 = (W - cx + S.guard * W) / fx;
-    double gy0 = (-cy - S.guard * H) / fy, gy1 = (H - cy + S.guard * H) / fy;
-    P.clx = (ux < gx0) || (ux > gx1);
-    P.cly = (uy < gy0) || (uy > gy1);
-    P.xh = fmin(fmax(ux, gx0), gx1);
-    P.yh = fmin(fmax(uy, gy0), gy1);
+    P.clx = (ux < C.gx0) || (ux > C.gx1);
+    P.cly = (uy < C.gy0) || (uy > C.gy1);
+    P.xh = fmin(fmax(ux, C.gx0), C.gx1);
+    P.yh = fmin(fmax(uy, C.gy0), C.gy1);
     double *J = P.J;
-    J[0] = fx / tz; J[1] = 0.0; J[2] = -fx * P.xh / tz;
-    J[3] = 0.0; J[4] = fy / tz; J[5] = -fy * P.yh / tz;
+    J[0] = C.fx / tz; J[1] = 0.0; J[2] = -C.fx * P.xh / tz;
+    J[3] = 0.0; J[4] = C.fy / tz; J[5] = -C.fy * P.yh / tz;
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 3; ++j)
             P.T[3 * i + j] = J[3 * i] * P.A[j] + J[3 * i + 1] * P.A[3 + j] + J[3 * i + 2] * P.A[6 + j];
@@ -76,33 +104,19 @@ __device__ inline void project_core(const splat_settings &S, const double *M, co
     double sxy = P.T[0] * P.T[3] + P.T[1] * P.T[4] + P.T[2] * P.T[5];
     double syy = P.T[3] * P.T[3] + P.T[4] * P.T[4] + P.T[5] * P.T[5] + S.eps2d;
     P.S2[0] = sxx; P.S2[1] = sxy; P.S2[2] = syy;
-    double idet = 1.0 / (sxx * syy - sxy * sxy);
-    P.Q[0] = syy * idet; P.Q[1] = -sxy * idet; P.Q[2] = sxx * idet;
-    P.mu[0] = fx * ux + cx;
-    P.mu[1] = fy * uy + cy;
+    if (conic) {
+        double idet = 1.0 / (sxx * syy - sxy * sxy);
+        P.Q[0] = syy * idet; P.Q[1] = -sxy * idet; P.Q[2] = sxx * idet;
+    }
+    P.mu[0] = C.fx * ux + C.cx;
+    P.mu[1] = C.fy * uy + C.cy;
 }
 
-// The projection of one Gaussian into one view.  Returns a cull code (0 = visible).
-__device__ int project_gauss(const splat_settings &S, const double *M, const double *K4, int W, int H,
-                             const float *x, const float *q, const float *s, float o, Proj &P) {
-    if (!(finite_f(x[0]) && finite_f(x[1]) && finite_f(x[2]) && finite_f(q[0]) && finite_f(q[1]) &&
-          finite_f(q[2]) && finite_f(q[3]) && finite_f(s[0]) && finite_f(s[1]) && finite_f(s[2]) &&
-          finite_f(o)))
-        return PC_NONFINITE;
-    // float32 depth key: fma chain on float32-rounded row 2 of W2C
-    P.depth32 = __fmaf_rn((float)M[8], x[0], __fmaf_rn((float)M[9], x[1], __fmaf_rn((float)M[10], x[2], (float)M[11])));
-    if (!(P.depth32 > (float)S.near_z)) return PC_NEAR;
-    if (P.depth32 > (float)S.far_z) return PC_FAR;
-    if ((double)o < S.alpha_min) return PC_OPAC;
-    {
-        double n2 = (double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3];
-        if (!(n2 >= 1e-24)) return PC_QUAT;
-    }
-    project_core(S, M, K4, W, H, x, q, s, P);
-    double sxx = P.S2[0], syy = P.S2[2];
-    double k2 = fmax(2.0 * log((double)o / S.alpha_min), 0.0);
-    double ex = sqrt(k2 * sxx) * (1.0 + S.pad_rel) + S.pad_px;
-    double ey = sqrt(k2 * syy) * (1.0 + S.pad_rel) + S.pad_px;
+// Pixel rectangle of the alpha >= alpha_min footprint (exact AABB of the ellipse,
+// padded); PC_OFF if it misses the image.
+__device__ inline int footprint(const splat_settings &S, double k2, int W, int H, Proj &P) {
+    double ex = sqrt(k2 * P.S2[0]) * (1.0 + S.pad_rel) + S.pad_px;
+    double ey = sqrt(k2 * P.S2[2]) * (1.0 + S.pad_rel) + S.pad_px;
     double a0 = ceil(P.mu[0] - 0.5 - ex), a1 = floor(P.mu[0] - 0.5 + ex);
     double b0 = ceil(P.mu[1] - 0.5 - ey), b1 = floor(P.mu[1] - 0.5 + ey);
     a0 = fmax(a0, 0.0); b0 = fmax(b0, 0.0);
@@ -112,16 +126,79 @@ __device__ int project_gauss(const splat_settings &S, const double *M, const dou
     return PC_OK;
 }
 
-__device__ inline void load_gauss(const splat_gaussians &g, int64_t i, float *x, float *q, float *s, float &o) {
-    int64_t n = g.n;
-    x[0] = g.mean[i]; x[1] = g.mean[n + i]; x[2] = g.mean[2 * n + i];
-    q[0] = g.quat[i]; q[1] = g.quat[n + i]; q[2] = g.quat[2 * n + i]; q[3] = g.quat[3 * n + i];
-    s[0] = g.scale[i]; s[1] = g.scale[n + i]; s[2] = g.scale[2 * n + i];
-    o = g.opacity[i];
+// float32 depth key: fma chain on float32-rounded row 2 of W2C
+__device__ inline float depth_key(const double *M, const float *x) {
+    return __fmaf_rn((float)M[8], x[0], __fmaf_rn((float)M[9], x[1], __fmaf_rn((float)M[10], x[2], (float)M[11])));
 }
 
-__device__ inline void flag_status(uint32_t *status, int code) {
-    uint32_t bits = (code == PC_NONFINITE ? SPLAT_ST_NONFINITE : 0u) | (code == PC_QUAT ? SPLAT_ST_DEGENERATE : 0u);
+// Conservative float32 frustum test, run before the float64 projection: true
+// only if the exact footprint rectangle is certainly empty.  The exact
+// half-width is k sqrt(Sigma2_xx) (1 + pad_rel) + pad_px with Sigma2_xx =
+// |J_x A|^2 + eps2d <= |J_x|^2 max(s)^2 + eps2d (W and R are rotations), where
+// J_x = (fx / z, 0, -fx xh / z) with the clamped ratio xh; likewise for y.  The
+// bound is widened by 0.1% + 1 px + 1e-5 |mu| to cover float32 rounding.
+__device__ inline bool offscreen_bound(const splat_settings &S, const double *M, const CamC &C, int W, int H,
+                                       const float *x, const float *s, float k2f, float z) {
+    float t0 = __fmaf_rn((float)M[0], x[0], __fmaf_rn((float)M[1], x[1], __fmaf_rn((float)M[2], x[2], (float)M[3])));
+    float t1 = __fmaf_rn((float)M[4], x[0], __fmaf_rn((float)M[5], x[1], __fmaf_rn((float)M[6], x[2], (float)M[7])));
+    float iz = 1.f / z;
+    float fx = (float)C.fx, fy = (float)C.fy, cx = (float)C.cx, cy = (float)C.cy;
+    float ux = t0 * iz, uy = t1 * iz;
+    float xh = fminf(fmaxf(ux, (float)C.gx0), (float)C.gx1);
+    float yh = fminf(fmaxf(uy, (float)C.gy0), (float)C.gy1);
+    float sm = fmaxf(fmaxf(s[0], s[1]), s[2]);
+    float e2 = (float)S.eps2d;
+    float jx = fx * iz, jy = fy * iz;
+    float sx = jx * jx * (1.f + xh * xh) * sm * sm + e2;
+    float sy = jy * jy * (1.f + yh * yh) * sm * sm + e2;
+    float pr = 1.f + (float)S.pad_rel, pp = (float)S.pad_px;
+    float mx = fx * ux + cx, my = fy * uy + cy;
+    float ex = (sqrtf(k2f * sx) * pr + pp) * 1.001f + 1.f + 1e-5f * fabsf(mx);
+    float ey = (sqrtf(k2f * sy) * pr + pp) * 1.001f + 1.f + 1e-5f * fabsf(my);
+    // NaN anywhere makes every comparison false: not culled here, decided exactly afterwards
+    return (mx - 0.5f + ex < 0.f) || (mx - 0.5f - ex > (float)(W - 1)) || (my - 0.5f + ey < 0.f) ||
+           (my - 0.5f - ey > (float)(H - 1));
+}
+
+// What a view makes of one Gaussian, in the order of the cull tests: non-finite
+// input, depth at or before the near plane, beyond the far plane, opacity below
+// alpha_min, degenerate quaternion, footprint off the image; 0 = visible.
+struct GaussIn {
+    float x[3], q[4], s[3], o;
+    bool fin, opac_ok, quat_ok;
+    GaussPre G;
+};
+
+__device__ inline void gauss_in(const splat_settings &S, const splat_gaussians &g, int64_t i, GaussIn &gi) {
+    int64_t n = g.n;
+    gi.x[0] = g.mean[i]; gi.x[1] = g.mean[n + i]; gi.x[2] = g.mean[2 * n + i];
+    gi.q[0] = g.quat[i]; gi.q[1] = g.quat[n + i]; gi.q[2] = g.quat[2 * n + i]; gi.q[3] = g.quat[3 * n + i];
+    gi.s[0] = g.scale[i]; gi.s[1] = g.scale[n + i]; gi.s[2] = g.scale[2 * n + i];
+    gi.o = g.opacity[i];
+    gi.fin = finite_f(gi.x[0]) && finite_f(gi.x[1]) && finite_f(gi.x[2]) && finite_f(gi.q[0]) && finite_f(gi.q[1]) &&
+             finite_f(gi.q[2]) && finite_f(gi.q[3]) && finite_f(gi.s[0]) && finite_f(gi.s[1]) && finite_f(gi.s[2]) &&
+             finite_f(gi.o);
+    gi.opac_ok = (double)gi.o >= S.alpha_min;
+    double n2 = (double)gi.q[0] * gi.q[0] + (double)gi.q[1] * gi.q[1] + (double)gi.q[2] * gi.q[2] +
+                (double)gi.q[3] * gi.q[3];
+    gi.quat_ok = n2 >= 1e-24;
+    if (gi.fin && gi.opac_ok && gi.quat_ok) gauss_pre(S, gi.q, gi.o, gi.G);
+}
+
+__device__ inline int classify(const splat_settings &S, const double *M, const CamC &C, int W, int H,
+                               const GaussIn &gi, Proj &P) {
+    if (!gi.fin) return PC_NONFINITE;
+    P.depth32 = depth_key(M, gi.x);
+    if (!(P.depth32 > (float)S.near_z)) return PC_NEAR;
+    if (P.depth32 > (float)S.far_z) return PC_FAR;
+    if (!gi.opac_ok) return PC_OPAC;
+    if (!gi.quat_ok) return PC_QUAT;
+    if (offscreen_bound(S, M, C, W, H, gi.x, gi.s, (float)gi.G.k2, P.depth32)) return PC_OFF;
+    project_view(S, M, C, gi.x, gi.s, gi.G, false, P);
+    return footprint(S, gi.G.k2, W, H, P);
+}
+
+__device__ inline void flag_status(uint32_t *status, uint32_t bits) {
     uint64_t any = __ballot(bits != 0);
     if (any) {
         // reduce the bits over the wave, then one atomic
@@ -131,86 +208,84 @@ __device__ inline void flag_status(uint32_t *status, int code) {
     }
 }
 
-// block-level exclusive rank of `vis` (256 threads = 4 waves); returns the block total via *tot
-__device__ inline uint32_t block_rank(bool vis, uint32_t *lds4, uint32_t *tot) {
-    uint64_t m = __ballot(vis);
-    int w = threadIdx.x >> 6;
-    if (__lane_id() == 0) lds4[w] = (uint32_t)__popcll(m);
-    __syncthreads();
-    uint32_t base = 0, total = 0;
-    for (int i = 0; i < 4; ++i) {
-        uint32_t c = lds4[i];
-        if (i < w) base += c;
-        total += c;
-    }
-    *tot = total;
-    return base + rank_in(m);
-}
-
+// Count pass: one thread per Gaussian walks every view (the parameters are read
+// once); per (view, wave) it stores the visibility mask and the visible count.
+// Slots are later numbered by an exclusive scan over (view, wave), so they are
+// compacted per view in Gaussian order.
 __global__ __launch_bounds__(256) void project_count_kernel(splat_settings S, splat_gaussians g, const double *w2c,
-                                                           const double *intr, int W, int H, int nb,
-                                                           uint32_t *blockcnt, uint64_t *visbits, uint32_t *status) {
-    __shared__ uint32_t lds4[4];
-    int v = blockIdx.y;
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int code = PC_OFF;
-    if (i < g.n) {
-        float x[3], q[4], s[3], o;
-        load_gauss(g, i, x, q, s, o);
-        Proj P;
-        code = project_gauss(S, w2c + 12 * v, intr + 4 * v, W, H, x, q, s, o, P);
+                                                           const CamC *cam, int W, int H, int V, int nb,
+                                                           uint32_t *wavecnt, uint64_t *visbits, uint32_t *status) {
+    const int b = blockIdx.x, w = threadIdx.x >> 6, lane = __lane_id();
+    const int64_t i = (int64_t)b * 256 + threadIdx.x;
+    const bool live = i < g.n;
+    GaussIn gi;
+    if (live) gauss_in(S, g, i, gi);
+    uint32_t bits = 0;
+    for (int v = 0; v < V; ++v) {
+        int code = PC_OFF;
+        if (live) {
+            Proj P;
+            code = classify(S, w2c + 12 * v, cam[v], W, H, gi, P);
+        }
+        bits |= (code == PC_NONFINITE ? SPLAT_ST_NONFINITE : 0u) | (code == PC_QUAT ? SPLAT_ST_DEGENERATE : 0u);
+        uint64_t m = __ballot(code == PC_OK);
+        if (lane == 0) {
+            size_t k = ((size_t)v * nb + b) * 4 + w;
+            visbits[k] = m;
+            wavecnt[k] = (uint32_t)__popcll(m);
+        }
     }
-    flag_status(status, code);
-    uint64_t m = __ballot(code == PC_OK);
-    if (__lane_id() == 0) visbits[((size_t)v * nb + blockIdx.x) * 4 + (threadIdx.x >> 6)] = m;
-    uint32_t tot;
-    block_rank(code == PC_OK, lds4, &tot);
-    if (threadIdx.x == 0) blockcnt[(size_t)v * nb + blockIdx.x] = tot;
+    flag_status(status, bits);
 }
 
+// Write pass: the same walk, projecting only the pairs the count pass marked
+// visible, into their slots.
 __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, splat_gaussians g, const double *w2c,
-                                                           const double *intr, int W, int H, int nb,
-                                                           const uint32_t *blockoff, int64_t slot_cap,
-                                                           float4 *rec, int2 *meta, Rect16 *rect,
+                                                           const CamC *cam, int W, int H, int V, int nb,
+                                                           const uint32_t *waveoff, const uint64_t *visbits,
+                                                           int64_t slot_cap, float4 *rec, int2 *meta, Rect16 *rect,
                                                            uint32_t *ntiles) {
-    __shared__ uint32_t lds4[4];
-    int v = blockIdx.y;
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int code = PC_OFF;
-    Proj P;
-    float x[3], q[4], s[3], o = 0.f;
-    if (i < g.n) {
-        load_gauss(g, i, x, q, s, o);
-        code = project_gauss(S, w2c + 12 * v, intr + 4 * v, W, H, x, q, s, o, P);
+    const int b = blockIdx.x, w = threadIdx.x >> 6, lane = __lane_id();
+    const int64_t i = (int64_t)b * 256 + threadIdx.x;
+    if (i >= g.n) return;
+    GaussIn gi;
+    gauss_in(S, g, i, gi);
+    const int64_t n = g.n;
+    const float cr = g.color[i], cg = g.color[n + i], cb = g.color[2 * n + i];
+    const int tw = S.tile_w, th = S.tile_h;
+    for (int v = 0; v < V; ++v) {
+        size_t k = ((size_t)v * nb + b) * 4 + w;
+        uint64_t m = visbits[k];
+        if (!((m >> lane) & 1ull)) continue;
+        uint64_t slot = (uint64_t)waveoff[k] + rank_in(m);
+        if (slot >= (uint64_t)slot_cap) continue;  // capacity flagged by the scan finisher
+        const double *M = w2c + 12 * v;
+        Proj P;
+        P.depth32 = depth_key(M, gi.x);
+        project_view(S, M, cam[v], gi.x, gi.s, gi.G, true, P);
+        footprint(S, gi.G.k2, W, H, P);  // visible: the count pass found this rectangle non-empty
+        float mxh = (float)P.mu[0], myh = (float)P.mu[1];
+        float mxl = (float)(P.mu[0] - (double)mxh), myl = (float)(P.mu[1] - (double)myh);
+        rec[3 * slot + 0] = make_float4(mxh, myh, mxl, myl);
+        rec[3 * slot + 1] = make_float4((float)P.Q[0], (float)P.Q[1], (float)P.Q[2], gi.o);
+        rec[3 * slot + 2] = make_float4(cr, cg, cb, P.depth32);
+        meta[slot] = make_int2((int)i, v);
+        Rect16 rc;
+        rc.x0 = (uint16_t)(P.px0 / tw); rc.x1 = (uint16_t)(P.px1 / tw);
+        rc.y0 = (uint16_t)(P.py0 / th); rc.y1 = (uint16_t)(P.py1 / th);
+        rect[slot] = rc;
+        ntiles[slot] = (uint32_t)(rc.x1 - rc.x0 + 1) * (uint32_t)(rc.y1 - rc.y0 + 1);
     }
-    uint32_t tot;
-    uint32_t r = block_rank(code == PC_OK, lds4, &tot);
-    if (code != PC_OK) return;
-    uint64_t slot = (uint64_t)blockoff[(size_t)v * nb + blockIdx.x] + r;
-    if (slot >= (uint64_t)slot_cap) return;  // capacity flagged by the scan finisher
-    float mxh = (float)P.mu[0], myh = (float)P.mu[1];
-    float mxl = (float)(P.mu[0] - (double)mxh), myl = (float)(P.mu[1] - (double)myh);
-    int64_t n = g.n;
-    rec[3 * slot + 0] = make_float4(mxh, myh, mxl, myl);
-    rec[3 * slot + 1] = make_float4((float)P.Q[0], (float)P.Q[1], (float)P.Q[2], o);
-    rec[3 * slot + 2] = make_float4(g.color[i], g.color[n + i], g.color[2 * n + i], P.depth32);
-    meta[slot] = make_int2((int)i, v);
-    int tw = S.tile_w, th = S.tile_h;
-    Rect16 rc;
-    rc.x0 = (uint16_t)(P.px0 / tw); rc.x1 = (uint16_t)(P.px1 / tw);
-    rc.y0 = (uint16_t)(P.py0 / th); rc.y1 = (uint16_t)(P.py1 / th);
-    rect[slot] = rc;
-    ntiles[slot] = (uint32_t)(rc.x1 - rc.x0 + 1) * (uint32_t)(rc.y1 - rc.y0 + 1);
 }
 
-// totals after the block-count scan: slot count (clamped), view offsets, capacity flag
-__global__ void project_finish_kernel(const uint32_t *blockoff, int V, int nb, int64_t slot_cap,
-                                      uint32_t *counts, uint32_t *view_off, uint32_t *status) {
-    int v = threadIdx.x;
-    uint32_t total = blockoff[(size_t)V * nb];
+// totals after the (view, wave) count scan: slot count (clamped), view offsets, capacity flag
+__global__ void project_finish_kernel(const uint32_t *waveoff, int V, int nw, int64_t slot_cap, uint32_t *counts,
+                                      uint32_t *view_off, uint32_t *status) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t total = waveoff[(size_t)V * nw];
     uint32_t cap = (uint32_t)slot_cap;
     if (v <= V) {
-        uint32_t off = (v < V) ? blockoff[(size_t)v * nb] : total;
+        uint32_t off = (v < V) ? waveoff[(size_t)v * nw] : total;
         view_off[v] = off < cap ? off : cap;
     }
     if (v == 0) {
@@ -225,7 +300,7 @@ __global__ void project_finish_kernel(const uint32_t *blockoff, int V, int nb, i
 // Chain rule of one visible (view, Gaussian) pair from its slot gradient gd[9]
 // = d(mu x, mu y; conic a, b, c; opacity; r, g, b).  Adds the quaternion, scale
 // and mean gradients to gq, gs, gm and returns the W2C gradient in gw[12].
-__device__ void slot_adjoint(const Proj &P, const double *M, const double *K4, const float *x, const float *s,
+__device__ void slot_adjoint(const Proj &P, const double *M, const CamC &C, const float *x, const float *s,
                              const float *gd, double *gq, double *gs, double *gm, double *gw) {
     double gmx = gd[0], gmy = gd[1], ga = gd[2], gb = gd[3], gc = gd[4];
     // conic -> Sigma2: G2 = -Q GQ Q with GQ = [[ga, gb/2], [gb/2, gc]]
@@ -250,7 +325,7 @@ __device__ void slot_adjoint(const Proj &P, const double *M, const double *K4, c
     for (int r = 0; r < 3; ++r)
         for (int k = 0; k < 3; ++k) gA[3 * r + k] = P.J[r] * gT[k] + P.J[3 + r] * gT[3 + k];
     // J(t), mu(t)
-    double fx = K4[0], fy = K4[1];
+    double fx = C.fx, fy = C.fy;
     double tx = P.t[0], ty = P.t[1], tz = P.t[2];
     double iz = 1.0 / tz, iz2 = iz * iz;
     double gt0 = gmx * fx * iz, gt1 = gmy * fy * iz;
@@ -352,11 +427,10 @@ struct LaneClass {
 // stored as the workgroup's partial; dw2c_reduce_kernel sums the partials of a
 // view in a fixed order (deterministic, no contended float64 atomics).
 __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, splat_gaussians g, const double *w2c,
-                                                         const double *intr, int W, int H, int V, int nb,
-                                                         const uint32_t *blockoff, const uint64_t *visbits,
-                                                         int64_t slot_cap, const float *grad2d, float *dquat,
-                                                         float *dscale, float *dopac, float *dcolor, float *dmean,
-                                                         double *dwpart) {
+                                                         const CamC *cam, int V, int nb, const uint32_t *waveoff,
+                                                         const uint64_t *visbits, int64_t slot_cap,
+                                                         const float *grad2d, float *dquat, float *dscale,
+                                                         float *dopac, float *dcolor, float *dmean, double *dwpart) {
     __shared__ double red[4][12];
     const int b = blockIdx.x, wv = threadIdx.x >> 6, lane = __lane_id();
     const LaneClass lc(lane);
@@ -364,13 +438,13 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
     const int64_t i = (int64_t)b * 256 + threadIdx.x;
     const int64_t n = g.n;
     const bool live = i < n;
-    float x[3] = {0.f, 0.f, 0.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, s[3] = {1.f, 1.f, 1.f}, o = 1.f;
-    if (live) load_gauss(g, i, x, q, s, o);
+    GaussIn gi;
+    if (live) gauss_in(S, g, i, gi);
     double gq[4] = {0, 0, 0, 0}, gs[3] = {0, 0, 0}, gm[3] = {0, 0, 0}, go = 0.0, gc[3] = {0, 0, 0};
     for (int v = 0; v < V; ++v) {
-        const uint64_t *vb = visbits + ((size_t)v * nb + b) * 4;
+        const size_t k0 = ((size_t)v * nb + b) * 4;
         double *part = dwpart + ((size_t)v * nb + b) * 12;
-        uint64_t mask = vb[wv];
+        uint64_t mask = visbits[k0 + wv];
         bool vis = live && ((mask >> lane) & 1ull);
         if (!__syncthreads_or(vis)) {  // nothing of this workgroup visible in view v
             if (threadIdx.x < 12) part[threadIdx.x] = 0.0;
@@ -379,20 +453,18 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
         double gw[12];
         for (int k = 0; k < 12; ++k) gw[k] = 0.0;
         if (vis) {
-            uint32_t before = 0;
-            for (int w2 = 0; w2 < wv; ++w2) before += (uint32_t)__popcll(vb[w2]);
-            uint64_t slot = (uint64_t)blockoff[(size_t)v * nb + b] + before + rank_in(mask);
+            uint64_t slot = (uint64_t)waveoff[k0 + wv] + rank_in(mask);
             if (slot < (uint64_t)slot_cap) {
                 const double *M = w2c + 12 * v;
-                const double *K4 = intr + 4 * v;
+                const CamC C = cam[v];
                 Proj P;
-                project_core(S, M, K4, W, H, x, q, s, P);
+                project_view(S, M, C, gi.x, gi.s, gi.G, true, P);
                 const float *gd = grad2d + 9 * slot;
                 go += gd[5];
                 gc[0] += gd[6];
                 gc[1] += gd[7];
                 gc[2] += gd[8];
-                slot_adjoint(P, M, K4, x, s, gd, gq, gs, gm, gw);
+                slot_adjoint(P, M, C, gi.x, gi.s, gd, gq, gs, gm, gw);
             }
         }
         double tot = 0.0;
@@ -438,28 +510,33 @@ __global__ __launch_bounds__(256) void dw2c_reduce_kernel(const double *dwpart, 
 
 int launch_project(const splat_plan &p, void *ws, const splat_gaussians &g, const double *w2c,
                    const double *intr, hipStream_t st) {
-    int V = p.n_views, nb = p.n_blocks_proj;
+    int V = p.n_views, nb = p.n_blocks_proj, nw = 4 * nb;
     uint32_t *status = ws_at<uint32_t>(ws, p.off_status);
     uint32_t *counts = ws_at<uint32_t>(ws, p.off_counts);
-    uint32_t *blockcnt = ws_at<uint32_t>(ws, p.off_blockcnt);
+    uint32_t *wavecnt = ws_at<uint32_t>(ws, p.off_blockcnt);
+    CamC *cam = ws_at<CamC>(ws, p.off_cam);
+    uint64_t *visbits = ws_at<uint64_t>(ws, p.off_visbits);
+    hipLaunchKernelGGL(camconst_kernel, dim3((V + 63) / 64), dim3(64), 0, st, p.s, intr, V, p.width, p.height, cam);
+    int rc = launch_status("camconst");
+    if (rc) return rc;
     if (g.n == 0) {
-        int rc = launch_fill_u32(blockcnt, 0u, (int64_t)V * nb + 1, st);
+        rc = launch_fill_u32(wavecnt, 0u, (int64_t)V * nw + 1, st);
         if (rc) return rc;
     } else {
-        hipLaunchKernelGGL(project_count_kernel, dim3(nb, V), dim3(256), 0, st, p.s, g, w2c, intr, p.width,
-                           p.height, nb, blockcnt, ws_at<uint64_t>(ws, p.off_visbits), status);
-        int rc = launch_status("project_count");
+        hipLaunchKernelGGL(project_count_kernel, dim3(nb), dim3(256), 0, st, p.s, g, w2c, cam, p.width, p.height, V,
+                           nb, wavecnt, visbits, status);
+        rc = launch_status("project_count");
         if (rc) return rc;
-        rc = launch_scan_u32(blockcnt, blockcnt, nullptr, (int64_t)V * nb, ws_at<uint32_t>(ws, p.off_scan),
-                             nullptr, st);
+        rc = launch_scan_u32(wavecnt, wavecnt, nullptr, (int64_t)V * nw, ws_at<uint32_t>(ws, p.off_scan), nullptr,
+                             st);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(project_finish_kernel, dim3(1), dim3(((V + 1 + 63) / 64) * 64), 0, st, blockcnt, V, nb,
+    hipLaunchKernelGGL(project_finish_kernel, dim3((V + 1 + 255) / 256), dim3(256), 0, st, wavecnt, V, nw,
                        p.slot_cap, counts, ws_at<uint32_t>(ws, p.off_view_off), status);
-    int rc = launch_status("project_finish");
+    rc = launch_status("project_finish");
     if (rc || g.n == 0) return rc;
-    hipLaunchKernelGGL(project_write_kernel, dim3(nb, V), dim3(256), 0, st, p.s, g, w2c, intr, p.width, p.height,
-                       nb, blockcnt, p.slot_cap, ws_at<float4>(ws, p.off_rec), ws_at<int2>(ws, p.off_meta),
+    hipLaunchKernelGGL(project_write_kernel, dim3(nb), dim3(256), 0, st, p.s, g, w2c, cam, p.width, p.height, V, nb,
+                       wavecnt, visbits, p.slot_cap, ws_at<float4>(ws, p.off_rec), ws_at<int2>(ws, p.off_meta),
                        ws_at<Rect16>(ws, p.off_rect), ws_at<uint32_t>(ws, p.off_ntiles));
     return launch_status("project_write");
 }
@@ -470,7 +547,11 @@ int launch_project_bwd(const splat_plan &p, void *ws, const splat_gaussians &g, 
     if (g.n == 0) return 0;
     int nb = p.n_blocks_proj;
     double *part = ws_at<double>(ws, p.off_dwpart);
-    hipLaunchKernelGGL(project_bwd_kernel, dim3(nb), dim3(256), 0, st, p.s, g, w2c, intr, p.width, p.height,
+    hipLaunchKernelGGL(camconst_kernel, dim3((p.n_views + 63) / 64), dim3(64), 0, st, p.s, intr, p.n_views, p.width,
+                       p.height, ws_at<CamC>(ws, p.off_cam));
+    int rc0 = launch_status("camconst");
+    if (rc0) return rc0;
+    hipLaunchKernelGGL(project_bwd_kernel, dim3(nb), dim3(256), 0, st, p.s, g, w2c, ws_at<CamC>(ws, p.off_cam),
                        p.n_views, nb, ws_at<uint32_t>(ws, p.off_blockcnt), ws_at<uint64_t>(ws, p.off_visbits),
                        p.slot_cap, ws_at<float>(ws, p.off_grad2d), dquat, dscale, dopac, dcolor, dmean, part);
     int rc = launch_status("project_bwd");
