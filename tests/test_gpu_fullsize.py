@@ -1,0 +1,150 @@
+"""GPU parity at the full workload sizes, in the launch configuration the benchmark
+times (16x16 tiles, one workgroup per work item, all views in one batch):
+
+* the single 1408x376 view of the 500k-Gaussian LiDAR scene: every pixel, and all
+  gradients;
+* the 64-view, 2M-Gaussian drive: the densest, median and sparsest views compared
+  pixel by pixel, and the gradients of a loss on exactly those three views;
+* the two-camera, 16-view calibration scene: Gaussian, W2C, extrinsic and time
+  offset gradients of a loss on four of its views.
+
+The oracle is handed only its own inputs (its own pose, its own image for dL/dimg);
+the GPU receives the same dL/dimg.  Pixels with a threshold decision near the
+margin (or an alpha_max kink) are left out of the gradient loss on both sides.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_2403_11577_amd import pipeline as pl
+
+from gpu_util import compare_images, rel_close, say
+
+pytestmark = pytest.mark.gpu
+
+TILE, PERSISTENT = (16, 16), False
+
+
+def _forward(scene):
+    ds = pl.DeviceScene.from_scene(scene)
+    xi = torch.as_tensor(scene.xi, dtype=torch.float64, device="cuda")
+    dl = torch.as_tensor(scene.delta, dtype=torch.float64, device="cuda")
+    fr = pl.fit_frame(ds, xi, dl, pl.make_settings(tile=TILE, persistent=PERSISTENT))
+    fr.clear_status()
+    pl.forward(fr, ds, xi, dl)
+    torch.cuda.synchronize()
+    return ds, fr, xi, dl
+
+
+def _views_np(fr, sel):
+    """GPU image, T and last Gaussian id of the views in sel, as numpy."""
+    ns, ni = fr.counts()
+    vals = fr.sorted_vals(ni).cpu().numpy().astype(np.int64)
+    gid_of_slot = fr.meta(ns).cpu().numpy()[:, 0].astype(np.int64)
+    img = fr.img[sel].cpu().numpy().astype(np.float64)
+    T = fr.T[sel].cpu().numpy().astype(np.float64)
+    lp = fr.last[sel].cpu().numpy().astype(np.int64)
+    lid = np.full(lp.shape, -1, np.int64)
+    m = lp >= 0
+    lid[m] = gid_of_slot[vals[lp[m]]]
+    return dict(img=img, T=T, last_id=lid)
+
+
+def _sub_views(scene, sel):
+    return synth.Views(np.asarray(scene.views.cam)[sel], np.asarray(scene.views.t)[sel])
+
+
+def _check_images(scene, fr, sel, w2c_ref, intr):
+    g = _views_np(fr, sel)
+    orc = oracle.render(scene.gauss, w2c_ref[sel], intr[sel], scene.rig.W, scene.rig.H, alternatives=True)
+    nbad, nfl, nex, mx = compare_images(g, orc)
+    say(f"  views {list(sel)}: flagged={nfl} excluded={nex} max_err={mx:.3g}")
+    assert nbad == 0
+    assert nex <= 0.001 * orc["nflag"].size
+
+
+def _check_grads(scene, ds, fr, xi, dl, sel, w2c_ref, intr, target_level=0.5, calib=True):
+    """Loss on the views in sel only: sum over them of the masked L1 against a flat target."""
+    V, H, W = scene.views.n, scene.rig.H, scene.rig.W
+    mset = oracle.Settings(margin=1e-2)
+    orc = oracle.render(scene.gauss, w2c_ref[sel], intr[sel], W, H, mset)
+    mask = (orc["nflag"] > 0) | (orc["kink"] > 0)
+    target = np.full_like(orc["img"], target_level)
+    _, dimg_sel = oracle.l1_loss(orc["img"], target, mask)
+    dimg_sel = dimg_sel.astype(np.float32)
+    dimg = torch.zeros((V, 3, H, W), dtype=torch.float32, device="cuda")
+    dimg[torch.as_tensor(sel, device="cuda")] = torch.as_tensor(dimg_sel, device="cuda")
+    gr = pl.alloc_grads(ds, with_mean=True)
+    pl.backward(fr, ds, xi, dl, dimg, gr)
+    torch.cuda.synchronize()
+    ref = oracle.grad(scene.gauss, w2c_ref[sel], intr[sel], W, H, dimg_sel.astype(np.float64),
+                      mask=mask.astype(np.int8))
+    errs = {}
+    names = ["scale", "opacity", "color", "mean"]
+    sc = np.asarray(scene.gauss.scale, np.float64)
+    if np.all(sc == sc[:1]):
+        # isotropic Gaussians: a rotation leaves them unchanged, so dL/dq is zero up to rounding on
+        # both sides; compare it with the size of a scale gradient times the scale
+        gq = gr.quat.cpu().numpy().astype(np.float64)
+        ref_gs = np.abs(ref["scale"] * sc).max()
+        lvl = max(np.abs(gq).max(), np.abs(ref["quat"]).max()) / ref_gs
+        errs["quat_isotropic_noise"] = (bool(lvl <= 1e-4), float(lvl))
+    else:
+        names.insert(0, "quat")
+    for name in names:
+        ok, err = rel_close(getattr(gr, name).cpu().numpy(), ref[name], 1e-3)
+        errs[name] = (ok, err)
+    gw = gr.w2c.cpu().numpy()
+    ok, err = rel_close(gw[sel], ref["w2c"], 1e-3)
+    errs["w2c"] = (ok, err)
+    others = np.setdiff1d(np.arange(V), sel)
+    errs["w2c_unlossed_views_zero"] = (bool(np.all(gw[others] == 0.0)), float(np.abs(gw[others]).max(initial=0.0)))
+    if calib:
+        rxi, rdl = oracle.pose_bwd(scene.traj, scene.rig, scene.xi, scene.delta, _sub_views(scene, sel), ref["w2c"])
+        for name, a, b in (("xi", gr.xi.cpu().numpy(), rxi), ("delta", gr.delta.cpu().numpy(), rdl)):
+            e = float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-12)))
+            errs[name] = (e <= 1e-3, e)
+    say(f"  masked frac {mask.mean():.4f} " + " ".join(f"{k}={v[1]:.2e}" for k, v in errs.items()))
+    for k, (ok, err) in errs.items():
+        assert ok, (k, err)
+
+
+def test_single_view_500k_full_image_and_gradients():
+    say("case: 500k Gaussians, one 1408x376 view")
+    scene = synth.kitti_single(0)
+    ds, fr, xi, dl = _forward(scene)
+    assert fr.status() == 0
+    w2c_ref, _, _ = oracle.pose(scene.traj, scene.rig, scene.xi, scene.delta, scene.views)
+    intr = oracle.view_intr(scene.rig, scene.views)
+    sel = np.array([0])
+    _check_images(scene, fr, sel, w2c_ref, intr)
+    _check_grads(scene, ds, fr, xi, dl, sel, w2c_ref, intr)
+
+
+def test_batched_drive_sampled_views():
+    say("case: 2M Gaussians, 64 views of 1408x376, densest / median / sparsest view")
+    scene = synth.batched64(0)
+    ds, fr, xi, dl = _forward(scene)
+    assert fr.status() == 0
+    view_off = fr.buf("view_off", torch.int32, scene.views.n + 1).cpu().numpy().astype(np.int64)
+    vis = np.diff(view_off)
+    order = np.argsort(vis, kind="stable")
+    sel = np.array(sorted({int(order[-1]), int(order[len(order) // 2]), int(order[0])}))
+    say(f"  visible per view: {[int(vis[v]) for v in sel]}")
+    w2c_ref, _, _ = oracle.pose(scene.traj, scene.rig, scene.xi, scene.delta, scene.views)
+    intr = oracle.view_intr(scene.rig, scene.views)
+    _check_images(scene, fr, sel, w2c_ref, intr)
+    _check_grads(scene, ds, fr, xi, dl, sel, w2c_ref, intr)
+
+
+def test_calibration_scene_gradients_on_four_views():
+    say("case: two cameras x 8 frames, 500k Gaussians, perturbed extrinsic and time offset")
+    scene = synth.calib16(0)
+    ds, fr, xi, dl = _forward(scene)
+    w2c_ref, _, _ = oracle.pose(scene.traj, scene.rig, scene.xi, scene.delta, scene.views)
+    intr = oracle.view_intr(scene.rig, scene.views)
+    # both cameras, first and last frame each (views are camera-major)
+    sel = np.array([0, 7, 8, 15])
+    _check_grads(scene, ds, fr, xi, dl, sel, w2c_ref, intr)

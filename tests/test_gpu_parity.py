@@ -148,9 +148,9 @@ def test_render_fwd_vs_oracle(name, tile):
     say(f"case: render_fwd scene={name} tile={tile}")
     scene = SCENES[name]()
     g = gpu_render(scene, tile=tile)
-    orc = oracle.render(scene.gauss, g["w2c"], oracle.view_intr(scene.rig, scene.views), scene.rig.W,
-                        scene.rig.H, alternatives=True)
     ref_w2c, _, _ = oracle.pose(scene.traj, scene.rig, scene.xi, scene.delta, scene.views)
+    orc = oracle.render(scene.gauss, ref_w2c, oracle.view_intr(scene.rig, scene.views), scene.rig.W,
+                        scene.rig.H, alternatives=True)
     np.testing.assert_allclose(g["w2c"], ref_w2c, atol=1e-12 * np.abs(ref_w2c).max())
     nbad, nfl, nex, mx = compare_images(g, orc)
     say(f"  flagged={nfl} excluded={nex} max_err={mx:.3g} slots={g['slots']} inst={g['inst']}")
@@ -179,14 +179,15 @@ def _grad_case(scene, tile, seed=0):
     fr, ds = g["frame"], g["ds"]
     # pixels with a threshold decision or an alpha_max kink near the margin are left out on both sides
     mset = oracle.Settings(margin=1e-2)
-    orc_m = oracle.render(scene.gauss, g["w2c"], oracle.view_intr(scene.rig, scene.views), scene.rig.W,
+    orc_m = oracle.render(scene.gauss, w2c_ref, oracle.view_intr(scene.rig, scene.views), scene.rig.W,
                           scene.rig.H, mset)
     mask = (orc_m["nflag"] > 0) | (orc_m["kink"] > 0)
-    L, dimg = oracle.l1_loss(g["img"], target, mask)   # the same dL/dimg for both sides
+    # dL/dimg from the oracle's own image, handed to both sides
+    L, dimg = oracle.l1_loss(orc_m["img"], target, mask)
     gr = pl.alloc_grads(ds, with_mean=True)
     pl.backward(fr, ds, g["xi"], g["delta"], torch.as_tensor(dimg, dtype=torch.float32, device="cuda"), gr)
     torch.cuda.synchronize()
-    ref = oracle.grad(scene.gauss, g["w2c"], oracle.view_intr(scene.rig, scene.views), scene.rig.W, scene.rig.H,
+    ref = oracle.grad(scene.gauss, w2c_ref, oracle.view_intr(scene.rig, scene.views), scene.rig.W, scene.rig.H,
                       dimg.astype(np.float32).astype(np.float64), mask=mask.astype(np.int8))
     rxi, rdl = oracle.pose_bwd(scene.traj, scene.rig, scene.xi, scene.delta, scene.views, ref["w2c"])
     out = {}
@@ -232,7 +233,8 @@ def test_empty_and_degenerate_inputs():
     s.gauss.quat[:, 5] = 0.0
     g = gpu_render(s)
     assert g["status"] & B.ST_NONFINITE and g["status"] & B.ST_DEGENERATE
-    orc = oracle.render(s.gauss, g["w2c"], oracle.view_intr(s.rig, s.views), s.rig.W, s.rig.H, alternatives=True)
+    w2c_ref, _, _ = oracle.pose(s.traj, s.rig, s.xi, s.delta, s.views)
+    orc = oracle.render(s.gauss, w2c_ref, oracle.view_intr(s.rig, s.views), s.rig.W, s.rig.H, alternatives=True)
     assert compare_images(g, orc)[0] == 0
 
 
