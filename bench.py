@@ -25,11 +25,34 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# ALU roofline (see the design notes): FP32 flops per unit, FMA = 2.
+# ALU roofline of the render kernels: FP32 flops (FMA = 2, exp2 / rcp / compare = 1) per
+# counted unit, from device-side pair counters.
+#   forward, per evaluated (pixel, Gaussian) pair: offset 2, exponent 8, exp2 1, clamp 1, alpha test 1
+#   forward, per blended pair: weight 1, transmittance 1, stop test 1, colour 6, last index 1
+#   backward, per evaluated pair (at or before the pixel's last contributor): as the forward, 13
+#   backward, per contributing pair: 1 - alpha and its reciprocal 2, T recovery 1, weight 1,
+#     colour gradient 6, dL/dC . c 5, dL/dalpha 3, suffix term 2, dL/dpower 2, moments 12 = 35
 FWD_FLOP_PER_EVAL, FWD_FLOP_PER_BLEND = 13, 10
-BWD_FLOP_PER_EVAL, BWD_FLOP_PER_CONTRIB = 13, 50
+BWD_FLOP_PER_EVAL, BWD_FLOP_PER_CONTRIB = 13, 35
 # 256 CUs x 64 FP32 lanes x 2 flops (FMA) x 2.4 GHz, without packed-FP32 issue
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# HBM bytes per render_bwd launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "batched64_hbm_traffic.md")
+RENDER_SRC = os.path.join(ROOT, "paper_2403_11577_amd", "csrc", "render.hip")
+
+
+def profiled_traffic(kernel):
+    """Bytes per launch from the committed counter summary, or None once the kernel source changed."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_PROFILE).read().splitlines()
+        kv = dict(l.split(": ", 1) for l in lines if ": " in l and not l.startswith(("|", "#", "`")))
+        sha = hashlib.sha256(open(RENDER_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if kv.get("source_sha256") != sha or not kv.get("kernel", "").startswith(kernel):
+        return None
+    return int(float(kv["traffic_bytes_per_launch"]))
 
 
 def log(*a):
@@ -152,7 +175,8 @@ def main():
         kern, dur_ms, flop = "render_fwd", fwd_ms, fwd_flop
     achieved = flop / (dur_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": kern, "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
-                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                "traffic": profiled_traffic(kern) if args.tile == "16x16" else None,
                 "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
                 "fwd_tflops": round(fwd_flop / (fwd_ms * 1e-3) / 1e12, 3),
                 "bwd_tflops": round(bwd_flop / (bwd_ms * 1e-3) / 1e12, 3), "pairs": stt}
