@@ -25,7 +25,7 @@ import subprocess
 import numpy as np
 
 __all__ = ["Settings", "build", "lib", "pose", "pose_bwd", "project_one", "render", "grad",
-           "project_all", "pixel_stack", "tile_lists", "l1_loss", "render_scene",
+           "project_all", "pixel_stack", "tile_lists", "l1_loss", "scale_reg", "render_scene",
            "loss_and_grad", "fd_loss", "view_intr", "gauss64", "num_threads", "PROJ_FIELDS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -47,18 +47,19 @@ class Settings:
     margin: float = 1e-4
     pad_px: float = 0.1
     pad_rel: float = 1e-4
+    roi_y0: int = 0          # first image row of the region of interest (Sec. III-C, image cropping)
 
 
 class _CSettings(C.Structure):
     _fields_ = [("near_z", C.c_double), ("far_z", C.c_double), ("eps2d", C.c_double),
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double), ("t_min", C.c_double),
                 ("guard", C.c_double), ("bg", C.c_double * 3), ("margin", C.c_double),
-                ("pad_px", C.c_double), ("pad_rel", C.c_double)]
+                ("pad_px", C.c_double), ("pad_rel", C.c_double), ("roi_y0", C.c_int32), ("roi_pad_", C.c_int32)]
 
 
 def _cs(s: Settings) -> _CSettings:
     return _CSettings(s.near_z, s.far_z, s.eps2d, s.alpha_min, s.alpha_max, s.t_min, s.guard,
-                      (C.c_double * 3)(*s.bg), s.margin, s.pad_px, s.pad_rel)
+                      (C.c_double * 3)(*s.bg), s.margin, s.pad_px, s.pad_rel, int(s.roi_y0), 0)
 
 
 def build(force: bool = False) -> str:
@@ -300,13 +301,29 @@ def tile_lists(proj, W, H, tile_w, tile_h, view=0):
 # ----------------------------------------------------------------------------
 # loss, pipeline helpers and finite differences
 # ----------------------------------------------------------------------------
-def l1_loss(img, target, mask=None):
-    """Mean absolute error (the L1 term of Eq. 4) and dL/dimg with sign(0) = 0."""
-    d = img - target
-    N = d.size
+def l1_loss(img, target, mask=None, roi_y0=0):
+    """Mean absolute error (the L1 term of Eq. 4) and dL/dimg with sign(0) = 0.
+
+    With roi_y0 > 0 the loss is the mean over the rows [roi_y0, H) only (Sec. III-C:
+    the losses use the bottom part of the image); dL/dimg is 0 above.  A mask
+    [V,H,W] leaves pixels out of the sum without changing the mean's count."""
+    d = np.array(img - target, dtype=np.float64)
+    d[:, :, :roi_y0, :] = 0.0
+    N = d[:, :, roi_y0:, :].size
     if mask is not None:
         d = d * (1 - mask[:, None].astype(np.float64))
     return np.abs(d).sum() / N, np.sign(d) / N
+
+
+def scale_reg(scale, lam=1e-3):
+    """L_scale of Sec. III-C times lambda_2: lam * sum_g ||s_g - mean(s_g)||_1 over the three
+    axes of every Gaussian, and its gradient with respect to the (activated) scales [3,G]."""
+    s = np.asarray(scale, np.float64)
+    m = s.mean(axis=0, keepdims=True)
+    sg = np.sign(s - m)
+    loss = lam * np.abs(s - m).sum()
+    grad = lam * (sg - sg.mean(axis=0, keepdims=True))
+    return loss, grad
 
 
 def render_scene(scene, gauss=None, xi=None, delta=None, settings=None, pruned=True, alternatives=False):

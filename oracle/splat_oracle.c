@@ -49,6 +49,8 @@ typedef struct {
     double margin;   /* relative margin of a threshold decision that is flagged */
     double pad_px;   /* footprint padding, pixels */
     double pad_rel;  /* footprint padding, relative to the radius */
+    int32_t roi_y0;  /* first image row of the region of interest (Sec. III-C, image cropping) */
+    int32_t roi_pad_;
 } or_settings;
 
 /* ------------------------------------------------------------------------ */
@@ -388,7 +390,7 @@ static void project_one(const or_settings *S, const double *x, const double *q, 
     P->rect_margin = near_int(bx0) || near_int(bx1) || near_int(by0) || near_int(by1);
     double fx0 = ceil(bx0), fx1 = floor(bx1), fy0 = ceil(by0), fy1 = floor(by1);
     if (fx0 < 0) fx0 = 0;
-    if (fy0 < 0) fy0 = 0;
+    if (fy0 < S->roi_y0) fy0 = S->roi_y0;  /* tiles are listed only inside the region of interest */
     if (fx1 > Wimg - 1) fx1 = Wimg - 1;
     if (fy1 > Himg - 1) fy1 = Himg - 1;
     if (!(fx0 <= fx1) || !(fy0 <= fy1)) { P->cull = CULL_OFFSCREEN; return; }
@@ -641,7 +643,14 @@ int or_render(const or_settings *S, int64_t G, const double *mean, const double 
         for (int y = 0; y < H; ++y) {
             for (int x = 0; x < W; ++x) {
                 pix_out po;
-                composite(S, &g, &vp, pruned ? &rl : NULL, x, y, NULL, 0, &po, NULL, NULL);
+                if (y >= S->roi_y0) {
+                    composite(S, &g, &vp, pruned ? &rl : NULL, x, y, NULL, 0, &po, NULL, NULL);
+                } else {  /* outside the region of interest: not rendered, background */
+                    memset(&po, 0, sizeof po);
+                    for (int c = 0; c < 3; ++c) po.C[c] = S->bg[c];
+                    po.T = 1.0;
+                    po.last = -1;
+                }
                 size_t p = (size_t)y * W + x;
                 size_t vo = (size_t)v * H * W;
                 for (int c = 0; c < 3; ++c) img[(size_t)v * 3 * H * W + (size_t)c * H * W + p] = po.C[c];
@@ -759,6 +768,7 @@ int or_grad(const or_settings *S, int64_t G, const double *mean, const double *q
             stack_e *stk = (stack_e *)malloc(sizeof(stack_e) * (size_t)(vp.n > 0 ? vp.n : 1));
 #pragma omp for schedule(dynamic, 1)
             for (int y = 0; y < H; ++y) {
+                if (y < S->roi_y0) continue;  /* not rendered */
                 for (int x = 0; x < W; ++x) {
                     size_t p = (size_t)y * W + x;
                     if (mask && mask[(size_t)v * H * W + p]) continue;
