@@ -79,6 +79,8 @@ typedef struct splat_settings {
     double bg[3];
     double pad_px, pad_rel;
     int32_t tile_w, tile_h, batch, persistent;
+    int32_t roi_y0;     /* first image row of the region of interest; rows above are not rendered */
+    int32_t reserved0;
 } splat_settings;
 
 /* Gaussian parameters: device SoA planes of length n (float32).
@@ -238,14 +240,17 @@ SPLAT_API int splat_project_bwd(const splat_plan *plan, void *ws, const splat_ga
                       float *dopacity, float *dcolor, float *dmean, double *dw2c, void *stream);
 
 /*
- * The L1 term of the photometric loss (paper Eq. 4): with N = V*3*H*W,
- * dL_dimg = sign(img - target)/N (sign(0) = 0) and *loss += sum |img - target|/N
+ * The L1 term of the photometric loss (paper Eq. 4) over the region of interest
+ * (rows [roi_y0, H); Sec. III-C computes the losses on the bottom part of the
+ * image): with N = V*3*(H - roi_y0)*W, dL_dimg = sign(img - target)/N inside the
+ * region (sign(0) = 0) and 0 above it, and *loss += sum |img - target|/N
  * (float64, caller zeroes it; NULL to skip).  img, target, dL_dimg are
  * [V][3][H][W] float32 device arrays; mask (nullable) is uint8 [V][H][W] and
- * removes the pixels where it is non-zero (e.g. outside a region of interest).
+ * removes the pixels where it is non-zero from the sum (N is unchanged).
+ * 0 <= roi_y0 < H.
  */
 SPLAT_API int splat_l1_loss_grad(const float *img, const float *target, const uint8_t *mask, int32_t n_views,
-                                 int32_t width, int32_t height, float *dL_dimg, double *loss, void *stream);
+                                 int32_t width, int32_t height, int32_t roi_y0, float *dL_dimg, double *loss, void *stream);
 
 /*
  * Instrumented variants of splat_render_fwd / splat_render_bwd: identical
@@ -260,6 +265,16 @@ SPLAT_API int splat_render_fwd_stats(const splat_plan *plan, void *ws, float *im
 SPLAT_API int splat_render_bwd_stats(const splat_plan *plan, void *ws, const float *dL_dimg,
                                      const float *T_final, const int32_t *last_pos, uint64_t *stats,
                                      void *stream);
+
+/*
+ * The scale regulariser of Sec. III-C: lambda * sum_g ||s_g - mean(s_g)||_1 over
+ * the three axes of every Gaussian (it keeps the axes of a Gaussian from drifting
+ * far apart).  scale[3][n] float32 device plane (activated scales); ADDS
+ * lambda * (sign(s - m) - mean of the three signs) to dscale[3][n] and the loss
+ * to *loss (float64, nullable).  The mean and the signs are taken in float64.
+ */
+SPLAT_API int splat_scale_reg(const float *scale, int64_t n, double lambda, float *dscale, double *loss,
+                              void *stream);
 
 /* Text of the last synchronous error on this thread ("" if none). */
 SPLAT_API const char *splat_last_error(void);

@@ -26,7 +26,7 @@ class splat_settings(C.Structure):
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double), ("t_min", C.c_double),
                 ("guard", C.c_double), ("bg", C.c_double * 3), ("pad_px", C.c_double),
                 ("pad_rel", C.c_double), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
-                ("batch", C.c_int32), ("persistent", C.c_int32)]
+                ("batch", C.c_int32), ("persistent", C.c_int32), ("roi_y0", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class splat_gaussians(C.Structure):
@@ -76,7 +76,8 @@ def lib():
                                     P, P, P, P, P, P, P]
     L.splat_render_fwd_stats.argtypes = [C.POINTER(splat_plan), P, P, P, P, P, P]
     L.splat_render_bwd_stats.argtypes = [C.POINTER(splat_plan), P, P, P, P, P, P]
-    L.splat_l1_loss_grad.argtypes = [P, P, P, I32, I32, I32, P, P, P]
+    L.splat_l1_loss_grad.argtypes = [P, P, P, I32, I32, I32, I32, P, P, P]
+    L.splat_scale_reg.argtypes = [P, I64, C.c_double, P, P, P]
     L.splat_last_error.restype = C.c_char_p
     L.splat_version.restype = C.c_char_p
     L.splat_struct_size.argtypes = [I32]
@@ -182,10 +183,15 @@ def splat_render_bwd_stats(plan, ws, dL_dimg, T_final, last_pos, stats, stream=N
                                         _ptr(stats), _stream(stream)), "splat_render_bwd_stats")
 
 
-def splat_l1_loss_grad(img, target, mask, dL_dimg, loss=None, stream=None):
+def splat_l1_loss_grad(img, target, mask, dL_dimg, loss=None, roi_y0=0, stream=None):
     V, _, H, W = img.shape
-    _check(lib().splat_l1_loss_grad(_ptr(img), _ptr(target), _ptr(mask), int(V), int(W), int(H), _ptr(dL_dimg),
-                                    _ptr(loss), _stream(stream)), "splat_l1_loss_grad")
+    _check(lib().splat_l1_loss_grad(_ptr(img), _ptr(target), _ptr(mask), int(V), int(W), int(H), int(roi_y0),
+                                    _ptr(dL_dimg), _ptr(loss), _stream(stream)), "splat_l1_loss_grad")
+
+
+def splat_scale_reg(scale, lam, dscale, loss=None, stream=None):
+    _check(lib().splat_scale_reg(_ptr(scale), int(scale.shape[1]), float(lam), _ptr(dscale), _ptr(loss),
+                                 _stream(stream)), "splat_scale_reg")
 
 
 def splat_version() -> str:

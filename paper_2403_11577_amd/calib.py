@@ -164,7 +164,7 @@ class Calibrator:
         self.loss.zero_()
         pl.zero_grads(self.gr)
         pl.forward(fr, w, self.xi_t, self.dl_t)
-        B.splat_l1_loss_grad(fr.img, self.tgt, None, self.dimg, self.loss)
+        B.splat_l1_loss_grad(fr.img, self.tgt, None, self.dimg, self.loss, self.settings.roi_y0)
         pl.backward(fr, w, self.xi_t, self.dl_t, self.dimg, self.gr)
         # activations and the optimiser (torch)
         self.color.grad = self.gr.color

@@ -71,6 +71,7 @@ static int check_settings(const splat_settings *s) {
         set_error("batch must be a multiple of 16 in [16, 256] (got %d)", s->batch); return SPLAT_EINVAL;
     }
     if (s->persistent != 0 && s->persistent != 1) { set_error("persistent must be 0 or 1"); return SPLAT_EINVAL; }
+    if (s->roi_y0 < 0) { set_error("roi_y0 must be >= 0 (got %d)", s->roi_y0); return SPLAT_EINVAL; }
     return SPLAT_OK;
 }
 
@@ -141,6 +142,8 @@ void splat_default_settings(splat_settings *s) {
     s->tile_h = 16;
     s->batch = 64;
     s->persistent = 1;
+    s->roi_y0 = 0;
+    s->reserved0 = 0;
 }
 
 int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, int32_t width, int32_t height,
@@ -154,6 +157,7 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     if (width < 1 || height < 1 || width > 16384 || height > 16384) {
         set_error("image size %dx%d outside [1, 16384]", width, height); return SPLAT_EINVAL;
     }
+    if (s->roi_y0 >= height) { set_error("roi_y0 %d must be below the image height %d", s->roi_y0, height); return SPLAT_EINVAL; }
     if (slot_cap < 1 || slot_cap >= ((int64_t)1 << 31) || inst_cap < 1 || inst_cap >= ((int64_t)1 << 31)) {
         set_error("capacities must be in [1, 2^31) (got %lld, %lld)", (long long)slot_cap, (long long)inst_cap);
         return SPLAT_EINVAL;
@@ -283,13 +287,22 @@ int splat_render_fwd_stats(const splat_plan *plan, void *ws, float *img, float *
 }
 
 int splat_l1_loss_grad(const float *img, const float *target, const uint8_t *mask, int32_t n_views, int32_t width,
-                       int32_t height, float *dL_dimg, double *loss, void *stream) {
+                       int32_t height, int32_t roi_y0, float *dL_dimg, double *loss, void *stream) {
     g_err[0] = 0;
     if (!img || !target || !dL_dimg) { set_error("l1_loss_grad: NULL argument"); return SPLAT_EINVAL; }
     if (n_views < 1 || width < 1 || height < 1) { set_error("l1_loss_grad: bad shape"); return SPLAT_EINVAL; }
-    int64_t hw = (int64_t)width * height;
-    double inv_n = 1.0 / (3.0 * (double)n_views * (double)hw);
-    return launch_l1(img, target, mask, n_views, hw, inv_n, dL_dimg, loss, (hipStream_t)stream);
+    if (roi_y0 < 0 || roi_y0 >= height) { set_error("l1_loss_grad: roi_y0 %d outside [0, %d)", roi_y0, height); return SPLAT_EINVAL; }
+    double inv_n = 1.0 / (3.0 * (double)n_views * (double)width * (double)(height - roi_y0));
+    return launch_l1(img, target, mask, n_views, width, height, roi_y0, inv_n, dL_dimg, loss, (hipStream_t)stream);
+}
+
+int splat_scale_reg(const float *scale, int64_t n, double lambda, float *dscale, double *loss, void *stream) {
+    g_err[0] = 0;
+    if (n < 0) { set_error("scale_reg: n must be >= 0"); return SPLAT_EINVAL; }
+    if (n == 0) return SPLAT_OK;
+    if (!scale || !dscale) { set_error("scale_reg: NULL argument"); return SPLAT_EINVAL; }
+    if (!std::isfinite(lambda)) { set_error("scale_reg: lambda must be finite"); return SPLAT_EINVAL; }
+    return launch_scale_reg(scale, n, lambda, dscale, loss, (hipStream_t)stream);
 }
 
 int splat_render_bwd(const splat_plan *plan, void *ws, const float *dL_dimg, const float *T_final,

@@ -79,8 +79,9 @@ int launch_render_fwd(const splat_plan &p, void *ws, float *img, float *T, int32
                       uint64_t *stats, hipStream_t st);
 int launch_render_bwd(const splat_plan &p, void *ws, const float *dimg, const float *T,
                       const int32_t *last, uint64_t *stats, hipStream_t st);
-int launch_l1(const float *img, const float *target, const uint8_t *mask, int64_t n_views, int64_t hw,
-              double inv_n, float *dimg, double *loss, hipStream_t st);
+int launch_l1(const float *img, const float *target, const uint8_t *mask, int64_t n_views, int32_t width,
+              int32_t height, int32_t roi_y0, double inv_n, float *dimg, double *loss, hipStream_t st);
+int launch_scale_reg(const float *scale, int64_t n, double lambda, float *dscale, double *loss, hipStream_t st);
 
 // device exclusive scan of u32 (binsort.hip): out[i] = sum in[0..i), out[n] = total;
 // n is read from *n_dev (clamped to n_cap); partials needs scan_partials(n_cap) u32.

@@ -113,13 +113,13 @@ __device__ inline void project_view(const splat_settings &S, const double *M, co
 }
 
 // Pixel rectangle of the alpha >= alpha_min footprint (exact AABB of the ellipse,
-// padded); PC_OFF if it misses the image.
+// padded) inside the rendered rows; PC_OFF if it misses them.
 __device__ inline int footprint(const splat_settings &S, double k2, int W, int H, Proj &P) {
     double ex = sqrt(k2 * P.S2[0]) * (1.0 + S.pad_rel) + S.pad_px;
     double ey = sqrt(k2 * P.S2[2]) * (1.0 + S.pad_rel) + S.pad_px;
     double a0 = ceil(P.mu[0] - 0.5 - ex), a1 = floor(P.mu[0] - 0.5 + ex);
     double b0 = ceil(P.mu[1] - 0.5 - ey), b1 = floor(P.mu[1] - 0.5 + ey);
-    a0 = fmax(a0, 0.0); b0 = fmax(b0, 0.0);
+    a0 = fmax(a0, 0.0); b0 = fmax(b0, (double)S.roi_y0);  // rows above the region of interest are not rendered
     a1 = fmin(a1, (double)(W - 1)); b1 = fmin(b1, (double)(H - 1));
     if (!(a0 <= a1) || !(b0 <= b1)) return PC_OFF;
     P.px0 = (int)a0; P.px1 = (int)a1; P.py0 = (int)b0; P.py1 = (int)b1;
@@ -156,7 +156,7 @@ __device__ inline bool offscreen_bound(const splat_settings &S, const double *M,
     float ex = (sqrtf(k2f * sx) * pr + pp) * 1.001f + 1.f + 1e-5f * fabsf(mx);
     float ey = (sqrtf(k2f * sy) * pr + pp) * 1.001f + 1.f + 1e-5f * fabsf(my);
     // NaN anywhere makes every comparison false: not culled here, decided exactly afterwards
-    return (mx - 0.5f + ex < 0.f) || (mx - 0.5f - ex > (float)(W - 1)) || (my - 0.5f + ey < 0.f) ||
+    return (mx - 0.5f + ex < 0.f) || (mx - 0.5f - ex > (float)(W - 1)) || (my - 0.5f + ey < (float)S.roi_y0) ||
            (my - 0.5f - ey > (float)(H - 1));
 }
 

@@ -39,7 +39,7 @@ struct RenderArgs {
     uint32_t *work;             // persistent work counter
     const uint32_t *counts;     // device counts (slots, instances)
     unsigned long long *stats;  // pair counters of the instrumented variant
-    int n_items, T, tiles_x, W, H, persistent;
+    int n_items, T, tiles_x, W, H, persistent, roi_y0;
     float amin, amax, tmin, lamin2;  // lamin2 = log2(alpha_min)
     float bg0, bg1, bg2;
 };
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
             px[k] = (float)(x0 - xb + qx) + 0.5f;
             py[k] = (float)(y0 - yb + qy) + 0.5f;
             T[k] = (x0 + qx < a.W && y0 + qy < a.H) ? 1.f : 0.f;
-            L[k] = T[k];
+            L[k] = y0 + qy >= a.roi_y0 ? T[k] : 0.f;  // above the region of interest: background, T = 1
             C0[k] = C1[k] = C2[k] = 0.f;
             last[k] = -1;
         }
@@ -475,6 +475,7 @@ RenderArgs make_args(const splat_plan &p, void *ws, unsigned long long *stats) {
     a.W = p.width;
     a.H = p.height;
     a.persistent = p.s.persistent;
+    a.roi_y0 = p.s.roi_y0;
     a.amin = (float)p.s.alpha_min;
     a.amax = (float)p.s.alpha_max;
     a.tmin = (float)p.s.t_min;

@@ -245,17 +245,17 @@ def fit_frame(ds: DeviceScene, xi, delta, settings=None, slot_cap=None, inst_cap
 # -----------------------------------------------------------------------------
 # loss (L1 part of Eq. 4)
 # -----------------------------------------------------------------------------
-def l1_loss_grad(img: torch.Tensor, target: torch.Tensor, mask=None, dimg=None, loss=None):
+def l1_loss_grad(img: torch.Tensor, target: torch.Tensor, mask=None, dimg=None, loss=None, roi_y0=0):
     """L1 mean and its gradient sign(img - target)/N (sign(0) = 0), by the library's L1 kernel.
 
-    mask (optional) is a bool/uint8 [V,H,W] tensor of pixels to leave out.
-    Returns (loss [1] float64 device tensor, dimg)."""
+    mask (optional) is a bool/uint8 [V,H,W] tensor of pixels to leave out; roi_y0 restricts
+    the mean to the rows [roi_y0, H).  Returns (loss [1] float64 device tensor, dimg)."""
     if dimg is None:
         dimg = torch.empty_like(img)
     if loss is None:
         loss = torch.zeros(1, dtype=torch.float64, device=img.device)
     m = None if mask is None else mask.to(torch.uint8).contiguous()
-    B.splat_l1_loss_grad(img, target.contiguous(), m, dimg, loss)
+    B.splat_l1_loss_grad(img, target.contiguous(), m, dimg, loss, roi_y0)
     return loss, dimg
 
 
@@ -287,7 +287,7 @@ class BatchedStep:
         if ev: ev["fwd"][0].record()
         B.splat_render_fwd(fr.plan, fr.ws, fr.img, fr.T, fr.last)
         if ev: ev["fwd"][1].record()
-        B.splat_l1_loss_grad(fr.img, self.targets, self.mask, self.dimg, self.loss)
+        B.splat_l1_loss_grad(fr.img, self.targets, self.mask, self.dimg, self.loss, fr.settings.roi_y0)
         if ev: ev["bwd"][0].record()
         B.splat_render_bwd(fr.plan, fr.ws, self.dimg, fr.T, fr.last)
         if ev: ev["bwd"][1].record()
@@ -322,7 +322,7 @@ class BatchedStep:
         B.splat_project(fr.plan, fr.ws, ds.gaussians(), fr.w2c, ds.intr)
         B.splat_bin_sort(fr.plan, fr.ws)
         B.splat_render_fwd_stats(fr.plan, fr.ws, fr.img, fr.T, fr.last, st)
-        B.splat_l1_loss_grad(fr.img, self.targets, self.mask, self.dimg, None)
+        B.splat_l1_loss_grad(fr.img, self.targets, self.mask, self.dimg, None, fr.settings.roi_y0)
         B.splat_render_bwd_stats(fr.plan, fr.ws, self.dimg, fr.T, fr.last, st)
         torch.cuda.synchronize()
         v = st.cpu().tolist()
@@ -366,7 +366,7 @@ class PerViewPlain:
             B.splat_bin_sort(fr.plan, fr.ws); sync()
             fr.counts()
             B.splat_render_fwd(fr.plan, fr.ws, fr.img, fr.T, fr.last); sync()
-            L, dimg = l1_loss_grad(fr.img, targets[v:v + 1])
+            L, dimg = l1_loss_grad(fr.img, targets[v:v + 1], roi_y0=fr.settings.roi_y0)
             dimg.mul_(1.0 / len(self.views))  # mean over all views, as in the batched step
             total += float(L) / len(self.views)
             zero_grads(g1)
