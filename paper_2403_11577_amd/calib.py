@@ -10,8 +10,9 @@ projection, binning, compositing, L1, adjoints); the optimiser and the parameter
 activations (sigmoid opacity, exponential scale) are plain torch.
 
 Learning rates of the Gaussian parameters are not given in the paper; those of
-the original 3DGS implementation are used.  The photometric loss here is the
-L1 term of Eq. (4) only (the D-SSIM term is not part of this build).
+the original 3DGS implementation are used.  As in Sec. III-C, only the bottom
+rows of every image are rendered and enter the loss (roi_frac), and L_scale
+(lambda_2 = 1e-3) is added.
 """
 from __future__ import annotations
 
@@ -45,6 +46,9 @@ class CalibConfig:
     # "scene": start from the scene's own Gaussians (pure registration when frozen)
     gauss_init: str = "random"
     freeze_gaussians: bool = False
+    # Sec. III-C: losses on the bottom part of the image only, and the scale regulariser
+    roi_frac: float = 0.5          # fraction of the rows (from the bottom) that is rendered
+    lam_scale: float = 1e-3        # lambda_2 of L_scale (0 disables it)
 
 
 def rotation_error_deg(xi):
@@ -62,7 +66,10 @@ class Calibrator:
         full = pl.DeviceScene.from_scene(scene, device=device)
         self.full = full
         V, G, Bv = full.n_views, full.n_gauss, cfg.batch_views
-        self.settings = settings or pl.make_settings()
+        base = settings or pl.make_settings()
+        roi = int(round(full.H * (1.0 - cfg.roi_frac)))
+        self.settings = pl.make_settings(tile=(base.tile_w, base.tile_h), batch=base.batch,
+                                         persistent=bool(base.persistent), roi_y0=min(max(roi, 0), full.H - 1))
         # targets: every view rendered at the ground-truth calibration with the true Gaussians
         zx = torch.zeros((full.n_cams, 6), dtype=torch.float64, device=device)
         zd = torch.zeros(full.n_cams, dtype=torch.float64, device=device)
@@ -166,6 +173,8 @@ class Calibrator:
         pl.forward(fr, w, self.xi_t, self.dl_t)
         B.splat_l1_loss_grad(fr.img, self.tgt, None, self.dimg, self.loss, self.settings.roi_y0)
         pl.backward(fr, w, self.xi_t, self.dl_t, self.dimg, self.gr)
+        if cfg.lam_scale > 0:
+            B.splat_scale_reg(w.scale, cfg.lam_scale, self.gr.scale, self.loss)
         # activations and the optimiser (torch)
         self.color.grad = self.gr.color
         self.logit_o.grad = self.gr.opacity * o * (1 - o)
