@@ -242,15 +242,32 @@ SPLAT_API int splat_project_bwd(const splat_plan *plan, void *ws, const splat_ga
 /*
  * The L1 term of the photometric loss (paper Eq. 4) over the region of interest
  * (rows [roi_y0, H); Sec. III-C computes the losses on the bottom part of the
- * image): with N = V*3*(H - roi_y0)*W, dL_dimg = sign(img - target)/N inside the
- * region (sign(0) = 0) and 0 above it, and *loss += sum |img - target|/N
- * (float64, caller zeroes it; NULL to skip).  img, target, dL_dimg are
- * [V][3][H][W] float32 device arrays; mask (nullable) is uint8 [V][H][W] and
- * removes the pixels where it is non-zero from the sum (N is unchanged).
- * 0 <= roi_y0 < H.
+ * image), scaled by weight ((1 - lambda_1) in Eq. 4, 1 for the L1 loss alone):
+ * with N = V*3*(H - roi_y0)*W, dL_dimg = weight * sign(img - target)/N inside the
+ * region (sign(0) = 0) and 0 above it (dL_dimg is overwritten), and *loss +=
+ * weight * sum |img - target|/N (float64, caller zeroes it; NULL to skip).  img,
+ * target, dL_dimg are [V][3][H][W] float32 device arrays; mask (nullable) is
+ * uint8 [V][H][W] and removes the pixels where it is non-zero from the sum (N is
+ * unchanged).  0 <= roi_y0 < H.
  */
 SPLAT_API int splat_l1_loss_grad(const float *img, const float *target, const uint8_t *mask, int32_t n_views,
-                                 int32_t width, int32_t height, int32_t roi_y0, float *dL_dimg, double *loss, void *stream);
+                                 int32_t width, int32_t height, int32_t roi_y0, double weight, float *dL_dimg,
+                                 double *loss, void *stream);
+
+/*
+ * The D-SSIM term of Eq. (4) (the structural-similarity loss of the original 3DGS
+ * work): SSIM with an 11x11 Gaussian window (sigma 1.5), zero padding, per
+ * channel, C1 = 0.01^2, C2 = 0.03^2, of the images cropped to the rows
+ * [roi_y0, H).  ADDS weight * d(1 - mean SSIM)/d img to dL_dimg (rows >= roi_y0)
+ * and weight * (1 - mean SSIM) to *loss (float64, nullable).  img, target and
+ * dL_dimg are [V][3][H][W] float32 device arrays; ws is device scratch of at least
+ * splat_dssim_workspace_size() bytes (three float maps of the cropped images),
+ * owned by the caller.
+ */
+SPLAT_API size_t splat_dssim_workspace_size(int32_t n_views, int32_t width, int32_t height, int32_t roi_y0);
+SPLAT_API int splat_dssim_loss_grad(const float *img, const float *target, int32_t n_views, int32_t width,
+                                    int32_t height, int32_t roi_y0, double weight, void *ws, size_t ws_bytes,
+                                    float *dL_dimg, double *loss, void *stream);
 
 /*
  * Instrumented variants of splat_render_fwd / splat_render_bwd: identical

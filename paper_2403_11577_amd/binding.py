@@ -76,7 +76,10 @@ def lib():
                                     P, P, P, P, P, P, P]
     L.splat_render_fwd_stats.argtypes = [C.POINTER(splat_plan), P, P, P, P, P, P]
     L.splat_render_bwd_stats.argtypes = [C.POINTER(splat_plan), P, P, P, P, P, P]
-    L.splat_l1_loss_grad.argtypes = [P, P, P, I32, I32, I32, I32, P, P, P]
+    L.splat_l1_loss_grad.argtypes = [P, P, P, I32, I32, I32, I32, C.c_double, P, P, P]
+    L.splat_dssim_workspace_size.argtypes = [I32, I32, I32, I32]
+    L.splat_dssim_workspace_size.restype = C.c_size_t
+    L.splat_dssim_loss_grad.argtypes = [P, P, I32, I32, I32, I32, C.c_double, P, C.c_size_t, P, P, P]
     L.splat_scale_reg.argtypes = [P, I64, C.c_double, P, P, P]
     L.splat_last_error.restype = C.c_char_p
     L.splat_version.restype = C.c_char_p
@@ -183,10 +186,21 @@ def splat_render_bwd_stats(plan, ws, dL_dimg, T_final, last_pos, stats, stream=N
                                         _ptr(stats), _stream(stream)), "splat_render_bwd_stats")
 
 
-def splat_l1_loss_grad(img, target, mask, dL_dimg, loss=None, roi_y0=0, stream=None):
+def splat_l1_loss_grad(img, target, mask, dL_dimg, loss=None, roi_y0=0, weight=1.0, stream=None):
     V, _, H, W = img.shape
     _check(lib().splat_l1_loss_grad(_ptr(img), _ptr(target), _ptr(mask), int(V), int(W), int(H), int(roi_y0),
-                                    _ptr(dL_dimg), _ptr(loss), _stream(stream)), "splat_l1_loss_grad")
+                                    float(weight), _ptr(dL_dimg), _ptr(loss), _stream(stream)), "splat_l1_loss_grad")
+
+
+def splat_dssim_workspace_size(n_views, width, height, roi_y0=0) -> int:
+    return int(lib().splat_dssim_workspace_size(int(n_views), int(width), int(height), int(roi_y0)))
+
+
+def splat_dssim_loss_grad(img, target, ws, dL_dimg, loss=None, roi_y0=0, weight=0.2, stream=None):
+    V, _, H, W = img.shape
+    _check(lib().splat_dssim_loss_grad(_ptr(img), _ptr(target), int(V), int(W), int(H), int(roi_y0), float(weight),
+                                       _ptr(ws), int(ws.numel() * ws.element_size()), _ptr(dL_dimg), _ptr(loss),
+                                       _stream(stream)), "splat_dssim_loss_grad")
 
 
 def splat_scale_reg(scale, lam, dscale, loss=None, stream=None):

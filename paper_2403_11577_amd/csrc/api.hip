@@ -287,13 +287,34 @@ int splat_render_fwd_stats(const splat_plan *plan, void *ws, float *img, float *
 }
 
 int splat_l1_loss_grad(const float *img, const float *target, const uint8_t *mask, int32_t n_views, int32_t width,
-                       int32_t height, int32_t roi_y0, float *dL_dimg, double *loss, void *stream) {
+                       int32_t height, int32_t roi_y0, double weight, float *dL_dimg, double *loss, void *stream) {
     g_err[0] = 0;
     if (!img || !target || !dL_dimg) { set_error("l1_loss_grad: NULL argument"); return SPLAT_EINVAL; }
     if (n_views < 1 || width < 1 || height < 1) { set_error("l1_loss_grad: bad shape"); return SPLAT_EINVAL; }
     if (roi_y0 < 0 || roi_y0 >= height) { set_error("l1_loss_grad: roi_y0 %d outside [0, %d)", roi_y0, height); return SPLAT_EINVAL; }
-    double inv_n = 1.0 / (3.0 * (double)n_views * (double)width * (double)(height - roi_y0));
+    if (!std::isfinite(weight)) { set_error("l1_loss_grad: weight must be finite"); return SPLAT_EINVAL; }
+    double inv_n = weight / (3.0 * (double)n_views * (double)width * (double)(height - roi_y0));
     return launch_l1(img, target, mask, n_views, width, height, roi_y0, inv_n, dL_dimg, loss, (hipStream_t)stream);
+}
+
+size_t splat_dssim_workspace_size(int32_t n_views, int32_t width, int32_t height, int32_t roi_y0) {
+    if (n_views < 1 || width < 1 || height < 1 || roi_y0 < 0 || roi_y0 >= height) return 0;
+    return dssim_ws_bytes(n_views, width, height, roi_y0);
+}
+
+int splat_dssim_loss_grad(const float *img, const float *target, int32_t n_views, int32_t width, int32_t height,
+                          int32_t roi_y0, double weight, void *ws, size_t ws_bytes, float *dL_dimg, double *loss,
+                          void *stream) {
+    g_err[0] = 0;
+    if (!img || !target || !dL_dimg || !ws) { set_error("dssim_loss_grad: NULL argument"); return SPLAT_EINVAL; }
+    if (n_views < 1 || n_views > 21845 || width < 1 || height < 1) { set_error("dssim_loss_grad: bad shape"); return SPLAT_EINVAL; }
+    if (roi_y0 < 0 || roi_y0 >= height) { set_error("dssim_loss_grad: roi_y0 %d outside [0, %d)", roi_y0, height); return SPLAT_EINVAL; }
+    if (!std::isfinite(weight)) { set_error("dssim_loss_grad: weight must be finite"); return SPLAT_EINVAL; }
+    size_t need = dssim_ws_bytes(n_views, width, height, roi_y0);
+    if (ws_bytes < need) {
+        set_error("dssim_loss_grad: workspace of %zu bytes, %zu needed", ws_bytes, need); return SPLAT_EINVAL;
+    }
+    return launch_dssim(img, target, n_views, width, height, roi_y0, weight, ws, dL_dimg, loss, (hipStream_t)stream);
 }
 
 int splat_scale_reg(const float *scale, int64_t n, double lambda, float *dscale, double *loss, void *stream) {

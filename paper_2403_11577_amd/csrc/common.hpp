@@ -82,6 +82,9 @@ int launch_render_bwd(const splat_plan &p, void *ws, const float *dimg, const fl
 int launch_l1(const float *img, const float *target, const uint8_t *mask, int64_t n_views, int32_t width,
               int32_t height, int32_t roi_y0, double inv_n, float *dimg, double *loss, hipStream_t st);
 int launch_scale_reg(const float *scale, int64_t n, double lambda, float *dscale, double *loss, hipStream_t st);
+size_t dssim_ws_bytes(int64_t n_views, int32_t width, int32_t height, int32_t roi_y0);
+int launch_dssim(const float *img, const float *target, int64_t n_views, int32_t width, int32_t height,
+                 int32_t roi_y0, double weight, void *ws, float *dimg, double *loss, hipStream_t st);
 
 // device exclusive scan of u32 (binsort.hip): out[i] = sum in[0..i), out[n] = total;
 // n is read from *n_dev (clamped to n_cap); partials needs scan_partials(n_cap) u32.

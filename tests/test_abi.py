@@ -106,7 +106,7 @@ def test_entry_points_reject_null_arguments_without_a_device():
     assert L.splat_render_bwd(C.byref(p), C.c_void_p(16), None, None, None, None) == -1
     assert L.splat_pose_interp_fwd(1, *([None] * 3), 1, *([None] * 4), 1, None, None, None, None, None) == -1
     assert b"2 trajectory knots" in L.splat_last_error()
-    assert L.splat_l1_loss_grad(None, None, None, 1, 4, 4, 0, None, None, None) == -1
+    assert L.splat_l1_loss_grad(None, None, None, 1, 4, 4, 0, 1.0, None, None, None) == -1
     bad = B.splat_plan()  # all zeros: not made by splat_plan_make
     assert L.splat_bin_sort(C.byref(bad), C.c_void_p(16), None) == -1
     assert b"not initialised" in L.splat_last_error()
@@ -124,7 +124,7 @@ def test_region_of_interest_is_validated():
     s.roi_y0 = 47
     assert B.splat_plan_make(s, 1, 10, 64, 48, 10, 10).s.roi_y0 == 47
     L = B.lib()
-    assert L.splat_l1_loss_grad(None, None, None, 1, 4, 4, 4, None, None, None) == -1
+    assert L.splat_l1_loss_grad(None, None, None, 1, 4, 4, 4, 1.0, None, None, None) == -1
 
 
 def test_scale_reg_rejects_bad_arguments_without_a_device():
@@ -133,3 +133,11 @@ def test_scale_reg_rejects_bad_arguments_without_a_device():
     assert L.splat_scale_reg(None, 5, 1e-3, None, None, None) == -1
     assert b"NULL" in L.splat_last_error()
     assert L.splat_scale_reg(None, -1, 1e-3, None, None, None) == -1
+
+
+def test_dssim_workspace_and_argument_checks_without_a_device():
+    L = B.lib()
+    assert L.splat_dssim_workspace_size(2, 10, 8, 3) == 3 * 6 * 5 * 10 * 4
+    assert L.splat_dssim_workspace_size(2, 10, 8, 8) == 0
+    assert L.splat_dssim_loss_grad(None, None, 1, 4, 4, 0, 0.2, None, 0, None, None, None) == -1
+    assert b"NULL" in L.splat_last_error()
