@@ -11,8 +11,8 @@ activations (sigmoid opacity, exponential scale) are plain torch.
 
 Learning rates of the Gaussian parameters are not given in the paper; those of
 the original 3DGS implementation are used.  As in Sec. III-C, only the bottom
-rows of every image are rendered and enter the loss (roi_frac), and L_scale
-(lambda_2 = 1e-3) is added.
+rows of every image are rendered and enter the loss (roi_frac); the photometric
+loss is Eq. (4), 0.8 L1 + 0.2 D-SSIM, and L_scale (lambda_2 = 1e-3) is added.
 """
 from __future__ import annotations
 
@@ -49,6 +49,7 @@ class CalibConfig:
     # Sec. III-C: losses on the bottom part of the image only, and the scale regulariser
     roi_frac: float = 0.5          # fraction of the rows (from the bottom) that is rendered
     lam_scale: float = 1e-3        # lambda_2 of L_scale (0 disables it)
+    lam_dssim: float = 0.2         # lambda_1 of Eq. 4: L_photo = (1 - lambda_1) L1 + lambda_1 D-SSIM
 
 
 def rotation_error_deg(xi):
@@ -126,6 +127,8 @@ class Calibrator:
         self.gr = pl.alloc_grads(self.win)
         self.dimg = torch.empty_like(self.fr.img)
         self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+        self.ssim_ws = torch.empty(B.splat_dssim_workspace_size(Bv, full.W, full.H, self.settings.roi_y0),
+                                   dtype=torch.uint8, device=device)
         self.rng = np.random.default_rng(cfg.seed)
         self.order = []
         # status words of the last two steps, copied to pinned memory and read two steps later
@@ -171,7 +174,10 @@ class Calibrator:
         self.loss.zero_()
         pl.zero_grads(self.gr)
         pl.forward(fr, w, self.xi_t, self.dl_t)
-        B.splat_l1_loss_grad(fr.img, self.tgt, None, self.dimg, self.loss, self.settings.roi_y0)
+        B.splat_l1_loss_grad(fr.img, self.tgt, None, self.dimg, self.loss, self.settings.roi_y0, 1.0 - cfg.lam_dssim)
+        if cfg.lam_dssim > 0:
+            B.splat_dssim_loss_grad(fr.img, self.tgt, self.ssim_ws, self.dimg, self.loss, self.settings.roi_y0,
+                                    cfg.lam_dssim)
         pl.backward(fr, w, self.xi_t, self.dl_t, self.dimg, self.gr)
         if cfg.lam_scale > 0:
             B.splat_scale_reg(w.scale, cfg.lam_scale, self.gr.scale, self.loss)
