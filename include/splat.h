@@ -293,6 +293,49 @@ SPLAT_API int splat_render_bwd_stats(const splat_plan *plan, void *ws, const flo
 SPLAT_API int splat_scale_reg(const float *scale, int64_t n, double lambda, float *dscale, double *loss,
                               void *stream);
 
+/*
+ * Gaussian parameters from a neural field, F(X|Theta) of Sec. III-C (the model of
+ * Instant-NGP with four heads).  Per Gaussian: the LiDAR position is normalised
+ * into [0,1]^3 by the box [lo, hi] and clamped; level l (resolution
+ * N_l = floor(n_min * b^l), b = exp(ln(n_max / n_min) / (levels - 1))) blends the
+ * 8 vertices of the position's cell trilinearly, each vertex being the row
+ * v0 + (N_l+1)(v1 + (N_l+1) v2) of the level's table when (N_l+1)^3 <= T, else
+ * the row (v0 * 1) ^ (v1 * 2654435761) ^ (v2 * 805459861) mod T (32-bit
+ * unsigned); the 2 * levels features go through an MLP 2L -> 64 -> 64 -> 11 with
+ * ReLU, and the heads give colour = sigmoid(o[0:3]), opacity = sigmoid(o[3]),
+ * scale = scale_max * sigmoid(o[4:7]) (below the voxel size, Sec. III-C) and
+ * quaternion = o[7:11] + (1, 0, 0, 0).
+ * Layout (float32 device arrays): tables[levels][T][2], w1[64][2*levels],
+ * b1[64], w2[64][64], b2[64], w3[11][64], b3[11] (row-major, out x in).
+ * Limits: 1 <= levels <= 16, feat = 2, hidden = 64, 4 <= log2_table <= 24,
+ * 1 <= n_min <= n_max, hi > lo on every axis, scale_max > 0.
+ */
+typedef struct splat_ngp {
+    int32_t levels, feat, log2_table, n_min, n_max, hidden;
+    double scale_max;
+    double lo[3], hi[3];
+    const float *tables;
+    const float *w1, *b1, *w2, *b2, *w3, *b3;
+} splat_ngp;
+
+/* Writes quat[4][n], scale[3][n], opacity[n], color[3][n] (the splat_gaussians
+ * planes) for the n positions mean[3][n]. */
+SPLAT_API int splat_ngp_fwd(const splat_ngp *m, const float *mean, int64_t n, float *quat, float *scale,
+                            float *opacity, float *color, void *stream);
+
+/* Device scratch of splat_ngp_bwd for n Gaussians (per-Gaussian activations and
+ * deltas, 1200 bytes each, plus the weight-gradient partials). */
+SPLAT_API size_t splat_ngp_workspace_size(int64_t n);
+
+/* Adjoint of splat_ngp_fwd: from d(loss)/d(quat, scale, opacity, color) it ADDS
+ * the gradients of the tables (float atomics; order-dependent rounding) and of
+ * the weights and biases (fixed-order sums).  ws is caller-owned scratch of at
+ * least splat_ngp_workspace_size(n) bytes. */
+SPLAT_API int splat_ngp_bwd(const splat_ngp *m, const float *mean, int64_t n, const float *dquat,
+                            const float *dscale, const float *dopacity, const float *dcolor, void *ws,
+                            size_t ws_bytes, float *dtables, float *dw1, float *db1, float *dw2, float *db2,
+                            float *dw3, float *db3, void *stream);
+
 /* Text of the last synchronous error on this thread ("" if none). */
 SPLAT_API const char *splat_last_error(void);
 
@@ -300,7 +343,7 @@ SPLAT_API const char *splat_last_error(void);
 SPLAT_API const char *splat_version(void);
 
 /* sizeof of the ABI structs, for bindings to check their mirrors:
- * which = 0 splat_settings, 1 splat_gaussians, 2 splat_plan; else 0. */
+ * which = 0 splat_settings, 1 splat_gaussians, 2 splat_plan, 3 splat_ngp; else 0. */
 SPLAT_API size_t splat_struct_size(int32_t which);
 
 #ifdef __cplusplus

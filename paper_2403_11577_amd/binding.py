@@ -49,6 +49,12 @@ class splat_plan(C.Structure):
                 [("sorted_buf", C.c_int32), ("radix_bits", C.c_int32)])
 
 
+class splat_ngp(C.Structure):
+    _fields_ = ([(n, C.c_int32) for n in ("levels", "feat", "log2_table", "n_min", "n_max", "hidden")] +
+                [("scale_max", C.c_double), ("lo", C.c_double * 3), ("hi", C.c_double * 3)] +
+                [(n, C.c_void_p) for n in ("tables", "w1", "b1", "w2", "b2", "w3", "b3")])
+
+
 _lib = None
 
 
@@ -85,7 +91,11 @@ def lib():
     L.splat_version.restype = C.c_char_p
     L.splat_struct_size.argtypes = [I32]
     L.splat_struct_size.restype = C.c_size_t
-    for w, st in ((0, splat_settings), (1, splat_gaussians), (2, splat_plan)):
+    L.splat_ngp_fwd.argtypes = [C.POINTER(splat_ngp), P, I64, P, P, P, P, P]
+    L.splat_ngp_workspace_size.argtypes = [I64]
+    L.splat_ngp_workspace_size.restype = C.c_size_t
+    L.splat_ngp_bwd.argtypes = [C.POINTER(splat_ngp), P, I64, P, P, P, P, P, C.c_size_t, P, P, P, P, P, P, P, P]
+    for w, st in ((0, splat_settings), (1, splat_gaussians), (2, splat_plan), (3, splat_ngp)):
         if L.splat_struct_size(w) != C.sizeof(st):
             raise SplatError(f"ABI mismatch: {st.__name__} is {L.splat_struct_size(w)} bytes in the "
                              f"library, {C.sizeof(st)} in the binding")
@@ -210,3 +220,28 @@ def splat_scale_reg(scale, lam, dscale, loss=None, stream=None):
 
 def splat_version() -> str:
     return lib().splat_version().decode()
+
+
+def ngp_struct(cfg, lo, hi, tables, w1, b1, w2, b2, w3, b3) -> splat_ngp:
+    """cfg: any object with levels, feat, log2_table, n_min, n_max, hidden, scale_max."""
+    return splat_ngp(int(cfg.levels), int(cfg.feat), int(cfg.log2_table), int(cfg.n_min), int(cfg.n_max),
+                     int(cfg.hidden), float(cfg.scale_max), (C.c_double * 3)(*[float(v) for v in lo]),
+                     (C.c_double * 3)(*[float(v) for v in hi]), _ptr(tables), _ptr(w1), _ptr(b1), _ptr(w2),
+                     _ptr(b2), _ptr(w3), _ptr(b3))
+
+
+def splat_ngp_fwd(model: splat_ngp, mean, quat, scale, opacity, color, stream=None):
+    _check(lib().splat_ngp_fwd(C.byref(model), _ptr(mean), int(mean.shape[1]), _ptr(quat), _ptr(scale),
+                               _ptr(opacity), _ptr(color), _stream(stream)), "splat_ngp_fwd")
+
+
+def splat_ngp_workspace_size(n) -> int:
+    return int(lib().splat_ngp_workspace_size(int(n)))
+
+
+def splat_ngp_bwd(model: splat_ngp, mean, dquat, dscale, dopacity, dcolor, ws, dtables, dw1, db1, dw2, db2, dw3,
+                  db3, stream=None):
+    _check(lib().splat_ngp_bwd(C.byref(model), _ptr(mean), int(mean.shape[1]), _ptr(dquat), _ptr(dscale),
+                               _ptr(dopacity), _ptr(dcolor), _ptr(ws), int(ws.numel() * ws.element_size()),
+                               _ptr(dtables), _ptr(dw1), _ptr(db1), _ptr(dw2), _ptr(db2), _ptr(dw3), _ptr(db3),
+                               _stream(stream)), "splat_ngp_bwd")

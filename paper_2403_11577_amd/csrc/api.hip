@@ -122,6 +122,7 @@ size_t splat_struct_size(int32_t which) {
         case 0: return sizeof(splat_settings);
         case 1: return sizeof(splat_gaussians);
         case 2: return sizeof(splat_plan);
+        case 3: return sizeof(splat_ngp);
         default: return 0;
     }
 }
@@ -356,6 +357,58 @@ int splat_project_bwd(const splat_plan *plan, void *ws, const splat_gaussians *g
     }
     return launch_project_bwd(*plan, ws, *g, w2c, intr, dquat, dscale, dopacity, dcolor, dmean, dw2c,
                               (hipStream_t)stream);
+}
+
+
+static int check_ngp(const splat_ngp *m, const char *who) {
+    if (!m) { set_error("%s: model is NULL", who); return SPLAT_EINVAL; }
+    if (m->levels < 1 || m->levels > 16 || m->feat != 2 || m->hidden != 64) {
+        set_error("%s: need 1 <= levels <= 16, feat = 2, hidden = 64 (got %d, %d, %d)", who, m->levels, m->feat,
+                  m->hidden);
+        return SPLAT_EUNSUPPORTED;
+    }
+    if (m->log2_table < 4 || m->log2_table > 24) { set_error("%s: log2_table outside [4, 24]", who); return SPLAT_EINVAL; }
+    if (m->n_min < 1 || m->n_max < m->n_min) { set_error("%s: need 1 <= n_min <= n_max", who); return SPLAT_EINVAL; }
+    for (int d = 0; d < 3; ++d)
+        if (!(m->hi[d] > m->lo[d]) || !std::isfinite(m->lo[d]) || !std::isfinite(m->hi[d])) {
+            set_error("%s: the box needs finite hi > lo on every axis", who); return SPLAT_EINVAL;
+        }
+    if (!(m->scale_max > 0.0)) { set_error("%s: scale_max must be > 0", who); return SPLAT_EINVAL; }
+    if (!m->tables || !m->w1 || !m->b1 || !m->w2 || !m->b2 || !m->w3 || !m->b3) {
+        set_error("%s: NULL model array", who); return SPLAT_EINVAL;
+    }
+    return SPLAT_OK;
+}
+
+int splat_ngp_fwd(const splat_ngp *m, const float *mean, int64_t n, float *quat, float *scale, float *opacity,
+                  float *color, void *stream) {
+    g_err[0] = 0;
+    int rc = check_ngp(m, "ngp_fwd");
+    if (rc) return rc;
+    if (n < 0 || n >= ((int64_t)1 << 31)) { set_error("ngp_fwd: n outside [0, 2^31)"); return SPLAT_EINVAL; }
+    if (n == 0) return SPLAT_OK;
+    if (!mean || !quat || !scale || !opacity || !color) { set_error("ngp_fwd: NULL argument"); return SPLAT_EINVAL; }
+    return launch_ngp_fwd(*m, mean, n, quat, scale, opacity, color, (hipStream_t)stream);
+}
+
+size_t splat_ngp_workspace_size(int64_t n) { return n < 0 ? 0 : ngp_ws_bytes(n); }
+
+int splat_ngp_bwd(const splat_ngp *m, const float *mean, int64_t n, const float *dquat, const float *dscale,
+                  const float *dopacity, const float *dcolor, void *ws, size_t ws_bytes, float *dtables, float *dw1,
+                  float *db1, float *dw2, float *db2, float *dw3, float *db3, void *stream) {
+    g_err[0] = 0;
+    int rc = check_ngp(m, "ngp_bwd");
+    if (rc) return rc;
+    if (n < 0 || n >= ((int64_t)1 << 31)) { set_error("ngp_bwd: n outside [0, 2^31)"); return SPLAT_EINVAL; }
+    if (n == 0) return SPLAT_OK;
+    if (!mean || !dquat || !dscale || !dopacity || !dcolor || !ws || !dtables || !dw1 || !db1 || !dw2 || !db2 ||
+        !dw3 || !db3) {
+        set_error("ngp_bwd: NULL argument"); return SPLAT_EINVAL;
+    }
+    size_t need = ngp_ws_bytes(n);
+    if (ws_bytes < need) { set_error("ngp_bwd: workspace of %zu bytes, %zu needed", ws_bytes, need); return SPLAT_EINVAL; }
+    return launch_ngp_bwd(*m, mean, n, dquat, dscale, dopacity, dcolor, ws, dtables, dw1, db1, dw2, db2, dw3, db3,
+                          (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -83,6 +83,12 @@ int launch_l1(const float *img, const float *target, const uint8_t *mask, int64_
               int32_t height, int32_t roi_y0, double inv_n, float *dimg, double *loss, hipStream_t st);
 int launch_scale_reg(const float *scale, int64_t n, double lambda, float *dscale, double *loss, hipStream_t st);
 size_t dssim_ws_bytes(int64_t n_views, int32_t width, int32_t height, int32_t roi_y0);
+size_t ngp_ws_bytes(int64_t n);
+int launch_ngp_fwd(const splat_ngp &m, const float *mean, int64_t n, float *quat, float *scale, float *opac,
+                   float *color, hipStream_t st);
+int launch_ngp_bwd(const splat_ngp &m, const float *mean, int64_t n, const float *dquat, const float *dscale,
+                   const float *dopac, const float *dcolor, void *ws, float *dtables, float *dw1, float *db1,
+                   float *dw2, float *db2, float *dw3, float *db3, hipStream_t st);
 int launch_dssim(const float *img, const float *target, int64_t n_views, int32_t width, int32_t height,
                  int32_t roi_y0, double weight, void *ws, float *dimg, double *loss, hipStream_t st);
 
