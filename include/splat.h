@@ -324,7 +324,7 @@ SPLAT_API int splat_ngp_fwd(const splat_ngp *m, const float *mean, int64_t n, fl
                             float *opacity, float *color, void *stream);
 
 /* Device scratch of splat_ngp_bwd for n Gaussians (per-Gaussian activations and
- * deltas, 1200 bytes each, plus the weight-gradient partials). */
+ * deltas, 1328 bytes each, plus the weight-gradient partials). */
 SPLAT_API size_t splat_ngp_workspace_size(int64_t n);
 
 /* Adjoint of splat_ngp_fwd: from d(loss)/d(quat, scale, opacity, color) it ADDS

@@ -50,6 +50,17 @@ class CalibConfig:
     roi_frac: float = 0.5          # fraction of the rows (from the bottom) that is rendered
     lam_scale: float = 1e-3        # lambda_2 of L_scale (0 disables it)
     lam_dssim: float = 0.2         # lambda_1 of Eq. 4: L_photo = (1 - lambda_1) L1 + lambda_1 D-SSIM
+    # Gaussian parameters: "field" = F(X|Theta), hash grid + MLP with four heads (Sec. III-C);
+    # "independent" = one free parameter set per Gaussian (the 3DGS model without the field)
+    model: str = "independent"
+    field_levels: int = 16
+    field_log2_table: int = 19
+    field_n_min: int = 16
+    field_n_max: int = 4096
+    field_scale_max: float = 0.05  # the voxel size of the point cloud (scales stay below it)
+    lr_field_table: float = 1e-2
+    lr_field_mlp: float = 1e-3
+    field_weight_decay: float = 1e-4   # on the hash grid (Sec. IV-B)
 
 
 def rotation_error_deg(xi):
@@ -106,6 +117,9 @@ class Calibrator:
             q[0] = 1.0
             self.quat = q.requires_grad_(True)
         self.log_s = torch.log(full.scale.clone()).requires_grad_(True)
+        self.field = None
+        if cfg.model == "field":
+            self._init_field(full, cfg)
         self.rho = torch.tensor(scene.xi[:, :3], dtype=torch.float64, device=device).requires_grad_(True)
         self.phi = torch.tensor(scene.xi[:, 3:], dtype=torch.float64, device=device).requires_grad_(True)
         self.delta = torch.tensor(scene.delta, dtype=torch.float64, device=device).requires_grad_(True)
@@ -115,6 +129,9 @@ class Calibrator:
             dict(params=[self.logit_o], lr=cfg.lr_opacity),
             dict(params=[self.log_s], lr=cfg.lr_scale),
             dict(params=[self.quat], lr=cfg.lr_quat),
+        ] if self.field is None else [
+            dict(params=[self.field["tables"]], lr=cfg.lr_field_table, weight_decay=cfg.field_weight_decay),
+            dict(params=[self.field[k] for k in ("w1", "b1", "w2", "b2", "w3", "b3")], lr=cfg.lr_field_mlp),
         ], eps=1e-15)
         self.opt_c = torch.optim.Adam([
             dict(params=[self.rho], lr=cfg.lr_trans),
@@ -122,6 +139,9 @@ class Calibrator:
             dict(params=[self.delta], lr=cfg.lr_time),
         ], eps=1e-15)
         self.base_lr = [[grp["lr"] for grp in o.param_groups] for o in (self.opt_g, self.opt_c)]
+        if self.field is not None:
+            self.field_ws = torch.empty(B.splat_ngp_workspace_size(G), dtype=torch.uint8, device=device)
+            self.field_grads = {k: torch.zeros_like(v) for k, v in self.field.items()}
         self.xi_t = torch.zeros((full.n_cams, 6), dtype=torch.float64, device=device)
         self.dl_t = torch.zeros(full.n_cams, dtype=torch.float64, device=device)
         self.gr = pl.alloc_grads(self.win)
@@ -136,6 +156,29 @@ class Calibrator:
         self._st_ev = [None, None]
         self.overflow_steps = []
         self.replans = 0
+
+    def _init_field(self, full, cfg):
+        """F(X|Theta): tables U(-1e-4, 1e-4), weights uniform(+-sqrt(6 / fan_in)), biases 0 (seeded)."""
+        G, dev = full.n_gauss, full.mean.device
+        g = torch.Generator(device="cpu").manual_seed(cfg.seed + 1)
+        T, L, H = 1 << cfg.field_log2_table, cfg.field_levels, 64
+        D = 2 * L
+
+        def uni(shape, bound):
+            return ((torch.rand(shape, generator=g) * 2 - 1) * bound).to(dev)
+
+        self.field = dict(tables=uni((L, T, 2), 1e-4), w1=uni((H, D), math.sqrt(6.0 / D)), b1=torch.zeros(H, device=dev),
+                          w2=uni((H, H), math.sqrt(6.0 / H)), b2=torch.zeros(H, device=dev),
+                          w3=uni((11, H), math.sqrt(6.0 / H)), b3=torch.zeros(11, device=dev))
+        for t in self.field.values():
+            t.requires_grad_(True)
+        lo = full.mean.min(dim=1).values.double().cpu().numpy() - 1.0
+        hi = full.mean.max(dim=1).values.double().cpu().numpy() + 1.0
+        conf = type("FieldCfg", (), dict(levels=L, feat=2, log2_table=cfg.field_log2_table, n_min=cfg.field_n_min,
+                                         n_max=cfg.field_n_max, hidden=H, scale_max=cfg.field_scale_max))
+        f = self.field
+        self.field_struct = B.ngp_struct(conf, lo, hi, f["tables"], f["w1"], f["b1"], f["w2"], f["b2"], f["w3"],
+                                         f["b3"])
 
     @staticmethod
     def _subscene(full, idx):
@@ -161,12 +204,15 @@ class Calibrator:
         w.intr.copy_(f.intr[idx])
         self.tgt.copy_(self.targets[idx])
         with torch.no_grad():
-            o = torch.sigmoid(self.logit_o)
-            s = torch.exp(self.log_s)
-            w.opacity.copy_(o)
-            w.scale.copy_(s)
-            w.color.copy_(self.color)
-            w.quat.copy_(self.quat)
+            if self.field is None:
+                o = torch.sigmoid(self.logit_o)
+                s = torch.exp(self.log_s)
+                w.opacity.copy_(o)
+                w.scale.copy_(s)
+                w.color.copy_(self.color)
+                w.quat.copy_(self.quat)
+            else:
+                B.splat_ngp_fwd(self.field_struct, w.mean, w.quat, w.scale, w.opacity, w.color)
             self.xi_t[:, :3].copy_(self.rho)
             self.xi_t[:, 3:].copy_(self.phi)
             self.dl_t.copy_(self.delta)
@@ -182,10 +228,19 @@ class Calibrator:
         if cfg.lam_scale > 0:
             B.splat_scale_reg(w.scale, cfg.lam_scale, self.gr.scale, self.loss)
         # activations and the optimiser (torch)
-        self.color.grad = self.gr.color
-        self.logit_o.grad = self.gr.opacity * o * (1 - o)
-        self.log_s.grad = self.gr.scale * s
-        self.quat.grad = self.gr.quat
+        if self.field is None:
+            self.color.grad = self.gr.color
+            self.logit_o.grad = self.gr.opacity * o * (1 - o)
+            self.log_s.grad = self.gr.scale * s
+            self.quat.grad = self.gr.quat
+        else:
+            fg = self.field_grads
+            for t in fg.values():
+                t.zero_()
+            B.splat_ngp_bwd(self.field_struct, w.mean, self.gr.quat, self.gr.scale, self.gr.opacity, self.gr.color,
+                            self.field_ws, fg["tables"], fg["w1"], fg["b1"], fg["w2"], fg["b2"], fg["w3"], fg["b3"])
+            for name, t in self.field.items():
+                t.grad = fg[name]
         frac = 1.0 - (1.0 - cfg.final_lr_frac) * min(1.0, k / max(1, cfg.steps - 1))
         for opt, lrs in zip((self.opt_g, self.opt_c), self.base_lr):
             for grp, lr0 in zip(opt.param_groups, lrs):

@@ -13,7 +13,8 @@
 //
 // Adjoint: the forward is recomputed, the 11 output gradients are pushed back
 // through the heads and the MLP, table gradients are scattered with hardware
-// float atomics (16 levels x 8 vertices x 2 features), and the per-Gaussian
+// float atomics (16 levels x 8 vertices x 2 features) after the lanes of a wave
+// that share a table row have been summed (coarse levels), and the per-Gaussian
 // activations and deltas are stored so that the weight gradients -- sums over all
 // Gaussians of outer products, a tall-skinny A^T B -- are formed by atb_kernel
 // (per-workgroup partials in registers, then a fixed-order reduction).
@@ -39,7 +40,7 @@ struct NgpArgs {
     float scale_max;
 };
 
-__device__ inline uint32_t vertex_row(const NgpArgs &a, int l, uint32_t v0, uint32_t v1, uint32_t v2) {
+__device__ __forceinline__ uint32_t vertex_row(const NgpArgs &a, int l, uint32_t v0, uint32_t v1, uint32_t v2) {
     if (a.dense[l]) {
         uint32_t n = (uint32_t)a.res[l] + 1u;
         return v0 + n * (v1 + n * v2);
@@ -48,7 +49,7 @@ __device__ inline uint32_t vertex_row(const NgpArgs &a, int l, uint32_t v0, uint
 }
 
 // cell and fractions of level l
-__device__ inline void level_cell(const NgpArgs &a, int l, const double *xn, uint32_t *cell, double *fr) {
+__device__ __forceinline__ void level_cell(const NgpArgs &a, int l, const double *xn, uint32_t *cell, double *fr) {
     int N = a.res[l];
     for (int d = 0; d < 3; ++d) {
         double p = xn[d] * (double)N;
@@ -59,37 +60,79 @@ __device__ inline void level_cell(const NgpArgs &a, int l, const double *xn, uin
     }
 }
 
-__device__ inline void normalise(const NgpArgs &a, const float *mean, int64_t n, int64_t i, double *xn) {
+__device__ __forceinline__ void normalise(const NgpArgs &a, const float *mean, int64_t n, int64_t i, double *xn) {
     for (int d = 0; d < 3; ++d) {
         double v = ((double)mean[d * n + i] - a.lo[d]) / a.ext[d];
         xn[d] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
     }
 }
 
-__device__ inline void encode(const NgpArgs &a, const float2 *tables, const double *xn, float *enc) {
+// the two features of level l
+__device__ __forceinline__ void encode_level(const NgpArgs &a, const float2 *tables, const double *xn, int l,
+                                             float &e0, float &e1) {
+    uint32_t cell[3];
+    double fr[3];
+    level_cell(a, l, xn, cell, fr);
+    const float2 *tab = tables + (int64_t)l * a.T;
+    e0 = 0.f;
+    e1 = 0.f;
 #pragma unroll
-    for (int l = 0; l < NL; ++l) {
-        if (l >= a.levels) {
-            enc[2 * l] = enc[2 * l + 1] = 0.f;
-            continue;
-        }
-        uint32_t cell[3];
-        double fr[3];
-        level_cell(a, l, xn, cell, fr);
-        const float2 *tab = tables + (int64_t)l * a.T;
-        float e0 = 0.f, e1 = 0.f;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
-            double w = (cx ? fr[0] : 1.0 - fr[0]) * (cy ? fr[1] : 1.0 - fr[1]) * (cz ? fr[2] : 1.0 - fr[2]);
-            float2 t = tab[vertex_row(a, l, cell[0] + cx, cell[1] + cy, cell[2] + cz)];
-            e0 = __fmaf_rn((float)w, t.x, e0);
-            e1 = __fmaf_rn((float)w, t.y, e1);
-        }
-        enc[2 * l] = e0;
-        enc[2 * l + 1] = e1;
+    for (int c = 0; c < 8; ++c) {
+        int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+        double w = (cx ? fr[0] : 1.0 - fr[0]) * (cy ? fr[1] : 1.0 - fr[1]) * (cz ? fr[2] : 1.0 - fr[2]);
+        float2 t = tab[vertex_row(a, l, cell[0] + cx, cell[1] + cy, cell[2] + cz)];
+        e0 = __fmaf_rn((float)w, t.x, e0);
+        e1 = __fmaf_rn((float)w, t.y, e1);
     }
 }
+
+// wave64 sum with DPP (quad swaps, half-row and row mirrors, row broadcasts); total in lane 63
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float ngp_dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xF, false));
+}
+
+__device__ __forceinline__ float ngp_wave_total(float x) {
+    x += ngp_dpp<0xB1, 0xF>(x);
+    x += ngp_dpp<0x4E, 0xF>(x);
+    x += ngp_dpp<0x141, 0xF>(x);
+    x += ngp_dpp<0x140, 0xF>(x);
+    x += ngp_dpp<0x142, 0xA>(x);
+    x += ngp_dpp<0x143, 0xC>(x);
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+// tab[2r] += a0, tab[2r+1] += a1 for every lane with a non-zero pair (all 64 lanes active,
+// e.g. Gaussians outside every view of the batch carry no gradient).  Lanes that share a
+// row are summed over the wave first, one row at a time while a row is shared by at least two
+// lanes (the coarse levels, where the whole wave often sits in one cell); the rest go
+// straight to the float atomics.
+__device__ __forceinline__ void scatter2(float *tab, uint32_t r, float a0, float a1) {
+    const int lane = __lane_id();
+    uint64_t todo = __ballot(a0 != 0.f || a1 != 0.f);  // Gaussians without a gradient add nothing
+#pragma unroll 1
+    for (int it = 0; it < 8 && todo; ++it) {
+        int leader = __ffsll((long long)todo) - 1;
+        uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)r, leader);
+        bool mine = ((todo >> lane) & 1ull) && r == key;
+        uint64_t peers = __ballot(mine);
+        if (__popcll(peers) < 2) break;
+        float s0 = ngp_wave_total(mine ? a0 : 0.f), s1 = ngp_wave_total(mine ? a1 : 0.f);
+        if (lane == leader) {
+            atomicAdd(tab + 2 * (int64_t)key, s0);
+            atomicAdd(tab + 2 * (int64_t)key + 1, s1);
+        }
+        todo &= ~peers;
+    }
+    if ((todo >> lane) & 1ull) {
+        atomicAdd(tab + 2 * (int64_t)r, a0);
+        atomicAdd(tab + 2 * (int64_t)r + 1, a1);
+    }
+}
+
+// Row layout of the stored activations and deltas (floats per Gaussian).
+enum { R_DOUT = 0, R_H2 = 12, R_DH2 = R_H2 + NH, R_H1 = R_DH2 + NH, R_DH1 = R_H1 + NH, R_ENC = R_DH1 + NH,
+       R_DE = R_ENC + ND, R_LEN = R_DE + ND };
 
 struct Weights {
     float w1[NH][ND], b1[NH], w2[NH][NH], b2[NH], w3[NO][NH], b3[NO];
@@ -110,33 +153,59 @@ __device__ inline void load_weights(Weights &W, const float *w1, const float *b1
     for (int i = threadIdx.x; i < NO; i += blockDim.x) W.b3[i] = b3[i];
 }
 
-__device__ inline void mlp(const Weights &W, const float *enc, float *h1, float *h2, float *o) {
+// Encoding and MLP 2L -> 64 -> 64 -> 11.  Every level's two features go straight into the 64
+// first-layer sums (the level loop stays rolled: its gathers are not all in flight at once),
+// and every second-layer unit straight into the 11 outputs, so one 64-wide vector is live at a
+// time.  With ROW, the encoding, h1 and h2 are also stored to the per-Gaussian row, with the
+// ReLU masks.
+template <bool ROW>
+__device__ __forceinline__ void field(const NgpArgs &a, const float2 *tables, const Weights &W, const double *xn,
+                                      float *o, float *row, uint64_t &m1, uint64_t &m2) {
+    float h1[NH];
+#pragma unroll
+    for (int j = 0; j < NH; ++j) h1[j] = W.b1[j];
+#pragma unroll 1
+    for (int l = 0; l < a.levels; ++l) {
+        float e0, e1;
+        encode_level(a, tables, xn, l, e0, e1);
+        if (ROW) {
+            row[R_ENC + 2 * l] = e0;
+            row[R_ENC + 2 * l + 1] = e1;
+        }
+#pragma unroll
+        for (int j = 0; j < NH; ++j) h1[j] = __fmaf_rn(W.w1[j][2 * l + 1], e1, __fmaf_rn(W.w1[j][2 * l], e0, h1[j]));
+    }
+    if (ROW)
+        for (int l = a.levels; l < NL; ++l) row[R_ENC + 2 * l] = row[R_ENC + 2 * l + 1] = 0.f;
 #pragma unroll
     for (int j = 0; j < NH; ++j) {
-        float s = W.b1[j];
-#pragma unroll
-        for (int i = 0; i < ND; ++i) s = __fmaf_rn(W.w1[j][i], enc[i], s);
+        float s = h1[j];
         h1[j] = s > 0.f ? s : 0.f;
+        if (ROW) {
+            row[R_H1 + j] = h1[j];
+            m1 |= (s > 0.f ? 1ull : 0ull) << j;
+        }
     }
 #pragma unroll
+    for (int k = 0; k < NO; ++k) o[k] = W.b3[k];
+#pragma unroll 2
     for (int j = 0; j < NH; ++j) {
         float s = W.b2[j];
 #pragma unroll
         for (int i = 0; i < NH; ++i) s = __fmaf_rn(W.w2[j][i], h1[i], s);
-        h2[j] = s > 0.f ? s : 0.f;
-    }
+        float h = s > 0.f ? s : 0.f;
+        if (ROW) {
+            row[R_H2 + j] = h;
+            m2 |= (s > 0.f ? 1ull : 0ull) << j;
+        }
 #pragma unroll
-    for (int k = 0; k < NO; ++k) {
-        float s = W.b3[k];
-#pragma unroll
-        for (int i = 0; i < NH; ++i) s = __fmaf_rn(W.w3[k][i], h2[i], s);
-        o[k] = s;
+        for (int k = 0; k < NO; ++k) o[k] = __fmaf_rn(W.w3[k][j], h, o[k]);
     }
 }
 
-__device__ inline float sigm(float x) { return 1.f / (1.f + __expf(-x)); }
+__device__ __forceinline__ float sigm(float x) { return 1.f / (1.f + __expf(-x)); }
 
-__global__ __launch_bounds__(256) void ngp_fwd_kernel(NgpArgs a, const float *mean, int64_t n, const float2 *tables,
+__global__ __launch_bounds__(256, 2) void ngp_fwd_kernel(NgpArgs a, const float *mean, int64_t n, const float2 *tables,
                                                      const float *w1, const float *b1, const float *w2,
                                                      const float *b2, const float *w3, const float *b3,
                                                      float *quat, float *scale, float *opac, float *color) {
@@ -146,9 +215,9 @@ __global__ __launch_bounds__(256) void ngp_fwd_kernel(NgpArgs a, const float *me
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double xn[3];
         normalise(a, mean, n, i, xn);
-        float enc[ND], h1[NH], h2[NH], o[NO];
-        encode(a, tables, xn, enc);
-        mlp(W, enc, h1, h2, o);
+        float o[NO];
+        uint64_t m1 = 0, m2 = 0;
+        field<false>(a, tables, W, xn, o, nullptr, m1, m2);
 #pragma unroll
         for (int c = 0; c < 3; ++c) color[c * n + i] = sigm(o[c]);
         opac[i] = sigm(o[3]);
@@ -160,10 +229,6 @@ __global__ __launch_bounds__(256) void ngp_fwd_kernel(NgpArgs a, const float *me
     }
 }
 
-// Row layout of the stored activations and deltas (floats per Gaussian).
-enum { R_DOUT = 0, R_H2 = 12, R_DH2 = R_H2 + NH, R_H1 = R_DH2 + NH, R_DH1 = R_H1 + NH, R_ENC = R_DH1 + NH,
-       R_LEN = R_ENC + ND };
-
 __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float *mean, int64_t n,
                                                         const float2 *tables, const float *w1, const float *b1,
                                                         const float *w2, const float *b2, const float *w3,
@@ -173,27 +238,19 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
     __shared__ Weights W;
     load_weights(W, w1, b1, w2, b2, w3, b3, 2 * a.levels);
     __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    // every lane runs every iteration (the wave-level combining below needs all 64 lanes);
+    // lanes past the end redo the last Gaussian and add nothing
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i0 = base + threadIdx.x;
+        const bool live = i0 < n;
+        const int64_t i = live ? i0 : n - 1;
         double xn[3];
         normalise(a, mean, n, i, xn);
-        float *row = rows + i * R_LEN;
+        float *row = rows + (live ? i : n) * R_LEN;  // row n: scratch of the lanes past the end
         // forward again; activations go to the row store at once
         float o[NO];
         uint64_t m1 = 0, m2 = 0;  // ReLU masks of the two hidden layers
-        {
-            float enc[ND], h1[NH], h2[NH];
-            encode(a, tables, xn, enc);
-            mlp(W, enc, h1, h2, o);
-#pragma unroll
-            for (int k = 0; k < NH; ++k) {
-                row[R_H2 + k] = h2[k];
-                row[R_H1 + k] = h1[k];
-                m1 |= (h1[k] > 0.f ? 1ull : 0ull) << k;
-                m2 |= (h2[k] > 0.f ? 1ull : 0ull) << k;
-            }
-#pragma unroll
-            for (int k = 0; k < ND; ++k) row[R_ENC + k] = enc[k];
-        }
+        field<true>(a, tables, W, xn, o, row, m1, m2);
         // heads
         float d[NO];
 #pragma unroll
@@ -212,6 +269,9 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) d[7 + c] = dquat[c * n + i];
+        if (!live)
+#pragma unroll
+            for (int k = 0; k < NO; ++k) d[k] = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) row[R_DOUT + k] = k < NO ? d[k] : 0.f;
         // second hidden layer: each delta stored as soon as it is formed
@@ -222,29 +282,32 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
             for (int k = 0; k < NO; ++k) s = __fmaf_rn(W.w3[k][j], d[k], s);
             row[R_DH2 + j] = (m2 >> j) & 1ull ? s : 0.f;
         }
-        // first hidden layer from the stored deltas (this thread's own row, cache resident)
-        float dh1[NH];
+        // first hidden layer from the stored deltas (this thread's own row, cache resident); each
+        // dh1[j] goes straight into the 2L encoding gradients
+        float de[ND];
+#pragma unroll
+        for (int e = 0; e < ND; ++e) de[e] = 0.f;
         {
             float dh2[NH];
 #pragma unroll
             for (int k = 0; k < NH; ++k) dh2[k] = row[R_DH2 + k];
-#pragma unroll
+#pragma unroll 2
             for (int j = 0; j < NH; ++j) {
                 float s = 0.f;
 #pragma unroll
                 for (int k = 0; k < NH; ++k) s = __fmaf_rn(W.w2[k][j], dh2[k], s);
-                dh1[j] = (m1 >> j) & 1ull ? s : 0.f;
-                row[R_DH1 + j] = dh1[j];
+                float dh = (m1 >> j) & 1ull ? s : 0.f;
+                row[R_DH1 + j] = dh;
+#pragma unroll
+                for (int e = 0; e < ND; ++e) de[e] = __fmaf_rn(W.w1[j][e], dh, de[e]);
             }
         }
-        // encoding gradient two features (one level) at a time, then the table adjoint of that level
-        for (int l = 0; l < a.levels; ++l) {
-            float de0 = 0.f, de1 = 0.f;
 #pragma unroll
-            for (int k = 0; k < NH; ++k) {
-                de0 = __fmaf_rn(W.w1[k][2 * l], dh1[k], de0);
-                de1 = __fmaf_rn(W.w1[k][2 * l + 1], dh1[k], de1);
-            }
+        for (int e = 0; e < ND; ++e) row[R_DE + e] = de[e];
+        // table adjoint, level by level
+#pragma unroll 1
+        for (int l = 0; l < a.levels; ++l) {
+            float de0 = row[R_DE + 2 * l], de1 = row[R_DE + 2 * l + 1];
             uint32_t cell[3];
             double fr[3];
             level_cell(a, l, xn, cell, fr);
@@ -254,8 +317,7 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
                 int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
                 float w = (float)((cx ? fr[0] : 1.0 - fr[0]) * (cy ? fr[1] : 1.0 - fr[1]) * (cz ? fr[2] : 1.0 - fr[2]));
                 uint32_t r = vertex_row(a, l, cell[0] + cx, cell[1] + cy, cell[2] + cz);
-                atomicAdd(tab + 2 * (int64_t)r, w * de0);
-                atomicAdd(tab + 2 * (int64_t)r + 1, w * de1);
+                scatter2(tab, r, w * de0, w * de1);
             }
         }
     }
@@ -353,7 +415,7 @@ int ngp_args(const splat_ngp &m, NgpArgs &a) {
 }  // namespace
 
 size_t ngp_ws_bytes(int64_t n) {
-    return (size_t)n * R_LEN * sizeof(float) + (size_t)ATB_GROUPS * (NH * NH + NH) * sizeof(float);
+    return (size_t)(n + 1) * R_LEN * sizeof(float) + (size_t)ATB_GROUPS * (NH * NH + NH) * sizeof(float);  // rows + partials
 }
 
 int launch_ngp_fwd(const splat_ngp &m, const float *mean, int64_t n, float *quat, float *scale, float *opac,
@@ -374,7 +436,7 @@ int launch_ngp_bwd(const splat_ngp &m, const float *mean, int64_t n, const float
     NgpArgs a;
     ngp_args(m, a);
     float *rows = static_cast<float *>(ws);
-    float *partial = rows + (size_t)n * R_LEN;
+    float *partial = rows + (size_t)(n + 1) * R_LEN;
     int64_t nb = (n + 255) / 256;
     if (nb > 8192) nb = 8192;
     hipLaunchKernelGGL(ngp_bwd_kernel, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n,
