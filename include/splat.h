@@ -26,7 +26,9 @@
  *                      grow the capacities and run again),
  *   SPLAT_ST_NONFINITE a Gaussian with a non-finite parameter (culled),
  *   SPLAT_ST_DEGENERATE a Gaussian with |q| < 1e-12 (culled),
- *   SPLAT_ST_EXTRAPOLATED a camera time outside the trajectory (informational).
+ *   SPLAT_ST_EXTRAPOLATED a camera time outside the trajectory (informational),
+ *   SPLAT_ST_RANGE     a point outside the voxel grid (voxel downsampling; the
+ *                      point was clamped into the grid).
  * The library never clears the status word; the caller zeroes it when it wants.
  *
  * Threading.  Re-entrant; no global mutable state except the thread-local
@@ -57,6 +59,7 @@ extern "C" {
 #define SPLAT_ST_NONFINITE 2u
 #define SPLAT_ST_DEGENERATE 4u
 #define SPLAT_ST_EXTRAPOLATED 8u
+#define SPLAT_ST_RANGE 16u
 
 /*
  * Renderer constants.  The paper fixes none of them (it defers the splatting
@@ -335,6 +338,25 @@ SPLAT_API int splat_ngp_bwd(const splat_ngp *m, const float *mean, int64_t n, co
                             const float *dscale, const float *dopacity, const float *dcolor, void *ws,
                             size_t ws_bytes, float *dtables, float *dw1, float *db1, float *dw2, float *db2,
                             float *dw3, float *db3, void *stream);
+
+/*
+ * Voxel downsampling of the accumulated LiDAR cloud (Sec. III-C: one point per
+ * voxel, run per stage of the coarse-to-fine schedule).  Point i (pts[3][n],
+ * float32 device planes x, y, z) lies in the voxel
+ *   v_d = floor((pts[d][i] - lo[d]) / voxel),  d = x, y, z  (float64 arithmetic),
+ * and of every occupied voxel the point with the lowest index is kept.  keep
+ * (device, >= n int32) receives the kept indices ordered by voxel (z, then y,
+ * then x, ascending) and *n_keep (device u32) their number.  Each v_d must lie in
+ * [0, 2^21): choose lo at or below the cloud's minimum and voxel large enough;
+ * a point outside (or a NaN coordinate) is clamped into the grid and
+ * SPLAT_ST_RANGE is OR-ed into *status (device u32).  ws is caller-owned scratch
+ * of at least splat_voxel_workspace_size(n) bytes.  Deterministic.  n = 0 only
+ * zeroes *n_keep.
+ */
+SPLAT_API size_t splat_voxel_workspace_size(int64_t n);
+SPLAT_API int splat_voxel_downsample(const float *pts, int64_t n, const double lo[3], double voxel, void *ws,
+                                     size_t ws_bytes, int32_t *keep, uint32_t *n_keep, uint32_t *status,
+                                     void *stream);
 
 /* Text of the last synchronous error on this thread ("" if none). */
 SPLAT_API const char *splat_last_error(void);

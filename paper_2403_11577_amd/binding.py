@@ -95,6 +95,9 @@ def lib():
     L.splat_ngp_workspace_size.argtypes = [I64]
     L.splat_ngp_workspace_size.restype = C.c_size_t
     L.splat_ngp_bwd.argtypes = [C.POINTER(splat_ngp), P, I64, P, P, P, P, P, C.c_size_t, P, P, P, P, P, P, P, P]
+    L.splat_voxel_workspace_size.argtypes = [I64]
+    L.splat_voxel_workspace_size.restype = C.c_size_t
+    L.splat_voxel_downsample.argtypes = [P, I64, C.POINTER(C.c_double), C.c_double, P, C.c_size_t, P, P, P, P]
     for w, st in ((0, splat_settings), (1, splat_gaussians), (2, splat_plan), (3, splat_ngp)):
         if L.splat_struct_size(w) != C.sizeof(st):
             raise SplatError(f"ABI mismatch: {st.__name__} is {L.splat_struct_size(w)} bytes in the "
@@ -245,3 +248,15 @@ def splat_ngp_bwd(model: splat_ngp, mean, dquat, dscale, dopacity, dcolor, ws, d
                                _ptr(dopacity), _ptr(dcolor), _ptr(ws), int(ws.numel() * ws.element_size()),
                                _ptr(dtables), _ptr(dw1), _ptr(db1), _ptr(dw2), _ptr(db2), _ptr(dw3), _ptr(db3),
                                _stream(stream)), "splat_ngp_bwd")
+
+
+def splat_voxel_workspace_size(n) -> int:
+    return int(lib().splat_voxel_workspace_size(int(n)))
+
+
+def splat_voxel_downsample(pts, lo, voxel, ws, keep, n_keep, status, stream=None):
+    """pts [3, n] float32 device; keep int32 [>= n]; n_keep, status uint32 device scalars."""
+    lo3 = (C.c_double * 3)(*[float(v) for v in lo])
+    _check(lib().splat_voxel_downsample(_ptr(pts), int(pts.shape[1]), lo3, float(voxel), _ptr(ws),
+                                        int(ws.numel() * ws.element_size()), _ptr(keep), _ptr(n_keep),
+                                        _ptr(status), _stream(stream)), "splat_voxel_downsample")

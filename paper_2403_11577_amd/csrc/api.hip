@@ -411,4 +411,25 @@ int splat_ngp_bwd(const splat_ngp *m, const float *mean, int64_t n, const float 
                           (hipStream_t)stream);
 }
 
+size_t splat_voxel_workspace_size(int64_t n) { return n < 0 ? 0 : voxel_ws_bytes(n); }
+
+int splat_voxel_downsample(const float *pts, int64_t n, const double *lo, double voxel, void *ws, size_t ws_bytes,
+                           int32_t *keep, uint32_t *n_keep, uint32_t *status, void *stream) {
+    g_err[0] = 0;
+    if (n < 0 || n >= ((int64_t)1 << 31)) { set_error("voxel_downsample: n outside [0, 2^31)"); return SPLAT_EINVAL; }
+    if (!lo || !n_keep) { set_error("voxel_downsample: NULL argument"); return SPLAT_EINVAL; }
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(lo[d])) { set_error("voxel_downsample: lo must be finite"); return SPLAT_EINVAL; }
+    if (!(voxel > 0.0) || !std::isfinite(voxel)) {
+        set_error("voxel_downsample: voxel size must be finite and > 0"); return SPLAT_EINVAL;
+    }
+    if (n == 0) return launch_fill_u32(n_keep, 0u, 1, (hipStream_t)stream);
+    if (!pts || !ws || !keep || !status) { set_error("voxel_downsample: NULL argument"); return SPLAT_EINVAL; }
+    size_t need = voxel_ws_bytes(n);
+    if (ws_bytes < need) {
+        set_error("voxel_downsample: workspace of %zu bytes, %zu needed", ws_bytes, need); return SPLAT_EINVAL;
+    }
+    return launch_voxel_downsample(pts, n, lo, voxel, ws, keep, n_keep, status, (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -475,6 +475,28 @@ int launch_scan_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, in
     return launch_status("scan_down");
 }
 
+int launch_radix_sort_u64(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, const uint32_t *counts, int bits,
+                          int nparts, uint32_t *hist, uint32_t *partials, hipStream_t st, int *sorted_in_1) {
+    int passes = (bits + kRadixBits - 1) / kRadixBits;
+    uint64_t *ki = k0, *ko = k1;
+    uint32_t *vi = v0, *vo = v1;
+    int nh = kRadixDigits * nparts;
+    int rc = 0;
+    for (int ps = 0; ps < passes; ++ps) {
+        int shift = kRadixBits * ps;
+        hipLaunchKernelGGL(radix_upsweep_kernel, dim3(nparts), dim3(RS_T), 0, st, ki, counts, shift, nparts, hist);
+        if ((rc = launch_status("radix_upsweep"))) return rc;
+        if ((rc = launch_scan_u32(hist, hist, nullptr, nh, partials, nullptr, st))) return rc;
+        hipLaunchKernelGGL(radix_downsweep_kernel, dim3(nparts), dim3(RS_T), 0, st, ki, vi, ko, vo, counts, shift,
+                           nparts, hist);
+        if ((rc = launch_status("radix_downsweep"))) return rc;
+        uint64_t *tk = ki; ki = ko; ko = tk;
+        uint32_t *tv = vi; vi = vo; vo = tv;
+    }
+    *sorted_in_1 = passes & 1;
+    return 0;
+}
+
 int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
     uint32_t *status = ws_at<uint32_t>(ws, p.off_status);
     uint32_t *counts = ws_at<uint32_t>(ws, p.off_counts);
@@ -503,24 +525,11 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
     if ((rc = launch_status("emit"))) return rc;
 
     // LSD radix sort over the used key bits
-    int bits = p.depth_bits + p.tile_bits;
-    int passes = (bits + kRadixBits - 1) / kRadixBits;
-    uint64_t *ki = keys0, *ko = keys1;
-    uint32_t *vi = vals0, *vo = vals1;
-    int nh = kRadixDigits * p.n_sort_blocks;
-    for (int ps = 0; ps < passes; ++ps) {
-        int shift = kRadixBits * ps;
-        hipLaunchKernelGGL(radix_upsweep_kernel, dim3(p.n_sort_blocks), dim3(RS_T), 0, st, ki, counts, shift,
-                           p.n_sort_blocks, hist);
-        if ((rc = launch_status("radix_upsweep"))) return rc;
-        rc = launch_scan_u32(hist, hist, nullptr, nh, partials, nullptr, st);
-        if (rc) return rc;
-        hipLaunchKernelGGL(radix_downsweep_kernel, dim3(p.n_sort_blocks), dim3(RS_T), 0, st, ki, vi, ko, vo, counts,
-                           shift, p.n_sort_blocks, hist);
-        if ((rc = launch_status("radix_downsweep"))) return rc;
-        uint64_t *tk = ki; ki = ko; ko = tk;
-        uint32_t *tv = vi; vi = vo; vo = tv;
-    }
+    int in1 = 0;
+    rc = launch_radix_sort_u64(keys0, keys1, vals0, vals1, counts, p.depth_bits + p.tile_bits, p.n_sort_blocks, hist,
+                               partials, st, &in1);
+    if (rc) return rc;
+    const uint64_t *ki = in1 ? keys1 : keys0;
     // ranges of every (view, tile) and the cost-ordered queue
     if ((rc = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, (int64_t)2 * nT, st))) return rc;
     int rb = (int)((p.inst_cap + 255) / 256);

@@ -32,7 +32,7 @@ import numpy as np
 __all__ = [
     "Gaussians", "Trajectory", "Rig", "Views", "Scene",
     "tiny_scene", "tiny_target", "kitti_single", "calib16", "batched64",
-    "calib_full", "small_drive", "random_rigid", "perturbation",
+    "calib_full", "small_drive", "drive_scans", "random_rigid", "perturbation",
     "quat_from_euler", "WORKLOADS",
 ]
 
@@ -43,6 +43,7 @@ WORKLOADS = {
     "calib16": "calib_2cam_8frame_500k_1408x376",
     "batched64": "batched_uneven_64v_2M_1408x376",
     "calib_full": "calib_loop_2cam_100frame_2M_1408x376",
+    "drive_scans": "lidar_accumulated_40scan",
 }
 
 
@@ -570,11 +571,10 @@ def _density(s):
     return 1.0
 
 
-def _drive_world(seed, n_points, scan_every=5.0, voxel=0.05, n_boxes=700):
+def _drive_boxes(rng, n_boxes):
+    """Boxes along the route, off every street; also the road samples and their tree."""
     from scipy.spatial import cKDTree
-    rng = np.random.default_rng(seed)
     pos = _drive_path()
-    traj = _drive_trajectory()
     # road centre line samples: boxes must stay off every street of the route
     s_samp = np.arange(-40.0, 341.0, 1.0)
     road = np.array([pos(s)[0] for s in s_samp])
@@ -587,6 +587,27 @@ def _drive_world(seed, n_points, scan_every=5.0, voxel=0.05, n_boxes=700):
             boxes.append(b)
         if len(boxes) == n_boxes:
             break
+    return boxes, s_samp, road_tree
+
+
+def drive_scans(seed=0, n_scans=40, n_boxes=700):
+    """The accumulated LiDAR cloud of a drive before any downsampling: n_scans
+    64-ring scans spread evenly over the 30 s route (the paper accumulates the
+    scans of its 40-frame sequences, Sec. IV-A), world frame, float32 [3, n],
+    scans in time order.  About 0.1 M returns per scan."""
+    rng = np.random.default_rng(seed)
+    traj = _drive_trajectory()
+    boxes, _, _ = _drive_boxes(rng, n_boxes)
+    dirs = _ray_dirs_lidar()
+    ks = np.linspace(0, len(traj.t) - 1, n_scans).round().astype(int)
+    clouds = [_cast(traj.p[k], _quat_to_mat(traj.q[k]), boxes, dirs) for k in ks]
+    return np.ascontiguousarray(np.concatenate(clouds).T.astype(np.float32))
+
+
+def _drive_world(seed, n_points, scan_every=5.0, voxel=0.05, n_boxes=700):
+    rng = np.random.default_rng(seed)
+    traj = _drive_trajectory()
+    boxes, s_samp, road_tree = _drive_boxes(rng, n_boxes)
     dirs = _ray_dirs_lidar()
     clouds = []
     step = int(round(scan_every / (10.0 * 0.1)))

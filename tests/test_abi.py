@@ -141,3 +141,23 @@ def test_dssim_workspace_and_argument_checks_without_a_device():
     assert L.splat_dssim_workspace_size(2, 10, 8, 8) == 0
     assert L.splat_dssim_loss_grad(None, None, 1, 4, 4, 0, 0.2, None, 0, None, None, None) == -1
     assert b"NULL" in L.splat_last_error()
+
+
+def test_voxel_downsample_argument_checks_without_a_device():
+    L = B.lib()
+    lo = (C.c_double * 3)(0.0, 0.0, 0.0)
+    assert L.splat_voxel_workspace_size(-1) == 0
+    assert L.splat_voxel_workspace_size(1000) >= 1000 * (16 + 8 + 4)  # two key, value and flag buffers
+    assert L.splat_voxel_downsample(None, 10, lo, 0.1, None, 0, None, None, None, None) == -1
+    assert b"NULL" in L.splat_last_error()
+    n_keep = C.c_void_p(16)
+    for voxel in (0.0, -1.0, float("inf"), float("nan")):
+        assert L.splat_voxel_downsample(C.c_void_p(16), 10, lo, voxel, C.c_void_p(16), 1 << 20, C.c_void_p(16),
+                                        n_keep, C.c_void_p(16), None) == -1
+    assert b"voxel size" in L.splat_last_error()
+    assert L.splat_voxel_downsample(C.c_void_p(16), 10, lo, 0.1, C.c_void_p(16), 8, C.c_void_p(16), n_keep,
+                                    C.c_void_p(16), None) == -1
+    assert b"workspace" in L.splat_last_error()
+    bad = (C.c_double * 3)(0.0, float("nan"), 0.0)
+    assert L.splat_voxel_downsample(C.c_void_p(16), 10, bad, 0.1, C.c_void_p(16), 1 << 20, C.c_void_p(16), n_keep,
+                                    C.c_void_p(16), None) == -1
