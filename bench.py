@@ -59,6 +59,98 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _event_ms(fn, reps):
+    """Mean device time of fn() over reps calls (HIP events on the current stream)."""
+    import torch
+    fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def measure_beyond_render(ds, settings, targets, img, reps=10):
+    """The paper's other per-step stages on the same 64-view, 2 M-Gaussian workload:
+    the bottom-half region of interest, D-SSIM, the hash-grid field F(X|Theta) and
+    the voxel downsampling of an accumulated drive cloud."""
+    import math
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2403_11577_amd import binding as B
+    from paper_2403_11577_amd import pipeline as pl
+
+    V, W, H, G, dev = ds.n_views, ds.W, ds.H, ds.n_gauss, "cuda"
+    xi = torch.zeros((ds.n_cams, 6), dtype=torch.float64, device=dev)
+    dl = torch.zeros(ds.n_cams, dtype=torch.float64, device=dev)
+    out = {}
+    # region of interest: only the bottom half of every image is binned, rendered and scored
+    roi = H // 2
+    rs = pl.make_settings(tile=(settings.tile_w, settings.tile_h), batch=settings.batch,
+                          persistent=bool(settings.persistent), roi_y0=roi)
+    st = pl.BatchedStep(ds, xi, dl, targets, rs)
+    ms = _event_ms(st.run, reps)
+    out["roi"] = {"roi_y0": roi, "ms_per_step": round(ms, 3),
+                  "mpx_s": round(V * W * (H - roi) / (ms * 1e-3) / 1e6, 2)}
+    log(f"[bench] ROI step: {ms:.3f} ms")
+    del st
+    torch.cuda.empty_cache()
+    # D-SSIM over the region of interest (forward moments + adjoint filter)
+    ws = torch.empty(B.splat_dssim_workspace_size(V, W, H, roi), dtype=torch.uint8, device=dev)
+    dimg = torch.zeros_like(img)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    ms = _event_ms(lambda: B.splat_dssim_loss_grad(img, targets, ws, dimg, loss, roi, 0.2), reps)
+    px = V * 3 * (H - roi) * W
+    out["dssim"] = {"ms": round(ms, 4), "pixels": px, "bytes_alg": 48 * px,
+                    "gbps": round(48 * px / (ms * 1e-3) / 1e9, 1)}
+    log(f"[bench] D-SSIM: {ms:.4f} ms")
+    del ws, dimg
+    # hash-grid field: parameters of every Gaussian, and the adjoint
+    cfg = type("FieldCfg", (), dict(levels=16, feat=2, log2_table=19, n_min=16, n_max=4096, hidden=64,
+                                    scale_max=0.05))
+    g = torch.Generator(device="cpu").manual_seed(3)
+    uni = lambda shape, b: ((torch.rand(shape, generator=g) * 2 - 1) * b).to(dev)
+    f = dict(tables=uni((16, 1 << 19, 2), 0.5), w1=uni((64, 32), math.sqrt(6 / 32)), b1=uni((64,), 0.1),
+             w2=uni((64, 64), math.sqrt(6 / 64)), b2=uni((64,), 0.1), w3=uni((11, 64), math.sqrt(6 / 64)),
+             b3=uni((11,), 0.5))
+    lo = ds.mean.min(dim=1).values.double().cpu().numpy() - 1.0
+    hi = ds.mean.max(dim=1).values.double().cpu().numpy() + 1.0
+    m = B.ngp_struct(cfg, lo, hi, f["tables"], f["w1"], f["b1"], f["w2"], f["b2"], f["w3"], f["b3"])
+    q, sc, op, co = (torch.empty(r, G, device=dev) for r in (4, 3, 1, 3))
+    op = op[0]
+    fwd_ms = _event_ms(lambda: B.splat_ngp_fwd(m, ds.mean, q, sc, op, co), reps)
+    d = {k: torch.randn(v.shape, generator=g).to(dev) * 1e-3 for k, v in (("q", q), ("s", sc), ("o", op), ("c", co))}
+    fws = torch.empty(B.splat_ngp_workspace_size(G), dtype=torch.uint8, device=dev)
+    gf = {k: torch.zeros_like(v) for k, v in f.items()}
+    bwd_ms = _event_ms(lambda: B.splat_ngp_bwd(m, ds.mean, d["q"], d["s"], d["o"], d["c"], fws, gf["tables"],
+                                               gf["w1"], gf["b1"], gf["w2"], gf["b2"], gf["w3"], gf["b3"]), 3)
+    out["field"] = {"gaussians": G, "fwd_ms": round(fwd_ms, 3), "bwd_ms": round(bwd_ms, 3),
+                    "fwd_mgauss_s": round(G / (fwd_ms * 1e-3) / 1e6, 1)}
+    log(f"[bench] field: fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms")
+    del f, gf, fws, d, q, sc, op, co
+    torch.cuda.empty_cache()
+    # voxel downsampling of a 40-scan accumulated drive cloud at the schedule's three sizes
+    pts = torch.as_tensor(synth.drive_scans(seed=0), device=dev)
+    n = int(pts.shape[1])
+    lo3 = pts.min(dim=1).values.double().cpu().tolist()
+    vws = torch.empty(B.splat_voxel_workspace_size(n), dtype=torch.uint8, device=dev)
+    keep = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(2, dtype=torch.int32, device=dev)
+    stages = []
+    for v in (0.10, 0.05, 0.02):
+        ms = _event_ms(lambda: B.splat_voxel_downsample(pts, lo3, v, vws, keep, cnt[0:1], cnt[1:2]), reps)
+        stages.append({"voxel_m": v, "kept": int(cnt[0].item()), "ms": round(ms, 3),
+                       "mpts_s": round(n / (ms * 1e-3) / 1e6, 1)})
+    out["voxel"] = {"points": n, "stages": stages}
+    log(f"[bench] voxel downsampling of {n} points: {stages}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +167,9 @@ def main():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (calibrates HBM byte counters)")
     ap.add_argument("--no-autotune", action="store_true", help="use --tile instead of the autotuner")
+    ap.add_argument("--no-beyond", action="store_true", help="skip the ROI / D-SSIM / field / voxel timings")
+    ap.add_argument("--c2f-steps", type=int, default=600,
+                    help="steps of the coarse-to-fine field calibration (10/5/2 cm in the ratio 4:1:1); 0 skips it")
     ap.add_argument("--calib-steps", type=int, default=3000,
                     help="steps of the calibration loop (2 cameras x 100 frames, 16 views per step); 0 skips it")
     args = ap.parse_args()
@@ -234,14 +329,38 @@ def main():
                                            f"fwd+bwd, {W}x{H}, {tcpu:.1f}s"}
         log(f"[bench] cpu oracle: {tcpu:.1f}s for one view")
 
+    beyond = None
+    if not args.no_beyond and not args.small:
+        beyond = measure_beyond_render(ds, settings, targets, step.fr.img)
+
     # ---- the calibration loop: 2 cameras x 100 frames in the same kind of world, 16 views per step ----
     calib = None
-    if args.calib_steps > 0 and not args.small:
+    c2f = None
+    if (args.calib_steps > 0 or args.c2f_steps > 0) and not args.small:
         del step
         torch.cuda.empty_cache()
         from paper_2403_11577_amd import calib as cb
         tc = time.time()
         cscene = synth.calib_full(seed=0)
+    if args.c2f_steps > 0 and not args.small:
+        # the paper's method: field F(X|Theta), Gaussians re-anchored at 10 / 5 / 2 cm voxels of the
+        # accumulated LiDAR cloud of the same drive, scales bounded by the voxel size
+        n1 = args.c2f_steps * 4 // 6
+        n2 = (args.c2f_steps - n1) // 2
+        stages = ((0.10, n1), (0.05, n2), (0.02, args.c2f_steps - n1 - n2))
+        cloud = torch.as_tensor(synth.drive_scans(seed=0, t0=4.0, t1=20.0), device=dev)
+        cal = cb.Calibrator(cscene, cb.CalibConfig(model="field", stages=stages, warmup=min(500, n1 // 4)),
+                            settings=settings, cloud=cloud)
+        res = cal.run(log_every=max(1, args.c2f_steps // 6), log=log)
+        c2f = {"cloud_points": int(cloud.shape[1]), "stages": res["stages"],
+               "steps_per_s": round(res["steps_per_s"], 2), "views_per_step": 16,
+               "final": {k: [round(x, 4) for x in res[k]] for k in ("rotation_deg", "translation_cm",
+                                                                   "time_offset_ms")},
+               "loss": round(res["loss"], 6)}
+        log(f"[bench] coarse-to-fine: {c2f['stages']}")
+        del cal, cloud
+        torch.cuda.empty_cache()
+    if args.calib_steps > 0 and not args.small:
         cal = cb.Calibrator(cscene, cb.CalibConfig(steps=args.calib_steps, warmup=min(500, args.calib_steps // 6)),
                             settings=settings)
         log(f"[bench] calibration setup {time.time() - tc:.1f}s; init rot "
@@ -280,6 +399,8 @@ def main():
         "cpu_baseline": cpu,
         "autotune": tune,
         "calibration": calib,
+        "beyond_render": beyond,
+        "coarse_to_fine": c2f,
     }
     print(json.dumps(out), flush=True)
 

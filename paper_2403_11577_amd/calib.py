@@ -13,6 +13,11 @@ Learning rates of the Gaussian parameters are not given in the paper; those of
 the original 3DGS implementation are used.  As in Sec. III-C, only the bottom
 rows of every image are rendered and enter the loss (roi_frac); the photometric
 loss is Eq. (4), 0.8 L1 + 0.2 D-SSIM, and L_scale (lambda_2 = 1e-3) is added.
+
+With the field model F(X|Theta) the Gaussians can follow the coarse-to-fine
+schedule of Sec. III-C and IV-B: each stage re-anchors them at one point per
+voxel of the accumulated cloud (10, 5, then 2 cm) and bounds their scales by the
+voxel size; the field, its optimiser state and the calibration carry over.
 """
 from __future__ import annotations
 
@@ -25,6 +30,11 @@ import torch
 
 from . import binding as B
 from . import pipeline as pl
+
+
+# coarse-to-fine schedules of Sec. IV-B: (voxel size in metres, steps)
+PAPER_STAGES = ((0.10, 4000), (0.05, 1000), (0.02, 1000))
+PAPER_STAGES_LIDAR_CAMERA = ((0.10, 2000), (0.05, 500), (0.02, 500))
 
 
 @dataclasses.dataclass
@@ -61,6 +71,9 @@ class CalibConfig:
     lr_field_table: float = 1e-2
     lr_field_mlp: float = 1e-3
     field_weight_decay: float = 1e-4   # on the hash grid (Sec. IV-B)
+    # coarse-to-fine voxelisation (field model): ((voxel_m, steps), ...); steps is then their sum.
+    # () keeps the scene's own points for the whole run.
+    stages: tuple = ()
 
 
 def rotation_error_deg(xi):
@@ -71,8 +84,14 @@ def rotation_error_deg(xi):
 class Calibrator:
     """Optimises Gaussians, extrinsic corrections xi = (rho, phi) and time offsets delta."""
 
-    def __init__(self, scene, cfg: CalibConfig = None, settings=None, device="cuda"):
+    def __init__(self, scene, cfg: CalibConfig = None, settings=None, device="cuda", cloud=None):
+        """cloud: the accumulated LiDAR points [3, n] (device float32) the stages downsample;
+        defaults to the scene's Gaussian means."""
         self.cfg = cfg = cfg or CalibConfig()
+        if cfg.stages:
+            if cfg.model != "field":
+                raise ValueError("the coarse-to-fine stages need the field model (model='field')")
+            cfg = self.cfg = dataclasses.replace(cfg, steps=int(sum(int(n) for _, n in cfg.stages)))
         self.scene = scene
         self.device = device
         full = pl.DeviceScene.from_scene(scene, device=device)
@@ -95,12 +114,13 @@ class Calibrator:
             counts.append(fr.counts())
             del fr
         # capacity: the largest batch seen, with a wide margin for footprints that grow in training
-        ns = max(c[0] for c in counts)
-        ni = max(c[1] for c in counts)
-        self.win = self._subscene(full, torch.arange(Bv, device=device) % V)
-        self.slot_cap = int(min(Bv * G, ns * 2 + 1024))
-        self.inst_cap = int(min((1 << 31) - 1, ni * 3 + 4096))
-        self.fr = pl.Frame(self.settings, Bv, G, full.W, full.H, self.slot_cap, self.inst_cap, device)
+        self._ns = max(c[0] for c in counts)
+        self._ni = max(c[1] for c in counts)
+        self.cloud = full.mean if cloud is None else cloud
+        self.stage_starts = np.cumsum([0] + [int(n) for _, n in cfg.stages])[:-1].tolist()
+        self.stage = -1
+        self.stage_log = []
+        self._set_points(full.mean)
         self.tgt = torch.empty((Bv, 3, full.H, full.W), dtype=torch.float32, device=device)
         # parameters (raw) and their activations
         if cfg.gauss_init == "scene":
@@ -140,12 +160,9 @@ class Calibrator:
         ], eps=1e-15)
         self.base_lr = [[grp["lr"] for grp in o.param_groups] for o in (self.opt_g, self.opt_c)]
         if self.field is not None:
-            self.field_ws = torch.empty(B.splat_ngp_workspace_size(G), dtype=torch.uint8, device=device)
             self.field_grads = {k: torch.zeros_like(v) for k, v in self.field.items()}
         self.xi_t = torch.zeros((full.n_cams, 6), dtype=torch.float64, device=device)
         self.dl_t = torch.zeros(full.n_cams, dtype=torch.float64, device=device)
-        self.gr = pl.alloc_grads(self.win)
-        self.dimg = torch.empty_like(self.fr.img)
         self.loss = torch.zeros(1, dtype=torch.float64, device=device)
         self.ssim_ws = torch.empty(B.splat_dssim_workspace_size(Bv, full.W, full.H, self.settings.roi_y0),
                                    dtype=torch.uint8, device=device)
@@ -172,13 +189,62 @@ class Calibrator:
                           w3=uni((11, H), math.sqrt(6.0 / H)), b3=torch.zeros(11, device=dev))
         for t in self.field.values():
             t.requires_grad_(True)
-        lo = full.mean.min(dim=1).values.double().cpu().numpy() - 1.0
-        hi = full.mean.max(dim=1).values.double().cpu().numpy() + 1.0
-        conf = type("FieldCfg", (), dict(levels=L, feat=2, log2_table=cfg.field_log2_table, n_min=cfg.field_n_min,
-                                         n_max=cfg.field_n_max, hidden=H, scale_max=cfg.field_scale_max))
-        f = self.field
+        lo = self.cloud.min(dim=1).values.double().cpu().numpy() - 1.0
+        hi = self.cloud.max(dim=1).values.double().cpu().numpy() + 1.0
+        self._field_box = (lo, hi)
+        self._set_scale_max(cfg.field_scale_max)
+
+    def _set_scale_max(self, scale_max):
+        cfg, f = self.cfg, self.field
+        conf = type("FieldCfg", (), dict(levels=cfg.field_levels, feat=2, log2_table=cfg.field_log2_table,
+                                         n_min=cfg.field_n_min, n_max=cfg.field_n_max, hidden=64,
+                                         scale_max=float(scale_max)))
+        lo, hi = self._field_box
         self.field_struct = B.ngp_struct(conf, lo, hi, f["tables"], f["w1"], f["b1"], f["w2"], f["b2"], f["w3"],
                                          f["b3"])
+
+    def _set_points(self, mean):
+        """Anchor the Gaussians at mean [3, G] (window scene, plan, gradients, scratch)."""
+        full, Bv, dev = self.full, self.cfg.batch_views, self.device
+        G = int(mean.shape[1])
+        z = lambda *s: torch.zeros(s, dtype=torch.float32, device=dev)
+        idx = torch.arange(Bv, device=dev) % full.n_views
+        self.win = pl.DeviceScene(mean, z(4, G), z(3, G), z(G), z(3, G), full.knot_t, full.knot_q, full.knot_p,
+                                  full.R0, full.t0, full.view_cam[idx].contiguous(), full.view_t[idx].contiguous(),
+                                  full.intr[idx].contiguous(), full.W, full.H)
+        # slots scale with the number of Gaussians; instances per slot as in the targets
+        r = G / max(1, full.n_gauss)
+        self.slot_cap = int(min(Bv * G, self._ns * 2 * r + 1024))
+        self.inst_cap = int(min((1 << 31) - 1, self._ni * 3 * r + 4096))
+        self.fr = pl.Frame(self.settings, Bv, G, full.W, full.H, self.slot_cap, self.inst_cap, dev)
+        self.gr = pl.alloc_grads(self.win)
+        self.dimg = torch.empty_like(self.fr.img)
+        if self.cfg.model == "field":
+            self.field_ws = torch.empty(B.splat_ngp_workspace_size(G), dtype=torch.uint8, device=dev)
+
+    def _enter_stage(self, i):
+        """Stage i of the coarse-to-fine schedule: one point per voxel of the cloud, scales below the voxel."""
+        voxel, n = self.cfg.stages[i]
+        self._close_stage()
+        t0 = time.perf_counter()
+        keep = pl.voxel_downsample(self.cloud, float(voxel))
+        mean = self.cloud[:, keep].contiguous()
+        self._set_points(mean)
+        self._set_scale_max(voxel)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        self.stage = i
+        self.stage_log.append(dict(voxel_m=float(voxel), steps=int(n), gaussians=int(mean.shape[1]),
+                                   setup_ms=round((t1 - t0) * 1e3, 2), done=0, _t0=t1))
+
+    def _close_stage(self):
+        """Wall time and step rate of the running stage (synchronises)."""
+        if self.stage_log and "_t0" in self.stage_log[-1]:
+            torch.cuda.synchronize()
+            e = self.stage_log[-1]
+            sec = time.perf_counter() - e.pop("_t0")
+            e["seconds"] = round(sec, 3)
+            e["steps_per_s"] = round(e["done"] / sec, 2) if sec > 0 else None
 
     @staticmethod
     def _subscene(full, idx):
@@ -196,7 +262,12 @@ class Calibrator:
 
     def step(self, k: int):
         cfg = self.cfg
+        if cfg.stages and self.stage + 1 < len(cfg.stages) and k >= self.stage_starts[self.stage + 1]:
+            self._drain_status()
+            self._enter_stage(self.stage + 1)
         self._poll(k)
+        if self.stage_log:
+            self.stage_log[-1]["done"] += 1
         idx = self._next_views()
         w, f = self.win, self.full
         w.view_cam.copy_(f.view_cam[idx])
@@ -274,10 +345,19 @@ class Calibrator:
         e.record()
         self._st_ev[j] = e
 
+    def _drain_status(self):
+        """Read the pending status words (before the plan they belong to is replaced)."""
+        for j in (0, 1):
+            ev, self._st_ev[j] = self._st_ev[j], None
+            if ev is not None:
+                ev.synchronize()
+                if int(self._st_host[j, 0]) & B.ST_CAPACITY:
+                    self.overflow_steps.append(-1)
+
     def _grow(self):
         """Re-plan with twice the capacities after a step whose instances or slots overflowed."""
         ns, ni = self.fr.counts()
-        G, Bv = self.full.n_gauss, self.cfg.batch_views
+        G, Bv = self.win.n_gauss, self.cfg.batch_views
         self.slot_cap = int(min(Bv * G, max(self.slot_cap, 2 * ns)))
         self.inst_cap = int(min((1 << 31) - 1, 2 * max(self.inst_cap, ni)))
         self.fr = pl.Frame(self.settings, Bv, G, self.full.W, self.full.H, self.slot_cap, self.inst_cap,
@@ -306,11 +386,12 @@ class Calibrator:
                     f"trans_cm {np.round(e['translation_cm'], 2)} dt_ms {np.round(e['time_offset_ms'], 2)}")
         torch.cuda.synchronize()
         sps = (steps - 10) / (time.perf_counter() - t0) if steps > 10 and t0 else float("nan")
+        self._close_stage()
         for k in range(max(0, steps - 2), steps):
             j = k & 1
             if self._st_ev[j] is not None and int(self._st_host[j, 0]) & B.ST_CAPACITY:
                 self.overflow_steps.append(k)
             self._st_ev[j] = None
         out = dict(steps=steps, steps_per_s=sps, loss=float(self.loss.item()), replans=self.replans,
-                   overflow_steps=len(self.overflow_steps), **self.errors())
+                   overflow_steps=len(self.overflow_steps), stages=self.stage_log, **self.errors())
         return out

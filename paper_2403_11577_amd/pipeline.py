@@ -407,3 +407,22 @@ class SplatRender(torch.autograd.Function):
         g = ds.gaussians(quat, scale, opacity, color)
         backward(fr, ds, xi, delta, dimg.contiguous(), gr, gauss=g)
         return gr.quat, gr.scale, gr.opacity, gr.color, gr.xi, gr.delta, None, None
+
+
+def voxel_downsample(pts: torch.Tensor, voxel: float, lo=None, ws=None):
+    """Indices (int64, device) of one point per voxel of pts [3, n] (the lowest index,
+    in voxel order); lo defaults to the cloud's minimum.  Synchronises once to read
+    the count.  Raises if a point fell outside the voxel grid."""
+    n = int(pts.shape[1])
+    if lo is None:
+        lo = pts.min(dim=1).values.double().cpu().tolist() if n else [0.0, 0.0, 0.0]
+    need = B.splat_voxel_workspace_size(n)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=pts.device)
+    keep = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
+    cnt = torch.zeros(2, dtype=torch.int32, device=pts.device)   # n_keep, status
+    B.splat_voxel_downsample(pts, lo, voxel, ws, keep, cnt[0:1], cnt[1:2])
+    m, st = cnt.cpu().tolist()
+    if st & B.ST_RANGE:
+        raise B.SplatError(f"voxel_downsample: points outside the {voxel} m grid from {lo}")
+    return keep[:m].long()

@@ -590,16 +590,18 @@ def _drive_boxes(rng, n_boxes):
     return boxes, s_samp, road_tree
 
 
-def drive_scans(seed=0, n_scans=40, n_boxes=700):
+def drive_scans(seed=0, n_scans=40, n_boxes=700, t0=0.0, t1=None):
     """The accumulated LiDAR cloud of a drive before any downsampling: n_scans
-    64-ring scans spread evenly over the 30 s route (the paper accumulates the
-    scans of its 40-frame sequences, Sec. IV-A), world frame, float32 [3, n],
-    scans in time order.  About 0.1 M returns per scan."""
+    64-ring scans spread evenly over [t0, t1] seconds of the 30 s route (the paper
+    accumulates the scans of its 40-frame sequences, Sec. IV-A), world frame,
+    float32 [3, n], scans in time order.  About 0.1 M returns per scan.  The world
+    (boxes) is that of the drive scenes with the same seed."""
     rng = np.random.default_rng(seed)
     traj = _drive_trajectory()
     boxes, _, _ = _drive_boxes(rng, n_boxes)
     dirs = _ray_dirs_lidar()
-    ks = np.linspace(0, len(traj.t) - 1, n_scans).round().astype(int)
+    t1 = traj.t[-1] if t1 is None else t1
+    ks = np.unique(np.searchsorted(traj.t, np.linspace(t0, t1, n_scans) - 1e-9).clip(0, len(traj.t) - 1))
     clouds = [_cast(traj.p[k], _quat_to_mat(traj.q[k]), boxes, dirs) for k in ks]
     return np.ascontiguousarray(np.concatenate(clouds).T.astype(np.float32))
 

@@ -49,3 +49,36 @@ def test_autotune_picks_a_candidate_and_results_are_shape_independent():
     b.run()
     torch.cuda.synchronize()
     assert torch.equal(a.fr.img, b.fr.img)
+
+
+def test_coarse_to_fine_stages_reanchor_the_field_gaussians():
+    """Sec. III-C / IV-B schedule on a small drive: each stage anchors the Gaussians at
+    one point per voxel of the cloud (the oracle's choice, in its order), bounds their
+    scales by the voxel size, and keeps the field and the calibration."""
+    import oracle
+    say("case: coarse-to-fine stages")
+    s = synth.small_drive(13, n_points=6000, W=160, H=64, f=70.0, n_frames=4, deg=2.0, metres=0.1, delta=0.02)
+    stages = ((0.8, 12), (0.4, 12), (0.2, 12))
+    cfg = cb.CalibConfig(warmup=6, batch_views=4, seed=2, model="field", field_log2_table=14, stages=stages)
+    cal = cb.Calibrator(s, cfg)
+    assert cal.cfg.steps == 36
+    cloud = cal.cloud.cpu().numpy()
+    lo = cloud.min(axis=1).astype(np.float64)
+    tables = cal.field["tables"]
+    seen = []
+    for k in range(cal.cfg.steps):
+        cal.step(k)
+        if k in (0, 12, 24):
+            voxel = stages[len(seen)][0]
+            torch.cuda.synchronize()
+            want = oracle.downsample(cloud, lo, voxel)
+            np.testing.assert_array_equal(cal.win.mean.cpu().numpy(), cloud[:, want])
+            sc = cal.win.scale.cpu().numpy()
+            assert sc.shape[1] == len(want) and np.all(sc > 0) and np.all(sc <= voxel)
+            seen.append(len(want))
+    torch.cuda.synchronize()
+    assert seen[0] < seen[1] < seen[2]
+    assert [st["gaussians"] for st in cal.stage_log] == seen
+    assert cal.field["tables"] is tables and len(cal.opt_g.state) > 0
+    assert math.isfinite(float(cal.loss.item()))
+    assert all(math.isfinite(x) for x in sum(cal.errors().values(), []))
