@@ -345,8 +345,9 @@ SPLAT_API int splat_ngp_bwd(const splat_ngp *m, const float *mean, int64_t n, co
  * float32 device planes x, y, z) lies in the voxel
  *   v_d = floor((pts[d][i] - lo[d]) / voxel),  d = x, y, z  (float64 arithmetic),
  * and of every occupied voxel the point with the lowest index is kept.  keep
- * (device, >= n int32) receives the kept indices ordered by voxel (z, then y,
- * then x, ascending) and *n_keep (device u32) their number.  Each v_d must lie in
+ * (device, >= n int32) receives the kept indices in Z-curve (Morton) order of
+ * their voxels (bit b of v_x, v_y, v_z is bit 3b, 3b+1, 3b+2 of the code) and
+ * *n_keep (device u32) their number.  Each v_d must lie in
  * [0, 2^21): choose lo at or below the cloud's minimum and voxel large enough;
  * a point outside (or a NaN coordinate) is clamped into the grid and
  * SPLAT_ST_RANGE is OR-ed into *status (device u32).  ws is caller-owned scratch

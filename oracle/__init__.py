@@ -5,4 +5,4 @@ Only the test suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 """
 from .oracle import *  # noqa: F401,F403
 from .ssim import dssim, ssim_map, window_1d  # noqa: F401
-from .voxel import downsample, voxel_keys  # noqa: F401
+from .voxel import downsample, morton_code, voxel_keys  # noqa: F401

@@ -1,10 +1,13 @@
 // voxel.hip -- voxel downsampling of the accumulated LiDAR cloud (Sec. III-C: one
 // point per voxel; the coarse-to-fine schedule runs it at 10, 5 and 2 cm).
 //
-// Voxel of a point: floor((x - lo) / voxel) per axis in float64, packed as
-// x | y << 21 | z << 42.  A stable radix sort of (key, index) puts every voxel's
-// points together in index order, so the first of each run is the point with the
-// lowest index; those are compacted in voxel (z, y, x) order.
+// Voxel of a point: floor((x - lo) / voxel) per axis in float64, 21 bits per axis,
+// packed as its Morton (Z-curve) code: bit b of x, y, z goes to bit 3b, 3b+1, 3b+2.
+// A stable radix sort of (code, index) puts every voxel's points together in index
+// order, so the first of each run is the point with the lowest index; those are
+// compacted in Z-curve order of their voxels, which keeps points that are close in
+// space close in memory (the hash-grid adjoint's scattered updates then share
+// cache lines and wave-level combining).
 #include "common.hpp"
 
 namespace splat {
@@ -36,6 +39,17 @@ VoxelLayout voxel_layout(int64_t n) {
     return L;
 }
 
+// spreads the low 21 bits of v to bits 0, 3, 6, ..., 60
+__device__ inline uint64_t spread3(uint64_t v) {
+    v &= 0x1FFFFFull;
+    v = (v | (v << 32)) & 0x001F00000000FFFFull;
+    v = (v | (v << 16)) & 0x001F0000FF0000FFull;
+    v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+    v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
 __global__ void voxel_key_kernel(const float *pts, int64_t n, double lo0, double lo1, double lo2, double voxel,
                                  uint64_t *keys, uint32_t *vals, uint32_t *counts, uint32_t *status) {
     if (blockIdx.x == 0 && threadIdx.x == 0) counts[CNT_INST] = (uint32_t)n;
@@ -47,7 +61,7 @@ __global__ void voxel_key_kernel(const float *pts, int64_t n, double lo0, double
             double c = floor(((double)pts[d * n + i] - lo[d]) / voxel);
             if (!(c >= 0.0)) { c = 0.0; clamped = true; }          // below the box (or NaN)
             if (c > (double)VMAX) { c = (double)VMAX; clamped = true; }
-            key |= (uint64_t)c << (VB * d);
+            key |= spread3((uint64_t)c) << d;
         }
         keys[i] = key;
         vals[i] = (uint32_t)i;

@@ -1,5 +1,5 @@
 """GPU parity of the voxel downsampling (one point per voxel, the lowest index, in
-(z, y, x) voxel order; Sec. III-C coarse-to-fine stages) against the oracle: the
+Z-curve order of the voxels; Sec. III-C coarse-to-fine stages) against the oracle: the
 kept indices must be identical, bit for bit."""
 import numpy as np
 import pytest
