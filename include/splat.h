@@ -326,8 +326,10 @@ typedef struct splat_ngp {
 SPLAT_API int splat_ngp_fwd(const splat_ngp *m, const float *mean, int64_t n, float *quat, float *scale,
                             float *opacity, float *color, void *stream);
 
-/* Device scratch of splat_ngp_bwd for n Gaussians (per-Gaussian activations and
- * deltas, 1328 bytes each, plus the weight-gradient partials). */
+/* Device scratch of splat_ngp_bwd and splat_ngp_bwd_indexed for n Gaussians
+ * (per-Gaussian activations and deltas, 1328 bytes each, encoding gradients,
+ * 128 bytes each, the weight-gradient partials and the index reduction's
+ * carries). */
 SPLAT_API size_t splat_ngp_workspace_size(int64_t n);
 
 /* Adjoint of splat_ngp_fwd: from d(loss)/d(quat, scale, opacity, color) it ADDS
@@ -358,6 +360,35 @@ SPLAT_API size_t splat_voxel_workspace_size(int64_t n);
 SPLAT_API int splat_voxel_downsample(const float *pts, int64_t n, const double lo[3], double voxel, void *ws,
                                      size_t ws_bytes, int32_t *keep, uint32_t *n_keep, uint32_t *status,
                                      void *stream);
+
+/*
+ * Table adjoint through an inverse index.  While the Gaussian positions stay
+ * fixed (a stage of the coarse-to-fine schedule, Sec. III-C), the table rows
+ * every position looks up, and the trilinear weights, do not change; the index
+ * lists, per level, every (Gaussian, weight) pair grouped by table row.
+ * splat_ngp_bwd_indexed then forms each row's gradient as one fixed-order
+ * float64 sum instead of float atomics: same result as splat_ngp_bwd up to
+ * rounding, reproducible bit for bit, and no contention.
+ * The index depends on mean, n and the model's levels, log2_table, n_min,
+ * n_max, lo and hi (not on the tables or weights); rebuild it when any of these
+ * change.  index is caller-owned device memory of splat_ngp_index_size(m, n)
+ * bytes (about 64 * levels bytes per Gaussian); the build needs a scratch ws of
+ * splat_ngp_index_workspace_size(m, n) bytes (about 224 * levels bytes per
+ * Gaussian).  n <= 2^24.  Sizes return 0 for invalid arguments.
+ */
+SPLAT_API size_t splat_ngp_index_size(const splat_ngp *m, int64_t n);
+SPLAT_API size_t splat_ngp_index_workspace_size(const splat_ngp *m, int64_t n);
+SPLAT_API int splat_ngp_index_build(const splat_ngp *m, const float *mean, int64_t n, void *index,
+                                    size_t index_bytes, void *ws, size_t ws_bytes, void *stream);
+
+/* splat_ngp_bwd with the table gradients formed through an index built by
+ * splat_ngp_index_build for the same mean, n and grid (see above).  ADDS to
+ * every gradient array; ws as for splat_ngp_bwd. */
+SPLAT_API int splat_ngp_bwd_indexed(const splat_ngp *m, const float *mean, int64_t n, const void *index,
+                                    size_t index_bytes, const float *dquat, const float *dscale,
+                                    const float *dopacity, const float *dcolor, void *ws, size_t ws_bytes,
+                                    float *dtables, float *dw1, float *db1, float *dw2, float *db2, float *dw3,
+                                    float *db3, void *stream);
 
 /* Text of the last synchronous error on this thread ("" if none). */
 SPLAT_API const char *splat_last_error(void);

@@ -411,6 +411,55 @@ int splat_ngp_bwd(const splat_ngp *m, const float *mean, int64_t n, const float 
                           (hipStream_t)stream);
 }
 
+static int check_ngp_index(const splat_ngp *m, int64_t n, const char *who) {
+    int rc = check_ngp(m, who);
+    if (rc) return rc;
+    if (n < 0 || n > ((int64_t)1 << 24)) { set_error("%s: n outside [0, 2^24]", who); return SPLAT_EINVAL; }
+    return SPLAT_OK;
+}
+
+size_t splat_ngp_index_size(const splat_ngp *m, int64_t n) {
+    g_err[0] = 0;
+    return check_ngp_index(m, n, "ngp_index_size") ? 0 : ngp_index_bytes(*m, n);
+}
+
+size_t splat_ngp_index_workspace_size(const splat_ngp *m, int64_t n) {
+    g_err[0] = 0;
+    return check_ngp_index(m, n, "ngp_index_workspace_size") ? 0 : ngp_index_ws_bytes(*m, n);
+}
+
+int splat_ngp_index_build(const splat_ngp *m, const float *mean, int64_t n, void *index, size_t index_bytes,
+                          void *ws, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    int rc = check_ngp_index(m, n, "ngp_index_build");
+    if (rc) return rc;
+    if (n == 0) return SPLAT_OK;
+    if (!mean || !index || !ws) { set_error("ngp_index_build: NULL argument"); return SPLAT_EINVAL; }
+    size_t ni = ngp_index_bytes(*m, n), nw = ngp_index_ws_bytes(*m, n);
+    if (index_bytes < ni) { set_error("ngp_index_build: index of %zu bytes, %zu needed", index_bytes, ni); return SPLAT_EINVAL; }
+    if (ws_bytes < nw) { set_error("ngp_index_build: workspace of %zu bytes, %zu needed", ws_bytes, nw); return SPLAT_EINVAL; }
+    return launch_ngp_index_build(*m, mean, n, index, ws, (hipStream_t)stream);
+}
+
+int splat_ngp_bwd_indexed(const splat_ngp *m, const float *mean, int64_t n, const void *index, size_t index_bytes,
+                          const float *dquat, const float *dscale, const float *dopacity, const float *dcolor,
+                          void *ws, size_t ws_bytes, float *dtables, float *dw1, float *db1, float *dw2, float *db2,
+                          float *dw3, float *db3, void *stream) {
+    g_err[0] = 0;
+    int rc = check_ngp_index(m, n, "ngp_bwd_indexed");
+    if (rc) return rc;
+    if (n == 0) return SPLAT_OK;
+    if (!mean || !index || !dquat || !dscale || !dopacity || !dcolor || !ws || !dtables || !dw1 || !db1 || !dw2 ||
+        !db2 || !dw3 || !db3) {
+        set_error("ngp_bwd_indexed: NULL argument"); return SPLAT_EINVAL;
+    }
+    size_t ni = ngp_index_bytes(*m, n), nw = ngp_ws_bytes(n);
+    if (index_bytes < ni) { set_error("ngp_bwd_indexed: index of %zu bytes, %zu needed", index_bytes, ni); return SPLAT_EINVAL; }
+    if (ws_bytes < nw) { set_error("ngp_bwd_indexed: workspace of %zu bytes, %zu needed", ws_bytes, nw); return SPLAT_EINVAL; }
+    return launch_ngp_bwd_indexed(*m, mean, n, index, dquat, dscale, dopacity, dcolor, ws, dtables, dw1, db1, dw2,
+                                  db2, dw3, db3, (hipStream_t)stream);
+}
+
 size_t splat_voxel_workspace_size(int64_t n) { return n < 0 ? 0 : voxel_ws_bytes(n); }
 
 int splat_voxel_downsample(const float *pts, int64_t n, const double *lo, double voxel, void *ws, size_t ws_bytes,

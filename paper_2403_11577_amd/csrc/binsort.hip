@@ -475,15 +475,15 @@ int launch_scan_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, in
     return launch_status("scan_down");
 }
 
-int launch_radix_sort_u64(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, const uint32_t *counts, int bits,
-                          int nparts, uint32_t *hist, uint32_t *partials, hipStream_t st, int *sorted_in_1) {
+int launch_radix_sort_u64(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, const uint32_t *counts, int bit0,
+                          int bits, int nparts, uint32_t *hist, uint32_t *partials, hipStream_t st, int *sorted_in_1) {
     int passes = (bits + kRadixBits - 1) / kRadixBits;
     uint64_t *ki = k0, *ko = k1;
     uint32_t *vi = v0, *vo = v1;
     int nh = kRadixDigits * nparts;
     int rc = 0;
     for (int ps = 0; ps < passes; ++ps) {
-        int shift = kRadixBits * ps;
+        int shift = bit0 + kRadixBits * ps;
         hipLaunchKernelGGL(radix_upsweep_kernel, dim3(nparts), dim3(RS_T), 0, st, ki, counts, shift, nparts, hist);
         if ((rc = launch_status("radix_upsweep"))) return rc;
         if ((rc = launch_scan_u32(hist, hist, nullptr, nh, partials, nullptr, st))) return rc;
@@ -526,7 +526,7 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
 
     // LSD radix sort over the used key bits
     int in1 = 0;
-    rc = launch_radix_sort_u64(keys0, keys1, vals0, vals1, counts, p.depth_bits + p.tile_bits, p.n_sort_blocks, hist,
+    rc = launch_radix_sort_u64(keys0, keys1, vals0, vals1, counts, 0, p.depth_bits + p.tile_bits, p.n_sort_blocks, hist,
                                partials, st, &in1);
     if (rc) return rc;
     const uint64_t *ki = in1 ? keys1 : keys0;

@@ -89,6 +89,12 @@ int launch_ngp_fwd(const splat_ngp &m, const float *mean, int64_t n, float *quat
 int launch_ngp_bwd(const splat_ngp &m, const float *mean, int64_t n, const float *dquat, const float *dscale,
                    const float *dopac, const float *dcolor, void *ws, float *dtables, float *dw1, float *db1,
                    float *dw2, float *db2, float *dw3, float *db3, hipStream_t st);
+size_t ngp_index_bytes(const splat_ngp &m, int64_t n);
+size_t ngp_index_ws_bytes(const splat_ngp &m, int64_t n);
+int launch_ngp_index_build(const splat_ngp &m, const float *mean, int64_t n, void *index, void *ws, hipStream_t st);
+int launch_ngp_bwd_indexed(const splat_ngp &m, const float *mean, int64_t n, const void *index, const float *dquat,
+                           const float *dscale, const float *dopac, const float *dcolor, void *ws, float *dtables,
+                           float *dw1, float *db1, float *dw2, float *db2, float *dw3, float *db3, hipStream_t st);
 int launch_dssim(const float *img, const float *target, int64_t n_views, int32_t width, int32_t height,
                  int32_t roi_y0, double weight, void *ws, float *dimg, double *loss, hipStream_t st);
 
@@ -98,10 +104,10 @@ size_t scan_partials(int64_t n_cap);
 int launch_scan_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, int64_t n_cap,
                     uint32_t *partials, uint32_t *total_dst, hipStream_t st);
 int launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
-// stable LSD radix sort of (k0, v0) over the low `bits` key bits, n = counts[CNT_INST];
+// stable LSD radix sort of (k0, v0) by key bits [bit0, bit0 + bits), n = counts[CNT_INST];
 // hist needs 2^kRadixBits * nparts + 1 u32, partials scan_partials of that
-int launch_radix_sort_u64(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, const uint32_t *counts, int bits,
-                          int nparts, uint32_t *hist, uint32_t *partials, hipStream_t st, int *sorted_in_1);
+int launch_radix_sort_u64(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, const uint32_t *counts, int bit0,
+                          int bits, int nparts, uint32_t *hist, uint32_t *partials, hipStream_t st, int *sorted_in_1);
 size_t voxel_ws_bytes(int64_t n);
 int launch_voxel_downsample(const float *pts, int64_t n, const double *lo, double voxel, void *ws, int32_t *keep,
                             uint32_t *n_keep, uint32_t *status, hipStream_t st);

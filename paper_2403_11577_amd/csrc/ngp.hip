@@ -12,12 +12,21 @@
 // scale_max * sigmoid, quaternion + (1, 0, 0, 0).
 //
 // Adjoint: the forward is recomputed, the 11 output gradients are pushed back
-// through the heads and the MLP, table gradients are scattered with hardware
-// float atomics (16 levels x 8 vertices x 2 features) after the lanes of a wave
-// that share a table row have been summed (coarse levels), and the per-Gaussian
-// activations and deltas are stored so that the weight gradients -- sums over all
-// Gaussians of outer products, a tall-skinny A^T B -- are formed by atb_kernel
-// (per-workgroup partials in registers, then a fixed-order reduction).
+// through the heads and the MLP, and the per-Gaussian activations and deltas are
+// stored so that the weight gradients -- sums over all Gaussians of outer
+// products, a tall-skinny A^T B -- are formed by atb_kernel (per-workgroup
+// partials in registers, then a fixed-order reduction).  The table gradient of a
+// row is the sum, over every (Gaussian, vertex) that looked it up, of the
+// trilinear weight times the Gaussian's encoding gradient.  Two ways to form it:
+//  * scatter: hardware float atomics (16 levels x 8 vertices x 2 features), after
+//    the lanes of a wave that share a row have been summed;
+//  * indexed: the positions are fixed while the Gaussians are (a calibration stage
+//    moves cameras, not Gaussians), so the lookups are inverted once -- every
+//    (Gaussian, weight) pair sorted by (level, row) -- and each step reduces the
+//    runs of that list: a workgroup sums 2048 consecutive pairs with a segmented
+//    scan and writes every row whose run it holds whole, a second kernel adds up
+//    the runs that cross workgroups.  No atomics, one writer per row, a fixed
+//    summation order (float64), so the table gradient is reproducible bit for bit.
 #include "common.hpp"
 
 namespace splat {
@@ -229,12 +238,15 @@ __global__ __launch_bounds__(256, 2) void ngp_fwd_kernel(NgpArgs a, const float 
     }
 }
 
+// SCATTER: table gradients by atomics into dtables; else the encoding gradients go to
+// dEc[level][Gaussian] for the indexed reduction.
+template <bool SCATTER>
 __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float *mean, int64_t n,
                                                         const float2 *tables, const float *w1, const float *b1,
                                                         const float *w2, const float *b2, const float *w3,
                                                         const float *b3, const float *dquat, const float *dscale,
                                                         const float *dopac, const float *dcolor, float *dtables,
-                                                        float *rows) {
+                                                        float *rows, float2 *dEc) {
     __shared__ Weights W;
     load_weights(W, w1, b1, w2, b2, w3, b3, 2 * a.levels);
     __syncthreads();
@@ -301,6 +313,13 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
 #pragma unroll
                 for (int e = 0; e < ND; ++e) de[e] = __fmaf_rn(W.w1[j][e], dh, de[e]);
             }
+        }
+        if (!SCATTER) {
+            if (live)
+#pragma unroll
+                for (int l = 0; l < NL; ++l)
+                    if (l < a.levels) dEc[(int64_t)l * n + i] = make_float2(de[2 * l], de[2 * l + 1]);
+            continue;
         }
 #pragma unroll
         for (int e = 0; e < ND; ++e) row[R_DE + e] = de[e];
@@ -391,6 +410,266 @@ __global__ void atb_reduce_kernel(const float *partial, int ngroups, int ma, int
 
 constexpr int ATB_GROUPS = 512;
 
+// ---- the inverse index of the table lookups ----
+constexpr int GT_T = 256;               // threads per reduction workgroup
+constexpr int GT_EPT = 8;               // index entries per thread
+constexpr int GT_TILE = GT_T * GT_EPT;  // entries per workgroup
+
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Index: per level, the 8 n (Gaussian, weight) pairs sorted by table row and padded with
+// zero-weight pairs to whole tiles (so a tile never spans two levels); ent_g holds the
+// Gaussian with bit 31 set on the first pair of a row's run; seg_row the row of every run;
+// tile_seg the run of each tile's first pair, tile_nh the number of runs starting in it.
+struct IndexLayout {
+    int64_t E, P, tpl, ntiles, nseg_cap;
+    size_t ent_g, ent_w, seg_row, tile_seg, tile_nh, end;
+};
+
+IndexLayout index_layout(int levels, int log2T, int64_t n) {
+    IndexLayout L;
+    L.E = 8 * n;
+    L.P = (L.E + GT_TILE - 1) / GT_TILE * GT_TILE;
+    L.tpl = L.P / GT_TILE;
+    L.ntiles = (int64_t)levels * L.tpl;
+    int64_t T = (int64_t)1 << log2T;
+    L.nseg_cap = (int64_t)levels * (L.E < T ? L.E : T);
+    int64_t tot = (int64_t)levels * L.P;
+    size_t o = 0;
+    L.ent_g = o; o = al256(o + (size_t)tot * 4);
+    L.ent_w = o; o = al256(o + (size_t)tot * 4);
+    L.seg_row = o; o = al256(o + (size_t)L.nseg_cap * 4);
+    L.tile_seg = o; o = al256(o + (size_t)L.ntiles * 4);
+    L.tile_nh = o; o = al256(o + (size_t)L.ntiles * 4);
+    L.end = o;
+    return L;
+}
+
+struct IndexBuildLayout {
+    size_t counts, keys, vals, flags, hist, partials, end;
+    int nparts;
+};
+
+IndexBuildLayout index_build_layout(int levels, int log2T, int64_t n) {
+    IndexLayout I = index_layout(levels, log2T, n);
+    int64_t te = (int64_t)levels * I.E, tp = (int64_t)levels * I.P;
+    IndexBuildLayout B;
+    int64_t np = (te + 8191) / 8192;
+    B.nparts = (int)(np < 1 ? 1 : (np > 2048 ? 2048 : np));
+    int64_t nh = (int64_t)kRadixDigits * B.nparts + 1;
+    size_t o = 0;
+    B.counts = o; o = al256(o + 8 * 4);
+    B.keys = o; o = al256(o + (size_t)2 * te * 8);
+    B.vals = o; o = al256(o + (size_t)2 * te * 4);
+    B.flags = o; o = al256(o + (size_t)(tp + 1) * 4);
+    B.hist = o; o = al256(o + (size_t)nh * 4);
+    size_t p1 = scan_partials(tp + 1), p2 = scan_partials(nh);
+    B.partials = o; o = al256(o + (p1 > p2 ? p1 : p2) * 4);
+    B.end = o;
+    return B;
+}
+
+// key = (level << log2T | row) << 32 | bits of the float weight, value = Gaussian; pair
+// (l, i, c) at position (l n + i) 8 + c
+__global__ void ngp_index_keys_kernel(NgpArgs a, int log2T, const float *mean, int64_t n, uint64_t *keys,
+                                      uint32_t *vals, uint32_t *counts) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) counts[CNT_INST] = (uint32_t)((int64_t)a.levels * 8 * n);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double xn[3];
+        normalise(a, mean, n, i, xn);
+#pragma unroll 1
+        for (int l = 0; l < a.levels; ++l) {
+            uint32_t cell[3];
+            double fr[3];
+            level_cell(a, l, xn, cell, fr);
+            uint64_t *kk = keys + ((int64_t)l * n + i) * 8;
+            uint32_t *vv = vals + ((int64_t)l * n + i) * 8;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+                float w = (float)((cx ? fr[0] : 1.0 - fr[0]) * (cy ? fr[1] : 1.0 - fr[1]) * (cz ? fr[2] : 1.0 - fr[2]));
+                uint32_t r = vertex_row(a, l, cell[0] + cx, cell[1] + cy, cell[2] + cz);
+                kk[c] = ((uint64_t)(((uint32_t)l << log2T) | r) << 32) | (uint64_t)__float_as_uint(w);
+                vv[c] = (uint32_t)i;
+            }
+        }
+    }
+}
+
+// sorted pairs -> padded per-level layout, run-start flags
+__global__ void ngp_index_place_kernel(const uint64_t *keys, const uint32_t *vals, int levels, int64_t E, int64_t P,
+                                       uint32_t *ent_g, float *ent_w, uint32_t *flags) {
+    const int64_t tot = (int64_t)levels * P;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t l = i / P, j = i - l * P;
+        uint32_t g = 0u, head = 0u;
+        float w = 0.f;
+        if (j < E) {
+            int64_t s = l * E + j;
+            uint64_t k = keys[s];
+            head = (j == 0 || (keys[s - 1] >> 32) != (k >> 32)) ? 1u : 0u;
+            g = vals[s];
+            w = __uint_as_float((uint32_t)k);
+        }
+        ent_g[i] = g | (head << 31);
+        ent_w[i] = w;
+        flags[i] = head;
+    }
+}
+
+// after the exclusive scan of the flags: the row of every run and the tile metadata
+__global__ void ngp_index_meta_kernel(const uint64_t *keys, const uint32_t *ent_g, const uint32_t *excl, int levels,
+                                      int64_t E, int64_t P, uint32_t tmask, uint32_t *seg_row, uint32_t *tile_seg,
+                                      uint32_t *tile_nh) {
+    const int64_t tot = (int64_t)levels * P;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t head = ent_g[i] >> 31;
+        uint32_t x = excl[i];
+        if (head) {
+            int64_t l = i / P, j = i - l * P;
+            seg_row[x] = (uint32_t)(keys[l * E + j] >> 32) & tmask;
+        }
+        if (i % GT_TILE == 0) {
+            int64_t t = i / GT_TILE;
+            tile_seg[t] = x + head - 1u;
+            tile_nh[t] = excl[i + GT_TILE] - x;
+        }
+    }
+}
+
+// running sum of a segmented sequence: c runs start in it, s = sum after the last start
+// (of everything when c = 0)
+struct SegAcc {
+    uint32_t c;
+    double s0, s1;
+};
+
+__device__ __forceinline__ SegAcc seg_join(const SegAcc &a, const SegAcc &b) {  // a, then b
+    SegAcc r;
+    r.c = a.c + b.c;
+    r.s0 = b.c ? b.s0 : a.s0 + b.s0;
+    r.s1 = b.c ? b.s1 : a.s1 + b.s1;
+    return r;
+}
+
+// One workgroup per tile of GT_TILE pairs (thread t owns pairs [8t, 8t + 8)).  A run that
+// starts and ends in the tile is written here (its only writer); the partial sum of a run
+// that started in an earlier tile and ends here goes to carry_head, that of the run still
+// open at the tile's end to carry_tail.
+__global__ __launch_bounds__(GT_T) void ngp_gather_kernel(int64_t n, int64_t T, int64_t tpl, int64_t ntiles,
+                                                         const uint32_t *ent_g, const float *ent_w,
+                                                         const uint32_t *seg_row, const uint32_t *tile_seg,
+                                                         const float2 *dEc, float *dtables, double2 *carry_head,
+                                                         double2 *carry_tail) {
+    __shared__ SegAcc wagg[GT_T / 64];
+    __shared__ uint32_t first_head[GT_T];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t tile = blockIdx.x;
+    const int64_t l = tile / tpl;
+    const int64_t base = tile * GT_TILE + (int64_t)t * GT_EPT;
+    const float2 *de = dEc + l * n;
+    const uint4 ga = *reinterpret_cast<const uint4 *>(ent_g + base);
+    const uint4 gb = *reinterpret_cast<const uint4 *>(ent_g + base + 4);
+    const float4 wa = *reinterpret_cast<const float4 *>(ent_w + base);
+    const float4 wb = *reinterpret_cast<const float4 *>(ent_w + base + 4);
+    const uint32_t g[GT_EPT] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+    const float wt[GT_EPT] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+    float v0[GT_EPT], v1[GT_EPT];
+#pragma unroll
+    for (int k = 0; k < GT_EPT; ++k) {
+        float2 d = de[g[k] & 0x7FFFFFFFu];
+        v0[k] = wt[k] * d.x;
+        v1[k] = wt[k] * d.y;
+    }
+    SegAcc agg = {0u, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < GT_EPT; ++k) {
+        if (g[k] >> 31) {
+            agg.c += 1u;
+            agg.s0 = v0[k];
+            agg.s1 = v1[k];
+        } else {
+            agg.s0 += v0[k];
+            agg.s1 += v1[k];
+        }
+    }
+    // exclusive scan over the workgroup, in thread order
+    SegAcc inc = agg;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        SegAcc o;
+        o.c = __shfl_up(inc.c, off);
+        o.s0 = __shfl_up(inc.s0, off);
+        o.s1 = __shfl_up(inc.s1, off);
+        if (lane >= off) inc = seg_join(o, inc);
+    }
+    SegAcc ex;
+    ex.c = __shfl_up(inc.c, 1);
+    ex.s0 = __shfl_up(inc.s0, 1);
+    ex.s1 = __shfl_up(inc.s1, 1);
+    if (lane == 0) ex = SegAcc{0u, 0.0, 0.0};
+    if (lane == 63) wagg[w] = inc;
+    first_head[t] = g[0] >> 31;
+    __syncthreads();
+    SegAcc pre = {0u, 0.0, 0.0};
+    for (int q = 0; q < w; ++q) pre = seg_join(pre, wagg[q]);
+    ex = seg_join(pre, ex);
+    uint32_t next_head;
+    if (t < GT_T - 1) next_head = first_head[t + 1];
+    else next_head = tile + 1 < ntiles ? ent_g[(tile + 1) * GT_TILE] >> 31 : 1u;
+    const uint32_t hf = first_head[0];
+    const uint32_t seg0 = tile_seg[tile];
+    uint32_t heads = ex.c;
+    double r0 = ex.s0, r1 = ex.s1;
+    float *tab = dtables + l * T * 2;
+#pragma unroll
+    for (int k = 0; k < GT_EPT; ++k) {
+        if (g[k] >> 31) {
+            heads += 1u;
+            r0 = v0[k];
+            r1 = v1[k];
+        } else {
+            r0 += v0[k];
+            r1 += v1[k];
+        }
+        uint32_t last = k < GT_EPT - 1 ? g[k + 1] >> 31 : next_head;
+        if (last) {
+            if (heads > 0u) {
+                float *dt = tab + 2 * (int64_t)seg_row[seg0 + heads - hf];
+                dt[0] += (float)r0;
+                dt[1] += (float)r1;
+            } else {
+                carry_head[tile] = make_double2(r0, r1);
+            }
+        } else if (t == GT_T - 1 && k == GT_EPT - 1) {
+            carry_tail[tile] = make_double2(r0, r1);
+        }
+    }
+}
+
+// Runs that cross tiles: the tile where such a run starts adds the carries of the tiles it
+// covers, in order, and writes the row.
+__global__ void ngp_fixup_kernel(int64_t T, int64_t tpl, int64_t ntiles, const uint32_t *ent_g,
+                                 const uint32_t *seg_row, const uint32_t *tile_seg, const uint32_t *tile_nh,
+                                 const double2 *carry_head, const double2 *carry_tail, float *dtables) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        if (t + 1 >= ntiles || (ent_g[(t + 1) * GT_TILE] >> 31) || tile_nh[t] == 0u) continue;
+        double s0 = carry_tail[t].x, s1 = carry_tail[t].y;
+        for (int64_t u = t + 1;; ++u) {
+            bool ends = tile_nh[u] > 0u || u + 1 >= ntiles || (ent_g[(u + 1) * GT_TILE] >> 31);
+            const double2 c = ends ? carry_head[u] : carry_tail[u];
+            s0 += c.x;
+            s1 += c.y;
+            if (ends) break;
+        }
+        uint32_t seg = tile_seg[t] + tile_nh[t] - (ent_g[t * GT_TILE] >> 31);
+        float *dt = dtables + ((t / tpl) * T + seg_row[seg]) * 2;
+        dt[0] += (float)s0;
+        dt[1] += (float)s1;
+    }
+}
+
 int ngp_args(const splat_ngp &m, NgpArgs &a) {
     a.levels = m.levels;
     a.T = (int64_t)1 << m.log2_table;
@@ -412,10 +691,120 @@ int ngp_args(const splat_ngp &m, NgpArgs &a) {
     return 0;
 }
 
+// adjoint scratch: per-Gaussian rows, A^T B partials, encoding gradients per level (indexed
+// path) and the run carries of the indexed reduction
+struct WsLayout {
+    size_t rows, partial, dec, carry_head, carry_tail, end;
+};
+
+WsLayout ws_layout(int64_t n) {
+    WsLayout W;
+    int64_t ntiles = (int64_t)NL * ((8 * n + GT_TILE - 1) / GT_TILE);
+    size_t o = 0;
+    W.rows = o; o = al256(o + (size_t)(n + 1) * R_LEN * sizeof(float));
+    W.partial = o; o = al256(o + (size_t)ATB_GROUPS * (NH * NH + NH) * sizeof(float));
+    W.dec = o; o = al256(o + (size_t)NL * n * sizeof(float2));
+    W.carry_head = o; o = al256(o + (size_t)ntiles * sizeof(double2));
+    W.carry_tail = o; o = al256(o + (size_t)ntiles * sizeof(double2));
+    W.end = o;
+    return W;
+}
+
 }  // namespace
 
-size_t ngp_ws_bytes(int64_t n) {
-    return (size_t)(n + 1) * R_LEN * sizeof(float) + (size_t)ATB_GROUPS * (NH * NH + NH) * sizeof(float);  // rows + partials
+size_t ngp_ws_bytes(int64_t n) { return ws_layout(n).end; }
+
+size_t ngp_index_bytes(const splat_ngp &m, int64_t n) { return index_layout(m.levels, m.log2_table, n).end; }
+
+size_t ngp_index_ws_bytes(const splat_ngp &m, int64_t n) {
+    return index_build_layout(m.levels, m.log2_table, n).end;
+}
+
+int launch_ngp_index_build(const splat_ngp &m, const float *mean, int64_t n, void *index, void *ws, hipStream_t st) {
+    NgpArgs a;
+    ngp_args(m, a);
+    const IndexLayout I = index_layout(m.levels, m.log2_table, n);
+    const IndexBuildLayout Bl = index_build_layout(m.levels, m.log2_table, n);
+    const int64_t te = (int64_t)m.levels * I.E, tp = (int64_t)m.levels * I.P;
+    uint32_t *counts = ws_at<uint32_t>(ws, Bl.counts);
+    uint64_t *k0 = ws_at<uint64_t>(ws, Bl.keys), *k1 = k0 + te;
+    uint32_t *v0 = ws_at<uint32_t>(ws, Bl.vals), *v1 = v0 + te;
+    uint32_t *flags = ws_at<uint32_t>(ws, Bl.flags);
+    int64_t nb = (n + 255) / 256;
+    if (nb > 8192) nb = 8192;
+    hipLaunchKernelGGL(ngp_index_keys_kernel, dim3((unsigned)nb), dim3(256), 0, st, a, m.log2_table, mean, n, k0, v0,
+                       counts);
+    int rc = launch_status("ngp_index_keys");
+    if (rc) return rc;
+    int lb = 0;
+    while ((1 << lb) < m.levels) ++lb;
+    int in1 = 0;
+    rc = launch_radix_sort_u64(k0, k1, v0, v1, counts, 32, m.log2_table + lb, Bl.nparts, ws_at<uint32_t>(ws, Bl.hist),
+                               ws_at<uint32_t>(ws, Bl.partials), st, &in1);
+    if (rc) return rc;
+    const uint64_t *ks = in1 ? k1 : k0;
+    const uint32_t *vs = in1 ? v1 : v0;
+    uint32_t *ent_g = ws_at<uint32_t>(index, I.ent_g);
+    int64_t gb = (tp + 255) / 256;
+    if (gb > 16384) gb = 16384;
+    hipLaunchKernelGGL(ngp_index_place_kernel, dim3((unsigned)gb), dim3(256), 0, st, ks, vs, m.levels, I.E, I.P,
+                       ent_g, ws_at<float>(index, I.ent_w), flags);
+    if ((rc = launch_status("ngp_index_place"))) return rc;
+    if ((rc = launch_scan_u32(flags, flags, nullptr, tp, ws_at<uint32_t>(ws, Bl.partials), nullptr, st))) return rc;
+    hipLaunchKernelGGL(ngp_index_meta_kernel, dim3((unsigned)gb), dim3(256), 0, st, ks, ent_g, flags, m.levels, I.E,
+                       I.P, a.tmask, ws_at<uint32_t>(index, I.seg_row), ws_at<uint32_t>(index, I.tile_seg),
+                       ws_at<uint32_t>(index, I.tile_nh));
+    return launch_status("ngp_index_meta");
+}
+
+namespace {
+int launch_atb_jobs(const splat_ngp &m, int64_t n, float *rows, float *partial, float *dw1, float *db1, float *dw2,
+                    float *db2, float *dw3, float *db3, hipStream_t st) {
+    int din = 2 * m.levels;
+    struct Job { int aoff, ma, boff, nb, dinw; float *dw, *db; };
+    Job jobs[3] = {{R_DOUT, NO, R_H2, NH, NH, dw3, db3}, {R_DH2, NH, R_H1, NH, NH, dw2, db2},
+                   {R_DH1, NH, R_ENC, din, din, dw1, db1}};
+    int rc;
+    for (const Job &j : jobs) {
+        hipLaunchKernelGGL(atb_kernel, dim3(ATB_GROUPS), dim3(256), 0, st, rows, n, j.aoff, j.ma, j.boff, j.nb,
+                           partial);
+        if ((rc = launch_status("ngp_atb"))) return rc;
+        hipLaunchKernelGGL(atb_reduce_kernel, dim3(16), dim3(256), 0, st, partial, ATB_GROUPS, j.ma, j.nb, j.dinw,
+                           j.dw, j.db);
+        if ((rc = launch_status("ngp_atb_reduce"))) return rc;
+    }
+    return 0;
+}
+}  // namespace
+
+int launch_ngp_bwd_indexed(const splat_ngp &m, const float *mean, int64_t n, const void *index, const float *dquat,
+                           const float *dscale, const float *dopac, const float *dcolor, void *ws, float *dtables,
+                           float *dw1, float *db1, float *dw2, float *db2, float *dw3, float *db3, hipStream_t st) {
+    NgpArgs a;
+    ngp_args(m, a);
+    const WsLayout W = ws_layout(n);
+    const IndexLayout I = index_layout(m.levels, m.log2_table, n);
+    float *rows = ws_at<float>(ws, W.rows);
+    float2 *dEc = ws_at<float2>(ws, W.dec);
+    int64_t nb = (n + 255) / 256;
+    if (nb > 8192) nb = 8192;
+    hipLaunchKernelGGL(ngp_bwd_kernel<false>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n,
+                       reinterpret_cast<const float2 *>(m.tables), m.w1, m.b1, m.w2, m.b2, m.w3, m.b3, dquat, dscale,
+                       dopac, dcolor, dtables, rows, dEc);
+    int rc = launch_status("ngp_bwd");
+    if (rc) return rc;
+    void *ix = const_cast<void *>(index);
+    const uint32_t *ent_g = ws_at<uint32_t>(ix, I.ent_g);
+    const uint32_t *seg_row = ws_at<uint32_t>(ix, I.seg_row), *tile_seg = ws_at<uint32_t>(ix, I.tile_seg);
+    double2 *ch = ws_at<double2>(ws, W.carry_head), *ct = ws_at<double2>(ws, W.carry_tail);
+    hipLaunchKernelGGL(ngp_gather_kernel, dim3((unsigned)I.ntiles), dim3(GT_T), 0, st, n, a.T, I.tpl, I.ntiles, ent_g,
+                       ws_at<float>(ix, I.ent_w), seg_row, tile_seg, dEc, dtables, ch, ct);
+    if ((rc = launch_status("ngp_gather"))) return rc;
+    int64_t fb = (I.ntiles + 255) / 256;
+    hipLaunchKernelGGL(ngp_fixup_kernel, dim3((unsigned)fb), dim3(256), 0, st, a.T, I.tpl, I.ntiles, ent_g, seg_row,
+                       tile_seg, ws_at<uint32_t>(ix, I.tile_nh), ch, ct, dtables);
+    if ((rc = launch_status("ngp_fixup"))) return rc;
+    return launch_atb_jobs(m, n, rows, ws_at<float>(ws, W.partial), dw1, db1, dw2, db2, dw3, db3, st);
 }
 
 int launch_ngp_fwd(const splat_ngp &m, const float *mean, int64_t n, float *quat, float *scale, float *opac,
@@ -435,28 +824,16 @@ int launch_ngp_bwd(const splat_ngp &m, const float *mean, int64_t n, const float
                    float *dw2, float *db2, float *dw3, float *db3, hipStream_t st) {
     NgpArgs a;
     ngp_args(m, a);
-    float *rows = static_cast<float *>(ws);
-    float *partial = rows + (size_t)(n + 1) * R_LEN;
+    const WsLayout W = ws_layout(n);
+    float *rows = ws_at<float>(ws, W.rows);
     int64_t nb = (n + 255) / 256;
     if (nb > 8192) nb = 8192;
-    hipLaunchKernelGGL(ngp_bwd_kernel, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n,
+    hipLaunchKernelGGL(ngp_bwd_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n,
                        reinterpret_cast<const float2 *>(m.tables), m.w1, m.b1, m.w2, m.b2, m.w3, m.b3, dquat, dscale,
-                       dopac, dcolor, dtables, rows);
+                       dopac, dcolor, dtables, rows, nullptr);
     int rc = launch_status("ngp_bwd");
     if (rc) return rc;
-    int din = 2 * m.levels;
-    struct Job { int aoff, ma, boff, nb, dinw; float *dw, *db; };
-    Job jobs[3] = {{R_DOUT, NO, R_H2, NH, NH, dw3, db3}, {R_DH2, NH, R_H1, NH, NH, dw2, db2},
-                   {R_DH1, NH, R_ENC, din, din, dw1, db1}};
-    for (const Job &j : jobs) {
-        hipLaunchKernelGGL(atb_kernel, dim3(ATB_GROUPS), dim3(256), 0, st, rows, n, j.aoff, j.ma, j.boff, j.nb,
-                           partial);
-        if ((rc = launch_status("ngp_atb"))) return rc;
-        hipLaunchKernelGGL(atb_reduce_kernel, dim3(16), dim3(256), 0, st, partial, ATB_GROUPS, j.ma, j.nb, j.dinw,
-                           j.dw, j.db);
-        if ((rc = launch_status("ngp_atb_reduce"))) return rc;
-    }
-    return 0;
+    return launch_atb_jobs(m, n, rows, ws_at<float>(ws, W.partial), dw1, db1, dw2, db2, dw3, db3, st);
 }
 
 }  // namespace splat

@@ -101,7 +101,7 @@ int launch_voxel_downsample(const float *pts, int64_t n, const double *lo, doubl
     int rc = launch_status("voxel_key");
     if (rc) return rc;
     int in1 = 0;
-    rc = launch_radix_sort_u64(k0, k1, v0, v1, counts, 3 * VB, L.nparts, ws_at<uint32_t>(ws, L.hist),
+    rc = launch_radix_sort_u64(k0, k1, v0, v1, counts, 0, 3 * VB, L.nparts, ws_at<uint32_t>(ws, L.hist),
                                ws_at<uint32_t>(ws, L.partials), st, &in1);
     if (rc) return rc;
     uint64_t *ks = in1 ? k1 : k0;

@@ -161,3 +161,23 @@ def test_voxel_downsample_argument_checks_without_a_device():
     bad = (C.c_double * 3)(0.0, float("nan"), 0.0)
     assert L.splat_voxel_downsample(C.c_void_p(16), 10, bad, 0.1, C.c_void_p(16), 1 << 20, C.c_void_p(16), n_keep,
                                     C.c_void_p(16), None) == -1
+
+
+def test_ngp_index_argument_checks_without_a_device():
+    L = B.lib()
+    m = B.splat_ngp(16, 2, 19, 16, 4096, 64, 0.05, (C.c_double * 3)(0, 0, 0), (C.c_double * 3)(1, 1, 1),
+                    *([C.c_void_p(16)] * 7))
+    n = 1000
+    assert L.splat_ngp_index_size(C.byref(m), n) >= 16 * 8 * n * 8      # (Gaussian, weight) pairs
+    assert L.splat_ngp_index_workspace_size(C.byref(m), n) >= 16 * 8 * n * 24
+    assert L.splat_ngp_index_size(None, n) == 0
+    assert L.splat_ngp_index_size(C.byref(m), (1 << 24) + 1) == 0
+    assert b"2^24" in L.splat_last_error()
+    assert L.splat_ngp_index_build(C.byref(m), None, n, None, 0, None, 0, None) == -1
+    assert L.splat_ngp_index_build(C.byref(m), C.c_void_p(16), n, C.c_void_p(16), 8, C.c_void_p(16), 1 << 40,
+                                   None) == -1
+    assert b"index of" in L.splat_last_error()
+    args = [C.c_void_p(16)] * 14
+    assert L.splat_ngp_bwd_indexed(C.byref(m), C.c_void_p(16), n, C.c_void_p(16), 1 << 40, *args[:4],
+                                   C.c_void_p(16), 8, *args[:7], None) == -1
+    assert b"workspace" in L.splat_last_error()

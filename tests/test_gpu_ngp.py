@@ -80,3 +80,102 @@ def test_ngp_backward_vs_oracle(name):
         ok, err = rel_close(grads[k].cpu().numpy(), ref[k], 1e-3)
         say(f"  {k}: {err:.2e}")
         assert ok, (k, err)
+
+
+def _bwd(model, xs, dd, ws, grads, index=None):
+    if index is None:
+        B.splat_ngp_bwd(model, xs, dd["quat"], dd["scale"], dd["opacity"], dd["color"], ws, grads["tables"],
+                        grads["w1"], grads["b1"], grads["w2"], grads["b2"], grads["w3"], grads["b3"])
+    else:
+        B.splat_ngp_bwd_indexed(model, xs, index, dd["quat"], dd["scale"], dd["opacity"], dd["color"], ws,
+                                grads["tables"], grads["w1"], grads["b1"], grads["w2"], grads["b2"], grads["w3"],
+                                grads["b3"])
+
+
+def _index(model, xs):
+    G = xs.shape[1]
+    index = torch.empty(B.splat_ngp_index_size(model, G), dtype=torch.uint8, device="cuda")
+    bws = torch.empty(B.splat_ngp_index_workspace_size(model, G), dtype=torch.uint8, device="cuda")
+    B.splat_ngp_index_build(model, xs, index, bws)
+    return index
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+@pytest.mark.parametrize("G", [5, 3000])
+def test_ngp_indexed_backward_vs_oracle_and_reproducible(name, G):
+    """Table gradients through the inverse index: the oracle's to 1e-3, the same weight
+    gradients as the atomic path bit for bit, and the same result on every call."""
+    cfg = CONFIGS[name]
+    say(f"case: ngp indexed backward {name} G={G}")
+    x, lo, hi, m = _case(cfg, max(G, 5), 4)
+    x = x[:G]
+    t, model = _gpu_model(cfg, lo, hi, m)
+    rng = np.random.default_rng(5)
+    d = dict(quat=rng.normal(size=(4, G)), scale=rng.normal(size=(3, G)), opacity=rng.normal(size=G),
+             color=rng.normal(size=(3, G)))
+    d["opacity"][::3] = 0.0
+    dd = {k: _dev(v.astype(np.float32)) for k, v in d.items()}
+    xs = _dev(x.T)
+    ws = torch.empty(B.splat_ngp_workspace_size(G), dtype=torch.uint8, device="cuda")
+    index = _index(model, xs)
+    runs = []
+    for _ in range(2):
+        grads = {k: torch.zeros_like(v) for k, v in t.items()}
+        _bwd(model, xs, dd, ws, grads, index)
+        torch.cuda.synchronize()
+        runs.append({k: v.cpu().numpy() for k, v in grads.items()})
+    for k in runs[0]:
+        assert np.array_equal(runs[0][k], runs[1][k]), k
+    scat = {k: torch.zeros_like(v) for k, v in t.items()}
+    _bwd(model, xs, dd, ws, scat)
+    torch.cuda.synchronize()
+    for k in ("w1", "b1", "w2", "b2", "w3", "b3"):
+        assert np.array_equal(runs[0][k], scat[k].cpu().numpy()), k
+    d32 = {k: v.astype(np.float32).astype(np.float64) for k, v in d.items()}
+    _, ref = N.params_and_grads(cfg, x.astype(np.float64), lo, hi, m, d32)
+    for k in ("tables", "w1", "w3"):
+        ok, err = rel_close(runs[0][k], ref[k], 1e-3)
+        say(f"  {k}: {err:.2e}")
+        assert ok, (k, err)
+    ok, err = rel_close(runs[0]["tables"], scat["tables"].cpu().numpy(), 1e-4)
+    assert ok, err
+
+
+def test_ngp_indexed_backward_at_two_million_gaussians():
+    """The drive scene's 2 M means, default grid: the indexed table gradient agrees with
+    the atomic one (float rounding apart) and is added to what dtables held."""
+    import synth
+    say("case: ngp indexed backward, 2M Gaussians")
+    pts = synth.batched64(seed=0).gauss.mean.astype(np.float64)
+    G = pts.shape[1]
+    cfg = CONFIGS["default"]
+    lo, hi = pts.min(axis=1) - 1.0, pts.max(axis=1) + 1.0
+    m = N.init_model(cfg, seed=7)
+    rng = np.random.default_rng(8)
+    m["tables"] = rng.uniform(-0.5, 0.5, size=m["tables"].shape).astype(np.float32)
+    t, model = _gpu_model(cfg, lo, hi, m)
+    xs = _dev(pts.astype(np.float32))
+    g = torch.Generator(device="cpu").manual_seed(9)
+    dd = {k: (torch.randn(s, generator=g) * 1e-3).to("cuda") for k, s in
+          (("quat", (4, G)), ("scale", (3, G)), ("opacity", (G,)), ("color", (3, G)))}
+    dd["opacity"][G // 2:] = 0.0
+    ws = torch.empty(B.splat_ngp_workspace_size(G), dtype=torch.uint8, device="cuda")
+    index = _index(model, xs)
+    gi = {k: torch.zeros_like(v) for k, v in t.items()}
+    _bwd(model, xs, dd, ws, gi, index)
+    gs = {k: torch.zeros_like(v) for k, v in t.items()}
+    _bwd(model, xs, dd, ws, gs)
+    # every row is written once, so onto a non-zero start the result is start + gradient in float32
+    base = torch.randn(t["tables"].shape, generator=g).to("cuda")
+    gb = base.clone()
+    gw = {k: torch.zeros_like(v) for k, v in t.items()}
+    gw["tables"] = gb
+    _bwd(model, xs, dd, ws, gw, index)
+    torch.cuda.synchronize()
+    a = gi["tables"].cpu().numpy()
+    ok, err = rel_close(a, gs["tables"].cpu().numpy(), 1e-4)
+    say(f"  tables vs atomics: {err:.2e}")
+    assert ok, err
+    assert np.array_equal(gb.cpu().numpy(), base.cpu().numpy() + a)
+    for k in ("w1", "b1", "w2", "b2", "w3", "b3"):
+        assert torch.equal(gi[k], gs[k]), k
