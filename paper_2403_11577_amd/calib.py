@@ -222,6 +222,21 @@ class Calibrator:
         if self.cfg.model == "field":
             self.field_ws = torch.empty(B.splat_ngp_workspace_size(G), dtype=torch.uint8, device=dev)
 
+    def _ensure_index(self):
+        """Inverse index of the field's table lookups for the current anchors (built once per
+        set of positions: the table adjoint then needs no atomics)."""
+        if getattr(self, "_index_mean", None) is self.win.mean:
+            return
+        self.field_index = None
+        G = self.win.n_gauss
+        self.field_index = torch.empty(B.splat_ngp_index_size(self.field_struct, G), dtype=torch.uint8,
+                                       device=self.device)
+        ws = torch.empty(B.splat_ngp_index_workspace_size(self.field_struct, G), dtype=torch.uint8,
+                         device=self.device)
+        B.splat_ngp_index_build(self.field_struct, self.win.mean, self.field_index, ws)
+        del ws
+        self._index_mean = self.win.mean
+
     def _enter_stage(self, i):
         """Stage i of the coarse-to-fine schedule: one point per voxel of the cloud, scales below the voxel."""
         voxel, n = self.cfg.stages[i]
@@ -231,6 +246,7 @@ class Calibrator:
         mean = self.cloud[:, keep].contiguous()
         self._set_points(mean)
         self._set_scale_max(voxel)
+        self._ensure_index()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         self.stage = i
@@ -308,8 +324,10 @@ class Calibrator:
             fg = self.field_grads
             for t in fg.values():
                 t.zero_()
-            B.splat_ngp_bwd(self.field_struct, w.mean, self.gr.quat, self.gr.scale, self.gr.opacity, self.gr.color,
-                            self.field_ws, fg["tables"], fg["w1"], fg["b1"], fg["w2"], fg["b2"], fg["w3"], fg["b3"])
+            self._ensure_index()
+            B.splat_ngp_bwd_indexed(self.field_struct, w.mean, self.field_index, self.gr.quat, self.gr.scale,
+                                    self.gr.opacity, self.gr.color, self.field_ws, fg["tables"], fg["w1"], fg["b1"],
+                                    fg["w2"], fg["b2"], fg["w3"], fg["b3"])
             for name, t in self.field.items():
                 t.grad = fg[name]
         frac = 1.0 - (1.0 - cfg.final_lr_frac) * min(1.0, k / max(1, cfg.steps - 1))

@@ -342,69 +342,119 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
     }
 }
 
-// C[ma][nb] = sum_r A_r[i] B_r[j] and s[ma] = sum_r A_r[i] over the rows r of a chunk
-// range, A_r = rows[r*R_LEN + aoff .. + ma), B_r = rows[r*R_LEN + boff .. + nb).
-// Each workgroup sums its own range in registers and writes its partial.
-constexpr int ATB_ROWS = 64;
+// C[MA][NB] = sum_r A_r[i] B_r[j] and s[MA] = sum_r A_r[i] over the rows r of a chunk
+// range, A_r = rows[r*R_LEN + aoff .. + MA), B_r = rows[r*R_LEN + boff .. + NB).  Each
+// workgroup sums its own range: rows are staged 32 at a time in LDS, every thread keeps a
+// 4 x 4 block of C in registers (two 16-byte LDS reads per 16 FMAs), and when C has fewer
+// than 256 such blocks the rows are split between thread groups whose sums are added in a
+// fixed order at the end.  The column sums s come from the threads that load A.
+constexpr int ATB_AR = 32;
 
-__global__ __launch_bounds__(256) void atb_kernel(const float *rows, int64_t n, int aoff, int ma, int boff, int nb,
-                                                 float *partial) {
-    __shared__ float sa[ATB_ROWS][NH + 1], sb[ATB_ROWS][NH + 1];
+template <int MA, int NB>
+__global__ __launch_bounds__(256) void atb_kernel(const float *rows, int64_t n, int aoff, int boff, float *partial) {
+    constexpr int TI = MA / 4, TJ = NB / 4, TT = TI * TJ, RS = 256 / TT;
+    constexpr int NA = ATB_AR * TI, NBV = ATB_AR * TJ;  // float4 loads per stage
+    // a thread always loads the same A column (t mod TI), which the column sums rely on
+    static_assert(MA % 4 == 0 && NB % 4 == 0 && TT <= 256 && (NA <= 256 || 256 % TI == 0), "atb tile shape");
+    __shared__ float4 sa[ATB_AR][TI], sb[ATB_AR][TJ];
+    __shared__ float red[RS > 1 ? 256 * 16 : 1];
+    __shared__ float4 bred[256];
     const int t = threadIdx.x;
-    const int ne = ma * nb + ma;
-    constexpr int KE = (NH * NH + NH + 255) / 256;
-    float acc[KE];
+    const int q = t / TT, tt = t - q * TT, ti = tt / TJ, tj = tt - ti * TJ;
+    float acc[16];
 #pragma unroll
-    for (int k = 0; k < KE; ++k) acc[k] = 0.f;
-    int64_t per = (n + gridDim.x - 1) / gridDim.x;
-    int64_t r0 = (int64_t)blockIdx.x * per, r1 = r0 + per < n ? r0 + per : n;
-    for (int64_t base = r0; base < r1; base += ATB_ROWS) {
-        int cnt = (int)(r1 - base < ATB_ROWS ? r1 - base : ATB_ROWS);
-        for (int i = t; i < ATB_ROWS * NH; i += 256) {
-            int r = i / NH, c = i - r * NH;
-            bool ok = r < cnt;
-            sa[r][c] = ok && c < ma ? rows[(base + r) * R_LEN + aoff + c] : 0.f;
-            sb[r][c] = ok && c < nb ? rows[(base + r) * R_LEN + boff + c] : 0.f;
+    for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+    float4 bs = make_float4(0.f, 0.f, 0.f, 0.f);  // column sums of the A values this thread loads
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = r0 + per < n ? r0 + per : n;
+    for (int64_t base = r0; base < r1; base += ATB_AR) {
+        const int cnt = (int)(r1 - base < ATB_AR ? r1 - base : ATB_AR);
+        for (int i = t; i < NA; i += 256) {
+            int r = i / TI, c = i - r * TI;
+            float4 v = r < cnt ? *reinterpret_cast<const float4 *>(rows + (base + r) * R_LEN + aoff + 4 * c)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+            sa[r][c] = v;
+            bs.x += v.x;
+            bs.y += v.y;
+            bs.z += v.z;
+            bs.w += v.w;
+        }
+        for (int i = t; i < NBV; i += 256) {
+            int r = i / TJ, c = i - r * TJ;
+            sb[r][c] = r < cnt ? *reinterpret_cast<const float4 *>(rows + (base + r) * R_LEN + boff + 4 * c)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
         }
         __syncthreads();
+        if (q < RS) {
+#pragma unroll 4
+            for (int r = q; r < ATB_AR; r += RS) {
+                const float4 a = sa[r][ti], bv = sb[r][tj];
+                const float av[4] = {a.x, a.y, a.z, a.w}, bw[4] = {bv.x, bv.y, bv.z, bv.w};
 #pragma unroll
-        for (int k = 0; k < KE; ++k) {
-            int e = t + 256 * k;
-            if (e >= ne) break;
-            float s = acc[k];
-            if (e < ma * nb) {
-                int i = e / nb, j = e - i * nb;
-#pragma unroll 8
-                for (int r = 0; r < ATB_ROWS; ++r) s = __fmaf_rn(sa[r][i], sb[r][j], s);
-            } else {
-                int i = e - ma * nb;
-#pragma unroll 8
-                for (int r = 0; r < ATB_ROWS; ++r) s += sa[r][i];
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[4 * i + j] = __fmaf_rn(av[i], bw[j], acc[4 * i + j]);
             }
-            acc[k] = s;
         }
         __syncthreads();
     }
+    constexpr int NE = MA * NB + MA;
+    float *out = partial + (int64_t)blockIdx.x * NE;
+    // row groups, added in order
+    if (RS > 1) {
+        if (q < RS && q > 0)
 #pragma unroll
-    for (int k = 0; k < KE; ++k) {
-        int e = t + 256 * k;
-        if (e < ne) partial[(int64_t)blockIdx.x * ne + e] = acc[k];
+            for (int k = 0; k < 16; ++k) red[(q * TT + tt) * 16 + k] = acc[k];
+        __syncthreads();
+        if (q == 0)
+            for (int g = 1; g < RS; ++g)
+#pragma unroll
+                for (int k = 0; k < 16; ++k) acc[k] += red[(g * TT + tt) * 16 + k];
+    }
+    if (q == 0)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) out[(4 * ti + i) * NB + 4 * tj + j] = acc[4 * i + j];
+    // column sums: thread t loaded column t mod TI of every row it staged
+    bred[t] = bs;
+    __syncthreads();
+    if (t < TI) {
+        float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int u = t; u < 256; u += TI) {
+            float4 v = bred[u];
+            s4.x += v.x;
+            s4.y += v.y;
+            s4.z += v.z;
+            s4.w += v.w;
+        }
+        out[MA * NB + 4 * t] = s4.x;
+        out[MA * NB + 4 * t + 1] = s4.y;
+        out[MA * NB + 4 * t + 2] = s4.z;
+        out[MA * NB + 4 * t + 3] = s4.w;
     }
 }
 
-// out[e] += sum over workgroups of partial[g][e] (fixed order); e < ma*nb goes to dw, the rest to db
-__global__ void atb_reduce_kernel(const float *partial, int ngroups, int ma, int nb, int din_w, float *dw,
-                                  float *db) {
-    int ne = ma * nb + ma;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int g = 0; g < ngroups; ++g) s += (double)partial[(int64_t)g * ne + e];
-        if (e < ma * nb) {
-            int i = e / nb, j = e - i * nb;
-            if (j < din_w) dw[i * din_w + j] += (float)s;
-        } else {
-            db[e - ma * nb] += (float)s;
-        }
+// out[e] += sum over workgroups of partial[g][e], in float64 and a fixed order (four
+// interleaved sums added in order); e < ma*nb is (i, j) of dw (i < mreal, j < din_w), the
+// rest db[i] (i < mreal)
+__global__ __launch_bounds__(256) void atb_reduce_kernel(const float *partial, int ngroups, int ma, int nb, int mreal,
+                                                        int din_w, float *dw, float *db) {
+    __shared__ double part[4][64];
+    const int ne = ma * nb + ma;
+    const int e = blockIdx.x * 64 + (threadIdx.x & 63), qg = threadIdx.x >> 6;
+    double s = 0.0;
+    if (e < ne)
+        for (int g = qg; g < ngroups; g += 4) s += (double)partial[(int64_t)g * ne + e];
+    part[qg][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (qg != 0 || e >= ne) return;
+    s = ((part[0][threadIdx.x] + part[1][threadIdx.x]) + part[2][threadIdx.x]) + part[3][threadIdx.x];
+    if (e < ma * nb) {
+        int i = e / nb, j = e - i * nb;
+        if (i < mreal && j < din_w) dw[i * din_w + j] += (float)s;
+    } else if (e - ma * nb < mreal) {
+        db[e - ma * nb] += (float)s;
     }
 }
 
@@ -758,22 +808,30 @@ int launch_ngp_index_build(const splat_ngp &m, const float *mean, int64_t n, voi
 }
 
 namespace {
+// weight gradients: dW3 = sum dOut^T h2 (11 x 64, dOut padded to 12), dW2 = sum dh2^T h1,
+// dW1 = sum dh1^T enc (enc padded to 32 columns); biases are the column sums of the deltas
 int launch_atb_jobs(const splat_ngp &m, int64_t n, float *rows, float *partial, float *dw1, float *db1, float *dw2,
                     float *db2, float *dw3, float *db3, hipStream_t st) {
-    int din = 2 * m.levels;
-    struct Job { int aoff, ma, boff, nb, dinw; float *dw, *db; };
-    Job jobs[3] = {{R_DOUT, NO, R_H2, NH, NH, dw3, db3}, {R_DH2, NH, R_H1, NH, NH, dw2, db2},
-                   {R_DH1, NH, R_ENC, din, din, dw1, db1}};
+    const int din = 2 * m.levels;
     int rc;
-    for (const Job &j : jobs) {
-        hipLaunchKernelGGL(atb_kernel, dim3(ATB_GROUPS), dim3(256), 0, st, rows, n, j.aoff, j.ma, j.boff, j.nb,
-                           partial);
-        if ((rc = launch_status("ngp_atb"))) return rc;
-        hipLaunchKernelGGL(atb_reduce_kernel, dim3(16), dim3(256), 0, st, partial, ATB_GROUPS, j.ma, j.nb, j.dinw,
-                           j.dw, j.db);
-        if ((rc = launch_status("ngp_atb_reduce"))) return rc;
-    }
-    return 0;
+    auto reduce = [&](int ma, int nb, int mreal, int dinw, float *dw, float *db) {
+        int ne = ma * nb + ma;
+        hipLaunchKernelGGL(atb_reduce_kernel, dim3((unsigned)((ne + 63) / 64)), dim3(256), 0, st, partial, ATB_GROUPS,
+                           ma, nb, mreal, dinw, dw, db);
+        return launch_status("ngp_atb_reduce");
+    };
+    hipLaunchKernelGGL((atb_kernel<12, NH>), dim3(ATB_GROUPS), dim3(256), 0, st, rows, n, (int)R_DOUT, (int)R_H2,
+                       partial);
+    if ((rc = launch_status("ngp_atb"))) return rc;
+    if ((rc = reduce(12, NH, NO, NH, dw3, db3))) return rc;
+    hipLaunchKernelGGL((atb_kernel<NH, NH>), dim3(ATB_GROUPS), dim3(256), 0, st, rows, n, (int)R_DH2, (int)R_H1,
+                       partial);
+    if ((rc = launch_status("ngp_atb"))) return rc;
+    if ((rc = reduce(NH, NH, NH, NH, dw2, db2))) return rc;
+    hipLaunchKernelGGL((atb_kernel<NH, ND>), dim3(ATB_GROUPS), dim3(256), 0, st, rows, n, (int)R_DH1, (int)R_ENC,
+                       partial);
+    if ((rc = launch_status("ngp_atb"))) return rc;
+    return reduce(NH, ND, NH, din, dw1, db1);
 }
 }  // namespace
 
