@@ -129,10 +129,26 @@ def measure_beyond_render(ds, settings, targets, img, reps=10):
     gf = {k: torch.zeros_like(v) for k, v in f.items()}
     bwd_ms = _event_ms(lambda: B.splat_ngp_bwd(m, ds.mean, d["q"], d["s"], d["o"], d["c"], fws, gf["tables"],
                                                gf["w1"], gf["b1"], gf["w2"], gf["b2"], gf["w3"], gf["b3"]), 3)
-    out["field"] = {"gaussians": G, "fwd_ms": round(fwd_ms, 3), "bwd_ms": round(bwd_ms, 3),
+    index = torch.empty(B.splat_ngp_index_size(m, G), dtype=torch.uint8, device=dev)
+    iws = torch.empty(B.splat_ngp_index_workspace_size(m, G), dtype=torch.uint8, device=dev)
+    build_ms = _event_ms(lambda: B.splat_ngp_index_build(m, ds.mean, index, iws), 1)
+    del iws
+    torch.cuda.empty_cache()
+    bwdi_ms = _event_ms(lambda: B.splat_ngp_bwd_indexed(m, ds.mean, index, d["q"], d["s"], d["o"], d["c"], fws,
+                                                        gf["tables"], gf["w1"], gf["b1"], gf["w2"], gf["b2"],
+                                                        gf["w3"], gf["b3"]), reps)
+    fwdt_ms = _event_ms(lambda: B.splat_ngp_fwd_train(m, ds.mean, q, sc, op, co, fws), reps)
+    bwds_ms = _event_ms(lambda: B.splat_ngp_bwd_saved(m, G, index, d["q"], d["s"], d["o"], d["c"], fws,
+                                                      gf["tables"], gf["w1"], gf["b1"], gf["w2"], gf["b2"],
+                                                      gf["w3"], gf["b3"]), reps)
+    out["field"] = {"gaussians": G, "fwd_ms": round(fwd_ms, 3), "bwd_atomic_ms": round(bwd_ms, 3),
+                    "bwd_indexed_ms": round(bwdi_ms, 3), "index_build_ms": round(build_ms, 3),
+                    "train_fwd_ms": round(fwdt_ms, 3), "train_bwd_ms": round(bwds_ms, 3),
+                    "train_step_ms": round(fwdt_ms + bwds_ms, 3),
                     "fwd_mgauss_s": round(G / (fwd_ms * 1e-3) / 1e6, 1)}
-    log(f"[bench] field: fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms")
-    del f, gf, fws, d, q, sc, op, co
+    log(f"[bench] field: fwd {fwd_ms:.3f} ms, bwd atomic {bwd_ms:.3f} ms, bwd indexed {bwdi_ms:.3f} ms, "
+        f"index build {build_ms:.3f} ms; training pair {fwdt_ms:.3f} + {bwds_ms:.3f} ms")
+    del f, gf, fws, d, q, sc, op, co, index
     torch.cuda.empty_cache()
     # voxel downsampling of a 40-scan accumulated drive cloud at the schedule's three sizes
     pts = torch.as_tensor(synth.drive_scans(seed=0), device=dev)

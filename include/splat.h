@@ -327,7 +327,7 @@ SPLAT_API int splat_ngp_fwd(const splat_ngp *m, const float *mean, int64_t n, fl
                             float *opacity, float *color, void *stream);
 
 /* Device scratch of splat_ngp_bwd and splat_ngp_bwd_indexed for n Gaussians
- * (per-Gaussian activations and deltas, 1328 bytes each, encoding gradients,
+ * (per-Gaussian activations and deltas, 1392 bytes each, encoding gradients,
  * 128 bytes each, the weight-gradient partials and the index reduction's
  * carries). */
 SPLAT_API size_t splat_ngp_workspace_size(int64_t n);
@@ -389,6 +389,21 @@ SPLAT_API int splat_ngp_bwd_indexed(const splat_ngp *m, const float *mean, int64
                                     const float *dopacity, const float *dcolor, void *ws, size_t ws_bytes,
                                     float *dtables, float *dw1, float *db1, float *dw2, float *db2, float *dw3,
                                     float *db3, void *stream);
+
+/* Training pair.  splat_ngp_fwd_train is splat_ngp_fwd that also keeps in ws
+ * (splat_ngp_workspace_size(n) bytes) what the adjoint needs: per Gaussian the
+ * encoding, both hidden layers, the outputs before the heads and the ReLU
+ * masks.  splat_ngp_bwd_saved is splat_ngp_bwd_indexed computed from those
+ * values instead of evaluating the field again (the positions are not read);
+ * it is valid only while ws, the tables and the weights are those of the last
+ * splat_ngp_fwd_train call on this ws, and it overwrites the deltas in ws (the
+ * forward values stay, so it may be called again). */
+SPLAT_API int splat_ngp_fwd_train(const splat_ngp *m, const float *mean, int64_t n, float *quat, float *scale,
+                                  float *opacity, float *color, void *ws, size_t ws_bytes, void *stream);
+SPLAT_API int splat_ngp_bwd_saved(const splat_ngp *m, int64_t n, const void *index, size_t index_bytes,
+                                  const float *dquat, const float *dscale, const float *dopacity,
+                                  const float *dcolor, void *ws, size_t ws_bytes, float *dtables, float *dw1,
+                                  float *db1, float *dw2, float *db2, float *dw3, float *db3, void *stream);
 
 /* Text of the last synchronous error on this thread ("" if none). */
 SPLAT_API const char *splat_last_error(void);

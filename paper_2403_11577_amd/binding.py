@@ -102,6 +102,9 @@ def lib():
     L.splat_ngp_index_build.argtypes = [C.POINTER(splat_ngp), P, I64, P, C.c_size_t, P, C.c_size_t, P]
     L.splat_ngp_bwd_indexed.argtypes = [C.POINTER(splat_ngp), P, I64, P, C.c_size_t, P, P, P, P, P, C.c_size_t,
                                         P, P, P, P, P, P, P, P]
+    L.splat_ngp_fwd_train.argtypes = [C.POINTER(splat_ngp), P, I64, P, P, P, P, P, C.c_size_t, P]
+    L.splat_ngp_bwd_saved.argtypes = [C.POINTER(splat_ngp), I64, P, C.c_size_t, P, P, P, P, P, C.c_size_t,
+                                      P, P, P, P, P, P, P, P]
     L.splat_voxel_workspace_size.argtypes = [I64]
     L.splat_voxel_workspace_size.restype = C.c_size_t
     L.splat_voxel_downsample.argtypes = [P, I64, C.POINTER(C.c_double), C.c_double, P, C.c_size_t, P, P, P, P]
@@ -278,6 +281,21 @@ def splat_ngp_bwd_indexed(model: splat_ngp, mean, index, dquat, dscale, dopacity
                                        _ptr(dopacity), _ptr(dcolor), _ptr(ws), int(ws.numel() * ws.element_size()),
                                        _ptr(dtables), _ptr(dw1), _ptr(db1), _ptr(dw2), _ptr(db2), _ptr(dw3),
                                        _ptr(db3), _stream(stream)), "splat_ngp_bwd_indexed")
+
+
+def splat_ngp_fwd_train(model: splat_ngp, mean, quat, scale, opacity, color, ws, stream=None):
+    _check(lib().splat_ngp_fwd_train(C.byref(model), _ptr(mean), int(mean.shape[1]), _ptr(quat), _ptr(scale),
+                                     _ptr(opacity), _ptr(color), _ptr(ws), int(ws.numel() * ws.element_size()),
+                                     _stream(stream)), "splat_ngp_fwd_train")
+
+
+def splat_ngp_bwd_saved(model: splat_ngp, n, index, dquat, dscale, dopacity, dcolor, ws, dtables, dw1, db1, dw2,
+                        db2, dw3, db3, stream=None):
+    _check(lib().splat_ngp_bwd_saved(C.byref(model), int(n), _ptr(index), int(index.numel() * index.element_size()),
+                                     _ptr(dquat), _ptr(dscale), _ptr(dopacity), _ptr(dcolor), _ptr(ws),
+                                     int(ws.numel() * ws.element_size()), _ptr(dtables), _ptr(dw1), _ptr(db1),
+                                     _ptr(dw2), _ptr(db2), _ptr(dw3), _ptr(db3), _stream(stream)),
+           "splat_ngp_bwd_saved")
 
 
 def splat_voxel_workspace_size(n) -> int:

@@ -299,7 +299,8 @@ class Calibrator:
                 w.color.copy_(self.color)
                 w.quat.copy_(self.quat)
             else:
-                B.splat_ngp_fwd(self.field_struct, w.mean, w.quat, w.scale, w.opacity, w.color)
+                self._ensure_index()
+                B.splat_ngp_fwd_train(self.field_struct, w.mean, w.quat, w.scale, w.opacity, w.color, self.field_ws)
             self.xi_t[:, :3].copy_(self.rho)
             self.xi_t[:, 3:].copy_(self.phi)
             self.dl_t.copy_(self.delta)
@@ -324,10 +325,9 @@ class Calibrator:
             fg = self.field_grads
             for t in fg.values():
                 t.zero_()
-            self._ensure_index()
-            B.splat_ngp_bwd_indexed(self.field_struct, w.mean, self.field_index, self.gr.quat, self.gr.scale,
-                                    self.gr.opacity, self.gr.color, self.field_ws, fg["tables"], fg["w1"], fg["b1"],
-                                    fg["w2"], fg["b2"], fg["w3"], fg["b3"])
+            B.splat_ngp_bwd_saved(self.field_struct, w.n_gauss, self.field_index, self.gr.quat, self.gr.scale,
+                                  self.gr.opacity, self.gr.color, self.field_ws, fg["tables"], fg["w1"], fg["b1"],
+                                  fg["w2"], fg["b2"], fg["w3"], fg["b3"])
             for name, t in self.field.items():
                 t.grad = fg[name]
         frac = 1.0 - (1.0 - cfg.final_lr_frac) * min(1.0, k / max(1, cfg.steps - 1))

@@ -460,6 +460,40 @@ int splat_ngp_bwd_indexed(const splat_ngp *m, const float *mean, int64_t n, cons
                                   db2, dw3, db3, (hipStream_t)stream);
 }
 
+int splat_ngp_fwd_train(const splat_ngp *m, const float *mean, int64_t n, float *quat, float *scale,
+                        float *opacity, float *color, void *ws, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    int rc = check_ngp(m, "ngp_fwd_train");
+    if (rc) return rc;
+    if (n < 0 || n >= ((int64_t)1 << 31)) { set_error("ngp_fwd_train: n outside [0, 2^31)"); return SPLAT_EINVAL; }
+    if (n == 0) return SPLAT_OK;
+    if (!mean || !quat || !scale || !opacity || !color || !ws) {
+        set_error("ngp_fwd_train: NULL argument"); return SPLAT_EINVAL;
+    }
+    size_t need = ngp_ws_bytes(n);
+    if (ws_bytes < need) { set_error("ngp_fwd_train: workspace of %zu bytes, %zu needed", ws_bytes, need); return SPLAT_EINVAL; }
+    return launch_ngp_fwd_train(*m, mean, n, quat, scale, opacity, color, ws, (hipStream_t)stream);
+}
+
+int splat_ngp_bwd_saved(const splat_ngp *m, int64_t n, const void *index, size_t index_bytes, const float *dquat,
+                        const float *dscale, const float *dopacity, const float *dcolor, void *ws, size_t ws_bytes,
+                        float *dtables, float *dw1, float *db1, float *dw2, float *db2, float *dw3, float *db3,
+                        void *stream) {
+    g_err[0] = 0;
+    int rc = check_ngp_index(m, n, "ngp_bwd_saved");
+    if (rc) return rc;
+    if (n == 0) return SPLAT_OK;
+    if (!index || !dquat || !dscale || !dopacity || !dcolor || !ws || !dtables || !dw1 || !db1 || !dw2 || !db2 ||
+        !dw3 || !db3) {
+        set_error("ngp_bwd_saved: NULL argument"); return SPLAT_EINVAL;
+    }
+    size_t ni = ngp_index_bytes(*m, n), nw = ngp_ws_bytes(n);
+    if (index_bytes < ni) { set_error("ngp_bwd_saved: index of %zu bytes, %zu needed", index_bytes, ni); return SPLAT_EINVAL; }
+    if (ws_bytes < nw) { set_error("ngp_bwd_saved: workspace of %zu bytes, %zu needed", ws_bytes, nw); return SPLAT_EINVAL; }
+    return launch_ngp_bwd_saved(*m, n, index, dquat, dscale, dopacity, dcolor, ws, dtables, dw1, db1, dw2, db2, dw3,
+                                db3, (hipStream_t)stream);
+}
+
 size_t splat_voxel_workspace_size(int64_t n) { return n < 0 ? 0 : voxel_ws_bytes(n); }
 
 int splat_voxel_downsample(const float *pts, int64_t n, const double *lo, double voxel, void *ws, size_t ws_bytes,

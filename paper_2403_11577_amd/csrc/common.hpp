@@ -95,6 +95,11 @@ int launch_ngp_index_build(const splat_ngp &m, const float *mean, int64_t n, voi
 int launch_ngp_bwd_indexed(const splat_ngp &m, const float *mean, int64_t n, const void *index, const float *dquat,
                            const float *dscale, const float *dopac, const float *dcolor, void *ws, float *dtables,
                            float *dw1, float *db1, float *dw2, float *db2, float *dw3, float *db3, hipStream_t st);
+int launch_ngp_fwd_train(const splat_ngp &m, const float *mean, int64_t n, float *quat, float *scale, float *opac,
+                         float *color, void *ws, hipStream_t st);
+int launch_ngp_bwd_saved(const splat_ngp &m, int64_t n, const void *index, const float *dquat, const float *dscale,
+                         const float *dopac, const float *dcolor, void *ws, float *dtables, float *dw1, float *db1,
+                         float *dw2, float *db2, float *dw3, float *db3, hipStream_t st);
 int launch_dssim(const float *img, const float *target, int64_t n_views, int32_t width, int32_t height,
                  int32_t roi_y0, double weight, void *ws, float *dimg, double *loss, hipStream_t st);
 

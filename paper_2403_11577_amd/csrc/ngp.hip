@@ -140,8 +140,10 @@ __device__ __forceinline__ void scatter2(float *tab, uint32_t r, float a0, float
 }
 
 // Row layout of the stored activations and deltas (floats per Gaussian).
+// R_O: the 11 outputs before the heads, R_MASK: the two ReLU masks (64-bit each, as floats).
 enum { R_DOUT = 0, R_H2 = 12, R_DH2 = R_H2 + NH, R_H1 = R_DH2 + NH, R_DH1 = R_H1 + NH, R_ENC = R_DH1 + NH,
-       R_DE = R_ENC + ND, R_LEN = R_DE + ND };
+       R_DE = R_ENC + ND, R_O = R_DE + ND, R_MASK = R_O + 12, R_LEN = R_MASK + 4 };
+static_assert(R_LEN % 4 == 0, "rows are read as float4");
 
 struct Weights {
     float w1[NH][ND], b1[NH], w2[NH][NH], b2[NH], w3[NO][NH], b3[NO];
@@ -214,10 +216,14 @@ __device__ __forceinline__ void field(const NgpArgs &a, const float2 *tables, co
 
 __device__ __forceinline__ float sigm(float x) { return 1.f / (1.f + __expf(-x)); }
 
+// SAVE: also store what the adjoint needs (encoding, hidden layers, outputs, ReLU masks) in
+// the per-Gaussian rows, so that it does not evaluate the field again
+template <bool SAVE>
 __global__ __launch_bounds__(256, 2) void ngp_fwd_kernel(NgpArgs a, const float *mean, int64_t n, const float2 *tables,
                                                      const float *w1, const float *b1, const float *w2,
                                                      const float *b2, const float *w3, const float *b3,
-                                                     float *quat, float *scale, float *opac, float *color) {
+                                                     float *quat, float *scale, float *opac, float *color,
+                                                     float *rows) {
     __shared__ Weights W;
     load_weights(W, w1, b1, w2, b2, w3, b3, 2 * a.levels);
     __syncthreads();
@@ -226,7 +232,14 @@ __global__ __launch_bounds__(256, 2) void ngp_fwd_kernel(NgpArgs a, const float 
         normalise(a, mean, n, i, xn);
         float o[NO];
         uint64_t m1 = 0, m2 = 0;
-        field<false>(a, tables, W, xn, o, nullptr, m1, m2);
+        float *row = SAVE ? rows + i * R_LEN : nullptr;
+        field<SAVE>(a, tables, W, xn, o, row, m1, m2);
+        if (SAVE) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) row[R_O + k] = k < NO ? o[k] : 0.f;
+            *reinterpret_cast<uint4 *>(row + R_MASK) =
+                make_uint4((uint32_t)m1, (uint32_t)(m1 >> 32), (uint32_t)m2, (uint32_t)(m2 >> 32));
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) color[c * n + i] = sigm(o[c]);
         opac[i] = sigm(o[3]);
@@ -238,9 +251,10 @@ __global__ __launch_bounds__(256, 2) void ngp_fwd_kernel(NgpArgs a, const float 
     }
 }
 
-// SCATTER: table gradients by atomics into dtables; else the encoding gradients go to
-// dEc[level][Gaussian] for the indexed reduction.
-template <bool SCATTER>
+// MODE 0: table gradients by atomics into dtables; MODE 1: the encoding gradients go to
+// dEc[level][Gaussian] for the indexed reduction; MODE 2: as 1, with the forward's values
+// read from the rows stored by the training forward instead of evaluated again.
+template <int MODE>
 __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float *mean, int64_t n,
                                                         const float2 *tables, const float *w1, const float *b1,
                                                         const float *w2, const float *b2, const float *w3,
@@ -257,12 +271,22 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
         const bool live = i0 < n;
         const int64_t i = live ? i0 : n - 1;
         double xn[3];
-        normalise(a, mean, n, i, xn);
         float *row = rows + (live ? i : n) * R_LEN;  // row n: scratch of the lanes past the end
-        // forward again; activations go to the row store at once
         float o[NO];
         uint64_t m1 = 0, m2 = 0;  // ReLU masks of the two hidden layers
-        field<true>(a, tables, W, xn, o, row, m1, m2);
+        if (MODE == 2) {
+            // the training forward's values (row i also for the lanes past the end: their gradient is 0)
+            const float *src = rows + i * R_LEN;
+#pragma unroll
+            for (int k = 0; k < NO; ++k) o[k] = src[R_O + k];
+            uint4 mk = *reinterpret_cast<const uint4 *>(src + R_MASK);
+            m1 = (uint64_t)mk.x | ((uint64_t)mk.y << 32);
+            m2 = (uint64_t)mk.z | ((uint64_t)mk.w << 32);
+        } else {
+            // forward again; activations go to the row store at once
+            normalise(a, mean, n, i, xn);
+            field<true>(a, tables, W, xn, o, row, m1, m2);
+        }
         // heads
         float d[NO];
 #pragma unroll
@@ -314,7 +338,7 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
                 for (int e = 0; e < ND; ++e) de[e] = __fmaf_rn(W.w1[j][e], dh, de[e]);
             }
         }
-        if (!SCATTER) {
+        if (MODE != 0) {
             if (live)
 #pragma unroll
                 for (int l = 0; l < NL; ++l)
@@ -835,9 +859,13 @@ int launch_atb_jobs(const splat_ngp &m, int64_t n, float *rows, float *partial, 
 }
 }  // namespace
 
-int launch_ngp_bwd_indexed(const splat_ngp &m, const float *mean, int64_t n, const void *index, const float *dquat,
-                           const float *dscale, const float *dopac, const float *dcolor, void *ws, float *dtables,
-                           float *dw1, float *db1, float *dw2, float *db2, float *dw3, float *db3, hipStream_t st) {
+namespace {
+// adjoint with the table gradients through the index; saved: the forward's values come from
+// the rows of the training forward (mean and the tables are not read)
+int ngp_bwd_via_index(const splat_ngp &m, const float *mean, int64_t n, const void *index, const float *dquat,
+                      const float *dscale, const float *dopac, const float *dcolor, void *ws, float *dtables,
+                      float *dw1, float *db1, float *dw2, float *db2, float *dw3, float *db3, bool saved,
+                      hipStream_t st) {
     NgpArgs a;
     ngp_args(m, a);
     const WsLayout W = ws_layout(n);
@@ -846,9 +874,13 @@ int launch_ngp_bwd_indexed(const splat_ngp &m, const float *mean, int64_t n, con
     float2 *dEc = ws_at<float2>(ws, W.dec);
     int64_t nb = (n + 255) / 256;
     if (nb > 8192) nb = 8192;
-    hipLaunchKernelGGL(ngp_bwd_kernel<false>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n,
-                       reinterpret_cast<const float2 *>(m.tables), m.w1, m.b1, m.w2, m.b2, m.w3, m.b3, dquat, dscale,
-                       dopac, dcolor, dtables, rows, dEc);
+    const float2 *tab = reinterpret_cast<const float2 *>(m.tables);
+    if (saved)
+        hipLaunchKernelGGL(ngp_bwd_kernel<2>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n, tab, m.w1, m.b1,
+                           m.w2, m.b2, m.w3, m.b3, dquat, dscale, dopac, dcolor, dtables, rows, dEc);
+    else
+        hipLaunchKernelGGL(ngp_bwd_kernel<1>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n, tab, m.w1, m.b1,
+                           m.w2, m.b2, m.w3, m.b3, dquat, dscale, dopac, dcolor, dtables, rows, dEc);
     int rc = launch_status("ngp_bwd");
     if (rc) return rc;
     void *ix = const_cast<void *>(index);
@@ -865,16 +897,45 @@ int launch_ngp_bwd_indexed(const splat_ngp &m, const float *mean, int64_t n, con
     return launch_atb_jobs(m, n, rows, ws_at<float>(ws, W.partial), dw1, db1, dw2, db2, dw3, db3, st);
 }
 
-int launch_ngp_fwd(const splat_ngp &m, const float *mean, int64_t n, float *quat, float *scale, float *opac,
-                   float *color, hipStream_t st) {
+int ngp_fwd(const splat_ngp &m, const float *mean, int64_t n, float *quat, float *scale, float *opac, float *color,
+            float *rows, hipStream_t st) {
     NgpArgs a;
     ngp_args(m, a);
     int64_t nb = (n + 255) / 256;
     if (nb > 8192) nb = 8192;
-    hipLaunchKernelGGL(ngp_fwd_kernel, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n,
-                       reinterpret_cast<const float2 *>(m.tables), m.w1, m.b1, m.w2, m.b2, m.w3, m.b3, quat, scale,
-                       opac, color);
+    const float2 *tab = reinterpret_cast<const float2 *>(m.tables);
+    if (rows)
+        hipLaunchKernelGGL(ngp_fwd_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n, tab, m.w1, m.b1,
+                           m.w2, m.b2, m.w3, m.b3, quat, scale, opac, color, rows);
+    else
+        hipLaunchKernelGGL(ngp_fwd_kernel<false>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n, tab, m.w1, m.b1,
+                           m.w2, m.b2, m.w3, m.b3, quat, scale, opac, color, rows);
     return launch_status("ngp_fwd");
+}
+}  // namespace
+
+int launch_ngp_bwd_indexed(const splat_ngp &m, const float *mean, int64_t n, const void *index, const float *dquat,
+                           const float *dscale, const float *dopac, const float *dcolor, void *ws, float *dtables,
+                           float *dw1, float *db1, float *dw2, float *db2, float *dw3, float *db3, hipStream_t st) {
+    return ngp_bwd_via_index(m, mean, n, index, dquat, dscale, dopac, dcolor, ws, dtables, dw1, db1, dw2, db2, dw3,
+                             db3, false, st);
+}
+
+int launch_ngp_bwd_saved(const splat_ngp &m, int64_t n, const void *index, const float *dquat, const float *dscale,
+                         const float *dopac, const float *dcolor, void *ws, float *dtables, float *dw1, float *db1,
+                         float *dw2, float *db2, float *dw3, float *db3, hipStream_t st) {
+    return ngp_bwd_via_index(m, nullptr, n, index, dquat, dscale, dopac, dcolor, ws, dtables, dw1, db1, dw2, db2, dw3,
+                             db3, true, st);
+}
+
+int launch_ngp_fwd(const splat_ngp &m, const float *mean, int64_t n, float *quat, float *scale, float *opac,
+                   float *color, hipStream_t st) {
+    return ngp_fwd(m, mean, n, quat, scale, opac, color, nullptr, st);
+}
+
+int launch_ngp_fwd_train(const splat_ngp &m, const float *mean, int64_t n, float *quat, float *scale, float *opac,
+                         float *color, void *ws, hipStream_t st) {
+    return ngp_fwd(m, mean, n, quat, scale, opac, color, ws_at<float>(ws, ws_layout(n).rows), st);
 }
 
 int launch_ngp_bwd(const splat_ngp &m, const float *mean, int64_t n, const float *dquat, const float *dscale,
@@ -886,7 +947,7 @@ int launch_ngp_bwd(const splat_ngp &m, const float *mean, int64_t n, const float
     float *rows = ws_at<float>(ws, W.rows);
     int64_t nb = (n + 255) / 256;
     if (nb > 8192) nb = 8192;
-    hipLaunchKernelGGL(ngp_bwd_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n,
+    hipLaunchKernelGGL(ngp_bwd_kernel<0>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n,
                        reinterpret_cast<const float2 *>(m.tables), m.w1, m.b1, m.w2, m.b2, m.w3, m.b3, dquat, dscale,
                        dopac, dcolor, dtables, rows, nullptr);
     int rc = launch_status("ngp_bwd");

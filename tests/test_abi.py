@@ -181,3 +181,18 @@ def test_ngp_index_argument_checks_without_a_device():
     assert L.splat_ngp_bwd_indexed(C.byref(m), C.c_void_p(16), n, C.c_void_p(16), 1 << 40, *args[:4],
                                    C.c_void_p(16), 8, *args[:7], None) == -1
     assert b"workspace" in L.splat_last_error()
+
+
+def test_ngp_training_pair_argument_checks_without_a_device():
+    L = B.lib()
+    m = B.splat_ngp(16, 2, 19, 16, 4096, 64, 0.05, (C.c_double * 3)(0, 0, 0), (C.c_double * 3)(1, 1, 1),
+                    *([C.c_void_p(16)] * 7))
+    p = C.c_void_p(16)
+    assert L.splat_ngp_fwd_train(C.byref(m), p, 100, p, p, p, p, None, 0, None) == -1
+    assert b"NULL" in L.splat_last_error()
+    assert L.splat_ngp_fwd_train(C.byref(m), p, 100, p, p, p, p, p, 16, None) == -1
+    assert b"workspace" in L.splat_last_error()
+    assert L.splat_ngp_bwd_saved(C.byref(m), 100, None, 0, *([p] * 4), p, 1 << 40, *([p] * 7), None) == -1
+    assert L.splat_ngp_bwd_saved(C.byref(m), 100, p, 1 << 40, *([p] * 4), p, 16, *([p] * 7), None) == -1
+    assert b"workspace" in L.splat_last_error()
+    assert L.splat_ngp_bwd_saved(C.byref(m), 0, None, 0, *([None] * 4), None, 0, *([None] * 7), None) == 0

@@ -179,3 +179,37 @@ def test_ngp_indexed_backward_at_two_million_gaussians():
     assert np.array_equal(gb.cpu().numpy(), base.cpu().numpy() + a)
     for k in ("w1", "b1", "w2", "b2", "w3", "b3"):
         assert torch.equal(gi[k], gs[k]), k
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_ngp_training_forward_and_saved_adjoint(name):
+    """The training forward gives the forward's parameters bit for bit, and the adjoint from
+    its stored values equals the adjoint that evaluates the field again, on every call."""
+    cfg = CONFIGS[name]
+    say(f"case: ngp training forward / saved adjoint {name}")
+    x, lo, hi, m = _case(cfg, 2500, 6)
+    t, model = _gpu_model(cfg, lo, hi, m)
+    G = x.shape[0]
+    xs = _dev(x.T)
+    mk = lambda: dict(quat=torch.empty((4, G), device="cuda"), scale=torch.empty((3, G), device="cuda"),
+                      opacity=torch.empty(G, device="cuda"), color=torch.empty((3, G), device="cuda"))
+    a, b = mk(), mk()
+    ws = torch.empty(B.splat_ngp_workspace_size(G), dtype=torch.uint8, device="cuda")
+    B.splat_ngp_fwd(model, xs, a["quat"], a["scale"], a["opacity"], a["color"])
+    B.splat_ngp_fwd_train(model, xs, b["quat"], b["scale"], b["opacity"], b["color"], ws)
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+    rng = np.random.default_rng(7)
+    dd = {k: _dev(rng.normal(size=v.shape).astype(np.float32)) for k, v in a.items()}
+    index = _index(model, xs)
+    ref = {k: torch.zeros_like(v) for k, v in t.items()}
+    ws2 = torch.empty_like(ws)
+    _bwd(model, xs, dd, ws2, ref, index)
+    for _ in range(2):
+        got = {k: torch.zeros_like(v) for k, v in t.items()}
+        B.splat_ngp_bwd_saved(model, G, index, dd["quat"], dd["scale"], dd["opacity"], dd["color"], ws,
+                              got["tables"], got["w1"], got["b1"], got["w2"], got["b2"], got["w3"], got["b3"])
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(got[k], ref[k]), k
