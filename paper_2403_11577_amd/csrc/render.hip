@@ -131,6 +131,16 @@ __device__ __forceinline__ uint32_t bcast_u(uint32_t v, int j) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, j);
 }
 
+// A batch is staged in LDS as three float4 per Gaussian: (mx, my, A, Bc), (Cc, lo2, r, g),
+// (b, 1/o, slot, -); the pair loops read Gaussian j back with a wave-uniform address (one
+// broadcast read per float4) instead of a readlane per value.  The workgroup is one wave,
+// whose LDS accesses complete in order, so no barrier is needed between the batches.
+__device__ __forceinline__ void put_stage(float4 (*sg)[3], const Stage &s, int lane) {
+    sg[lane][0] = make_float4(s.mx, s.my, s.A, s.Bc);
+    sg[lane][1] = make_float4(s.Cc, s.lo2, s.r, s.g);
+    sg[lane][2] = make_float4(s.b, s.io, __uint_as_float(s.slot), 0.f);
+}
+
 // exponent in log2 units including log2(opacity): A dx^2 + Bc dx dy + Cc dy^2 + lo2
 __device__ __forceinline__ float power2(float dx, float dy, float A, float Bc, float Cc, float lo2) {
     return __fmaf_rn(dx, __fmaf_rn(A, dx, Bc * dy), __fmaf_rn(Cc * dy, dy, lo2));
@@ -190,6 +200,7 @@ __device__ __forceinline__ bool next_item(const RenderArgs &a, int iter, int &it
 template <int TW, int TH, bool STATS>
 __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img, float *Tout, int32_t *lastout) {
     constexpr int NSB = TW * TH / 64, SBX = TW / 8;
+    __shared__ float4 sg[64][3];  // the staged batch, read back with wave-uniform addresses
     const int lane = threadIdx.x;
     const int lx = lane & 7, ly = lane >> 3;
     const size_t HW = (size_t)a.W * a.H;
@@ -217,6 +228,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
         }
         const float fxb = (float)xb, fyb = (float)yb, fox = (float)(x0 - xb), foy = (float)(y0 - yb);
         Stage cur = derive<TW, TH>(a, load_raw(a, load_slot(a, rg.x + lane, rg.y), nslots), fxb, fyb, fox, foy);
+        put_stage(sg, cur, lane);
         uint32_t sl_next = load_slot(a, rg.x + 64 + lane, rg.y);
         for (uint32_t b = rg.x; b < rg.y; b += 64) {
             uint32_t live = 0;  // sub-blocks with a pixel still compositing
@@ -225,13 +237,16 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
             if (live == 0) break;
             Raw raw_next = load_raw(a, sl_next, nslots);              // records of batch b + 64
             uint32_t sl_after = load_slot(a, b + 128 + lane, rg.y);   // slot ids of batch b + 128
-            int n = (int)min(64u, rg.y - b);
-            for (int j = 0; j < n; ++j) {
+            // the Gaussians of the batch that reach a live sub-block, in order (lanes past the
+            // list end carry an empty mask)
+            uint64_t todo = __ballot((cur.mask & live) != 0u);
+            while (todo) {
+                const int j = __ffsll((long long)todo) - 1;
+                todo &= todo - 1ull;
+                const float4 q0 = sg[j][0], q1 = sg[j][1], q2 = sg[j][2];
                 uint32_t m = bcast_u(cur.mask, j) & live;
-                if (m == 0u) continue;
-                float mx = bcast(cur.mx, j), my = bcast(cur.my, j);
-                float A = bcast(cur.A, j), Bc = bcast(cur.Bc, j), Cc = bcast(cur.Cc, j), lo2 = bcast(cur.lo2, j);
-                float cr = bcast(cur.r, j), cg = bcast(cur.g, j), cb = bcast(cur.b, j);
+                const float mx = q0.x, my = q0.y, A = q0.z, Bc = q0.w, Cc = q1.x, lo2 = q1.y;
+                const float cr = q1.z, cg = q1.w, cb = q2.x;
                 int idx = (int)(b + j);
 #pragma unroll
                 for (int k = 0; k < NSB; ++k) {
@@ -254,6 +269,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
                 }
             }
             cur = derive<TW, TH>(a, raw_next, fxb, fyb, fox, foy);
+            put_stage(sg, cur, lane);
             sl_next = sl_after;
         }
         size_t vo = (size_t)v * HW;
@@ -321,6 +337,7 @@ template <int TW, int TH, bool STATS>
 __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const float *dimg, const float *Tin,
                                                        const int32_t *lastin, float *grad2d) {
     constexpr int NSB = TW * TH / 64, SBX = TW / 8;
+    __shared__ float4 sg[64][3];  // the staged batch (see put_stage)
     const int lane = threadIdx.x;
     const int lx = lane & 7, ly = lane >> 3;
     const size_t HW = (size_t)a.W * a.H;
@@ -376,6 +393,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
         int bs = max((int)rg.x, e - 64);
         Stage cur = derive<TW, TH>(a, load_raw(a, load_slot(a, (uint32_t)(bs + lane), (uint32_t)e), nslots), fxb,
                                    fyb, fox, foy);
+        put_stage(sg, cur, lane);
         int bs2 = max((int)rg.x, bs - 64);
         uint32_t sl_next = load_slot(a, (uint32_t)(bs2 + lane), (uint32_t)bs);
         while (e > (int)rg.x) {
@@ -384,13 +402,17 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
             int bs3 = max((int)rg.x, bs2 - 64);
             Raw raw_next = load_raw(a, sl_next, nslots);                                 // batch [bs2, bs)
             uint32_t sl_after = load_slot(a, (uint32_t)(bs3 + lane), (uint32_t)bs2);   // batch [bs3, bs2)
-            for (int j = n - 1; j >= 0; --j) {
+            // the batch's Gaussians with a footprint in the tile, last first (lanes at or past n
+            // carry an empty mask)
+            uint64_t todo = __ballot(cur.mask != 0u && lane < n);
+            while (todo) {
+                const int j = 63 - __builtin_clzll(todo);
+                todo &= ~(1ull << j);
+                const float4 q0 = sg[j][0], q1 = sg[j][1], q2 = sg[j][2];
                 uint32_t m = bcast_u(cur.mask, j);
-                if (m == 0u) continue;
                 int idx = bs + j;
-                float mx = bcast(cur.mx, j), my = bcast(cur.my, j);
-                float A = bcast(cur.A, j), Bc = bcast(cur.Bc, j), Cc = bcast(cur.Cc, j), lo2 = bcast(cur.lo2, j);
-                float cr = bcast(cur.r, j), cg = bcast(cur.g, j), cb = bcast(cur.b, j);
+                const float mx = q0.x, my = q0.y, A = q0.z, Bc = q0.w, Cc = q1.x, lo2 = q1.y;
+                const float cr = q1.z, cg = q1.w, cb = q2.x;
                 // per-lane sums of dp = dL/dpower and its moments in (dx, dy), and of the colour weights
                 float m0 = 0.f, mx1 = 0.f, my1 = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
                 bool hit_any = false;
@@ -430,8 +452,8 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
                 //   dL/dmu = (a Mx + b My, b Mx + c My), dL/d(a, b, c) = (-Mxx/2, -Mxy, -Myy/2),
                 //   dL/do = M0 / o   (applied per lane before the reduction: all linear)
                 float ca = -2.f * LN2 * A, cbv = -LN2 * Bc, ccv = -2.f * LN2 * Cc;
-                float io = bcast(cur.io, j);
-                uint32_t slot = bcast_u(cur.slot, j);
+                float io = q2.y;
+                uint32_t slot = __float_as_uint(q2.z);
                 float vals[9] = {__fmaf_rn(ca, mx1, cbv * my1), __fmaf_rn(cbv, mx1, ccv * my1), -0.5f * mxx, -mxy,
                                  -0.5f * myy, m0 * io, gr, gg, gbl};
                 float tot = reduce9(vals, c0, c1, c2, c3);
@@ -439,6 +461,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
                 if (writer) atomicAdd(grad2d + 9 * (size_t)slot + cls, tot);
             }
             cur = derive<TW, TH>(a, raw_next, fxb, fyb, fox, foy);
+            put_stage(sg, cur, lane);
             sl_next = sl_after;
             e = e2;
             bs = bs2;
