@@ -190,7 +190,8 @@ SPLAT_API int splat_pose_interp_bwd(int32_t K, const double *knot_t, const doubl
  * compacted per view in Gaussian order into slots.
  *   g: Gaussians (device planes); w2c[V][12] float64 (device);
  *   intr[V][4] float64 (fx, fy, cx, cy) per view (device).
- * Writes counts, view_off, rec, meta, rect, ntiles in the workspace.
+ * Writes counts, view_off, rec, meta, rect, ntiles in the workspace, and zeroes
+ * every written slot's gradient for splat_render_bwd.
  */
 SPLAT_API int splat_project(const splat_plan *plan, void *ws, const splat_gaussians *g, const double *w2c,
                   const double *intr, void *stream);
@@ -224,9 +225,10 @@ SPLAT_API int splat_render_fwd(const splat_plan *plan, void *ws, float *img, flo
  * Backward compositing (the adjoint of splat_render_fwd): every pixel walks
  * its list in reverse from last_pos, recovering T by division and the suffix
  * colour sum, and accumulates d(loss)/d(mean2d, conic, opacity, colour) of
- * every slot with wave-reduced atomics into the workspace gradient buffer
- * (zeroed here first).  dL_dimg[V][3][H][W], T_final and last_pos are the
- * caller's (last two from splat_render_fwd).
+ * every slot with wave-reduced atomics into the workspace gradient buffer,
+ * which splat_project zeroed: call it once per projection (a second call adds
+ * to the first).  dL_dimg[V][3][H][W], T_final and last_pos are the caller's
+ * (last two from splat_render_fwd).
  */
 SPLAT_API int splat_render_bwd(const splat_plan *plan, void *ws, const float *dL_dimg, const float *T_final,
                      const int32_t *last_pos, void *stream);

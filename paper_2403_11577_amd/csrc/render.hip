@@ -475,12 +475,6 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
     }
 }
 
-__global__ void zero_grad2d_kernel(const uint32_t *counts, float *g) {
-    uint64_t n = (uint64_t)counts[CNT_SLOTS] * 9;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        g[i] = 0.f;
-}
-
 __global__ void reset_work_kernel(uint32_t *w) { *w = 0u; }
 
 RenderArgs make_args(const splat_plan &p, void *ws, unsigned long long *stats) {
@@ -540,13 +534,9 @@ template <int TW, int TH>
 int bwd_impl(const splat_plan &p, void *ws, const float *dimg, const float *T, const int32_t *last,
              unsigned long long *stats, hipStream_t st) {
     RenderArgs a = make_args(p, ws, stats);
-    float *g2 = ws_at<float>(ws, p.off_grad2d);
-    uint32_t *counts = ws_at<uint32_t>(ws, p.off_counts);
-    int zb = (int)((p.slot_cap * 9 + 255) / 256);
-    if (zb > 8192) zb = 8192;
-    hipLaunchKernelGGL(zero_grad2d_kernel, dim3(zb), dim3(256), 0, st, counts, g2);
-    int rc = launch_status("zero_grad2d");
-    if (rc || a.n_items == 0) return rc;
+    float *g2 = ws_at<float>(ws, p.off_grad2d);  // zeroed per slot by the projection
+    int rc = 0;
+    if (a.n_items == 0) return rc;
     int grid = a.n_items;
     if (a.persistent) {
         hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(1), 0, st, a.work);
