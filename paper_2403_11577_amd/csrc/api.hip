@@ -222,7 +222,7 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     p.off_scan = take(nparts * 4);
     p.off_grad2d = take((size_t)slot_cap * 36);
     p.off_visbits = take((size_t)n_views * p.n_blocks_proj * 4 * 8);
-    p.off_dwpart = take((size_t)n_views * p.n_blocks_proj * 12 * 8);
+    p.off_dwpart = take((size_t)n_views * p.n_blocks_proj * 4 * 12 * 8);
     p.off_cam = take((size_t)n_views * 8 * 8);
     p.ws_bytes = off;
     *plan = p;

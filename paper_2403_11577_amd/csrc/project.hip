@@ -434,7 +434,9 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
                                                          const uint64_t *visbits, int64_t slot_cap,
                                                          const float *grad2d, float *dquat, float *dscale,
                                                          float *dopac, float *dcolor, float *dmean, double *dwpart) {
-    __shared__ double red[4][12];
+    // Every wave walks the views on its own (no workgroup barrier in the loop), writing its
+    // FP64 W2C partial per view; the next view's visibility word and slot base are loaded
+    // while the current view is processed.
     const int b = blockIdx.x, wv = threadIdx.x >> 6, lane = __lane_id();
     const LaneClass lc(lane);
     const bool writer = lane < 16 && lc.cls < 12;
@@ -444,41 +446,44 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
     GaussIn gi;
     if (live) gauss_in(S, g, i, gi);
     double gq[4] = {0, 0, 0, 0}, gs[3] = {0, 0, 0}, gm[3] = {0, 0, 0}, go = 0.0, gc[3] = {0, 0, 0};
-    for (int v = 0; v < V; ++v) {
-        const size_t k0 = ((size_t)v * nb + b) * 4;
-        double *part = dwpart + ((size_t)v * nb + b) * 12;
-        uint64_t mask = visbits[k0 + wv];
-        bool vis = live && ((mask >> lane) & 1ull);
-        if (!__syncthreads_or(vis)) {  // nothing of this workgroup visible in view v
-            if (threadIdx.x < 12) part[threadIdx.x] = 0.0;
-            continue;
+    size_t k0 = (size_t)b * 4 + wv;  // (view, block, wave) index of view 0
+    const size_t kstep = (size_t)nb * 4;
+    uint64_t mask = visbits[k0];
+    uint32_t base = waveoff[k0];
+    for (int v = 0; v < V; ++v, k0 += kstep) {
+        uint64_t mask_n = 0;
+        uint32_t base_n = 0;
+        if (v + 1 < V) {
+            mask_n = visbits[k0 + kstep];
+            base_n = waveoff[k0 + kstep];
         }
-        double gw[12];
-        for (int k = 0; k < 12; ++k) gw[k] = 0.0;
-        if (vis) {
-            uint64_t slot = (uint64_t)waveoff[k0 + wv] + rank_in(mask);
-            if (slot < (uint64_t)slot_cap) {
-                const double *M = w2c + 12 * v;
-                const CamC C = cam[v];
-                Proj P;
-                project_view(S, M, C, gi.x, gi.s, gi.G, true, P);
-                const float *gd = grad2d + 9 * slot;
-                go += gd[5];
-                gc[0] += gd[6];
-                gc[1] += gd[7];
-                gc[2] += gd[8];
-                slot_adjoint(P, M, C, gi.x, gi.s, gd, gq, gs, gm, gw);
+        double *part = dwpart + k0 * 12;
+        const bool vis = live && ((mask >> lane) & 1ull);
+        if (mask == 0ull) {  // nothing of this wave visible in view v
+            if (lane < 12) part[lane] = 0.0;
+        } else {
+            double gw[12];
+            for (int k = 0; k < 12; ++k) gw[k] = 0.0;
+            if (vis) {
+                uint64_t slot = (uint64_t)base + rank_in(mask);
+                if (slot < (uint64_t)slot_cap) {
+                    const double *M = w2c + 12 * v;
+                    const CamC C = cam[v];
+                    Proj P;
+                    project_view(S, M, C, gi.x, gi.s, gi.G, true, P);
+                    const float *gd = grad2d + 9 * slot;
+                    go += gd[5];
+                    gc[0] += gd[6];
+                    gc[1] += gd[7];
+                    gc[2] += gd[8];
+                    slot_adjoint(P, M, C, gi.x, gi.s, gd, gq, gs, gm, gw);
+                }
             }
+            double tot = reduce12(gw, lc.c0, lc.c1, lc.c2, lc.c3);
+            if (writer) part[lc.cls] = tot;
         }
-        double tot = 0.0;
-        if (mask != 0ull) tot = reduce12(gw, lc.c0, lc.c1, lc.c2, lc.c3);  // wave-uniform
-        if (writer) red[wv][lc.cls] = tot;
-        __syncthreads();
-        if (threadIdx.x < 12) {
-            int k = threadIdx.x;
-            part[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-        }
-        __syncthreads();
+        mask = mask_n;
+        base = base_n;
     }
     if (!live) return;
     for (int k = 0; k < 4; ++k) dquat[k * n + i] += (float)gq[k];
@@ -489,15 +494,15 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
         for (int k = 0; k < 3; ++k) dmean[k * n + i] += (float)gm[k];
 }
 
-// dw2c[v] += sum over the workgroups of their partials, in a fixed order.
-__global__ __launch_bounds__(256) void dw2c_reduce_kernel(const double *dwpart, int nb, double *dw2c) {
+// dw2c[v] += sum over the (block, wave) partials of view v, in a fixed order.
+__global__ __launch_bounds__(256) void dw2c_reduce_kernel(const double *dwpart, int nparts, double *dw2c) {
     __shared__ double red[4][12];
     const int v = blockIdx.x, wv = threadIdx.x >> 6, lane = __lane_id();
     const LaneClass lc(lane);
     double acc[12];
     for (int k = 0; k < 12; ++k) acc[k] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 256) {
-        const double *p = dwpart + ((size_t)v * nb + b) * 12;
+    for (int q = threadIdx.x; q < nparts; q += 256) {
+        const double *p = dwpart + ((size_t)v * nparts + q) * 12;
         for (int k = 0; k < 12; ++k) acc[k] += p[k];
     }
     double tot = reduce12(acc, lc.c0, lc.c1, lc.c2, lc.c3);
@@ -560,7 +565,7 @@ int launch_project_bwd(const splat_plan &p, void *ws, const splat_gaussians &g, 
                        p.slot_cap, ws_at<float>(ws, p.off_grad2d), dquat, dscale, dopac, dcolor, dmean, part);
     int rc = launch_status("project_bwd");
     if (rc) return rc;
-    hipLaunchKernelGGL(dw2c_reduce_kernel, dim3(p.n_views), dim3(256), 0, st, part, nb, dw2c);
+    hipLaunchKernelGGL(dw2c_reduce_kernel, dim3(p.n_views), dim3(256), 0, st, part, 4 * nb, dw2c);
     return launch_status("dw2c_reduce");
 }
 
