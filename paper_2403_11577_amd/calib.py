@@ -166,8 +166,9 @@ class Calibrator:
         self.loss = torch.zeros(1, dtype=torch.float64, device=device)
         self.ssim_ws = torch.empty(B.splat_dssim_workspace_size(Bv, full.W, full.H, self.settings.roi_y0),
                                    dtype=torch.uint8, device=device)
-        self.rng = np.random.default_rng(cfg.seed)
-        self.order = []
+        # view order: epochs of seeded permutations, drawn on the device (no host copy per step)
+        self._perm_gen = torch.Generator(device=device).manual_seed(cfg.seed)
+        self.order = torch.empty(0, dtype=torch.int64, device=device)
         # status words of the last two steps, copied to pinned memory and read two steps later
         self._st_host = torch.zeros((2, 1), dtype=torch.int32).pin_memory()
         self._st_ev = [None, None]
@@ -271,10 +272,11 @@ class Calibrator:
 
     def _next_views(self):
         Bv, V = self.cfg.batch_views, self.full.n_views
-        if len(self.order) < Bv:
-            self.order.extend(self.rng.permutation(V).tolist())
+        if self.order.numel() < Bv:
+            perm = torch.randperm(V, generator=self._perm_gen, device=self.device)
+            self.order = torch.cat([self.order, perm])
         sel, self.order = self.order[:Bv], self.order[Bv:]
-        return torch.as_tensor(sel, device=self.device)
+        return sel
 
     def step(self, k: int):
         cfg = self.cfg
