@@ -196,3 +196,18 @@ def test_ngp_training_pair_argument_checks_without_a_device():
     assert L.splat_ngp_bwd_saved(C.byref(m), 100, p, 1 << 40, *([p] * 4), p, 16, *([p] * 7), None) == -1
     assert b"workspace" in L.splat_last_error()
     assert L.splat_ngp_bwd_saved(C.byref(m), 0, None, 0, *([None] * 4), None, 0, *([None] * 7), None) == 0
+
+
+def test_header_is_plain_c99(tmp_path):
+    """include/splat.h compiles as strict C99 (no C++ or torch types in the ABI)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text('#include "splat.h"\nint main(void) { splat_settings s; return (int)sizeof(s) == 0; }\n')
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", f"-I{inc}",
+                        str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
