@@ -74,6 +74,8 @@ class CalibConfig:
     # coarse-to-fine voxelisation (field model): ((voxel_m, steps), ...); steps is then their sum.
     # () keeps the scene's own points for the whole run.
     stages: tuple = ()
+    # replay each step's device work from a captured HIP graph (re-captured when the plan changes)
+    graph: bool = True
 
 
 def rotation_error_deg(xi):
@@ -144,23 +146,34 @@ class Calibrator:
         self.phi = torch.tensor(scene.xi[:, 3:], dtype=torch.float64, device=device).requires_grad_(True)
         self.delta = torch.tensor(scene.delta, dtype=torch.float64, device=device).requires_grad_(True)
         # two optimisers: the calibration one only starts stepping after the warm-up
+        # in graph mode the learning rates are device tensors, updated before every replay
+        lr = (lambda v: torch.tensor(v, dtype=torch.float32, device=device)) if cfg.graph else float
         self.opt_g = torch.optim.Adam([
-            dict(params=[self.color], lr=cfg.lr_color),
-            dict(params=[self.logit_o], lr=cfg.lr_opacity),
-            dict(params=[self.log_s], lr=cfg.lr_scale),
-            dict(params=[self.quat], lr=cfg.lr_quat),
+            dict(params=[self.color], lr=lr(cfg.lr_color)),
+            dict(params=[self.logit_o], lr=lr(cfg.lr_opacity)),
+            dict(params=[self.log_s], lr=lr(cfg.lr_scale)),
+            dict(params=[self.quat], lr=lr(cfg.lr_quat)),
         ] if self.field is None else [
-            dict(params=[self.field["tables"]], lr=cfg.lr_field_table, weight_decay=cfg.field_weight_decay),
-            dict(params=[self.field[k] for k in ("w1", "b1", "w2", "b2", "w3", "b3")], lr=cfg.lr_field_mlp),
-        ], eps=1e-15)
+            dict(params=[self.field["tables"]], lr=lr(cfg.lr_field_table), weight_decay=cfg.field_weight_decay),
+            dict(params=[self.field[k] for k in ("w1", "b1", "w2", "b2", "w3", "b3")], lr=lr(cfg.lr_field_mlp)),
+        ], eps=1e-15, capturable=cfg.graph)
         self.opt_c = torch.optim.Adam([
-            dict(params=[self.rho], lr=cfg.lr_trans),
-            dict(params=[self.phi], lr=cfg.lr_rot),
-            dict(params=[self.delta], lr=cfg.lr_time),
-        ], eps=1e-15)
-        self.base_lr = [[grp["lr"] for grp in o.param_groups] for o in (self.opt_g, self.opt_c)]
+            dict(params=[self.rho], lr=lr(cfg.lr_trans)),
+            dict(params=[self.phi], lr=lr(cfg.lr_rot)),
+            dict(params=[self.delta], lr=lr(cfg.lr_time)),
+        ], eps=1e-15, capturable=cfg.graph)
+        self.base_lr = [[float(grp["lr"]) for grp in o.param_groups] for o in (self.opt_g, self.opt_c)]
+        # gradient buffers the step writes in place (fixed addresses, as a captured graph needs)
+        for t in (self.rho, self.phi, self.delta):
+            t.grad = torch.zeros_like(t)
+        if self.field is None:
+            self.logit_o.grad = torch.zeros_like(self.logit_o)
+            self.log_s.grad = torch.zeros_like(self.log_s)
+        self._graph = None
         if self.field is not None:
             self.field_grads = {k: torch.zeros_like(v) for k, v in self.field.items()}
+            for name, t in self.field.items():
+                t.grad = self.field_grads[name]
         self.xi_t = torch.zeros((full.n_cams, 6), dtype=torch.float64, device=device)
         self.dl_t = torch.zeros(full.n_cams, dtype=torch.float64, device=device)
         self.loss = torch.zeros(1, dtype=torch.float64, device=device)
@@ -222,6 +235,7 @@ class Calibrator:
         self.dimg = torch.empty_like(self.fr.img)
         if self.cfg.model == "field":
             self.field_ws = torch.empty(B.splat_ngp_workspace_size(G), dtype=torch.uint8, device=dev)
+        self._graph = None
 
     def _ensure_index(self):
         """Inverse index of the field's table lookups for the current anchors (built once per
@@ -286,7 +300,37 @@ class Calibrator:
         self._poll(k)
         if self.stage_log:
             self.stage_log[-1]["done"] += 1
-        idx = self._next_views()
+        if not hasattr(self, "_idx"):
+            self._idx = torch.zeros(cfg.batch_views, dtype=torch.int64, device=self.device)
+        self._idx.copy_(self._next_views())
+        frac = 1.0 - (1.0 - cfg.final_lr_frac) * min(1.0, k / max(1, cfg.steps - 1))
+        for opt, lrs in zip((self.opt_g, self.opt_c), self.base_lr):
+            for grp, lr0 in zip(opt.param_groups, lrs):
+                if cfg.graph:
+                    grp["lr"].fill_(lr0 * frac)
+                else:
+                    grp["lr"] = lr0 * frac
+        if cfg.graph and self._graph is not None:
+            self._graph.replay()
+        else:
+            self._body()
+            if cfg.graph:  # this step ran eagerly (lazy initialisation); record the next ones
+                self._capture()
+        if k >= cfg.warmup:
+            self.opt_c.step()
+        self._queue_status(k)
+
+    def _capture(self):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self._body()
+        self._graph = g
+
+    def _body(self):
+        """The device work of one step: views of the batch, Gaussian parameters, render forward,
+        losses, adjoints, the Gaussian (or field) optimiser step, and the calibration gradients."""
+        cfg = self.cfg
+        idx = self._idx
         w, f = self.win, self.full
         w.view_cam.copy_(f.view_cam[idx])
         w.view_t.copy_(f.view_t[idx])
@@ -306,44 +350,36 @@ class Calibrator:
             self.xi_t[:, :3].copy_(self.rho)
             self.xi_t[:, 3:].copy_(self.phi)
             self.dl_t.copy_(self.delta)
-        fr = self.fr
-        self.loss.zero_()
-        pl.zero_grads(self.gr)
-        pl.forward(fr, w, self.xi_t, self.dl_t)
-        B.splat_l1_loss_grad(fr.img, self.tgt, None, self.dimg, self.loss, self.settings.roi_y0, 1.0 - cfg.lam_dssim)
-        if cfg.lam_dssim > 0:
-            B.splat_dssim_loss_grad(fr.img, self.tgt, self.ssim_ws, self.dimg, self.loss, self.settings.roi_y0,
-                                    cfg.lam_dssim)
-        pl.backward(fr, w, self.xi_t, self.dl_t, self.dimg, self.gr)
-        if cfg.lam_scale > 0:
-            B.splat_scale_reg(w.scale, cfg.lam_scale, self.gr.scale, self.loss)
-        # activations and the optimiser (torch)
-        if self.field is None:
-            self.color.grad = self.gr.color
-            self.logit_o.grad = self.gr.opacity * o * (1 - o)
-            self.log_s.grad = self.gr.scale * s
-            self.quat.grad = self.gr.quat
-        else:
-            fg = self.field_grads
-            for t in fg.values():
-                t.zero_()
-            B.splat_ngp_bwd_saved(self.field_struct, w.n_gauss, self.field_index, self.gr.quat, self.gr.scale,
-                                  self.gr.opacity, self.gr.color, self.field_ws, fg["tables"], fg["w1"], fg["b1"],
-                                  fg["w2"], fg["b2"], fg["w3"], fg["b3"])
-            for name, t in self.field.items():
-                t.grad = fg[name]
-        frac = 1.0 - (1.0 - cfg.final_lr_frac) * min(1.0, k / max(1, cfg.steps - 1))
-        for opt, lrs in zip((self.opt_g, self.opt_c), self.base_lr):
-            for grp, lr0 in zip(opt.param_groups, lrs):
-                grp["lr"] = lr0 * frac
+            fr = self.fr
+            self.loss.zero_()
+            pl.zero_grads(self.gr)
+            pl.forward(fr, w, self.xi_t, self.dl_t)
+            B.splat_l1_loss_grad(fr.img, self.tgt, None, self.dimg, self.loss, self.settings.roi_y0,
+                                 1.0 - cfg.lam_dssim)
+            if cfg.lam_dssim > 0:
+                B.splat_dssim_loss_grad(fr.img, self.tgt, self.ssim_ws, self.dimg, self.loss, self.settings.roi_y0,
+                                        cfg.lam_dssim)
+            pl.backward(fr, w, self.xi_t, self.dl_t, self.dimg, self.gr)
+            if cfg.lam_scale > 0:
+                B.splat_scale_reg(w.scale, cfg.lam_scale, self.gr.scale, self.loss)
+            # gradients of the optimised tensors (written in place)
+            if self.field is None:
+                self.color.grad = self.gr.color
+                self.quat.grad = self.gr.quat
+                torch.mul(self.gr.opacity, o * (1 - o), out=self.logit_o.grad)
+                torch.mul(self.gr.scale, s, out=self.log_s.grad)
+            else:
+                fg = self.field_grads
+                for t in fg.values():
+                    t.zero_()
+                B.splat_ngp_bwd_saved(self.field_struct, w.n_gauss, self.field_index, self.gr.quat, self.gr.scale,
+                                      self.gr.opacity, self.gr.color, self.field_ws, fg["tables"], fg["w1"],
+                                      fg["b1"], fg["w2"], fg["b2"], fg["w3"], fg["b3"])
+            self.rho.grad.copy_(self.gr.xi[:, :3])
+            self.phi.grad.copy_(self.gr.xi[:, 3:])
+            self.delta.grad.copy_(self.gr.delta)
         if not cfg.freeze_gaussians:
             self.opt_g.step()
-        if k >= cfg.warmup:
-            self.rho.grad = self.gr.xi[:, :3].contiguous()
-            self.phi.grad = self.gr.xi[:, 3:].contiguous()
-            self.delta.grad = self.gr.delta
-            self.opt_c.step()
-        self._queue_status(k)
 
     def _poll(self, k: int):
         """Before step k: read the status word of step k-2, which has finished by now."""
@@ -383,6 +419,7 @@ class Calibrator:
         self.fr = pl.Frame(self.settings, Bv, G, self.full.W, self.full.H, self.slot_cap, self.inst_cap,
                            self.device)
         self.dimg = torch.empty_like(self.fr.img)
+        self._graph = None
         self.replans += 1
 
     def errors(self):

@@ -9,9 +9,10 @@
 // the loss term is weight * (1 - mean S) and, the window being symmetric,
 //   dL/dx = w*G1 + 2 x (w*G11) + y (w*G12),   G = dL/dS * (dS/dm1, dS/dm11, dS/dm12).
 // Two launches: ssim_fwd forms the moments (separable filter through LDS, float64
-// accumulation: the stage is bandwidth-bound, so float64 costs nothing and keeps
-// m11 - m1^2 free of float32 cancellation) and stores G per pixel; ssim_bwd
-// filters G and adds the gradient into dL/dimg.
+// accumulation, which keeps m11 - m1^2 free of float32 cancellation) and stores G
+// per pixel; ssim_bwd filters G and adds the gradient into dL/dimg.  Workgroups
+// take 32 x 32 output tiles; in each pass a thread filters 14 inputs held in
+// registers into 4 outputs.
 #include "common.hpp"
 
 namespace splat {
@@ -19,8 +20,10 @@ namespace {
 
 constexpr int SR = 5;                 // window radius
 constexpr int SW = 2 * SR + 1;        // window width
-constexpr int STX = 32, STY = 16;     // output tile
-constexpr int SLX = STX + 2 * SR, SLY = STY + 2 * SR;
+constexpr int OX = 32, OY = 32;       // output tile
+constexpr int IX = OX + 2 * SR, IY = OY + 2 * SR;
+constexpr int CPT = 4;                // outputs per thread along the filtered direction
+constexpr int NV = CPT + 2 * SR;      // inputs a thread reads for them
 constexpr double SC1 = 0.01 * 0.01, SC2 = 0.03 * 0.03;
 
 struct SsimArgs {
@@ -34,15 +37,34 @@ __device__ inline int64_t plane_px(const SsimArgs &a, int plane, int r, int c) {
     return (int64_t)plane * a.hw + (int64_t)(r + a.roi) * a.W + c;
 }
 
+// The separable filter, both passes: a thread filters NV = CPT + 10 consecutive inputs held
+// in registers into CPT consecutive outputs (11 taps each), so every input is read from LDS
+// once per thread rather than once per tap.
+template <int NM>
+__device__ __forceinline__ void filter_cpt(const double (&g)[SW], const double (&v)[NM][NV], double (&out)[NM][CPT]) {
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+#pragma unroll
+        for (int o = 0; o < CPT; ++o) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < SW; ++k) acc = fma(g[k], v[m][o + k], acc);
+            out[m][o] = acc;
+        }
+}
+
 __global__ __launch_bounds__(256) void ssim_fwd_kernel(SsimArgs a, const float *x, const float *y, double fscale,
                                                       double weight, float *G, double *loss) {
-    __shared__ float sx[SLY][SLX], sy[SLY][SLX];
-    __shared__ double hm[5][SLY][STX];
+    __shared__ float sx[IY][IX + 1], sy[IY][IX + 1];
+    __shared__ double hm[5][IY][OX];
     __shared__ double part[4];
     const int t = threadIdx.x, plane = blockIdx.z;
-    const int x0 = blockIdx.x * STX, y0 = blockIdx.y * STY;
-    for (int i = t; i < SLY * SLX; i += 256) {
-        int r = i / SLX, c = i - r * SLX;
+    const int x0 = blockIdx.x * OX, y0 = blockIdx.y * OY;
+    double g[SW];
+#pragma unroll
+    for (int k = 0; k < SW; ++k) g[k] = a.g[k];
+    for (int i = t; i < IY * IX; i += 256) {
+        int r = i / IX, c = i - r * IX;
         int gr = y0 + r - SR, gc = x0 + c - SR;
         bool in = gr >= 0 && gr < a.Hc && gc >= 0 && gc < a.W;
         int64_t o = in ? plane_px(a, plane, gr, gc) : 0;
@@ -50,57 +72,69 @@ __global__ __launch_bounds__(256) void ssim_fwd_kernel(SsimArgs a, const float *
         sy[r][c] = in ? y[o] : 0.f;
     }
     __syncthreads();
-    for (int i = t; i < SLY * STX; i += 256) {
-        int r = i / STX, c = i - r * STX;
-        double m1 = 0, m2 = 0, m11 = 0, m22 = 0, m12 = 0;
+    // rows: the five raw moments x, y, x^2, y^2, xy of every halo row, CPT columns per item
+    for (int it = t; it < IY * (OX / CPT); it += 256) {
+        const int r = it / (OX / CPT), c0 = (it - r * (OX / CPT)) * CPT;
+        double v[5][NV];
 #pragma unroll
-        for (int k = 0; k < SW; ++k) {
-            double xv = sx[r][c + k], yv = sy[r][c + k], gk = a.g[k];
-            m1 += gk * xv;
-            m2 += gk * yv;
-            m11 += gk * (xv * xv);
-            m22 += gk * (yv * yv);
-            m12 += gk * (xv * yv);
+        for (int k = 0; k < NV; ++k) {
+            double xv = sx[r][c0 + k], yv = sy[r][c0 + k];
+            v[0][k] = xv;
+            v[1][k] = yv;
+            v[2][k] = xv * xv;
+            v[3][k] = yv * yv;
+            v[4][k] = xv * yv;
         }
-        hm[0][r][c] = m1; hm[1][r][c] = m2; hm[2][r][c] = m11; hm[3][r][c] = m22; hm[4][r][c] = m12;
+        double out[5][CPT];
+        filter_cpt<5>(g, v, out);
+#pragma unroll
+        for (int m = 0; m < 5; ++m)
+#pragma unroll
+            for (int o = 0; o < CPT; ++o) hm[m][r][c0 + o] = out[m][o];
     }
     __syncthreads();
-    double ssum = 0.0;
-    const int64_t gbase = (int64_t)plane * a.hwc;
-    for (int i = t; i < STY * STX; i += 256) {
-        int r = i / STX, c = i - r * STX;
-        int gr = y0 + r, gc = x0 + c;
-        if (gr >= a.Hc || gc >= a.W) continue;
-        double m1 = 0, m2 = 0, m11 = 0, m22 = 0, m12 = 0;
+    // columns: CPT rows of one column per thread, then SSIM and its partials
+    const int c = t % OX, r0 = (t / OX) * CPT;
+    double mo[5][CPT];
+    {
+        double v[5][NV];
 #pragma unroll
-        for (int k = 0; k < SW; ++k) {
-            double gk = a.g[k];
-            m1 += gk * hm[0][r + k][c];
-            m2 += gk * hm[1][r + k][c];
-            m11 += gk * hm[2][r + k][c];
-            m22 += gk * hm[3][r + k][c];
-            m12 += gk * hm[4][r + k][c];
-        }
-        double A = 2.0 * m1 * m2 + SC1;
-        double B = 2.0 * (m12 - m1 * m2) + SC2;
-        double C = m1 * m1 + m2 * m2 + SC1;
-        double D = (m11 - m1 * m1) + (m22 - m2 * m2) + SC2;
-        double S = (A * B) / (C * D);
+        for (int m = 0; m < 5; ++m)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[m][k] = hm[m][r0 + k][c];
+        filter_cpt<5>(g, v, mo);
+    }
+    double ssum = 0.0;
+    const int64_t gbase = (int64_t)plane * a.hwc, np = (int64_t)gridDim.z * a.hwc;
+    const int gc = x0 + c;
+#pragma unroll
+    for (int o = 0; o < CPT; ++o) {
+        const int gr = y0 + r0 + o;
+        if (gr >= a.Hc || gc >= a.W) continue;
+        const double m1 = mo[0][o], m2 = mo[1][o], m11 = mo[2][o], m22 = mo[3][o], m12 = mo[4][o];
+        const double A = 2.0 * m1 * m2 + SC1;
+        const double B = 2.0 * (m12 - m1 * m2) + SC2;
+        const double C = m1 * m1 + m2 * m2 + SC1;
+        const double D = (m11 - m1 * m1) + (m22 - m2 * m2) + SC2;
+        // one division for the four reciprocals
+        const double AB = A * B, CD = C * D, P = 1.0 / (AB * CD);
+        const double rA = B * CD * P, rB = A * CD * P, rC = AB * D * P, rD = AB * C * P;
+        const double S = AB * AB * P;
         ssum += S;
         // dS/dm1 = S (2 m2 / A - 2 m2 / B - 2 m1 / C + 2 m1 / D), dS/dm11 = -S / D, dS/dm12 = 2 S / B
-        double d1 = S * (2.0 * m2 / A - 2.0 * m2 / B - 2.0 * m1 / C + 2.0 * m1 / D);
-        double d11 = -S / D, d12 = 2.0 * S / B;
-        int64_t o = gbase + (int64_t)gr * a.W + gc;
-        G[o] = (float)(fscale * d1);
-        G[(int64_t)gridDim.z * a.hwc + o] = (float)(fscale * d11);
-        G[2 * (int64_t)gridDim.z * a.hwc + o] = (float)(fscale * d12);
+        const double d1 = 2.0 * S * (m2 * (rA - rB) + m1 * (rD - rC));
+        const double d11 = -S * rD, d12 = 2.0 * S * rB;
+        const int64_t q = gbase + (int64_t)gr * a.W + gc;
+        G[q] = (float)(fscale * d1);
+        G[np + q] = (float)(fscale * d11);
+        G[2 * np + q] = (float)(fscale * d12);
     }
     ssum = wave_sum(ssum);
     if ((t & 63) == 0) part[t >> 6] = ssum;
     __syncthreads();
     if (t == 0 && loss) {
-        double s = ((part[0] + part[1]) + part[2]) + part[3];
-        double add = fscale * s;  // fscale = -weight / N
+        double sm = ((part[0] + part[1]) + part[2]) + part[3];
+        double add = fscale * sm;  // fscale = -weight / N
         if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) add += weight;
         atomicAdd(loss, add);
     }
@@ -108,13 +142,16 @@ __global__ __launch_bounds__(256) void ssim_fwd_kernel(SsimArgs a, const float *
 
 __global__ __launch_bounds__(256) void ssim_bwd_kernel(SsimArgs a, const float *x, const float *y, const float *G,
                                                       float *dimg) {
-    __shared__ float sg[3][SLY][SLX];
-    __shared__ double hm[3][SLY][STX];
+    __shared__ float sg[3][IY][IX + 1];
+    __shared__ double hm[3][IY][OX];
     const int t = threadIdx.x, plane = blockIdx.z;
-    const int x0 = blockIdx.x * STX, y0 = blockIdx.y * STY;
+    const int x0 = blockIdx.x * OX, y0 = blockIdx.y * OY;
     const int64_t np = (int64_t)gridDim.z * a.hwc;
-    for (int i = t; i < SLY * SLX; i += 256) {
-        int r = i / SLX, c = i - r * SLX;
+    double g[SW];
+#pragma unroll
+    for (int k = 0; k < SW; ++k) g[k] = a.g[k];
+    for (int i = t; i < IY * IX; i += 256) {
+        int r = i / IX, c = i - r * IX;
         int gr = y0 + r - SR, gc = x0 + c - SR;
         bool in = gr >= 0 && gr < a.Hc && gc >= 0 && gc < a.W;
         int64_t o = in ? (int64_t)plane * a.hwc + (int64_t)gr * a.W + gc : 0;
@@ -123,34 +160,39 @@ __global__ __launch_bounds__(256) void ssim_bwd_kernel(SsimArgs a, const float *
         sg[2][r][c] = in ? G[2 * np + o] : 0.f;
     }
     __syncthreads();
-    for (int i = t; i < SLY * STX; i += 256) {
-        int r = i / STX, c = i - r * STX;
-        double f1 = 0, f11 = 0, f12 = 0;
+    for (int it = t; it < IY * (OX / CPT); it += 256) {
+        const int r = it / (OX / CPT), c0 = (it - r * (OX / CPT)) * CPT;
+        double v[3][NV];
 #pragma unroll
-        for (int k = 0; k < SW; ++k) {
-            double gk = a.g[k];
-            f1 += gk * sg[0][r][c + k];
-            f11 += gk * sg[1][r][c + k];
-            f12 += gk * sg[2][r][c + k];
-        }
-        hm[0][r][c] = f1; hm[1][r][c] = f11; hm[2][r][c] = f12;
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[m][k] = sg[m][r][c0 + k];
+        double out[3][CPT];
+        filter_cpt<3>(g, v, out);
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int o = 0; o < CPT; ++o) hm[m][r][c0 + o] = out[m][o];
     }
     __syncthreads();
-    for (int i = t; i < STY * STX; i += 256) {
-        int r = i / STX, c = i - r * STX;
-        int gr = y0 + r, gc = x0 + c;
-        if (gr >= a.Hc || gc >= a.W) continue;
-        double f1 = 0, f11 = 0, f12 = 0;
+    const int c = t % OX, r0 = (t / OX) * CPT;
+    double f[3][CPT];
+    {
+        double v[3][NV];
 #pragma unroll
-        for (int k = 0; k < SW; ++k) {
-            double gk = a.g[k];
-            f1 += gk * hm[0][r + k][c];
-            f11 += gk * hm[1][r + k][c];
-            f12 += gk * hm[2][r + k][c];
-        }
-        int64_t o = plane_px(a, plane, gr, gc);
-        double xv = x[o], yv = y[o];
-        dimg[o] += (float)(f1 + 2.0 * xv * f11 + yv * f12);
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[m][k] = hm[m][r0 + k][c];
+        filter_cpt<3>(g, v, f);
+    }
+    const int gc = x0 + c;
+#pragma unroll
+    for (int o = 0; o < CPT; ++o) {
+        const int gr = y0 + r0 + o;
+        if (gr >= a.Hc || gc >= a.W) continue;
+        const int64_t q = plane_px(a, plane, gr, gc);
+        const double xv = x[q], yv = y[q];
+        dimg[q] += (float)(f[0][o] + 2.0 * xv * f[1][o] + yv * f[2][o]);
     }
 }
 
@@ -178,7 +220,7 @@ int launch_dssim(const float *img, const float *target, int64_t n_views, int32_t
     for (int k = 0; k < SW; ++k) a.g[k] /= sum;
     double n = 3.0 * (double)n_views * (double)a.hwc;
     double fscale = -weight / n;
-    dim3 grid((width + STX - 1) / STX, (a.Hc + STY - 1) / STY, (unsigned)(n_views * 3));
+    dim3 grid((width + OX - 1) / OX, (a.Hc + OY - 1) / OY, (unsigned)(n_views * 3));
     float *G = static_cast<float *>(ws);
     hipLaunchKernelGGL(ssim_fwd_kernel, grid, dim3(256), 0, st, a, img, target, fscale, weight, G, loss);
     int rc = launch_status("ssim_fwd");
