@@ -367,42 +367,37 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
 }
 
 // C[MA][NB] = sum_r A_r[i] B_r[j] and s[MA] = sum_r A_r[i] over the rows r of a chunk
-// range, A_r = rows[r*R_LEN + aoff .. + MA), B_r = rows[r*R_LEN + boff .. + NB): a dense
-// contraction over the Gaussians, done on the matrix cores.  Each workgroup sums its own
-// range: 32 rows at a time are staged in LDS (A padded to a multiple of 16 columns with
-// zeros), and the 16 x 16 blocks of C are spread over the four waves, each accumulating its
-// blocks with v_mfma_f32_16x16x4f32 (K = 4 rows per instruction: lane l supplies A[k][m]
-// and B[k][n] with k = l / 16 and m, n = l % 16, and holds C[4 (l / 16) + i][l % 16] in
-// accumulator i).  The column sums come from the threads that load A.
+// range, A_r = rows[r*R_LEN + aoff .. + MA), B_r = rows[r*R_LEN + boff .. + NB).  Each
+// workgroup sums its own range: rows are staged 32 at a time in LDS, every thread keeps a
+// 4 x 4 block of C in registers (two 16-byte LDS reads per 16 FMAs), and when C has fewer
+// than 256 such blocks the rows are split between thread groups whose sums are added in a
+// fixed order at the end.  The column sums s come from the threads that load A.
 constexpr int ATB_AR = 32;
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int MA, int NB>
 __global__ __launch_bounds__(256) void atb_kernel(const float *rows, int64_t n, int aoff, int boff, float *partial) {
-    constexpr int MP = (MA + 15) / 16 * 16;            // A columns padded for the 16-wide blocks
-    constexpr int TI = MA / 4, TP = MP / 4, TJ = NB / 4;
-    constexpr int BI = MP / 16, BJ = NB / 16, NBLK = BI * BJ, PER = (NBLK + 3) / 4;  // blocks per wave
-    constexpr int NA = ATB_AR * TP, NBV = ATB_AR * TJ;  // float4 loads per stage
-    // a thread always loads the same A column (t mod TP), which the column sums rely on
-    static_assert(MA % 4 == 0 && NB % 16 == 0 && (NA <= 256 || 256 % TP == 0), "atb tile shape");
-    __shared__ float sa[ATB_AR][MP], sb[ATB_AR][NB];
+    constexpr int TI = MA / 4, TJ = NB / 4, TT = TI * TJ, RS = 256 / TT;
+    constexpr int NA = ATB_AR * TI, NBV = ATB_AR * TJ;  // float4 loads per stage
+    // a thread always loads the same A column (t mod TI), which the column sums rely on
+    static_assert(MA % 4 == 0 && NB % 4 == 0 && TT <= 256 && (NA <= 256 || 256 % TI == 0), "atb tile shape");
+    __shared__ float4 sa[ATB_AR][TI], sb[ATB_AR][TJ];
+    __shared__ float red[RS > 1 ? 256 * 16 : 1];
     __shared__ float4 bred[256];
-    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    const int lk = lane >> 4, lm = lane & 15;
-    f32x4 acc[PER];
+    const int t = threadIdx.x;
+    const int q = t / TT, tt = t - q * TT, ti = tt / TJ, tj = tt - ti * TJ;
+    float acc[16];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 16; ++k) acc[k] = 0.f;
     float4 bs = make_float4(0.f, 0.f, 0.f, 0.f);  // column sums of the A values this thread loads
     const int64_t per = (n + gridDim.x - 1) / gridDim.x;
     const int64_t r0 = (int64_t)blockIdx.x * per, r1 = r0 + per < n ? r0 + per : n;
     for (int64_t base = r0; base < r1; base += ATB_AR) {
         const int cnt = (int)(r1 - base < ATB_AR ? r1 - base : ATB_AR);
         for (int i = t; i < NA; i += 256) {
-            int r = i / TP, c = i - r * TP;
-            float4 v = (r < cnt && c < TI)
-                           ? *reinterpret_cast<const float4 *>(rows + (base + r) * R_LEN + aoff + 4 * c)
-                           : make_float4(0.f, 0.f, 0.f, 0.f);
-            *reinterpret_cast<float4 *>(&sa[r][4 * c]) = v;
+            int r = i / TI, c = i - r * TI;
+            float4 v = r < cnt ? *reinterpret_cast<const float4 *>(rows + (base + r) * R_LEN + aoff + 4 * c)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+            sa[r][c] = v;
             bs.x += v.x;
             bs.y += v.y;
             bs.z += v.z;
@@ -410,44 +405,47 @@ __global__ __launch_bounds__(256) void atb_kernel(const float *rows, int64_t n, 
         }
         for (int i = t; i < NBV; i += 256) {
             int r = i / TJ, c = i - r * TJ;
-            float4 v = r < cnt ? *reinterpret_cast<const float4 *>(rows + (base + r) * R_LEN + boff + 4 * c)
+            sb[r][c] = r < cnt ? *reinterpret_cast<const float4 *>(rows + (base + r) * R_LEN + boff + 4 * c)
                                : make_float4(0.f, 0.f, 0.f, 0.f);
-            *reinterpret_cast<float4 *>(&sb[r][4 * c]) = v;
         }
         __syncthreads();
+        if (q < RS) {
+#pragma unroll 4
+            for (int r = q; r < ATB_AR; r += RS) {
+                const float4 a = sa[r][ti], bv = sb[r][tj];
+                const float av[4] = {a.x, a.y, a.z, a.w}, bw[4] = {bv.x, bv.y, bv.z, bv.w};
 #pragma unroll
-        for (int kk = 0; kk < ATB_AR; kk += 4) {
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const int blk = w * PER + q;
-                if (blk < NBLK) {  // uniform over the wave
-                    const int bi = blk / BJ, bj = blk - bi * BJ;
-                    const float av = sa[kk + lk][16 * bi + lm], bv = sb[kk + lk][16 * bj + lm];
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[q], 0, 0, 0);
-                }
+                    for (int j = 0; j < 4; ++j) acc[4 * i + j] = __fmaf_rn(av[i], bw[j], acc[4 * i + j]);
             }
         }
         __syncthreads();
     }
     constexpr int NE = MA * NB + MA;
     float *out = partial + (int64_t)blockIdx.x * NE;
+    // row groups, added in order
+    if (RS > 1) {
+        if (q < RS && q > 0)
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int blk = w * PER + q;
-        if (blk >= NBLK) continue;
-        const int bi = blk / BJ, bj = blk - bi * BJ;
+            for (int k = 0; k < 16; ++k) red[(q * TT + tt) * 16 + k] = acc[k];
+        __syncthreads();
+        if (q == 0)
+            for (int g = 1; g < RS; ++g)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = 16 * bi + 4 * lk + i, col = 16 * bj + lm;
-            if (row < MA) out[row * NB + col] = acc[q][i];
-        }
+                for (int k = 0; k < 16; ++k) acc[k] += red[(g * TT + tt) * 16 + k];
     }
-    // column sums: thread t loaded column t mod TP of every row it staged
+    if (q == 0)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) out[(4 * ti + i) * NB + 4 * tj + j] = acc[4 * i + j];
+    // column sums: thread t loaded column t mod TI of every row it staged
     bred[t] = bs;
     __syncthreads();
     if (t < TI) {
         float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int u = t; u < 256; u += TP) {
+        for (int u = t; u < 256; u += TI) {
             float4 v = bred[u];
             s4.x += v.x;
             s4.y += v.y;
