@@ -378,7 +378,8 @@ def main():
         res = cal.run(log_every=max(1, args.c2f_steps // 6), log=log)
         wall = time.perf_counter() - tr
         c2f = {"method": "field + coarse-to-fine 10/5/2 cm + bottom-half 0.8 L1 + 0.2 D-SSIM + 1e-3 L_scale",
-               "cloud_points": int(cloud.shape[1]), "stages": res["stages"], "seconds": round(wall, 2),
+               "cloud_points": int(cloud.shape[1]), "stages": res["stages"], "tiles": res["tiles"],
+               "seconds": round(wall, 2),
                "steps_per_s": round(res["steps_per_s"], 2), "views_per_step": 16,
                "init": {k: [round(x, 3) for x in init[k]] for k in init},
                "final": {k: [round(x, 4) for x in res[k]] for k in ("rotation_deg", "translation_cm",
@@ -394,6 +395,7 @@ def main():
             f"{[round(x, 2) for x in cal.errors()['rotation_deg']]} deg")
         res = cal.run(log_every=max(1, args.calib_steps // 6), log=log)
         calib = {"steps_per_s": round(res["steps_per_s"], 2), "steps": res["steps"], "views_per_step": 16,
+                 "tiles": res["tiles"],
                  "final": {k: [round(x, 4) for x in res[k]] for k in ("rotation_deg", "translation_cm",
                                                                      "time_offset_ms")},
                  "init": {"rotation_deg": [round(x, 3) for x in cb.rotation_error_deg(cscene.xi)],

@@ -76,6 +76,10 @@ class CalibConfig:
     stages: tuple = ()
     # replay each step's device work from a captured HIP graph (re-captured when the plan changes)
     graph: bool = True
+    # every this many steps, and after every stage change, time the candidate tile shapes on a few
+    # real steps and keep the fastest (the best shape moves with the Gaussians' opacities); 0 keeps
+    # the given settings
+    tile_tune: int = 500
 
 
 def rotation_error_deg(xi):
@@ -100,9 +104,19 @@ class Calibrator:
         self.full = full
         V, G, Bv = full.n_views, full.n_gauss, cfg.batch_views
         base = settings or pl.make_settings()
-        roi = int(round(full.H * (1.0 - cfg.roi_frac)))
-        self.settings = pl.make_settings(tile=(base.tile_w, base.tile_h), batch=base.batch,
-                                         persistent=bool(base.persistent), roi_y0=min(max(roi, 0), full.H - 1))
+        roi = min(max(int(round(full.H * (1.0 - cfg.roi_frac))), 0), full.H - 1)
+        tiles = [(base.tile_w, base.tile_h)]
+        if cfg.tile_tune:
+            tiles += [t for t in ((16, 16), (8, 8)) if t != tiles[0]]
+        self._cands = [pl.make_settings(tile=t, batch=base.batch, roi_y0=roi,
+                                        persistent=bool(base.persistent) if i == 0 else False)
+                       for i, t in enumerate(tiles)]
+        self._cur = 0
+        self.settings = self._cands[0]
+        self._frames, self._graphs, self._caps = {}, {}, {}
+        self._next_tune = 2 if cfg.tile_tune else None
+        self._trial, self._trial_ev = [], {}
+        self.tile_log = []
         # targets: every view rendered at the ground-truth calibration with the true Gaussians
         zx = torch.zeros((full.n_cams, 6), dtype=torch.float64, device=device)
         zd = torch.zeros(full.n_cams, dtype=torch.float64, device=device)
@@ -226,16 +240,35 @@ class Calibrator:
         self.win = pl.DeviceScene(mean, z(4, G), z(3, G), z(G), z(3, G), full.knot_t, full.knot_q, full.knot_p,
                                   full.R0, full.t0, full.view_cam[idx].contiguous(), full.view_t[idx].contiguous(),
                                   full.intr[idx].contiguous(), full.W, full.H)
-        # slots scale with the number of Gaussians; instances per slot as in the targets
+        # slots scale with the number of Gaussians; instances per slot as in the targets (with the
+        # first candidate's tiles; smaller tiles cut a footprint into more of them)
         r = G / max(1, full.n_gauss)
-        self.slot_cap = int(min(Bv * G, self._ns * 2 * r + 1024))
-        self.inst_cap = int(min((1 << 31) - 1, self._ni * 3 * r + 4096))
-        self.fr = pl.Frame(self.settings, Bv, G, full.W, full.H, self.slot_cap, self.inst_cap, dev)
+        slot_cap = int(min(Bv * G, self._ns * 2 * r + 1024))
+        inst_cap = self._ni * 3 * r + 4096
+        a0 = self._cands[0].tile_w * self._cands[0].tile_h
+        self._caps = {i: (slot_cap, int(min((1 << 31) - 1, inst_cap * max(1.0, (a0 / (c.tile_w * c.tile_h)) ** 0.75))))
+                      for i, c in enumerate(self._cands)}
+        self._frames, self._graphs = {}, {}
+        self._use(self._cur)
         self.gr = pl.alloc_grads(self.win)
         self.dimg = torch.empty_like(self.fr.img)
         if self.cfg.model == "field":
             self.field_ws = torch.empty(B.splat_ngp_workspace_size(G), dtype=torch.uint8, device=dev)
-        self._graph = None
+
+    def _use(self, ci):
+        """Render with candidate ci from now on (its plan and graph are kept for later switches)."""
+        self._cur = ci
+        self.settings = self._cands[ci]
+        if ci not in self._frames:
+            sc, ic = self._caps[ci]
+            self._frames[ci] = pl.Frame(self.settings, self.cfg.batch_views, self.win.n_gauss, self.full.W,
+                                        self.full.H, sc, ic, self.device)
+        self.fr = self._frames[ci]
+        self.slot_cap, self.inst_cap = self._caps[ci]
+        self.dimg = getattr(self, "dimg", None)
+        if self.dimg is None or self.dimg.shape != self.fr.img.shape:
+            self.dimg = torch.empty_like(self.fr.img)
+        self._graph = self._graphs.get(ci)
 
     def _ensure_index(self):
         """Inverse index of the field's table lookups for the current anchors (built once per
@@ -265,6 +298,9 @@ class Calibrator:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         self.stage = i
+        if self.cfg.tile_tune:
+            self._trial = []
+            self._next_tune = self.stage_starts[i] + 1
         self.stage_log.append(dict(voxel_m=float(voxel), steps=int(n), gaussians=int(mean.shape[1]),
                                    setup_ms=round((t1 - t0) * 1e3, 2), done=0, _t0=t1))
 
@@ -310,12 +346,28 @@ class Calibrator:
                     grp["lr"].fill_(lr0 * frac)
                 else:
                     grp["lr"] = lr0 * frac
+        if self._next_tune is not None and k >= self._next_tune and not self._trial:
+            # three steps per candidate; the first one of each may include a graph capture
+            self._trial = [ci for ci in range(len(self._cands)) for _ in range(3)]
+            self._trial_ev = {ci: [] for ci in range(len(self._cands))}
+        ev = None
+        if self._trial:
+            ci = self._trial.pop(0)
+            if ci != self._cur:
+                self._use(ci)
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            ev[0].record()
         if cfg.graph and self._graph is not None:
             self._graph.replay()
         else:
             self._body()
             if cfg.graph:  # this step ran eagerly (lazy initialisation); record the next ones
                 self._capture()
+        if ev is not None:
+            ev[1].record()
+            self._trial_ev[self._cur].append(ev)
+            if not self._trial:
+                self._finish_tune(k)
         if k >= cfg.warmup:
             self.opt_c.step()
         self._queue_status(k)
@@ -325,6 +377,20 @@ class Calibrator:
         with torch.cuda.graph(g):
             self._body()
         self._graph = g
+        self._graphs[self._cur] = g
+
+    def _finish_tune(self, k):
+        torch.cuda.synchronize()
+        ms = {}
+        for ci, evs in self._trial_ev.items():
+            t = sorted(a.elapsed_time(b) for a, b in evs[1:]) or [float("inf")]
+            ms[ci] = t[len(t) // 2]
+        best = min(ms, key=ms.get)
+        self._use(best)
+        self.tile_log.append(dict(step=k, ms={f"{c.tile_w}x{c.tile_h}": round(ms[i], 3)
+                                              for i, c in enumerate(self._cands)},
+                                  tile=f"{self._cands[best].tile_w}x{self._cands[best].tile_h}"))
+        self._next_tune = k + self.cfg.tile_tune
 
     def _body(self):
         """The device work of one step: views of the batch, Gaussian parameters, render forward,
@@ -411,15 +477,15 @@ class Calibrator:
                     self.overflow_steps.append(-1)
 
     def _grow(self):
-        """Re-plan with twice the capacities after a step whose instances or slots overflowed."""
+        """Re-plan the current candidate with twice the capacities after a step whose instances or
+        slots overflowed."""
         ns, ni = self.fr.counts()
         G, Bv = self.win.n_gauss, self.cfg.batch_views
-        self.slot_cap = int(min(Bv * G, max(self.slot_cap, 2 * ns)))
-        self.inst_cap = int(min((1 << 31) - 1, 2 * max(self.inst_cap, ni)))
-        self.fr = pl.Frame(self.settings, Bv, G, self.full.W, self.full.H, self.slot_cap, self.inst_cap,
-                           self.device)
-        self.dimg = torch.empty_like(self.fr.img)
-        self._graph = None
+        sc, ic = self._caps[self._cur]
+        self._caps[self._cur] = (int(min(Bv * G, max(sc, 2 * ns))), int(min((1 << 31) - 1, 2 * max(ic, ni))))
+        self._frames.pop(self._cur, None)
+        self._graphs.pop(self._cur, None)
+        self._use(self._cur)
         self.replans += 1
 
     def errors(self):
@@ -450,5 +516,6 @@ class Calibrator:
                 self.overflow_steps.append(k)
             self._st_ev[j] = None
         out = dict(steps=steps, steps_per_s=sps, loss=float(self.loss.item()), replans=self.replans,
-                   overflow_steps=len(self.overflow_steps), stages=self.stage_log, **self.errors())
+                   overflow_steps=len(self.overflow_steps), stages=self.stage_log, tiles=self.tile_log,
+                   **self.errors())
         return out

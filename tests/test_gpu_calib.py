@@ -115,3 +115,16 @@ def test_graph_replayed_steps_follow_the_eager_steps(model):
     np.testing.assert_allclose(xb, xa, rtol=0, atol=0.02 * np.abs(xa - x0).max() + 1e-7)
     np.testing.assert_allclose(db, da, rtol=0, atol=0.02 * np.abs(da - s.delta).max() + 1e-7)
     assert np.abs(da - s.delta).max() > 1e-4  # the time offsets did move
+
+
+def test_calibration_retunes_its_tile_shape():
+    """The loop times its tile candidates on real steps, keeps the fastest, and keeps going."""
+    say("case: calibration tile retuning")
+    s = synth.small_drive(15, n_points=4000, W=160, H=64, f=70.0, n_frames=4, deg=2.0, metres=0.1, delta=0.02)
+    cal = cb.Calibrator(s, cb.CalibConfig(steps=30, warmup=5, batch_views=4, seed=6, tile_tune=12))
+    res = cal.run()
+    assert len(res["tiles"]) == 2  # rounds of six timed steps from steps 2 and 19 (12 after the first ended)
+    for t in res["tiles"]:
+        assert t["tile"] in t["ms"] and set(t["ms"]) == {"16x16", "8x8"}
+        assert t["ms"][t["tile"]] == min(t["ms"].values())
+    assert math.isfinite(res["loss"])
