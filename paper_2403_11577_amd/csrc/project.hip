@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, sp
                                                            const CamC *cam, int W, int H, int V, int nb,
                                                            const uint32_t *waveoff, const uint64_t *visbits,
                                                            int64_t slot_cap, float4 *rec, int2 *meta, Rect16 *rect,
-                                                           uint32_t *ntiles, float *grad2d) {
+                                                           uint32_t *ntiles) {
     const int b = blockIdx.x, w = threadIdx.x >> 6, lane = __lane_id();
     const int64_t i = (int64_t)b * 256 + threadIdx.x;
     if (i >= g.n) return;
@@ -275,10 +275,14 @@ __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, sp
         rc.y0 = (uint16_t)(P.py0 / th); rc.y1 = (uint16_t)(P.py1 / th);
         rect[slot] = rc;
         ntiles[slot] = (uint32_t)(rc.x1 - rc.x0 + 1) * (uint32_t)(rc.y1 - rc.y0 + 1);
-        float *gd = grad2d + 9 * slot;  // the slot's gradient, accumulated by the render adjoint
-#pragma unroll
-        for (int q = 0; q < 9; ++q) gd[q] = 0.f;
     }
+}
+
+// The slots' gradients, which the render adjoint accumulates, start at zero.
+__global__ void zero_grad2d_kernel(const uint32_t *counts, float *g) {
+    uint64_t n = (uint64_t)counts[CNT_SLOTS] * 9;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        g[i] = 0.f;
 }
 
 // totals after the (view, wave) count scan: slot count (clamped), view offsets, capacity flag
@@ -545,9 +549,12 @@ int launch_project(const splat_plan &p, void *ws, const splat_gaussians &g, cons
     if (rc || g.n == 0) return rc;
     hipLaunchKernelGGL(project_write_kernel, dim3(nb), dim3(256), 0, st, p.s, g, w2c, cam, p.width, p.height, V, nb,
                        wavecnt, visbits, p.slot_cap, ws_at<float4>(ws, p.off_rec), ws_at<int2>(ws, p.off_meta),
-                       ws_at<Rect16>(ws, p.off_rect), ws_at<uint32_t>(ws, p.off_ntiles),
-                       ws_at<float>(ws, p.off_grad2d));
-    return launch_status("project_write");
+                       ws_at<Rect16>(ws, p.off_rect), ws_at<uint32_t>(ws, p.off_ntiles));
+    if ((rc = launch_status("project_write"))) return rc;
+    int zb = (int)((p.slot_cap * 9 + 255) / 256);
+    if (zb > 8192) zb = 8192;
+    hipLaunchKernelGGL(zero_grad2d_kernel, dim3(zb), dim3(256), 0, st, counts, ws_at<float>(ws, p.off_grad2d));
+    return launch_status("zero_grad2d");
 }
 
 int launch_project_bwd(const splat_plan &p, void *ws, const splat_gaussians &g, const double *w2c,
