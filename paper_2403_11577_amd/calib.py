@@ -80,6 +80,7 @@ class CalibConfig:
     # real steps and keep the fastest (the best shape moves with the Gaussians' opacities); 0 keeps
     # the given settings
     tile_tune: int = 500
+    fused_adam: bool = True        # torch's single-kernel Adam (else its multi-tensor one)
 
 
 def rotation_error_deg(xi):
@@ -170,12 +171,12 @@ class Calibrator:
         ] if self.field is None else [
             dict(params=[self.field["tables"]], lr=lr(cfg.lr_field_table), weight_decay=cfg.field_weight_decay),
             dict(params=[self.field[k] for k in ("w1", "b1", "w2", "b2", "w3", "b3")], lr=lr(cfg.lr_field_mlp)),
-        ], eps=1e-15, capturable=cfg.graph)
+        ], eps=1e-15, capturable=cfg.graph, fused=cfg.fused_adam or None)
         self.opt_c = torch.optim.Adam([
             dict(params=[self.rho], lr=lr(cfg.lr_trans)),
             dict(params=[self.phi], lr=lr(cfg.lr_rot)),
             dict(params=[self.delta], lr=lr(cfg.lr_time)),
-        ], eps=1e-15, capturable=cfg.graph)
+        ], eps=1e-15, capturable=cfg.graph, fused=cfg.fused_adam or None)
         self.base_lr = [[float(grp["lr"]) for grp in o.param_groups] for o in (self.opt_g, self.opt_c)]
         # gradient buffers the step writes in place (fixed addresses, as a captured graph needs)
         for t in (self.rho, self.phi, self.delta):
