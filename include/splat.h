@@ -83,7 +83,9 @@ typedef struct splat_settings {
     double pad_px, pad_rel;
     int32_t tile_w, tile_h, batch, persistent;
     int32_t roi_y0;     /* first image row of the region of interest; rows above are not rendered */
-    int32_t reserved0;
+    int32_t split_len;  /* instances per work item of the render adjoint (0: 1024; else a power of
+                           two in [64, 2^24]); a tile list at least this long is split into chunks of
+                           this length that are walked in parallel                                 */
 } splat_settings;
 
 /* Gaussian parameters: device SoA planes of length n (float32).
@@ -108,7 +110,8 @@ typedef struct splat_plan {
     int64_t n_gauss, slot_cap, inst_cap;
     size_t ws_bytes;
     size_t off_status;      /* u32                                                      */
-    size_t off_counts;      /* u32[8]: 0 slots, 1 instances, 2 work counter, 3..7 spare  */
+    size_t off_counts;      /* u32[8]: 0 slots, 1 instances, 2 work counter, 3 split lists, 4 chunks
+                               of the split lists, 5 render-adjoint items, 6..7 spare        */
     size_t off_view_off;    /* u32[V+1] first slot of every view                          */
     size_t off_blockcnt;    /* u32[V*n_blocks_proj*4+1] visible count per (view, wave), scanned in place to slot offsets */
     size_t off_rec;         /* float4[3][slot_cap]: (mx,my,lx,ly) (a,b,c,o) (r,g,b,depth) */
@@ -127,6 +130,16 @@ typedef struct splat_plan {
     size_t off_cam;         /* f64[V][8]: per-view camera constants of the projection       */
     int32_t sorted_buf;     /* which of the two key/value buffers holds the sorted result */
     int32_t radix_bits;     /* digit width of the LSD radix sort (passes = ceil(key bits / radix_bits)) */
+    int32_t split_len;      /* instances per render-adjoint work item (the settings' value or 1024)   */
+    int32_t reserved1;
+    int64_t chk_cap;        /* checkpoint slots (an upper bound of what the tile lists can need)     */
+    int64_t bq_cap;         /* render-adjoint work items (upper bound)                               */
+    size_t off_bqueue;      /* uint4[bq_cap]: adjoint items (view-tile, chunk, first checkpoint slot or
+                               0xFFFFFFFF, 0): the chunks of the split lists, then the other tiles,
+                               both in work-queue order                                              */
+    size_t off_bqoff;       /* u32[V*T+1]: chunk count per split queue position, scanned to offsets */
+    size_t off_chk;         /* float4[chk_cap][tile_w*tile_h]: per-pixel (T, C) of a split list: its
+                               first slot holds the final state, slot c the state where chunk c starts */
 } splat_plan;
 
 /* Fill `s` with the default settings listed above (16x16 tiles, batch 64,

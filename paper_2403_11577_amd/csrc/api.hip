@@ -72,6 +72,9 @@ static int check_settings(const splat_settings *s) {
     }
     if (s->persistent != 0 && s->persistent != 1) { set_error("persistent must be 0 or 1"); return SPLAT_EINVAL; }
     if (s->roi_y0 < 0) { set_error("roi_y0 must be >= 0 (got %d)", s->roi_y0); return SPLAT_EINVAL; }
+    if (s->split_len != 0 && (s->split_len < 64 || s->split_len > (1 << 24) || (s->split_len & (s->split_len - 1)))) {
+        set_error("split_len must be 0 or a power of two in [64, 2^24] (got %d)", s->split_len); return SPLAT_EINVAL;
+    }
     return SPLAT_OK;
 }
 
@@ -144,7 +147,7 @@ void splat_default_settings(splat_settings *s) {
     s->batch = 64;
     s->persistent = 1;
     s->roi_y0 = 0;
-    s->reserved0 = 0;
+    s->split_len = 0;
 }
 
 int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, int32_t width, int32_t height,
@@ -206,6 +209,8 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     size_t np3 = scan_partials((int64_t)kRadixDigits * p.n_sort_blocks);
     if (np2 > nparts) nparts = np2;
     if (np3 > nparts) nparts = np3;
+    size_t np4 = scan_partials((int64_t)n_views * p.tiles_per_view + 1);
+    if (np4 > nparts) nparts = np4;
     p.off_status = take(4);
     p.off_counts = take(8 * 4);
     p.off_view_off = take((size_t)(n_views + 1) * 4);
@@ -224,6 +229,14 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     p.off_visbits = take((size_t)n_views * p.n_blocks_proj * 4 * 8);
     p.off_dwpart = take((size_t)n_views * p.n_blocks_proj * 4 * 12 * 8);
     p.off_cam = take((size_t)n_views * 8 * 8);
+    // render-adjoint work items: a list of L >= split_len instances becomes ceil(L / split_len) <=
+    // 2 L / split_len chunks, so the split lists need fewer than 2 inst_cap / split_len chunks
+    p.split_len = s->split_len ? s->split_len : 1024;
+    p.chk_cap = 2 * ((inst_cap + p.split_len - 1) / p.split_len) + 1;
+    p.bq_cap = (int64_t)ntiles_all + p.chk_cap;
+    p.off_bqueue = take((size_t)p.bq_cap * 16);
+    p.off_bqoff = take(((size_t)ntiles_all + 1) * 4);
+    p.off_chk = take((size_t)p.chk_cap * (size_t)(s->tile_w * s->tile_h) * 16);
     p.ws_bytes = off;
     *plan = p;
     return SPLAT_OK;

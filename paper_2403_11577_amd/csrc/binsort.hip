@@ -448,6 +448,49 @@ __global__ __launch_bounds__(256) void queue_scatter_kernel(const uint2 *ranges,
     }
 }
 
+// -------------------------------------------------------------------------------------
+// render-adjoint work items
+// -------------------------------------------------------------------------------------
+// A list of at least Lc = 2^lc_log instances is split into ceil(L / Lc) chunks that the
+// adjoint walks in parallel.  The queue is ordered by floor(log2 L), so the split lists are
+// exactly its first nsplit positions.  Per split position the chunk count is written for a
+// scan; nsplit is written by the one position where the split prefix ends.
+__global__ __launch_bounds__(256) void split_count_kernel(const uint2 *ranges, const uint32_t *queue, int n,
+                                                         int lc_log, uint32_t *cnt, uint32_t *counts) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        uint2 r = ranges[queue[q]];
+        uint32_t L = r.y - r.x;
+        bool sp = (L >> lc_log) != 0u;
+        cnt[q] = sp ? (uint32_t)(((uint64_t)L + (1u << lc_log) - 1) >> lc_log) : 0u;
+        bool sp_next = false;
+        if (q + 1 < n) {
+            uint2 r2 = ranges[queue[q + 1]];
+            sp_next = ((r2.y - r2.x) >> lc_log) != 0u;
+        }
+        if (sp && !sp_next) counts[CNT_NSPLIT] = (uint32_t)(q + 1);
+        if (q == 0 && !sp) counts[CNT_NSPLIT] = 0u;
+    }
+}
+
+// items: the chunks of the split lists (at their scanned offsets; chunk c of a list whose
+// checkpoints start at slot s is (tile, c, s)), then the unsplit tiles (tile, 0, ~0)
+__global__ __launch_bounds__(256) void split_items_kernel(const uint2 *ranges, const uint32_t *queue, int n,
+                                                         const uint32_t *off, uint32_t *counts, uint4 *items,
+                                                         int64_t cap) {
+    uint32_t ns = counts[CNT_NSPLIT], nch = counts[CNT_NCHUNK];
+    if (blockIdx.x == 0 && threadIdx.x == 0) counts[CNT_BITEMS] = nch + ((uint32_t)n - ns);
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        uint32_t t = queue[q];
+        if ((uint32_t)q < ns) {
+            uint32_t o = off[q], c1 = off[q + 1];
+            for (uint32_t c = 0; o + c < c1 && (int64_t)(o + c) < cap; ++c) items[o + c] = make_uint4(t, c, o, 0u);
+        } else {
+            uint64_t i = (uint64_t)nch + (uint32_t)q - ns;
+            if ((int64_t)i < cap) items[i] = make_uint4(t, 0u, 0xFFFFFFFFu, 0u);
+        }
+    }
+}
+
 }  // namespace
 
 size_t scan_partials(int64_t n_cap) { return (size_t)((n_cap + SCAN_TILE - 1) / SCAN_TILE) + 1; }
@@ -544,7 +587,18 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
     hipLaunchKernelGGL(queue_scan_kernel, dim3(1), dim3(64), 0, st, qh);
     if ((rc = launch_status("queue_scan"))) return rc;
     hipLaunchKernelGGL(queue_scatter_kernel, dim3(qb), dim3(256), 0, st, ranges, nT, qh, queue);
-    return launch_status("queue_scatter");
+    if ((rc = launch_status("queue_scatter"))) return rc;
+
+    // render-adjoint items: split lists first, each as its chunks, then the other tiles
+    uint32_t *boff = ws_at<uint32_t>(ws, p.off_bqoff);
+    int lc_log = 0;
+    while ((1 << lc_log) < p.split_len) ++lc_log;
+    hipLaunchKernelGGL(split_count_kernel, dim3(qb), dim3(256), 0, st, ranges, queue, nT, lc_log, boff, counts);
+    if ((rc = launch_status("split_count"))) return rc;
+    if ((rc = launch_scan_u32(boff, boff, counts + CNT_NSPLIT, nT, partials, counts + CNT_NCHUNK, st))) return rc;
+    hipLaunchKernelGGL(split_items_kernel, dim3(qb), dim3(256), 0, st, ranges, queue, nT, boff, counts,
+                       ws_at<uint4>(ws, p.off_bqueue), p.bq_cap);
+    return launch_status("split_items");
 }
 
 }  // namespace splat

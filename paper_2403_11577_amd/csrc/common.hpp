@@ -29,7 +29,7 @@ struct alignas(8) Rect16 {
 };
 
 // counter indices in off_counts
-enum { CNT_SLOTS = 0, CNT_INST = 1, CNT_WORK = 2 };
+enum { CNT_SLOTS = 0, CNT_INST = 1, CNT_WORK = 2, CNT_NSPLIT = 3, CNT_NCHUNK = 4, CNT_BITEMS = 5 };
 
 // float <-> bits
 __device__ inline uint32_t f2u(float f) { return __float_as_uint(f); }

@@ -37,9 +37,13 @@ struct RenderArgs {
     const uint2 *ranges;        // [V*T]
     const uint32_t *queue;      // [V*T] work items in decreasing cost
     uint32_t *work;             // persistent work counter
-    const uint32_t *counts;     // device counts (slots, instances)
+    const uint32_t *counts;     // device counts (slots, instances, split lists, adjoint items)
+    const uint4 *bitems;        // adjoint work items (tile, chunk, first checkpoint slot, -)
+    const uint32_t *boff;       // first checkpoint slot of each split queue position
+    float4 *chk;                // checkpoints: per-pixel (T, C) of the split lists
     unsigned long long *stats;  // pair counters of the instrumented variant
     int n_items, T, tiles_x, W, H, persistent, roi_y0;
+    uint32_t lc, chk_cap;       // split length, checkpoint slots
     float amin, amax, tmin, lamin2;  // lamin2 = log2(alpha_min)
     float bg0, bg1, bg2;
 };
@@ -174,16 +178,28 @@ __device__ inline void stat_add(unsigned long long *dst, unsigned long long v) {
     if (__lane_id() == 0 && v) atomicAdd(dst, v);
 }
 
-__device__ __forceinline__ bool next_item(const RenderArgs &a, int iter, int &item) {
+// Work items: persistent waves pull them from a counter; otherwise workgroup b takes items
+// b, b + grid, ... (the grid covers the forward's items; the adjoint can have a few more).
+__device__ __forceinline__ bool next_item(const RenderArgs &a, int iter, int n, int &item) {
     if (a.persistent) {
         uint32_t it = 0;
         if (__lane_id() == 0) it = atomicAdd(a.work, 1u);
         item = __builtin_amdgcn_readfirstlane((int)it);
     } else {
-        if (iter > 0) return false;
-        item = blockIdx.x;
+        item = (int)blockIdx.x + iter * (int)gridDim.x;
     }
-    return item < a.n_items;
+    return item < n;
+}
+
+// checkpoint of a split list: the per-pixel (T, C) of one tile
+template <int NSB>
+__device__ __forceinline__ void put_chk(const RenderArgs &a, uint32_t slot, const float (&T)[NSB],
+                                        const float (&C0)[NSB], const float (&C1)[NSB], const float (&C2)[NSB],
+                                        int lane) {
+    if (slot >= a.chk_cap) return;  // cannot happen: the capacity bounds every split list's chunks
+    float4 *d = a.chk + (size_t)slot * (NSB * 64) + lane;
+#pragma unroll
+    for (int k = 0; k < NSB; ++k) d[k * 64] = make_float4(T[k], C0[k], C1[k], C2[k]);
 }
 
 // Pixel layout: lane l covers pixel (l & 7, l >> 3) of every 8x8 sub-block k of
@@ -205,9 +221,10 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
     const int lx = lane & 7, ly = lane >> 3;
     const size_t HW = (size_t)a.W * a.H;
     const uint32_t nslots = a.counts[CNT_SLOTS];
+    const uint32_t nsplit = a.counts[CNT_NSPLIT];
     unsigned long long n_eval = 0, n_blend = 0;
     int item;
-    for (int iter = 0; next_item(a, iter, item); ++iter) {
+    for (int iter = 0; next_item(a, iter, a.n_items, item); ++iter) {
         int tid = (int)a.queue[item];
         int v = tid / a.T, tile = tid - v * a.T;
         int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
@@ -230,7 +247,16 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
         Stage cur = derive<TW, TH>(a, load_raw(a, load_slot(a, rg.x + lane, rg.y), nslots), fxb, fyb, fox, foy);
         put_stage(sg, cur, lane);
         uint32_t sl_next = load_slot(a, rg.x + 64 + lane, rg.y);
+        // a split list records (T, C) where each of its chunks starts (chunks are whole batches)
+        const bool split = (uint32_t)item < nsplit;
+        const uint32_t cslot = split ? a.boff[item] : 0u;
+        uint32_t bnext = split ? rg.x + a.lc : 0xFFFFFFFFu, cnext = cslot + 1;
         for (uint32_t b = rg.x; b < rg.y; b += 64) {
+            if (b == bnext) {
+                put_chk<NSB>(a, cnext, T, C0, C1, C2, lane);
+                ++cnext;
+                bnext += a.lc;
+            }
             uint32_t live = 0;  // sub-blocks with a pixel still compositing
 #pragma unroll
             for (int k = 0; k < NSB; ++k) live |= __ballot(L[k] > 0.f) ? (1u << k) : 0u;
@@ -271,6 +297,12 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
             cur = derive<TW, TH>(a, raw_next, fxb, fyb, fox, foy);
             put_stage(sg, cur, lane);
             sl_next = sl_after;
+        }
+        if (split) {
+            // chunks after an early exit start from the final state, which the first slot also holds
+            const uint32_t cend = cslot + (rg.y - rg.x + a.lc - 1) / a.lc;
+            for (; cnext < cend; ++cnext) put_chk<NSB>(a, cnext, T, C0, C1, C2, lane);
+            put_chk<NSB>(a, cslot, T, C0, C1, C2, lane);
         }
         size_t vo = (size_t)v * HW;
 #pragma unroll
@@ -348,14 +380,30 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
     const int cls = (int)c0 | ((int)c1 << 1) | ((int)c2 << 2) | ((int)c3 << 3);
     const bool writer = lane < 16 && cls < 9;
     unsigned long long n_eval = 0, n_contrib = 0, n_atomic = 0;
+    const int n_items = (int)min(a.counts[CNT_BITEMS], (uint32_t)a.n_items);
     int item;
-    for (int iter = 0; next_item(a, iter, item); ++iter) {
-        int tid = (int)a.queue[item];
+    for (int iter = 0; next_item(a, iter, n_items, item); ++iter) {
+        const uint4 it = a.bitems[item];
+        int tid = (int)it.x;
         int v = tid / a.T, tile = tid - v * a.T;
         int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
         int x0 = tx * TW, y0 = ty * TH;
         int xb = x0 & ~31, yb = y0 & ~31;
         uint2 rg = a.ranges[tid];
+        // the walk covers [cs, ce): the whole list, or chunk it.y of a split list; a chunk other
+        // than the last starts from the checkpoint where the next chunk starts
+        int cs = (int)rg.x, ce = (int)rg.y;
+        bool from_chk = false;
+        size_t qoff = 0, foff = 0;
+        if (it.z != 0xFFFFFFFFu) {
+            uint32_t nc = (rg.y - rg.x + a.lc - 1) / a.lc;
+            cs = (int)(rg.x + it.y * a.lc);
+            ce = min((int)rg.y, cs + (int)a.lc);
+            from_chk = it.y + 1 < nc;
+            if (it.z + it.y + 1 >= a.chk_cap || it.y >= nc) continue;  // cannot happen (capacity bound)
+            qoff = (size_t)(it.z + it.y + 1) * (NSB * 64) + lane;
+            foff = (size_t)it.z * (NSB * 64) + lane;
+        }
         float T[NSB], P[NSB], gc0[NSB], gc1[NSB], gc2[NSB], px[NSB], py[NSB];
         int last[NSB], kmax[NSB];
         size_t vo = (size_t)v * HW;
@@ -380,26 +428,32 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
                 gc2[k] = dimg[3 * vo + 2 * HW + o];
             }
             P[k] = T[k] * (gc0[k] * a.bg0 + gc1[k] * a.bg1 + gc2[k] * a.bg2);
-            int mk = last[k];
+            if (from_chk) {
+                // colour behind the chunk: C_final - C(ce) plus the background
+                const float4 q = a.chk[qoff + k * 64], f = a.chk[foff + k * 64];
+                P[k] += __fmaf_rn(gc2[k], f.w - q.w, __fmaf_rn(gc1[k], f.z - q.z, gc0[k] * (f.y - q.y)));
+                T[k] = q.x;
+            }
+            int mk = min(last[k], ce - 1);
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) mk = max(mk, __shfl_xor(mk, o, kWave));
             kmax[k] = __builtin_amdgcn_readfirstlane(mk);  // per sub-block: walk no further than this
             wmax = max(wmax, kmax[k]);
         }
-        int hi = wmax + 1;  // walk [rg.x, hi) backwards
-        if (hi <= (int)rg.x) continue;
+        int hi = wmax + 1;  // walk [cs, hi) backwards
+        if (hi <= cs) continue;
         const float fxb = (float)xb, fyb = (float)yb, fox = (float)(x0 - xb), foy = (float)(y0 - yb);
         int e = hi;
-        int bs = max((int)rg.x, e - 64);
+        int bs = max(cs, e - 64);
         Stage cur = derive<TW, TH>(a, load_raw(a, load_slot(a, (uint32_t)(bs + lane), (uint32_t)e), nslots), fxb,
                                    fyb, fox, foy);
         put_stage(sg, cur, lane);
-        int bs2 = max((int)rg.x, bs - 64);
+        int bs2 = max(cs, bs - 64);
         uint32_t sl_next = load_slot(a, (uint32_t)(bs2 + lane), (uint32_t)bs);
-        while (e > (int)rg.x) {
+        while (e > cs) {
             int n = e - bs;
             int e2 = bs;
-            int bs3 = max((int)rg.x, bs2 - 64);
+            int bs3 = max(cs, bs2 - 64);
             Raw raw_next = load_raw(a, sl_next, nslots);                                 // batch [bs2, bs)
             uint32_t sl_after = load_slot(a, (uint32_t)(bs3 + lane), (uint32_t)bs2);   // batch [bs3, bs2)
             // the batch's Gaussians with a footprint in the tile, last first (lanes at or past n
@@ -485,6 +539,11 @@ RenderArgs make_args(const splat_plan &p, void *ws, unsigned long long *stats) {
     a.queue = ws_at<uint32_t>(ws, p.off_queue);
     a.work = ws_at<uint32_t>(ws, p.off_counts) + CNT_WORK;
     a.counts = ws_at<uint32_t>(ws, p.off_counts);
+    a.bitems = ws_at<uint4>(ws, p.off_bqueue);
+    a.boff = ws_at<uint32_t>(ws, p.off_bqoff);
+    a.chk = ws_at<float4>(ws, p.off_chk);
+    a.lc = (uint32_t)p.split_len;
+    a.chk_cap = (uint32_t)p.chk_cap;
     a.stats = stats;
     a.n_items = p.n_views * p.tiles_per_view;
     a.T = p.tiles_per_view;
@@ -536,12 +595,14 @@ int bwd_impl(const splat_plan &p, void *ws, const float *dimg, const float *T, c
     RenderArgs a = make_args(p, ws, stats);
     float *g2 = ws_at<float>(ws, p.off_grad2d);  // zeroed per slot by the projection
     int rc = 0;
-    if (a.n_items == 0) return rc;
-    int grid = a.n_items;
+    const int nT = a.n_items;
+    if (nT == 0) return rc;
+    a.n_items = (int)(p.bq_cap < INT32_MAX ? p.bq_cap : INT32_MAX);  // bound of the device item count
+    int grid = nT;
     if (a.persistent) {
         hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(1), 0, st, a.work);
         if ((rc = launch_status("reset_work"))) return rc;
-        grid = persistent_grid(a.n_items, 32);
+        grid = persistent_grid(nT, 32);
     }
     if (stats)
         hipLaunchKernelGGL((render_bwd_kernel<TW, TH, true>), dim3(grid), dim3(64), 0, st, a, dimg, T, last, g2);

@@ -172,10 +172,12 @@ def test_render_invariant_across_launch_shapes():
                 assert np.array_equal(o["last_id"], base["last_id"])
 
 
-def _grad_case(scene, tile, seed=0):
+def _grad_case(scene, tile, seed=0, split_len=0, persistent=True, keep=None):
     w2c_ref, _, _ = oracle.pose(scene.traj, scene.rig, scene.xi, scene.delta, scene.views)
     target = oracle.render_scene(scene, xi=scene.xi_gt, delta=scene.delta_gt)["img"]
-    g = gpu_render(scene, tile=tile)
+    g = gpu_render(scene, tile=tile, split_len=split_len, persistent=persistent)
+    if keep is not None:
+        keep["render"] = g
     fr, ds = g["frame"], g["ds"]
     # pixels with a threshold decision or an alpha_max kink near the margin are left out on both sides
     mset = oracle.Settings(margin=1e-2)
@@ -191,6 +193,8 @@ def _grad_case(scene, tile, seed=0):
                       dimg.astype(np.float32).astype(np.float64), mask=mask.astype(np.int8))
     rxi, rdl = oracle.pose_bwd(scene.traj, scene.rig, scene.xi, scene.delta, scene.views, ref["w2c"])
     out = {}
+    if keep is not None:
+        keep["grads"] = {n: getattr(gr, n).cpu().numpy() for n in ("quat", "scale", "opacity", "color", "mean", "w2c")}
     for name in ("quat", "scale", "opacity", "color", "mean"):
         ok, err = rel_close(getattr(gr, name).cpu().numpy(), ref[name], 1e-3)
         out[name] = (ok, err)
@@ -209,6 +213,38 @@ def test_gradients_vs_oracle(tile):
     say("  masked frac %.4f " % mfrac + " ".join(f"{k}={v[1]:.2e}" for k, v in out.items()))
     for k, (ok, err) in out.items():
         assert ok, (k, err)
+
+
+@pytest.mark.parametrize("tile, persistent", [((16, 16), True), ((8, 8), True), ((16, 16), False), ((8, 8), False)])
+def test_gradients_split_lists_vs_oracle(tile, persistent):
+    # every tile list of 64 instances or more is walked by the adjoint as chunks of 64, each
+    # started from the forward's checkpoint where the next chunk starts
+    say(f"case: gradients with split lists tile={tile} persistent={persistent}")
+    scene = synth.small_drive(5, n_frames=2)
+    kept, base = {}, {}
+    out, _ = _grad_case(scene, tile, split_len=64, persistent=persistent, keep=kept)
+    fr = kept["render"]["frame"]
+    cnt = fr.buf("counts", torch.int32, 8).cpu().numpy()
+    nT = fr.plan.n_views * fr.plan.tiles_per_view
+    rg = fr.buf("ranges", torch.int32, 2 * nT).view(nT, 2).cpu().numpy().astype(np.int64)
+    L = rg[:, 1] - rg[:, 0]
+    nsplit, nchunk, nitems = int(cnt[3]), int(cnt[4]), int(cnt[5])
+    say(f"  split lists {nsplit}, chunks {nchunk}, adjoint items {nitems}, longest list {L.max()}")
+    assert nsplit == int((L >= 64).sum()) and nsplit > 0
+    assert nchunk == int(((L[L >= 64] + 63) // 64).sum())
+    assert nitems == nchunk + nT - nsplit
+    say("  " + " ".join(f"{k}={v[1]:.2e}" for k, v in out.items()))
+    for k, (ok, err) in out.items():
+        assert ok, (k, err)
+    # the same adjoint without splitting: the forward is identical, the gradients agree to rounding
+    _grad_case(scene, tile, split_len=1 << 24, persistent=persistent, keep=base)
+    for k in ("img", "T", "last_id"):
+        assert np.array_equal(kept["render"][k], base["render"][k]), k
+    for k, a in kept["grads"].items():
+        b = base["grads"][k]
+        err = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+        say(f"  split vs unsplit {k}: {err:.2e}")
+        assert err <= 1e-4, (k, err)
 
 
 def test_gradients_tiny_vs_oracle():
