@@ -245,6 +245,7 @@ def main():
         log(f"[bench] autotune: {tune['best']} of {len(tune['candidates'])} candidates")
 
     step = pl.BatchedStep(ds, xi, delta, targets, settings)
+    split_len = int(step.fr.plan.split_len)
     step.run()
     torch.cuda.synchronize()
     ns, ni = step.fr.counts()
@@ -419,6 +420,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "views": V, "width": W, "height": H, "gaussians": int(scene.gauss.n),
                    "tile": args.tile, "persistent": bool(settings.persistent), "path": "batched",
+                   "joined_forward": bool(settings.split_fwd), "split_len": split_len,
                    "visible_per_view": {"min": int(vis.min()), "median": int(np.median(vis)), "max": int(vis.max())}},
         "loss": loss,
         "graph": graph,

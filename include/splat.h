@@ -86,6 +86,11 @@ typedef struct splat_settings {
     int32_t split_len;  /* instances per work item of the render adjoint (0: 1024; else a power of
                            two in [64, 2^24]); a tile list at least this long is split into chunks of
                            this length that are walked in parallel                                 */
+    int32_t split_fwd;  /* 1: the forward also composites the chunks after the first of every split
+                           list in parallel, each from T = 1, and joins them per pixel (exact up to
+                           rounding; a chunk in which a pixel could reach t_min is walked in order).
+                           Pays off when few pixels saturate; 0 (default): one walk per list */
+    int32_t reserved0;
 } splat_settings;
 
 /* Gaussian parameters: device SoA planes of length n (float32).
@@ -140,6 +145,8 @@ typedef struct splat_plan {
     size_t off_bqoff;       /* u32[V*T+1]: chunk count per split queue position, scanned to offsets */
     size_t off_chk;         /* float4[chk_cap][tile_w*tile_h]: per-pixel (T, C) of a split list: its
                                first slot holds the final state, slot c the state where chunk c starts */
+    size_t off_chklast;     /* i32[chk_cap][tile_w*tile_h]: last blended instance of chunk c composited
+                               on its own (split_fwd)                                                   */
 } splat_plan;
 
 /* Fill `s` with the default settings listed above (16x16 tiles, batch 64,
@@ -229,7 +236,13 @@ SPLAT_API int splat_bin_sort(const splat_plan *plan, void *ws, void *stream);
  * blend that would take T below t_min, and accumulates C += c alpha T.
  * Outputs (device, float32/int32): img[V][3][H][W] = C + T bg,
  * T_final[V][H][W], last_pos[V][H][W] = instance index of the last blended
- * Gaussian (into the sorted value buffer) or -1.
+ * Gaussian (into the sorted value buffer) or -1.  Also records the
+ * checkpoints of the split lists that splat_render_bwd starts its chunks from.
+ * With settings.split_fwd the chunks after the first of each split list are
+ * composited in parallel from T = 1 and joined per pixel (C += T C_chunk,
+ * T *= T_chunk); a chunk in which some pixel of the tile could reach t_min
+ * (T T_chunk below t_min with a relative margin covering the rounding) is
+ * walked in order instead, so the stop decisions are the sequential ones.
  */
 SPLAT_API int splat_render_fwd(const splat_plan *plan, void *ws, float *img, float *T_final,
                      int32_t *last_pos, void *stream);

@@ -1,9 +1,11 @@
 """Launch-shape autotuner for the batched step.
 
 Results do not depend on the launch shape (images, transmittances and last
-contributors are bitwise identical across tile shapes and dispatch modes), so the
-tuner only measures: for every candidate (tile shape, persistent or grid dispatch)
-it builds a workspace sized for the scene, replays a few steps and keeps the
+contributors are bitwise identical across tile shapes and dispatch modes, and the
+forward that joins separately composited chunks of long tile lists differs from
+the walk in order by rounding only), so the tuner only measures: for every
+candidate (tile shape, persistent or grid dispatch, joined forward or not) it
+builds a workspace sized for the scene, replays a few steps and keeps the
 fastest.  Results are cached in a JSON file keyed by GPU architecture, image
 size, view count and a Gaussian-count bucket.
 """
@@ -35,17 +37,18 @@ def _load_cache():
         return {}
 
 
-def autotune(ds, xi, delta, targets, steps=3, tiles=TILES, modes=(False, True), use_cache=True):
+def autotune(ds, xi, delta, targets, steps=3, tiles=TILES, modes=(False, True), joined=(0, 1), use_cache=True):
     """Return (settings, report) of the fastest launch shape for this scene's batched step."""
     key = _key(ds)
     cache = _load_cache() if use_cache else {}
     if use_cache and key in cache:
         c = cache[key]
-        return pl.make_settings(tile=tuple(c["tile"]), persistent=c["persistent"]), dict(cached=True, **c)
+        return (pl.make_settings(tile=tuple(c["tile"]), persistent=c["persistent"], split_fwd=c.get("split_fwd", 0)),
+                dict(cached=True, **c))
     results = []
     for tile in tiles:
-        for pers in modes:
-            st = pl.make_settings(tile=tile, persistent=pers)
+        for pers, sf in ((p, j) for p in modes for j in joined):
+            st = pl.make_settings(tile=tile, persistent=pers, split_fwd=sf)
             step = pl.BatchedStep(ds, xi, delta, targets, st)
             step.run()
             torch.cuda.synchronize()
@@ -56,7 +59,7 @@ def autotune(ds, xi, delta, targets, steps=3, tiles=TILES, modes=(False, True), 
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
-            results.append(dict(tile=list(tile), persistent=bool(pers), ms=round(ms, 3)))
+            results.append(dict(tile=list(tile), persistent=bool(pers), split_fwd=int(sf), ms=round(ms, 3)))
             del step
             torch.cuda.empty_cache()
     best = min(results, key=lambda r: r["ms"])
@@ -69,4 +72,5 @@ def autotune(ds, xi, delta, targets, steps=3, tiles=TILES, modes=(False, True), 
                 json.dump(cache, f, indent=1)
         except OSError:
             pass
-    return pl.make_settings(tile=tuple(best["tile"]), persistent=best["persistent"]), report
+    return (pl.make_settings(tile=tuple(best["tile"]), persistent=best["persistent"], split_fwd=best["split_fwd"]),
+            report)

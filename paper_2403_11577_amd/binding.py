@@ -26,7 +26,8 @@ class splat_settings(C.Structure):
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double), ("t_min", C.c_double),
                 ("guard", C.c_double), ("bg", C.c_double * 3), ("pad_px", C.c_double),
                 ("pad_rel", C.c_double), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
-                ("batch", C.c_int32), ("persistent", C.c_int32), ("roi_y0", C.c_int32), ("split_len", C.c_int32)]
+                ("batch", C.c_int32), ("persistent", C.c_int32), ("roi_y0", C.c_int32), ("split_len", C.c_int32),
+                ("split_fwd", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class splat_gaussians(C.Structure):
@@ -48,7 +49,7 @@ class splat_plan(C.Structure):
                 [(n, C.c_size_t) for n in _PLAN_OFFS] +
                 [("sorted_buf", C.c_int32), ("radix_bits", C.c_int32), ("split_len", C.c_int32),
                  ("reserved1", C.c_int32), ("chk_cap", C.c_int64), ("bq_cap", C.c_int64)] +
-                [(n, C.c_size_t) for n in ("off_bqueue", "off_bqoff", "off_chk")])
+                [(n, C.c_size_t) for n in ("off_bqueue", "off_bqoff", "off_chk", "off_chklast")])
 
 
 class splat_ngp(C.Structure):

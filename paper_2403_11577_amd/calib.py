@@ -80,6 +80,10 @@ class CalibConfig:
     # real steps and keep the fastest (the best shape moves with the Gaussians' opacities); 0 keeps
     # the given settings
     tile_tune: int = 500
+    # the candidates include, for each tile shape, the forward that composites the chunks of long
+    # tile lists in parallel and joins them (pays off while few pixels saturate)
+    tune_split_fwd: bool = True
+    split_len: int = 512           # instances per chunk of a split tile list
     fused_adam: bool = True        # torch's single-kernel Adam (else its multi-tensor one)
 
 
@@ -106,12 +110,15 @@ class Calibrator:
         V, G, Bv = full.n_views, full.n_gauss, cfg.batch_views
         base = settings or pl.make_settings()
         roi = min(max(int(round(full.H * (1.0 - cfg.roi_frac))), 0), full.H - 1)
-        tiles = [(base.tile_w, base.tile_h)]
+        # candidates (tile, joined forward); the first is the given settings
+        cands = [((base.tile_w, base.tile_h), int(base.split_fwd))]
         if cfg.tile_tune:
-            tiles += [t for t in ((16, 16), (8, 8)) if t != tiles[0]]
+            sfs = (0, 1) if cfg.tune_split_fwd else (int(base.split_fwd),)
+            cands += [(t, sf) for t in ((16, 16), (8, 8)) for sf in sfs if (t, sf) != cands[0]]
         self._cands = [pl.make_settings(tile=t, batch=base.batch, roi_y0=roi,
-                                        persistent=bool(base.persistent) if i == 0 else False)
-                       for i, t in enumerate(tiles)]
+                                        persistent=bool(base.persistent) if i == 0 else False,
+                                        split_len=base.split_len or cfg.split_len, split_fwd=sf)
+                       for i, (t, sf) in enumerate(cands)]
         self._cur = 0
         self.settings = self._cands[0]
         self._frames, self._graphs, self._caps = {}, {}, {}
@@ -388,9 +395,9 @@ class Calibrator:
             ms[ci] = t[len(t) // 2]
         best = min(ms, key=ms.get)
         self._use(best)
-        self.tile_log.append(dict(step=k, ms={f"{c.tile_w}x{c.tile_h}": round(ms[i], 3)
-                                              for i, c in enumerate(self._cands)},
-                                  tile=f"{self._cands[best].tile_w}x{self._cands[best].tile_h}"))
+        name = lambda c: f"{c.tile_w}x{c.tile_h}" + ("+join" if c.split_fwd else "")
+        self.tile_log.append(dict(step=k, ms={name(c): round(ms[i], 3) for i, c in enumerate(self._cands)},
+                                  tile=name(self._cands[best])))
         self._next_tune = k + self.cfg.tile_tune
 
     def _body(self):

@@ -75,6 +75,7 @@ static int check_settings(const splat_settings *s) {
     if (s->split_len != 0 && (s->split_len < 64 || s->split_len > (1 << 24) || (s->split_len & (s->split_len - 1)))) {
         set_error("split_len must be 0 or a power of two in [64, 2^24] (got %d)", s->split_len); return SPLAT_EINVAL;
     }
+    if (s->split_fwd != 0 && s->split_fwd != 1) { set_error("split_fwd must be 0 or 1"); return SPLAT_EINVAL; }
     return SPLAT_OK;
 }
 
@@ -148,6 +149,8 @@ void splat_default_settings(splat_settings *s) {
     s->persistent = 1;
     s->roi_y0 = 0;
     s->split_len = 0;
+    s->split_fwd = 0;
+    s->reserved0 = 0;
 }
 
 int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, int32_t width, int32_t height,
@@ -237,6 +240,7 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     p.off_bqueue = take((size_t)p.bq_cap * 16);
     p.off_bqoff = take(((size_t)ntiles_all + 1) * 4);
     p.off_chk = take((size_t)p.chk_cap * (size_t)(s->tile_w * s->tile_h) * 16);
+    p.off_chklast = take((size_t)p.chk_cap * (size_t)(s->tile_w * s->tile_h) * 4);
     p.ws_bytes = off;
     *plan = p;
     return SPLAT_OK;

@@ -41,6 +41,7 @@ struct RenderArgs {
     const uint4 *bitems;        // adjoint work items (tile, chunk, first checkpoint slot, -)
     const uint32_t *boff;       // first checkpoint slot of each split queue position
     float4 *chk;                // checkpoints: per-pixel (T, C) of the split lists
+    int32_t *chklast;           // last blended instance of a chunk composited on its own
     unsigned long long *stats;  // pair counters of the instrumented variant
     int n_items, T, tiles_x, W, H, persistent, roi_y0;
     uint32_t lc, chk_cap;       // split length, checkpoint slots
@@ -213,24 +214,56 @@ __device__ __forceinline__ void put_chk(const RenderArgs &a, uint32_t slot, cons
 //
 // STATS = true is the instrumented variant (pair counters for the roofline);
 // it computes exactly the same outputs.
-template <int TW, int TH, bool STATS>
+//
+// MODE 0 composites every list in order.  A split list (at least split_len
+// instances) records (T, C) where each of its chunks starts, for the adjoint.
+// MODE 1 composites chunks 1.. of every split list on their own, from T = 1 with
+// the same stop rule, and stores per pixel (T_chunk or -1 if the pixel stopped
+// inside the chunk, C_chunk) and the chunk's last blended instance in the chunk's
+// checkpoint slot.  MODE 2 is MODE 0 that, at the start of chunk c >= 1, joins the
+// chunk's own result instead of walking it (C += T C_chunk, T *= T_chunk, last =
+// last_chunk) unless some live pixel of the tile could reach t_min inside it:
+// T T_chunk >= t_min (1 + margin) with T_chunk >= t_min guarantees that the
+// sequential walk (T decreasing monotonically) stops nowhere in the chunk, the
+// margin covering the rounding by which the sequential product can differ.
+template <int TW, int TH, bool STATS, int MODE>
 __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img, float *Tout, int32_t *lastout) {
-    constexpr int NSB = TW * TH / 64, SBX = TW / 8;
+    constexpr int NSB = TW * TH / 64, SBX = TW / 8, NPIX = TW * TH;
     __shared__ float4 sg[64][3];  // the staged batch, read back with wave-uniform addresses
     const int lane = threadIdx.x;
     const int lx = lane & 7, ly = lane >> 3;
     const size_t HW = (size_t)a.W * a.H;
     const uint32_t nslots = a.counts[CNT_SLOTS];
     const uint32_t nsplit = a.counts[CNT_NSPLIT];
+    const int n_items = MODE == 1 ? (int)min(a.counts[CNT_NCHUNK], a.chk_cap) : a.n_items;
+    const float thr = a.tmin * (1.001f + 1.2e-7f * (float)a.lc);
     unsigned long long n_eval = 0, n_blend = 0;
     int item;
-    for (int iter = 0; next_item(a, iter, a.n_items, item); ++iter) {
-        int tid = (int)a.queue[item];
+    for (int iter = 0; MODE == 1 ? (item = (int)blockIdx.x + iter * (int)gridDim.x) < n_items
+                                  : next_item(a, iter, n_items, item);
+         ++iter) {
+        int tid;
+        uint32_t lo, hi, lslot = 0;
+        uint2 rg;
+        if (MODE == 1) {
+            const uint4 it = a.bitems[item];
+            if (it.y == 0u || it.z == 0xFFFFFFFFu) continue;  // the first chunk is walked by MODE 2
+            tid = (int)it.x;
+            rg = a.ranges[tid];
+            lo = rg.x + it.y * a.lc;
+            hi = min(rg.y, lo + a.lc);
+            lslot = it.z + it.y;
+            if (lo >= rg.y || lslot >= a.chk_cap) continue;  // cannot happen
+        } else {
+            tid = (int)a.queue[item];
+            rg = a.ranges[tid];
+            lo = rg.x;
+            hi = rg.y;
+        }
         int v = tid / a.T, tile = tid - v * a.T;
         int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
         int x0 = tx * TW, y0 = ty * TH;
         int xb = x0 & ~31, yb = y0 & ~31;
-        uint2 rg = a.ranges[tid];
         float T[NSB], L[NSB], C0[NSB], C1[NSB], C2[NSB], px[NSB], py[NSB];
         int last[NSB];
 #pragma unroll
@@ -244,40 +277,76 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
             last[k] = -1;
         }
         const float fxb = (float)xb, fyb = (float)yb, fox = (float)(x0 - xb), foy = (float)(y0 - yb);
-        Stage cur = derive<TW, TH>(a, load_raw(a, load_slot(a, rg.x + lane, rg.y), nslots), fxb, fyb, fox, foy);
+        Stage cur = derive<TW, TH>(a, load_raw(a, load_slot(a, lo + lane, hi), nslots), fxb, fyb, fox, foy);
         put_stage(sg, cur, lane);
-        uint32_t sl_next = load_slot(a, rg.x + 64 + lane, rg.y);
+        uint32_t sl_next = load_slot(a, lo + 64 + lane, hi);
         // a split list records (T, C) where each of its chunks starts (chunks are whole batches)
-        const bool split = (uint32_t)item < nsplit;
+        const bool split = MODE != 1 && (uint32_t)item < nsplit;
         const uint32_t cslot = split ? a.boff[item] : 0u;
         uint32_t bnext = split ? rg.x + a.lc : 0xFFFFFFFFu, cnext = cslot + 1;
-        for (uint32_t b = rg.x; b < rg.y; b += 64) {
+        for (uint32_t b = lo; b < hi; b += 64) {
             if (b == bnext) {
-                put_chk<NSB>(a, cnext, T, C0, C1, C2, lane);
+                bool joined = false;
+                if (MODE == 2 && cnext < a.chk_cap) {
+                    const float4 *src = a.chk + (size_t)cnext * NPIX + lane;
+                    bool need = false;
+#pragma unroll
+                    for (int k = 0; k < NSB; ++k) need |= L[k] > 0.f && !(T[k] * src[k * 64].x >= thr);
+                    joined = __ballot(need) == 0ull;
+                    if (joined) {
+                        const int32_t *lsrc = a.chklast + (size_t)cnext * NPIX + lane;
+                        float4 *dst = a.chk + (size_t)cnext * NPIX + lane;
+#pragma unroll
+                        for (int k = 0; k < NSB; ++k) {
+                            const float4 q = src[k * 64];
+                            const int ll = lsrc[k * 64];
+                            dst[k * 64] = make_float4(T[k], C0[k], C1[k], C2[k]);  // state where chunk c starts
+                            if (L[k] > 0.f) {
+                                C0[k] = __fmaf_rn(L[k], q.y, C0[k]);
+                                C1[k] = __fmaf_rn(L[k], q.z, C1[k]);
+                                C2[k] = __fmaf_rn(L[k], q.w, C2[k]);
+                                T[k] = T[k] * q.x;
+                                L[k] = T[k];
+                                last[k] = ll >= 0 ? ll : last[k];
+                            }
+                        }
+                    }
+                }
+                if (!joined) put_chk<NSB>(a, cnext, T, C0, C1, C2, lane);
                 ++cnext;
                 bnext += a.lc;
+                if (joined) {
+                    // continue at the next chunk: restage its first batch
+                    const uint32_t bn = b + a.lc;
+                    cur = derive<TW, TH>(a, load_raw(a, load_slot(a, bn + lane, hi), nslots), fxb, fyb, fox, foy);
+                    put_stage(sg, cur, lane);
+                    sl_next = load_slot(a, bn + 64 + lane, hi);
+                    b = bn - 64;
+                    continue;
+                }
             }
             uint32_t live = 0;  // sub-blocks with a pixel still compositing
 #pragma unroll
             for (int k = 0; k < NSB; ++k) live |= __ballot(L[k] > 0.f) ? (1u << k) : 0u;
             if (live == 0) break;
             Raw raw_next = load_raw(a, sl_next, nslots);              // records of batch b + 64
-            uint32_t sl_after = load_slot(a, b + 128 + lane, rg.y);   // slot ids of batch b + 128
+            uint32_t sl_after = load_slot(a, b + 128 + lane, hi);     // slot ids of batch b + 128
             // the Gaussians of the batch that reach a live sub-block, in order (lanes past the
             // list end carry an empty mask)
             uint64_t todo = __ballot((cur.mask & live) != 0u);
-            while (todo) {
-                const int j = __ffsll((long long)todo) - 1;
-                todo &= todo - 1ull;
-                const float4 q0 = sg[j][0], q1 = sg[j][1], q2 = sg[j][2];
-                uint32_t m = bcast_u(cur.mask, j) & live;
+            // two Gaussians per pass: the staged values of both are read before the first is
+            // evaluated, so the second read is in flight meanwhile (without a second one the pass
+            // evaluates the first again with zero opacity, which blends nothing)
+            auto blend = [&](int j, const float4 q0, const float4 q1, const float cb, bool real) {
+                // with one sub-block every Gaussian of the ballot reaches it
+                const uint32_t m = NSB == 1 ? 1u : bcast_u(cur.mask, j) & live;
                 const float mx = q0.x, my = q0.y, A = q0.z, Bc = q0.w, Cc = q1.x, lo2 = q1.y;
-                const float cr = q1.z, cg = q1.w, cb = q2.x;
-                int idx = (int)(b + j);
+                const float cr = q1.z, cg = q1.w;
+                const int idx = (int)(b + j);
 #pragma unroll
                 for (int k = 0; k < NSB; ++k) {
                     if (!(m & (1u << k))) continue;  // wave-uniform
-                    if (STATS) n_eval += L[k] > 0.f;
+                    if (STATS) n_eval += real && L[k] > 0.f;
                     float dx = px[k] - mx, dy = py[k] - my;
                     float al = fminf(a.amax, exp2_hw(power2(dx, dy, A, Bc, Cc, lo2)));
                     al = al >= a.amin ? al : 0.f;
@@ -293,10 +362,35 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
                     C2[k] = __fmaf_rn(cb, w, C2[k]);
                     last[k] = w > 0.f ? idx : last[k];
                 }
+            };
+            while (todo) {
+                const int j1 = __ffsll((long long)todo) - 1;
+                todo &= todo - 1ull;
+                const bool two = todo != 0ull;
+                const int j2 = two ? __ffsll((long long)todo) - 1 : j1;
+                todo &= todo - 1ull;
+                const float4 a0 = sg[j1][0], a1 = sg[j1][1], b0 = sg[j2][0];
+                float4 b1 = sg[j2][1];
+                const float a2 = sg[j1][2].x, b2 = sg[j2][2].x;
+                b1.y = two ? b1.y : -256.f;  // log2 of the opacity: alpha = 0 < alpha_min
+                blend(j1, a0, a1, a2, true);
+                blend(j2, b0, b1, b2, two);
             }
             cur = derive<TW, TH>(a, raw_next, fxb, fyb, fox, foy);
             put_stage(sg, cur, lane);
             sl_next = sl_after;
+        }
+        if (MODE == 1) {
+            // the chunk on its own: (T_chunk, C_chunk), T_chunk = -1 where the pixel stopped in it
+            float4 *d = a.chk + (size_t)lslot * NPIX + lane;
+            int32_t *dl = a.chklast + (size_t)lslot * NPIX + lane;
+#pragma unroll
+            for (int k = 0; k < NSB; ++k) {
+                bool inside = x0 + 8 * (k % SBX) + lx < a.W && y0 + 8 * (k / SBX) + ly < a.H && y0 + 8 * (k / SBX) + ly >= a.roi_y0;
+                d[k * 64] = make_float4(inside && !(L[k] > 0.f) ? -1.f : T[k], C0[k], C1[k], C2[k]);
+                dl[k * 64] = last[k];
+            }
+            continue;
         }
         if (split) {
             // chunks after an early exit start from the final state, which the first slot also holds
@@ -463,7 +557,8 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
                 const int j = 63 - __builtin_clzll(todo);
                 todo &= ~(1ull << j);
                 const float4 q0 = sg[j][0], q1 = sg[j][1], q2 = sg[j][2];
-                uint32_t m = bcast_u(cur.mask, j);
+                // with one sub-block every Gaussian of the ballot reaches it
+                const uint32_t m = NSB == 1 ? 1u : bcast_u(cur.mask, j);
                 int idx = bs + j;
                 const float mx = q0.x, my = q0.y, A = q0.z, Bc = q0.w, Cc = q1.x, lo2 = q1.y;
                 const float cr = q1.z, cg = q1.w, cb = q2.x;
@@ -542,6 +637,7 @@ RenderArgs make_args(const splat_plan &p, void *ws, unsigned long long *stats) {
     a.bitems = ws_at<uint4>(ws, p.off_bqueue);
     a.boff = ws_at<uint32_t>(ws, p.off_bqoff);
     a.chk = ws_at<float4>(ws, p.off_chk);
+    a.chklast = ws_at<int32_t>(ws, p.off_chklast);
     a.lc = (uint32_t)p.split_len;
     a.chk_cap = (uint32_t)p.chk_cap;
     a.stats = stats;
@@ -575,17 +671,26 @@ int fwd_impl(const splat_plan &p, void *ws, float *img, float *T, int32_t *last,
              hipStream_t st) {
     RenderArgs a = make_args(p, ws, stats);
     if (a.n_items == 0) return 0;
+    int rc = 0;
+    const bool joined = p.s.split_fwd && !stats;  // the instrumented variant walks every list in order
+    if (joined) {
+        // chunks 1.. of the split lists on their own (about equal work items: a static grid)
+        int g1 = persistent_grid((int)(p.chk_cap < INT32_MAX ? p.chk_cap : INT32_MAX), 32);
+        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, false, 1>), dim3(g1), dim3(64), 0, st, a, img, T, last);
+        if ((rc = launch_status("render_fwd_chunks"))) return rc;
+    }
     int grid = a.n_items;
     if (a.persistent) {
         hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(1), 0, st, a.work);
-        int rc = launch_status("reset_work");
-        if (rc) return rc;
+        if ((rc = launch_status("reset_work"))) return rc;
         grid = persistent_grid(a.n_items, 32);
     }
     if (stats)
-        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, true>), dim3(grid), dim3(64), 0, st, a, img, T, last);
+        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, true, 0>), dim3(grid), dim3(64), 0, st, a, img, T, last);
+    else if (joined)
+        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, false, 2>), dim3(grid), dim3(64), 0, st, a, img, T, last);
     else
-        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, false>), dim3(grid), dim3(64), 0, st, a, img, T, last);
+        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, false, 0>), dim3(grid), dim3(64), 0, st, a, img, T, last);
     return launch_status("render_fwd");
 }
 

@@ -23,13 +23,14 @@ def oracle_settings():
 
 
 def gpu_render(scene, tile=(16, 16), batch=64, persistent=True, views=None, w2c=None, xi=None, delta=None, roi_y0=0,
-               split_len=0):
+               split_len=0, split_fwd=0):
     """Run the batched HIP forward on a scene; returns dict of numpy outputs plus the frame."""
     ds = pl.DeviceScene.from_scene(scene, views=views)
     xi_t = torch.as_tensor(scene.xi if xi is None else xi, dtype=torch.float64, device="cuda")
     dl_t = torch.as_tensor(scene.delta if delta is None else delta, dtype=torch.float64, device="cuda")
     w2c_t = None if w2c is None else torch.as_tensor(np.ascontiguousarray(w2c), dtype=torch.float64, device="cuda")
-    st = pl.make_settings(tile=tile, batch=batch, persistent=persistent, roi_y0=roi_y0, split_len=split_len)
+    st = pl.make_settings(tile=tile, batch=batch, persistent=persistent, roi_y0=roi_y0, split_len=split_len,
+                          split_fwd=split_fwd)
     fr = pl.fit_frame(ds, xi_t, dl_t, st, w2c=w2c_t)
     fr.clear_status()
     img, T, last = pl.forward(fr, ds, xi_t, dl_t, w2c=w2c_t)

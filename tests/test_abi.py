@@ -42,7 +42,7 @@ def test_default_settings_are_the_documented_readings():
 def test_plan_layout_is_aligned_and_disjoint():
     s = B.default_settings()
     p = B.splat_plan_make(s, 3, 1000, 100, 37, 2000, 9000)
-    names = [n for n in B._PLAN_OFFS if n != "ws_bytes"] + ["off_bqueue", "off_bqoff", "off_chk"]
+    names = [n for n in B._PLAN_OFFS if n != "ws_bytes"] + ["off_bqueue", "off_bqoff", "off_chk", "off_chklast"]
     offs = sorted((getattr(p, n), n) for n in names)
     assert all(o % 256 == 0 for o, _ in offs)
     assert len({o for o, _ in offs}) == len(offs)
@@ -51,7 +51,8 @@ def test_plan_layout_is_aligned_and_disjoint():
     # checkpoint slots, so 2 inst_cap / split_len (+1) bound them; the adjoint items add the tiles
     assert p.split_len == 1024
     assert p.chk_cap == 2 * -(-9000 // 1024) + 1 and p.bq_cap == 63 + p.chk_cap
-    assert p.ws_bytes - p.off_chk >= p.chk_cap * 16 * 16 * 16
+    assert p.off_chklast - p.off_chk >= p.chk_cap * 16 * 16 * 16
+    assert p.ws_bytes - p.off_chklast >= p.chk_cap * 16 * 16 * 4
     assert p.tiles_x == 7 and p.tiles_y == 3 and p.tiles_per_view == 21
     # key = (view*T + tile) << depth_bits | depth: 63 items need 6 bits, the 0.2..256 m window 27
     assert p.tile_bits == 6 and p.depth_bits == 27
@@ -76,7 +77,7 @@ def test_plan_make_rejects_bad_shapes(kw, msg):
 @pytest.mark.parametrize("field, value", [
     ("tile_w", 12), ("batch", 8), ("batch", 300), ("near_z", 0.0), ("far_z", 0.1),
     ("alpha_min", 0.0), ("alpha_max", 1.0), ("t_min", 0.0), ("eps2d", -1.0), ("persistent", 2),
-    ("split_len", 32), ("split_len", 96), ("split_len", 1 << 25), ("split_len", -64),
+    ("split_len", 32), ("split_len", 96), ("split_len", 1 << 25), ("split_len", -64), ("split_fwd", 2),
 ])
 def test_plan_make_rejects_bad_settings(field, value):
     s = B.default_settings()

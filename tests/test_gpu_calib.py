@@ -41,14 +41,17 @@ def test_autotune_picks_a_candidate_and_results_are_shape_independent():
     dl = torch.as_tensor(s.delta, dtype=torch.float64, device="cuda")
     tgt = torch.zeros((ds.n_views, 3, ds.H, ds.W), dtype=torch.float32, device="cuda")
     st, rep = at.autotune(ds, xi, dl, tgt, steps=2, use_cache=False)
-    assert len(rep["candidates"]) == 8
+    assert len(rep["candidates"]) == 16  # 4 tile shapes x grid/persistent x joined forward or not
     assert rep["best"]["ms"] == min(c["ms"] for c in rep["candidates"])
     a = pl.BatchedStep(ds, xi, dl, tgt, st)
     b = pl.BatchedStep(ds, xi, dl, tgt, pl.make_settings())
     a.run()
     b.run()
     torch.cuda.synchronize()
-    assert torch.equal(a.fr.img, b.fr.img)
+    if st.split_fwd:  # the joined forward agrees with the walk in order to rounding
+        assert float((a.fr.img - b.fr.img).abs().max()) <= 1e-5
+    else:
+        assert torch.equal(a.fr.img, b.fr.img)
 
 
 def test_coarse_to_fine_stages_reanchor_the_field_gaussians():
@@ -121,10 +124,11 @@ def test_calibration_retunes_its_tile_shape():
     """The loop times its tile candidates on real steps, keeps the fastest, and keeps going."""
     say("case: calibration tile retuning")
     s = synth.small_drive(15, n_points=4000, W=160, H=64, f=70.0, n_frames=4, deg=2.0, metres=0.1, delta=0.02)
-    cal = cb.Calibrator(s, cb.CalibConfig(steps=30, warmup=5, batch_views=4, seed=6, tile_tune=12))
+    cal = cb.Calibrator(s, cb.CalibConfig(steps=40, warmup=5, batch_views=4, seed=6, tile_tune=12))
     res = cal.run()
-    assert len(res["tiles"]) == 2  # rounds of six timed steps from steps 2 and 19 (12 after the first ended)
+    # rounds of twelve timed steps (three per candidate) from steps 2 and 25 (12 after the first ended)
+    assert len(res["tiles"]) == 2
     for t in res["tiles"]:
-        assert t["tile"] in t["ms"] and set(t["ms"]) == {"16x16", "8x8"}
+        assert t["tile"] in t["ms"] and set(t["ms"]) == {"16x16", "8x8", "16x16+join", "8x8+join"}
         assert t["ms"][t["tile"]] == min(t["ms"].values())
     assert math.isfinite(res["loss"])

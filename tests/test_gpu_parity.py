@@ -172,10 +172,10 @@ def test_render_invariant_across_launch_shapes():
                 assert np.array_equal(o["last_id"], base["last_id"])
 
 
-def _grad_case(scene, tile, seed=0, split_len=0, persistent=True, keep=None):
+def _grad_case(scene, tile, seed=0, split_len=0, persistent=True, keep=None, split_fwd=0):
     w2c_ref, _, _ = oracle.pose(scene.traj, scene.rig, scene.xi, scene.delta, scene.views)
     target = oracle.render_scene(scene, xi=scene.xi_gt, delta=scene.delta_gt)["img"]
-    g = gpu_render(scene, tile=tile, split_len=split_len, persistent=persistent)
+    g = gpu_render(scene, tile=tile, split_len=split_len, persistent=persistent, split_fwd=split_fwd)
     if keep is not None:
         keep["render"] = g
     fr, ds = g["frame"], g["ds"]
@@ -245,6 +245,51 @@ def test_gradients_split_lists_vs_oracle(tile, persistent):
         err = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
         say(f"  split vs unsplit {k}: {err:.2e}")
         assert err <= 1e-4, (k, err)
+
+
+def _faint(scene, factor=0.1):
+    # the regime at the start of a calibration: faint Gaussians, few pixels reach t_min
+    scene.gauss.opacity = (scene.gauss.opacity * np.float32(factor)).astype(np.float32)
+    return scene
+
+
+@pytest.mark.parametrize("faint", [False, True])
+@pytest.mark.parametrize("tile, persistent", [((16, 16), True), ((8, 8), False), ((16, 32), True)])
+def test_render_joined_chunks_vs_oracle(tile, persistent, faint):
+    # chunks of 64 composited on their own and joined per pixel, or walked in order where a
+    # pixel could reach t_min: the same images, T and last contributors as the oracle
+    say(f"case: joined chunks tile={tile} persistent={persistent} faint={faint}")
+    scene = synth.small_drive(6, n_frames=2)
+    if faint:
+        scene = _faint(scene)
+    g = gpu_render(scene, tile=tile, persistent=persistent, split_len=64, split_fwd=1)
+    ref_w2c, _, _ = oracle.pose(scene.traj, scene.rig, scene.xi, scene.delta, scene.views)
+    orc = oracle.render(scene.gauss, ref_w2c, oracle.view_intr(scene.rig, scene.views), scene.rig.W,
+                        scene.rig.H, alternatives=True)
+    nbad, nfl, nex, mx = compare_images(g, orc)
+    fr = g["frame"]
+    cnt = fr.buf("counts", torch.int32, 8).cpu().numpy()
+    say(f"  split lists {int(cnt[3])} chunks {int(cnt[4])} flagged={nfl} excluded={nex} max_err={mx:.3g} "
+        f"min T {g['T'].min():.3g}")
+    assert int(cnt[4]) > int(cnt[3]) > 0
+    assert g["status"] == 0
+    assert nbad == 0
+    assert nex <= 0.001 * orc["nflag"].size
+    # and within rounding of the walk in order (pixels with a decision at the threshold margin aside)
+    o = gpu_render(scene, tile=tile, persistent=persistent, split_len=64, split_fwd=0)
+    plain = orc["nflag"] == 0
+    assert np.array_equal(o["last_id"][plain], g["last_id"][plain])
+    assert float(np.abs(o["img"] - g["img"]).max(axis=1)[plain].max()) <= 1e-5
+    assert float(np.abs(o["T"] - g["T"])[plain].max()) <= 1e-5
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_gradients_joined_chunks_vs_oracle(tile):
+    say(f"case: gradients with joined chunks tile={tile}")
+    out, _ = _grad_case(_faint(synth.small_drive(5, n_frames=2)), tile, split_len=64, split_fwd=1)
+    say("  " + " ".join(f"{k}={v[1]:.2e}" for k, v in out.items()))
+    for k, (ok, err) in out.items():
+        assert ok, (k, err)
 
 
 def test_gradients_tiny_vs_oracle():
