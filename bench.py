@@ -26,14 +26,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # ALU roofline of the render kernels: FP32 flops (FMA = 2, exp2 / rcp / compare = 1) per
-# counted unit, from device-side pair counters.
-#   forward, per evaluated (pixel, Gaussian) pair: offset 2, exponent 8, exp2 1, clamp 1, alpha test 1
-#   forward, per blended pair: weight 1, transmittance 1, stop test 1, colour 6, last index 1
-#   backward, per evaluated pair (at or before the pixel's last contributor): as the forward, 13
-#   backward, per contributing pair: 1 - alpha and its reciprocal 2, T recovery 1, weight 1,
-#     colour gradient 6, dL/dC . c 5, dL/dalpha 3, suffix term 2, dL/dpower 2, moments 12 = 35
-FWD_FLOP_PER_EVAL, FWD_FLOP_PER_BLEND = 13, 10
-BWD_FLOP_PER_EVAL, BWD_FLOP_PER_CONTRIB = 13, 35
+# contributing (pixel, Gaussian) pair -- alpha >= alpha_min before the pixel stops -- the unit
+# of algorithmic work; evaluated pairs that contribute nothing are overhead and only reported.
+#   forward: offset 2, exponent 8, exp2 1, clamp 1, alpha test 1 (13) + weight 1,
+#     transmittance 1, stop test 1, colour 6, last index 1 (10) = 23
+#   backward: the same evaluation 13 + 1 - alpha and its reciprocal 2, T recovery 1, weight 1,
+#     colour gradient 6, dL/dC . c 5, dL/dalpha 3, suffix term 2, dL/dpower 2, moments 12 (35) = 48
+FWD_FLOP_PER_PAIR, BWD_FLOP_PER_PAIR = 23, 48
 # 256 CUs x 64 FP32 lanes x 2 flops (FMA) x 2.4 GHz, without packed-FP32 issue
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # HBM bytes per render_bwd launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
@@ -280,8 +279,8 @@ def main():
 
     # ---- roofline of the dominant render kernel (pair counts from the instrumented variant) ----
     stt = step.stats()
-    fwd_flop = FWD_FLOP_PER_EVAL * stt["fwd_eval"] + FWD_FLOP_PER_BLEND * stt["fwd_blend"]
-    bwd_flop = BWD_FLOP_PER_EVAL * stt["bwd_eval"] + BWD_FLOP_PER_CONTRIB * stt["bwd_contrib"]
+    fwd_flop = FWD_FLOP_PER_PAIR * stt["fwd_blend"]
+    bwd_flop = BWD_FLOP_PER_PAIR * stt["bwd_contrib"]
     if bwd_ms >= fwd_ms:
         kern, dur_ms, flop = "render_bwd", bwd_ms, bwd_flop
     else:

@@ -147,6 +147,8 @@ typedef struct splat_plan {
                                first slot holds the final state, slot c the state where chunk c starts */
     size_t off_chklast;     /* i32[chk_cap][tile_w*tile_h]: last blended instance of chunk c composited
                                on its own (split_fwd)                                                   */
+    size_t off_bmask;       /* u8[inst_cap]: per instance, bit k set when the forward blended it into a
+                               pixel of 8x8 sub-block k of its tile; the adjoint skips the others      */
 } splat_plan;
 
 /* Fill `s` with the default settings listed above (16x16 tiles, batch 64,
@@ -236,8 +238,9 @@ SPLAT_API int splat_bin_sort(const splat_plan *plan, void *ws, void *stream);
  * blend that would take T below t_min, and accumulates C += c alpha T.
  * Outputs (device, float32/int32): img[V][3][H][W] = C + T bg,
  * T_final[V][H][W], last_pos[V][H][W] = instance index of the last blended
- * Gaussian (into the sorted value buffer) or -1.  Also records the
- * checkpoints of the split lists that splat_render_bwd starts its chunks from.
+ * Gaussian (into the sorted value buffer) or -1.  Also records, for
+ * splat_render_bwd, the checkpoints of the split lists it starts its chunks
+ * from and which 8x8 sub-blocks of its tile each instance was blended into.
  * With settings.split_fwd the chunks after the first of each split list are
  * composited in parallel from T = 1 and joined per pixel (C += T C_chunk,
  * T *= T_chunk); a chunk in which some pixel of the tile could reach t_min

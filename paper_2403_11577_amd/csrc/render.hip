@@ -42,6 +42,7 @@ struct RenderArgs {
     const uint32_t *boff;       // first checkpoint slot of each split queue position
     float4 *chk;                // checkpoints: per-pixel (T, C) of the split lists
     int32_t *chklast;           // last blended instance of a chunk composited on its own
+    uint8_t *bmask;             // per instance: sub-blocks it was blended into (forward writes)
     unsigned long long *stats;  // pair counters of the instrumented variant
     int n_items, T, tiles_x, W, H, persistent, roi_y0;
     uint32_t lc, chk_cap;       // split length, checkpoint slots
@@ -66,11 +67,17 @@ struct Stage {
 struct Raw {
     float4 r0, r1, r2;
     uint32_t slot;
+    uint32_t bm;  // adjoint: the sub-blocks the forward blended this instance into
 };
 
 __device__ __forceinline__ uint32_t load_slot(const RenderArgs &a, uint32_t idx, uint32_t end) {
     uint32_t v = a.vals[idx < end ? idx : 0u];  // vals[0] exists whenever this runs (end > 0)
     return idx < end ? v : 0xFFFFFFFFu;
+}
+
+__device__ __forceinline__ uint32_t load_bm(const RenderArgs &a, uint32_t idx, uint32_t end) {
+    uint32_t v = a.bmask[idx < end ? idx : 0u];
+    return idx < end ? v : 0u;
 }
 
 // Unconditional gather (a branch here would make the compiler wait for the data
@@ -82,13 +89,16 @@ __device__ __forceinline__ Raw load_raw(const RenderArgs &a, uint32_t slot, uint
     bool ok = slot < nslots;
     size_t s = ok ? (size_t)slot : 0;
     r.slot = ok ? slot : 0xFFFFFFFFu;
+    r.bm = 0u;
     r.r0 = a.rec[3 * s + 0];
     r.r1 = a.rec[3 * s + 1];
     r.r2 = a.rec[3 * s + 2];
     return r;
 }
 
-template <int TW, int TH>
+// The adjoint (BM = true) takes the forward's blend mask instead of the footprint mask: a
+// Gaussian reaches a pixel's colour only through a blend, so the mask is exact and tighter.
+template <int TW, int TH, bool BM = false>
 __device__ __forceinline__ Stage derive(const RenderArgs &a, const Raw &raw, float xb, float yb, float ox, float oy) {
     constexpr int SBX = TW / 8, NSB = TW * TH / 64;
     Stage s;
@@ -105,6 +115,12 @@ __device__ __forceinline__ Stage derive(const RenderArgs &a, const Raw &raw, flo
     s.r = raw.r2.x;
     s.g = raw.r2.y;
     s.b = raw.r2.z;
+    if (BM) {
+        s.mask = valid ? raw.bm : 0u;
+        asm volatile("" : "+v"(s.mx), "+v"(s.my), "+v"(s.A), "+v"(s.Bc), "+v"(s.Cc), "+v"(s.lo2));
+        asm volatile("" : "+v"(s.io), "+v"(s.r), "+v"(s.g), "+v"(s.b), "+v"(s.slot), "+v"(s.mask));
+        return s;
+    }
     // footprint box: half-widths k sqrt(Sigma2_ii), Sigma2 = conic^-1, k^2 = 2 ln(o / alpha_min)
     float ca = raw.r1.x, cb = raw.r1.y, cc = raw.r1.z;
     float idet = __builtin_amdgcn_rcpf(fmaxf(ca * cc - cb * cb, 1e-30f));
@@ -329,6 +345,9 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
 #pragma unroll
             for (int k = 0; k < NSB; ++k) live |= __ballot(L[k] > 0.f) ? (1u << k) : 0u;
             if (live == 0) break;
+            uint64_t blended[NSB];  // per sub-block: the Gaussians of the batch that blended into it
+#pragma unroll
+            for (int k = 0; k < NSB; ++k) blended[k] = 0ull;
             Raw raw_next = load_raw(a, sl_next, nslots);              // records of batch b + 64
             uint32_t sl_after = load_slot(a, b + 128 + lane, hi);     // slot ids of batch b + 128
             // the Gaussians of the batch that reach a live sub-block, in order (lanes past the
@@ -348,7 +367,11 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
                     if (!(m & (1u << k))) continue;  // wave-uniform
                     if (STATS) n_eval += real && L[k] > 0.f;
                     float dx = px[k] - mx, dy = py[k] - my;
-                    float al = fminf(a.amax, exp2_hw(power2(dx, dy, A, Bc, Cc, lo2)));
+                    const float pw = power2(dx, dy, A, Bc, Cc, lo2);
+                    // no live pixel of the sub-block within reach of alpha_min: nothing blends
+                    // (2^(log2 alpha_min - 0.01) is below alpha_min by far more than the rounding)
+                    if (__ballot(L[k] > 0.f && pw >= a.lamin2 - 0.01f) == 0ull) continue;
+                    float al = fminf(a.amax, exp2_hw(pw));
                     al = al >= a.amin ? al : 0.f;
                     float w = al * L[k];
                     float Tn = T[k] - w;
@@ -361,6 +384,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
                     C1[k] = __fmaf_rn(cg, w, C1[k]);
                     C2[k] = __fmaf_rn(cb, w, C2[k]);
                     last[k] = w > 0.f ? idx : last[k];
+                    blended[k] |= __ballot(w > 0.f) ? (1ull << j) : 0ull;
                 }
             };
             while (todo) {
@@ -375,6 +399,12 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
                 b1.y = two ? b1.y : -256.f;  // log2 of the opacity: alpha = 0 < alpha_min
                 blend(j1, a0, a1, a2, true);
                 blend(j2, b0, b1, b2, two);
+            }
+            {
+                uint32_t bm = 0;
+#pragma unroll
+                for (int k = 0; k < NSB; ++k) bm |= ((blended[k] >> lane) & 1ull) ? (1u << k) : 0u;
+                if (b + lane < hi) a.bmask[b + lane] = (uint8_t)bm;
             }
             cur = derive<TW, TH>(a, raw_next, fxb, fyb, fox, foy);
             put_stage(sg, cur, lane);
@@ -539,17 +569,21 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
         const float fxb = (float)xb, fyb = (float)yb, fox = (float)(x0 - xb), foy = (float)(y0 - yb);
         int e = hi;
         int bs = max(cs, e - 64);
-        Stage cur = derive<TW, TH>(a, load_raw(a, load_slot(a, (uint32_t)(bs + lane), (uint32_t)e), nslots), fxb,
-                                   fyb, fox, foy);
+        Raw raw0 = load_raw(a, load_slot(a, (uint32_t)(bs + lane), (uint32_t)e), nslots);
+        raw0.bm = load_bm(a, (uint32_t)(bs + lane), (uint32_t)e);
+        Stage cur = derive<TW, TH, true>(a, raw0, fxb, fyb, fox, foy);
         put_stage(sg, cur, lane);
         int bs2 = max(cs, bs - 64);
         uint32_t sl_next = load_slot(a, (uint32_t)(bs2 + lane), (uint32_t)bs);
+        uint32_t bm_next = load_bm(a, (uint32_t)(bs2 + lane), (uint32_t)bs);
         while (e > cs) {
             int n = e - bs;
             int e2 = bs;
             int bs3 = max(cs, bs2 - 64);
             Raw raw_next = load_raw(a, sl_next, nslots);                                 // batch [bs2, bs)
+            raw_next.bm = bm_next;
             uint32_t sl_after = load_slot(a, (uint32_t)(bs3 + lane), (uint32_t)bs2);   // batch [bs3, bs2)
+            uint32_t bm_after = load_bm(a, (uint32_t)(bs3 + lane), (uint32_t)bs2);
             // the batch's Gaussians with a footprint in the tile, last first (lanes at or past n
             // carry an empty mask)
             uint64_t todo = __ballot(cur.mask != 0u && lane < n);
@@ -609,9 +643,10 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
                 if (STATS && lane == 0) ++n_atomic;
                 if (writer) atomicAdd(grad2d + 9 * (size_t)slot + cls, tot);
             }
-            cur = derive<TW, TH>(a, raw_next, fxb, fyb, fox, foy);
+            cur = derive<TW, TH, true>(a, raw_next, fxb, fyb, fox, foy);
             put_stage(sg, cur, lane);
             sl_next = sl_after;
+            bm_next = bm_after;
             e = e2;
             bs = bs2;
             bs2 = bs3;
@@ -638,6 +673,7 @@ RenderArgs make_args(const splat_plan &p, void *ws, unsigned long long *stats) {
     a.boff = ws_at<uint32_t>(ws, p.off_bqoff);
     a.chk = ws_at<float4>(ws, p.off_chk);
     a.chklast = ws_at<int32_t>(ws, p.off_chklast);
+    a.bmask = ws_at<uint8_t>(ws, p.off_bmask);
     a.lc = (uint32_t)p.split_len;
     a.chk_cap = (uint32_t)p.chk_cap;
     a.stats = stats;
