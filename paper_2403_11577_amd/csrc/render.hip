@@ -169,6 +169,12 @@ __device__ __forceinline__ float power2(float dx, float dy, float A, float Bc, f
 
 __device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// alpha = min(alpha_max, 2^power) as one median-of-three: 2^power is never negative or NaN
+// here (culled Gaussians carry finite parameters), where the result equals fminf's
+__device__ __forceinline__ float alpha_of(float pw, float amax) {
+    return __builtin_amdgcn_fmed3f(exp2_hw(pw), 0.f, amax);
+}
+
 // wave64 sum with DPP (quad swaps, half-row and row mirrors, row broadcasts);
 // the total ends up in lane 63
 template <int CTRL, int ROWS>
@@ -371,7 +377,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
                     // no live pixel of the sub-block within reach of alpha_min: nothing blends
                     // (2^(log2 alpha_min - 0.01) is below alpha_min by far more than the rounding)
                     if (__ballot(L[k] > 0.f && pw >= a.lamin2 - 0.01f) == 0ull) continue;
-                    float al = fminf(a.amax, exp2_hw(pw));
+                    float al = alpha_of(pw, a.amax);
                     al = al >= a.amin ? al : 0.f;
                     float w = al * L[k];
                     float Tn = T[k] - w;
@@ -603,7 +609,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
                 for (int k = 0; k < NSB; ++k) {
                     if (!(m & (1u << k)) || idx > kmax[k]) continue;  // wave-uniform
                     float dx = px[k] - mx, dy = py[k] - my;
-                    float al = fminf(a.amax, exp2_hw(power2(dx, dy, A, Bc, Cc, lo2)));
+                    float al = alpha_of(power2(dx, dy, A, Bc, Cc, lo2), a.amax);
                     bool hit = (idx <= last[k]) && (al >= a.amin);
                     if (STATS) n_eval += idx <= last[k];
                     if (__ballot(hit) == 0) continue;  // wave-uniform
