@@ -83,7 +83,9 @@ class CalibConfig:
     # the candidates include, for each tile shape, the forward that composites the chunks of long
     # tile lists in parallel and joins them (pays off while few pixels saturate)
     tune_split_fwd: bool = True
-    split_len: int = 512           # instances per chunk of a split tile list
+    # instances per chunk of a split tile list: the faint Gaussians of a calibration leave long,
+    # unsaturated lists, which short chunks balance best (128 against 1,024 for saturating scenes)
+    split_len: int = 128
     fused_adam: bool = True        # torch's single-kernel Adam (else its multi-tensor one)
 
 
