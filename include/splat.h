@@ -123,7 +123,7 @@ typedef struct splat_plan {
     size_t off_meta;        /* int2[slot_cap]: (Gaussian id, view)                       */
     size_t off_rect;        /* u16x4[slot_cap]: tile rect (x0,x1,y0,y1) inclusive         */
     size_t off_ntiles;      /* u32[slot_cap+1]: tiles per slot, scanned to offsets       */
-    size_t off_keys;        /* u64[2][inst_cap]                                          */
+    size_t off_keys;        /* u64[2][inst_cap] (the sort's last passes keep u32 keys, see key_shift) */
     size_t off_vals;        /* u32[2][inst_cap]                                          */
     size_t off_ranges;      /* u32x2[V*T]: [start,end) of every (view, tile) list         */
     size_t off_queue;       /* u32[V*T]: (view, tile) work items, most expensive first    */
@@ -136,7 +136,8 @@ typedef struct splat_plan {
     int32_t sorted_buf;     /* which of the two key/value buffers holds the sorted result */
     int32_t radix_bits;     /* digit width of the LSD radix sort (passes = ceil(key bits / radix_bits)) */
     int32_t split_len;      /* instances per render-adjoint work item (the settings' value or 1024)   */
-    int32_t reserved1;
+    int32_t key_shift;      /* >= 0: the sorted keys are u32 (key >> key_shift), in the first half of
+                               the sorted key buffer; -1: u64 keys                                      */
     int64_t chk_cap;        /* checkpoint slots (an upper bound of what the tile lists can need)     */
     int64_t bq_cap;         /* render-adjoint work items (upper bound)                               */
     size_t off_bqueue;      /* uint4[bq_cap]: adjoint items (view-tile, chunk, first checkpoint slot or

@@ -48,7 +48,7 @@ class splat_plan(C.Structure):
                 [(n, C.c_int64) for n in ("n_gauss", "slot_cap", "inst_cap")] +
                 [(n, C.c_size_t) for n in _PLAN_OFFS] +
                 [("sorted_buf", C.c_int32), ("radix_bits", C.c_int32), ("split_len", C.c_int32),
-                 ("reserved1", C.c_int32), ("chk_cap", C.c_int64), ("bq_cap", C.c_int64)] +
+                 ("key_shift", C.c_int32), ("chk_cap", C.c_int64), ("bq_cap", C.c_int64)] +
                 [(n, C.c_size_t) for n in ("off_bqueue", "off_bqoff", "off_chk", "off_chklast", "off_bmask")])
 
 

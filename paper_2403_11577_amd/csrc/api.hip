@@ -199,6 +199,16 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     int passes = (bits + kRadixBits - 1) / kRadixBits;
     p.radix_bits = kRadixBits;
     p.sorted_buf = passes & 1;
+    // the sort carries 32-bit keys (key >> key_shift) from the first pass whose remaining digits
+    // fit 32 bits, if that shift stays within the depth field (the tile stays recoverable)
+    p.key_shift = -1;
+    for (int ps = 0; ps + 1 < passes; ++ps) {
+        int s1 = kRadixBits * (ps + 1);
+        if (s1 <= p.depth_bits && bits - s1 <= 32) {
+            p.key_shift = s1;
+            break;
+        }
+    }
 
     size_t off = 0;
     auto take = [&](size_t bytes) {

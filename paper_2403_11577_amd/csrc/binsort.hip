@@ -221,7 +221,8 @@ constexpr uint32_t kDigitMask = (uint32_t)kRadixDigits - 1u;
 constexpr int RS_DPT = kRadixDigits / RS_T;  // digits owned per thread
 static_assert(kRadixDigits % RS_T == 0, "digits must be a multiple of the workgroup size");
 
-__global__ __launch_bounds__(RS_T) void radix_upsweep_kernel(const uint64_t *keys, const uint32_t *counts, int shift,
+template <typename K>
+__global__ __launch_bounds__(RS_T) void radix_upsweep_kernel(const K *keys, const uint32_t *counts, int shift,
                                                             int nparts, uint32_t *hist) {
     __shared__ uint32_t h[kRadixDigits];
     for (int q = 0; q < RS_DPT; ++q) h[q * RS_T + threadIdx.x] = 0;
@@ -274,21 +275,26 @@ constexpr int RS_KPT = SPLAT_RADIX_KPT;  // keys per thread per tile
 constexpr int RS_WTILE = 64 * RS_KPT;
 constexpr int RS_TILE = RS_T * RS_KPT;
 
-__device__ inline void rs_load(const uint64_t *kin, const uint32_t *vin, uint32_t base, uint32_t e, int w, int lane,
-                               uint64_t (&key)[RS_KPT], uint32_t (&val)[RS_KPT]) {
+template <typename K>
+__device__ inline void rs_load(const K *kin, const uint32_t *vin, uint32_t base, uint32_t e, int w, int lane,
+                               K (&key)[RS_KPT], uint32_t (&val)[RS_KPT]) {
 #pragma unroll
     for (int k = 0; k < RS_KPT; ++k) {
         uint32_t i = base + w * RS_WTILE + k * 64 + lane;
         bool act = i < e;
-        key[k] = act ? kin[i] : 0ull;
+        key[k] = act ? kin[i] : (K)0;
         val[k] = act ? vin[i] : 0u;
     }
 }
 
-__global__ __launch_bounds__(RS_T) void radix_downsweep_kernel(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
+// KI keys in, KO keys out: a pass after which every remaining digit lies at or above bit
+// out_shift can write the keys shifted down by out_shift as 32-bit words (the later passes
+// then move 4 bytes less per key, read and written)
+template <typename KI, typename KO>
+__global__ __launch_bounds__(RS_T) void radix_downsweep_kernel(const KI *kin, const uint32_t *vin, KO *kout,
                                                               uint32_t *vout, const uint32_t *counts, int shift,
-                                                              int nparts, const uint32_t *hoff) {
-    __shared__ uint64_t sk[RS_TILE];
+                                                              int out_shift, int nparts, const uint32_t *hoff) {
+    __shared__ KI sk[RS_TILE];
     __shared__ uint32_t sv[RS_TILE];
     __shared__ uint32_t wc[RS_T / 64][kRadixDigits];  // per-wave running counts, then per-wave bases
     __shared__ uint32_t tstart[kRadixDigits];         // first LDS position of each digit in the tile
@@ -305,13 +311,13 @@ __global__ __launch_bounds__(RS_T) void radix_downsweep_kernel(const uint64_t *k
     uint32_t n = counts[CNT_INST];
     uint32_t b, e;
     chunk_of(n, nparts, blockIdx.x, b, e);
-    uint64_t key[RS_KPT];
+    KI key[RS_KPT];
     uint32_t val[RS_KPT];
     if (b < e) rs_load(kin, vin, b, e, w, lane, key, val);
     int parity = 0;
     for (uint32_t base = b; base < e; base += RS_TILE) {
         uint32_t tn = min((uint32_t)RS_TILE, e - base);
-        uint64_t nkey[RS_KPT];
+        KI nkey[RS_KPT];
         uint32_t nval[RS_KPT], rank[RS_KPT];
         if (base + RS_TILE < e) rs_load(kin, vin, base + RS_TILE, e, w, lane, nkey, nval);
         // stable rank inside the wave: the peers' leader bumps the wave's counter after all
@@ -366,11 +372,11 @@ __global__ __launch_bounds__(RS_T) void radix_downsweep_kernel(const uint64_t *k
         for (int k = 0; k < RS_KPT; ++k) {
             uint32_t i = k * RS_T + t;
             if (i < tn) {
-                uint64_t kk = sk[i];
+                KI kk = sk[i];
                 uint32_t d = (uint32_t)(kk >> shift) & kDigitMask;
                 uint32_t dst = gstart[d] + (i - tstart[d]);
                 if (dst < n) {  // always true when both sweeps saw the same keys
-                    kout[dst] = kk;
+                    kout[dst] = (KO)(kk >> out_shift);
                     vout[dst] = sv[i];
                 }
             }
@@ -390,7 +396,8 @@ __global__ __launch_bounds__(RS_T) void radix_downsweep_kernel(const uint64_t *k
 // -------------------------------------------------------------------------------------
 // tile ranges and the work queue
 // -------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void ranges_kernel(const uint64_t *keys, const uint32_t *counts, int depth_bits,
+template <typename K>
+__global__ __launch_bounds__(256) void ranges_kernel(const K *keys, const uint32_t *counts, int depth_bits,
                                                     uint64_t n_tiles, uint2 *ranges) {
     uint32_t n = counts[CNT_INST];
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
@@ -518,26 +525,59 @@ int launch_scan_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, in
     return launch_status("scan_down");
 }
 
-int launch_radix_sort_u64(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, const uint32_t *counts, int bit0,
-                          int bits, int nparts, uint32_t *hist, uint32_t *partials, hipStream_t st, int *sorted_in_1) {
+int launch_radix_sort_keys(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, const uint32_t *counts, int bit0,
+                           int bits, int nparts, uint32_t *hist, uint32_t *partials, hipStream_t st, int *sorted_in_1,
+                           int max_shift, int *key_shift) {
     int passes = (bits + kRadixBits - 1) / kRadixBits;
+    const int top = bit0 + bits;
+    // first pass after which the remaining digits fit a 32-bit word shifted down by S <= max_shift
+    int sw = -1, S = 0;
+    for (int p = 0; p + 1 < passes && max_shift >= 0; ++p) {
+        int s1 = bit0 + kRadixBits * (p + 1);
+        if (s1 <= max_shift && top - s1 <= 32) {
+            sw = p;
+            S = s1;
+            break;
+        }
+    }
     uint64_t *ki = k0, *ko = k1;
     uint32_t *vi = v0, *vo = v1;
     int nh = kRadixDigits * nparts;
     int rc = 0;
     for (int ps = 0; ps < passes; ++ps) {
         int shift = bit0 + kRadixBits * ps;
-        hipLaunchKernelGGL(radix_upsweep_kernel, dim3(nparts), dim3(RS_T), 0, st, ki, counts, shift, nparts, hist);
+        auto *ki32 = reinterpret_cast<uint32_t *>(ki);
+        auto *ko32 = reinterpret_cast<uint32_t *>(ko);
+        if (sw >= 0 && ps > sw)
+            hipLaunchKernelGGL(radix_upsweep_kernel<uint32_t>, dim3(nparts), dim3(RS_T), 0, st, ki32, counts, shift - S,
+                               nparts, hist);
+        else
+            hipLaunchKernelGGL(radix_upsweep_kernel<uint64_t>, dim3(nparts), dim3(RS_T), 0, st, ki, counts, shift, nparts,
+                               hist);
         if ((rc = launch_status("radix_upsweep"))) return rc;
         if ((rc = launch_scan_u32(hist, hist, nullptr, nh, partials, nullptr, st))) return rc;
-        hipLaunchKernelGGL(radix_downsweep_kernel, dim3(nparts), dim3(RS_T), 0, st, ki, vi, ko, vo, counts, shift,
-                           nparts, hist);
+        if (sw < 0 || ps < sw)
+            hipLaunchKernelGGL((radix_downsweep_kernel<uint64_t, uint64_t>), dim3(nparts), dim3(RS_T), 0, st, ki, vi, ko,
+                               vo, counts, shift, 0, nparts, hist);
+        else if (ps == sw)
+            hipLaunchKernelGGL((radix_downsweep_kernel<uint64_t, uint32_t>), dim3(nparts), dim3(RS_T), 0, st, ki, vi,
+                               ko32, vo, counts, shift, S, nparts, hist);
+        else
+            hipLaunchKernelGGL((radix_downsweep_kernel<uint32_t, uint32_t>), dim3(nparts), dim3(RS_T), 0, st, ki32, vi,
+                               ko32, vo, counts, shift - S, 0, nparts, hist);
         if ((rc = launch_status("radix_downsweep"))) return rc;
         uint64_t *tk = ki; ki = ko; ko = tk;
         uint32_t *tv = vi; vi = vo; vo = tv;
     }
     *sorted_in_1 = passes & 1;
+    if (key_shift) *key_shift = sw >= 0 ? S : -1;
     return 0;
+}
+
+int launch_radix_sort_u64(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, const uint32_t *counts, int bit0,
+                          int bits, int nparts, uint32_t *hist, uint32_t *partials, hipStream_t st, int *sorted_in_1) {
+    return launch_radix_sort_keys(k0, k1, v0, v1, counts, bit0, bits, nparts, hist, partials, st, sorted_in_1, -1,
+                                  nullptr);
 }
 
 int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
@@ -568,16 +608,26 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
     if ((rc = launch_status("emit"))) return rc;
 
     // LSD radix sort over the used key bits
-    int in1 = 0;
-    rc = launch_radix_sort_u64(keys0, keys1, vals0, vals1, counts, 0, p.depth_bits + p.tile_bits, p.n_sort_blocks, hist,
-                               partials, st, &in1);
+    // the passes after the depth digits carry 32-bit keys (key >> key_shift, key_shift <= depth_bits)
+    int in1 = 0, kshift = -1;
+    rc = launch_radix_sort_keys(keys0, keys1, vals0, vals1, counts, 0, p.depth_bits + p.tile_bits, p.n_sort_blocks,
+                                hist, partials, st, &in1, p.depth_bits, &kshift);
     if (rc) return rc;
+    if (kshift != p.key_shift) {
+        set_error("bin_sort: plan key shift %d does not match the sort's %d", p.key_shift, kshift);
+        return SPLAT_EINVAL;
+    }
     const uint64_t *ki = in1 ? keys1 : keys0;
     // ranges of every (view, tile) and the cost-ordered queue
     if ((rc = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, (int64_t)2 * nT, st))) return rc;
     int rb = (int)((p.inst_cap + 255) / 256);
     if (rb > 8192) rb = 8192;
-    hipLaunchKernelGGL(ranges_kernel, dim3(rb), dim3(256), 0, st, ki, counts, p.depth_bits, (uint64_t)nT, ranges);
+    if (kshift >= 0)
+        hipLaunchKernelGGL(ranges_kernel<uint32_t>, dim3(rb), dim3(256), 0, st, reinterpret_cast<const uint32_t *>(ki),
+                           counts, p.depth_bits - kshift, (uint64_t)nT, ranges);
+    else
+        hipLaunchKernelGGL(ranges_kernel<uint64_t>, dim3(rb), dim3(256), 0, st, ki, counts, p.depth_bits, (uint64_t)nT,
+                           ranges);
     if ((rc = launch_status("ranges"))) return rc;
     if ((rc = launch_fill_u32(qh, 0u, 66, st))) return rc;
     int qb = (nT + 255) / 256;

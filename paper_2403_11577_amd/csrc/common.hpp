@@ -113,6 +113,11 @@ int launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 // hist needs 2^kRadixBits * nparts + 1 u32, partials scan_partials of that
 int launch_radix_sort_u64(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, const uint32_t *counts, int bit0,
                           int bits, int nparts, uint32_t *hist, uint32_t *partials, hipStream_t st, int *sorted_in_1);
+// the same sort, where the passes after the first whose remaining digits fit 32 bits above
+// a shift S <= max_shift carry u32 keys (key >> S); *key_shift = S, or -1 when none does
+int launch_radix_sort_keys(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, const uint32_t *counts, int bit0,
+                           int bits, int nparts, uint32_t *hist, uint32_t *partials, hipStream_t st, int *sorted_in_1,
+                           int max_shift, int *key_shift);
 size_t voxel_ws_bytes(int64_t n);
 int launch_voxel_downsample(const float *pts, int64_t n, const double *lo, double voxel, void *ws, int32_t *keep,
                             uint32_t *n_keep, uint32_t *status, hipStream_t st);

@@ -131,8 +131,11 @@ class Frame:
         return base[o:o + n]
 
     def sorted_keys(self, n: int) -> torch.Tensor:
+        """The sorted keys: int64, or int32 (key >> plan.key_shift) when the sort narrowed them."""
         base = self.buf("keys", torch.int64, 2 * int(self.plan.inst_cap))
         o = int(self.plan.inst_cap) if self.plan.sorted_buf else 0
+        if int(self.plan.key_shift) >= 0:
+            return base[o:o + int(self.plan.inst_cap)].view(torch.int32)[:n]
         return base[o:o + n]
 
     def ranges(self) -> torch.Tensor:

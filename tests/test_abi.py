@@ -60,6 +60,9 @@ def test_plan_layout_is_aligned_and_disjoint():
     rb = p.radix_bits
     assert 4 <= rb <= 12
     assert p.sorted_buf == ((p.tile_bits + p.depth_bits + rb - 1) // rb) % 2
+    # the sort narrows its keys to u32 (key >> key_shift) after the first pass whose remaining
+    # digits fit 32 bits, the shift staying within the depth field: 9 here (24 bits remain)
+    assert p.key_shift == rb and p.tile_bits + p.depth_bits - p.key_shift <= 32
 
 
 @pytest.mark.parametrize("kw, msg", [

@@ -116,7 +116,8 @@ def test_bin_sort_vs_oracle(tile):
     fr = g["frame"]
     ns, ni = g["slots"], g["inst"]
     vals = fr.sorted_vals(ni).cpu().numpy().astype(np.int64)
-    keys = fr.sorted_keys(ni).cpu().numpy().view(np.uint64)
+    keys = fr.sorted_keys(ni).cpu().numpy()
+    keys = keys.view(np.uint32) if int(fr.plan.key_shift) >= 0 else keys.view(np.uint64)
     meta = fr.meta(ns).cpu().numpy()
     ranges = fr.ranges().cpu().numpy().astype(np.int64)
     assert np.all(np.diff(keys) >= 0)
