@@ -9,9 +9,10 @@
 //
 // Radix sort: reduce-then-scan per kRadixBits-bit digit with a fixed number of
 // partitions (the key count lives on the device, so the grid never depends on
-// it); inside a partition keys are ranked per wave with wave64 ballot peer
-// matching, which keeps the order stable without any inter-workgroup waiting,
-// and leave through an LDS reorder so that the scattered writes coalesce.
+// it); the reduce counts digits with per-wave LDS histograms; inside a partition
+// keys are ranked per wave with wave64 ballot peer matching, which keeps the
+// order stable without any inter-workgroup waiting, and leave through an LDS
+// reorder so that the scattered writes coalesce.
 #include "common.hpp"
 
 namespace splat {
@@ -224,23 +225,25 @@ static_assert(kRadixDigits % RS_T == 0, "digits must be a multiple of the workgr
 template <typename K>
 __global__ __launch_bounds__(RS_T) void radix_upsweep_kernel(const K *keys, const uint32_t *counts, int shift,
                                                             int nparts, uint32_t *hist) {
-    __shared__ uint32_t h[kRadixDigits];
-    for (int q = 0; q < RS_DPT; ++q) h[q * RS_T + threadIdx.x] = 0;
+    // one LDS histogram per wave, plain LDS atomics (equal digits in a wave serialise in hardware)
+    __shared__ uint32_t h[RS_T / 64][kRadixDigits];
+    const int w = threadIdx.x >> 6;
+    for (int q = 0; q < RS_DPT; ++q)
+        for (int ww = 0; ww < RS_T / 64; ++ww) h[ww][q * RS_T + threadIdx.x] = 0;
     __syncthreads();
     uint32_t n = counts[CNT_INST];
     uint32_t b, e;
     chunk_of(n, nparts, blockIdx.x, b, e);
     for (uint32_t base = b; base < e; base += RS_T) {
         uint32_t i = base + threadIdx.x;
-        bool act = i < e;
-        uint32_t d = act ? (uint32_t)(keys[i] >> shift) & kDigitMask : 0u;
-        uint64_t peers = match_digit(d, act);
-        if (act && rank_in(peers) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+        if (i < e) atomicAdd(&h[w][(uint32_t)(keys[i] >> shift) & kDigitMask], 1u);
     }
     __syncthreads();
     for (int q = 0; q < RS_DPT; ++q) {
         int d = q * RS_T + threadIdx.x;
-        hist[(size_t)d * nparts + blockIdx.x] = h[d];
+        uint32_t c = 0;
+        for (int ww = 0; ww < RS_T / 64; ++ww) c += h[ww][d];
+        hist[(size_t)d * nparts + blockIdx.x] = c;
     }
 }
 
