@@ -258,7 +258,10 @@ SPLAT_API int splat_render_fwd(const splat_plan *plan, void *ws, float *img, flo
  * every slot with wave-reduced atomics into the workspace gradient buffer,
  * which splat_project zeroed: call it once per projection (a second call adds
  * to the first).  dL_dimg[V][3][H][W], T_final and last_pos are the caller's
- * (last two from splat_render_fwd).
+ * (last two from splat_render_fwd).  The chunks of a split list are walked in
+ * parallel, each from the checkpoint splat_render_fwd recorded, and a Gaussian
+ * is evaluated only in the sub-blocks the forward blended it into: call it
+ * after splat_render_fwd of the same splat_bin_sort.
  */
 SPLAT_API int splat_render_bwd(const splat_plan *plan, void *ws, const float *dL_dimg, const float *T_final,
                      const int32_t *last_pos, void *stream);

@@ -10,14 +10,22 @@
 // accumulates per-slot gradients with one wave-reduced atomic group per
 // (tile, Gaussian).
 //
-// gfx950 mapping: one wave64 workgroup per (view, tile) work item, TW*TH/64
-// pixels per lane.  A batch of 64 Gaussian records is gathered one record per
-// lane (the next batch is in flight while the current one is evaluated) and
-// broadcast to the whole wave with v_readlane into scalar registers, so the
-// pair loop needs no LDS and no barrier.  The wave leaves a tile as soon as
-// every lane is saturated (ballot).  Work items come from a queue ordered by
-// decreasing list length; the hardware dispatcher hands them out in order, or
-// persistent waves pull them from a counter.
+// gfx950 mapping: one wave64 workgroup per work item, TW*TH/64 pixels per lane
+// (lane l owns pixel (l mod 8, l div 8) of every 8x8 sub-block).  A batch of 64
+// Gaussian records is gathered one record per lane (the next batch is in flight
+// while the current one is evaluated), staged in LDS and read back with
+// wave-uniform addresses; a workgroup is one wave, so no barrier is needed.  The
+// forward leaves a tile as soon as every pixel has stopped, skips sub-blocks
+// that no live pixel of it can see, and takes two Gaussians per pass.  Work items
+// come from a queue ordered by decreasing list length; the hardware dispatcher
+// hands them out in order, or persistent waves pull them from a counter.
+//
+// Long lists.  A list of at least split_len instances is cut into chunks.  The
+// forward records every pixel's (T, C) where each chunk starts, so the adjoint
+// walks the chunks as separate work items; optionally the forward also
+// composites chunks 1.. on their own and joins them (see the forward kernel).
+// The forward also leaves, per instance, the sub-blocks it was blended into;
+// the adjoint evaluates only those.
 //
 // Both kernels evaluate alpha with the same inline function, with float
 // contraction disabled, so the backward pass sees exactly the forward decisions,

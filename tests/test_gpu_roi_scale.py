@@ -62,13 +62,26 @@ def test_roi_tile_lists_vs_oracle():
             assert [x for x in mine if x not in mset] == [x for x in ref if x not in mset], (v, t)
 
 
-def test_roi_gradients_vs_oracle():
-    say("case: roi gradients")
+@pytest.mark.parametrize("split_len, split_fwd, faint", [(0, 0, False), (64, 1, False), (64, 1, True)])
+def test_roi_gradients_vs_oracle(split_len, split_fwd, faint):
+    # also with the lists walked as chunks of 64 and the joined forward, which must leave the
+    # rows above the region untouched (their pixels never composite)
+    say(f"case: roi gradients split_len={split_len} split_fwd={split_fwd} faint={faint}")
     s, roi = _scene(), 19
+    if faint:
+        s.gauss.opacity = (s.gauss.opacity * np.float32(0.1)).astype(np.float32)
     w2c_ref, _, _ = oracle.pose(s.traj, s.rig, s.xi, s.delta, s.views)
     intr = oracle.view_intr(s.rig, s.views)
     target = oracle.render_scene(s, xi=s.xi_gt, delta=s.delta_gt)["img"]
-    g = gpu_render(s, roi_y0=roi)
+    g = gpu_render(s, roi_y0=roi, split_len=split_len, split_fwd=split_fwd)
+    if split_len:
+        cnt = g["frame"].buf("counts", torch.int32, 8).cpu().numpy()
+        assert int(cnt[4]) > int(cnt[3]) > 0  # lists were split
+        orc_img = oracle.render(s.gauss, w2c_ref, intr, s.rig.W, s.rig.H, oracle.Settings(roi_y0=roi),
+                                alternatives=True)
+        nbad, _, _, _ = compare_images(g, orc_img)
+        assert nbad == 0
+        assert np.all(g["T"][:, :roi] == 1.0) and np.all(g["last_pos"][:, :roi] == -1)
     mset = oracle.Settings(margin=1e-2, roi_y0=roi)
     orc = oracle.render(s.gauss, w2c_ref, intr, s.rig.W, s.rig.H, mset)
     mask = (orc["nflag"] > 0) | (orc["kink"] > 0)
