@@ -314,35 +314,58 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
         const bool split = MODE != 1 && (uint32_t)item < nsplit;
         const uint32_t cslot = split ? a.boff[item] : 0u;
         uint32_t bnext = split ? rg.x + a.lc : 0xFFFFFFFFu, cnext = cslot + 1;
+        // MODE 2, a chunk walked in order: its live pixels that cannot stop in it are joined at
+        // once and parked (L = 0) until the chunk ends at park_end; the walk ends early when
+        // the other pixels have stopped
+        bool parked = false;
+        uint32_t park_end = 0u;
+        float parkL[NSB];
+#pragma unroll
+        for (int k = 0; k < NSB; ++k) parkL[k] = 0.f;
         for (uint32_t b = lo; b < hi; b += 64) {
+            if (MODE == 2 && parked && b == park_end) {
+#pragma unroll
+                for (int k = 0; k < NSB; ++k) L[k] = parkL[k] > 0.f ? parkL[k] : L[k];
+                parked = false;
+            }
             if (b == bnext) {
-                bool joined = false;
+                bool joined = false, wrote = false;
                 if (MODE == 2 && cnext < a.chk_cap) {
                     const float4 *src = a.chk + (size_t)cnext * NPIX + lane;
                     bool need = false;
 #pragma unroll
                     for (int k = 0; k < NSB; ++k) need |= L[k] > 0.f && !(T[k] * src[k * 64].x >= thr);
                     joined = __ballot(need) == 0ull;
-                    if (joined) {
-                        const int32_t *lsrc = a.chklast + (size_t)cnext * NPIX + lane;
-                        float4 *dst = a.chk + (size_t)cnext * NPIX + lane;
+                    const int32_t *lsrc = a.chklast + (size_t)cnext * NPIX + lane;
+                    float4 *dst = a.chk + (size_t)cnext * NPIX + lane;
+                    bool any_park = false;
 #pragma unroll
-                        for (int k = 0; k < NSB; ++k) {
-                            const float4 q = src[k * 64];
-                            const int ll = lsrc[k * 64];
-                            dst[k * 64] = make_float4(T[k], C0[k], C1[k], C2[k]);  // state where chunk c starts
-                            if (L[k] > 0.f) {
-                                C0[k] = __fmaf_rn(L[k], q.y, C0[k]);
-                                C1[k] = __fmaf_rn(L[k], q.z, C1[k]);
-                                C2[k] = __fmaf_rn(L[k], q.w, C2[k]);
-                                T[k] = T[k] * q.x;
-                                L[k] = T[k];
-                                last[k] = ll >= 0 ? ll : last[k];
-                            }
+                    for (int k = 0; k < NSB; ++k) {
+                        const float4 q = src[k * 64];
+                        const int ll = lsrc[k * 64];
+                        dst[k * 64] = make_float4(T[k], C0[k], C1[k], C2[k]);  // state where chunk c starts
+                        const bool jk = L[k] > 0.f && T[k] * q.x >= thr;    // cannot stop in the chunk
+                        if (jk) {
+                            C0[k] = __fmaf_rn(L[k], q.y, C0[k]);
+                            C1[k] = __fmaf_rn(L[k], q.z, C1[k]);
+                            C2[k] = __fmaf_rn(L[k], q.w, C2[k]);
+                            T[k] = T[k] * q.x;
+                            L[k] = T[k];
+                            last[k] = ll >= 0 ? ll : last[k];
+                        }
+                        if (!joined) {
+                            parkL[k] = jk ? L[k] : 0.f;
+                            L[k] = jk ? 0.f : L[k];
+                            any_park |= jk;
                         }
                     }
+                    wrote = true;
+                    if (!joined && __ballot(any_park) != 0ull) {
+                        parked = true;
+                        park_end = bnext + a.lc;
+                    }
                 }
-                if (!joined) put_chk<NSB>(a, cnext, T, C0, C1, C2, lane);
+                if (!wrote) put_chk<NSB>(a, cnext, T, C0, C1, C2, lane);
                 ++cnext;
                 bnext += a.lc;
                 if (joined) {
@@ -358,7 +381,18 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
             uint32_t live = 0;  // sub-blocks with a pixel still compositing
 #pragma unroll
             for (int k = 0; k < NSB; ++k) live |= __ballot(L[k] > 0.f) ? (1u << k) : 0u;
-            if (live == 0) break;
+            if (live == 0) {
+                if (MODE == 2 && parked && park_end < hi) {
+                    // the walking pixels have stopped: the parked ones resume where the chunk ends
+                    cur = derive<TW, TH>(a, load_raw(a, load_slot(a, park_end + lane, hi), nslots), fxb, fyb, fox,
+                                         foy);
+                    put_stage(sg, cur, lane);
+                    sl_next = load_slot(a, park_end + 64 + lane, hi);
+                    b = park_end - 64;
+                    continue;
+                }
+                break;  // every pixel has stopped (parked ones already hold the state at the list end)
+            }
             uint64_t blended[NSB];  // per sub-block: the Gaussians of the batch that blended into it
 #pragma unroll
             for (int k = 0; k < NSB; ++k) blended[k] = 0ull;
@@ -418,6 +452,8 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
                 uint32_t bm = 0;
 #pragma unroll
                 for (int k = 0; k < NSB; ++k) bm |= ((blended[k] >> lane) & 1ull) ? (1u << k) : 0u;
+                // with parked pixels the chunk's own pass holds their blends (a superset is exact)
+                if (MODE == 2 && parked && b + lane < hi) bm |= a.bmask[b + lane];
                 if (b + lane < hi) a.bmask[b + lane] = (uint8_t)bm;
             }
             cur = derive<TW, TH>(a, raw_next, fxb, fyb, fox, foy);
