@@ -85,6 +85,14 @@ static int check_plan(const splat_plan *p, const void *ws, const char *who) {
     if (p->n_views < 1 || p->ws_bytes == 0 || p->tiles_per_view < 1 || check_settings(&p->s)) {
         set_error("%s: plan is not initialised by splat_plan_make", who); return SPLAT_EINVAL;
     }
+    // the chunking of long lists assumes whole 64-instance batches and capacities that cover the
+    // tiles (a changed split_len needs a new plan: the checkpoint capacity depends on it)
+    const int64_t ntiles = (int64_t)p->n_views * p->tiles_per_view;
+    if (p->split_len < 64 || p->split_len > (1 << 24) || (p->split_len & (p->split_len - 1)) ||
+        p->chk_cap != 2 * ((p->inst_cap + p->split_len - 1) / p->split_len) + 1 || p->bq_cap != ntiles + p->chk_cap) {
+        set_error("%s: plan's split fields are inconsistent (make a new plan instead of editing them)", who);
+        return SPLAT_EINVAL;
+    }
     return SPLAT_OK;
 }
 

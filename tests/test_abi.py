@@ -90,6 +90,16 @@ def test_plan_make_rejects_bad_settings(field, value):
         B.splat_plan_make(s, 1, 10, 64, 64, 10, 10)
 
 
+def test_entry_points_reject_an_edited_split_length():
+    # the checkpoint capacity is sized for the plan's split_len: editing it is an error, not a fault
+    L = B.lib()
+    p = B.splat_plan_make(B.default_settings(), 1, 10, 64, 64, 10, 100)
+    p.split_len = 64
+    assert L.splat_render_fwd(C.byref(p), C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), None) == -1
+    assert b"split fields" in L.splat_last_error()
+    assert L.splat_bin_sort(C.byref(p), C.c_void_p(16), None) == -1
+
+
 def test_too_many_work_items_is_unsupported():
     # 1023 views of 2048 x 2048 8x8 tiles exceed the 2^31 (view, tile) items the key and queue allow
     s = B.default_settings()
