@@ -150,6 +150,8 @@ typedef struct splat_plan {
                                on its own (split_fwd)                                                   */
     size_t off_bmask;       /* u8[inst_cap]: per instance, bit k set when the forward blended it into a
                                pixel of 8x8 sub-block k of its tile; the adjoint skips the others      */
+    size_t off_dkey;        /* u32[slot_cap]: depth field of each slot's sort key,
+                               bits(depth32) - bits(near_z) (a compact copy for the emission)        */
 } splat_plan;
 
 /* Fill `s` with the default settings listed above (16x16 tiles, batch 64,

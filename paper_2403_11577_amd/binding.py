@@ -49,7 +49,8 @@ class splat_plan(C.Structure):
                 [(n, C.c_size_t) for n in _PLAN_OFFS] +
                 [("sorted_buf", C.c_int32), ("radix_bits", C.c_int32), ("split_len", C.c_int32),
                  ("key_shift", C.c_int32), ("chk_cap", C.c_int64), ("bq_cap", C.c_int64)] +
-                [(n, C.c_size_t) for n in ("off_bqueue", "off_bqoff", "off_chk", "off_chklast", "off_bmask")])
+                [(n, C.c_size_t) for n in ("off_bqueue", "off_bqoff", "off_chk", "off_chklast", "off_bmask",
+                                                      "off_dkey")])
 
 
 class splat_ngp(C.Structure):

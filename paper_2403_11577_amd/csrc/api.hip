@@ -260,6 +260,7 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     p.off_chk = take((size_t)p.chk_cap * (size_t)(s->tile_w * s->tile_h) * 16);
     p.off_chklast = take((size_t)p.chk_cap * (size_t)(s->tile_w * s->tile_h) * 4);
     p.off_bmask = take((size_t)inst_cap);
+    p.off_dkey = take((size_t)slot_cap * 4);
     p.ws_bytes = off;
     *plan = p;
     return SPLAT_OK;

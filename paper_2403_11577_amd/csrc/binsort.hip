@@ -169,19 +169,17 @@ __global__ void inst_finish_kernel(const uint32_t *offs, int64_t inst_cap, uint3
 }
 
 __global__ __launch_bounds__(256) void emit_kernel(const uint32_t *counts, const uint32_t *offs, const Rect16 *rect,
-                                                  const float4 *rec, const int2 *meta, int tiles_x, int T,
-                                                  int depth_bits, float near32,
-                                                  uint64_t *keys, uint32_t *vals) {
+                                                  const uint32_t *dkeys, const int2 *meta, int tiles_x, int T,
+                                                  int depth_bits, uint64_t *keys, uint32_t *vals) {
     uint32_t ns = counts[CNT_SLOTS];
     uint32_t ni = counts[CNT_INST];  // <= capacity; only slots wholly below it emit
-    uint32_t nb = __float_as_uint(near32);
     for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < ns;
          s += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t o = offs[s];
         Rect16 r = rect[s];
         uint32_t nt = (uint32_t)(r.x1 - r.x0 + 1) * (uint32_t)(r.y1 - r.y0 + 1);
         if ((uint64_t)o + nt > (uint64_t)ni) continue;
-        uint64_t dkey = (uint64_t)(__float_as_uint(rec[3 * s + 2].w) - nb);
+        uint64_t dkey = (uint64_t)dkeys[s];  // bits(depth32) - bits(near_z), written by the projection
         uint64_t vbase = (uint64_t)meta[s].y * (uint64_t)T;
         for (int ty = r.y0; ty <= r.y1; ++ty)
             for (int tx = r.x0; tx <= r.x1; ++tx) {
@@ -606,8 +604,8 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
     int eb = (int)((p.slot_cap + 255) / 256);
     if (eb > 8192) eb = 8192;
     hipLaunchKernelGGL(emit_kernel, dim3(eb), dim3(256), 0, st, counts, ntiles, ws_at<Rect16>(ws, p.off_rect),
-                       ws_at<float4>(ws, p.off_rec), ws_at<int2>(ws, p.off_meta), p.tiles_x, p.tiles_per_view,
-                       p.depth_bits, (float)p.s.near_z, keys0, vals0);
+                       ws_at<uint32_t>(ws, p.off_dkey), ws_at<int2>(ws, p.off_meta), p.tiles_x, p.tiles_per_view,
+                       p.depth_bits, keys0, vals0);
     if ((rc = launch_status("emit"))) return rc;
 
     // LSD radix sort over the used key bits

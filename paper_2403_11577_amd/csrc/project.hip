@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, sp
                                                            const CamC *cam, int W, int H, int V, int nb,
                                                            const uint32_t *waveoff, const uint64_t *visbits,
                                                            int64_t slot_cap, float4 *rec, int2 *meta, Rect16 *rect,
-                                                           uint32_t *ntiles) {
+                                                           uint32_t *ntiles, uint32_t *dkey) {
     const int b = blockIdx.x, w = threadIdx.x >> 6, lane = __lane_id();
     const int64_t i = (int64_t)b * 256 + threadIdx.x;
     if (i >= g.n) return;
@@ -270,6 +270,7 @@ __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, sp
         rec[3 * slot + 1] = make_float4((float)P.Q[0], (float)P.Q[1], (float)P.Q[2], gi.o);
         rec[3 * slot + 2] = make_float4(cr, cg, cb, P.depth32);
         meta[slot] = make_int2((int)i, v);
+        dkey[slot] = __float_as_uint(P.depth32) - __float_as_uint((float)S.near_z);
         Rect16 rc;
         rc.x0 = (uint16_t)(P.px0 / tw); rc.x1 = (uint16_t)(P.px1 / tw);
         rc.y0 = (uint16_t)(P.py0 / th); rc.y1 = (uint16_t)(P.py1 / th);
@@ -549,7 +550,8 @@ int launch_project(const splat_plan &p, void *ws, const splat_gaussians &g, cons
     if (rc || g.n == 0) return rc;
     hipLaunchKernelGGL(project_write_kernel, dim3(nb), dim3(256), 0, st, p.s, g, w2c, cam, p.width, p.height, V, nb,
                        wavecnt, visbits, p.slot_cap, ws_at<float4>(ws, p.off_rec), ws_at<int2>(ws, p.off_meta),
-                       ws_at<Rect16>(ws, p.off_rect), ws_at<uint32_t>(ws, p.off_ntiles));
+                       ws_at<Rect16>(ws, p.off_rect), ws_at<uint32_t>(ws, p.off_ntiles),
+                       ws_at<uint32_t>(ws, p.off_dkey));
     if ((rc = launch_status("project_write"))) return rc;
     int zb = (int)((p.slot_cap * 9 + 255) / 256);
     if (zb > 8192) zb = 8192;

@@ -42,7 +42,7 @@ def test_default_settings_are_the_documented_readings():
 def test_plan_layout_is_aligned_and_disjoint():
     s = B.default_settings()
     p = B.splat_plan_make(s, 3, 1000, 100, 37, 2000, 9000)
-    names = [n for n in B._PLAN_OFFS if n != "ws_bytes"] + ["off_bqueue", "off_bqoff", "off_chk", "off_chklast", "off_bmask"]
+    names = [n for n in B._PLAN_OFFS if n != "ws_bytes"] + ["off_bqueue", "off_bqoff", "off_chk", "off_chklast", "off_bmask", "off_dkey"]
     offs = sorted((getattr(p, n), n) for n in names)
     assert all(o % 256 == 0 for o, _ in offs)
     assert len({o for o, _ in offs}) == len(offs)
@@ -53,7 +53,7 @@ def test_plan_layout_is_aligned_and_disjoint():
     assert p.chk_cap == 2 * -(-9000 // 1024) + 1 and p.bq_cap == 63 + p.chk_cap
     assert p.off_chklast - p.off_chk >= p.chk_cap * 16 * 16 * 16
     assert p.off_bmask - p.off_chklast >= p.chk_cap * 16 * 16 * 4
-    assert p.ws_bytes - p.off_bmask >= 9000
+    assert p.off_dkey - p.off_bmask >= 9000 and p.ws_bytes - p.off_dkey >= 2000 * 4
     assert p.tiles_x == 7 and p.tiles_y == 3 and p.tiles_per_view == 21
     # key = (view*T + tile) << depth_bits | depth: 63 items need 6 bits, the 0.2..256 m window 27
     assert p.tile_bits == 6 and p.depth_bits == 27
