@@ -166,6 +166,11 @@ class Calibrator:
         self.field = None
         if cfg.model == "field":
             self._init_field(full, cfg)
+        else:
+            # the render reads the colour and rotation parameters in place (the optimiser updates
+            # them in place too); opacity and scale are activations formed every step
+            self.win.color = self.color.detach()
+            self.win.quat = self.quat.detach()
         self.rho = torch.tensor(scene.xi[:, :3], dtype=torch.float64, device=device).requires_grad_(True)
         self.phi = torch.tensor(scene.xi[:, 3:], dtype=torch.float64, device=device).requires_grad_(True)
         self.delta = torch.tensor(scene.delta, dtype=torch.float64, device=device).requires_grad_(True)
@@ -408,18 +413,14 @@ class Calibrator:
         cfg = self.cfg
         idx = self._idx
         w, f = self.win, self.full
-        w.view_cam.copy_(f.view_cam[idx])
-        w.view_t.copy_(f.view_t[idx])
-        w.intr.copy_(f.intr[idx])
-        self.tgt.copy_(self.targets[idx])
+        torch.index_select(f.view_cam, 0, idx, out=w.view_cam)
+        torch.index_select(f.view_t, 0, idx, out=w.view_t)
+        torch.index_select(f.intr, 0, idx, out=w.intr)
+        torch.index_select(self.targets, 0, idx, out=self.tgt)
         with torch.no_grad():
             if self.field is None:
-                o = torch.sigmoid(self.logit_o)
-                s = torch.exp(self.log_s)
-                w.opacity.copy_(o)
-                w.scale.copy_(s)
-                w.color.copy_(self.color)
-                w.quat.copy_(self.quat)
+                o = torch.sigmoid(self.logit_o, out=w.opacity)
+                s = torch.exp(self.log_s, out=w.scale)
             else:
                 self._ensure_index()
                 B.splat_ngp_fwd_train(self.field_struct, w.mean, w.quat, w.scale, w.opacity, w.color, self.field_ws)
