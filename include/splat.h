@@ -448,8 +448,43 @@ SPLAT_API const char *splat_last_error(void);
 /* Library version string. */
 SPLAT_API const char *splat_version(void);
 
+/*
+ * The optimiser step of the per-Gaussian parameters in the calibration loop:
+ * Adam, the optimiser the paper trains with (Sec. IV-B), over up to
+ * SPLAT_ADAM_MAX_GROUPS parameter arrays in one launch, fused with the
+ * activation the render applies to each.  Per element of a group (float32
+ * device arrays of n values; the value array holds act(param), what the render
+ * read this step; act = identity uses param itself and value may be NULL):
+ *   g = grad * act'(param)          sigmoid: value (1 - value); exp: value; identity: 1
+ *   t = *step + 1,  m = b1 m + (1 - b1) g,  s = b2 s + (1 - b2) g^2
+ *   param -= lr / (1 - b1^t) * m / (sqrt(s) / sqrt(1 - b2^t) + eps)
+ *   value = act(param),  grad = 0   (ready for the next step's adjoint, which adds)
+ * and then *step += 1 (a float32 device scalar shared by the groups).  lr is a
+ * device scalar per group, so a captured graph replays with the caller's current
+ * rates.  exp_avg and exp_avg_sq start at zero (the caller's).
+ */
+#define SPLAT_ADAM_MAX_GROUPS 8
+#define SPLAT_ACT_IDENTITY 0
+#define SPLAT_ACT_SIGMOID 1
+#define SPLAT_ACT_EXP 2
+typedef struct splat_adam_group {
+    float *param;        /* raw parameter, updated in place            */
+    float *exp_avg;      /* first moment                               */
+    float *exp_avg_sq;   /* second moment                              */
+    float *grad;         /* d(loss)/d(value), zeroed after the update  */
+    float *value;        /* act(param), rewritten (NULL for identity)   */
+    const float *lr;     /* device scalar learning rate                */
+    int64_t n;
+    int32_t act;         /* SPLAT_ACT_*                                */
+    int32_t reserved;
+} splat_adam_group;
+
+SPLAT_API int splat_adam_step(const splat_adam_group *groups, int32_t n_groups, double beta1, double beta2,
+                              double eps, float *step, void *stream);
+
 /* sizeof of the ABI structs, for bindings to check their mirrors:
- * which = 0 splat_settings, 1 splat_gaussians, 2 splat_plan, 3 splat_ngp; else 0. */
+ * which = 0 splat_settings, 1 splat_gaussians, 2 splat_plan, 3 splat_ngp,
+ * 4 splat_adam_group; else 0. */
 SPLAT_API size_t splat_struct_size(int32_t which);
 
 #ifdef __cplusplus

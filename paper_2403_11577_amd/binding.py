@@ -53,6 +53,16 @@ class splat_plan(C.Structure):
                                                       "off_dkey")])
 
 
+ADAM_MAX_GROUPS = 8
+ACT_IDENTITY, ACT_SIGMOID, ACT_EXP = 0, 1, 2
+
+
+class splat_adam_group(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("exp_avg", C.c_void_p), ("exp_avg_sq", C.c_void_p), ("grad", C.c_void_p),
+                ("value", C.c_void_p), ("lr", C.c_void_p), ("n", C.c_int64), ("act", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class splat_ngp(C.Structure):
     _fields_ = ([(n, C.c_int32) for n in ("levels", "feat", "log2_table", "n_min", "n_max", "hidden")] +
                 [("scale_max", C.c_double), ("lo", C.c_double * 3), ("hi", C.c_double * 3)] +
@@ -91,6 +101,7 @@ def lib():
     L.splat_dssim_workspace_size.restype = C.c_size_t
     L.splat_dssim_loss_grad.argtypes = [P, P, I32, I32, I32, I32, C.c_double, P, C.c_size_t, P, P, P]
     L.splat_scale_reg.argtypes = [P, I64, C.c_double, P, P, P]
+    L.splat_adam_step.argtypes = [C.POINTER(splat_adam_group), I32, C.c_double, C.c_double, C.c_double, P, P]
     L.splat_last_error.restype = C.c_char_p
     L.splat_version.restype = C.c_char_p
     L.splat_struct_size.argtypes = [I32]
@@ -112,7 +123,7 @@ def lib():
     L.splat_voxel_workspace_size.argtypes = [I64]
     L.splat_voxel_workspace_size.restype = C.c_size_t
     L.splat_voxel_downsample.argtypes = [P, I64, C.POINTER(C.c_double), C.c_double, P, C.c_size_t, P, P, P, P]
-    for w, st in ((0, splat_settings), (1, splat_gaussians), (2, splat_plan), (3, splat_ngp)):
+    for w, st in ((0, splat_settings), (1, splat_gaussians), (2, splat_plan), (3, splat_ngp), (4, splat_adam_group)):
         if L.splat_struct_size(w) != C.sizeof(st):
             raise SplatError(f"ABI mismatch: {st.__name__} is {L.splat_struct_size(w)} bytes in the "
                              f"library, {C.sizeof(st)} in the binding")
@@ -228,6 +239,21 @@ def splat_dssim_loss_grad(img, target, ws, dL_dimg, loss=None, roi_y0=0, weight=
     _check(lib().splat_dssim_loss_grad(_ptr(img), _ptr(target), int(V), int(W), int(H), int(roi_y0), float(weight),
                                        _ptr(ws), int(ws.numel() * ws.element_size()), _ptr(dL_dimg), _ptr(loss),
                                        _stream(stream)), "splat_dssim_loss_grad")
+
+
+def splat_adam_step(groups, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+    """groups: [(param, exp_avg, exp_avg_sq, grad, value or None, lr, act)] of float32 device tensors
+    (lr a one-element device tensor); step: one-element float32 device tensor, advanced by one."""
+    arr = (splat_adam_group * len(groups))()
+    for a, (param, m, v, grad, value, lr, act) in zip(arr, groups):
+        n = param.numel()
+        for t in (m, v, grad) + ((value,) if value is not None else ()):
+            if t.numel() != n or not t.is_contiguous() or str(t.dtype) != "torch.float32":
+                raise SplatError("splat_adam_step: arrays of a group must be contiguous float32 of one size")
+        a.param, a.exp_avg, a.exp_avg_sq, a.grad = _ptr(param), _ptr(m), _ptr(v), _ptr(grad)
+        a.value, a.lr, a.n, a.act = _ptr(value), _ptr(lr), n, int(act)
+    _check(lib().splat_adam_step(arr, len(groups), float(beta1), float(beta2), float(eps), _ptr(step),
+                                 _stream(stream)), "splat_adam_step")
 
 
 def splat_scale_reg(scale, lam, dscale, loss=None, stream=None):

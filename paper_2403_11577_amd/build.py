@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsplat.so")
-SOURCES = ["api.hip", "pose.hip", "project.hip", "binsort.hip", "render.hip", "loss.hip", "ssim.hip", "ngp.hip", "voxel.hip"]
+SOURCES = ["api.hip", "pose.hip", "project.hip", "binsort.hip", "render.hip", "loss.hip", "ssim.hip", "ngp.hip", "voxel.hip", "adam.hip"]
 ARCH = os.environ.get("SPLAT_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

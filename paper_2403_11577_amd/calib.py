@@ -87,6 +87,9 @@ class CalibConfig:
     # unsaturated lists, which short chunks balance best (128 against 1,024 for saturating scenes)
     split_len: int = 128
     fused_adam: bool = True        # torch's single-kernel Adam (else its multi-tensor one)
+    # independent Gaussians: the library's Adam step over the four parameter arrays in one launch,
+    # fused with their activations and the clearing of their gradients (else torch's Adam)
+    native_adam: bool = True
 
 
 def rotation_error_deg(xi):
@@ -192,6 +195,19 @@ class Calibrator:
             dict(params=[self.delta], lr=lr(cfg.lr_time)),
         ], eps=1e-15, capturable=cfg.graph, fused=cfg.fused_adam or None)
         self.base_lr = [[float(grp["lr"]) for grp in o.param_groups] for o in (self.opt_g, self.opt_c)]
+        self._native = self.field is None and cfg.native_adam
+        if self._native:
+            # moments, a step counter and device learning rates of the library's Adam step, in the
+            # order of opt_g's groups (colour, opacity logit, log scale, rotation); the render's
+            # activations are formed once here and then rewritten by every step
+            raw = (self.color, self.logit_o, self.log_s, self.quat)
+            self._nat_m = [torch.zeros_like(t) for t in raw]
+            self._nat_v = [torch.zeros_like(t) for t in raw]
+            self._nat_lr = [torch.tensor([lr0], dtype=torch.float32, device=device) for lr0 in self.base_lr[0]]
+            self._nat_step = torch.zeros(1, dtype=torch.float32, device=device)
+            with torch.no_grad():
+                torch.sigmoid(self.logit_o, out=self.win.opacity)
+                torch.exp(self.log_s, out=self.win.scale)
         # gradient buffers the step writes in place (fixed addresses, as a captured graph needs)
         for t in (self.rho, self.phi, self.delta):
             t.grad = torch.zeros_like(t)
@@ -361,6 +377,9 @@ class Calibrator:
                     grp["lr"].fill_(lr0 * frac)
                 else:
                     grp["lr"] = lr0 * frac
+        if self._native:
+            for t, lr0 in zip(self._nat_lr, self.base_lr[0]):
+                t.fill_(lr0 * frac)
         if self._next_tune is not None and k >= self._next_tune and not self._trial:
             # three steps per candidate; the first one of each may include a graph capture
             self._trial = [ci for ci in range(len(self._cands)) for _ in range(3)]
@@ -417,10 +436,12 @@ class Calibrator:
         torch.index_select(f.view_t, 0, idx, out=w.view_t)
         torch.index_select(f.intr, 0, idx, out=w.intr)
         torch.index_select(self.targets, 0, idx, out=self.tgt)
+        native = self._native and not cfg.freeze_gaussians
         with torch.no_grad():
             if self.field is None:
-                o = torch.sigmoid(self.logit_o, out=w.opacity)
-                s = torch.exp(self.log_s, out=w.scale)
+                if not native:  # else the previous step's Adam left them in place
+                    o = torch.sigmoid(self.logit_o, out=w.opacity)
+                    s = torch.exp(self.log_s, out=w.scale)
             else:
                 self._ensure_index()
                 B.splat_ngp_fwd_train(self.field_struct, w.mean, w.quat, w.scale, w.opacity, w.color, self.field_ws)
@@ -429,7 +450,12 @@ class Calibrator:
             self.dl_t.copy_(self.delta)
             fr = self.fr
             self.loss.zero_()
-            pl.zero_grads(self.gr)
+            if native:  # the Gaussian gradients were cleared by the previous Adam step
+                for t in (self.gr.mean, self.gr.w2c, self.gr.xi, self.gr.delta):
+                    if t is not None:
+                        t.zero_()
+            else:
+                pl.zero_grads(self.gr)
             pl.forward(fr, w, self.xi_t, self.dl_t)
             B.splat_l1_loss_grad(fr.img, self.tgt, None, self.dimg, self.loss, self.settings.roi_y0,
                                  1.0 - cfg.lam_dssim)
@@ -440,7 +466,9 @@ class Calibrator:
             if cfg.lam_scale > 0:
                 B.splat_scale_reg(w.scale, cfg.lam_scale, self.gr.scale, self.loss)
             # gradients of the optimised tensors (written in place)
-            if self.field is None:
+            if native:
+                pass  # the fused step below chains them through the activations itself
+            elif self.field is None:
                 self.color.grad = self.gr.color
                 self.quat.grad = self.gr.quat
                 torch.mul(self.gr.opacity, o * (1 - o), out=self.logit_o.grad)
@@ -455,7 +483,16 @@ class Calibrator:
             self.rho.grad.copy_(self.gr.xi[:, :3])
             self.phi.grad.copy_(self.gr.xi[:, 3:])
             self.delta.grad.copy_(self.gr.delta)
-        if not cfg.freeze_gaussians:
+        if native:
+            gr = self.gr
+            raw = (self.color, self.logit_o, self.log_s, self.quat)
+            grads = (gr.color, gr.opacity, gr.scale, gr.quat)
+            values = (None, w.opacity, w.scale, None)
+            acts = (B.ACT_IDENTITY, B.ACT_SIGMOID, B.ACT_EXP, B.ACT_IDENTITY)
+            B.splat_adam_step([(p.detach(), m, v, g, val, lr, a) for p, m, v, g, val, lr, a in
+                               zip(raw, self._nat_m, self._nat_v, grads, values, self._nat_lr, acts)],
+                              self._nat_step)
+        elif not cfg.freeze_gaussians:
             self.opt_g.step()
 
     def _poll(self, k: int):

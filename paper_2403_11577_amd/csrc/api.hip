@@ -135,6 +135,7 @@ size_t splat_struct_size(int32_t which) {
         case 1: return sizeof(splat_gaussians);
         case 2: return sizeof(splat_plan);
         case 3: return sizeof(splat_ngp);
+        case 4: return sizeof(splat_adam_group);
         default: return 0;
     }
 }
@@ -362,6 +363,31 @@ int splat_scale_reg(const float *scale, int64_t n, double lambda, float *dscale,
     if (!scale || !dscale) { set_error("scale_reg: NULL argument"); return SPLAT_EINVAL; }
     if (!std::isfinite(lambda)) { set_error("scale_reg: lambda must be finite"); return SPLAT_EINVAL; }
     return launch_scale_reg(scale, n, lambda, dscale, loss, (hipStream_t)stream);
+}
+
+int splat_adam_step(const splat_adam_group *groups, int32_t n_groups, double beta1, double beta2, double eps,
+                    float *step, void *stream) {
+    g_err[0] = 0;
+    if (!groups || !step) { set_error("adam_step: NULL argument"); return SPLAT_EINVAL; }
+    if (n_groups < 1 || n_groups > SPLAT_ADAM_MAX_GROUPS) {
+        set_error("adam_step: n_groups must be in [1, %d] (got %d)", SPLAT_ADAM_MAX_GROUPS, n_groups);
+        return SPLAT_EINVAL;
+    }
+    if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps >= 0.0) || !std::isfinite(eps)) {
+        set_error("adam_step: need 0 <= beta1, beta2 < 1 and 0 <= eps < inf"); return SPLAT_EINVAL;
+    }
+    for (int i = 0; i < n_groups; ++i) {
+        const splat_adam_group &g = groups[i];
+        if (g.n < 0 || g.n >= ((int64_t)1 << 40)) { set_error("adam_step: group %d has n = %lld", i, (long long)g.n); return SPLAT_EINVAL; }
+        if (g.act < SPLAT_ACT_IDENTITY || g.act > SPLAT_ACT_EXP) {
+            set_error("adam_step: group %d has an unknown activation %d", i, g.act); return SPLAT_EINVAL;
+        }
+        if (g.n > 0 && (!g.param || !g.exp_avg || !g.exp_avg_sq || !g.grad || !g.lr ||
+                        (g.act != SPLAT_ACT_IDENTITY && !g.value))) {
+            set_error("adam_step: group %d has a NULL array", i); return SPLAT_EINVAL;
+        }
+    }
+    return launch_adam(groups, n_groups, beta1, beta2, eps, step, (hipStream_t)stream);
 }
 
 int splat_render_bwd(const splat_plan *plan, void *ws, const float *dL_dimg, const float *T_final,

@@ -82,6 +82,8 @@ int launch_render_bwd(const splat_plan &p, void *ws, const float *dimg, const fl
 int launch_l1(const float *img, const float *target, const uint8_t *mask, int64_t n_views, int32_t width,
               int32_t height, int32_t roi_y0, double inv_n, float *dimg, double *loss, hipStream_t st);
 int launch_scale_reg(const float *scale, int64_t n, double lambda, float *dscale, double *loss, hipStream_t st);
+int launch_adam(const splat_adam_group *groups, int n_groups, double beta1, double beta2, double eps, float *step,
+                hipStream_t st);
 size_t dssim_ws_bytes(int64_t n_views, int32_t width, int32_t height, int32_t roi_y0);
 size_t ngp_ws_bytes(int64_t n);
 int launch_ngp_fwd(const splat_ngp &m, const float *mean, int64_t n, float *quat, float *scale, float *opac,

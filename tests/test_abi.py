@@ -234,3 +234,22 @@ def test_header_is_plain_c99(tmp_path):
     r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", f"-I{inc}",
                         str(src)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_adam_step_rejects_bad_groups_without_a_device():
+    L = B.lib()
+    g = (B.splat_adam_group * 2)()
+    for a in g:
+        a.n, a.act = 4, B.ACT_IDENTITY
+        a.param = a.exp_avg = a.exp_avg_sq = a.grad = a.lr = C.c_void_p(16)
+    step = C.c_void_p(16)
+    assert L.splat_adam_step(None, 1, 0.9, 0.999, 1e-15, step, None) == -1
+    assert L.splat_adam_step(g, 0, 0.9, 0.999, 1e-15, step, None) == -1
+    assert L.splat_adam_step(g, B.ADAM_MAX_GROUPS + 1, 0.9, 0.999, 1e-15, step, None) == -1
+    assert L.splat_adam_step(g, 2, 1.0, 0.999, 1e-15, step, None) == -1
+    g[1].act = B.ACT_SIGMOID  # needs the value array
+    assert L.splat_adam_step(g, 2, 0.9, 0.999, 1e-15, step, None) == -1
+    assert b"NULL" in L.splat_last_error()
+    g[1].act = 7
+    assert L.splat_adam_step(g, 2, 0.9, 0.999, 1e-15, step, None) == -1
+    assert b"activation" in L.splat_last_error()

@@ -7,6 +7,7 @@ import torch
 
 import synth
 from paper_2403_11577_amd import autotune as at
+from paper_2403_11577_amd import binding as B
 from paper_2403_11577_amd import calib as cb
 from paper_2403_11577_amd import pipeline as pl
 
@@ -132,3 +133,38 @@ def test_calibration_retunes_its_tile_shape():
         assert t["tile"] in t["ms"] and set(t["ms"]) == {"16x16", "8x8", "16x16+join", "8x8+join"}
         assert t["ms"][t["tile"]] == min(t["ms"].values())
     assert math.isfinite(res["loss"])
+
+
+def test_native_adam_step_matches_torch_adam():
+    """splat_adam_step against torch.optim.Adam on the raw parameters, with the activation's
+    derivative applied to the gradient of the activated value, over four steps."""
+    say("case: native Adam step")
+    g = torch.Generator(device="cpu").manual_seed(3)
+    sizes, acts, lrs = (1000, 777, 513), (B.ACT_IDENTITY, B.ACT_SIGMOID, B.ACT_EXP), (2.5e-3, 5e-2, 5e-3)
+    raw = [torch.randn(n, generator=g).cuda() for n in sizes]
+    ref = [r.clone().requires_grad_(True) for r in raw]
+    opt = torch.optim.Adam([dict(params=[r], lr=lr) for r, lr in zip(ref, lrs)], eps=1e-15)
+    act = lambda a, x: x if a == B.ACT_IDENTITY else (torch.sigmoid(x) if a == B.ACT_SIGMOID else torch.exp(x))
+    mine = [r.clone() for r in raw]
+    m = [torch.zeros_like(r) for r in raw]
+    v = [torch.zeros_like(r) for r in raw]
+    vals = [act(a, r).contiguous() for a, r in zip(acts, mine)]
+    grads = [torch.zeros_like(r) for r in raw]
+    lr_t = [torch.tensor([lr], device="cuda") for lr in lrs]
+    step = torch.zeros(1, device="cuda")
+    for k in range(4):
+        dval = [torch.randn(n, generator=g).cuda() for n in sizes]
+        for gr, d in zip(grads, dval):
+            gr.copy_(d)
+        B.splat_adam_step([(p, mm, vv, gr, None if a == B.ACT_IDENTITY else val, lr, a)
+                           for p, mm, vv, gr, val, lr, a in zip(mine, m, v, grads, vals, lr_t, acts)], step)
+        opt.zero_grad()
+        loss = sum((act(a, r) * d).sum() for a, r, d in zip(acts, ref, dval))
+        loss.backward()
+        opt.step()
+        torch.cuda.synchronize()
+        assert float(step) == k + 1
+        for a, p, r, val, gr in zip(acts, mine, ref, vals, grads):
+            np.testing.assert_allclose(p.cpu().numpy(), r.detach().cpu().numpy(), rtol=2e-5, atol=2e-6)
+            np.testing.assert_allclose(val.cpu().numpy(), act(a, p).cpu().numpy(), rtol=1e-6, atol=1e-7)
+            assert torch.count_nonzero(gr) == 0
