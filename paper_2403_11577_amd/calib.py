@@ -203,7 +203,9 @@ class Calibrator:
             raw = (self.color, self.logit_o, self.log_s, self.quat)
             self._nat_m = [torch.zeros_like(t) for t in raw]
             self._nat_v = [torch.zeros_like(t) for t in raw]
-            self._nat_lr = [torch.tensor([lr0], dtype=torch.float32, device=device) for lr0 in self.base_lr[0]]
+            self._nat_lr0 = torch.tensor(self.base_lr[0], dtype=torch.float32, device=device)
+            self._nat_lr_all = self._nat_lr0.clone()
+            self._nat_lr = [self._nat_lr_all[i:i + 1] for i in range(len(self.base_lr[0]))]
             self._nat_step = torch.zeros(1, dtype=torch.float32, device=device)
             with torch.no_grad():
                 torch.sigmoid(self.logit_o, out=self.win.opacity)
@@ -372,14 +374,15 @@ class Calibrator:
         self._idx.copy_(self._next_views())
         frac = 1.0 - (1.0 - cfg.final_lr_frac) * min(1.0, k / max(1, cfg.steps - 1))
         for opt, lrs in zip((self.opt_g, self.opt_c), self.base_lr):
+            if opt is self.opt_g and self._native:
+                continue  # the fused step reads its own rates
             for grp, lr0 in zip(opt.param_groups, lrs):
                 if cfg.graph:
                     grp["lr"].fill_(lr0 * frac)
                 else:
                     grp["lr"] = lr0 * frac
         if self._native:
-            for t, lr0 in zip(self._nat_lr, self.base_lr[0]):
-                t.fill_(lr0 * frac)
+            torch.mul(self._nat_lr0, frac, out=self._nat_lr_all)  # all four rates in one kernel
         if self._next_tune is not None and k >= self._next_tune and not self._trial:
             # three steps per candidate; the first one of each may include a graph capture
             self._trial = [ci for ci in range(len(self._cands)) for _ in range(3)]
