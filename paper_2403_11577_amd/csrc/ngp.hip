@@ -139,11 +139,22 @@ __device__ __forceinline__ void scatter2(float *tab, uint32_t r, float a0, float
     }
 }
 
-// Row layout of the stored activations and deltas (floats per Gaussian).
-// R_O: the 11 outputs before the heads, R_MASK: the two ReLU masks (64-bit each, as floats).
+// Stored activations and deltas, R_LEN values per Gaussian, kept feature-major: value f of
+// Gaussian i at rows[f * ld + i] (ld = row_ld(n) >= n + 1, column n is the scratch of lanes
+// past the end), so that a thread writing its Gaussian's values makes coalesced stores
+// across the wave.  R_O: the 11 outputs before the heads, R_MASK: the two ReLU masks
+// (64-bit each, as floats).
 enum { R_DOUT = 0, R_H2 = 12, R_DH2 = R_H2 + NH, R_H1 = R_DH2 + NH, R_DH1 = R_H1 + NH, R_ENC = R_DH1 + NH,
        R_DE = R_ENC + ND, R_O = R_DE + ND, R_MASK = R_O + 12, R_LEN = R_MASK + 4 };
-static_assert(R_LEN % 4 == 0, "rows are read as float4");
+
+__host__ __device__ inline int64_t row_ld(int64_t n) { return (n + 64) & ~(int64_t)63; }
+
+// the values of one Gaussian (one column of the feature-major store)
+struct RowRef {
+    float *p;
+    int64_t ld;
+    __device__ float &operator[](int f) const { return p[(int64_t)f * ld]; }
+};
 
 struct Weights {
     float w1[NH][ND], b1[NH], w2[NH][NH], b2[NH], w3[NO][NH], b3[NO];
@@ -171,7 +182,7 @@ __device__ inline void load_weights(Weights &W, const float *w1, const float *b1
 // ReLU masks.
 template <bool ROW>
 __device__ __forceinline__ void field(const NgpArgs &a, const float2 *tables, const Weights &W, const double *xn,
-                                      float *o, float *row, uint64_t &m1, uint64_t &m2) {
+                                      float *o, RowRef row, uint64_t &m1, uint64_t &m2) {
     float h1[NH];
 #pragma unroll
     for (int j = 0; j < NH; ++j) h1[j] = W.b1[j];
@@ -232,13 +243,15 @@ __global__ __launch_bounds__(256, 2) void ngp_fwd_kernel(NgpArgs a, const float 
         normalise(a, mean, n, i, xn);
         float o[NO];
         uint64_t m1 = 0, m2 = 0;
-        float *row = SAVE ? rows + i * R_LEN : nullptr;
+        const RowRef row{SAVE ? rows + i : nullptr, row_ld(n)};
         field<SAVE>(a, tables, W, xn, o, row, m1, m2);
         if (SAVE) {
 #pragma unroll
             for (int k = 0; k < 12; ++k) row[R_O + k] = k < NO ? o[k] : 0.f;
-            *reinterpret_cast<uint4 *>(row + R_MASK) =
-                make_uint4((uint32_t)m1, (uint32_t)(m1 >> 32), (uint32_t)m2, (uint32_t)(m2 >> 32));
+            row[R_MASK + 0] = __uint_as_float((uint32_t)m1);
+            row[R_MASK + 1] = __uint_as_float((uint32_t)(m1 >> 32));
+            row[R_MASK + 2] = __uint_as_float((uint32_t)m2);
+            row[R_MASK + 3] = __uint_as_float((uint32_t)(m2 >> 32));
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) color[c * n + i] = sigm(o[c]);
@@ -271,17 +284,17 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
         const bool live = i0 < n;
         const int64_t i = live ? i0 : n - 1;
         double xn[3];
-        float *row = rows + (live ? i : n) * R_LEN;  // row n: scratch of the lanes past the end
+        const int64_t ld = row_ld(n);
+        const RowRef row{rows + (live ? i : n), ld};  // column n: scratch of the lanes past the end
         float o[NO];
         uint64_t m1 = 0, m2 = 0;  // ReLU masks of the two hidden layers
         if (MODE == 2) {
-            // the training forward's values (row i also for the lanes past the end: their gradient is 0)
-            const float *src = rows + i * R_LEN;
+            // the training forward's values (column i also for the lanes past the end: their gradient is 0)
+            const RowRef src{rows + i, ld};
 #pragma unroll
             for (int k = 0; k < NO; ++k) o[k] = src[R_O + k];
-            uint4 mk = *reinterpret_cast<const uint4 *>(src + R_MASK);
-            m1 = (uint64_t)mk.x | ((uint64_t)mk.y << 32);
-            m2 = (uint64_t)mk.z | ((uint64_t)mk.w << 32);
+            m1 = (uint64_t)__float_as_uint(src[R_MASK + 0]) | ((uint64_t)__float_as_uint(src[R_MASK + 1]) << 32);
+            m2 = (uint64_t)__float_as_uint(src[R_MASK + 2]) | ((uint64_t)__float_as_uint(src[R_MASK + 3]) << 32);
         } else {
             // forward again; activations go to the row store at once
             normalise(a, mean, n, i, xn);
@@ -366,96 +379,121 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
     }
 }
 
-// C[MA][NB] = sum_r A_r[i] B_r[j] and s[MA] = sum_r A_r[i] over the rows r of a chunk
-// range, A_r = rows[r*R_LEN + aoff .. + MA), B_r = rows[r*R_LEN + boff .. + NB).  Each
-// workgroup sums its own range: rows are staged 32 at a time in LDS, every thread keeps a
-// 4 x 4 block of C in registers (two 16-byte LDS reads per 16 FMAs), and when C has fewer
-// than 256 such blocks the rows are split between thread groups whose sums are added in a
-// fixed order at the end.  The column sums s come from the threads that load A.
-constexpr int ATB_AR = 32;
+// C[MA][NB] = sum_r A_r[i] B_r[j] and s[MA] = sum_r A_r[i] over the Gaussians r of a chunk
+// range, A_r[i] = rows[(aoff + i) * ld + r], B_r[j] = rows[(boff + j) * ld + r].  Each
+// workgroup sums its own range (a multiple of 4 Gaussians long, so every 16-byte load is
+// aligned): 64 Gaussians at a time are staged in LDS, feature-major as in memory, with
+// 16-byte loads of 4 consecutive Gaussians.  A thread keeps a 4 x 4 block of C in
+// registers, features ti + TI i of A and tj + TJ j of B (so the 16-byte LDS reads of
+// neighbouring threads land in different banks), and takes 4 Gaussians per step: eight
+// 16-byte reads per 64 FMAs.  The column sums of A are kept by the loading threads, whose
+// features and Gaussian offsets are the same in every batch.  When C has fewer than 256 such
+// blocks the Gaussians are split between thread groups whose sums are added in a fixed
+// order at the end.
+constexpr int ATB_AR = 64;
 
 template <int MA, int NB>
 __global__ __launch_bounds__(256) void atb_kernel(const float *rows, int64_t n, int aoff, int boff, float *partial) {
     constexpr int TI = MA / 4, TJ = NB / 4, TT = TI * TJ, RS = 256 / TT;
-    constexpr int NA = ATB_AR * TI, NBV = ATB_AR * TJ;  // float4 loads per stage
-    // a thread always loads the same A column (t mod TI), which the column sums rely on
-    static_assert(MA % 4 == 0 && NB % 4 == 0 && TT <= 256 && (NA <= 256 || 256 % TI == 0), "atb tile shape");
-    __shared__ float4 sa[ATB_AR][TI], sb[ATB_AR][TJ];
+    constexpr int KQ = ATB_AR / 4;                   // 16-byte quads per feature and batch
+    constexpr int SR = ATB_AR + 4;                   // padded LDS feature row (floats)
+    constexpr int LA = (MA * KQ + 255) / 256;        // A quads each thread loads per batch
+    constexpr int LB = (NB * KQ + 255) / 256;
+    static_assert(MA % 4 == 0 && NB % 4 == 0 && TT <= 256 && 256 % KQ == 0, "atb tile shape");
+    __shared__ __align__(16) float sa[MA * SR], sb[NB * SR];
     __shared__ float red[RS > 1 ? 256 * 16 : 1];
-    __shared__ float4 bred[256];
     const int t = threadIdx.x;
     const int q = t / TT, tt = t - q * TT, ti = tt / TJ, tj = tt - ti * TJ;
+    const int lk = t % KQ, lf = t / KQ;  // loader: quad lk of features lf + (256 / KQ) m
+    const int64_t ld = row_ld(n);
     float acc[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) acc[k] = 0.f;
-    float4 bs = make_float4(0.f, 0.f, 0.f, 0.f);  // column sums of the A values this thread loads
-    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    float cs[LA];
+#pragma unroll
+    for (int m = 0; m < LA; ++m) cs[m] = 0.f;
+    const int64_t per = ((n + gridDim.x - 1) / gridDim.x + 3) & ~(int64_t)3;
     const int64_t r0 = (int64_t)blockIdx.x * per, r1 = r0 + per < n ? r0 + per : n;
     for (int64_t base = r0; base < r1; base += ATB_AR) {
         const int cnt = (int)(r1 - base < ATB_AR ? r1 - base : ATB_AR);
-        for (int i = t; i < NA; i += 256) {
-            int r = i / TI, c = i - r * TI;
-            float4 v = r < cnt ? *reinterpret_cast<const float4 *>(rows + (base + r) * R_LEN + aoff + 4 * c)
-                               : make_float4(0.f, 0.f, 0.f, 0.f);
-            sa[r][c] = v;
-            bs.x += v.x;
-            bs.y += v.y;
-            bs.z += v.z;
-            bs.w += v.w;
+        const int r = 4 * lk;
+        // a quad that starts at or past cnt is not loaded; one that straddles it is masked
+        auto quad = [&](int f) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < cnt) {
+                v = *reinterpret_cast<const float4 *>(rows + (int64_t)f * ld + base + r);
+                if (r + 1 >= cnt) v.y = 0.f;
+                if (r + 2 >= cnt) v.z = 0.f;
+                if (r + 3 >= cnt) v.w = 0.f;
+            }
+            return v;
+        };
+#pragma unroll
+        for (int m = 0; m < LA; ++m) {
+            const int f = lf + (256 / KQ) * m;
+            if (f < MA) {
+                const float4 v = quad(aoff + f);
+                cs[m] += (v.x + v.y) + (v.z + v.w);
+                *reinterpret_cast<float4 *>(sa + f * SR + r) = v;
+            }
         }
-        for (int i = t; i < NBV; i += 256) {
-            int r = i / TJ, c = i - r * TJ;
-            sb[r][c] = r < cnt ? *reinterpret_cast<const float4 *>(rows + (base + r) * R_LEN + boff + 4 * c)
-                               : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int m = 0; m < LB; ++m) {
+            const int f = lf + (256 / KQ) * m;
+            if (f < NB) *reinterpret_cast<float4 *>(sb + f * SR + r) = quad(boff + f);
         }
         __syncthreads();
         if (q < RS) {
-#pragma unroll 4
-            for (int r = q; r < ATB_AR; r += RS) {
-                const float4 a = sa[r][ti], bv = sb[r][tj];
-                const float av[4] = {a.x, a.y, a.z, a.w}, bw[4] = {bv.x, bv.y, bv.z, bv.w};
+#pragma unroll 2
+            for (int k = q; k < KQ; k += RS) {
+                float4 a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const float4 *>(sa + (ti + TI * i) * SR + 4 * k);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const float4 *>(sb + (tj + TJ * j) * SR + 4 * k);
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[4 * i + j] = __fmaf_rn(av[i], bw[j], acc[4 * i + j]);
+                    for (int j = 0; j < 4; ++j) {
+                        float s = acc[4 * i + j];
+                        s = __fmaf_rn(a[i].x, b[j].x, s);
+                        s = __fmaf_rn(a[i].y, b[j].y, s);
+                        s = __fmaf_rn(a[i].z, b[j].z, s);
+                        acc[4 * i + j] = __fmaf_rn(a[i].w, b[j].w, s);
+                    }
             }
         }
         __syncthreads();
     }
     constexpr int NE = MA * NB + MA;
     float *out = partial + (int64_t)blockIdx.x * NE;
+    // column sums: the KQ loaders of a feature are consecutive lanes of one wave
+#pragma unroll
+    for (int m = 0; m < LA; ++m) {
+        float s = cs[m];
+#pragma unroll
+        for (int o = KQ / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, KQ);
+        const int f = lf + (256 / KQ) * m;
+        if (lk == 0 && f < MA) out[MA * NB + f] = s;
+    }
     // row groups, added in order
     if (RS > 1) {
-        if (q < RS && q > 0)
+        if (q < RS && q > 0) {
 #pragma unroll
             for (int k = 0; k < 16; ++k) red[(q * TT + tt) * 16 + k] = acc[k];
+        }
         __syncthreads();
         if (q == 0)
-            for (int g = 1; g < RS; ++g)
+            for (int g = 1; g < RS; ++g) {
 #pragma unroll
                 for (int k = 0; k < 16; ++k) acc[k] += red[(g * TT + tt) * 16 + k];
+            }
     }
-    if (q == 0)
+    if (q == 0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) out[(4 * ti + i) * NB + 4 * tj + j] = acc[4 * i + j];
-    // column sums: thread t loaded column t mod TI of every row it staged
-    bred[t] = bs;
-    __syncthreads();
-    if (t < TI) {
-        float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int u = t; u < 256; u += TI) {
-            float4 v = bred[u];
-            s4.x += v.x;
-            s4.y += v.y;
-            s4.z += v.z;
-            s4.w += v.w;
-        }
-        out[MA * NB + 4 * t] = s4.x;
-        out[MA * NB + 4 * t + 1] = s4.y;
-        out[MA * NB + 4 * t + 2] = s4.z;
-        out[MA * NB + 4 * t + 3] = s4.w;
+            for (int j = 0; j < 4; ++j) out[(ti + TI * i) * NB + tj + TJ * j] = acc[4 * i + j];
     }
 }
 
@@ -775,7 +813,7 @@ WsLayout ws_layout(int64_t n) {
     WsLayout W;
     int64_t ntiles = (int64_t)NL * ((8 * n + GT_TILE - 1) / GT_TILE);
     size_t o = 0;
-    W.rows = o; o = al256(o + (size_t)(n + 1) * R_LEN * sizeof(float));
+    W.rows = o; o = al256(o + (size_t)row_ld(n) * R_LEN * sizeof(float));
     W.partial = o; o = al256(o + (size_t)ATB_GROUPS * (NH * NH + NH) * sizeof(float));
     W.dec = o; o = al256(o + (size_t)NL * n * sizeof(float2));
     W.carry_head = o; o = al256(o + (size_t)ntiles * sizeof(double2));
