@@ -220,6 +220,8 @@ constexpr uint32_t kDigitMask = (uint32_t)kRadixDigits - 1u;
 constexpr int RS_DPT = kRadixDigits / RS_T;  // digits owned per thread
 static_assert(kRadixDigits % RS_T == 0, "digits must be a multiple of the workgroup size");
 
+constexpr int RS_UKPT = 16;  // keys per thread per upsweep round
+
 template <typename K>
 __global__ __launch_bounds__(RS_T) void radix_upsweep_kernel(const K *keys, const uint32_t *counts, int shift,
                                                             int nparts, uint32_t *hist) {
@@ -232,9 +234,17 @@ __global__ __launch_bounds__(RS_T) void radix_upsweep_kernel(const K *keys, cons
     uint32_t n = counts[CNT_INST];
     uint32_t b, e;
     chunk_of(n, nparts, blockIdx.x, b, e);
-    for (uint32_t base = b; base < e; base += RS_T) {
-        uint32_t i = base + threadIdx.x;
-        if (i < e) atomicAdd(&h[w][(uint32_t)(keys[i] >> shift) & kDigitMask], 1u);
+    // RS_UKPT independent coalesced loads per thread are in flight before their counts
+    for (uint32_t base = b; base < e; base += RS_T * RS_UKPT) {
+        K kk[RS_UKPT];
+#pragma unroll
+        for (int k = 0; k < RS_UKPT; ++k) {
+            const uint32_t i = base + k * RS_T + threadIdx.x;
+            kk[k] = i < e ? keys[i] : (K)0;
+        }
+#pragma unroll
+        for (int k = 0; k < RS_UKPT; ++k)
+            if (base + k * RS_T + threadIdx.x < e) atomicAdd(&h[w][(uint32_t)(kk[k] >> shift) & kDigitMask], 1u);
     }
     __syncthreads();
     for (int q = 0; q < RS_DPT; ++q) {
