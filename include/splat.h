@@ -131,7 +131,7 @@ typedef struct splat_plan {
     size_t off_scan;        /* u32[scan partials]                                        */
     size_t off_grad2d;      /* float[slot_cap][9]: d(mu x,y; conic a,b,c; o; r,g,b)       */
     size_t off_visbits;     /* u64[V*n_blocks_proj*4]: visible (view, Gaussian) bit masks  */
-    size_t off_dwpart;      /* f64[V][n_blocks_proj][4][12]: per-wave W2C gradient partials */
+    size_t off_dwpart;      /* f64[V][n_blocks_proj][4][12] per-wave W2C gradient partials, then f64[V][32][12] stage sums */
     size_t off_cam;         /* f64[V][8]: per-view camera constants of the projection       */
     int32_t sorted_buf;     /* which of the two key/value buffers holds the sorted result */
     int32_t radix_bits;     /* digit width of the LSD radix sort (passes = ceil(key bits / radix_bits)) */

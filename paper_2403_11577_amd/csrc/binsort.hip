@@ -407,15 +407,30 @@ __global__ __launch_bounds__(RS_T) void radix_downsweep_kernel(const KI *kin, co
 // -------------------------------------------------------------------------------------
 // tile ranges and the work queue
 // -------------------------------------------------------------------------------------
+// Tile t's instances are [ranges[t].x, ranges[t].y) of the sorted keys.  A thread takes 4
+// consecutive keys and the one on each side (all six loads issued before any store), and
+// writes the bounds of the runs that start or end among its four.
 template <typename K>
-__global__ __launch_bounds__(256) void ranges_kernel(const K *keys, const uint32_t *counts, int depth_bits,
-                                                    uint64_t n_tiles, uint2 *ranges) {
-    uint32_t n = counts[CNT_INST];
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t t = keys[i] >> depth_bits;
-        if (t >= n_tiles) continue;  // cannot happen for emitted keys; keeps the write in bounds
-        if (i == 0 || (keys[i - 1] >> depth_bits) != t) ranges[t].x = (uint32_t)i;
-        if (i + 1 == n || (keys[i + 1] >> depth_bits) != t) ranges[t].y = (uint32_t)(i + 1);
+__global__ __launch_bounds__(256) void ranges_kernel(const K *__restrict__ keys, const uint32_t *counts,
+                                                    int depth_bits, uint64_t n_tiles, uint2 *__restrict__ ranges) {
+    const uint32_t n = counts[CNT_INST];
+    const uint64_t ng = ((uint64_t)n + 3) / 4;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += (uint64_t)gridDim.x * blockDim.x) {
+        const int64_t i0 = 4 * (int64_t)g;
+        uint64_t t[6];  // tiles of keys i0 - 1 .. i0 + 4; all ones outside [0, n)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int64_t i = i0 - 1 + k;
+            t[k] = (i >= 0 && i < (int64_t)n) ? (uint64_t)(keys[i] >> depth_bits) : ~0ull;
+        }
+#pragma unroll
+        for (int k = 1; k <= 4; ++k) {
+            const uint64_t tk = t[k];
+            if (tk >= n_tiles) continue;  // past the end; cannot happen for emitted keys
+            const uint32_t i = (uint32_t)(i0 + k - 1);
+            if (t[k - 1] != tk) ranges[tk].x = i;
+            if (t[k + 1] != tk) ranges[tk].y = i + 1;
+        }
     }
 }
 
@@ -631,7 +646,7 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
     const uint64_t *ki = in1 ? keys1 : keys0;
     // ranges of every (view, tile) and the cost-ordered queue
     if ((rc = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, (int64_t)2 * nT, st))) return rc;
-    int rb = (int)((p.inst_cap + 255) / 256);
+    int rb = (int)((p.inst_cap / 4 + 256) / 256);
     if (rb > 8192) rb = 8192;
     if (kshift >= 0)
         hipLaunchKernelGGL(ranges_kernel<uint32_t>, dim3(rb), dim3(256), 0, st, reinterpret_cast<const uint32_t *>(ki),

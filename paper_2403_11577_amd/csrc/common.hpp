@@ -17,6 +17,7 @@ constexpr int kWave = 64;
 #endif
 constexpr int kRadixBits = SPLAT_RADIX_BITS;
 constexpr int kRadixDigits = 1 << kRadixBits;
+constexpr int kDw2cStages = 32;  // workgroups per view summing the W2C gradient partials
 
 // workspace views --------------------------------------------------------------
 template <typename T>

@@ -499,14 +499,19 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
         for (int k = 0; k < 3; ++k) dmean[k * n + i] += (float)gm[k];
 }
 
-// dw2c[v] += sum over the (block, wave) partials of view v, in a fixed order.
-__global__ __launch_bounds__(256) void dw2c_reduce_kernel(const double *dwpart, int nparts, double *dw2c) {
+// dw2c[v] += sum over the (block, wave) partials of view v, in a fixed order, in two
+// stages: workgroup (s, v) sums the partials q = t + 256 (s + DW_S j) of view v (thread t,
+// j = 0, 1, ...) into stage[v][s], then dw2c_finish_kernel adds the DW_S stage sums of a
+// view in order.  DW_S workgroups per view keep the whole chip reading.
+constexpr int DW_S = kDw2cStages;
+
+__global__ __launch_bounds__(256) void dw2c_reduce_kernel(const double *dwpart, int nparts, double *stage) {
     __shared__ double red[4][12];
-    const int v = blockIdx.x, wv = threadIdx.x >> 6, lane = __lane_id();
+    const int s = blockIdx.x, v = blockIdx.y, wv = threadIdx.x >> 6, lane = __lane_id();
     const LaneClass lc(lane);
     double acc[12];
     for (int k = 0; k < 12; ++k) acc[k] = 0.0;
-    for (int q = threadIdx.x; q < nparts; q += 256) {
+    for (int q = threadIdx.x + 256 * s; q < nparts; q += 256 * DW_S) {
         const double *p = dwpart + ((size_t)v * nparts + q) * 12;
         for (int k = 0; k < 12; ++k) acc[k] += p[k];
     }
@@ -515,8 +520,16 @@ __global__ __launch_bounds__(256) void dw2c_reduce_kernel(const double *dwpart, 
     __syncthreads();
     if (threadIdx.x < 12) {
         int k = threadIdx.x;
-        dw2c[12 * v + k] += ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+        stage[((size_t)v * DW_S + s) * 12 + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
     }
+}
+
+__global__ void dw2c_finish_kernel(const double *stage, double *dw2c) {
+    const int v = blockIdx.x, k = threadIdx.x;
+    if (k >= 12) return;
+    double t = 0.0;
+    for (int s = 0; s < DW_S; ++s) t += stage[((size_t)v * DW_S + s) * 12 + k];
+    dw2c[12 * v + k] += t;
 }
 
 }  // namespace
@@ -574,8 +587,12 @@ int launch_project_bwd(const splat_plan &p, void *ws, const splat_gaussians &g, 
                        p.slot_cap, ws_at<float>(ws, p.off_grad2d), dquat, dscale, dopac, dcolor, dmean, part);
     int rc = launch_status("project_bwd");
     if (rc) return rc;
-    hipLaunchKernelGGL(dw2c_reduce_kernel, dim3(p.n_views), dim3(256), 0, st, part, 4 * nb, dw2c);
-    return launch_status("dw2c_reduce");
+    // the stage sums sit after the partials (the plan sizes the region for both)
+    double *stage = part + (size_t)p.n_views * 4 * nb * 12;
+    hipLaunchKernelGGL(dw2c_reduce_kernel, dim3(DW_S, p.n_views), dim3(256), 0, st, part, 4 * nb, stage);
+    if ((rc = launch_status("dw2c_reduce"))) return rc;
+    hipLaunchKernelGGL(dw2c_finish_kernel, dim3(p.n_views), dim3(64), 0, st, stage, dw2c);
+    return launch_status("dw2c_finish");
 }
 
 }  // namespace splat
