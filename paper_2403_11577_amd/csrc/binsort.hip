@@ -168,9 +168,11 @@ __global__ void inst_finish_kernel(const uint32_t *offs, int64_t inst_cap, uint3
     atomicOr(status, SPLAT_ST_CAPACITY);
 }
 
-__global__ __launch_bounds__(256) void emit_kernel(const uint32_t *counts, const uint32_t *offs, const Rect16 *rect,
-                                                  const uint32_t *dkeys, const int2 *meta, int tiles_x, int T,
-                                                  int depth_bits, uint64_t *keys, uint32_t *vals) {
+__global__ __launch_bounds__(256) void emit_kernel(const uint32_t *__restrict__ counts,
+                                                  const uint32_t *__restrict__ offs, const Rect16 *__restrict__ rect,
+                                                  const uint32_t *__restrict__ dkeys, const int2 *__restrict__ meta,
+                                                  int tiles_x, int T, int depth_bits, uint64_t *__restrict__ keys,
+                                                  uint32_t *__restrict__ vals) {
     uint32_t ns = counts[CNT_SLOTS];
     uint32_t ni = counts[CNT_INST];  // <= capacity; only slots wholly below it emit
     for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < ns;
@@ -626,8 +628,8 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
     if (rc) return rc;
     hipLaunchKernelGGL(inst_finish_kernel, dim3(1), dim3(64), 0, st, ntiles, p.inst_cap, counts, status);
     if ((rc = launch_status("inst_finish"))) return rc;
-    int eb = (int)((p.slot_cap + 255) / 256);
-    if (eb > 8192) eb = 8192;
+    int eb = (int)((p.slot_cap + 255) / 256);  // about one slot per thread
+    if (eb > 65536) eb = 65536;
     hipLaunchKernelGGL(emit_kernel, dim3(eb), dim3(256), 0, st, counts, ntiles, ws_at<Rect16>(ws, p.off_rect),
                        ws_at<uint32_t>(ws, p.off_dkey), ws_at<int2>(ws, p.off_meta), p.tiles_x, p.tiles_per_view,
                        p.depth_bits, keys0, vals0);
