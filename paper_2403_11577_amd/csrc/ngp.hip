@@ -520,7 +520,7 @@ __global__ __launch_bounds__(256) void atb_reduce_kernel(const float *partial, i
     }
 }
 
-constexpr int ATB_GROUPS = 512;
+constexpr int ATB_GROUPS = 1024;
 
 // ---- the inverse index of the table lookups ----
 constexpr int GT_T = 256;               // threads per reduction workgroup
