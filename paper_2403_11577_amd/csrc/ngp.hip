@@ -380,35 +380,37 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
 }
 
 // C[MA][NB] = sum_r A_r[i] B_r[j] and s[MA] = sum_r A_r[i] over the Gaussians r of a chunk
-// range, A_r[i] = rows[(aoff + i) * ld + r], B_r[j] = rows[(boff + j) * ld + r].  Each
-// workgroup sums its own range (a multiple of 4 Gaussians long, so every 16-byte load is
-// aligned): 64 Gaussians at a time are staged in LDS, feature-major as in memory, with
-// 16-byte loads of 4 consecutive Gaussians.  A thread keeps a 4 x 4 block of C in
-// registers, features ti + TI i of A and tj + TJ j of B (so the 16-byte LDS reads of
-// neighbouring threads land in different banks), and takes 4 Gaussians per step: eight
-// 16-byte reads per 64 FMAs.  The column sums of A are kept by the loading threads, whose
-// features and Gaussian offsets are the same in every batch.  When C has fewer than 256 such
-// blocks the Gaussians are split between thread groups whose sums are added in a fixed
-// order at the end.
+// range, A_r[i] = rows[(aoff + i) * ld + r], B_r[j] = rows[(boff + j) * ld + r]: a dense
+// contraction over the Gaussians, run on the matrix cores (v_mfma_f32_16x16x4f32, FP32
+// products and sums).  Each workgroup sums its own range (a multiple of 4 Gaussians long, so
+// every 16-byte load is aligned): 64 Gaussians at a time are staged in LDS, feature-major as
+// in memory, with 16-byte loads of 4 consecutive Gaussians.  C is cut into 16 x 16 tiles
+// (A's rows padded to a multiple of 16 with zeros), each owned by one wave; per step a lane
+// reads the 4 Gaussians (4 (lane / 16) + 0..3 of a group of 16) of its A row lane % 16 and
+// B column lane % 16 with one 16-byte LDS read each, and four MFMAs take them as the k
+// index.  The column sums of A are kept by the loading threads, whose features and Gaussian
+// offsets are the same in every batch.
 constexpr int ATB_AR = 64;
+
+typedef float atb_f4 __attribute__((ext_vector_type(4)));
 
 template <int MA, int NB>
 __global__ __launch_bounds__(256) void atb_kernel(const float *rows, int64_t n, int aoff, int boff, float *partial) {
-    constexpr int TI = MA / 4, TJ = NB / 4, TT = TI * TJ, RS = 256 / TT;
-    constexpr int KQ = ATB_AR / 4;                   // 16-byte quads per feature and batch
-    constexpr int SR = ATB_AR + 4;                   // padded LDS feature row (floats)
-    constexpr int LA = (MA * KQ + 255) / 256;        // A quads each thread loads per batch
+    constexpr int MP = (MA + 15) / 16 * 16;       // A rows padded to whole tiles
+    constexpr int TI = MP / 16, TJ = NB / 16;      // tiles of C
+    constexpr int TPW = TI * TJ / 4;               // tiles per wave
+    constexpr int KQ = ATB_AR / 4;                 // 16-byte quads per feature and batch
+    constexpr int SR = ATB_AR + 4;                 // padded LDS feature row (floats)
+    constexpr int LA = (MA * KQ + 255) / 256;      // A quads each thread loads per batch
     constexpr int LB = (NB * KQ + 255) / 256;
-    static_assert(MA % 4 == 0 && NB % 4 == 0 && TT <= 256 && 256 % KQ == 0, "atb tile shape");
+    static_assert(NB % 16 == 0 && (TI * TJ) % 4 == 0 && 256 % KQ == 0 && ATB_AR % 16 == 0, "atb tile shape");
     __shared__ __align__(16) float sa[MA * SR], sb[NB * SR];
-    __shared__ float red[RS > 1 ? 256 * 16 : 1];
-    const int t = threadIdx.x;
-    const int q = t / TT, tt = t - q * TT, ti = tt / TJ, tj = tt - ti * TJ;
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int lk = t % KQ, lf = t / KQ;  // loader: quad lk of features lf + (256 / KQ) m
     const int64_t ld = row_ld(n);
-    float acc[16];
+    atb_f4 acc[TPW];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+    for (int u = 0; u < TPW; ++u) acc[u] = atb_f4{0.f, 0.f, 0.f, 0.f};
     float cs[LA];
 #pragma unroll
     for (int m = 0; m < LA; ++m) cs[m] = 0.f;
@@ -417,7 +419,7 @@ __global__ __launch_bounds__(256) void atb_kernel(const float *rows, int64_t n, 
     for (int64_t base = r0; base < r1; base += ATB_AR) {
         const int cnt = (int)(r1 - base < ATB_AR ? r1 - base : ATB_AR);
         const int r = 4 * lk;
-        // a quad that starts at or past cnt is not loaded; one that straddles it is masked
+        // a quad that starts at or past cnt is zero; one that straddles it is masked
         auto quad = [&](int f) {
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
             if (r < cnt) {
@@ -443,24 +445,20 @@ __global__ __launch_bounds__(256) void atb_kernel(const float *rows, int64_t n, 
             if (f < NB) *reinterpret_cast<float4 *>(sb + f * SR + r) = quad(boff + f);
         }
         __syncthreads();
-        if (q < RS) {
-#pragma unroll 2
-            for (int k = q; k < KQ; k += RS) {
-                float4 a[4], b[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const float4 *>(sa + (ti + TI * i) * SR + 4 * k);
+        for (int kg = 0; kg < ATB_AR / 16; ++kg) {
+            const int gr = kg * 16 + 4 * (lane >> 4);  // this lane's 4 Gaussians of the group
 #pragma unroll
-                for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const float4 *>(sb + (tj + TJ * j) * SR + 4 * k);
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        float s = acc[4 * i + j];
-                        s = __fmaf_rn(a[i].x, b[j].x, s);
-                        s = __fmaf_rn(a[i].y, b[j].y, s);
-                        s = __fmaf_rn(a[i].z, b[j].z, s);
-                        acc[4 * i + j] = __fmaf_rn(a[i].w, b[j].w, s);
-                    }
+            for (int u = 0; u < TPW; ++u) {
+                const int tile = w * TPW + u, ti = tile / TJ, tj = tile - ti * TJ;
+                const int fa = ti * 16 + (lane & 15), fb = tj * 16 + (lane & 15);
+                float4 av = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (MP == MA || fa < MA) av = *reinterpret_cast<const float4 *>(sa + fa * SR + gr);
+                const float4 bv = *reinterpret_cast<const float4 *>(sb + fb * SR + gr);
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc[u], 0, 0, 0);
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc[u], 0, 0, 0);
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, acc[u], 0, 0, 0);
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, acc[u], 0, 0, 0);
             }
         }
         __syncthreads();
@@ -476,24 +474,16 @@ __global__ __launch_bounds__(256) void atb_kernel(const float *rows, int64_t n, 
         const int f = lf + (256 / KQ) * m;
         if (lk == 0 && f < MA) out[MA * NB + f] = s;
     }
-    // row groups, added in order
-    if (RS > 1) {
-        if (q < RS && q > 0) {
+    // accumulator element i of a lane is C[16 ti + 4 (lane / 16) + i][16 tj + lane % 16]
 #pragma unroll
-            for (int k = 0; k < 16; ++k) red[(q * TT + tt) * 16 + k] = acc[k];
+    for (int u = 0; u < TPW; ++u) {
+        const int tile = w * TPW + u, ti = tile / TJ, tj = tile - ti * TJ;
+        const int col = tj * 16 + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = ti * 16 + 4 * (lane >> 4) + i;
+            if (MP == MA || row < MA) out[row * NB + col] = acc[u][i];
         }
-        __syncthreads();
-        if (q == 0)
-            for (int g = 1; g < RS; ++g) {
-#pragma unroll
-                for (int k = 0; k < 16; ++k) acc[k] += red[(g * TT + tt) * 16 + k];
-            }
-    }
-    if (q == 0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) out[(ti + TI * i) * NB + tj + TJ * j] = acc[4 * i + j];
     }
 }
 
