@@ -488,16 +488,24 @@ __global__ __launch_bounds__(256) void atb_kernel(const float *rows, int64_t n, 
 }
 
 // out[e] += sum over workgroups of partial[g][e], in float64 and a fixed order (four
-// interleaved sums added in order); e < ma*nb is (i, j) of dw (i < mreal, j < din_w), the
-// rest db[i] (i < mreal)
+// interleaved sums of eight interleaved sums each, added in order); e < ma*nb is (i, j)
+// of dw (i < mreal, j < din_w), the rest db[i] (i < mreal)
 __global__ __launch_bounds__(256) void atb_reduce_kernel(const float *partial, int ngroups, int ma, int nb, int mreal,
                                                         int din_w, float *dw, float *db) {
     __shared__ double part[4][64];
     const int ne = ma * nb + ma;
     const int e = blockIdx.x * 64 + (threadIdx.x & 63), qg = threadIdx.x >> 6;
     double s = 0.0;
-    if (e < ne)
-        for (int g = qg; g < ngroups; g += 4) s += (double)partial[(int64_t)g * ne + e];
+    if (e < ne) {
+        // eight sums over every 32nd workgroup keep eight loads in flight; fixed order throughout
+        double t[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int g = qg;
+        for (; g + 28 < ngroups; g += 32)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] += (double)partial[(int64_t)(g + 4 * u) * ne + e];
+        for (; g < ngroups; g += 4) t[0] += (double)partial[(int64_t)g * ne + e];
+        s = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+    }
     part[qg][threadIdx.x & 63] = s;
     __syncthreads();
     if (qg != 0 || e >= ne) return;
