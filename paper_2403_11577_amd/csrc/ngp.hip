@@ -15,7 +15,7 @@
 // through the heads and the MLP, and the per-Gaussian activations and deltas are
 // stored so that the weight gradients -- sums over all Gaussians of outer
 // products, a tall-skinny A^T B -- are formed by atb_kernel (per-workgroup
-// partials in registers, then a fixed-order reduction).  The table gradient of a
+// partials on the matrix cores, then a fixed-order float64 reduction).  The table gradient of a
 // row is the sum, over every (Gaussian, vertex) that looked it up, of the
 // trilinear weight times the Gaussian's encoding gradient.  Two ways to form it:
 //  * scatter: hardware float atomics (16 levels x 8 vertices x 2 features), after

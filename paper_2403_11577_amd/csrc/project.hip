@@ -6,12 +6,14 @@
 // is EWA splatting: 2-D covariance J A A^T J^T + eps2d I under the perspective
 // Jacobian J, its inverse (conic) and the screen-space mean.
 //
-// Layout: one thread per (view, Gaussian) candidate; SoA float32 parameter
-// planes are read coalesced; the arithmetic is float64 (the projection is
-// bandwidth bound, so the float64 rate costs nothing and removes the float32
-// cancellation of thin, elongated footprints).  Visible pairs are compacted per
-// view in Gaussian order by a count pass, a scan and a write pass that both
-// call the same projection function.
+// Layout: one thread per Gaussian, walking every view, so its view-independent
+// part (rotation, footprint radius) is formed once; SoA float32 parameter planes
+// are read coalesced.  The arithmetic is float64: on this chip the float64 vector
+// rate equals the unpacked float32 rate, and float64 removes the float32
+// cancellation of thin, elongated footprints (a float32 pre-cull rejects most
+// invisible pairs first).  Visible pairs are compacted per view in Gaussian order
+// by a count pass, a scan and a write pass that both call the same projection
+// function.
 #include "common.hpp"
 
 namespace splat {
