@@ -423,6 +423,18 @@ def kitti_single(seed=0, n_points=500_000, W=1408, H=376, f=552.0):
                  info={"n_scans": n_scans, "n_boxes": len(boxes)})
 
 
+def anisotropic(scene: Scene, seed=7, jitter=0.3) -> Scene:
+    """The same scene with anisotropic, randomly rotated Gaussians: every scale axis
+    multiplied by exp(N(0, jitter)) and every quaternion replaced by a random unit
+    quaternion (normalised N(0, I4) draw).  Means, opacities and colours are kept."""
+    rng = np.random.default_rng(seed)
+    g = scene.gauss.copy()
+    g.scale = (g.scale.astype(np.float64) * np.exp(rng.normal(0.0, jitter, g.scale.shape))).astype(np.float32)
+    q = rng.normal(size=(4, g.n))
+    g.quat = (q / np.linalg.norm(q, axis=0, keepdims=True)).astype(np.float32)
+    return dataclasses.replace(scene, name=scene.name + "_aniso", gauss=g)
+
+
 def _arc_trajectory(n_knots, dt=0.1, speed=10.0, radius=50.0, t0=0.0, wobble_deg=1.0):
     """Ego on a circular arc at constant speed, sampled at 1/dt Hz, with a small
     pitch/roll wobble so that the interpolated rotations are not single-axis."""
