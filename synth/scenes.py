@@ -33,7 +33,7 @@ __all__ = [
     "Gaussians", "Trajectory", "Rig", "Views", "Scene",
     "tiny_scene", "tiny_target", "kitti_single", "calib16", "batched64",
     "calib_full", "small_drive", "drive_scans", "random_rigid", "perturbation",
-    "quat_from_euler", "WORKLOADS",
+    "quat_from_euler", "anisotropic", "WORKLOADS",
 ]
 
 # workload name of every generator
