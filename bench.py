@@ -9,10 +9,11 @@ backward compositing -> projection adjoint -> pose adjoint, for all 64 views, wi
 inputs resident in HBM.  The targets are the same scene rendered at a slightly
 different calibration, so every covered pixel carries a loss gradient.
 
-Prints ONE JSON line: Mpixels/s (fwd+bwd) of the batched persistent path, with
-the per-view plain launch, the hipGraph replay, the ALU roofline of the dominant
-render kernel (HIP events around its launches in the timed region) and the FP64
-CPU oracle on a one-view sample as context.
+Prints ONE JSON line: Mpixels/s (fwd+bwd) of the batched path, with the per-view
+plain launch (with and without a host synchronisation after every stage), the
+hipGraph replay, the roofline of the dominant render kernel (algorithmic bytes
+and operations over its duration from HIP events in the timed region) and the
+FP64 CPU oracle on bounded samples as context.
 """
 from __future__ import annotations
 
@@ -25,16 +26,20 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# ALU roofline of the render kernels: FP32 flops (FMA = 2, exp2 / rcp / compare = 1) per
-# contributing (pixel, Gaussian) pair -- alpha >= alpha_min before the pixel stops -- the unit
-# of algorithmic work; evaluated pairs that contribute nothing are overhead and only reported.
-#   forward: offset 2, exponent 8, exp2 1, clamp 1, alpha test 1 (13) + weight 1,
-#     transmittance 1, stop test 1, colour 6, last index 1 (10) = 23
-#   backward: the same evaluation 13 + 1 - alpha and its reciprocal 2, T recovery 1, weight 1,
-#     colour gradient 6, dL/dC . c 5, dL/dalpha 3, suffix term 2, dL/dpower 2, moments 12 (35) = 48
-FWD_FLOP_PER_PAIR, BWD_FLOP_PER_PAIR = 23, 48
-# 256 CUs x 64 FP32 lanes x 2 flops (FMA) x 2.4 GHz, without packed-FP32 issue
-ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# Roofline of the render kernels from their algorithmic work, counted in units the
+# instrumented kernel twins report: a contributing (pixel, Gaussian) pair is one with
+# alpha >= alpha_min before the pixel stops.  Operations per contributing pair: forward 15
+# plus one exp; backward 45 plus one exp and one reciprocal.  Bytes that must cross HBM:
+# per instance (Gaussian, tile) its 4-byte slot id and 36-byte record; per pixel 20 bytes
+# (forward: colour, T, last; backward: dL/dC, T, last); per backward atomic group (one
+# (tile, Gaussian) with a contributor) its nine 4-byte gradient sums.  The attainable rate
+# is min(HBM peak x ops/byte, FP32 vector peak); evaluated pairs that contribute nothing
+# are overhead and only reported.
+FWD_OPS_PER_PAIR, BWD_OPS_PER_PAIR = 16, 47
+BYTES_PER_INSTANCE, BYTES_PER_PIXEL, BYTES_PER_ATOMIC_GROUP = 40, 20, 36
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TOPS = 157.3          # published FP32 vector peak
+ISSUE_PEAK_TOPS = 256 * 64 * 2 * 2.4e9 / 1e12   # one wave64 FMA per CU per cycle (no dual issue): 78.6
 # HBM bytes per render_bwd launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "batched64_hbm_traffic.md")
 RENDER_SRC = os.path.join(ROOT, "paper_2403_11577_amd", "csrc", "render.hip")
@@ -166,6 +171,77 @@ def measure_beyond_render(ds, settings, targets, img, reps=10):
     return out
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(scene, vis, small=False):
+    """The FP64 oracle as it stands, on the host cores: forward (pruned by footprint boxes,
+    or brute force over every Gaussian at every pixel) plus the exact adjoint of an L1 loss
+    against a flat grey target, per sample.  Samples: the tiny configuration (2,000 Gaussians,
+    256x64) in both render modes, the 500k-Gaussian single 1408x376 view, and the densest,
+    median and sparsest views of the benchmark drive; each at all host threads of one GPU's
+    share (16) and, where it stays within seconds, on one thread.  The headline value is the
+    median drive view at all threads."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    allc = min(16, os.cpu_count() or 1)
+
+    def leg(name, sc, v, nth, pruned=True):
+        got = oracle.set_num_threads(nth)
+        sub = synth.Views(np.asarray(sc.views.cam)[v:v + 1], np.asarray(sc.views.t)[v:v + 1])
+        w2c, _, _ = oracle.pose(sc.traj, sc.rig, sc.xi, sc.delta, sub)
+        intr = oracle.view_intr(sc.rig, sub)
+        W, H = sc.rig.W, sc.rig.H
+        t0 = time.perf_counter()
+        r = oracle.render(sc.gauss, w2c, intr, W, H, pruned=pruned)
+        t1 = time.perf_counter()
+        _, dimg = oracle.l1_loss(r["img"], np.full_like(r["img"], 0.5))
+        oracle.grad(sc.gauss, w2c, intr, W, H, dimg)
+        t2 = time.perf_counter()
+        out = {"sample": name, "mode": "aabb" if pruned else "brute_force", "threads": got,
+               "gaussians": int(sc.gauss.n), "pixels": W * H, "fwd_s": round(t1 - t0, 3),
+               "bwd_s": round(t2 - t1, 3), "mpx_s": round(W * H / (t2 - t0) / 1e6, 4)}
+        log(f"[bench] cpu oracle {name} {out['mode']} x{got}: {t2 - t0:.2f}s")
+        return out
+
+    legs = []
+    tiny = synth.tiny_scene(0)
+    for nth in (1, allc):
+        legs.append(leg("tiny_2k_256x64", tiny, 0, nth, pruned=False))
+        legs.append(leg("tiny_2k_256x64", tiny, 0, nth))
+    head = None
+    if not small:
+        single = synth.kitti_single(0)
+        legs.append(leg("single_500k_1408x376", single, 0, allc))
+        legs.append(leg("single_500k_1408x376", single, 0, 1))
+        del single
+        order = np.argsort(vis, kind="stable")
+        picks = (("sparsest", int(order[0])), ("median", int(order[len(order) // 2])), ("densest", int(order[-1])))
+        for tag, v in picks:
+            legs.append(leg(f"drive_view{v}_{tag}_{int(vis[v])}visible", scene, v, allc))
+            if tag == "median":
+                head = legs[-1]
+        legs.append(leg(f"drive_view{picks[0][1]}_sparsest_{int(vis[picks[0][1]])}visible", scene, picks[0][1], 1))
+    else:
+        head = legs[-1]
+    oracle.set_num_threads(allc)
+    return {"value": head["mpx_s"], "unit": "Mpixels/s", "cores": head["threads"], "kind": "oracle",
+            "sample": f"{head['sample']} of the benchmark workload, fwd+bwd ({head['mode']}), "
+                      f"{head['fwd_s'] + head['bwd_s']:.1f}s",
+            "cpu_model": _cpu_model(), "cpu_count": os.cpu_count(), "legs": legs,
+            "seconds_total": round(sum(l["fwd_s"] + l["bwd_s"] for l in legs), 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,19 +355,37 @@ def main():
 
     # ---- roofline of the dominant render kernel (pair counts from the instrumented variant) ----
     stt = step.stats()
-    fwd_flop = FWD_FLOP_PER_PAIR * stt["fwd_blend"]
-    bwd_flop = BWD_FLOP_PER_PAIR * stt["bwd_contrib"]
-    if bwd_ms >= fwd_ms:
-        kern, dur_ms, flop = "render_bwd", bwd_ms, bwd_flop
-    else:
-        kern, dur_ms, flop = "render_fwd", fwd_ms, fwd_flop
-    achieved = flop / (dur_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": kern, "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
-                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
-                "traffic": profiled_traffic(kern) if args.tile == "16x16" else None,
-                "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
-                "fwd_tflops": round(fwd_flop / (fwd_ms * 1e-3) / 1e12, 3),
-                "bwd_tflops": round(bwd_flop / (bwd_ms * 1e-3) / 1e12, 3), "pairs": stt}
+    npx = V * W * H
+
+    def kernel_roofline(name, ms, ops, nbytes):
+        ai = ops / nbytes
+        attain_tops = min(HBM_PEAK_GBS * 1e9 * ai / 1e12, VALU_PEAK_TOPS)
+        tops = ops / (ms * 1e-3) / 1e12
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        hbm = HBM_PEAK_GBS * 1e9 * ai / 1e12 < VALU_PEAK_TOPS
+        return {"bound": "hbm" if hbm else "alu", "kernel": name,
+                "achieved": round(gbs if hbm else tops, 3), "peak": HBM_PEAK_GBS if hbm else VALU_PEAK_TOPS,
+                "unit": "GB/s" if hbm else "TFLOP/s", "frac": round(tops / attain_tops, 4),
+                "ms": round(ms, 4), "bytes_alg": int(nbytes), "ops_alg": int(ops), "ai": round(ai, 3),
+                "alu_tops": round(tops, 3), "alu_frac_published": round(tops / VALU_PEAK_TOPS, 4),
+                "alu_frac_issue": round(tops / ISSUE_PEAK_TOPS, 4)}
+
+    fwd_rl = kernel_roofline("render_fwd", fwd_ms, FWD_OPS_PER_PAIR * stt["fwd_blend"],
+                             BYTES_PER_INSTANCE * stt["instances"] + BYTES_PER_PIXEL * npx)
+    bwd_rl = kernel_roofline("render_bwd", bwd_ms, BWD_OPS_PER_PAIR * stt["bwd_contrib"],
+                             BYTES_PER_INSTANCE * stt["instances"] + BYTES_PER_PIXEL * npx
+                             + BYTES_PER_ATOMIC_GROUP * stt["bwd_atomic_groups"])
+    roofline = dict(bwd_rl if bwd_ms >= fwd_ms else fwd_rl)
+    roofline["traffic"] = profiled_traffic(roofline["kernel"]) if args.tile == "16x16" else None
+    roofline["valu_peak_published"] = VALU_PEAK_TOPS
+    roofline["valu_issue_peak"] = round(ISSUE_PEAK_TOPS, 2)
+    roofline["render_fwd"] = fwd_rl
+    roofline["render_bwd"] = bwd_rl
+    roofline["pairs"] = stt
+    roofline["evals_per_contrib"] = {"fwd": round(stt["fwd_eval"] / max(1, stt["fwd_blend"]), 3),
+                                     "bwd": round(stt["bwd_eval"] / max(1, stt["bwd_contrib"]), 3)}
+    log(f"[bench] roofline: fwd frac {fwd_rl['frac']} ({fwd_rl['achieved']} {fwd_rl['unit']}), "
+        f"bwd frac {bwd_rl['frac']} ({bwd_rl['achieved']} {bwd_rl['unit']})")
 
     # ---- hipGraph replay of the same step ----
     graph = None
@@ -321,30 +415,24 @@ def main():
             pv.step(xi, delta, targets, gr)
         torch.cuda.synchronize()
         p_ms = 1e3 * (time.perf_counter() - tp) / args.per_view_steps
-        per_view = {"ms_per_step": round(p_ms, 3), "mpx_s": round(V * W * H / (p_ms * 1e-3) / 1e6, 2)}
-        log(f"[bench] per-view plain: {p_ms:.3f} ms/step")
+        # the same per-view launches back to back: no host synchronisation or count read-back
+        tp = time.perf_counter()
+        for _ in range(args.per_view_steps):
+            pl.zero_grads(gr)
+            pv.step(xi, delta, targets, gr, sync=False)
+        torch.cuda.synchronize()
+        q_ms = 1e3 * (time.perf_counter() - tp) / args.per_view_steps
+        per_view = {"ms_per_step": round(p_ms, 3), "mpx_s": round(V * W * H / (p_ms * 1e-3) / 1e6, 2),
+                    "syncs": "host synchronisation after every stage of every view and two count read-backs "
+                             "per view (after projection and after binning)",
+                    "nosync": {"ms_per_step": round(q_ms, 3), "mpx_s": round(V * W * H / (q_ms * 1e-3) / 1e6, 2)}}
+        log(f"[bench] per-view plain: {p_ms:.3f} ms/step; without host syncs {q_ms:.3f} ms/step")
         del pv
 
-    # ---- FP64 CPU oracle on a bounded sample: the median-visible view, fwd + bwd ----
+    # ---- FP64 CPU oracle on bounded samples (test infrastructure, timed for context only) ----
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        nthreads = min(16, os.cpu_count() or 1)
-        os.environ.setdefault("OMP_NUM_THREADS", str(nthreads))
-        v = int(np.argsort(vis)[len(vis) // 2])
-        sub = synth.Views(scene.views.cam[v:v + 1], scene.views.t[v:v + 1])
-        w2c, _, _ = oracle.pose(scene.traj, scene.rig, np.zeros((2, 6)), np.zeros(2), sub)
-        intr = oracle.view_intr(scene.rig, sub)
-        tc = time.perf_counter()
-        r = oracle.render(scene.gauss, w2c, intr, W, H)
-        tgt = targets[v:v + 1].cpu().numpy().astype(np.float64)
-        _, dimg = oracle.l1_loss(r["img"], tgt)
-        oracle.grad(scene.gauss, w2c, intr, W, H, dimg)
-        tcpu = time.perf_counter() - tc
-        cpu = {"value": round(W * H / tcpu / 1e6, 4), "unit": "Mpixels/s", "cores": oracle.num_threads(),
-               "kind": "oracle", "sample": f"view {v} of {V} (median visible, {int(vis[v])} Gaussians), "
-                                           f"fwd+bwd, {W}x{H}, {tcpu:.1f}s"}
-        log(f"[bench] cpu oracle: {tcpu:.1f}s for one view")
+        cpu = cpu_baseline(scene, vis, small=args.small)
 
     beyond = None
     if not args.no_beyond and not args.small:
@@ -418,13 +506,17 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "views": V, "width": W, "height": H, "gaussians": int(scene.gauss.n),
-                   "tile": args.tile, "persistent": bool(settings.persistent), "path": "batched",
+                   "tile": args.tile, "batch": int(settings.batch), "persistent": bool(settings.persistent),
+                   "path": "batched",
                    "joined_forward": bool(settings.split_fwd), "split_len": split_len,
                    "visible_per_view": {"min": int(vis.min()), "median": int(np.median(vis)), "max": int(vis.max())}},
         "loss": loss,
         "graph": graph,
         "per_view_plain": per_view,
         "speedup_vs_per_view": (round(per_view["ms_per_step"] / ms_step, 3) if per_view else None),
+        "speedup_vs_per_view_nosync": (round(per_view["nosync"]["ms_per_step"] / ms_step, 3) if per_view else None),
+        "dispatch": ("one launch per stage for all views, one workgroup per work item in cost order"
+                     if not settings.persistent else "one launch per stage for all views, persistent waves"),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "autotune": tune,

@@ -129,7 +129,8 @@ typedef struct splat_plan {
     size_t off_queue;       /* u32[V*T]: (view, tile) work items, most expensive first    */
     size_t off_hist;        /* u32[2^radix_bits*n_sort_blocks + 129] radix / queue histograms */
     size_t off_scan;        /* u32[scan partials]                                        */
-    size_t off_grad2d;      /* float[slot_cap][9]: d(mu x,y; conic a,b,c; o; r,g,b)       */
+    size_t off_grad2d;      /* float[slot_cap][9]: moments of dL/dpower over the pixel offsets
+                               (x, y, xx, xy, yy, 1), then dL/d(r,g,b)                      */
     size_t off_visbits;     /* u64[V*n_blocks_proj*4]: visible (view, Gaussian) bit masks  */
     size_t off_dwpart;      /* f64[V][n_blocks_proj][4][12] per-wave W2C gradient partials, then f64[V][32][12] stage sums */
     size_t off_cam;         /* f64[V][8]: per-view camera constants of the projection       */
@@ -181,7 +182,9 @@ SPLAT_API int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t 
  *   world), knot_p[K][3]; R0[C][9] row-major, t0[C][3]; xi[C][6] = (rho, phi);
  *   delta[C] seconds; view_cam[V] in [0,C); view_t[V] seconds.
  *   Output w2c[V][12] float64, row-major [W | w] with x_cam = W x_world + w.
- * Monotonicity of knot_t is the caller's contract (checked by the binding).
+ * Monotonicity of knot_t and the range of view_cam are the caller's contract:
+ * the library does not read device data on the host, so it cannot check them
+ * (the Python binding checks both once, when a scene is copied to the device).
  */
 SPLAT_API int splat_pose_interp_fwd(int32_t K, const double *knot_t, const double *knot_q,
                           const double *knot_p, int32_t C, const double *R0, const double *t0,
@@ -190,7 +193,10 @@ SPLAT_API int splat_pose_interp_fwd(int32_t K, const double *knot_t, const doubl
                           uint32_t *status, void *stream);
 
 /*
- * Adjoint of splat_pose_interp_fwd: given dL/dw2c[V][12] (float64) it ADDS
+ * Adjoint of splat_pose_interp_fwd (end of Sec. III-B: the photometric loss
+ * reaches the extrinsic and the time offset through the input pose, i.e.
+ * through Eq. 2, Eq. 1 and the interpolation of Sec. III-A).
+ * Given dL/dw2c[V][12] (float64) it ADDS
  * dL/dxi[C][6] and dL/ddelta[C] (float64, caller zeroes).  The rotation part
  * uses the right Jacobian of SO(3); d/ddelta goes through the interpolation
  * (translation velocity of the segment and its angular velocity).  Views of
@@ -254,7 +260,8 @@ SPLAT_API int splat_render_fwd(const splat_plan *plan, void *ws, float *img, flo
                      int32_t *last_pos, void *stream);
 
 /*
- * Backward compositing (the adjoint of splat_render_fwd): every pixel walks
+ * Backward compositing: the adjoint of Phi (Eq. 5) that carries the loss
+ * gradient back to the 2-D Gaussians (end of Sec. III-B).  Every pixel walks
  * its list in reverse from last_pos, recovering T by division and the suffix
  * colour sum, and accumulates d(loss)/d(mean2d, conic, opacity, colour) of
  * every slot with wave-reduced atomics into the workspace gradient buffer,
@@ -269,7 +276,9 @@ SPLAT_API int splat_render_bwd(const splat_plan *plan, void *ws, const float *dL
                      const int32_t *last_pos, void *stream);
 
 /*
- * Adjoint of splat_project: from the slot gradients it ADDS d(loss)/d quat,
+ * Adjoint of splat_project (end of Sec. III-B: gradients to the Gaussian
+ * parameters and, through Eq. 3 and Eq. 2, to the camera pose): from the slot
+ * gradients it ADDS d(loss)/d quat,
  * scale, opacity, colour and (if dmean != NULL) mean of every Gaussian
  * (float32 device planes of the parameter shapes; the caller zeroes them), and
  * ADDS d(loss)/d w2c[V][12] (float64, reduced in float64; caller zeroes).
@@ -312,10 +321,13 @@ SPLAT_API int splat_dssim_loss_grad(const float *img, const float *target, int32
 /*
  * Instrumented variants of splat_render_fwd / splat_render_bwd: identical
  * outputs, plus pair counters ADDED into stats (uint64 device array, caller
- * zeroes): [0] forward evaluated (pixel, Gaussian) pairs, [1] forward blended
- * pairs, [2] backward evaluated pairs, [3] backward contributing pairs,
- * [4] backward wave-reduced atomic groups (9 atomics each).  Used to turn
- * kernel durations into achieved work; slower than the plain calls.
+ * zeroes, 8 entries): [0] forward evaluated (pixel, Gaussian) pairs, [1] forward
+ * blended pairs, [2] backward evaluated pairs, [3] backward contributing pairs,
+ * [4] backward wave-reduced atomic groups (9 atomics each), [5] forward
+ * (Gaussian, 8x8 sub-block) evaluations of a wave (the exponent computed for its
+ * 64 pixels), [6] those of them that went on to blend, [7] backward (Gaussian,
+ * 8x8 sub-block) evaluations of a wave.  Used to turn kernel durations into
+ * achieved work; slower than the plain calls.
  */
 SPLAT_API int splat_render_fwd_stats(const splat_plan *plan, void *ws, float *img, float *T_final,
                                      int32_t *last_pos, uint64_t *stats, void *stream);

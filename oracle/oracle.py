@@ -102,6 +102,15 @@ def num_threads() -> int:
     return int(lib().or_num_threads())
 
 
+def set_num_threads(n: int) -> int:
+    """Threads of the OpenMP loops from now on (for timing the oracle); returns the new count."""
+    f = lib().omp_set_num_threads
+    f.argtypes = [C.c_int]
+    f.restype = None
+    f(int(n))
+    return num_threads()
+
+
 def _p(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 

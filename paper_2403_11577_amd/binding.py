@@ -141,6 +141,45 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+_DT = {"f32": "torch.float32", "f64": "torch.float64", "i32": "torch.int32", "i64": "torch.int64",
+       "u8": "torch.uint8"}
+
+
+def _arg(t, name, dt, numel=None, at_least=False, optional=False):
+    """Pointer of a device tensor after checking what the C ABI cannot: that it is a
+    contiguous device tensor of the element type the call reads or writes, with the
+    number of elements the call touches (or at least that many).  The kernels trust
+    these sizes, so an undersized buffer must not reach them."""
+    if t is None:
+        if optional:
+            return None
+        raise SplatError(f"{name}: a device tensor is required")
+    if not getattr(t, "is_cuda", False):
+        raise SplatError(f"{name}: must be a device tensor")
+    if str(t.dtype) not in (_DT[dt],) and not (dt == "i32" and str(t.dtype) == "torch.uint32"):
+        raise SplatError(f"{name}: dtype {t.dtype}, expected {_DT[dt]}")
+    if not t.is_contiguous():
+        raise SplatError(f"{name}: must be contiguous")
+    if numel is not None:
+        n = t.numel()
+        if (n < numel) if at_least else (n != numel):
+            raise SplatError(f"{name}: {n} elements, expected {'at least ' if at_least else ''}{numel}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _ws(plan, ws):
+    if ws is None or not getattr(ws, "is_cuda", False) or not ws.is_contiguous():
+        raise SplatError("ws: a contiguous device tensor is required")
+    if ws.numel() * ws.element_size() < int(plan.ws_bytes):
+        raise SplatError(f"ws: {ws.numel() * ws.element_size()} bytes, the plan needs {int(plan.ws_bytes)}")
+    return C.c_void_p(ws.data_ptr())
+
+
+def _img_sizes(plan):
+    V, H, W = int(plan.n_views), int(plan.height), int(plan.width)
+    return V * 3 * H * W, V * H * W
+
+
 def _stream(stream=None):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
@@ -168,66 +207,107 @@ def splat_plan_make(settings: splat_settings, n_views: int, n_gauss: int, width:
 
 
 def gaussians_struct(mean, quat, scale, opacity, color) -> splat_gaussians:
-    return splat_gaussians(_ptr(mean), _ptr(quat), _ptr(scale), _ptr(opacity), _ptr(color),
-                           int(opacity.shape[0]))
+    n = int(opacity.numel())
+    return splat_gaussians(_arg(mean, "mean", "f32", 3 * n), _arg(quat, "quat", "f32", 4 * n),
+                           _arg(scale, "scale", "f32", 3 * n), _arg(opacity, "opacity", "f32", n),
+                           _arg(color, "color", "f32", 3 * n), n)
+
+
+def _pose_args(knot_t, knot_q, knot_p, R0, t0, xi, delta, view_cam, view_t):
+    K, Cn, V = int(knot_t.numel()), int(delta.numel()), int(view_cam.numel())
+    return [K, _arg(knot_t, "knot_t", "f64", K), _arg(knot_q, "knot_q", "f64", 4 * K),
+            _arg(knot_p, "knot_p", "f64", 3 * K), Cn, _arg(R0, "R0", "f64", 9 * Cn), _arg(t0, "t0", "f64", 3 * Cn),
+            _arg(xi, "xi", "f64", 6 * Cn), _arg(delta, "delta", "f64", Cn), V,
+            _arg(view_cam, "view_cam", "i32", V), _arg(view_t, "view_t", "f64", V)], V, Cn
 
 
 def splat_pose_interp_fwd(knot_t, knot_q, knot_p, R0, t0, xi, delta, view_cam, view_t, w2c,
                           status=None, stream=None):
-    _check(lib().splat_pose_interp_fwd(int(knot_t.shape[0]), _ptr(knot_t), _ptr(knot_q), _ptr(knot_p),
-                                       int(R0.shape[0]), _ptr(R0), _ptr(t0), _ptr(xi), _ptr(delta),
-                                       int(view_cam.shape[0]), _ptr(view_cam), _ptr(view_t), _ptr(w2c),
-                                       _ptr(status), _stream(stream)), "splat_pose_interp_fwd")
+    a, V, _ = _pose_args(knot_t, knot_q, knot_p, R0, t0, xi, delta, view_cam, view_t)
+    _check(lib().splat_pose_interp_fwd(*a, _arg(w2c, "w2c", "f64", 12 * V),
+                                       _arg(status, "status", "i32", 1, at_least=True, optional=True),
+                                       _stream(stream)), "splat_pose_interp_fwd")
 
 
 def splat_pose_interp_bwd(knot_t, knot_q, knot_p, R0, t0, xi, delta, view_cam, view_t, dw2c, dxi,
                           ddelta, stream=None):
-    _check(lib().splat_pose_interp_bwd(int(knot_t.shape[0]), _ptr(knot_t), _ptr(knot_q), _ptr(knot_p),
-                                       int(R0.shape[0]), _ptr(R0), _ptr(t0), _ptr(xi), _ptr(delta),
-                                       int(view_cam.shape[0]), _ptr(view_cam), _ptr(view_t), _ptr(dw2c),
-                                       _ptr(dxi), _ptr(ddelta), _stream(stream)), "splat_pose_interp_bwd")
+    a, V, Cn = _pose_args(knot_t, knot_q, knot_p, R0, t0, xi, delta, view_cam, view_t)
+    _check(lib().splat_pose_interp_bwd(*a, _arg(dw2c, "dw2c", "f64", 12 * V), _arg(dxi, "dxi", "f64", 6 * Cn),
+                                       _arg(ddelta, "ddelta", "f64", Cn), _stream(stream)), "splat_pose_interp_bwd")
+
+
+def _check_gauss(plan, gauss: splat_gaussians):
+    if int(gauss.n) != int(plan.n_gauss):
+        raise SplatError(f"Gaussians: {int(gauss.n)}, the plan was made for {int(plan.n_gauss)}")
 
 
 def splat_project(plan, ws, gauss: splat_gaussians, w2c, intr, stream=None):
-    _check(lib().splat_project(C.byref(plan), _ptr(ws), C.byref(gauss), _ptr(w2c), _ptr(intr),
-                               _stream(stream)), "splat_project")
+    _check_gauss(plan, gauss)
+    V = int(plan.n_views)
+    _check(lib().splat_project(C.byref(plan), _ws(plan, ws), C.byref(gauss), _arg(w2c, "w2c", "f64", 12 * V),
+                               _arg(intr, "intr", "f64", 4 * V), _stream(stream)), "splat_project")
 
 
 def splat_bin_sort(plan, ws, stream=None):
-    _check(lib().splat_bin_sort(C.byref(plan), _ptr(ws), _stream(stream)), "splat_bin_sort")
+    _check(lib().splat_bin_sort(C.byref(plan), _ws(plan, ws), _stream(stream)), "splat_bin_sort")
+
+
+def _render_out(plan, img, T_final, last_pos, img_name="img"):
+    n3, n1 = _img_sizes(plan)
+    return (_arg(img, img_name, "f32", n3), _arg(T_final, "T_final", "f32", n1),
+            _arg(last_pos, "last_pos", "i32", n1))
 
 
 def splat_render_fwd(plan, ws, img, T_final, last_pos, stream=None):
-    _check(lib().splat_render_fwd(C.byref(plan), _ptr(ws), _ptr(img), _ptr(T_final), _ptr(last_pos),
+    _check(lib().splat_render_fwd(C.byref(plan), _ws(plan, ws), *_render_out(plan, img, T_final, last_pos),
                                   _stream(stream)), "splat_render_fwd")
 
 
 def splat_render_bwd(plan, ws, dL_dimg, T_final, last_pos, stream=None):
-    _check(lib().splat_render_bwd(C.byref(plan), _ptr(ws), _ptr(dL_dimg), _ptr(T_final), _ptr(last_pos),
-                                  _stream(stream)), "splat_render_bwd")
+    _check(lib().splat_render_bwd(C.byref(plan), _ws(plan, ws),
+                                  *_render_out(plan, dL_dimg, T_final, last_pos, "dL_dimg"), _stream(stream)),
+           "splat_render_bwd")
 
 
 def splat_project_bwd(plan, ws, gauss: splat_gaussians, w2c, intr, dquat, dscale, dopacity, dcolor,
                       dmean, dw2c, stream=None):
-    _check(lib().splat_project_bwd(C.byref(plan), _ptr(ws), C.byref(gauss), _ptr(w2c), _ptr(intr),
-                                   _ptr(dquat), _ptr(dscale), _ptr(dopacity), _ptr(dcolor), _ptr(dmean),
-                                   _ptr(dw2c), _stream(stream)), "splat_project_bwd")
+    _check_gauss(plan, gauss)
+    V, G = int(plan.n_views), int(plan.n_gauss)
+    _check(lib().splat_project_bwd(C.byref(plan), _ws(plan, ws), C.byref(gauss), _arg(w2c, "w2c", "f64", 12 * V),
+                                   _arg(intr, "intr", "f64", 4 * V), _arg(dquat, "dquat", "f32", 4 * G),
+                                   _arg(dscale, "dscale", "f32", 3 * G), _arg(dopacity, "dopacity", "f32", G),
+                                   _arg(dcolor, "dcolor", "f32", 3 * G),
+                                   _arg(dmean, "dmean", "f32", 3 * G, optional=True),
+                                   _arg(dw2c, "dw2c", "f64", 12 * V), _stream(stream)), "splat_project_bwd")
 
 
 def splat_render_fwd_stats(plan, ws, img, T_final, last_pos, stats, stream=None):
-    _check(lib().splat_render_fwd_stats(C.byref(plan), _ptr(ws), _ptr(img), _ptr(T_final), _ptr(last_pos),
-                                        _ptr(stats), _stream(stream)), "splat_render_fwd_stats")
+    _check(lib().splat_render_fwd_stats(C.byref(plan), _ws(plan, ws), *_render_out(plan, img, T_final, last_pos),
+                                        _arg(stats, "stats", "i64", 8, at_least=True),
+                                        _stream(stream)), "splat_render_fwd_stats")
 
 
 def splat_render_bwd_stats(plan, ws, dL_dimg, T_final, last_pos, stats, stream=None):
-    _check(lib().splat_render_bwd_stats(C.byref(plan), _ptr(ws), _ptr(dL_dimg), _ptr(T_final), _ptr(last_pos),
-                                        _ptr(stats), _stream(stream)), "splat_render_bwd_stats")
+    _check(lib().splat_render_bwd_stats(C.byref(plan), _ws(plan, ws),
+                                        *_render_out(plan, dL_dimg, T_final, last_pos, "dL_dimg"),
+                                        _arg(stats, "stats", "i64", 8, at_least=True), _stream(stream)),
+           "splat_render_bwd_stats")
+
+
+def _image_pair(img, target, dL_dimg):
+    if img.dim() != 4 or img.shape[1] != 3:
+        raise SplatError(f"img: shape {tuple(img.shape)}, expected [V, 3, H, W]")
+    n = int(img.numel())
+    return (_arg(img, "img", "f32", n), _arg(target, "target", "f32", n), _arg(dL_dimg, "dL_dimg", "f32", n))
 
 
 def splat_l1_loss_grad(img, target, mask, dL_dimg, loss=None, roi_y0=0, weight=1.0, stream=None):
     V, _, H, W = img.shape
-    _check(lib().splat_l1_loss_grad(_ptr(img), _ptr(target), _ptr(mask), int(V), int(W), int(H), int(roi_y0),
-                                    float(weight), _ptr(dL_dimg), _ptr(loss), _stream(stream)), "splat_l1_loss_grad")
+    pi, pt, pd = _image_pair(img, target, dL_dimg)
+    _check(lib().splat_l1_loss_grad(pi, pt, _arg(mask, "mask", "u8", V * H * W, optional=True), int(V), int(W),
+                                    int(H), int(roi_y0), float(weight), pd,
+                                    _arg(loss, "loss", "f64", 1, at_least=True, optional=True), _stream(stream)),
+           "splat_l1_loss_grad")
 
 
 def splat_dssim_workspace_size(n_views, width, height, roi_y0=0) -> int:
@@ -236,8 +316,10 @@ def splat_dssim_workspace_size(n_views, width, height, roi_y0=0) -> int:
 
 def splat_dssim_loss_grad(img, target, ws, dL_dimg, loss=None, roi_y0=0, weight=0.2, stream=None):
     V, _, H, W = img.shape
-    _check(lib().splat_dssim_loss_grad(_ptr(img), _ptr(target), int(V), int(W), int(H), int(roi_y0), float(weight),
-                                       _ptr(ws), int(ws.numel() * ws.element_size()), _ptr(dL_dimg), _ptr(loss),
+    pi, pt, pd = _image_pair(img, target, dL_dimg)
+    _check(lib().splat_dssim_loss_grad(pi, pt, int(V), int(W), int(H), int(roi_y0), float(weight),
+                                       _arg(ws, "ws", "u8"), int(ws.numel() * ws.element_size()), pd,
+                                       _arg(loss, "loss", "f64", 1, at_least=True, optional=True),
                                        _stream(stream)), "splat_dssim_loss_grad")
 
 

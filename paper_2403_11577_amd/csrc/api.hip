@@ -67,8 +67,8 @@ static int check_settings(const splat_settings *s) {
     if (!tile_supported(s->tile_w, s->tile_h)) {
         set_error("unsupported tile %dx%d (8x8, 16x16, 16x32, 32x16)", s->tile_w, s->tile_h); return SPLAT_EINVAL;
     }
-    if (s->batch < 16 || s->batch > 256 || (s->batch % 16)) {
-        set_error("batch must be a multiple of 16 in [16, 256] (got %d)", s->batch); return SPLAT_EINVAL;
+    if (s->batch != 32 && s->batch != 64 && s->batch != 128 && s->batch != 256) {
+        set_error("batch must be 32, 64, 128 or 256 (got %d)", s->batch); return SPLAT_EINVAL;
     }
     if (s->persistent != 0 && s->persistent != 1) { set_error("persistent must be 0 or 1"); return SPLAT_EINVAL; }
     if (s->roi_y0 < 0) { set_error("roi_y0 must be >= 0 (got %d)", s->roi_y0); return SPLAT_EINVAL; }

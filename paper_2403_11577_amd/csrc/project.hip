@@ -307,14 +307,20 @@ __global__ void project_finish_kernel(const uint32_t *waveoff, int V, int nw, in
 // ----------------------------------------------------------------------------------
 // adjoint
 // ----------------------------------------------------------------------------------
-// Chain rule of one visible (view, Gaussian) pair from its slot gradient gd[9]
-// = d(mu x, mu y; conic a, b, c; opacity; r, g, b).  Adds the quaternion, scale
-// and mean gradients to gq, gs, gm and returns the W2C gradient in gw[12].
+// Chain rule of one visible (view, Gaussian) pair from its slot gradient: the
+// render adjoint leaves in gd[0..4] the moments (Mx, My, Mxx, Mxy, Myy) of
+// dL/dpower over the pixel offsets d = pixel - mu (M. = sum dL/dpower * d. over
+// the pixels), with power = -(a dx^2 + 2 b dx dy + c dy^2)/2 for the conic
+// (a, b, c), so that dL/dmu = (a Mx + b My, b Mx + c My) and
+// dL/d(a, b, c) = (-Mxx/2, -Mxy, -Myy/2).  Adds the quaternion, scale and mean
+// gradients to gq, gs, gm and returns the W2C gradient in gw[12].
 __device__ void slot_adjoint(const Proj &P, const double *M, const CamC &C, const float *x, const float *s,
                              const float *gd, double *gq, double *gs, double *gm, double *gw) {
-    double gmx = gd[0], gmy = gd[1], ga = gd[2], gb = gd[3], gc = gd[4];
-    // conic -> Sigma2: G2 = -Q GQ Q with GQ = [[ga, gb/2], [gb/2, gc]]
     double a = P.Q[0], b = P.Q[1], c = P.Q[2];
+    const double Mx = gd[0], My = gd[1];
+    double gmx = a * Mx + b * My, gmy = b * Mx + c * My;
+    double ga = -0.5 * (double)gd[2], gb = -(double)gd[3], gc = -0.5 * (double)gd[4];
+    // conic -> Sigma2: G2 = -Q GQ Q with GQ = [[ga, gb/2], [gb/2, gc]]
     double hb = 0.5 * gb;
     double m00 = a * ga + b * hb, m01 = a * hb + b * gc;
     double m10 = b * ga + c * hb, m11 = b * hb + c * gc;
@@ -479,7 +485,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
                     Proj P;
                     project_view(S, M, C, gi.x, gi.s, gi.G, true, P);
                     const float *gd = grad2d + 9 * slot;
-                    go += gd[5];
+                    go += (double)gd[5] / (double)gi.o;   // gd[5] = sum of dL/dpower = o dL/do
                     gc[0] += gd[6];
                     gc[1] += gd[7];
                     gc[2] += gd[8];

@@ -65,7 +65,7 @@ struct RenderArgs {
 // alpha >= alpha_min footprint can reach (padded by 1% + 0.6 px; a sub-block
 // outside it only ever evaluates alpha < alpha_min).
 struct Stage {
-    float mx, my, A, Bc, Cc, lo2, io, r, g, b;
+    float mx, my, A, Bc, Cc, lo2, r, g, b;
     uint32_t slot, mask;
 };
 
@@ -119,14 +119,13 @@ __device__ __forceinline__ Stage derive(const RenderArgs &a, const Raw &raw, flo
     float o = raw.r1.w;
     bool valid = raw.slot != 0xFFFFFFFFu && o > 0.f;
     s.lo2 = valid ? __log2f(o) : -256.f;
-    s.io = valid ? __builtin_amdgcn_rcpf(o) : 0.f;
     s.r = raw.r2.x;
     s.g = raw.r2.y;
     s.b = raw.r2.z;
     if (BM) {
         s.mask = valid ? raw.bm : 0u;
         asm volatile("" : "+v"(s.mx), "+v"(s.my), "+v"(s.A), "+v"(s.Bc), "+v"(s.Cc), "+v"(s.lo2));
-        asm volatile("" : "+v"(s.io), "+v"(s.r), "+v"(s.g), "+v"(s.b), "+v"(s.slot), "+v"(s.mask));
+        asm volatile("" : "+v"(s.r), "+v"(s.g), "+v"(s.b), "+v"(s.slot), "+v"(s.mask));
         return s;
     }
     // footprint box: half-widths k sqrt(Sigma2_ii), Sigma2 = conic^-1, k^2 = 2 ln(o / alpha_min)
@@ -148,7 +147,7 @@ __device__ __forceinline__ Stage derive(const RenderArgs &a, const Raw &raw, flo
     // recompute them from the raw registers at the top of the next evaluation
     // loop, after the next gather has been issued, and wait for that gather
     asm volatile("" : "+v"(s.mx), "+v"(s.my), "+v"(s.A), "+v"(s.Bc), "+v"(s.Cc), "+v"(s.lo2));
-    asm volatile("" : "+v"(s.io), "+v"(s.r), "+v"(s.g), "+v"(s.b), "+v"(s.slot), "+v"(s.mask));
+    asm volatile("" : "+v"(s.r), "+v"(s.g), "+v"(s.b), "+v"(s.slot), "+v"(s.mask));
     return s;
 }
 
@@ -161,13 +160,13 @@ __device__ __forceinline__ uint32_t bcast_u(uint32_t v, int j) {
 }
 
 // A batch is staged in LDS as three float4 per Gaussian: (mx, my, A, Bc), (Cc, lo2, r, g),
-// (b, 1/o, slot, -); the pair loops read Gaussian j back with a wave-uniform address (one
+// (b, -, slot, -); the pair loops read Gaussian j back with a wave-uniform address (one
 // broadcast read per float4) instead of a readlane per value.  The workgroup is one wave,
 // whose LDS accesses complete in order, so no barrier is needed between the batches.
 __device__ __forceinline__ void put_stage(float4 (*sg)[3], const Stage &s, int lane) {
     sg[lane][0] = make_float4(s.mx, s.my, s.A, s.Bc);
     sg[lane][1] = make_float4(s.Cc, s.lo2, s.r, s.g);
-    sg[lane][2] = make_float4(s.b, s.io, __uint_as_float(s.slot), 0.f);
+    sg[lane][2] = make_float4(s.b, 0.f, __uint_as_float(s.slot), 0.f);
 }
 
 // exponent in log2 units including log2(opacity): A dx^2 + Bc dx dy + Cc dy^2 + lo2
@@ -256,18 +255,20 @@ __device__ __forceinline__ void put_chk(const RenderArgs &a, uint32_t slot, cons
 // T T_chunk >= t_min (1 + margin) with T_chunk >= t_min guarantees that the
 // sequential walk (T decreasing monotonically) stops nowhere in the chunk, the
 // margin covering the rounding by which the sequential product can differ.
-template <int TW, int TH, bool STATS, int MODE>
+template <int TW, int TH, bool STATS, int MODE, int NB>
 __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img, float *Tout, int32_t *lastout) {
     constexpr int NSB = TW * TH / 64, SBX = TW / 8, NPIX = TW * TH;
-    __shared__ float4 sg[64][3];  // the staged batch, read back with wave-uniform addresses
+    constexpr int R = NB >= 64 ? NB / 64 : 1;      // sub-batches of 64 staged at once
+    __shared__ float4 sg[R * 64][3];  // the staged batch, read back with wave-uniform addresses
     const int lane = threadIdx.x;
     const int lx = lane & 7, ly = lane >> 3;
+    const bool stager = NB >= 64 || lane < NB;     // lanes that gather a Gaussian of the batch
     const size_t HW = (size_t)a.W * a.H;
     const uint32_t nslots = a.counts[CNT_SLOTS];
     const uint32_t nsplit = a.counts[CNT_NSPLIT];
     const int n_items = MODE == 1 ? (int)min(a.counts[CNT_NCHUNK], a.chk_cap) : a.n_items;
     const float thr = a.tmin * (1.001f + 1.2e-7f * (float)a.lc);
-    unsigned long long n_eval = 0, n_blend = 0;
+    unsigned long long n_eval = 0, n_blend = 0, w_eval = 0, w_blend = 0;
     int item;
     for (int iter = 0; MODE == 1 ? (item = (int)blockIdx.x + iter * (int)gridDim.x) < n_items
                                   : next_item(a, iter, n_items, item);
@@ -307,9 +308,23 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
             last[k] = -1;
         }
         const float fxb = (float)xb, fyb = (float)yb, fox = (float)(x0 - xb), foy = (float)(y0 - yb);
-        Stage cur = derive<TW, TH>(a, load_raw(a, load_slot(a, lo + lane, hi), nslots), fxb, fyb, fox, foy);
-        put_stage(sg, cur, lane);
-        uint32_t sl_next = load_slot(a, lo + 64 + lane, hi);
+        // the batch [b, b + NB): sub-batch r holds instances b + 64 r + lane; the staged values go to
+        // LDS, each lane keeps the sub-block masks of its Gaussians
+        uint32_t cmask[R], sl_next[R];
+        auto slot_at = [&](uint32_t base, int r) {
+            return stager ? load_slot(a, base + 64u * r + lane, hi) : 0xFFFFFFFFu;
+        };
+        auto stage = [&](uint32_t base) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                Stage c = derive<TW, TH>(a, load_raw(a, slot_at(base, r), nslots), fxb, fyb, fox, foy);
+                put_stage(sg + 64 * r, c, lane);
+                cmask[r] = c.mask;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) sl_next[r] = slot_at(base + NB, r);
+        };
+        stage(lo);
         // a split list records (T, C) where each of its chunks starts (chunks are whole batches)
         const bool split = MODE != 1 && (uint32_t)item < nsplit;
         const uint32_t cslot = split ? a.boff[item] : 0u;
@@ -322,7 +337,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
         float parkL[NSB];
 #pragma unroll
         for (int k = 0; k < NSB; ++k) parkL[k] = 0.f;
-        for (uint32_t b = lo; b < hi; b += 64) {
+        for (uint32_t b = lo; b < hi; b += NB) {
             if (MODE == 2 && parked && b == park_end) {
 #pragma unroll
                 for (int k = 0; k < NSB; ++k) L[k] = parkL[k] > 0.f ? parkL[k] : L[k];
@@ -371,10 +386,8 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
                 if (joined) {
                     // continue at the next chunk: restage its first batch
                     const uint32_t bn = b + a.lc;
-                    cur = derive<TW, TH>(a, load_raw(a, load_slot(a, bn + lane, hi), nslots), fxb, fyb, fox, foy);
-                    put_stage(sg, cur, lane);
-                    sl_next = load_slot(a, bn + 64 + lane, hi);
-                    b = bn - 64;
+                    stage(bn);
+                    b = bn - NB;
                     continue;
                 }
             }
@@ -384,81 +397,99 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
             if (live == 0) {
                 if (MODE == 2 && parked && park_end < hi) {
                     // the walking pixels have stopped: the parked ones resume where the chunk ends
-                    cur = derive<TW, TH>(a, load_raw(a, load_slot(a, park_end + lane, hi), nslots), fxb, fyb, fox,
-                                         foy);
-                    put_stage(sg, cur, lane);
-                    sl_next = load_slot(a, park_end + 64 + lane, hi);
-                    b = park_end - 64;
+                    stage(park_end);
+                    b = park_end - NB;
                     continue;
                 }
                 break;  // every pixel has stopped (parked ones already hold the state at the list end)
             }
-            uint64_t blended[NSB];  // per sub-block: the Gaussians of the batch that blended into it
+            Raw raw_next[R];
+            uint32_t sl_after[R];
 #pragma unroll
-            for (int k = 0; k < NSB; ++k) blended[k] = 0ull;
-            Raw raw_next = load_raw(a, sl_next, nslots);              // records of batch b + 64
-            uint32_t sl_after = load_slot(a, b + 128 + lane, hi);     // slot ids of batch b + 128
-            // the Gaussians of the batch that reach a live sub-block, in order (lanes past the
-            // list end carry an empty mask)
-            uint64_t todo = __ballot((cur.mask & live) != 0u);
-            // two Gaussians per pass: the staged values of both are read before the first is
-            // evaluated, so the second read is in flight meanwhile (without a second one the pass
-            // evaluates the first again with zero opacity, which blends nothing)
-            auto blend = [&](int j, const float4 q0, const float4 q1, const float cb, bool real) {
-                // with one sub-block every Gaussian of the ballot reaches it
-                const uint32_t m = NSB == 1 ? 1u : bcast_u(cur.mask, j) & live;
-                const float mx = q0.x, my = q0.y, A = q0.z, Bc = q0.w, Cc = q1.x, lo2 = q1.y;
-                const float cr = q1.z, cg = q1.w;
-                const int idx = (int)(b + j);
+            for (int r = 0; r < R; ++r) raw_next[r] = load_raw(a, sl_next[r], nslots);  // records of batch b + NB
 #pragma unroll
-                for (int k = 0; k < NSB; ++k) {
-                    if (!(m & (1u << k))) continue;  // wave-uniform
-                    if (STATS) n_eval += real && L[k] > 0.f;
-                    float dx = px[k] - mx, dy = py[k] - my;
-                    const float pw = power2(dx, dy, A, Bc, Cc, lo2);
-                    // no live pixel of the sub-block within reach of alpha_min: nothing blends
-                    // (2^(log2 alpha_min - 0.01) is below alpha_min by far more than the rounding)
-                    if (__ballot(L[k] > 0.f && pw >= a.lamin2 - 0.01f) == 0ull) continue;
-                    float al = alpha_of(pw, a.amax);
-                    al = al >= a.amin ? al : 0.f;
-                    float w = al * L[k];
-                    float Tn = T[k] - w;
-                    bool stop = Tn < a.tmin;  // cannot hold for a stopped pixel: its T stays >= t_min
-                    w = stop ? 0.f : w;
-                    T[k] = stop ? T[k] : Tn;
-                    L[k] = stop ? 0.f : L[k] - w;
-                    if (STATS) n_blend += w > 0.f;
-                    C0[k] = __fmaf_rn(cr, w, C0[k]);
-                    C1[k] = __fmaf_rn(cg, w, C1[k]);
-                    C2[k] = __fmaf_rn(cb, w, C2[k]);
-                    last[k] = w > 0.f ? idx : last[k];
-                    blended[k] |= __ballot(w > 0.f) ? (1ull << j) : 0ull;
+            for (int r = 0; r < R; ++r) sl_after[r] = slot_at(b + 2 * NB, r);         // slot ids of batch b + 2 NB
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (r > 0) {
+                    live = 0;
+#pragma unroll
+                    for (int k = 0; k < NSB; ++k) live |= __ballot(L[k] > 0.f) ? (1u << k) : 0u;
                 }
-            };
-            while (todo) {
-                const int j1 = __ffsll((long long)todo) - 1;
-                todo &= todo - 1ull;
-                const bool two = todo != 0ull;
-                const int j2 = two ? __ffsll((long long)todo) - 1 : j1;
-                todo &= todo - 1ull;
-                const float4 a0 = sg[j1][0], a1 = sg[j1][1], b0 = sg[j2][0];
-                float4 b1 = sg[j2][1];
-                const float a2 = sg[j1][2].x, b2 = sg[j2][2].x;
-                b1.y = two ? b1.y : -256.f;  // log2 of the opacity: alpha = 0 < alpha_min
-                blend(j1, a0, a1, a2, true);
-                blend(j2, b0, b1, b2, two);
-            }
-            {
-                uint32_t bm = 0;
+                const uint32_t bb = b + 64u * r;   // first instance of the sub-batch
+                const float4(*sgr)[3] = sg + 64 * r;
+                uint64_t blended[NSB];  // per sub-block: the Gaussians of the sub-batch that blended into it
 #pragma unroll
-                for (int k = 0; k < NSB; ++k) bm |= ((blended[k] >> lane) & 1ull) ? (1u << k) : 0u;
-                // with parked pixels the chunk's own pass holds their blends (a superset is exact)
-                if (MODE == 2 && parked && b + lane < hi) bm |= a.bmask[b + lane];
-                if (b + lane < hi) a.bmask[b + lane] = (uint8_t)bm;
+                for (int k = 0; k < NSB; ++k) blended[k] = 0ull;
+                // the Gaussians of the sub-batch that reach a live sub-block, in order (lanes past the
+                // list end carry an empty mask)
+                uint64_t todo = __ballot((cmask[r] & live) != 0u);
+                // two Gaussians per pass: the staged values of both are read before the first is
+                // evaluated, so the second read is in flight meanwhile (without a second one the pass
+                // evaluates the first again with zero opacity, which blends nothing)
+                auto blend = [&](int j, const float4 q0, const float4 q1, const float cb, bool real) {
+                    // with one sub-block every Gaussian of the ballot reaches it
+                    const uint32_t m = NSB == 1 ? 1u : bcast_u(cmask[r], j) & live;
+                    const float mx = q0.x, my = q0.y, A = q0.z, Bc = q0.w, Cc = q1.x, lo2 = q1.y;
+                    const float cr = q1.z, cg = q1.w;
+                    const int idx = (int)(bb + j);
+#pragma unroll
+                    for (int k = 0; k < NSB; ++k) {
+                        if (!(m & (1u << k))) continue;  // wave-uniform
+                        if (STATS) n_eval += real && L[k] > 0.f;
+                        if (STATS) w_eval += lane == 0;
+                        float dx = px[k] - mx, dy = py[k] - my;
+                        const float pw = power2(dx, dy, A, Bc, Cc, lo2);
+                        // no live pixel of the sub-block within reach of alpha_min: nothing blends
+                        // (2^(log2 alpha_min - 0.01) is below alpha_min by far more than the rounding)
+                        if (__ballot(L[k] > 0.f && pw >= a.lamin2 - 0.01f) == 0ull) continue;
+                        if (STATS) w_blend += lane == 0;
+                        float al = alpha_of(pw, a.amax);
+                        al = al >= a.amin ? al : 0.f;
+                        float w = al * L[k];
+                        float Tn = T[k] - w;
+                        bool stop = Tn < a.tmin;  // cannot hold for a stopped pixel: its T stays >= t_min
+                        w = stop ? 0.f : w;
+                        T[k] = stop ? T[k] : Tn;
+                        L[k] = stop ? 0.f : L[k] - w;
+                        if (STATS) n_blend += w > 0.f;
+                        C0[k] = __fmaf_rn(cr, w, C0[k]);
+                        C1[k] = __fmaf_rn(cg, w, C1[k]);
+                        C2[k] = __fmaf_rn(cb, w, C2[k]);
+                        last[k] = w > 0.f ? idx : last[k];
+                        blended[k] |= __ballot(w > 0.f) ? (1ull << j) : 0ull;
+                    }
+                };
+                while (todo) {
+                    const int j1 = __ffsll((long long)todo) - 1;
+                    todo &= todo - 1ull;
+                    const bool two = todo != 0ull;
+                    const int j2 = two ? __ffsll((long long)todo) - 1 : j1;
+                    todo &= todo - 1ull;
+                    const float4 a0 = sgr[j1][0], a1 = sgr[j1][1], b0 = sgr[j2][0];
+                    float4 b1 = sgr[j2][1];
+                    const float a2 = sgr[j1][2].x, b2 = sgr[j2][2].x;
+                    b1.y = two ? b1.y : -256.f;  // log2 of the opacity: alpha = 0 < alpha_min
+                    blend(j1, a0, a1, a2, true);
+                    blend(j2, b0, b1, b2, two);
+                }
+                if (stager) {
+                    uint32_t bm = 0;
+#pragma unroll
+                    for (int k = 0; k < NSB; ++k) bm |= ((blended[k] >> lane) & 1ull) ? (1u << k) : 0u;
+                    // with parked pixels the chunk's own pass holds their blends (a superset is exact)
+                    if (MODE == 2 && parked && bb + lane < hi) bm |= a.bmask[bb + lane];
+                    if (bb + lane < hi) a.bmask[bb + lane] = (uint8_t)bm;
+                }
             }
-            cur = derive<TW, TH>(a, raw_next, fxb, fyb, fox, foy);
-            put_stage(sg, cur, lane);
-            sl_next = sl_after;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                Stage c = derive<TW, TH>(a, raw_next[r], fxb, fyb, fox, foy);
+                put_stage(sg + 64 * r, c, lane);
+                cmask[r] = c.mask;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) sl_next[r] = sl_after[r];
         }
         if (MODE == 1) {
             // the chunk on its own: (T_chunk, C_chunk), T_chunk = -1 where the pixel stopped in it
@@ -495,6 +526,8 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
     if (STATS) {
         stat_add(a.stats + 0, n_eval);
         stat_add(a.stats + 1, n_blend);
+        stat_add(a.stats + 5, w_eval);
+        stat_add(a.stats + 6, w_blend);
     }
 }
 
@@ -539,13 +572,15 @@ __device__ __forceinline__ float reduce9(const float (&v)[9], bool c0, bool c1, 
 // clamped at alpha_max); dL/d(conic) and dL/d(mean) follow from the power.
 // Lanes that do not blend a Gaussian run the same instructions with alpha = 0,
 // which changes nothing (1 / (1 - 0) = 1 exactly).
-template <int TW, int TH, bool STATS>
+template <int TW, int TH, bool STATS, int NB>
 __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const float *dimg, const float *Tin,
                                                        const int32_t *lastin, float *grad2d) {
     constexpr int NSB = TW * TH / 64, SBX = TW / 8;
-    __shared__ float4 sg[64][3];  // the staged batch (see put_stage)
+    constexpr int R = NB >= 64 ? NB / 64 : 1;      // sub-batches of 64 staged at once
+    __shared__ float4 sg[R * 64][3];  // the staged batch (see put_stage)
     const int lane = threadIdx.x;
     const int lx = lane & 7, ly = lane >> 3;
+    const bool stager = NB >= 64 || lane < NB;
     const size_t HW = (size_t)a.W * a.H;
     const uint32_t nslots = a.counts[CNT_SLOTS];
     // reduction classes of this lane (see reduce9) and the lanes that write them
@@ -553,7 +588,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
     const bool c0 = b0 ^ b2, c1 = b1 ^ b2, c2 = b2 ^ b3, c3 = b3;
     const int cls = (int)c0 | ((int)c1 << 1) | ((int)c2 << 2) | ((int)c3 << 3);
     const bool writer = lane < 16 && cls < 9;
-    unsigned long long n_eval = 0, n_contrib = 0, n_atomic = 0;
+    unsigned long long n_eval = 0, n_contrib = 0, n_atomic = 0, w_eval = 0;
     const int n_items = (int)min(a.counts[CNT_BITEMS], (uint32_t)a.n_items);
     int item;
     for (int iter = 0; next_item(a, iter, n_items, item); ++iter) {
@@ -617,86 +652,118 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
         int hi = wmax + 1;  // walk [cs, hi) backwards
         if (hi <= cs) continue;
         const float fxb = (float)xb, fyb = (float)yb, fox = (float)(x0 - xb), foy = (float)(y0 - yb);
+        // batches [bs, e) of up to NB instances from the end of the walk; sub-batch r holds
+        // instances bs + 64 r + lane
+        uint32_t cmask[R], sl_next[R], bm_next[R];
+        auto slot_at = [&](int base, int r, int end) {
+            return stager ? load_slot(a, (uint32_t)(base + 64 * r + lane), (uint32_t)end) : 0xFFFFFFFFu;
+        };
+        auto bm_at = [&](int base, int r, int end) {
+            return stager ? load_bm(a, (uint32_t)(base + 64 * r + lane), (uint32_t)end) : 0u;
+        };
         int e = hi;
-        int bs = max(cs, e - 64);
-        Raw raw0 = load_raw(a, load_slot(a, (uint32_t)(bs + lane), (uint32_t)e), nslots);
-        raw0.bm = load_bm(a, (uint32_t)(bs + lane), (uint32_t)e);
-        Stage cur = derive<TW, TH, true>(a, raw0, fxb, fyb, fox, foy);
-        put_stage(sg, cur, lane);
-        int bs2 = max(cs, bs - 64);
-        uint32_t sl_next = load_slot(a, (uint32_t)(bs2 + lane), (uint32_t)bs);
-        uint32_t bm_next = load_bm(a, (uint32_t)(bs2 + lane), (uint32_t)bs);
-        while (e > cs) {
-            int n = e - bs;
-            int e2 = bs;
-            int bs3 = max(cs, bs2 - 64);
-            Raw raw_next = load_raw(a, sl_next, nslots);                                 // batch [bs2, bs)
-            raw_next.bm = bm_next;
-            uint32_t sl_after = load_slot(a, (uint32_t)(bs3 + lane), (uint32_t)bs2);   // batch [bs3, bs2)
-            uint32_t bm_after = load_bm(a, (uint32_t)(bs3 + lane), (uint32_t)bs2);
-            // the batch's Gaussians with a footprint in the tile, last first (lanes at or past n
-            // carry an empty mask)
-            uint64_t todo = __ballot(cur.mask != 0u && lane < n);
-            while (todo) {
-                const int j = 63 - __builtin_clzll(todo);
-                todo &= ~(1ull << j);
-                const float4 q0 = sg[j][0], q1 = sg[j][1], q2 = sg[j][2];
-                // with one sub-block every Gaussian of the ballot reaches it
-                const uint32_t m = NSB == 1 ? 1u : bcast_u(cur.mask, j);
-                int idx = bs + j;
-                const float mx = q0.x, my = q0.y, A = q0.z, Bc = q0.w, Cc = q1.x, lo2 = q1.y;
-                const float cr = q1.z, cg = q1.w, cb = q2.x;
-                // per-lane sums of dp = dL/dpower and its moments in (dx, dy), and of the colour weights
-                float m0 = 0.f, mx1 = 0.f, my1 = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
-                bool hit_any = false;
+        int bs = max(cs, e - NB);
 #pragma unroll
-                for (int k = 0; k < NSB; ++k) {
-                    if (!(m & (1u << k)) || idx > kmax[k]) continue;  // wave-uniform
-                    float dx = px[k] - mx, dy = py[k] - my;
-                    float al = alpha_of(power2(dx, dy, A, Bc, Cc, lo2), a.amax);
-                    bool hit = (idx <= last[k]) && (al >= a.amin);
-                    if (STATS) n_eval += idx <= last[k];
-                    if (__ballot(hit) == 0) continue;  // wave-uniform
-                    hit_any = true;
-                    if (STATS) n_contrib += hit;
-                    float ah = hit ? al : 0.f;
-                    float iom = __builtin_amdgcn_rcpf(1.f - ah);
-                    float Tj = T[k] * iom;
-                    float w = ah * Tj;
-                    float gdc = __fmaf_rn(gc2[k], cb, __fmaf_rn(gc1[k], cg, gc0[k] * cr));
-                    gr = __fmaf_rn(w, gc0[k], gr);
-                    gg = __fmaf_rn(w, gc1[k], gg);
-                    gbl = __fmaf_rn(w, gc2[k], gbl);
-                    float dal = __fmaf_rn(Tj, gdc, -(iom * P[k]));
-                    P[k] = __fmaf_rn(w, gdc, P[k]);
-                    T[k] = Tj;
-                    float dp = al < a.amax ? dal * ah : 0.f;  // no gradient through the alpha_max clamp
-                    float tx = dp * dx, tyv = dp * dy;
-                    m0 += dp;
-                    mx1 += tx;
-                    my1 += tyv;
-                    mxx = __fmaf_rn(tx, dx, mxx);
-                    mxy = __fmaf_rn(tx, dy, mxy);
-                    myy = __fmaf_rn(tyv, dy, myy);
-                }
-                if (!hit_any) continue;
-                // power = -(a dx^2 + 2 b dx dy + c dy^2)/2 with dx = pixel - mean, and
-                // a = -2 ln2 A, b = -ln2 Bc, c = -2 ln2 Cc:
-                //   dL/dmu = (a Mx + b My, b Mx + c My), dL/d(a, b, c) = (-Mxx/2, -Mxy, -Myy/2),
-                //   dL/do = M0 / o   (applied per lane before the reduction: all linear)
-                float ca = -2.f * LN2 * A, cbv = -LN2 * Bc, ccv = -2.f * LN2 * Cc;
-                float io = q2.y;
-                uint32_t slot = __float_as_uint(q2.z);
-                float vals[9] = {__fmaf_rn(ca, mx1, cbv * my1), __fmaf_rn(cbv, mx1, ccv * my1), -0.5f * mxx, -mxy,
-                                 -0.5f * myy, m0 * io, gr, gg, gbl};
-                float tot = reduce9(vals, c0, c1, c2, c3);
-                if (STATS && lane == 0) ++n_atomic;
-                if (writer) atomicAdd(grad2d + 9 * (size_t)slot + cls, tot);
+        for (int r = 0; r < R; ++r) {
+            Raw raw0 = load_raw(a, slot_at(bs, r, e), nslots);
+            raw0.bm = bm_at(bs, r, e);
+            Stage c = derive<TW, TH, true>(a, raw0, fxb, fyb, fox, foy);
+            put_stage(sg + 64 * r, c, lane);
+            cmask[r] = c.mask;
+        }
+        int bs2 = max(cs, bs - NB);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            sl_next[r] = slot_at(bs2, r, bs);
+            bm_next[r] = bm_at(bs2, r, bs);
+        }
+        while (e > cs) {
+            int e2 = bs;
+            int bs3 = max(cs, bs2 - NB);
+            Raw raw_next[R];
+            uint32_t sl_after[R], bm_after[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                raw_next[r] = load_raw(a, sl_next[r], nslots);  // batch [bs2, bs)
+                raw_next[r].bm = bm_next[r];
             }
-            cur = derive<TW, TH, true>(a, raw_next, fxb, fyb, fox, foy);
-            put_stage(sg, cur, lane);
-            sl_next = sl_after;
-            bm_next = bm_after;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                sl_after[r] = slot_at(bs3, r, bs2);  // batch [bs3, bs2)
+                bm_after[r] = bm_at(bs3, r, bs2);
+            }
+#pragma unroll
+            for (int rr = R - 1; rr >= 0; --rr) {
+                const int sb = bs + 64 * rr;   // first instance of the sub-batch
+                const int n = e - sb;          // instances of the batch at or after sb
+                if (n <= 0) continue;          // wave-uniform: the sub-batch lies past the walk's end
+                const float4(*sgr)[3] = sg + 64 * rr;
+                // the sub-batch's Gaussians with a footprint in the tile, last first (lanes at or past
+                // n carry an empty mask)
+                uint64_t todo = __ballot(cmask[rr] != 0u && lane < n);
+                while (todo) {
+                    const int j = 63 - __builtin_clzll(todo);
+                    todo &= ~(1ull << j);
+                    const float4 q0 = sgr[j][0], q1 = sgr[j][1], q2 = sgr[j][2];
+                    // with one sub-block every Gaussian of the ballot reaches it
+                    const uint32_t m = NSB == 1 ? 1u : bcast_u(cmask[rr], j);
+                    int idx = sb + j;
+                    const float mx = q0.x, my = q0.y, A = q0.z, Bc = q0.w, Cc = q1.x, lo2 = q1.y;
+                    const float cr = q1.z, cg = q1.w, cb = q2.x;
+                    // per-lane sums of dp = dL/dpower and its moments in (dx, dy), and of the colour weights
+                    float m0 = 0.f, mx1 = 0.f, my1 = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, gr = 0.f, gg = 0.f,
+                          gbl = 0.f;
+                    bool hit_any = false;
+#pragma unroll
+                    for (int k = 0; k < NSB; ++k) {
+                        if (!(m & (1u << k)) || idx > kmax[k]) continue;  // wave-uniform
+                        float dx = px[k] - mx, dy = py[k] - my;
+                        float al = alpha_of(power2(dx, dy, A, Bc, Cc, lo2), a.amax);
+                        bool hit = (idx <= last[k]) && (al >= a.amin);
+                        if (STATS) n_eval += idx <= last[k];
+                        if (STATS) w_eval += lane == 0;
+                        if (__ballot(hit) == 0) continue;  // wave-uniform
+                        hit_any = true;
+                        if (STATS) n_contrib += hit;
+                        float ah = hit ? al : 0.f;
+                        float iom = __builtin_amdgcn_rcpf(1.f - ah);
+                        float Tj = T[k] * iom;
+                        float w = ah * Tj;
+                        float gdc = __fmaf_rn(gc2[k], cb, __fmaf_rn(gc1[k], cg, gc0[k] * cr));
+                        gr = __fmaf_rn(w, gc0[k], gr);
+                        gg = __fmaf_rn(w, gc1[k], gg);
+                        gbl = __fmaf_rn(w, gc2[k], gbl);
+                        float dal = __fmaf_rn(Tj, gdc, -(iom * P[k]));
+                        P[k] = __fmaf_rn(w, gdc, P[k]);
+                        T[k] = Tj;
+                        float dp = al < a.amax ? dal * ah : 0.f;  // no gradient through the alpha_max clamp
+                        float tx = dp * dx, tyv = dp * dy;
+                        m0 += dp;
+                        mx1 += tx;
+                        my1 += tyv;
+                        mxx = __fmaf_rn(tx, dx, mxx);
+                        mxy = __fmaf_rn(tx, dy, mxy);
+                        myy = __fmaf_rn(tyv, dy, myy);
+                    }
+                    if (!hit_any) continue;
+                    // the slot's gradient is left as the moments of dL/dpower (the projection adjoint
+                    // turns them into dL/dmu, dL/dconic and dL/do with its own conic and opacity:
+                    // all linear in the moments, so the sum over tiles commutes with it)
+                    uint32_t slot = __float_as_uint(q2.z);
+                    float vals[9] = {mx1, my1, mxx, mxy, myy, m0, gr, gg, gbl};
+                    float tot = reduce9(vals, c0, c1, c2, c3);
+                    if (STATS && lane == 0) ++n_atomic;
+                    if (writer) atomicAdd(grad2d + 9 * (size_t)slot + cls, tot);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                Stage c = derive<TW, TH, true>(a, raw_next[r], fxb, fyb, fox, foy);
+                put_stage(sg + 64 * r, c, lane);
+                cmask[r] = c.mask;
+                sl_next[r] = sl_after[r];
+                bm_next[r] = bm_after[r];
+            }
             e = e2;
             bs = bs2;
             bs2 = bs3;
@@ -706,6 +773,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a, const floa
         stat_add(a.stats + 2, n_eval);
         stat_add(a.stats + 3, n_contrib);
         stat_add(a.stats + 4, n_atomic);
+        stat_add(a.stats + 7, w_eval);
     }
 }
 
@@ -752,7 +820,7 @@ int persistent_grid(int n_items, int wg_per_cu) {
     return g < n_items ? g : n_items;
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int NB>
 int fwd_impl(const splat_plan &p, void *ws, float *img, float *T, int32_t *last, unsigned long long *stats,
              hipStream_t st) {
     RenderArgs a = make_args(p, ws, stats);
@@ -762,7 +830,7 @@ int fwd_impl(const splat_plan &p, void *ws, float *img, float *T, int32_t *last,
     if (joined) {
         // chunks 1.. of the split lists on their own (about equal work items: a static grid)
         int g1 = persistent_grid((int)(p.chk_cap < INT32_MAX ? p.chk_cap : INT32_MAX), 32);
-        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, false, 1>), dim3(g1), dim3(64), 0, st, a, img, T, last);
+        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, false, 1, NB>), dim3(g1), dim3(64), 0, st, a, img, T, last);
         if ((rc = launch_status("render_fwd_chunks"))) return rc;
     }
     int grid = a.n_items;
@@ -772,15 +840,15 @@ int fwd_impl(const splat_plan &p, void *ws, float *img, float *T, int32_t *last,
         grid = persistent_grid(a.n_items, 32);
     }
     if (stats)
-        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, true, 0>), dim3(grid), dim3(64), 0, st, a, img, T, last);
+        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, true, 0, NB>), dim3(grid), dim3(64), 0, st, a, img, T, last);
     else if (joined)
-        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, false, 2>), dim3(grid), dim3(64), 0, st, a, img, T, last);
+        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, false, 2, NB>), dim3(grid), dim3(64), 0, st, a, img, T, last);
     else
-        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, false, 0>), dim3(grid), dim3(64), 0, st, a, img, T, last);
+        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, false, 0, NB>), dim3(grid), dim3(64), 0, st, a, img, T, last);
     return launch_status("render_fwd");
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int NB>
 int bwd_impl(const splat_plan &p, void *ws, const float *dimg, const float *T, const int32_t *last,
              unsigned long long *stats, hipStream_t st) {
     RenderArgs a = make_args(p, ws, stats);
@@ -796,10 +864,40 @@ int bwd_impl(const splat_plan &p, void *ws, const float *dimg, const float *T, c
         grid = persistent_grid(nT, 32);
     }
     if (stats)
-        hipLaunchKernelGGL((render_bwd_kernel<TW, TH, true>), dim3(grid), dim3(64), 0, st, a, dimg, T, last, g2);
+        hipLaunchKernelGGL((render_bwd_kernel<TW, TH, true, NB>), dim3(grid), dim3(64), 0, st, a, dimg, T, last, g2);
     else
-        hipLaunchKernelGGL((render_bwd_kernel<TW, TH, false>), dim3(grid), dim3(64), 0, st, a, dimg, T, last, g2);
+        hipLaunchKernelGGL((render_bwd_kernel<TW, TH, false, NB>), dim3(grid), dim3(64), 0, st, a, dimg, T, last, g2);
     return launch_status("render_bwd");
+}
+
+// Gaussians staged per LDS batch: the settings' value, at most the split length (chunk starts
+// are batch starts); results do not depend on it
+int batch_of(const splat_plan &p) { return p.s.batch < p.split_len ? p.s.batch : p.split_len; }
+
+template <int TW, int TH>
+int fwd_tile(const splat_plan &p, void *ws, float *img, float *T, int32_t *last, unsigned long long *s,
+             hipStream_t st) {
+    switch (batch_of(p)) {
+        case 32: return fwd_impl<TW, TH, 32>(p, ws, img, T, last, s, st);
+        case 64: return fwd_impl<TW, TH, 64>(p, ws, img, T, last, s, st);
+        case 128: return fwd_impl<TW, TH, 128>(p, ws, img, T, last, s, st);
+        case 256: return fwd_impl<TW, TH, 256>(p, ws, img, T, last, s, st);
+    }
+    set_error("render_fwd: unsupported batch %d", p.s.batch);
+    return SPLAT_EUNSUPPORTED;
+}
+
+template <int TW, int TH>
+int bwd_tile(const splat_plan &p, void *ws, const float *dimg, const float *T, const int32_t *last,
+             unsigned long long *s, hipStream_t st) {
+    switch (batch_of(p)) {
+        case 32: return bwd_impl<TW, TH, 32>(p, ws, dimg, T, last, s, st);
+        case 64: return bwd_impl<TW, TH, 64>(p, ws, dimg, T, last, s, st);
+        case 128: return bwd_impl<TW, TH, 128>(p, ws, dimg, T, last, s, st);
+        case 256: return bwd_impl<TW, TH, 256>(p, ws, dimg, T, last, s, st);
+    }
+    set_error("render_bwd: unsupported batch %d", p.s.batch);
+    return SPLAT_EUNSUPPORTED;
 }
 
 }  // namespace
@@ -808,10 +906,10 @@ int launch_render_fwd(const splat_plan &p, void *ws, float *img, float *T, int32
                       hipStream_t st) {
     int tw = p.s.tile_w, th = p.s.tile_h;
     auto *s = reinterpret_cast<unsigned long long *>(stats);
-    if (tw == 16 && th == 16) return fwd_impl<16, 16>(p, ws, img, T, last, s, st);
-    if (tw == 8 && th == 8) return fwd_impl<8, 8>(p, ws, img, T, last, s, st);
-    if (tw == 16 && th == 32) return fwd_impl<16, 32>(p, ws, img, T, last, s, st);
-    if (tw == 32 && th == 16) return fwd_impl<32, 16>(p, ws, img, T, last, s, st);
+    if (tw == 16 && th == 16) return fwd_tile<16, 16>(p, ws, img, T, last, s, st);
+    if (tw == 8 && th == 8) return fwd_tile<8, 8>(p, ws, img, T, last, s, st);
+    if (tw == 16 && th == 32) return fwd_tile<16, 32>(p, ws, img, T, last, s, st);
+    if (tw == 32 && th == 16) return fwd_tile<32, 16>(p, ws, img, T, last, s, st);
     set_error("render_fwd: unsupported tile %dx%d", tw, th);
     return SPLAT_EUNSUPPORTED;
 }
@@ -820,10 +918,10 @@ int launch_render_bwd(const splat_plan &p, void *ws, const float *dimg, const fl
                       uint64_t *stats, hipStream_t st) {
     int tw = p.s.tile_w, th = p.s.tile_h;
     auto *s = reinterpret_cast<unsigned long long *>(stats);
-    if (tw == 16 && th == 16) return bwd_impl<16, 16>(p, ws, dimg, T, last, s, st);
-    if (tw == 8 && th == 8) return bwd_impl<8, 8>(p, ws, dimg, T, last, s, st);
-    if (tw == 16 && th == 32) return bwd_impl<16, 32>(p, ws, dimg, T, last, s, st);
-    if (tw == 32 && th == 16) return bwd_impl<32, 16>(p, ws, dimg, T, last, s, st);
+    if (tw == 16 && th == 16) return bwd_tile<16, 16>(p, ws, dimg, T, last, s, st);
+    if (tw == 8 && th == 8) return bwd_tile<8, 8>(p, ws, dimg, T, last, s, st);
+    if (tw == 16 && th == 32) return bwd_tile<16, 32>(p, ws, dimg, T, last, s, st);
+    if (tw == 32 && th == 16) return bwd_tile<32, 16>(p, ws, dimg, T, last, s, st);
     set_error("render_bwd: unsupported tile %dx%d", tw, th);
     return SPLAT_EUNSUPPORTED;
 }

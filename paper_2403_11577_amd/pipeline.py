@@ -73,6 +73,14 @@ class DeviceScene:
         vt = np.asarray(scene.views.t, np.float64)
         if views is not None:
             cam, vt = cam[views], vt[views]
+        # what the pose kernels cannot check on the device: knot times strictly increasing,
+        # every view's camera index inside the rig (checked once here, on the host copy)
+        kt = np.asarray(scene.traj.t, np.float64)
+        if kt.ndim != 1 or kt.size < 2 or not np.all(np.diff(kt) > 0):
+            raise B.SplatError("trajectory knot times must be at least two and strictly increasing")
+        n_cams = int(np.asarray(scene.rig.R0).reshape(-1, 9).shape[0])
+        if cam.size and (cam.min() < 0 or cam.max() >= n_cams):
+            raise B.SplatError(f"view camera indices must lie in [0, {n_cams})")
         return DeviceScene(f32(g.mean), f32(g.quat), f32(g.scale), f32(g.opacity), f32(g.color),
                            f64(scene.traj.t), f64(scene.traj.q), f64(scene.traj.p),
                            f64(scene.rig.R0.reshape(-1, 9)), f64(scene.rig.t0),
@@ -103,6 +111,9 @@ class Frame:
         self.T = torch.empty((n_views, H, W), dtype=torch.float32, device=device)
         self.last = torch.empty((n_views, H, W), dtype=torch.int32, device=device)
         self.w2c = torch.empty((n_views, 12), dtype=torch.float64, device=device)
+        # bumped by every render into this frame: the adjoint reads the workspace state (sorted
+        # lists, checkpoints, blend masks) and T / last of the most recent forward only
+        self.generation = 0
         self.clear_status()
 
     # typed views into the workspace ----------------------------------------------------
@@ -173,6 +184,7 @@ def forward(fr: Frame, ds: DeviceScene, xi: torch.Tensor, delta: torch.Tensor, g
     else:
         fr.w2c.copy_(w2c)
     g = ds.gaussians() if gauss is None else gauss
+    fr.generation += 1
     B.splat_project(fr.plan, fr.ws, g, fr.w2c, ds.intr)
     B.splat_bin_sort(fr.plan, fr.ws)
     B.splat_render_fwd(fr.plan, fr.ws, fr.img, fr.T, fr.last)
@@ -284,6 +296,7 @@ class BatchedStep:
         self.loss.zero_()
         zero_grads(self.gr)
         pose_fwd(fr, ds, self.xi, self.delta)
+        fr.generation += 1
         B.splat_project(fr.plan, fr.ws, ds.gaussians(), fr.w2c, ds.intr)
         B.splat_bin_sort(fr.plan, fr.ws)
         ev = self.events
@@ -322,6 +335,7 @@ class BatchedStep:
         fr, ds = self.fr, self.ds
         st = torch.zeros(8, dtype=torch.int64, device=ds.opacity.device)
         pose_fwd(fr, ds, self.xi, self.delta)
+        fr.generation += 1
         B.splat_project(fr.plan, fr.ws, ds.gaussians(), fr.w2c, ds.intr)
         B.splat_bin_sort(fr.plan, fr.ws)
         B.splat_render_fwd_stats(fr.plan, fr.ws, fr.img, fr.T, fr.last, st)
@@ -331,7 +345,7 @@ class BatchedStep:
         v = st.cpu().tolist()
         ns, ni = fr.counts()
         return dict(fwd_eval=v[0], fwd_blend=v[1], bwd_eval=v[2], bwd_contrib=v[3], bwd_atomic_groups=v[4],
-                    slots=ns, instances=ni)
+                    fwd_wave_evals=v[5], fwd_wave_blends=v[6], bwd_wave_evals=v[7], slots=ns, instances=ni)
 
 
 # -----------------------------------------------------------------------------
@@ -358,26 +372,30 @@ class PerViewPlain:
             fr = fit_frame(dv, xi, delta, s)
             self.views.append((dv, fr, alloc_grads(dv)))
 
-    def step(self, xi, delta, targets, gr: Grads):
-        """fwd + L1 + bwd over every view, one view at a time; returns the loss."""
+    def step(self, xi, delta, targets, gr: Grads, sync=True):
+        """fwd + L1 + bwd over every view, one view at a time; returns the loss (a device
+        tensor when sync is False: then no stage waits for the host and no count is read)."""
         total = 0.0
-        sync = torch.cuda.synchronize
+        sync_fn = torch.cuda.synchronize if sync else (lambda: None)
         for v, (dv, fr, g1) in enumerate(self.views):
-            pose_fwd(fr, dv, xi, delta); sync()
-            B.splat_project(fr.plan, fr.ws, dv.gaussians(), fr.w2c, dv.intr); sync()
-            fr.counts()
-            B.splat_bin_sort(fr.plan, fr.ws); sync()
-            fr.counts()
-            B.splat_render_fwd(fr.plan, fr.ws, fr.img, fr.T, fr.last); sync()
+            fr.generation += 1
+            pose_fwd(fr, dv, xi, delta); sync_fn()
+            B.splat_project(fr.plan, fr.ws, dv.gaussians(), fr.w2c, dv.intr); sync_fn()
+            if sync:
+                fr.counts()
+            B.splat_bin_sort(fr.plan, fr.ws); sync_fn()
+            if sync:
+                fr.counts()
+            B.splat_render_fwd(fr.plan, fr.ws, fr.img, fr.T, fr.last); sync_fn()
             L, dimg = l1_loss_grad(fr.img, targets[v:v + 1], roi_y0=fr.settings.roi_y0)
             dimg.mul_(1.0 / len(self.views))  # mean over all views, as in the batched step
-            total += float(L) / len(self.views)
+            total = total + (float(L) if sync else L) / len(self.views)
             zero_grads(g1)
-            B.splat_render_bwd(fr.plan, fr.ws, dimg, fr.T, fr.last); sync()
+            B.splat_render_bwd(fr.plan, fr.ws, dimg, fr.T, fr.last); sync_fn()
             B.splat_project_bwd(fr.plan, fr.ws, dv.gaussians(), fr.w2c, dv.intr, g1.quat, g1.scale,
-                                g1.opacity, g1.color, None, g1.w2c); sync()
+                                g1.opacity, g1.color, None, g1.w2c); sync_fn()
             B.splat_pose_interp_bwd(dv.knot_t, dv.knot_q, dv.knot_p, dv.R0, dv.t0, xi, delta, dv.view_cam,
-                                    dv.view_t, g1.w2c, g1.xi, g1.delta); sync()
+                                    dv.view_t, g1.w2c, g1.xi, g1.delta); sync_fn()
             gr.quat += g1.quat; gr.scale += g1.scale; gr.opacity += g1.opacity; gr.color += g1.color
             gr.xi += g1.xi; gr.delta += g1.delta
         return total
@@ -392,13 +410,18 @@ class SplatRender(torch.autograd.Function):
     backward returns d(loss)/d quat, scale, opacity, colour, d(loss)/d xi
     (extrinsic se(3) correction, rho then phi) and d(loss)/d delta (time offset),
     all from the hand-written adjoint kernels.
+
+    The adjoint reads what the forward left in the Frame (sorted lists, checkpoints,
+    blend masks, T and last contributor), so one Frame serves one live graph node:
+    rendering into the same Frame again before this node's backward makes the
+    backward raise instead of returning the gradients of the other render.
     """
 
     @staticmethod
     def forward(ctx, quat, scale, opacity, color, xi, delta, fr: Frame, ds: DeviceScene):
         g = ds.gaussians(quat, scale, opacity, color)
         forward(fr, ds, xi, delta, gauss=g)
-        ctx.fr, ctx.ds = fr, ds
+        ctx.fr, ctx.ds, ctx.generation = fr, ds, fr.generation
         ctx.save_for_backward(quat, scale, opacity, color, xi, delta)
         return fr.img.clone()
 
@@ -406,6 +429,9 @@ class SplatRender(torch.autograd.Function):
     def backward(ctx, dimg):
         quat, scale, opacity, color, xi, delta = ctx.saved_tensors
         fr, ds = ctx.fr, ctx.ds
+        if fr.generation != ctx.generation:
+            raise B.SplatError("SplatRender.backward: the Frame was rendered into again after this forward; "
+                               "give each live render its own Frame")
         gr = alloc_grads(ds)
         g = ds.gaussians(quat, scale, opacity, color)
         backward(fr, ds, xi, delta, dimg.contiguous(), gr, gauss=g)

@@ -79,7 +79,7 @@ def test_plan_make_rejects_bad_shapes(kw, msg):
 
 
 @pytest.mark.parametrize("field, value", [
-    ("tile_w", 12), ("batch", 8), ("batch", 300), ("near_z", 0.0), ("far_z", 0.1),
+    ("tile_w", 12), ("batch", 8), ("batch", 300), ("batch", 16), ("batch", 48), ("near_z", 0.0), ("far_z", 0.1),
     ("alpha_min", 0.0), ("alpha_max", 1.0), ("t_min", 0.0), ("eps2d", -1.0), ("persistent", 2),
     ("split_len", 32), ("split_len", 96), ("split_len", 1 << 25), ("split_len", -64), ("split_fwd", 2),
 ])
@@ -253,3 +253,42 @@ def test_adam_step_rejects_bad_groups_without_a_device():
     g[1].act = 7
     assert L.splat_adam_step(g, 2, 0.9, 0.999, 1e-15, step, None) == -1
     assert b"activation" in L.splat_last_error()
+
+
+def test_binding_checks_buffers_before_the_library():
+    """The wrappers refuse host tensors, wrong element types and undersized buffers on the host,
+    before anything reaches the library (which cannot see tensor sizes)."""
+    import torch
+    p = B.splat_plan_make(B.default_settings(), 2, 10, 32, 16, 20, 100)
+    ws = torch.empty(int(p.ws_bytes), dtype=torch.uint8)
+    img = torch.empty((2, 3, 16, 32))
+    T = torch.empty((2, 16, 32))
+    last = torch.empty((2, 16, 32), dtype=torch.int32)
+    with pytest.raises(B.SplatError, match="device"):
+        B.splat_render_fwd(p, ws, img, T, last)
+    with pytest.raises(B.SplatError, match="device"):
+        B.splat_bin_sort(p, ws)
+    with pytest.raises(B.SplatError, match="device"):
+        B.splat_l1_loss_grad(img, img, None, img)
+
+
+def test_device_scene_rejects_bad_trajectories_and_cameras():
+    """Knot times must increase strictly and view cameras must exist: checked once on the host,
+    since the pose kernels read these only on the device."""
+    import dataclasses
+    import numpy as np
+    import synth
+    from paper_2403_11577_amd import pipeline as pl
+    s = synth.small_drive(0, n_frames=1)
+    pl.DeviceScene.from_scene(s, device="cpu")
+    t = np.asarray(s.traj.t, np.float64).copy()
+    t[3] = t[2]
+    bad = dataclasses.replace(s, traj=dataclasses.replace(s.traj, t=t))
+    with pytest.raises(B.SplatError, match="strictly increasing"):
+        pl.DeviceScene.from_scene(bad, device="cpu")
+    cam = np.asarray(s.views.cam).copy()
+    cam[0] = 2
+    bad = dataclasses.replace(s, views=dataclasses.replace(s.views, cam=cam))
+    with pytest.raises(B.SplatError, match="camera indices"):
+        pl.DeviceScene.from_scene(bad, device="cpu")
+

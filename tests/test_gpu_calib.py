@@ -42,8 +42,12 @@ def test_autotune_picks_a_candidate_and_results_are_shape_independent():
     dl = torch.as_tensor(s.delta, dtype=torch.float64, device="cuda")
     tgt = torch.zeros((ds.n_views, 3, ds.H, ds.W), dtype=torch.float32, device="cuda")
     st, rep = at.autotune(ds, xi, dl, tgt, steps=2, use_cache=False)
-    assert len(rep["candidates"]) == 16  # 4 tile shapes x grid/persistent x joined forward or not
+    # 4 tile shapes x grid/persistent x joined forward or not at 64 Gaussians per LDS batch, then the
+    # winner at 32, 128 and 256
+    assert len(rep["candidates"]) == 19
+    assert sorted(c["batch"] for c in rep["candidates"][16:]) == [32, 128, 256]
     assert rep["best"]["ms"] == min(c["ms"] for c in rep["candidates"])
+    assert st.batch == rep["best"]["batch"]
     a = pl.BatchedStep(ds, xi, dl, tgt, st)
     b = pl.BatchedStep(ds, xi, dl, tgt, pl.make_settings())
     a.run()

@@ -165,12 +165,67 @@ def test_render_invariant_across_launch_shapes():
     scene = synth.small_drive(4, n_frames=2)
     base = gpu_render(scene, tile=(16, 16), batch=64, persistent=True)
     for tile in TILES:
-        for batch in (16, 64, 256):
+        for batch in (32, 64, 128, 256):
             for pers in (True, False):
                 o = gpu_render(scene, tile=tile, batch=batch, persistent=pers)
                 assert np.array_equal(o["img"], base["img"]), (tile, batch, pers)
                 assert np.array_equal(o["T"], base["T"])
                 assert np.array_equal(o["last_id"], base["last_id"])
+
+
+def _read_blend_masks(o):
+    """The blend masks the adjoint reads: in every tile list, the instances up to the last
+    contributor of any pixel of the tile (the forward leaves the rest of a list unwritten once
+    every pixel of the tile has stopped)."""
+    fr = o["frame"]
+    V, H, W = o["T"].shape
+    TW, TH = int(fr.plan.s.tile_w), int(fr.plan.s.tile_h)
+    tx_n, nt = int(fr.plan.tiles_x), int(fr.plan.tiles_per_view)
+    rg = fr.ranges().cpu().numpy().astype(np.int64)
+    lp = o["last_pos"]
+    yy, xx = np.mgrid[0:H, 0:W]
+    tile = (yy // TH) * tx_n + xx // TW
+    maxlp = np.full(V * nt, -1, np.int64)
+    for v in range(V):
+        np.maximum.at(maxlp, v * nt + tile.ravel(), lp[v].ravel())
+    bm = fr.buf("bmask", torch.uint8, int(o["inst"])).cpu().numpy()
+    pos = np.arange(bm.size)
+    owner = np.repeat(np.arange(rg.shape[0]), np.maximum(rg[:, 1] - rg[:, 0], 0))
+    starts = np.repeat(rg[:, 0], np.maximum(rg[:, 1] - rg[:, 0], 0))
+    assert np.array_equal(starts + (pos - np.repeat(np.cumsum(np.maximum(rg[:, 1] - rg[:, 0], 0)) -
+                                                    np.maximum(rg[:, 1] - rg[:, 0], 0),
+                                                    np.maximum(rg[:, 1] - rg[:, 0], 0))), pos)
+    return np.where(pos <= maxlp[owner], bm, 0)
+
+
+@pytest.mark.parametrize("split_len, split_fwd", [(64, 0), (64, 1), (256, 1)])
+def test_batch_size_invariance_with_split_lists(split_len, split_fwd):
+    """Gaussians per LDS batch (32, 64, 128, 256; at most the split length) change only the
+    staging: images, T and last ids are bitwise those of batch 64 (also for lists split into
+    chunks and joined), the blend masks the adjoint reads are the same, and the gradients agree
+    to float-atomic ordering."""
+    say(f"case: batch invariance, split_len={split_len} split_fwd={split_fwd}")
+    scene = synth.small_drive(4, n_frames=2)
+    outs = {}
+    for batch in (64, 32, 128, 256):
+        o = gpu_render(scene, tile=(8, 8), batch=batch, persistent=False, split_len=split_len,
+                       split_fwd=split_fwd)
+        fr = o["frame"]
+        dimg = torch.as_tensor(np.sign(o["img"] - 0.4).astype(np.float32) * 1e-3, device="cuda")
+        gr = pl.alloc_grads(o["ds"])
+        pl.backward(fr, o["ds"], o["xi"], o["delta"], dimg, gr)
+        torch.cuda.synchronize()
+        outs[batch] = (o, _read_blend_masks(o),
+                       {n: getattr(gr, n).cpu().numpy() for n in ("quat", "scale", "opacity", "color", "xi", "delta")})
+    ref, ref_bm, ref_g = outs[64]
+    for batch, (o, bm, g) in outs.items():
+        assert np.array_equal(o["img"], ref["img"]), batch
+        assert np.array_equal(o["T"], ref["T"]), batch
+        assert np.array_equal(o["last_id"], ref["last_id"]), batch
+        assert np.array_equal(bm, ref_bm), batch
+        for n in g:
+            ok, err = rel_close(g[n], ref_g[n], 1e-5)
+            assert ok, (batch, n, err)
 
 
 def _grad_case(scene, tile, seed=0, split_len=0, persistent=True, keep=None, split_fwd=0):
@@ -407,6 +462,34 @@ def test_autograd_function_matches_kernels():
     for a, b in ((co.grad, step.gr.color), (xi.grad, step.gr.xi), (dl.grad, step.gr.delta), (q.grad, step.gr.quat)):
         ok, err = rel_close(a.detach().cpu().numpy(), b.cpu().numpy(), 1e-4)
         assert ok, err
+    # a second render into the same Frame before the first node's backward: that backward would
+    # read the second render's lists, so it must refuse
+    img1 = pl.SplatRender.apply(q, sc, op, co, xi, dl, step.fr, ds)
+    img2 = pl.SplatRender.apply(q, sc * 1.01, op, co, xi, dl, step.fr, ds)
+    with pytest.raises(B.SplatError, match="rendered into again"):
+        (img1 - step.targets).abs().mean().backward()
+    (img2 - step.targets).abs().mean().backward()   # the latest render still differentiates
+
+
+def test_binding_rejects_undersized_and_misplaced_buffers():
+    """The wrappers check element types, contiguity, device and sizes before any launch: the
+    kernels trust the sizes the plan implies, so a wrong buffer must not reach them."""
+    say("case: binding argument checks")
+    scene = synth.small_drive(7, n_frames=2)
+    step = _step_for(scene)
+    fr = step.fr
+    with pytest.raises(B.SplatError, match="elements"):
+        B.splat_render_fwd(fr.plan, fr.ws, fr.img[:1], fr.T, fr.last)
+    with pytest.raises(B.SplatError, match="dtype"):
+        B.splat_render_bwd(fr.plan, fr.ws, step.dimg.double(), fr.T, fr.last)
+    with pytest.raises(B.SplatError, match="contiguous"):
+        B.splat_render_fwd(fr.plan, fr.ws, fr.img.transpose(2, 3), fr.T, fr.last)
+    with pytest.raises(B.SplatError, match="device"):
+        B.splat_render_fwd(fr.plan, fr.ws, fr.img.cpu(), fr.T, fr.last)
+    with pytest.raises(B.SplatError, match="plan needs"):
+        B.splat_bin_sort(fr.plan, fr.ws[:16])
+    with pytest.raises(B.SplatError, match="elements"):
+        B.splat_project(fr.plan, fr.ws, step.ds.gaussians(), fr.w2c[:1], step.ds.intr)
 
 
 def test_per_view_plain_matches_batched():
