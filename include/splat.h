@@ -319,6 +319,26 @@ SPLAT_API int splat_dssim_loss_grad(const float *img, const float *target, int32
                                     float *dL_dimg, double *loss, void *stream);
 
 /*
+ * splat_dssim_loss_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments and results without ws.  The three gradient maps live in a fixed
+ * array inside the library that holds SPLAT_DSSIM_NOALLOC_MAX_PX pixel-channels,
+ * i.e. 3 * n_views * (height - roi_y0) * width must not exceed it (192 MiB of
+ * device memory, reserved on every GPU the library runs on until the process
+ * ends); a larger input returns SPLAT_EINVAL and launches nothing.  The call
+ * allocates nothing and calls no allocating routine; the array's device address
+ * is looked up once per device, on the first call with that device current.
+ * Every call on one GPU uses that GPU's one array, so calls that overlap on one
+ * GPU (other streams, other threads) race and give undefined results; calls
+ * ordered on one stream are safe.  Nothing of the array needs clearing: each call
+ * writes every entry it reads.
+ */
+#define SPLAT_DSSIM_NOALLOC_MAX_PX (1 << 24)
+SPLAT_API int splat_dssim_loss_grad_noalloc(const float *img, const float *target, int32_t n_views, int32_t width,
+                                            int32_t height, int32_t roi_y0, double weight, float *dL_dimg,
+                                            double *loss, void *stream);
+
+/*
  * Instrumented variants of splat_render_fwd / splat_render_bwd: identical
  * outputs, plus pair counters ADDED into stats (uint64 device array, caller
  * zeroes, 8 entries): [0] forward evaluated (pixel, Gaussian) pairs, [1] forward

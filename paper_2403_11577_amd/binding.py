@@ -100,6 +100,7 @@ def lib():
     L.splat_dssim_workspace_size.argtypes = [I32, I32, I32, I32]
     L.splat_dssim_workspace_size.restype = C.c_size_t
     L.splat_dssim_loss_grad.argtypes = [P, P, I32, I32, I32, I32, C.c_double, P, C.c_size_t, P, P, P]
+    L.splat_dssim_loss_grad_noalloc.argtypes = [P, P, I32, I32, I32, I32, C.c_double, P, P, P]
     L.splat_scale_reg.argtypes = [P, I64, C.c_double, P, P, P]
     L.splat_adam_step.argtypes = [C.POINTER(splat_adam_group), I32, C.c_double, C.c_double, C.c_double, P, P]
     L.splat_last_error.restype = C.c_char_p
@@ -321,6 +322,18 @@ def splat_dssim_loss_grad(img, target, ws, dL_dimg, loss=None, roi_y0=0, weight=
                                        _arg(ws, "ws", "u8"), int(ws.numel() * ws.element_size()), pd,
                                        _arg(loss, "loss", "f64", 1, at_least=True, optional=True),
                                        _stream(stream)), "splat_dssim_loss_grad")
+
+
+DSSIM_NOALLOC_MAX_PX = 1 << 24
+
+
+def splat_dssim_loss_grad_noalloc(img, target, dL_dimg, loss=None, roi_y0=0, weight=0.2, stream=None):
+    """splat_dssim_loss_grad without a workspace (the library's fixed scratch array)."""
+    V, _, H, W = img.shape
+    pi, pt, pd = _image_pair(img, target, dL_dimg)
+    _check(lib().splat_dssim_loss_grad_noalloc(pi, pt, int(V), int(W), int(H), int(roi_y0), float(weight), pd,
+                                               _arg(loss, "loss", "f64", 1, at_least=True, optional=True),
+                                               _stream(stream)), "splat_dssim_loss_grad_noalloc")
 
 
 def splat_adam_step(groups, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):

@@ -356,6 +356,28 @@ int splat_dssim_loss_grad(const float *img, const float *target, int32_t n_views
     return launch_dssim(img, target, n_views, width, height, roi_y0, weight, ws, dL_dimg, loss, (hipStream_t)stream);
 }
 
+int splat_dssim_loss_grad_noalloc(const float *img, const float *target, int32_t n_views, int32_t width,
+                                  int32_t height, int32_t roi_y0, double weight, float *dL_dimg, double *loss,
+                                  void *stream) {
+    g_err[0] = 0;
+    if (!img || !target || !dL_dimg) { set_error("dssim_loss_grad_noalloc: NULL argument"); return SPLAT_EINVAL; }
+    if (n_views < 1 || width < 1 || height < 1) { set_error("dssim_loss_grad_noalloc: bad shape"); return SPLAT_EINVAL; }
+    if (roi_y0 < 0 || roi_y0 >= height) {
+        set_error("dssim_loss_grad_noalloc: roi_y0 %d outside [0, %d)", roi_y0, height); return SPLAT_EINVAL;
+    }
+    if (!std::isfinite(weight)) { set_error("dssim_loss_grad_noalloc: weight must be finite"); return SPLAT_EINVAL; }
+    const int64_t px = 3 * (int64_t)n_views * (int64_t)(height - roi_y0) * (int64_t)width;
+    if (px > (int64_t)SPLAT_DSSIM_NOALLOC_MAX_PX) {
+        set_error("dssim_loss_grad_noalloc: %lld pixel-channels exceed the maximum of %lld "
+                  "(use splat_dssim_loss_grad with a workspace)", (long long)px, (long long)SPLAT_DSSIM_NOALLOC_MAX_PX);
+        return SPLAT_EINVAL;
+    }
+    float *G = nullptr;
+    int rc = dssim_scratch(&G);
+    if (rc) return rc;
+    return launch_dssim(img, target, n_views, width, height, roi_y0, weight, G, dL_dimg, loss, (hipStream_t)stream);
+}
+
 int splat_scale_reg(const float *scale, int64_t n, double lambda, float *dscale, double *loss, void *stream) {
     g_err[0] = 0;
     if (n < 0) { set_error("scale_reg: n must be >= 0"); return SPLAT_EINVAL; }

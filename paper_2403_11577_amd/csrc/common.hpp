@@ -105,6 +105,8 @@ int launch_ngp_bwd_saved(const splat_ngp &m, int64_t n, const void *index, const
                          float *dw2, float *db2, float *dw3, float *db3, hipStream_t st);
 int launch_dssim(const float *img, const float *target, int64_t n_views, int32_t width, int32_t height,
                  int32_t roi_y0, double weight, void *ws, float *dimg, double *loss, hipStream_t st);
+// device address of the current GPU's D-SSIM scratch array (allocation-free entry point)
+int dssim_scratch(float **out);
 
 // device exclusive scan of u32 (binsort.hip): out[i] = sum in[0..i), out[n] = total;
 // n is read from *n_dev (clamped to n_cap); partials needs scan_partials(n_cap) u32.

@@ -13,7 +13,14 @@
 // per pixel; ssim_bwd filters G and adds the gradient into dL/dimg.  Workgroups
 // take 32 x 32 output tiles; in each pass a thread filters 14 inputs held in
 // registers into 4 outputs.
+#include <mutex>
+
 #include "common.hpp"
+
+// Gradient maps of the allocation-free entry point, one copy per GPU.  In host code
+// the name is only a host-side stand-in: kernels receive the device address that
+// hipGetSymbolAddress returns (dssim_scratch below).
+static __device__ __align__(256) float scratch[3 * (size_t)SPLAT_DSSIM_NOALLOC_MAX_PX];
 
 namespace splat {
 namespace {
@@ -227,6 +234,35 @@ int launch_dssim(const float *img, const float *target, int64_t n_views, int32_t
     if (rc) return rc;
     hipLaunchKernelGGL(ssim_bwd_kernel, grid, dim3(256), 0, st, a, img, target, G, dimg);
     return launch_status("ssim_bwd");
+}
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch[kMaxDevices];  // device address of each GPU's scratch array, once looked up
+}  // namespace
+
+// Device address of the current GPU's scratch array: looked up on the first call on that
+// device (with it current) and kept; every later call reuses it.
+int dssim_scratch(float **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        set_error("dssim_loss_grad_noalloc: no current device below %d", kMaxDevices);
+        return SPLAT_ELAUNCH;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("dssim_loss_grad_noalloc: hipGetSymbolAddress of the scratch array failed on device %d: %s",
+                      dev, hipGetErrorString(e));
+            return SPLAT_ELAUNCH;
+        }
+        g_scratch[dev] = static_cast<float *>(p);
+    }
+    *out = g_scratch[dev];
+    return 0;
 }
 
 }  // namespace splat

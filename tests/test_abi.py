@@ -292,3 +292,13 @@ def test_device_scene_rejects_bad_trajectories_and_cameras():
     with pytest.raises(B.SplatError, match="camera indices"):
         pl.DeviceScene.from_scene(bad, device="cpu")
 
+
+def test_noalloc_dssim_rejects_oversized_inputs_on_the_host():
+    """The allocation-free D-SSIM call checks its size against the fixed array before it
+    touches a device: nothing is launched, so no GPU is needed."""
+    L = B.lib()
+    big = B.DSSIM_NOALLOC_MAX_PX // (3 * 64 * 64) + 1
+    assert L.splat_dssim_loss_grad_noalloc(C.c_void_p(16), C.c_void_p(16), big, 64, 64, 0, 0.2, C.c_void_p(16),
+                                           None, None) == -1
+    assert b"exceed the maximum" in L.splat_last_error()
+    assert L.splat_dssim_loss_grad_noalloc(None, None, 1, 8, 8, 0, 0.2, None, None, None) == -1
