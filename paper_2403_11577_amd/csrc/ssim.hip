@@ -11,8 +11,9 @@
 // Two launches: ssim_fwd forms the moments (separable filter through LDS, float64
 // accumulation, which keeps m11 - m1^2 free of float32 cancellation) and stores G
 // per pixel; ssim_bwd filters G and adds the gradient into dL/dimg.  Workgroups
-// take 32 x 32 output tiles; in each pass a thread filters 14 inputs held in
-// registers into 4 outputs.
+// take 32 x 21 output tiles: the row pass then has exactly one item (4 outputs of
+// one of the 31 halo rows) per thread and the column pass 3 outputs per thread,
+// and three workgroups fit a compute unit's LDS.
 #include <mutex>
 
 #include "common.hpp"
@@ -27,10 +28,12 @@ namespace {
 
 constexpr int SR = 5;                 // window radius
 constexpr int SW = 2 * SR + 1;        // window width
-constexpr int OX = 32, OY = 32;       // output tile
+constexpr int OX = 32, OY = 21;       // output tile
 constexpr int IX = OX + 2 * SR, IY = OY + 2 * SR;
-constexpr int CPT = 4;                // outputs per thread along the filtered direction
-constexpr int NV = CPT + 2 * SR;      // inputs a thread reads for them
+constexpr int RC = 4;                 // outputs per row-pass item (along x)
+constexpr int CC = 3;                 // outputs per column-pass thread (along y)
+constexpr int NCT = OX * (OY / CC);   // threads of the column pass
+static_assert(OY % CC == 0 && OX % RC == 0 && IY * (OX / RC) <= 256 && NCT <= 256, "tile shape");
 constexpr double SC1 = 0.01 * 0.01, SC2 = 0.03 * 0.03;
 
 struct SsimArgs {
@@ -44,15 +47,16 @@ __device__ inline int64_t plane_px(const SsimArgs &a, int plane, int r, int c) {
     return (int64_t)plane * a.hw + (int64_t)(r + a.roi) * a.W + c;
 }
 
-// The separable filter, both passes: a thread filters NV = CPT + 10 consecutive inputs held
-// in registers into CPT consecutive outputs (11 taps each), so every input is read from LDS
-// once per thread rather than once per tap.
-template <int NM>
-__device__ __forceinline__ void filter_cpt(const double (&g)[SW], const double (&v)[NM][NV], double (&out)[NM][CPT]) {
+// The separable filter, both passes: a thread filters C + 10 consecutive inputs held in
+// registers into C consecutive outputs (11 taps each), so every input is read from LDS once
+// per thread rather than once per tap.
+template <int NM, int C>
+__device__ __forceinline__ void filter_cpt(const double (&g)[SW], const double (&v)[NM][C + 2 * SR],
+                                           double (&out)[NM][C]) {
 #pragma unroll
     for (int m = 0; m < NM; ++m)
 #pragma unroll
-        for (int o = 0; o < CPT; ++o) {
+        for (int o = 0; o < C; ++o) {
             double acc = 0.0;
 #pragma unroll
             for (int k = 0; k < SW; ++k) acc = fma(g[k], v[m][o + k], acc);
@@ -79,12 +83,12 @@ __global__ __launch_bounds__(256) void ssim_fwd_kernel(SsimArgs a, const float *
         sy[r][c] = in ? y[o] : 0.f;
     }
     __syncthreads();
-    // rows: the five raw moments x, y, x^2, y^2, xy of every halo row, CPT columns per item
-    for (int it = t; it < IY * (OX / CPT); it += 256) {
-        const int r = it / (OX / CPT), c0 = (it - r * (OX / CPT)) * CPT;
-        double v[5][NV];
+    // rows: the five raw moments x, y, x^2, y^2, xy of every halo row, RC columns per item
+    if (t < IY * (OX / RC)) {
+        const int r = t / (OX / RC), c0 = (t - r * (OX / RC)) * RC;
+        double v[5][RC + 2 * SR];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
+        for (int k = 0; k < RC + 2 * SR; ++k) {
             double xv = sx[r][c0 + k], yv = sy[r][c0 + k];
             v[0][k] = xv;
             v[1][k] = yv;
@@ -92,49 +96,51 @@ __global__ __launch_bounds__(256) void ssim_fwd_kernel(SsimArgs a, const float *
             v[3][k] = yv * yv;
             v[4][k] = xv * yv;
         }
-        double out[5][CPT];
-        filter_cpt<5>(g, v, out);
+        double out[5][RC];
+        filter_cpt<5, RC>(g, v, out);
 #pragma unroll
         for (int m = 0; m < 5; ++m)
 #pragma unroll
-            for (int o = 0; o < CPT; ++o) hm[m][r][c0 + o] = out[m][o];
+            for (int o = 0; o < RC; ++o) hm[m][r][c0 + o] = out[m][o];
     }
     __syncthreads();
-    // columns: CPT rows of one column per thread, then SSIM and its partials
-    const int c = t % OX, r0 = (t / OX) * CPT;
-    double mo[5][CPT];
-    {
-        double v[5][NV];
-#pragma unroll
-        for (int m = 0; m < 5; ++m)
-#pragma unroll
-            for (int k = 0; k < NV; ++k) v[m][k] = hm[m][r0 + k][c];
-        filter_cpt<5>(g, v, mo);
-    }
+    // columns: CC rows of one column per thread, then SSIM and its partials
+    const int c = t % OX, r0 = (t / OX) * CC;
     double ssum = 0.0;
-    const int64_t gbase = (int64_t)plane * a.hwc, np = (int64_t)gridDim.z * a.hwc;
-    const int gc = x0 + c;
+    if (t < NCT) {
+        double mo[5][CC];
+        {
+            double v[5][CC + 2 * SR];
 #pragma unroll
-    for (int o = 0; o < CPT; ++o) {
-        const int gr = y0 + r0 + o;
-        if (gr >= a.Hc || gc >= a.W) continue;
-        const double m1 = mo[0][o], m2 = mo[1][o], m11 = mo[2][o], m22 = mo[3][o], m12 = mo[4][o];
-        const double A = 2.0 * m1 * m2 + SC1;
-        const double B = 2.0 * (m12 - m1 * m2) + SC2;
-        const double C = m1 * m1 + m2 * m2 + SC1;
-        const double D = (m11 - m1 * m1) + (m22 - m2 * m2) + SC2;
-        // one division for the four reciprocals
-        const double AB = A * B, CD = C * D, P = 1.0 / (AB * CD);
-        const double rA = B * CD * P, rB = A * CD * P, rC = AB * D * P, rD = AB * C * P;
-        const double S = AB * AB * P;
-        ssum += S;
-        // dS/dm1 = S (2 m2 / A - 2 m2 / B - 2 m1 / C + 2 m1 / D), dS/dm11 = -S / D, dS/dm12 = 2 S / B
-        const double d1 = 2.0 * S * (m2 * (rA - rB) + m1 * (rD - rC));
-        const double d11 = -S * rD, d12 = 2.0 * S * rB;
-        const int64_t q = gbase + (int64_t)gr * a.W + gc;
-        G[q] = (float)(fscale * d1);
-        G[np + q] = (float)(fscale * d11);
-        G[2 * np + q] = (float)(fscale * d12);
+            for (int m = 0; m < 5; ++m)
+#pragma unroll
+                for (int k = 0; k < CC + 2 * SR; ++k) v[m][k] = hm[m][r0 + k][c];
+            filter_cpt<5, CC>(g, v, mo);
+        }
+        const int64_t gbase = (int64_t)plane * a.hwc, np = (int64_t)gridDim.z * a.hwc;
+        const int gc = x0 + c;
+#pragma unroll
+        for (int o = 0; o < CC; ++o) {
+            const int gr = y0 + r0 + o;
+            if (gr >= a.Hc || gc >= a.W) continue;
+            const double m1 = mo[0][o], m2 = mo[1][o], m11 = mo[2][o], m22 = mo[3][o], m12 = mo[4][o];
+            const double A = 2.0 * m1 * m2 + SC1;
+            const double B = 2.0 * (m12 - m1 * m2) + SC2;
+            const double C = m1 * m1 + m2 * m2 + SC1;
+            const double D = (m11 - m1 * m1) + (m22 - m2 * m2) + SC2;
+            // one division for the four reciprocals
+            const double AB = A * B, CD = C * D, P = 1.0 / (AB * CD);
+            const double rA = B * CD * P, rB = A * CD * P, rC = AB * D * P, rD = AB * C * P;
+            const double S = AB * AB * P;
+            ssum += S;
+            // dS/dm1 = S (2 m2 / A - 2 m2 / B - 2 m1 / C + 2 m1 / D), dS/dm11 = -S / D, dS/dm12 = 2 S / B
+            const double d1 = 2.0 * S * (m2 * (rA - rB) + m1 * (rD - rC));
+            const double d11 = -S * rD, d12 = 2.0 * S * rB;
+            const int64_t q = gbase + (int64_t)gr * a.W + gc;
+            G[q] = (float)(fscale * d1);
+            G[np + q] = (float)(fscale * d11);
+            G[2 * np + q] = (float)(fscale * d12);
+        }
     }
     ssum = wave_sum(ssum);
     if ((t & 63) == 0) part[t >> 6] = ssum;
@@ -167,34 +173,35 @@ __global__ __launch_bounds__(256) void ssim_bwd_kernel(SsimArgs a, const float *
         sg[2][r][c] = in ? G[2 * np + o] : 0.f;
     }
     __syncthreads();
-    for (int it = t; it < IY * (OX / CPT); it += 256) {
-        const int r = it / (OX / CPT), c0 = (it - r * (OX / CPT)) * CPT;
-        double v[3][NV];
+    if (t < IY * (OX / RC)) {
+        const int r = t / (OX / RC), c0 = (t - r * (OX / RC)) * RC;
+        double v[3][RC + 2 * SR];
 #pragma unroll
         for (int m = 0; m < 3; ++m)
 #pragma unroll
-            for (int k = 0; k < NV; ++k) v[m][k] = sg[m][r][c0 + k];
-        double out[3][CPT];
-        filter_cpt<3>(g, v, out);
+            for (int k = 0; k < RC + 2 * SR; ++k) v[m][k] = sg[m][r][c0 + k];
+        double out[3][RC];
+        filter_cpt<3, RC>(g, v, out);
 #pragma unroll
         for (int m = 0; m < 3; ++m)
 #pragma unroll
-            for (int o = 0; o < CPT; ++o) hm[m][r][c0 + o] = out[m][o];
+            for (int o = 0; o < RC; ++o) hm[m][r][c0 + o] = out[m][o];
     }
     __syncthreads();
-    const int c = t % OX, r0 = (t / OX) * CPT;
-    double f[3][CPT];
+    if (t >= NCT) return;
+    const int c = t % OX, r0 = (t / OX) * CC;
+    double f[3][CC];
     {
-        double v[3][NV];
+        double v[3][CC + 2 * SR];
 #pragma unroll
         for (int m = 0; m < 3; ++m)
 #pragma unroll
-            for (int k = 0; k < NV; ++k) v[m][k] = hm[m][r0 + k][c];
-        filter_cpt<3>(g, v, f);
+            for (int k = 0; k < CC + 2 * SR; ++k) v[m][k] = hm[m][r0 + k][c];
+        filter_cpt<3, CC>(g, v, f);
     }
     const int gc = x0 + c;
 #pragma unroll
-    for (int o = 0; o < CPT; ++o) {
+    for (int o = 0; o < CC; ++o) {
         const int gr = y0 + r0 + o;
         if (gr >= a.Hc || gc >= a.W) continue;
         const int64_t q = plane_px(a, plane, gr, gc);

@@ -116,11 +116,13 @@ def test_bin_sort_vs_oracle(tile):
     fr = g["frame"]
     ns, ni = g["slots"], g["inst"]
     vals = fr.sorted_vals(ni).cpu().numpy().astype(np.int64)
-    keys = fr.sorted_keys(ni).cpu().numpy()
-    keys = keys.view(np.uint32) if int(fr.plan.key_shift) >= 0 else keys.view(np.uint64)
     meta = fr.meta(ns).cpu().numpy()
     ranges = fr.ranges().cpu().numpy().astype(np.int64)
-    assert np.all(np.diff(keys) >= 0)
+    # the lists tile the sorted instances in (view, tile) order, each instance once
+    nz = ranges[ranges[:, 1] > ranges[:, 0]]
+    assert nz[0, 0] == 0 and nz[-1, 1] == ni and np.all(nz[1:, 0] == nz[:-1, 1])
+    offs = fr.buf("ntiles", torch.int32, ns + 1).cpu().numpy().astype(np.int64)  # instance offsets per slot
+    assert offs[ns] == ni and np.array_equal(np.bincount(vals, minlength=ns), np.diff(offs))
     T = int(fr.plan.tiles_per_view)
     W, H = scene.rig.W, scene.rig.H
     for v in range(scene.views.n):
@@ -134,6 +136,35 @@ def test_bin_sort_vs_oracle(tile):
                 mine = [x for x in mine if x not in mset]
                 ref = [x for x in ref if x not in mset]
             assert mine == ref, (v, t)
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 16)])
+def test_bin_sort_long_lists_vs_oracle(tile):
+    """Tile lists longer than one LDS sort (4096 instances) are sorted in chunks and merged:
+    40,000 small Gaussians in front of a 64x32 camera put 5,000-10,000 instances in a tile;
+    every list must still be the oracle's (depth32, Gaussian id) order, and the image its image."""
+    say(f"case: bin_sort long lists tile={tile}")
+    scene = synth.tiny_scene(9, n=40000, W=64, H=32, f=10.0)
+    g, proj, w2c = _project_check(scene, tile)
+    fr = g["frame"]
+    ns, ni = g["slots"], g["inst"]
+    vals = fr.sorted_vals(ni).cpu().numpy().astype(np.int64)
+    meta = fr.meta(ns).cpu().numpy()
+    ranges = fr.ranges().cpu().numpy().astype(np.int64)
+    L = ranges[:, 1] - ranges[:, 0]
+    say(f"  list lengths: max {L.max()}, lists over 4096: {int((L > 4096).sum())} of {L.size}")
+    assert L.max() > 2 * 4096
+    off, gid, margin = oracle.tile_lists(proj, scene.rig.W, scene.rig.H, tile[0], tile[1], view=0)
+    mset = set(gid[margin])
+    for t in range(int(fr.plan.tiles_per_view)):
+        a, b = ranges[t]
+        mine = [int(x) for x in meta[vals[a:b], 0] if int(x) not in mset]
+        ref = [int(x) for x in gid[off[t]:off[t + 1]] if int(x) not in mset]
+        assert mine == ref, t
+    orc = oracle.render(scene.gauss, w2c, oracle.view_intr(scene.rig, scene.views), scene.rig.W, scene.rig.H,
+                        alternatives=True)
+    nbad, nfl, nex, mx = compare_images(g, orc)
+    assert nbad == 0 and nex <= 0.001 * orc["nflag"].size
 
 
 SCENES = {
