@@ -2,20 +2,20 @@
 // (F(X|Theta) of Sec. III-C: the model of Instant-NGP with four heads for colour,
 // opacity, scale and rotation), forward and adjoint.
 //
-// Per Gaussian (one thread): the position is normalised into [0,1]^3 by the scene
-// box; at every level l the cell of p = x_n N_l is found in float64 (so the cell
-// and the trilinear weights are those of the definition), the 8 vertices are
-// looked up -- dense index where the level's (N_l+1)^3 vertices fit in the table,
-// spatial hash (v0 * 1) ^ (v1 * 2654435761) ^ (v2 * 805459861) mod T otherwise --
-// and blended; the 32 features go through 32 -> 64 -> 64 -> 11 (ReLU) with the
-// weights broadcast from LDS; heads: colour and opacity sigmoid, scale
-// scale_max * sigmoid, quaternion + (1, 0, 0, 0).
+// Per Gaussian: the position is normalised into [0,1]^3 by the scene box; at every
+// level l the cell of p = x_n N_l is found in float64 (so the cell and the trilinear
+// weights are those of the definition), the 8 vertices are looked up -- dense index where
+// the level's (N_l+1)^3 vertices fit in the table, spatial hash
+// (v0 * 1) ^ (v1 * 2654435761) ^ (v2 * 805459861) mod T otherwise -- and blended; the 32
+// features go through 32 -> 64 -> 64 -> 11 (ReLU); heads: colour and opacity sigmoid,
+// scale scale_max * sigmoid, quaternion + (1, 0, 0, 0).  A wave takes a block of Gaussians at a
+// time and runs the three layers on the matrix cores (see the MLP section below).
 //
-// Adjoint: the forward is recomputed, the 11 output gradients are pushed back
-// through the heads and the MLP, and the per-Gaussian activations and deltas are
-// stored so that the weight gradients -- sums over all Gaussians of outer
-// products, a tall-skinny A^T B -- are formed by atb_kernel (per-workgroup
-// partials on the matrix cores, then a fixed-order float64 reduction).  The table gradient of a
+// Adjoint: the 11 output gradients are pushed back through the heads and the MLP (on the
+// matrix cores, from the forward's values stored per Gaussian, or evaluated again), and
+// the activations and deltas are stored so that the weight gradients -- sums over all
+// Gaussians of outer products, a tall-skinny A^T B -- are formed by atb_kernel
+// (per-workgroup partials on the matrix cores, then a fixed-order float64 reduction).  The table gradient of a
 // row is the sum, over every (Gaussian, vertex) that looked it up, of the
 // trilinear weight times the Gaussian's encoding gradient.  Two ways to form it:
 //  * scatter: hardware float atomics (16 levels x 8 vertices x 2 features), after
@@ -49,17 +49,22 @@ struct NgpArgs {
     float scale_max;
 };
 
-__device__ __forceinline__ uint32_t vertex_row(const NgpArgs &a, int l, uint32_t v0, uint32_t v1, uint32_t v2) {
-    if (a.dense[l]) {
-        uint32_t n = (uint32_t)a.res[l] + 1u;
-        return v0 + n * (v1 + n * v2);
-    }
-    return ((v0 * 1u) ^ (v1 * 2654435761u) ^ (v2 * 805459861u)) & a.tmask;
+// both indexings are formed and one is selected: the dense flag may differ between the lanes
+// of a wave, and a branch per vertex would keep the table reads from being issued together
+__device__ __forceinline__ uint32_t vertex_row_n(int dense, uint32_t N, uint32_t tmask, uint32_t v0, uint32_t v1,
+                                                 uint32_t v2) {
+    const uint32_t m = N + 1u;
+    const uint32_t rd = v0 + m * (v1 + m * v2);
+    const uint32_t rh = ((v0 * 1u) ^ (v1 * 2654435761u) ^ (v2 * 805459861u)) & tmask;
+    return dense ? rd : rh;
 }
 
-// cell and fractions of level l
-__device__ __forceinline__ void level_cell(const NgpArgs &a, int l, const double *xn, uint32_t *cell, double *fr) {
-    int N = a.res[l];
+__device__ __forceinline__ uint32_t vertex_row(const NgpArgs &a, int l, uint32_t v0, uint32_t v1, uint32_t v2) {
+    return vertex_row_n(a.dense[l], (uint32_t)a.res[l], a.tmask, v0, v1, v2);
+}
+
+// cell and fractions at resolution N
+__device__ __forceinline__ void level_cell_n(int N, const double *xn, uint32_t *cell, double *fr) {
     for (int d = 0; d < 3; ++d) {
         double p = xn[d] * (double)N;
         double c = floor(p);
@@ -69,6 +74,10 @@ __device__ __forceinline__ void level_cell(const NgpArgs &a, int l, const double
     }
 }
 
+__device__ __forceinline__ void level_cell(const NgpArgs &a, int l, const double *xn, uint32_t *cell, double *fr) {
+    level_cell_n(a.res[l], xn, cell, fr);
+}
+
 __device__ __forceinline__ void normalise(const NgpArgs &a, const float *mean, int64_t n, int64_t i, double *xn) {
     for (int d = 0; d < 3; ++d) {
         double v = ((double)mean[d * n + i] - a.lo[d]) / a.ext[d];
@@ -76,12 +85,12 @@ __device__ __forceinline__ void normalise(const NgpArgs &a, const float *mean, i
     }
 }
 
-// the two features of level l
-__device__ __forceinline__ void encode_level(const NgpArgs &a, const float2 *tables, const double *xn, int l,
-                                             float &e0, float &e1) {
+// the two features of level l (resolution N, dense indexing or not)
+__device__ __forceinline__ void encode_at(const NgpArgs &a, const float2 *tables, int l, int N, int dense,
+                                          const double *xn, float &e0, float &e1) {
     uint32_t cell[3];
     double fr[3];
-    level_cell(a, l, xn, cell, fr);
+    level_cell_n(N, xn, cell, fr);
     const float2 *tab = tables + (int64_t)l * a.T;
     e0 = 0.f;
     e1 = 0.f;
@@ -89,7 +98,7 @@ __device__ __forceinline__ void encode_level(const NgpArgs &a, const float2 *tab
     for (int c = 0; c < 8; ++c) {
         int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
         double w = (cx ? fr[0] : 1.0 - fr[0]) * (cy ? fr[1] : 1.0 - fr[1]) * (cz ? fr[2] : 1.0 - fr[2]);
-        float2 t = tab[vertex_row(a, l, cell[0] + cx, cell[1] + cy, cell[2] + cz)];
+        float2 t = tab[vertex_row_n(dense, (uint32_t)N, a.tmask, cell[0] + cx, cell[1] + cy, cell[2] + cz)];
         e0 = __fmaf_rn((float)w, t.x, e0);
         e1 = __fmaf_rn((float)w, t.y, e1);
     }
@@ -111,269 +120,474 @@ __device__ __forceinline__ float ngp_wave_total(float x) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
-// tab[2r] += a0, tab[2r+1] += a1 for every lane with a non-zero pair (all 64 lanes active,
-// e.g. Gaussians outside every view of the batch carry no gradient).  Lanes that share a
-// row are summed over the wave first, one row at a time while a row is shared by at least two
-// lanes (the coarse levels, where the whole wave often sits in one cell); the rest go
+// tab[2e] += a0, tab[2e+1] += a1 for every lane with a non-zero pair (all 64 lanes active;
+// e = level * T + row, so lanes of different levels never combine).  Lanes that share an
+// entry are summed over the wave first, one entry at a time while an entry is shared by at
+// least two lanes (the coarse levels, where many Gaussians sit in one cell); the rest go
 // straight to the float atomics.
-__device__ __forceinline__ void scatter2(float *tab, uint32_t r, float a0, float a1) {
+__device__ __forceinline__ void scatter2(float *tab, int64_t e, float a0, float a1) {
     const int lane = __lane_id();
     uint64_t todo = __ballot(a0 != 0.f || a1 != 0.f);  // Gaussians without a gradient add nothing
 #pragma unroll 1
     for (int it = 0; it < 8 && todo; ++it) {
         int leader = __ffsll((long long)todo) - 1;
-        uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)r, leader);
-        bool mine = ((todo >> lane) & 1ull) && r == key;
+        const uint32_t klo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)e, leader);
+        const uint32_t khi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)e >> 32), leader);
+        const int64_t key = (int64_t)(((uint64_t)khi << 32) | klo);
+        bool mine = ((todo >> lane) & 1ull) && e == key;
         uint64_t peers = __ballot(mine);
         if (__popcll(peers) < 2) break;
         float s0 = ngp_wave_total(mine ? a0 : 0.f), s1 = ngp_wave_total(mine ? a1 : 0.f);
         if (lane == leader) {
-            atomicAdd(tab + 2 * (int64_t)key, s0);
-            atomicAdd(tab + 2 * (int64_t)key + 1, s1);
+            atomicAdd(tab + 2 * key, s0);
+            atomicAdd(tab + 2 * key + 1, s1);
         }
         todo &= ~peers;
     }
     if ((todo >> lane) & 1ull) {
-        atomicAdd(tab + 2 * (int64_t)r, a0);
-        atomicAdd(tab + 2 * (int64_t)r + 1, a1);
+        atomicAdd(tab + 2 * e, a0);
+        atomicAdd(tab + 2 * e + 1, a1);
     }
 }
 
 // Stored activations and deltas, R_LEN values per Gaussian, kept feature-major: value f of
-// Gaussian i at rows[f * ld + i] (ld = row_ld(n) >= n + 1, column n is the scratch of lanes
-// past the end), so that a thread writing its Gaussian's values makes coalesced stores
-// across the wave.  R_O: the 11 outputs before the heads, R_MASK: the two ReLU masks
-// (64-bit each, as floats).
+// Gaussian i at rows[f * ld + i] (ld = row_ld(n), a multiple of 64 above n, so the 64
+// columns of every block of 64 or fewer Gaussians exist; columns past n are scratch), so that the
+// 16 lanes of a lane group store 16 consecutive Gaussians.  R_O: the 11 outputs before the
+// heads.  R_MASK: the ReLU decisions as bits, 16 per (layer, lane group) in the order the
+// tile layout below holds them (R_MASK + 4 layer + q, bit 4 t + v for unit 16 t + 4 q + v), so
+// that the adjoint reads 8 words per Gaussian instead of both hidden layers.
 enum { R_DOUT = 0, R_H2 = 12, R_DH2 = R_H2 + NH, R_H1 = R_DH2 + NH, R_DH1 = R_H1 + NH, R_ENC = R_DH1 + NH,
-       R_DE = R_ENC + ND, R_O = R_DE + ND, R_MASK = R_O + 12, R_LEN = R_MASK + 4 };
+       R_O = R_ENC + ND, R_MASK = R_O + 12, R_LEN = R_MASK + 8 };
 
 __host__ __device__ inline int64_t row_ld(int64_t n) { return (n + 64) & ~(int64_t)63; }
 
-// the values of one Gaussian (one column of the feature-major store)
-struct RowRef {
-    float *p;
-    int64_t ld;
-    __device__ float &operator[](int f) const { return p[(int64_t)f * ld]; }
+// ---- the MLP on the matrix cores ----
+//
+// One wave evaluates the 16 FJ Gaussians g0 .. g0 + 16 FJ - 1 with v_mfma_f32_16x16x4f32
+// (FP32 products and sums).  Lane l = 16 q + c (c = l % 16) holds every 16 x 16 block of a
+// layer's features in "tile layout": register v of tile (t, j) is feature 16 t + 4 q + v of
+// Gaussian g0 + 16 j + c (j < FJ).  That is the layout of an MFMA result (rows 4 q + v,
+// column c), and it is also the layout in which the next layer takes the tile as its B
+// operand when MFMA number v of an input tile uses, in lane group q, the input feature
+// 16 t + 4 q + v as its k index: the layers chain in registers.  The A operand (weights)
+// comes from LDS as one 16-byte read per lane for four consecutive MFMAs; weight rows are
+// padded to 4 mod 32 floats, so the 16 rows a lane group reads fall into distinct banks.
+// The encoding is computed in tile layout from the start: lane group q evaluates the levels
+// 2 q, 2 q + 1, 8 + 2 q and 9 + 2 q of the lane's Gaussians g0 + 16 j + c.
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mma(float a, float b, f4 acc) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+}
+
+constexpr int P32 = ND + 4, P64 = NH + 4, P16 = 16 + 4;  // padded row lengths (floats)
+
+// forward weights: w3 and b3 padded to 16 outputs with zeros, w1 to 32 inputs
+struct __align__(16) WFwd {
+    float w1[NH][P32], w2[NH][P64], w3[16][P64], b1[NH], b2[NH], b3[16];
 };
 
-struct Weights {
-    float w1[NH][ND], b1[NH], w2[NH][NH], b2[NH], w3[NO][NH], b3[NO];
+// adjoint weights, transposed: w3t[j][k] = w3[k][j] (k < 16), w2t[i][j] = w2[j][i], w1t[e][j] = w1[j][e]
+struct __align__(16) WBwd {
+    float w3t[NH][P16], w2t[NH][P64], w1t[ND][P64];
 };
 
-__device__ inline void load_weights(Weights &W, const float *w1, const float *b1, const float *w2, const float *b2,
-                                    const float *w3, const float *b3, int din) {
+__device__ inline void load_fwd(WFwd &W, const float *w1, const float *b1, const float *w2, const float *b2,
+                                const float *w3, const float *b3, int din) {
     for (int i = threadIdx.x; i < NH * ND; i += blockDim.x) {
-        int r = i / ND, c = i - r * ND;
-        W.w1[r][c] = c < din ? w1[r * din + c] : 0.f;
+        int r = i / ND, e = i - r * ND;
+        W.w1[r][e] = e < din ? w1[r * din + e] : 0.f;
     }
     for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) W.w2[i / NH][i % NH] = w2[i];
-    for (int i = threadIdx.x; i < NO * NH; i += blockDim.x) W.w3[i / NH][i % NH] = w3[i];
+    for (int i = threadIdx.x; i < 16 * NH; i += blockDim.x) W.w3[i / NH][i % NH] = i < NO * NH ? w3[i] : 0.f;
     for (int i = threadIdx.x; i < NH; i += blockDim.x) {
         W.b1[i] = b1[i];
         W.b2[i] = b2[i];
     }
-    for (int i = threadIdx.x; i < NO; i += blockDim.x) W.b3[i] = b3[i];
+    for (int i = threadIdx.x; i < 16; i += blockDim.x) W.b3[i] = i < NO ? b3[i] : 0.f;
 }
 
-// Encoding and MLP 2L -> 64 -> 64 -> 11.  Every level's two features go straight into the 64
-// first-layer sums (the level loop stays rolled: its gathers are not all in flight at once),
-// and every second-layer unit straight into the 11 outputs, so one 64-wide vector is live at a
-// time.  With ROW, the encoding, h1 and h2 are also stored to the per-Gaussian row, with the
-// ReLU masks.
-template <bool ROW>
-__device__ __forceinline__ void field(const NgpArgs &a, const float2 *tables, const Weights &W, const double *xn,
-                                      float *o, RowRef row, uint64_t &m1, uint64_t &m2) {
-    float h1[NH];
-#pragma unroll
-    for (int j = 0; j < NH; ++j) h1[j] = W.b1[j];
-#pragma unroll 1
-    for (int l = 0; l < a.levels; ++l) {
-        float e0, e1;
-        encode_level(a, tables, xn, l, e0, e1);
-        if (ROW) {
-            row[R_ENC + 2 * l] = e0;
-            row[R_ENC + 2 * l + 1] = e1;
-        }
-#pragma unroll
-        for (int j = 0; j < NH; ++j) h1[j] = __fmaf_rn(W.w1[j][2 * l + 1], e1, __fmaf_rn(W.w1[j][2 * l], e0, h1[j]));
+__device__ inline void load_bwd(WBwd &W, const float *w1, const float *w2, const float *w3, int din) {
+    for (int i = threadIdx.x; i < NH * 16; i += blockDim.x) {
+        int j = i / 16, k = i - j * 16;
+        W.w3t[j][k] = k < NO ? w3[k * NH + j] : 0.f;
     }
-    if (ROW)
-        for (int l = a.levels; l < NL; ++l) row[R_ENC + 2 * l] = row[R_ENC + 2 * l + 1] = 0.f;
-#pragma unroll
-    for (int j = 0; j < NH; ++j) {
-        float s = h1[j];
-        h1[j] = s > 0.f ? s : 0.f;
-        if (ROW) {
-            row[R_H1 + j] = h1[j];
-            m1 |= (s > 0.f ? 1ull : 0ull) << j;
-        }
+    for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) {
+        int r = i / NH, cc = i - r * NH;
+        W.w2t[cc][r] = w2[i];
     }
-#pragma unroll
-    for (int k = 0; k < NO; ++k) o[k] = W.b3[k];
-#pragma unroll 2
-    for (int j = 0; j < NH; ++j) {
-        float s = W.b2[j];
-#pragma unroll
-        for (int i = 0; i < NH; ++i) s = __fmaf_rn(W.w2[j][i], h1[i], s);
-        float h = s > 0.f ? s : 0.f;
-        if (ROW) {
-            row[R_H2 + j] = h;
-            m2 |= (s > 0.f ? 1ull : 0ull) << j;
-        }
-#pragma unroll
-        for (int k = 0; k < NO; ++k) o[k] = __fmaf_rn(W.w3[k][j], h, o[k]);
+    for (int i = threadIdx.x; i < NH * ND; i += blockDim.x) {
+        int j = i / ND, e = i - j * ND;
+        W.w1t[e][j] = e < din ? w1[j * din + e] : 0.f;
     }
+}
+
+__device__ __forceinline__ f4 lds4(const float *p) { return *reinterpret_cast<const f4 *>(p); }
+
+// levels evaluated by lane group q in slot s: 8 (s >> 1) + 2 q + (s & 1)
+__device__ __forceinline__ int slot_level(int s, int q) { return 8 * (s >> 1) + 2 * q + (s & 1); }
+
+// v[8 (s >> 1) + (s & 1) + 2 q] with the four candidates read as scalars
+__device__ __forceinline__ int pick_level(const int *v, int s, int q) {
+    const int b = 8 * (s >> 1) + (s & 1);
+    int r = v[b];
+    r = q == 1 ? v[b + 2] : r;
+    r = q == 2 ? v[b + 4] : r;
+    r = q == 3 ? v[b + 6] : r;
+    return r;
 }
 
 __device__ __forceinline__ float sigm(float x) { return 1.f / (1.f + __expf(-x)); }
 
-// SAVE: also store what the adjoint needs (encoding, hidden layers, outputs, ReLU masks) in
-// the per-Gaussian rows, so that it does not evaluate the field again
-template <bool SAVE>
-__global__ __launch_bounds__(256, 2) void ngp_fwd_kernel(NgpArgs a, const float *mean, int64_t n, const float2 *tables,
-                                                     const float *w1, const float *b1, const float *w2,
-                                                     const float *b2, const float *w3, const float *b3,
-                                                     float *quat, float *scale, float *opac, float *color,
-                                                     float *rows) {
-    __shared__ Weights W;
-    load_weights(W, w1, b1, w2, b2, w3, b3, 2 * a.levels);
-    __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double xn[3];
-        normalise(a, mean, n, i, xn);
-        float o[NO];
-        uint64_t m1 = 0, m2 = 0;
-        const RowRef row{SAVE ? rows + i : nullptr, row_ld(n)};
-        field<SAVE>(a, tables, W, xn, o, row, m1, m2);
-        if (SAVE) {
+// The field for the 16 FJ Gaussians of block g0 (lanes past n evaluate the last Gaussian and
+// write no parameters; PARAMS = false writes none at all).  SAVE: the encoding, both hidden layers (after the ReLU) and the
+// outputs before the heads also go to the rows.
+template <int FJ, bool SAVE, bool PARAMS = true>
+__device__ __forceinline__ void field_block(const NgpArgs &a, const float2 *tables, const WFwd &W, const float *mean,
+                                            int64_t n, int64_t g0, float *quat, float *scale, float *opac,
+                                            float *color, float *rows) {
+    const int lane = __lane_id(), c = lane & 15, q = lane >> 4;
+    // the row stride, opaque to the compiler: the offsets of the stores below are then formed
+    // where they are used, instead of all of them being hoisted out of the block loop
+    int64_t ld = row_ld(n);
+    asm volatile("" : "+s"(ld));
+    // the lane's column of the rows at feature 4 q: feature F + 4 q + v of Gaussian g0 + 16 j + c
+    // is lr[(F + v) ld + 16 j], a wave-uniform offset
+    float *lr = SAVE ? rows + 4 * q * ld + g0 + c : nullptr;
+    float *mr = SAVE ? rows + (int64_t)q * ld + g0 + c : nullptr;  // mask word R_MASK + 4 layer + q
+    // opaque as well, so that every store adds a wave-uniform offset to them (otherwise the
+    // compiler folds 4 q into a per-lane multiplier of ld for each store and keeps them all)
+    asm volatile("" : "+v"(lr), "+v"(mr));
+    f4 E[2][FJ];
+    {
+        double xn[FJ][3];
 #pragma unroll
-            for (int k = 0; k < 12; ++k) row[R_O + k] = k < NO ? o[k] : 0.f;
-            row[R_MASK + 0] = __uint_as_float((uint32_t)m1);
-            row[R_MASK + 1] = __uint_as_float((uint32_t)(m1 >> 32));
-            row[R_MASK + 2] = __uint_as_float((uint32_t)m2);
-            row[R_MASK + 3] = __uint_as_float((uint32_t)(m2 >> 32));
+        for (int j = 0; j < FJ; ++j) {
+            const int64_t g = g0 + 16 * j + c;
+            normalise(a, mean, n, g < n ? g : n - 1, xn[j]);
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) color[c * n + i] = sigm(o[c]);
-        opac[i] = sigm(o[3]);
+        for (int s = 0; s < 4; ++s) {
+            // a level past the model's is evaluated at level 0 and contributes zero (no branch)
+            const bool on = slot_level(s, q) < a.levels;
+            const int l = on ? slot_level(s, q) : 0;
+            const int N = on ? pick_level(a.res, s, q) : a.res[0];
+            const int dense = on ? pick_level(a.dense, s, q) : a.dense[0];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) scale[c * n + i] = a.scale_max * sigm(o[4 + c]);
-        quat[i] = o[7] + 1.f;
+            for (int j = 0; j < FJ; ++j) {
+                float e0, e1;
+                encode_at(a, tables, l, N, dense, xn[j], e0, e1);
+                E[s >> 1][j][2 * (s & 1)] = on ? e0 : 0.f;
+                E[s >> 1][j][2 * (s & 1) + 1] = on ? e1 : 0.f;
+            }
+            // one slot's 32 gathers in flight at a time (all of them at once would not fit the registers)
+            asm volatile("" ::: "memory");
+        }
+    }
+    if (SAVE)
 #pragma unroll
-        for (int c = 1; c < 4; ++c) quat[c * n + i] = o[7 + c];
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int j = 0; j < FJ; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) lr[(int64_t)(R_ENC + 16 * t + v) * ld + 16 * j] = E[t][j][v];
+    // hidden layer 1
+    f4 H[4][FJ];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const f4 b = lds4(&W.b1[16 * t + 4 * q]);
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) H[t][j] = b;
+    }
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const f4 w = lds4(&W.w1[16 * t + c][16 * kt + 4 * q]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int j = 0; j < FJ; ++j) H[t][j] = mma(w[v], E[kt][j][v], H[t][j]);
+        }
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) {
+        uint32_t m = 0u;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float h = H[t][j][v] > 0.f ? H[t][j][v] : 0.f;
+                H[t][j][v] = h;
+                m |= (h > 0.f ? 1u : 0u) << (4 * t + v);
+                if (SAVE) lr[(int64_t)(R_H1 + 16 * t + v) * ld + 16 * j] = h;
+            }
+        if (SAVE) mr[(int64_t)R_MASK * ld + 16 * j] = __uint_as_float(m);
+    }
+    // hidden layer 2
+    f4 G[4][FJ];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const f4 b = lds4(&W.b2[16 * t + 4 * q]);
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) G[t][j] = b;
+    }
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const f4 w = lds4(&W.w2[16 * t + c][16 * kt + 4 * q]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int j = 0; j < FJ; ++j) G[t][j] = mma(w[v], H[kt][j][v], G[t][j]);
+        }
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) {
+        uint32_t m = 0u;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float h = G[t][j][v] > 0.f ? G[t][j][v] : 0.f;
+                G[t][j][v] = h;
+                m |= (h > 0.f ? 1u : 0u) << (4 * t + v);
+                if (SAVE) lr[(int64_t)(R_H2 + 16 * t + v) * ld + 16 * j] = h;
+            }
+        if (SAVE) mr[(int64_t)(R_MASK + 4) * ld + 16 * j] = __uint_as_float(m);
+    }
+    // outputs (rows 11..15 of the padded w3 are zero)
+    f4 O[FJ];
+    {
+        const f4 b = lds4(&W.b3[4 * q]);
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) O[j] = b;
+    }
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) {
+        const f4 w = lds4(&W.w3[c][16 * kt + 4 * q]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int j = 0; j < FJ; ++j) O[j] = mma(w[v], G[kt][j][v], O[j]);
+    }
+    // heads: output k = 4 q + v; colour 0..2 and opacity 3 sigmoid, scale 4..6
+    // scale_max sigmoid, quaternion 7..10 + (1, 0, 0, 0)
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) {
+        const int64_t g = g0 + 16 * j + c;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int k = 4 * q + v;
+            const float o = O[j][v];
+            if (SAVE && k < 12) lr[(int64_t)(R_O + v) * ld + 16 * j] = o;
+            if (!PARAMS || g >= n || k >= NO) continue;
+            const float s = sigm(o);
+            if (k < 3) color[k * n + g] = s;
+            else if (k == 3) opac[g] = s;
+            else if (k < 7) scale[(k - 4) * n + g] = a.scale_max * s;
+            else quat[(k - 7) * n + g] = k == 7 ? o + 1.f : o;
+        }
     }
 }
 
+// The adjoint of block g0 from the stored rows: output deltas, dL/dh2 and dL/dh1 go to the
+// rows (for the weight gradients), the encoding gradients are returned in tile layout
+// (register v of tile (t, j): feature 16 t + 4 q + v of Gaussian g0 + 16 j + c; zero for
+// lanes past n).
+template <int FJ>
+__device__ __forceinline__ void adjoint_block(const NgpArgs &a, const WBwd &W, int64_t n, int64_t g0,
+                                              const float *dquat, const float *dscale, const float *dopac,
+                                              const float *dcolor, float *rows, f4 (&dE)[2][FJ]) {
+    const int lane = __lane_id(), c = lane & 15, q = lane >> 4;
+    // the row stride, opaque to the compiler: the offsets of the stores below are then formed
+    // where they are used, instead of all of them being hoisted out of the block loop
+    int64_t ld = row_ld(n);
+    asm volatile("" : "+s"(ld));
+    float *lr = rows + 4 * q * ld + g0 + c;  // as in the forward
+    asm volatile("" : "+v"(lr));
+    // the ReLU decisions of the lane's units, loaded with the outputs before anything is stored
+    uint32_t m1[FJ], m2[FJ];
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) {
+        const float *mr = lr + (int64_t)(R_MASK - 3 * q) * ld + 16 * j;  // R_MASK + q
+        m1[j] = __float_as_uint(mr[0]);
+        m2[j] = __float_as_uint(mr[(int64_t)4 * ld]);
+    }
+    f4 D[FJ];
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) {
+        const int64_t g = g0 + 16 * j + c;
+        const bool live = g < n;
+        const int64_t gc = live ? g : n - 1;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int k = 4 * q + v;
+            float d = 0.f;
+            if (k < NO) {
+                const float o = lr[(int64_t)(R_O + v) * ld + 16 * j];
+                const float s = sigm(o);
+                if (k < 3) d = dcolor[k * n + gc] * s * (1.f - s);
+                else if (k == 3) d = dopac[gc] * s * (1.f - s);
+                else if (k < 7) d = dscale[(k - 4) * n + gc] * a.scale_max * s * (1.f - s);
+                else d = dquat[(k - 7) * n + gc];
+            }
+            d = live ? d : 0.f;
+            D[j][v] = d;
+            if (k < 12) lr[(int64_t)(R_DOUT + v) * ld + 16 * j] = d;
+        }
+    }
+    // dL/dh2 = w3^T dOut where h2 > 0
+    f4 G[4][FJ];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) G[t][j] = f4{0.f, 0.f, 0.f, 0.f};
+        const f4 w = lds4(&W.w3t[16 * t + c][4 * q]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int j = 0; j < FJ; ++j) G[t][j] = mma(w[v], D[j][v], G[t][j]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int j = 0; j < FJ; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float d = (m2[j] >> (4 * t + v)) & 1u ? G[t][j][v] : 0.f;
+                G[t][j][v] = d;
+                lr[(int64_t)(R_DH2 + 16 * t + v) * ld + 16 * j] = d;
+            }
+    // dL/dh1 = w2^T dL/dh2 where h1 > 0
+    f4 H[4][FJ];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) H[t][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const f4 w = lds4(&W.w2t[16 * t + c][16 * kt + 4 * q]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int j = 0; j < FJ; ++j) H[t][j] = mma(w[v], G[kt][j][v], H[t][j]);
+        }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int j = 0; j < FJ; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float d = (m1[j] >> (4 * t + v)) & 1u ? H[t][j][v] : 0.f;
+                H[t][j][v] = d;
+                lr[(int64_t)(R_DH1 + 16 * t + v) * ld + 16 * j] = d;
+            }
+    // dL/denc = w1^T dL/dh1
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) dE[t][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const f4 w = lds4(&W.w1t[16 * t + c][16 * kt + 4 * q]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int j = 0; j < FJ; ++j) dE[t][j] = mma(w[v], H[kt][j][v], dE[t][j]);
+        }
+}
+
+// SAVE: also store what the adjoint needs in the per-Gaussian rows.  Each wave takes blocks
+// of FB = 16 FJ Gaussians; the weights are staged once per workgroup.  Measured at 2M
+// Gaussians: the forward alone is fastest with 16 Gaussians per wave (fewer registers, five
+// waves per SIMD to cover the table reads), the training forward with 64.
+template <bool SAVE, int FJ = SAVE ? 4 : 1, int FB = 16 * FJ>
+__global__ __launch_bounds__(256, 2) void ngp_fwd_kernel(NgpArgs a, const float *mean, int64_t n, const float2 *tables,
+                                                      const float *w1, const float *b1, const float *w2,
+                                                      const float *b2, const float *w3, const float *b3,
+                                                      float *quat, float *scale, float *opac, float *color,
+                                                      float *rows) {
+    __shared__ WFwd W;
+    load_fwd(W, w1, b1, w2, b2, w3, b3, 2 * a.levels);
+    __syncthreads();
+    const int64_t nblk = (n + FB - 1) / FB;
+    for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nblk; b += (int64_t)gridDim.x * 4)
+        field_block<FJ, SAVE>(a, tables, W, mean, n, FB * b, quat, scale, opac, color, rows);
+}
+
+template <int MODE> struct __align__(16) BwdSmem { WFwd f; WBwd b; };
+template <> struct __align__(16) BwdSmem<2> { WBwd b; };
+
 // MODE 0: table gradients by atomics into dtables; MODE 1: the encoding gradients go to
 // dEc[level][Gaussian] for the indexed reduction; MODE 2: as 1, with the forward's values
-// read from the rows stored by the training forward instead of evaluated again.
-template <int MODE>
-__global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float *mean, int64_t n,
-                                                        const float2 *tables, const float *w1, const float *b1,
-                                                        const float *w2, const float *b2, const float *w3,
-                                                        const float *b3, const float *dquat, const float *dscale,
-                                                        const float *dopac, const float *dcolor, float *dtables,
-                                                        float *rows, float2 *dEc) {
-    __shared__ Weights W;
-    load_weights(W, w1, b1, w2, b2, w3, b3, 2 * a.levels);
+// read from the rows stored by the training forward instead of evaluated again (modes 0
+// and 1 evaluate the field of the block and store the rows first).  Blocks of 32 Gaussians
+// per wave in mode 2 (four waves per SIMD), 64 when the field is evaluated too.
+template <int MODE, int FJ = MODE == 2 ? 2 : 4, int FB = 16 * FJ>
+__global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float *mean, int64_t n, const float2 *tables,
+                                                      const float *w1, const float *b1, const float *w2,
+                                                      const float *b2, const float *w3, const float *b3,
+                                                      const float *dquat, const float *dscale, const float *dopac,
+                                                      const float *dcolor, float *dtables, float *rows, float2 *dEc) {
+    __shared__ BwdSmem<MODE> S;
+    if constexpr (MODE != 2) load_fwd(S.f, w1, b1, w2, b2, w3, b3, 2 * a.levels);
+    load_bwd(S.b, w1, w2, w3, 2 * a.levels);
     __syncthreads();
-    // every lane runs every iteration (the wave-level combining below needs all 64 lanes);
-    // lanes past the end redo the last Gaussian and add nothing
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i0 = base + threadIdx.x;
-        const bool live = i0 < n;
-        const int64_t i = live ? i0 : n - 1;
-        double xn[3];
-        const int64_t ld = row_ld(n);
-        const RowRef row{rows + (live ? i : n), ld};  // column n: scratch of the lanes past the end
-        float o[NO];
-        uint64_t m1 = 0, m2 = 0;  // ReLU masks of the two hidden layers
-        if (MODE == 2) {
-            // the training forward's values (column i also for the lanes past the end: their gradient is 0)
-            const RowRef src{rows + i, ld};
+    const int lane = __lane_id(), c = lane & 15, q = lane >> 4;
+    const int64_t nblk = (n + FB - 1) / FB;
+    for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nblk; b += (int64_t)gridDim.x * 4) {
+        const int64_t g0 = FB * b;
+        if constexpr (MODE != 2)
+            field_block<FJ, true, false>(a, tables, S.f, mean, n, g0, nullptr, nullptr, nullptr, nullptr, rows);
+        f4 dE[2][FJ];
+        adjoint_block<FJ>(a, S.b, n, g0, dquat, dscale, dopac, dcolor, rows, dE);
+        if constexpr (MODE != 0) {
 #pragma unroll
-            for (int k = 0; k < NO; ++k) o[k] = src[R_O + k];
-            m1 = (uint64_t)__float_as_uint(src[R_MASK + 0]) | ((uint64_t)__float_as_uint(src[R_MASK + 1]) << 32);
-            m2 = (uint64_t)__float_as_uint(src[R_MASK + 2]) | ((uint64_t)__float_as_uint(src[R_MASK + 3]) << 32);
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int j = 0; j < FJ; ++j) {
+                    const int64_t g = g0 + 16 * j + c;
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        const int l = 8 * t + 2 * q + p;
+                        if (g < n && l < a.levels) dEc[(int64_t)l * n + g] = make_float2(dE[t][j][2 * p], dE[t][j][2 * p + 1]);
+                    }
+                }
         } else {
-            // forward again; activations go to the row store at once
-            normalise(a, mean, n, i, xn);
-            field<true>(a, tables, W, xn, o, row, m1, m2);
-        }
-        // heads
-        float d[NO];
+            // table adjoint: every (Gaussian, level, vertex) adds weight * dL/denc to its row
+            double xn[FJ][3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float s = sigm(o[c]);
-            d[c] = dcolor[c * n + i] * s * (1.f - s);
-        }
-        {
-            float s = sigm(o[3]);
-            d[3] = dopac[i] * s * (1.f - s);
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float s = sigm(o[4 + c]);
-            d[4 + c] = dscale[c * n + i] * a.scale_max * s * (1.f - s);
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) d[7 + c] = dquat[c * n + i];
-        if (!live)
-#pragma unroll
-            for (int k = 0; k < NO; ++k) d[k] = 0.f;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) row[R_DOUT + k] = k < NO ? d[k] : 0.f;
-        // second hidden layer: each delta stored as soon as it is formed
-#pragma unroll 4
-        for (int j = 0; j < NH; ++j) {
-            float s = 0.f;
-#pragma unroll
-            for (int k = 0; k < NO; ++k) s = __fmaf_rn(W.w3[k][j], d[k], s);
-            row[R_DH2 + j] = (m2 >> j) & 1ull ? s : 0.f;
-        }
-        // first hidden layer from the stored deltas (this thread's own row, cache resident); each
-        // dh1[j] goes straight into the 2L encoding gradients
-        float de[ND];
-#pragma unroll
-        for (int e = 0; e < ND; ++e) de[e] = 0.f;
-        {
-            float dh2[NH];
-#pragma unroll
-            for (int k = 0; k < NH; ++k) dh2[k] = row[R_DH2 + k];
-#pragma unroll 2
-            for (int j = 0; j < NH; ++j) {
-                float s = 0.f;
-#pragma unroll
-                for (int k = 0; k < NH; ++k) s = __fmaf_rn(W.w2[k][j], dh2[k], s);
-                float dh = (m1 >> j) & 1ull ? s : 0.f;
-                row[R_DH1 + j] = dh;
-#pragma unroll
-                for (int e = 0; e < ND; ++e) de[e] = __fmaf_rn(W.w1[j][e], dh, de[e]);
+            for (int j = 0; j < FJ; ++j) {
+                const int64_t g = g0 + 16 * j + c;
+                normalise(a, mean, n, g < n ? g : n - 1, xn[j]);
             }
-        }
-        if (MODE != 0) {
-            if (live)
 #pragma unroll
-                for (int l = 0; l < NL; ++l)
-                    if (l < a.levels) dEc[(int64_t)l * n + i] = make_float2(de[2 * l], de[2 * l + 1]);
-            continue;
-        }
+            for (int s = 0; s < 4; ++s) {
+                const int l = slot_level(s, q);
+                const int N = pick_level(a.res, s, q), dense = pick_level(a.dense, s, q);
+                const bool on = l < a.levels;
 #pragma unroll
-        for (int e = 0; e < ND; ++e) row[R_DE + e] = de[e];
-        // table adjoint, level by level
-#pragma unroll 1
-        for (int l = 0; l < a.levels; ++l) {
-            float de0 = row[R_DE + 2 * l], de1 = row[R_DE + 2 * l + 1];
-            uint32_t cell[3];
-            double fr[3];
-            level_cell(a, l, xn, cell, fr);
-            float *tab = dtables + (int64_t)l * a.T * 2;
+                for (int j = 0; j < FJ; ++j) {
+                    const float de0 = dE[s >> 1][j][2 * (s & 1)], de1 = dE[s >> 1][j][2 * (s & 1) + 1];
+                    uint32_t cell[3] = {0u, 0u, 0u};
+                    double fr[3] = {0.0, 0.0, 0.0};
+                    if (on) level_cell_n(N, xn[j], cell, fr);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
-                float w = (float)((cx ? fr[0] : 1.0 - fr[0]) * (cy ? fr[1] : 1.0 - fr[1]) * (cz ? fr[2] : 1.0 - fr[2]));
-                uint32_t r = vertex_row(a, l, cell[0] + cx, cell[1] + cy, cell[2] + cz);
-                scatter2(tab, r, w * de0, w * de1);
+                    for (int cc = 0; cc < 8; ++cc) {
+                        int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
+                        float w = (float)((cx ? fr[0] : 1.0 - fr[0]) * (cy ? fr[1] : 1.0 - fr[1]) * (cz ? fr[2] : 1.0 - fr[2]));
+                        uint32_t r = vertex_row_n(dense, (uint32_t)N, a.tmask, cell[0] + cx, cell[1] + cy, cell[2] + cz);
+                        // lanes past n carry zero deltas; levels past the model's add nothing
+                        const bool add = on;
+                        scatter2(dtables, add ? (int64_t)l * a.T + r : 0, add ? w * de0 : 0.f, add ? w * de1 : 0.f);
+                    }
+                }
             }
         }
     }
@@ -780,6 +994,13 @@ __global__ void ngp_fixup_kernel(int64_t T, int64_t tpl, int64_t ntiles, const u
     }
 }
 
+// workgroups of the field kernels: four waves of fb Gaussians each per pass, at most 1024
+// workgroups (the weights are staged once per workgroup)
+int64_t field_groups(int64_t n, int fb) {
+    int64_t g = (n + 4 * fb - 1) / (4 * fb);
+    return g < 1 ? 1 : (g > 1024 ? 1024 : g);
+}
+
 int ngp_args(const splat_ngp &m, NgpArgs &a) {
     a.levels = m.levels;
     a.T = (int64_t)1 << m.log2_table;
@@ -908,8 +1129,7 @@ int ngp_bwd_via_index(const splat_ngp &m, const float *mean, int64_t n, const vo
     const IndexLayout I = index_layout(m.levels, m.log2_table, n);
     float *rows = ws_at<float>(ws, W.rows);
     float2 *dEc = ws_at<float2>(ws, W.dec);
-    int64_t nb = (n + 255) / 256;
-    if (nb > 8192) nb = 8192;
+    const int64_t nb = field_groups(n, saved ? 32 : 64);
     const float2 *tab = reinterpret_cast<const float2 *>(m.tables);
     if (saved)
         hipLaunchKernelGGL(ngp_bwd_kernel<2>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n, tab, m.w1, m.b1,
@@ -937,8 +1157,7 @@ int ngp_fwd(const splat_ngp &m, const float *mean, int64_t n, float *quat, float
             float *rows, hipStream_t st) {
     NgpArgs a;
     ngp_args(m, a);
-    int64_t nb = (n + 255) / 256;
-    if (nb > 8192) nb = 8192;
+    const int64_t nb = field_groups(n, rows ? 64 : 16);
     const float2 *tab = reinterpret_cast<const float2 *>(m.tables);
     if (rows)
         hipLaunchKernelGGL(ngp_fwd_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n, tab, m.w1, m.b1,
@@ -981,8 +1200,7 @@ int launch_ngp_bwd(const splat_ngp &m, const float *mean, int64_t n, const float
     ngp_args(m, a);
     const WsLayout W = ws_layout(n);
     float *rows = ws_at<float>(ws, W.rows);
-    int64_t nb = (n + 255) / 256;
-    if (nb > 8192) nb = 8192;
+    const int64_t nb = field_groups(n, 64);
     hipLaunchKernelGGL(ngp_bwd_kernel<0>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n,
                        reinterpret_cast<const float2 *>(m.tables), m.w1, m.b1, m.w2, m.b2, m.w3, m.b3, dquat, dscale,
                        dopac, dcolor, dtables, rows, nullptr);
