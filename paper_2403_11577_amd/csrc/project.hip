@@ -162,6 +162,33 @@ __device__ inline bool offscreen_bound(const splat_settings &S, const double *M,
            (my - 0.5f - ey > (float)(H - 1));
 }
 
+// Conservative float32 test of the opposite kind: true only if the exact footprint rectangle
+// is certainly non-empty.  The exact half-width is at least h = k sqrt(eps2d) + pad_px
+// (Sigma2_xx >= eps2d); with h >= 1/2 the interval [u - h, u + h] around u = mu_x - 1/2
+// contains the integer nearest to u, which lies in [0, W - 1] whenever u does (likewise for
+// y and the rows [roi_y0, H - 1]).  u is bounded through the float32 mean: its error in u_x
+// is at most 1e-6 (a0 + |u_x| a2) / z, a0 and a2 being the sums of the magnitudes of the terms
+// of t0 and z (four roundings of 2^-24 each, widened 4x), and 1e-5 |mu| + 1 px are added.
+__device__ inline bool onscreen_bound(const splat_settings &S, const double *M, const CamC &C, int W, int H,
+                                      const float *x, float k2f, float z) {
+    const float h = sqrtf(k2f * (float)S.eps2d) * 0.9999f + (float)S.pad_px;
+    if (!(h >= 0.5001f)) return false;
+    float t0 = __fmaf_rn((float)M[0], x[0], __fmaf_rn((float)M[1], x[1], __fmaf_rn((float)M[2], x[2], (float)M[3])));
+    float t1 = __fmaf_rn((float)M[4], x[0], __fmaf_rn((float)M[5], x[1], __fmaf_rn((float)M[6], x[2], (float)M[7])));
+    float a0 = fabsf((float)M[0] * x[0]) + fabsf((float)M[1] * x[1]) + fabsf((float)M[2] * x[2]) + fabsf((float)M[3]);
+    float a1 = fabsf((float)M[4] * x[0]) + fabsf((float)M[5] * x[1]) + fabsf((float)M[6] * x[2]) + fabsf((float)M[7]);
+    float a2 = fabsf((float)M[8] * x[0]) + fabsf((float)M[9] * x[1]) + fabsf((float)M[10] * x[2]) + fabsf((float)M[11]);
+    float iz = 1.f / z;
+    float ux = t0 * iz, uy = t1 * iz;
+    float fx = (float)C.fx, fy = (float)C.fy;
+    float mx = fx * ux + (float)C.cx, my = fy * uy + (float)C.cy;
+    float dx = 1.f + 1e-5f * fabsf(mx) + 1e-6f * fabsf(fx) * (a0 + fabsf(ux) * a2) * iz;
+    float dy = 1.f + 1e-5f * fabsf(my) + 1e-6f * fabsf(fy) * (a1 + fabsf(uy) * a2) * iz;
+    float u = mx - 0.5f, v = my - 0.5f;
+    // NaN anywhere makes every comparison false: decided exactly afterwards
+    return (u - dx >= 0.f) && (u + dx <= (float)(W - 1)) && (v - dy >= (float)S.roi_y0) && (v + dy <= (float)(H - 1));
+}
+
 // What a view makes of one Gaussian, in the order of the cull tests: non-finite
 // input, depth at or before the near plane, beyond the far plane, opacity below
 // alpha_min, degenerate quaternion, footprint off the image; 0 = visible.
@@ -196,6 +223,8 @@ __device__ inline int classify(const splat_settings &S, const double *M, const C
     if (!gi.opac_ok) return PC_OPAC;
     if (!gi.quat_ok) return PC_QUAT;
     if (offscreen_bound(S, M, C, W, H, gi.x, gi.s, (float)gi.G.k2, P.depth32)) return PC_OFF;
+    // most visible pairs are decided here; the float64 projection is for the ones near an edge
+    if (onscreen_bound(S, M, C, W, H, gi.x, (float)gi.G.k2, P.depth32)) return PC_OK;
     project_view(S, M, C, gi.x, gi.s, gi.G, false, P);
     return footprint(S, gi.G.k2, W, H, P);
 }
@@ -281,7 +310,8 @@ __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, sp
     }
 }
 
-// The slots' gradients, which the render adjoint accumulates, start at zero.
+// The slots' gradients, which the render adjoint accumulates, start at zero (a separate
+// pass: clearing them in the write pass measured slower).
 __global__ void zero_grad2d_kernel(const uint32_t *counts, float *g) {
     uint64_t n = (uint64_t)counts[CNT_SLOTS] * 9;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
