@@ -37,7 +37,10 @@ def _gpu_dssim(img, tgt, roi, weight, base=None):
 
 
 @pytest.mark.parametrize("kind", ["random", "smooth"])
-@pytest.mark.parametrize("shape, roi", [((2, 37, 50), 0), ((2, 37, 50), 11), ((1, 70, 97), 35), ((3, 9, 13), 2)])
+# tile counts (32 x 21 output tiles per view and channel): 24, 24, 24, 9, 3 (fewer workgroups than
+# XCDs: one sequence of tiles) and 18 (a grid of 16 workgroups: uneven ranges per XCD)
+@pytest.mark.parametrize("shape, roi", [((2, 37, 50), 0), ((2, 37, 50), 11), ((1, 70, 97), 35), ((3, 9, 13), 2),
+                                        ((1, 9, 13), 0), ((1, 30, 70), 0)])
 def test_dssim_vs_oracle(kind, shape, roi):
     say(f"case: dssim {kind} shape={shape} roi={roi}")
     V, H, W = shape

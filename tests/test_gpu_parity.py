@@ -108,6 +108,69 @@ def test_project_vs_oracle(tile):
     _project_check(synth.small_drive(1, n_frames=2), tile)
 
 
+def _edge_scene(seed, n=3000, roi_y0=0):
+    """Small, faint Gaussians whose means project within a few pixels of the image borders
+    (and of the first row of the region of interest): the projection's visibility test is
+    decided there by its exact float64 path or by its float32 bounds, and the opacities span
+    the value below which a footprint's half-width can fall under half a pixel."""
+    s = synth.tiny_scene(seed)
+    rng = np.random.default_rng(seed)
+    W, H = s.rig.W, s.rig.H
+    fx, fy, cx, cy = s.rig.intr[0]
+    u = rng.uniform(-3.0, 3.0, n)
+    v = rng.uniform(-3.0, 3.0, n)
+    side = rng.integers(0, 4, n)
+    u = np.where(side == 1, W + u, u)                       # left / right edges
+    ys = rng.choice([0.0, float(H), float(roi_y0)], n)
+    v = np.where(side >= 2, ys + v, rng.uniform(0, H, n))   # top / bottom / region-of-interest row
+    u = np.where(side >= 2, rng.uniform(0, W, n), u)
+    z = rng.uniform(2.0, 20.0, n)
+    mean = np.stack([(u - cx) / fx * z, (v - cy) / fy * z, z])
+    g = s.gauss.subset(np.arange(n) % s.gauss.n)
+    g.mean = mean.astype(np.float32)
+    g.scale = np.exp(rng.uniform(np.log(1e-4), np.log(0.05), size=(3, n))).astype(np.float32)
+    g.opacity = (rng.choice([1.0, 1.1, 1.25, 1.3, 1.35, 1.5, 3.0, 50.0, 250.0], n) / 255.0).astype(np.float32)
+    s.gauss = g
+    return s
+
+
+@pytest.mark.parametrize("pad_px, roi_y0", [(0.1, 0), (0.6, 0), (0.1, 23)])
+def test_projection_visibility_at_image_edges(pad_px, roi_y0):
+    """Pairs whose footprints touch the image border: the visible set, the float32 depth
+    and the float64 mean and conic match the oracle, whichever test decided visibility."""
+    say(f"case: projection at the image edges pad_px={pad_px} roi_y0={roi_y0}")
+    scene = _edge_scene(3, roi_y0=roi_y0)
+    w2c, _, _ = oracle.pose(scene.traj, scene.rig, scene.xi, scene.delta, scene.views)
+    intr = oracle.view_intr(scene.rig, scene.views)
+    W, H = scene.rig.W, scene.rig.H
+    ds = pl.DeviceScene.from_scene(scene)
+    xi = torch.as_tensor(scene.xi, dtype=torch.float64, device="cuda")
+    dl = torch.as_tensor(scene.delta, dtype=torch.float64, device="cuda")
+    w2c_t = torch.as_tensor(np.ascontiguousarray(w2c), dtype=torch.float64, device="cuda")
+    st = pl.make_settings(tile=(16, 16), pad_px=pad_px, roi_y0=roi_y0)
+    fr = pl.fit_frame(ds, xi, dl, st, w2c=w2c_t)
+    pl.forward(fr, ds, xi, dl, w2c=w2c_t)
+    torch.cuda.synchronize()
+    ns, _ = fr.counts()
+    meta = fr.meta(ns).cpu().numpy()
+    rec = fr.records(ns).cpu().numpy()
+    proj = oracle.project_all(scene.gauss, w2c, intr, W, H, oracle.Settings(pad_px=pad_px, roi_y0=roi_y0))
+    gids = meta[:, 0]
+    vis = np.nonzero(proj["cull"][0] == 0)[0]
+    rm = set(np.nonzero(proj["rect_margin"][0])[0])
+    say(f"  visible {len(gids)} of {scene.gauss.n} (oracle {len(vis)}, {len(rm)} at a rounding step)")
+    assert 200 < len(vis) < scene.gauss.n - 200   # both kinds of pair are present
+    assert set(gids) ^ set(vis) <= rm
+    common = np.intersect1d(gids, vis)
+    idx = np.searchsorted(gids, common)
+    r = rec[idx]
+    assert np.array_equal(r[:, 11].view(np.uint32), proj["depth32"][0][common].view(np.uint32))
+    mu = r[:, 0:2].astype(np.float64) + r[:, 2:4].astype(np.float64)
+    np.testing.assert_allclose(mu, proj["mu"][0][common], rtol=0, atol=1e-5)
+    np.testing.assert_allclose(r[:, 4:7], proj["conic"][0][common], rtol=2e-6,
+                               atol=2e-6 * np.abs(proj["conic"][0][common]).max())
+
+
 @pytest.mark.parametrize("tile", TILES)
 def test_bin_sort_vs_oracle(tile):
     say(f"case: bin_sort tile={tile}")
