@@ -152,7 +152,20 @@ typedef struct splat_plan {
     size_t off_bmask;       /* u8[inst_cap]: per instance, bit k set when the forward blended it into a
                                pixel of 8x8 sub-block k of its tile; the adjoint skips the others      */
     size_t off_dkey;        /* u32[slot_cap]: depth field of each slot's sort key,
-                               bits(depth32) - bits(near_z) (a compact copy for the emission)        */
+                               bits(depth32) - bits(near_z) (a compact copy for the emission; with
+                               slot_sort, the slot sort's input keys, overwritten by it)             */
+    int32_t slot_sort;      /* 1: the slots are sorted by their depth field first, carrying a packed
+                               payload; the instances are emitted in that order with u32 keys
+                               view*T + tile and sorted on the tile bits only (the same order as the
+                               64-bit sort: stable sorts, ties in depth keep the slot order).  Chosen
+                               when the payload fits 64 bits; 0: one 64-bit key per instance.        */
+    int32_t pack_bits[3];   /* slot_sort: widths b0, b1, b2 of the payload fields: slot | first tile
+                               << b0 | (w - 1) << (b0 + tile_bits) | (h - 1) << (b0 + tile_bits + b1),
+                               the tile rect being w x h tiles from its first tile (view*T + tile) */
+    size_t off_spay;        /* u64[2][slot_cap]: packed payloads of the slot sort (slot_sort)        */
+    size_t off_skeys;       /* u32[slot_cap]: the slot sort's second key buffer (slot_sort)          */
+    size_t off_soff;        /* u32[slot_cap+1]: tiles per slot in depth order, scanned to instance
+                               offsets (slot_sort)                                                   */
 } splat_plan;
 
 /* Fill `s` with the default settings listed above (16x16 tiles, batch 64,
@@ -228,15 +241,25 @@ SPLAT_API int splat_project(const splat_plan *plan, void *ws, const splat_gaussi
                   const double *intr, void *stream);
 
 /*
- * Tile binning: one instance per (slot, covered tile) with key
- * ((view*T + tile) << depth_bits) | (bits(depth32) - bits(near_z)) and value =
- * slot, emitted in (view, Gaussian, tile row-major) order, then a stable LSD
- * radix sort on the used key bits, so every tile list is in (depth32, Gaussian
- * id) order.  Writes the sorted values, per-(view, tile) ranges and the
- * cost-ordered work queue in the workspace; plan->sorted_buf names the buffer
- * that holds the sorted result (it is a function of the plan only).
- * The per-slot tile counts written by splat_project are turned into instance
- * offsets in place, so call this exactly once after each splat_project.
+ * Tile binning (the paper has no passage for it: it is how Phi of Eq. 5 finds
+ * the Gaussians of a tile in depth order).  Every tile list ends up in
+ * (depth32, Gaussian id) order, value = slot:
+ *  - plan->slot_sort = 1: the slots are sorted by bits(depth32) - bits(near_z)
+ *    (stable LSD radix sort, so equal depths keep the slot order, which is
+ *    (view, Gaussian id)), one instance per (slot, covered tile) is emitted in
+ *    that order with key view*T + tile, and a stable radix sort on the tile bits
+ *    finishes the lists;
+ *  - plan->slot_sort = 0: the instances are emitted in (view, Gaussian, tile
+ *    row-major) order with key ((view*T + tile) << depth_bits) | (bits(depth32)
+ *    - bits(near_z)) and sorted on all key bits.
+ * Writes the sorted values, per-(view, tile) ranges and the cost-ordered work
+ * queue in the workspace; plan->sorted_buf names the buffer that holds the
+ * sorted result (it is a function of the plan only).  With slot_sort = 0 the
+ * per-slot tile counts written by splat_project are turned into instance
+ * offsets in place; with slot_sort = 1 the slot sort consumes the depth fields.
+ * Either way, call this exactly once after each splat_project.  When the
+ * instances exceed inst_cap, the longest prefix of whole slots in emission
+ * order is kept and SPLAT_ST_CAPACITY is set.
  */
 SPLAT_API int splat_bin_sort(const splat_plan *plan, void *ws, void *stream);
 

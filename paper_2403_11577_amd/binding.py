@@ -50,7 +50,9 @@ class splat_plan(C.Structure):
                 [("sorted_buf", C.c_int32), ("radix_bits", C.c_int32), ("split_len", C.c_int32),
                  ("key_shift", C.c_int32), ("chk_cap", C.c_int64), ("bq_cap", C.c_int64)] +
                 [(n, C.c_size_t) for n in ("off_bqueue", "off_bqoff", "off_chk", "off_chklast", "off_bmask",
-                                                      "off_dkey")])
+                                                      "off_dkey")] +
+                [("slot_sort", C.c_int32), ("pack_bits", C.c_int32 * 3)] +
+                [(n, C.c_size_t) for n in ("off_spay", "off_skeys", "off_soff")])
 
 
 ADAM_MAX_GROUPS = 8

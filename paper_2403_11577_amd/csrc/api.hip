@@ -40,6 +40,29 @@ static int bit_length(uint64_t x) {
     return b;
 }
 
+// Where the sorted instances end up: the buffer (0 or 1) after the last pass, and key_shift >= 0
+// when the sorted keys are u32 (key >> key_shift).  The 64-bit instance sort narrows its keys to
+// 32 bits from the first pass whose remaining digits fit 32 bits above a shift inside the depth
+// field; the slot-first sort's instance keys are the tile field itself (key >> depth_bits).
+static void sort_fields(const splat_plan &p, int slot_sort, int32_t *sorted_buf, int32_t *key_shift) {
+    if (slot_sort) {
+        *sorted_buf = ((p.tile_bits + kRadixBits - 1) / kRadixBits) & 1;
+        *key_shift = p.depth_bits;
+        return;
+    }
+    int bits = p.depth_bits + p.tile_bits;
+    int passes = (bits + kRadixBits - 1) / kRadixBits;
+    *sorted_buf = passes & 1;
+    *key_shift = -1;
+    for (int ps = 0; ps + 1 < passes; ++ps) {
+        int s1 = kRadixBits * (ps + 1);
+        if (s1 <= p.depth_bits && bits - s1 <= 32) {
+            *key_shift = s1;
+            break;
+        }
+    }
+}
+
 static uint32_t fbits(float f) {
     uint32_t u;
     memcpy(&u, &f, 4);
@@ -91,6 +114,20 @@ static int check_plan(const splat_plan *p, const void *ws, const char *who) {
     if (p->split_len < 64 || p->split_len > (1 << 24) || (p->split_len & (p->split_len - 1)) ||
         p->chk_cap != 2 * ((p->inst_cap + p->split_len - 1) / p->split_len) + 1 || p->bq_cap != ntiles + p->chk_cap) {
         set_error("%s: plan's split fields are inconsistent (make a new plan instead of editing them)", who);
+        return SPLAT_EINVAL;
+    }
+    // the slot-first sort may be switched off (the 64-bit instance sort needs nothing extra), with
+    // sorted_buf and key_shift set to match; it may not be switched on where the payload does not fit
+    int32_t sb = 0, ks = 0;
+    bool fits = p->pack_bits[0] >= (p->slot_cap > 1 ? bit_length((uint64_t)(p->slot_cap - 1)) : 1) &&
+                p->pack_bits[1] >= bit_length((uint64_t)(p->tiles_x - 1)) &&
+                p->pack_bits[2] >= bit_length((uint64_t)(p->tiles_y - 1)) &&
+                p->pack_bits[0] + p->tile_bits + p->pack_bits[1] + p->pack_bits[2] <= 64;
+    if (p->slot_sort == 0 || p->slot_sort == 1) sort_fields(*p, p->slot_sort, &sb, &ks);
+    if ((p->slot_sort != 0 && p->slot_sort != 1) || (p->slot_sort == 1 && !fits) || p->sorted_buf != sb ||
+        p->key_shift != ks) {
+        set_error("%s: plan's sort fields are inconsistent (slot_sort %d, sorted_buf %d, key_shift %d)", who,
+                  p->slot_sort, p->sorted_buf, p->key_shift);
         return SPLAT_EINVAL;
     }
     return SPLAT_OK;
@@ -204,20 +241,13 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     p.n_gauss = n_gauss;
     p.slot_cap = slot_cap;
     p.inst_cap = inst_cap;
-    int bits = p.depth_bits + p.tile_bits;
-    int passes = (bits + kRadixBits - 1) / kRadixBits;
     p.radix_bits = kRadixBits;
-    p.sorted_buf = passes & 1;
-    // the sort carries 32-bit keys (key >> key_shift) from the first pass whose remaining digits
-    // fit 32 bits, if that shift stays within the depth field (the tile stays recoverable)
-    p.key_shift = -1;
-    for (int ps = 0; ps + 1 < passes; ++ps) {
-        int s1 = kRadixBits * (ps + 1);
-        if (s1 <= p.depth_bits && bits - s1 <= 32) {
-            p.key_shift = s1;
-            break;
-        }
-    }
+    // the slot-first sort packs (slot, first tile, rect width - 1, rect height - 1) into 64 bits
+    p.pack_bits[0] = slot_cap > 1 ? bit_length((uint64_t)(slot_cap - 1)) : 1;
+    p.pack_bits[1] = bit_length((uint64_t)(p.tiles_x - 1));
+    p.pack_bits[2] = bit_length((uint64_t)(p.tiles_y - 1));
+    p.slot_sort = p.pack_bits[0] + p.tile_bits + p.pack_bits[1] + p.pack_bits[2] <= 64 ? 1 : 0;
+    sort_fields(p, p.slot_sort, &p.sorted_buf, &p.key_shift);
 
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -262,6 +292,9 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     p.off_chklast = take((size_t)p.chk_cap * (size_t)(s->tile_w * s->tile_h) * 4);
     p.off_bmask = take((size_t)inst_cap);
     p.off_dkey = take((size_t)slot_cap * 4);
+    p.off_spay = take(p.slot_sort ? (size_t)slot_cap * 16 : 0);
+    p.off_skeys = take(p.slot_sort ? (size_t)slot_cap * 4 : 0);
+    p.off_soff = take(p.slot_sort ? (size_t)(slot_cap + 1) * 4 : 0);
     p.ws_bytes = off;
     *plan = p;
     return SPLAT_OK;

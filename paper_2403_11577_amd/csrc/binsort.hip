@@ -1,11 +1,17 @@
-// binsort.hip -- tile binning: scans, instance emission, stable LSD radix sort on
-// 64-bit keys, per-(view, tile) ranges and the cost-ordered work queue.
+// binsort.hip -- tile binning: scans, instance emission, stable LSD radix sorts,
+// per-(view, tile) ranges and the cost-ordered work queue.
 //
-// Every (slot, covered tile) pair becomes one instance with key
-//   ((view * T + tile) << depth_bits) | (bits(depth32) - bits(near_z))
-// and value = slot.  Instances are emitted in (view, Gaussian, tile row-major)
-// order and the sort is stable, so inside a tile the order is (depth32,
-// Gaussian id) -- ties on depth are broken by the Gaussian index.
+// Every (slot, covered tile) pair becomes one instance with value = slot, and every
+// tile list ends up in (depth32, Gaussian id) order.  Two ways:
+//  - slot-first (the default where a slot's payload fits 64 bits): the slots, which
+//    the projection numbers in (view, Gaussian id) order, are sorted by
+//    bits(depth32) - bits(near_z) carrying (slot, first tile, rect size); their
+//    instances are emitted in that order with key view * T + tile and sorted on
+//    the tile bits.  The depth passes then move one element per visible pair rather
+//    than per (pair, tile), and the instance passes 32-bit keys.
+//  - one 64-bit key per instance, ((view * T + tile) << depth_bits) | (bits(depth32)
+//    - bits(near_z)), emitted in (view, Gaussian, tile row-major) order.
+// All sorts are stable, so ties on depth are broken by the Gaussian index.
 //
 // Radix sort: reduce-then-scan per kRadixBits-bit digit with a fixed number of
 // partitions (the key count lives on the device, so the grid never depends on
@@ -193,6 +199,57 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint32_t *__restrict__ 
     }
 }
 
+// Slot-first binning.  A slot's payload (written by the projection) packs the slot id, its first
+// tile (view * T + tile) and its rect's width and height in tiles minus one, at bit offsets 0,
+// b0, b0 + tb, b0 + tb + b1; after the depth sort of the slots, pay[s] is the payload of the s-th
+// nearest slot.
+struct PayBits {
+    int b0, tb, b1;
+};
+
+__device__ inline uint64_t field(uint64_t p, int at, int width) {
+    if (width == 0 || at >= 64) return 0ull;
+    const uint64_t v = p >> at;
+    return width >= 64 ? v : v & ((1ull << width) - 1ull);
+}
+
+// tiles of every slot in depth order (scanned afterwards to the instance offsets)
+__global__ __launch_bounds__(256) void slot_tiles_kernel(const uint32_t *__restrict__ counts,
+                                                        const uint64_t *__restrict__ pay, PayBits pb,
+                                                        uint32_t *__restrict__ soff) {
+    const uint32_t ns = counts[CNT_SLOTS];
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t p = pay[s];
+        const uint32_t w = (uint32_t)field(p, pb.b0 + pb.tb, pb.b1) + 1u;
+        const uint32_t h = (uint32_t)field(p, pb.b0 + pb.tb + pb.b1, 64) + 1u;
+        soff[s] = w * h;
+    }
+}
+
+// one instance per (slot, covered tile) in depth order: key view * T + tile (u32), value slot
+__global__ __launch_bounds__(256) void emit_sorted_kernel(const uint32_t *__restrict__ counts,
+                                                         const uint32_t *__restrict__ soff,
+                                                         const uint64_t *__restrict__ pay, PayBits pb, int tiles_x,
+                                                         uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const uint32_t ns = counts[CNT_SLOTS];
+    const uint32_t ni = counts[CNT_INST];  // <= capacity; only slots wholly below it emit
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t o = soff[s];
+        const uint64_t p = pay[s];
+        const uint32_t slot = (uint32_t)field(p, 0, pb.b0);
+        const uint32_t first = (uint32_t)field(p, pb.b0, pb.tb);
+        const uint32_t w = (uint32_t)field(p, pb.b0 + pb.tb, pb.b1) + 1u;
+        const uint32_t h = (uint32_t)field(p, pb.b0 + pb.tb + pb.b1, 64) + 1u;
+        if ((uint64_t)o + (uint64_t)w * h > (uint64_t)ni) continue;
+        for (uint32_t dy = 0; dy < h; ++dy)
+            for (uint32_t dx = 0; dx < w; ++dx) {
+                keys[o] = first + dy * (uint32_t)tiles_x + dx;
+                vals[o] = slot;
+                ++o;
+            }
+    }
+}
+
 // -------------------------------------------------------------------------------------
 // radix sort
 // -------------------------------------------------------------------------------------
@@ -225,15 +282,15 @@ static_assert(kRadixDigits % RS_T == 0, "digits must be a multiple of the workgr
 constexpr int RS_UKPT = 16;  // keys per thread per upsweep round
 
 template <typename K>
-__global__ __launch_bounds__(RS_T) void radix_upsweep_kernel(const K *keys, const uint32_t *counts, int shift,
-                                                            int nparts, uint32_t *hist) {
+__global__ __launch_bounds__(RS_T) void radix_upsweep_kernel(const K *keys, const uint32_t *counts, int cnt_idx,
+                                                            int shift, int nparts, uint32_t *hist) {
     // one LDS histogram per wave, plain LDS atomics (equal digits in a wave serialise in hardware)
     __shared__ uint32_t h[RS_T / 64][kRadixDigits];
     const int w = threadIdx.x >> 6;
     for (int q = 0; q < RS_DPT; ++q)
         for (int ww = 0; ww < RS_T / 64; ++ww) h[ww][q * RS_T + threadIdx.x] = 0;
     __syncthreads();
-    uint32_t n = counts[CNT_INST];
+    uint32_t n = counts[cnt_idx];
     uint32_t b, e;
     chunk_of(n, nparts, blockIdx.x, b, e);
     // RS_UKPT independent coalesced loads per thread are in flight before their counts
@@ -288,27 +345,28 @@ constexpr int RS_KPT = SPLAT_RADIX_KPT;  // keys per thread per tile
 constexpr int RS_WTILE = 64 * RS_KPT;
 constexpr int RS_TILE = RS_T * RS_KPT;
 
-template <typename K>
-__device__ inline void rs_load(const K *kin, const uint32_t *vin, uint32_t base, uint32_t e, int w, int lane,
-                               K (&key)[RS_KPT], uint32_t (&val)[RS_KPT]) {
+template <typename K, typename V>
+__device__ inline void rs_load(const K *kin, const V *vin, uint32_t base, uint32_t e, int w, int lane,
+                               K (&key)[RS_KPT], V (&val)[RS_KPT]) {
 #pragma unroll
     for (int k = 0; k < RS_KPT; ++k) {
         uint32_t i = base + w * RS_WTILE + k * 64 + lane;
         bool act = i < e;
         key[k] = act ? kin[i] : (K)0;
-        val[k] = act ? vin[i] : 0u;
+        val[k] = act ? vin[i] : (V)0;
     }
 }
 
 // KI keys in, KO keys out: a pass after which every remaining digit lies at or above bit
 // out_shift can write the keys shifted down by out_shift as 32-bit words (the later passes
-// then move 4 bytes less per key, read and written)
-template <typename KI, typename KO>
-__global__ __launch_bounds__(RS_T) void radix_downsweep_kernel(const KI *kin, const uint32_t *vin, KO *kout,
-                                                              uint32_t *vout, const uint32_t *counts, int shift,
+// then move 4 bytes less per key, read and written).  V: the values carried along; the key
+// count is counts[cnt_idx].
+template <typename KI, typename KO, typename V>
+__global__ __launch_bounds__(RS_T) void radix_downsweep_kernel(const KI *kin, const V *vin, KO *kout, V *vout,
+                                                              const uint32_t *counts, int cnt_idx, int shift,
                                                               int out_shift, int nparts, const uint32_t *hoff) {
     __shared__ KI sk[RS_TILE];
-    __shared__ uint32_t sv[RS_TILE];
+    __shared__ V sv[RS_TILE];
     __shared__ uint32_t wc[RS_T / 64][kRadixDigits];  // per-wave running counts, then per-wave bases
     __shared__ uint32_t tstart[kRadixDigits];         // first LDS position of each digit in the tile
     __shared__ uint32_t gstart[kRadixDigits];         // global position of the tile's first key of each digit
@@ -321,17 +379,18 @@ __global__ __launch_bounds__(RS_T) void radix_downsweep_kernel(const KI *kin, co
         for (int ww = 0; ww < RS_T / 64; ++ww) wc[ww][d] = 0;
     }
     __syncthreads();
-    uint32_t n = counts[CNT_INST];
+    uint32_t n = counts[cnt_idx];
     uint32_t b, e;
     chunk_of(n, nparts, blockIdx.x, b, e);
     KI key[RS_KPT];
-    uint32_t val[RS_KPT];
+    V val[RS_KPT];
     if (b < e) rs_load(kin, vin, b, e, w, lane, key, val);
     int parity = 0;
     for (uint32_t base = b; base < e; base += RS_TILE) {
         uint32_t tn = min((uint32_t)RS_TILE, e - base);
         KI nkey[RS_KPT];
-        uint32_t nval[RS_KPT], rank[RS_KPT];
+        V nval[RS_KPT];
+        uint32_t rank[RS_KPT];
         if (base + RS_TILE < e) rs_load(kin, vin, base + RS_TILE, e, w, lane, nkey, nval);
         // stable rank inside the wave: the peers' leader bumps the wave's counter after all
         // lanes read it (LDS operations of one wave complete in issue order)
@@ -577,28 +636,54 @@ int launch_radix_sort_keys(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v
         auto *ki32 = reinterpret_cast<uint32_t *>(ki);
         auto *ko32 = reinterpret_cast<uint32_t *>(ko);
         if (sw >= 0 && ps > sw)
-            hipLaunchKernelGGL(radix_upsweep_kernel<uint32_t>, dim3(nparts), dim3(RS_T), 0, st, ki32, counts, shift - S,
-                               nparts, hist);
+            hipLaunchKernelGGL(radix_upsweep_kernel<uint32_t>, dim3(nparts), dim3(RS_T), 0, st, ki32, counts,
+                               (int)CNT_INST, shift - S, nparts, hist);
         else
-            hipLaunchKernelGGL(radix_upsweep_kernel<uint64_t>, dim3(nparts), dim3(RS_T), 0, st, ki, counts, shift, nparts,
-                               hist);
+            hipLaunchKernelGGL(radix_upsweep_kernel<uint64_t>, dim3(nparts), dim3(RS_T), 0, st, ki, counts,
+                               (int)CNT_INST, shift, nparts, hist);
         if ((rc = launch_status("radix_upsweep"))) return rc;
         if ((rc = launch_scan_u32(hist, hist, nullptr, nh, partials, nullptr, st))) return rc;
         if (sw < 0 || ps < sw)
-            hipLaunchKernelGGL((radix_downsweep_kernel<uint64_t, uint64_t>), dim3(nparts), dim3(RS_T), 0, st, ki, vi, ko,
-                               vo, counts, shift, 0, nparts, hist);
+            hipLaunchKernelGGL((radix_downsweep_kernel<uint64_t, uint64_t, uint32_t>), dim3(nparts), dim3(RS_T), 0, st, ki,
+                               vi, ko, vo, counts, (int)CNT_INST, shift, 0, nparts, hist);
         else if (ps == sw)
-            hipLaunchKernelGGL((radix_downsweep_kernel<uint64_t, uint32_t>), dim3(nparts), dim3(RS_T), 0, st, ki, vi,
-                               ko32, vo, counts, shift, S, nparts, hist);
+            hipLaunchKernelGGL((radix_downsweep_kernel<uint64_t, uint32_t, uint32_t>), dim3(nparts), dim3(RS_T), 0, st, ki,
+                               vi, ko32, vo, counts, (int)CNT_INST, shift, S, nparts, hist);
         else
-            hipLaunchKernelGGL((radix_downsweep_kernel<uint32_t, uint32_t>), dim3(nparts), dim3(RS_T), 0, st, ki32, vi,
-                               ko32, vo, counts, shift - S, 0, nparts, hist);
+            hipLaunchKernelGGL((radix_downsweep_kernel<uint32_t, uint32_t, uint32_t>), dim3(nparts), dim3(RS_T), 0, st,
+                               ki32, vi, ko32, vo, counts, (int)CNT_INST, shift - S, 0, nparts, hist);
         if ((rc = launch_status("radix_downsweep"))) return rc;
         uint64_t *tk = ki; ki = ko; ko = tk;
         uint32_t *tv = vi; vi = vo; vo = tv;
     }
     *sorted_in_1 = passes & 1;
     if (key_shift) *key_shift = sw >= 0 ? S : -1;
+    return 0;
+}
+
+// Stable LSD sort of counts[cnt_idx] u32 keys on bits [0, bits), carrying V values; the result
+// is in the second buffers when *sorted_in_1 (an odd number of passes).
+template <typename V>
+int launch_radix_sort_u32(uint32_t *k0, uint32_t *k1, V *v0, V *v1, const uint32_t *counts, int cnt_idx, int bits,
+                          int nparts, uint32_t *hist, uint32_t *partials, hipStream_t st, int *sorted_in_1) {
+    const int passes = (bits + kRadixBits - 1) / kRadixBits;
+    const int nh = kRadixDigits * nparts;
+    uint32_t *ki = k0, *ko = k1;
+    V *vi = v0, *vo = v1;
+    int rc = 0;
+    for (int ps = 0; ps < passes; ++ps) {
+        const int shift = kRadixBits * ps;
+        hipLaunchKernelGGL(radix_upsweep_kernel<uint32_t>, dim3(nparts), dim3(RS_T), 0, st, ki, counts, cnt_idx, shift,
+                           nparts, hist);
+        if ((rc = launch_status("radix_upsweep"))) return rc;
+        if ((rc = launch_scan_u32(hist, hist, nullptr, nh, partials, nullptr, st))) return rc;
+        hipLaunchKernelGGL((radix_downsweep_kernel<uint32_t, uint32_t, V>), dim3(nparts), dim3(RS_T), 0, st, ki, vi, ko,
+                           vo, counts, cnt_idx, shift, 0, nparts, hist);
+        if ((rc = launch_status("radix_downsweep"))) return rc;
+        uint32_t *tk = ki; ki = ko; ko = tk;
+        V *tv = vi; vi = vo; vo = tv;
+    }
+    *sorted_in_1 = passes & 1;
     return 0;
 }
 
@@ -623,26 +708,52 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
     uint32_t *qh = hist + (size_t)kRadixDigits * p.n_sort_blocks + 1;
     int nT = p.n_views * p.tiles_per_view;
 
-    // instance offsets: exclusive scan of the per-slot tile counts
-    int rc = launch_scan_u32(ntiles, ntiles, counts + CNT_SLOTS, p.slot_cap, partials, nullptr, st);
-    if (rc) return rc;
-    hipLaunchKernelGGL(inst_finish_kernel, dim3(1), dim3(64), 0, st, ntiles, p.inst_cap, counts, status);
-    if ((rc = launch_status("inst_finish"))) return rc;
     int eb = (int)((p.slot_cap + 255) / 256);  // about one slot per thread
     if (eb > 65536) eb = 65536;
-    hipLaunchKernelGGL(emit_kernel, dim3(eb), dim3(256), 0, st, counts, ntiles, ws_at<Rect16>(ws, p.off_rect),
-                       ws_at<uint32_t>(ws, p.off_dkey), ws_at<int2>(ws, p.off_meta), p.tiles_x, p.tiles_per_view,
-                       p.depth_bits, keys0, vals0);
-    if ((rc = launch_status("emit"))) return rc;
-
-    // LSD radix sort over the used key bits
-    // the passes after the depth digits carry 32-bit keys (key >> key_shift, key_shift <= depth_bits)
-    int in1 = 0, kshift = -1;
-    rc = launch_radix_sort_keys(keys0, keys1, vals0, vals1, counts, 0, p.depth_bits + p.tile_bits, p.n_sort_blocks,
-                                hist, partials, st, &in1, p.depth_bits, &kshift);
-    if (rc) return rc;
-    if (kshift != p.key_shift) {
-        set_error("bin_sort: plan key shift %d does not match the sort's %d", p.key_shift, kshift);
+    int rc = 0, in1 = 0, kshift = -1;
+    if (p.slot_sort) {
+        // slots by depth (the payload travels along), then the instances, emitted in that order,
+        // by tile: stable sorts, so a tile's list is in (depth, slot) order as with the 64-bit keys
+        uint64_t *pay0 = ws_at<uint64_t>(ws, p.off_spay), *pay1 = pay0 + p.slot_cap;
+        uint32_t *soff = ws_at<uint32_t>(ws, p.off_soff);
+        const PayBits pb{p.pack_bits[0], p.tile_bits, p.pack_bits[1]};
+        int sin1 = 0;
+        rc = launch_radix_sort_u32<uint64_t>(ws_at<uint32_t>(ws, p.off_dkey), ws_at<uint32_t>(ws, p.off_skeys), pay0,
+                                             pay1, counts, CNT_SLOTS, p.depth_bits, p.n_sort_blocks, hist, partials, st,
+                                             &sin1);
+        if (rc) return rc;
+        const uint64_t *pay = sin1 ? pay1 : pay0;
+        hipLaunchKernelGGL(slot_tiles_kernel, dim3(eb), dim3(256), 0, st, counts, pay, pb, soff);
+        if ((rc = launch_status("slot_tiles"))) return rc;
+        if ((rc = launch_scan_u32(soff, soff, counts + CNT_SLOTS, p.slot_cap, partials, nullptr, st))) return rc;
+        hipLaunchKernelGGL(inst_finish_kernel, dim3(1), dim3(64), 0, st, soff, p.inst_cap, counts, status);
+        if ((rc = launch_status("inst_finish"))) return rc;
+        uint32_t *k32 = reinterpret_cast<uint32_t *>(keys0);
+        hipLaunchKernelGGL(emit_sorted_kernel, dim3(eb), dim3(256), 0, st, counts, soff, pay, pb, p.tiles_x, k32, vals0);
+        if ((rc = launch_status("emit_sorted"))) return rc;
+        rc = launch_radix_sort_u32<uint32_t>(k32, reinterpret_cast<uint32_t *>(keys1), vals0, vals1, counts, CNT_INST,
+                                             p.tile_bits, p.n_sort_blocks, hist, partials, st, &in1);
+        if (rc) return rc;
+        kshift = p.depth_bits;  // the instance keys are the tile field of the 64-bit key
+    } else {
+        // instance offsets: exclusive scan of the per-slot tile counts
+        rc = launch_scan_u32(ntiles, ntiles, counts + CNT_SLOTS, p.slot_cap, partials, nullptr, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(inst_finish_kernel, dim3(1), dim3(64), 0, st, ntiles, p.inst_cap, counts, status);
+        if ((rc = launch_status("inst_finish"))) return rc;
+        hipLaunchKernelGGL(emit_kernel, dim3(eb), dim3(256), 0, st, counts, ntiles, ws_at<Rect16>(ws, p.off_rect),
+                           ws_at<uint32_t>(ws, p.off_dkey), ws_at<int2>(ws, p.off_meta), p.tiles_x, p.tiles_per_view,
+                           p.depth_bits, keys0, vals0);
+        if ((rc = launch_status("emit"))) return rc;
+        // LSD radix sort over the used key bits
+        // the passes after the depth digits carry 32-bit keys (key >> key_shift, key_shift <= depth_bits)
+        rc = launch_radix_sort_keys(keys0, keys1, vals0, vals1, counts, 0, p.depth_bits + p.tile_bits,
+                                    p.n_sort_blocks, hist, partials, st, &in1, p.depth_bits, &kshift);
+        if (rc) return rc;
+    }
+    if (kshift != p.key_shift || in1 != p.sorted_buf) {
+        set_error("bin_sort: plan key shift %d / sorted buffer %d do not match the sort's %d / %d", p.key_shift,
+                  p.sorted_buf, kshift, in1);
         return SPLAT_EINVAL;
     }
     const uint64_t *ki = in1 ? keys1 : keys0;

@@ -269,13 +269,21 @@ __global__ __launch_bounds__(256) void project_count_kernel(splat_settings S, sp
     flag_status(status, bits);
 }
 
+// Packing of a slot's payload for the slot-first bin sort (null spay: not used): slot id, first
+// tile (view * T + tile), rect width - 1 and height - 1 in tiles, at bit offsets 0, b0, b0 + tb,
+// b0 + tb + b1.
+struct SlotPack {
+    uint64_t *spay;
+    int b0, tb, b1, tiles_x, T;
+};
+
 // Write pass: the same walk, projecting only the pairs the count pass marked
 // visible, into their slots.
 __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, splat_gaussians g, const double *w2c,
                                                            const CamC *cam, int W, int H, int V, int nb,
                                                            const uint32_t *waveoff, const uint64_t *visbits,
                                                            int64_t slot_cap, float4 *rec, int2 *meta, Rect16 *rect,
-                                                           uint32_t *ntiles, uint32_t *dkey) {
+                                                           uint32_t *ntiles, uint32_t *dkey, SlotPack sp) {
     const int b = blockIdx.x, w = threadIdx.x >> 6, lane = __lane_id();
     const int64_t i = (int64_t)b * 256 + threadIdx.x;
     if (i >= g.n) return;
@@ -307,6 +315,13 @@ __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, sp
         rc.y0 = (uint16_t)(P.py0 / th); rc.y1 = (uint16_t)(P.py1 / th);
         rect[slot] = rc;
         ntiles[slot] = (uint32_t)(rc.x1 - rc.x0 + 1) * (uint32_t)(rc.y1 - rc.y0 + 1);
+        if (sp.spay) {
+            const uint64_t first = (uint64_t)v * (uint64_t)sp.T + (uint64_t)rc.y0 * (uint64_t)sp.tiles_x + rc.x0;
+            // a field of width 0 holds 0 and may sit at bit 64: no shift by 64
+            const int s1 = sp.b0 + sp.tb, s2 = s1 + sp.b1;
+            sp.spay[slot] = slot | (first << sp.b0) | (s1 < 64 ? (uint64_t)(rc.x1 - rc.x0) << s1 : 0ull) |
+                            (s2 < 64 ? (uint64_t)(rc.y1 - rc.y0) << s2 : 0ull);
+        }
     }
 }
 
@@ -602,7 +617,9 @@ int launch_project(const splat_plan &p, void *ws, const splat_gaussians &g, cons
     hipLaunchKernelGGL(project_write_kernel, dim3(nb), dim3(256), 0, st, p.s, g, w2c, cam, p.width, p.height, V, nb,
                        wavecnt, visbits, p.slot_cap, ws_at<float4>(ws, p.off_rec), ws_at<int2>(ws, p.off_meta),
                        ws_at<Rect16>(ws, p.off_rect), ws_at<uint32_t>(ws, p.off_ntiles),
-                       ws_at<uint32_t>(ws, p.off_dkey));
+                       ws_at<uint32_t>(ws, p.off_dkey),
+                       SlotPack{p.slot_sort ? ws_at<uint64_t>(ws, p.off_spay) : nullptr, p.pack_bits[0], p.tile_bits,
+                                p.pack_bits[1], p.tiles_x, p.tiles_per_view});
     if ((rc = launch_status("project_write"))) return rc;
     int zb = (int)((p.slot_cap * 9 + 255) / 256);
     if (zb > 8192) zb = 8192;

@@ -47,6 +47,22 @@ def gpu_render(scene, tile=(16, 16), batch=64, persistent=True, views=None, w2c=
                 status=fr.status(), slots=ns, inst=ni, w2c=fr.w2c.cpu().numpy())
 
 
+def use_instance_sort(fr):
+    """Switch a frame's plan from the slot-first bin sort to one 64-bit key per instance (always
+    allowed), with the sorted-buffer and key-shift fields of that sort; the library checks them."""
+    p = fr.plan
+    bits = int(p.depth_bits) + int(p.tile_bits)
+    rb = int(p.radix_bits)
+    passes = (bits + rb - 1) // rb
+    ks = -1
+    for ps in range(passes - 1):
+        s1 = rb * (ps + 1)
+        if s1 <= int(p.depth_bits) and bits - s1 <= 32:
+            ks = s1
+            break
+    p.slot_sort, p.sorted_buf, p.key_shift = 0, passes & 1, ks
+
+
 def compare_images(gpu, orc, tol=ALPHA_T_TOL):
     """Per-pixel comparison with the oracle's alternatives at flagged decisions.
 

@@ -42,7 +42,8 @@ def test_default_settings_are_the_documented_readings():
 def test_plan_layout_is_aligned_and_disjoint():
     s = B.default_settings()
     p = B.splat_plan_make(s, 3, 1000, 100, 37, 2000, 9000)
-    names = [n for n in B._PLAN_OFFS if n != "ws_bytes"] + ["off_bqueue", "off_bqoff", "off_chk", "off_chklast", "off_bmask", "off_dkey"]
+    names = [n for n in B._PLAN_OFFS if n != "ws_bytes"] + ["off_bqueue", "off_bqoff", "off_chk", "off_chklast",
+                                                           "off_bmask", "off_dkey", "off_spay", "off_skeys", "off_soff"]
     offs = sorted((getattr(p, n), n) for n in names)
     assert all(o % 256 == 0 for o, _ in offs)
     assert len({o for o, _ in offs}) == len(offs)
@@ -53,16 +54,42 @@ def test_plan_layout_is_aligned_and_disjoint():
     assert p.chk_cap == 2 * -(-9000 // 1024) + 1 and p.bq_cap == 63 + p.chk_cap
     assert p.off_chklast - p.off_chk >= p.chk_cap * 16 * 16 * 16
     assert p.off_bmask - p.off_chklast >= p.chk_cap * 16 * 16 * 4
-    assert p.off_dkey - p.off_bmask >= 9000 and p.ws_bytes - p.off_dkey >= 2000 * 4
+    assert p.off_dkey - p.off_bmask >= 9000 and p.off_spay - p.off_dkey >= 2000 * 4
+    assert p.off_skeys - p.off_spay >= 2000 * 16 and p.off_soff - p.off_skeys >= 2000 * 4
+    assert p.ws_bytes - p.off_soff >= 2001 * 4
     assert p.tiles_x == 7 and p.tiles_y == 3 and p.tiles_per_view == 21
     # key = (view*T + tile) << depth_bits | depth: 63 items need 6 bits, the 0.2..256 m window 27
     assert p.tile_bits == 6 and p.depth_bits == 27
     rb = p.radix_bits
     assert 4 <= rb <= 12
-    assert p.sorted_buf == ((p.tile_bits + p.depth_bits + rb - 1) // rb) % 2
-    # the sort narrows its keys to u32 (key >> key_shift) after the first pass whose remaining
-    # digits fit 32 bits, the shift staying within the depth field: 9 here (24 bits remain)
-    assert p.key_shift == rb and p.tile_bits + p.depth_bits - p.key_shift <= 32
+    # slot-first bin sort: payload = slot (11 bits for 2000 slots) | first tile (6) | w - 1 (3, 7
+    # tiles) | h - 1 (2, 3 tiles), 22 bits; the instance keys are the tile field (key >> 27)
+    assert p.slot_sort == 1 and list(p.pack_bits) == [11, 3, 2]
+    assert p.sorted_buf == ((p.tile_bits + rb - 1) // rb) % 2 and p.key_shift == p.depth_bits
+
+
+def test_plan_sort_fields_are_checked():
+    """The plan may be switched from the slot-first bin sort to one 64-bit key per instance (the
+    GPU parity tests run both), but only with the sorted-buffer and key-shift fields of that
+    sort; inconsistent sort fields are refused before anything is launched."""
+    L = B.lib()
+    p = B.splat_plan_make(B.default_settings(), 3, 1000, 100, 37, 2000, 9000)
+    rb = p.radix_bits
+    p.slot_sort = 0   # the 64-bit sort needs sorted_buf = passes mod 2 and key_shift = 9 here
+    assert L.splat_bin_sort(C.byref(p), C.c_void_p(16), None) == -1
+    assert b"sort fields are inconsistent" in L.splat_last_error()
+    p.sorted_buf = ((p.tile_bits + p.depth_bits + rb - 1) // rb) % 2
+    p.key_shift = -1
+    assert L.splat_render_fwd(C.byref(p), C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), None) == -1
+    assert b"sort fields are inconsistent" in L.splat_last_error()
+    p.slot_sort = 2
+    assert L.splat_bin_sort(C.byref(p), C.c_void_p(16), None) == -1
+    assert b"sort fields are inconsistent" in L.splat_last_error()
+    # the payload must fit: 2^40 slots would need 40 bits for the slot id alone
+    q = B.splat_plan_make(B.default_settings(), 3, 1000, 100, 37, 2000, 9000)
+    q.pack_bits[0] = 1
+    assert L.splat_bin_sort(C.byref(q), C.c_void_p(16), None) == -1
+    assert b"sort fields are inconsistent" in L.splat_last_error()
 
 
 @pytest.mark.parametrize("kw, msg", [

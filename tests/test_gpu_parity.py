@@ -15,7 +15,7 @@ import synth
 from paper_2403_11577_amd import binding as B
 from paper_2403_11577_amd import pipeline as pl
 
-from gpu_util import compare_images, gpu_render, rel_close, say
+from gpu_util import use_instance_sort, compare_images, gpu_render, rel_close, say
 
 pytestmark = pytest.mark.gpu
 
@@ -171,21 +171,40 @@ def test_projection_visibility_at_image_edges(pad_px, roi_y0):
                                atol=2e-6 * np.abs(proj["conic"][0][common]).max())
 
 
+@pytest.mark.parametrize("path", ["slot_first", "instance_keys"])
 @pytest.mark.parametrize("tile", TILES)
-def test_bin_sort_vs_oracle(tile):
-    say(f"case: bin_sort tile={tile}")
+def test_bin_sort_vs_oracle(tile, path):
+    say(f"case: bin_sort tile={tile} path={path}")
     scene = synth.small_drive(2, n_frames=2)
     g, proj, w2c = _project_check(scene, tile)
     fr = g["frame"]
-    ns, ni = g["slots"], g["inst"]
+    assert int(fr.plan.slot_sort) == 1  # the default where the payload fits 64 bits
+    if path == "instance_keys":
+        use_instance_sort(fr)
+        pl.forward(fr, g["ds"], g["xi"], g["delta"], w2c=torch.as_tensor(w2c, device="cuda"))
+        torch.cuda.synchronize()
+        assert fr.status() == 0
+    ns, ni = fr.counts()
+    assert (ns, ni) == (g["slots"], g["inst"])
     vals = fr.sorted_vals(ni).cpu().numpy().astype(np.int64)
     meta = fr.meta(ns).cpu().numpy()
     ranges = fr.ranges().cpu().numpy().astype(np.int64)
     # the lists tile the sorted instances in (view, tile) order, each instance once
     nz = ranges[ranges[:, 1] > ranges[:, 0]]
     assert nz[0, 0] == 0 and nz[-1, 1] == ni and np.all(nz[1:, 0] == nz[:-1, 1])
-    offs = fr.buf("ntiles", torch.int32, ns + 1).cpu().numpy().astype(np.int64)  # instance offsets per slot
-    assert offs[ns] == ni and np.array_equal(np.bincount(vals, minlength=ns), np.diff(offs))
+    if path == "instance_keys":  # the per-slot tile counts were scanned in place to instance offsets
+        per_slot = np.diff(fr.buf("ntiles", torch.int32, ns + 1).cpu().numpy().astype(np.int64))
+    else:
+        per_slot = fr.buf("ntiles", torch.int32, ns).cpu().numpy().astype(np.int64)
+    assert per_slot.sum() == ni and np.array_equal(np.bincount(vals, minlength=ns), per_slot)
+    # the sorted keys are the (view, tile) of every instance
+    keys = fr.sorted_keys(ni).cpu().numpy().astype(np.int64)
+    if int(fr.plan.key_shift) >= 0:
+        tile_of = keys >> (int(fr.plan.depth_bits) - int(fr.plan.key_shift))
+    else:
+        tile_of = keys >> int(fr.plan.depth_bits)
+    for t in np.nonzero(ranges[:, 1] > ranges[:, 0])[0][:: 7]:
+        assert np.all(tile_of[ranges[t, 0]:ranges[t, 1]] == t)
     T = int(fr.plan.tiles_per_view)
     W, H = scene.rig.W, scene.rig.H
     for v in range(scene.views.n):
@@ -202,14 +221,27 @@ def test_bin_sort_vs_oracle(tile):
 
 
 @pytest.mark.parametrize("tile", [(16, 16), (32, 16)])
-def test_bin_sort_long_lists_vs_oracle(tile):
-    """Tile lists longer than one LDS sort (4096 instances) are sorted in chunks and merged:
-    40,000 small Gaussians in front of a 64x32 camera put 5,000-10,000 instances in a tile;
-    every list must still be the oracle's (depth32, Gaussian id) order, and the image its image."""
-    say(f"case: bin_sort long lists tile={tile}")
+@pytest.mark.parametrize("path", ["slot_first", "instance_keys"])
+def test_bin_sort_long_lists_vs_oracle(tile, path):
+    """Tile lists far longer than one radix-sort tile of 4096 keys: 40,000 small Gaussians in
+    front of a 64x32 camera put 5,000-10,000 instances in a tile; every list must still be the
+    oracle's (depth32, Gaussian id) order, and the image its image, with either bin sort."""
+    say(f"case: bin_sort long lists tile={tile} path={path}")
     scene = synth.tiny_scene(9, n=40000, W=64, H=32, f=10.0)
     g, proj, w2c = _project_check(scene, tile)
     fr = g["frame"]
+    if path == "instance_keys":
+        use_instance_sort(fr)
+        img, T, last = pl.forward(fr, g["ds"], g["xi"], g["delta"], w2c=torch.as_tensor(w2c, device="cuda"))
+        torch.cuda.synchronize()
+        assert fr.status() == 0
+        g = dict(g, img=img.cpu().numpy().astype(np.float64), T=T.cpu().numpy().astype(np.float64))
+        lastp = last.cpu().numpy().astype(np.int64)
+        vals0 = fr.sorted_vals(g["inst"]).cpu().numpy().astype(np.int64)
+        meta0 = fr.meta(g["slots"]).cpu().numpy()
+        gid = np.full(lastp.shape, -1, np.int64)
+        gid[lastp >= 0] = meta0[vals0[lastp[lastp >= 0]], 0]
+        g["last_pos"], g["last_id"] = lastp, gid
     ns, ni = g["slots"], g["inst"]
     vals = fr.sorted_vals(ni).cpu().numpy().astype(np.int64)
     meta = fr.meta(ns).cpu().numpy()
