@@ -226,27 +226,54 @@ __global__ __launch_bounds__(256) void slot_tiles_kernel(const uint32_t *__restr
     }
 }
 
-// one instance per (slot, covered tile) in depth order: key view * T + tile (u32), value slot
+// one instance per (slot, covered tile) in depth order: key view * T + tile (u32), value slot.
+// A wave takes 64 consecutive slots; their instances form one run of the output, which the
+// lanes write in turn (coalesced stores, and no lane waits for a large slot of another): run
+// position q belongs to the last of the 64 slots that starts at or before q.
 __global__ __launch_bounds__(256) void emit_sorted_kernel(const uint32_t *__restrict__ counts,
                                                          const uint32_t *__restrict__ soff,
                                                          const uint64_t *__restrict__ pay, PayBits pb, int tiles_x,
                                                          uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    __shared__ uint32_t sbeg[4][64];  // per wave: run position of each slot's first instance
+    __shared__ uint64_t spl[4][64];   // per wave: the slots' payloads
     const uint32_t ns = counts[CNT_SLOTS];
     const uint32_t ni = counts[CNT_INST];  // <= capacity; only slots wholly below it emit
-    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t o = soff[s];
-        const uint64_t p = pay[s];
-        const uint32_t slot = (uint32_t)field(p, 0, pb.b0);
-        const uint32_t first = (uint32_t)field(p, pb.b0, pb.tb);
-        const uint32_t w = (uint32_t)field(p, pb.b0 + pb.tb, pb.b1) + 1u;
-        const uint32_t h = (uint32_t)field(p, pb.b0 + pb.tb + pb.b1, 64) + 1u;
-        if ((uint64_t)o + (uint64_t)w * h > (uint64_t)ni) continue;
-        for (uint32_t dy = 0; dy < h; ++dy)
-            for (uint32_t dx = 0; dx < w; ++dx) {
-                keys[o] = first + dy * (uint32_t)tiles_x + dx;
-                vals[o] = slot;
-                ++o;
-            }
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    for (uint64_t s0 = ((uint64_t)blockIdx.x * 4 + w) * 64; s0 < ns; s0 += (uint64_t)gridDim.x * 256) {
+        const uint64_t s = s0 + lane;
+        const bool valid = s < ns;
+        const uint32_t o = valid ? soff[s] : 0u;
+        const uint64_t p = valid ? pay[s] : 0ull;
+        uint32_t nt = 0u;
+        if (valid) {
+            nt = ((uint32_t)field(p, pb.b0 + pb.tb, pb.b1) + 1u) * ((uint32_t)field(p, pb.b0 + pb.tb + pb.b1, 64) + 1u);
+            if ((uint64_t)o + nt > (uint64_t)ni) nt = 0u;  // and so does every later slot
+        }
+        const uint32_t run0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)o);  // lane 0 is valid
+        const uint32_t rel = valid ? o - run0 : 0xFFFFFFFFu;
+        // the run ends where the last slot with instances ends
+        uint32_t end = nt ? rel + nt : 0u;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) end = max(end, (uint32_t)__shfl_xor((int)end, d, kWave));
+        sbeg[w][lane] = rel;
+        spl[w][lane] = p;
+        __builtin_amdgcn_wave_barrier();  // one wave: its LDS writes complete before its reads
+        for (uint32_t q = lane; q < end; q += 64) {
+            int j = 0;  // the last slot whose first instance is at or before q
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1)
+                if (sbeg[w][j + step] <= q) j += step;
+            const uint64_t pj = spl[w][j];
+            const uint32_t wj = (uint32_t)field(pj, pb.b0 + pb.tb, pb.b1) + 1u;
+            const uint32_t r = q - sbeg[w][j];
+            uint32_t dy = (uint32_t)((float)r * __builtin_amdgcn_rcpf((float)wj));
+            if (dy * wj > r) --dy;           // the float estimate is within one of r / wj
+            if ((dy + 1u) * wj <= r) ++dy;
+            const uint32_t dx = r - dy * wj;
+            keys[run0 + q] = (uint32_t)field(pj, pb.b0, pb.tb) + dy * (uint32_t)tiles_x + dx;
+            vals[run0 + q] = (uint32_t)field(pj, 0, pb.b0);
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -729,7 +756,8 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
         hipLaunchKernelGGL(inst_finish_kernel, dim3(1), dim3(64), 0, st, soff, p.inst_cap, counts, status);
         if ((rc = launch_status("inst_finish"))) return rc;
         uint32_t *k32 = reinterpret_cast<uint32_t *>(keys0);
-        hipLaunchKernelGGL(emit_sorted_kernel, dim3(eb), dim3(256), 0, st, counts, soff, pay, pb, p.tiles_x, k32, vals0);
+        hipLaunchKernelGGL(emit_sorted_kernel, dim3((eb + 3) / 4), dim3(256), 0, st, counts, soff, pay, pb, p.tiles_x,
+                           k32, vals0);
         if ((rc = launch_status("emit_sorted"))) return rc;
         rc = launch_radix_sort_u32<uint32_t>(k32, reinterpret_cast<uint32_t *>(keys1), vals0, vals1, counts, CNT_INST,
                                              p.tile_bits, p.n_sort_blocks, hist, partials, st, &in1);
