@@ -234,8 +234,8 @@ SPLAT_API int splat_pose_interp_bwd(int32_t K, const double *knot_t, const doubl
  * compacted per view in Gaussian order into slots.
  *   g: Gaussians (device planes); w2c[V][12] float64 (device);
  *   intr[V][4] float64 (fx, fy, cx, cy) per view (device).
- * Writes counts, view_off, rec, meta, rect, ntiles in the workspace, and zeroes
- * every written slot's gradient for splat_render_bwd.
+ * Writes counts, view_off, rec, meta, rect, ntiles (and, with plan->slot_sort,
+ * the slot payloads) in the workspace.
  */
 SPLAT_API int splat_project(const splat_plan *plan, void *ws, const splat_gaussians *g, const double *w2c,
                   const double *intr, void *stream);
@@ -272,7 +272,8 @@ SPLAT_API int splat_bin_sort(const splat_plan *plan, void *ws, void *stream);
  * T_final[V][H][W], last_pos[V][H][W] = instance index of the last blended
  * Gaussian (into the sorted value buffer) or -1.  Also records, for
  * splat_render_bwd, the checkpoints of the split lists it starts its chunks
- * from and which 8x8 sub-blocks of its tile each instance was blended into.
+ * from and which 8x8 sub-blocks of its tile each instance was blended into,
+ * and clears the slots' gradient sums that splat_render_bwd adds into.
  * With settings.split_fwd the chunks after the first of each split list are
  * composited in parallel from T = 1 and joined per pixel (C += T C_chunk,
  * T *= T_chunk); a chunk in which some pixel of the tile could reach t_min
@@ -288,7 +289,7 @@ SPLAT_API int splat_render_fwd(const splat_plan *plan, void *ws, float *img, flo
  * its list in reverse from last_pos, recovering T by division and the suffix
  * colour sum, and accumulates d(loss)/d(mean2d, conic, opacity, colour) of
  * every slot with wave-reduced atomics into the workspace gradient buffer,
- * which splat_project zeroed: call it once per projection (a second call adds
+ * which splat_render_fwd cleared: call it once per forward (a second call adds
  * to the first).  dL_dimg[V][3][H][W], T_final and last_pos are the caller's
  * (last two from splat_render_fwd).  The chunks of a split list are walked in
  * parallel, each from the checkpoint splat_render_fwd recorded, and a Gaussian

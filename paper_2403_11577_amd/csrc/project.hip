@@ -325,13 +325,6 @@ __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, sp
     }
 }
 
-// The slots' gradients, which the render adjoint accumulates, start at zero (a separate
-// pass: clearing them in the write pass measured slower).
-__global__ void zero_grad2d_kernel(const uint32_t *counts, float *g) {
-    uint64_t n = (uint64_t)counts[CNT_SLOTS] * 9;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        g[i] = 0.f;
-}
 
 // totals after the (view, wave) count scan: slot count (clamped), view offsets, capacity flag
 __global__ void project_finish_kernel(const uint32_t *waveoff, int V, int nw, int64_t slot_cap, uint32_t *counts,
@@ -620,11 +613,7 @@ int launch_project(const splat_plan &p, void *ws, const splat_gaussians &g, cons
                        ws_at<uint32_t>(ws, p.off_dkey),
                        SlotPack{p.slot_sort ? ws_at<uint64_t>(ws, p.off_spay) : nullptr, p.pack_bits[0], p.tile_bits,
                                 p.pack_bits[1], p.tiles_x, p.tiles_per_view});
-    if ((rc = launch_status("project_write"))) return rc;
-    int zb = (int)((p.slot_cap * 9 + 255) / 256);
-    if (zb > 8192) zb = 8192;
-    hipLaunchKernelGGL(zero_grad2d_kernel, dim3(zb), dim3(256), 0, st, counts, ws_at<float>(ws, p.off_grad2d));
-    return launch_status("zero_grad2d");
+    return launch_status("project_write");
 }
 
 int launch_project_bwd(const splat_plan &p, void *ws, const splat_gaussians &g, const double *w2c,

@@ -51,6 +51,7 @@ struct RenderArgs {
     float4 *chk;                // checkpoints: per-pixel (T, C) of the split lists
     int32_t *chklast;           // last blended instance of a chunk composited on its own
     uint8_t *bmask;             // per instance: sub-blocks it was blended into (forward writes)
+    float4 *g2z;                // the slots' gradient sums, cleared by the forward for the adjoint
     unsigned long long *stats;  // pair counters of the instrumented variant
     int n_items, T, tiles_x, W, H, persistent, roi_y0;
     uint32_t lc, chk_cap;       // split length, checkpoint slots
@@ -273,6 +274,15 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
     for (int iter = 0; MODE == 1 ? (item = (int)blockIdx.x + iter * (int)gridDim.x) < n_items
                                   : next_item(a, iter, n_items, item);
          ++iter) {
+        if (MODE != 1) {
+            // the adjoint adds into the slots' nine gradient sums: work item i clears its share of
+            // them (the kernel is bound by its instructions, the stores cost it little; the
+            // region is padded to 256 bytes, so the last float4 stays inside it)
+            const uint32_t n4 = (a.counts[CNT_SLOTS] * 9u + 3u) / 4u;
+            const uint32_t per = (n4 + (uint32_t)n_items - 1u) / (uint32_t)n_items;
+            const uint32_t q1 = min((uint32_t)item * per + per, n4);
+            for (uint32_t q = (uint32_t)item * per + lane; q < q1; q += 64u) a.g2z[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
         int tid;
         uint32_t lo, hi, lslot = 0;
         uint2 rg;
@@ -794,6 +804,7 @@ RenderArgs make_args(const splat_plan &p, void *ws, unsigned long long *stats) {
     a.chk = ws_at<float4>(ws, p.off_chk);
     a.chklast = ws_at<int32_t>(ws, p.off_chklast);
     a.bmask = ws_at<uint8_t>(ws, p.off_bmask);
+    a.g2z = ws_at<float4>(ws, p.off_grad2d);
     a.lc = (uint32_t)p.split_len;
     a.chk_cap = (uint32_t)p.chk_cap;
     a.stats = stats;
@@ -854,7 +865,7 @@ template <int TW, int TH, int NB>
 int bwd_impl(const splat_plan &p, void *ws, const float *dimg, const float *T, const int32_t *last,
              unsigned long long *stats, hipStream_t st) {
     RenderArgs a = make_args(p, ws, stats);
-    float *g2 = ws_at<float>(ws, p.off_grad2d);  // zeroed per slot by the projection
+    float *g2 = ws_at<float>(ws, p.off_grad2d);  // cleared by the forward
     int rc = 0;
     const int nT = a.n_items;
     if (nT == 0) return rc;
