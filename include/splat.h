@@ -284,6 +284,22 @@ SPLAT_API int splat_render_fwd(const splat_plan *plan, void *ws, float *img, flo
                      int32_t *last_pos, void *stream);
 
 /*
+ * splat_render_fwd and, in the same launch, splat_l1_loss_grad of the image it
+ * renders (paper Eq. 4, the L1 term; the rows [plan->s.roi_y0, H)): img,
+ * T_final and last_pos as splat_render_fwd writes them, dL_dimg = weight *
+ * sign(img - target)/N inside the region of interest (0 above it and where
+ * mask is set; N = V*3*(H - roi_y0)*W) and *loss += weight * sum |img -
+ * target|/N (float64, caller zeroes it; NULL to skip), exactly as
+ * splat_l1_loss_grad computes them (dL_dimg bit for bit; the loss summed in
+ * another order).  target and dL_dimg are [V][3][H][W] float32, mask (nullable)
+ * uint8 [V][H][W].  The forward is bound by its instructions, so the extra
+ * per-pixel reads and writes cost it little.
+ */
+SPLAT_API int splat_render_fwd_l1(const splat_plan *plan, void *ws, float *img, float *T_final, int32_t *last_pos,
+                                  const float *target, const uint8_t *mask, double weight, float *dL_dimg,
+                                  double *loss, void *stream);
+
+/*
  * Backward compositing: the adjoint of Phi (Eq. 5) that carries the loss
  * gradient back to the 2-D Gaussians (end of Sec. III-B).  Every pixel walks
  * its list in reverse from last_pos, recovering T by division and the suffix

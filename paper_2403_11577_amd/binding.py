@@ -97,6 +97,7 @@ def lib():
     L.splat_project_bwd.argtypes = [C.POINTER(splat_plan), P, C.POINTER(splat_gaussians), P, P,
                                     P, P, P, P, P, P, P]
     L.splat_render_fwd_stats.argtypes = [C.POINTER(splat_plan), P, P, P, P, P, P]
+    L.splat_render_fwd_l1.argtypes = [C.POINTER(splat_plan), P, P, P, P, P, P, C.c_double, P, P, P]
     L.splat_render_bwd_stats.argtypes = [C.POINTER(splat_plan), P, P, P, P, P, P]
     L.splat_l1_loss_grad.argtypes = [P, P, P, I32, I32, I32, I32, C.c_double, P, P, P]
     L.splat_dssim_workspace_size.argtypes = [I32, I32, I32, I32]
@@ -264,6 +265,17 @@ def _render_out(plan, img, T_final, last_pos, img_name="img"):
 def splat_render_fwd(plan, ws, img, T_final, last_pos, stream=None):
     _check(lib().splat_render_fwd(C.byref(plan), _ws(plan, ws), *_render_out(plan, img, T_final, last_pos),
                                   _stream(stream)), "splat_render_fwd")
+
+
+def splat_render_fwd_l1(plan, ws, img, T_final, last_pos, target, mask, dL_dimg, loss=None, weight=1.0,
+                        stream=None):
+    V, H, W = int(plan.n_views), int(plan.height), int(plan.width)
+    out = _render_out(plan, img, T_final, last_pos)
+    _check(lib().splat_render_fwd_l1(C.byref(plan), _ws(plan, ws), *out, _arg(target, "target", "f32", V * 3 * H * W),
+                                     _arg(mask, "mask", "u8", V * H * W, optional=True), float(weight),
+                                     _arg(dL_dimg, "dL_dimg", "f32", V * 3 * H * W),
+                                     _arg(loss, "loss", "f64", 1, at_least=True, optional=True), _stream(stream)),
+           "splat_render_fwd_l1")
 
 
 def splat_render_bwd(plan, ws, dL_dimg, T_final, last_pos, stream=None):

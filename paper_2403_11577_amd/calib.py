@@ -459,9 +459,8 @@ class Calibrator:
                         t.zero_()
             else:
                 pl.zero_grads(self.gr)
-            pl.forward(fr, w, self.xi_t, self.dl_t)
-            B.splat_l1_loss_grad(fr.img, self.tgt, None, self.dimg, self.loss, self.settings.roi_y0,
-                                 1.0 - cfg.lam_dssim)
+            # render and the L1 term (over the plan's region of interest) in one launch
+            pl.forward(fr, w, self.xi_t, self.dl_t, l1=(self.tgt, None, self.dimg, self.loss, 1.0 - cfg.lam_dssim))
             if cfg.lam_dssim > 0:
                 B.splat_dssim_loss_grad(fr.img, self.tgt, self.ssim_ws, self.dimg, self.loss, self.settings.roi_y0,
                                         cfg.lam_dssim)

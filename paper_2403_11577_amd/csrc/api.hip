@@ -349,6 +349,25 @@ int splat_render_fwd(const splat_plan *plan, void *ws, float *img, float *T_fina
     return launch_render_fwd(*plan, ws, img, T_final, last_pos, nullptr, (hipStream_t)stream);
 }
 
+int splat_render_fwd_l1(const splat_plan *plan, void *ws, float *img, float *T_final, int32_t *last_pos,
+                        const float *target, const uint8_t *mask, double weight, float *dL_dimg, double *loss,
+                        void *stream) {
+    g_err[0] = 0;
+    int rc = check_plan(plan, ws, "render_fwd_l1");
+    if (rc) return rc;
+    if (!img || !T_final || !last_pos || !target || !dL_dimg) {
+        set_error("render_fwd_l1: NULL argument"); return SPLAT_EINVAL;
+    }
+    if (plan->s.roi_y0 >= plan->height) {
+        set_error("render_fwd_l1: roi_y0 %d leaves no rows of %d", plan->s.roi_y0, plan->height); return SPLAT_EINVAL;
+    }
+    if (!std::isfinite(weight)) { set_error("render_fwd_l1: weight must be finite"); return SPLAT_EINVAL; }
+    const double inv_n = weight / (3.0 * (double)plan->n_views * (double)plan->width *
+                                   (double)(plan->height - plan->s.roi_y0));
+    const L1Fuse l1{target, mask, dL_dimg, loss, inv_n};
+    return launch_render_fwd(*plan, ws, img, T_final, last_pos, nullptr, (hipStream_t)stream, &l1);
+}
+
 int splat_render_fwd_stats(const splat_plan *plan, void *ws, float *img, float *T_final, int32_t *last_pos,
                            uint64_t *stats, void *stream) {
     g_err[0] = 0;

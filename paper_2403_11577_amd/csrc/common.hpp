@@ -76,8 +76,18 @@ int launch_project_bwd(const splat_plan &p, void *ws, const splat_gaussians &g, 
                        const double *intr, float *dquat, float *dscale, float *dopac,
                        float *dcolor, float *dmean, double *dw2c, hipStream_t st);
 int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st);
+// The L1 term fused into the forward's output stage (target null: not fused): per pixel of the
+// region of interest d = img - target (0 where mask is set), dimg = sign(d) inv_n, *loss +=
+// sum |d| inv_n, as launch_l1 computes them.
+struct L1Fuse {
+    const float *target;
+    const uint8_t *mask;
+    float *dimg;
+    double *loss;
+    double inv_n;
+};
 int launch_render_fwd(const splat_plan &p, void *ws, float *img, float *T, int32_t *last,
-                      uint64_t *stats, hipStream_t st);
+                      uint64_t *stats, hipStream_t st, const L1Fuse *l1 = nullptr);
 int launch_render_bwd(const splat_plan &p, void *ws, const float *dimg, const float *T,
                       const int32_t *last, uint64_t *stats, hipStream_t st);
 int launch_l1(const float *img, const float *target, const uint8_t *mask, int64_t n_views, int32_t width,

@@ -52,6 +52,7 @@ struct RenderArgs {
     int32_t *chklast;           // last blended instance of a chunk composited on its own
     uint8_t *bmask;             // per instance: sub-blocks it was blended into (forward writes)
     float4 *g2z;                // the slots' gradient sums, cleared by the forward for the adjoint
+    L1Fuse l1;                  // the L1 term at the forward's output stage (l1.target null: off)
     unsigned long long *stats;  // pair counters of the instrumented variant
     int n_items, T, tiles_x, W, H, persistent, roi_y0;
     uint32_t lc, chk_cap;       // split length, checkpoint slots
@@ -520,17 +521,38 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
             put_chk<NSB>(a, cslot, T, C0, C1, C2, lane);
         }
         size_t vo = (size_t)v * HW;
+        double l1acc = 0.0;
 #pragma unroll
         for (int k = 0; k < NSB; ++k) {
             int gx = x0 + 8 * (k % SBX) + lx, gy = y0 + 8 * (k / SBX) + ly;
             if (gx >= a.W || gy >= a.H) continue;
             size_t o = (size_t)gy * a.W + gx;
             float Tfin = T[k];
-            img[3 * vo + o] = __fmaf_rn(Tfin, a.bg0, C0[k]);
-            img[3 * vo + HW + o] = __fmaf_rn(Tfin, a.bg1, C1[k]);
-            img[3 * vo + 2 * HW + o] = __fmaf_rn(Tfin, a.bg2, C2[k]);
+            const float c[3] = {__fmaf_rn(Tfin, a.bg0, C0[k]), __fmaf_rn(Tfin, a.bg1, C1[k]),
+                                __fmaf_rn(Tfin, a.bg2, C2[k])};
+            img[3 * vo + o] = c[0];
+            img[3 * vo + HW + o] = c[1];
+            img[3 * vo + 2 * HW + o] = c[2];
             Tout[vo + o] = Tfin;
             lastout[vo + o] = last[k];
+            if (a.l1.target) {
+                // the L1 term of this pixel, as the loss kernel forms it from the stored image
+                const bool in = gy >= a.roi_y0 && !(a.l1.mask && a.l1.mask[vo + o]);
+                const float g = (float)a.l1.inv_n;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const size_t q = 3 * vo + (size_t)ch * HW + o;
+                    float d = c[ch] - a.l1.target[q];
+                    d = in ? d : 0.f;
+                    a.l1.dimg[q] = d > 0.f ? g : (d < 0.f ? -g : 0.f);
+                    l1acc += (double)fabsf(d);
+                }
+            }
+        }
+        if (a.l1.target && a.l1.loss) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) l1acc += __shfl_xor(l1acc, off, kWave);
+            if (lane == 0 && l1acc != 0.0) atomicAdd(a.l1.loss, l1acc * a.l1.inv_n);
         }
     }
     if (STATS) {
@@ -805,6 +827,7 @@ RenderArgs make_args(const splat_plan &p, void *ws, unsigned long long *stats) {
     a.chklast = ws_at<int32_t>(ws, p.off_chklast);
     a.bmask = ws_at<uint8_t>(ws, p.off_bmask);
     a.g2z = ws_at<float4>(ws, p.off_grad2d);
+    a.l1 = L1Fuse{nullptr, nullptr, nullptr, nullptr, 0.0};
     a.lc = (uint32_t)p.split_len;
     a.chk_cap = (uint32_t)p.chk_cap;
     a.stats = stats;
@@ -835,8 +858,9 @@ int persistent_grid(int n_items, int wg_per_cu) {
 
 template <int TW, int TH, int NB>
 int fwd_impl(const splat_plan &p, void *ws, float *img, float *T, int32_t *last, unsigned long long *stats,
-             hipStream_t st) {
+             hipStream_t st, const L1Fuse *l1) {
     RenderArgs a = make_args(p, ws, stats);
+    if (l1) a.l1 = *l1;
     if (a.n_items == 0) return 0;
     int rc = 0;
     const bool joined = p.s.split_fwd && !stats;  // the instrumented variant walks every list in order
@@ -889,12 +913,12 @@ int batch_of(const splat_plan &p) { return p.s.batch < p.split_len ? p.s.batch :
 
 template <int TW, int TH>
 int fwd_tile(const splat_plan &p, void *ws, float *img, float *T, int32_t *last, unsigned long long *s,
-             hipStream_t st) {
+             hipStream_t st, const L1Fuse *l1) {
     switch (batch_of(p)) {
-        case 32: return fwd_impl<TW, TH, 32>(p, ws, img, T, last, s, st);
-        case 64: return fwd_impl<TW, TH, 64>(p, ws, img, T, last, s, st);
-        case 128: return fwd_impl<TW, TH, 128>(p, ws, img, T, last, s, st);
-        case 256: return fwd_impl<TW, TH, 256>(p, ws, img, T, last, s, st);
+        case 32: return fwd_impl<TW, TH, 32>(p, ws, img, T, last, s, st, l1);
+        case 64: return fwd_impl<TW, TH, 64>(p, ws, img, T, last, s, st, l1);
+        case 128: return fwd_impl<TW, TH, 128>(p, ws, img, T, last, s, st, l1);
+        case 256: return fwd_impl<TW, TH, 256>(p, ws, img, T, last, s, st, l1);
     }
     set_error("render_fwd: unsupported batch %d", p.s.batch);
     return SPLAT_EUNSUPPORTED;
@@ -916,13 +940,13 @@ int bwd_tile(const splat_plan &p, void *ws, const float *dimg, const float *T, c
 }  // namespace
 
 int launch_render_fwd(const splat_plan &p, void *ws, float *img, float *T, int32_t *last, uint64_t *stats,
-                      hipStream_t st) {
+                      hipStream_t st, const L1Fuse *l1) {
     int tw = p.s.tile_w, th = p.s.tile_h;
     auto *s = reinterpret_cast<unsigned long long *>(stats);
-    if (tw == 16 && th == 16) return fwd_tile<16, 16>(p, ws, img, T, last, s, st);
-    if (tw == 8 && th == 8) return fwd_tile<8, 8>(p, ws, img, T, last, s, st);
-    if (tw == 16 && th == 32) return fwd_tile<16, 32>(p, ws, img, T, last, s, st);
-    if (tw == 32 && th == 16) return fwd_tile<32, 16>(p, ws, img, T, last, s, st);
+    if (tw == 16 && th == 16) return fwd_tile<16, 16>(p, ws, img, T, last, s, st, l1);
+    if (tw == 8 && th == 8) return fwd_tile<8, 8>(p, ws, img, T, last, s, st, l1);
+    if (tw == 16 && th == 32) return fwd_tile<16, 32>(p, ws, img, T, last, s, st, l1);
+    if (tw == 32 && th == 16) return fwd_tile<32, 16>(p, ws, img, T, last, s, st, l1);
     set_error("render_fwd: unsupported tile %dx%d", tw, th);
     return SPLAT_EUNSUPPORTED;
 }

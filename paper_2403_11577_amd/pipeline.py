@@ -177,8 +177,10 @@ def pose_fwd(fr: Frame, ds: DeviceScene, xi: torch.Tensor, delta: torch.Tensor):
     return fr.w2c
 
 
-def forward(fr: Frame, ds: DeviceScene, xi: torch.Tensor, delta: torch.Tensor, gauss=None, w2c=None):
-    """pose -> project -> bin/sort -> render; returns (img, T_final, last_pos)."""
+def forward(fr: Frame, ds: DeviceScene, xi: torch.Tensor, delta: torch.Tensor, gauss=None, w2c=None, l1=None):
+    """pose -> project -> bin/sort -> render; returns (img, T_final, last_pos).  With l1 = (target,
+    mask, dimg, loss, weight) the render also forms the L1 term over the plan's region of
+    interest in the same launch (splat_render_fwd_l1)."""
     if w2c is None:
         w2c = pose_fwd(fr, ds, xi, delta)
     else:
@@ -187,7 +189,11 @@ def forward(fr: Frame, ds: DeviceScene, xi: torch.Tensor, delta: torch.Tensor, g
     fr.generation += 1
     B.splat_project(fr.plan, fr.ws, g, fr.w2c, ds.intr)
     B.splat_bin_sort(fr.plan, fr.ws)
-    B.splat_render_fwd(fr.plan, fr.ws, fr.img, fr.T, fr.last)
+    if l1 is None:
+        B.splat_render_fwd(fr.plan, fr.ws, fr.img, fr.T, fr.last)
+    else:
+        target, mask, dimg, loss, weight = l1
+        B.splat_render_fwd_l1(fr.plan, fr.ws, fr.img, fr.T, fr.last, target, mask, dimg, loss, weight)
     return fr.img, fr.T, fr.last
 
 
@@ -276,7 +282,7 @@ def l1_loss_grad(img: torch.Tensor, target: torch.Tensor, mask=None, dimg=None, 
 
 class BatchedStep:
     """One calibration step over all views, batched: pose -> project -> bin/sort ->
-    render -> L1 -> render_bwd -> project_bwd -> pose_bwd, every stage one set of
+    render + L1 -> render_bwd -> project_bwd -> pose_bwd, every stage one set of
     launches for all views (persistent render over the cost-ordered queue).  The
     step can be captured once in a HIP graph and replayed."""
 
@@ -301,9 +307,9 @@ class BatchedStep:
         B.splat_bin_sort(fr.plan, fr.ws)
         ev = self.events
         if ev: ev["fwd"][0].record()
-        B.splat_render_fwd(fr.plan, fr.ws, fr.img, fr.T, fr.last)
+        # the forward and the L1 term in one launch (the loss kernel's outputs, bit for bit)
+        B.splat_render_fwd_l1(fr.plan, fr.ws, fr.img, fr.T, fr.last, self.targets, self.mask, self.dimg, self.loss)
         if ev: ev["fwd"][1].record()
-        B.splat_l1_loss_grad(fr.img, self.targets, self.mask, self.dimg, self.loss, fr.settings.roi_y0)
         if ev: ev["bwd"][0].record()
         B.splat_render_bwd(fr.plan, fr.ws, self.dimg, fr.T, fr.last)
         if ev: ev["bwd"][1].record()

@@ -127,6 +127,24 @@ def test_entry_points_reject_an_edited_split_length():
     assert L.splat_bin_sort(C.byref(p), C.c_void_p(16), None) == -1
 
 
+def test_render_fwd_l1_rejects_bad_arguments_before_launching():
+    L = B.lib()
+    s = B.default_settings()
+    p = B.splat_plan_make(s, 1, 10, 64, 37, 10, 100)
+    buf = C.c_void_p(16)
+    # a NULL target or gradient is refused
+    assert L.splat_render_fwd_l1(C.byref(p), buf, buf, buf, buf, None, None, 1.0, buf, None, None) == -1
+    assert b"NULL argument" in L.splat_last_error()
+    # the region of interest must leave rows (N > 0; splat_plan_make already refuses such a plan,
+    # an edited one is refused here), and the weight must be finite
+    q = B.splat_plan_make(s, 1, 10, 64, 37, 10, 100)
+    q.s.roi_y0 = 37
+    assert L.splat_render_fwd_l1(C.byref(q), buf, buf, buf, buf, buf, None, 1.0, buf, None, None) == -1
+    assert b"leaves no rows" in L.splat_last_error()
+    assert L.splat_render_fwd_l1(C.byref(p), buf, buf, buf, buf, buf, None, float("inf"), buf, None, None) == -1
+    assert b"finite" in L.splat_last_error()
+
+
 def test_too_many_work_items_is_unsupported():
     # 1023 views of 2048 x 2048 8x8 tiles exceed the 2^31 (view, tile) items the key and queue allow
     s = B.default_settings()

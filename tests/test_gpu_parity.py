@@ -540,6 +540,40 @@ def test_l1_kernel_vs_numpy():
     np.testing.assert_array_equal(dimg.cpu().numpy(), ref_d.astype(np.float32))
 
 
+@pytest.mark.parametrize("tile, roi, masked", [((16, 16), 0, False), ((8, 8), 9, True), ((32, 16), 17, False),
+                                                ((16, 32), 0, True)])
+def test_render_fwd_l1_matches_the_separate_calls(tile, roi, masked):
+    """The forward with the L1 term in the same launch writes the forward's outputs and the loss
+    kernel's gradient bit for bit, and the loss up to the order of its float64 sum (Eq. 4's L1 term
+    over the region of interest, with and without a mask)."""
+    say(f"case: render_fwd_l1 tile={tile} roi={roi} masked={masked}")
+    scene = synth.small_drive(4, n_frames=2)
+    ds = pl.DeviceScene.from_scene(scene)
+    xi, dl = _dev(scene.xi), _dev(scene.delta)
+    st = pl.make_settings(tile=tile, roi_y0=roi)
+    fr = pl.fit_frame(ds, xi, dl, st)
+    V, H, W = fr.V, fr.H, fr.W
+    rng = np.random.default_rng(roi)
+    tgt = torch.as_tensor(rng.uniform(size=(V, 3, H, W)).astype(np.float32), device="cuda")
+    mask = None
+    if masked:
+        m = np.zeros((V, H, W), np.uint8)
+        m[:, H // 3:H // 2, W // 4:W // 2] = 1
+        mask = torch.as_tensor(m, device="cuda")
+    img, T, last = (t.clone() for t in pl.forward(fr, ds, xi, dl))
+    ref_loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ref_d = torch.empty_like(img)
+    B.splat_l1_loss_grad(img, tgt, mask, ref_d, ref_loss, roi, 0.8)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    d = torch.full_like(img, float("nan"))
+    img2, T2, last2 = pl.forward(fr, ds, xi, dl, l1=(tgt, mask, d, loss, 0.8))
+    torch.cuda.synchronize()
+    assert torch.equal(img2, img) and torch.equal(T2, T) and torch.equal(last2, last)
+    assert torch.equal(d, ref_d)
+    say(f"  loss {loss.item():.12f} vs {ref_loss.item():.12f}")
+    assert float(loss.item()) == pytest.approx(float(ref_loss.item()), rel=1e-12)
+
+
 def _step_for(scene, tile=(16, 16)):
     ds = pl.DeviceScene.from_scene(scene)
     xi, dl = _dev(scene.xi), _dev(scene.delta)
