@@ -32,11 +32,14 @@ sys.path.insert(0, ROOT)
 # plus one exp; backward 45 plus one exp and one reciprocal.  Bytes that must cross HBM:
 # per instance (Gaussian, tile) its 4-byte slot id and 36-byte record; per pixel 20 bytes
 # (forward: colour, T, last; backward: dL/dC, T, last); per backward atomic group (one
-# (tile, Gaussian) with a contributor) its nine 4-byte gradient sums.  The attainable rate
+# (tile, Gaussian) with a contributor) its nine 4-byte gradient sums.  The timed forward is
+# the joined launch that also forms the L1 term (target read, dL/dC written: 24 bytes per
+# pixel) and clears the slots' nine gradient sums (36 bytes per slot).  The attainable rate
 # is min(HBM peak x ops/byte, FP32 vector peak); evaluated pairs that contribute nothing
 # are overhead and only reported.
 FWD_OPS_PER_PAIR, BWD_OPS_PER_PAIR = 16, 47
 BYTES_PER_INSTANCE, BYTES_PER_PIXEL, BYTES_PER_ATOMIC_GROUP = 40, 20, 36
+BYTES_PER_PIXEL_L1, BYTES_PER_SLOT_CLEAR = 24, 36
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 157.3          # published FP32 vector peak
 ISSUE_PEAK_TOPS = 256 * 64 * 2 * 2.4e9 / 1e12   # one wave64 FMA per CU per cycle (no dual issue): 78.6
@@ -371,7 +374,8 @@ def main():
                 "alu_frac_issue": round(tops / ISSUE_PEAK_TOPS, 4)}
 
     fwd_rl = kernel_roofline("render_fwd", fwd_ms, FWD_OPS_PER_PAIR * stt["fwd_blend"],
-                             BYTES_PER_INSTANCE * stt["instances"] + BYTES_PER_PIXEL * npx)
+                             BYTES_PER_INSTANCE * stt["instances"] + (BYTES_PER_PIXEL + BYTES_PER_PIXEL_L1) * npx
+                             + BYTES_PER_SLOT_CLEAR * stt["slots"])
     bwd_rl = kernel_roofline("render_bwd", bwd_ms, BWD_OPS_PER_PAIR * stt["bwd_contrib"],
                              BYTES_PER_INSTANCE * stt["instances"] + BYTES_PER_PIXEL * npx
                              + BYTES_PER_ATOMIC_GROUP * stt["bwd_atomic_groups"])
