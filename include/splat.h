@@ -166,6 +166,9 @@ typedef struct splat_plan {
     size_t off_skeys;       /* u32[slot_cap]: the slot sort's second key buffer (slot_sort)          */
     size_t off_soff;        /* u32[slot_cap+1]: tiles per slot in depth order, scanned to instance
                                offsets (slot_sort)                                                   */
+    size_t off_l1part;      /* f64[V*T + ceil(V*T / 4096)]: splat_render_fwd_l1's partial sums of
+                               |C - target|, one per (view, tile) work item, then one per group of
+                               4096 items; summed in this fixed order                              */
 } splat_plan;
 
 /* Fill `s` with the default settings listed above (16x16 tiles, batch 64,

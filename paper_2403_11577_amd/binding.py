@@ -52,7 +52,7 @@ class splat_plan(C.Structure):
                 [(n, C.c_size_t) for n in ("off_bqueue", "off_bqoff", "off_chk", "off_chklast", "off_bmask",
                                                       "off_dkey")] +
                 [("slot_sort", C.c_int32), ("pack_bits", C.c_int32 * 3)] +
-                [(n, C.c_size_t) for n in ("off_spay", "off_skeys", "off_soff")])
+                [(n, C.c_size_t) for n in ("off_spay", "off_skeys", "off_soff", "off_l1part")])
 
 
 ADAM_MAX_GROUPS = 8

@@ -53,6 +53,7 @@ struct RenderArgs {
     uint8_t *bmask;             // per instance: sub-blocks it was blended into (forward writes)
     float4 *g2z;                // the slots' gradient sums, cleared by the forward for the adjoint
     L1Fuse l1;                  // the L1 term at the forward's output stage (l1.target null: off)
+    double *l1part;             // its sum of |C - target| per work item
     unsigned long long *stats;  // pair counters of the instrumented variant
     int n_items, T, tiles_x, W, H, persistent, roi_y0;
     uint32_t lc, chk_cap;       // split length, checkpoint slots
@@ -550,9 +551,11 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
             }
         }
         if (a.l1.target && a.l1.loss) {
+            // one partial per work item, summed in item order after the launch (a device-wide
+            // atomic per item on one address serialises at the memory side)
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) l1acc += __shfl_xor(l1acc, off, kWave);
-            if (lane == 0 && l1acc != 0.0) atomicAdd(a.l1.loss, l1acc * a.l1.inv_n);
+            if (lane == 0) a.l1part[item] = l1acc;
         }
     }
     if (STATS) {
@@ -813,6 +816,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void re
 
 __global__ void reset_work_kernel(uint32_t *w) { *w = 0u; }
 
+// Fixed-order sum of the forward's L1 partials: workgroup g adds items [g kL1Span, (g+1) kL1Span)
+// (thread t the items t mod 256, then a tree over the threads) into out[g]; with scale != 0 a
+// single workgroup adds scale times the sum of all n into *loss instead.
+__global__ __launch_bounds__(256) void l1_sum_kernel(const double *in, int n, double *out, double scale,
+                                                     double *loss) {
+    __shared__ double s[256];
+    const int t = threadIdx.x;
+    const int b = loss ? 0 : (int)blockIdx.x * kL1Span;
+    const int e = loss ? n : min(n, b + kL1Span);
+    double acc = 0.0;
+    for (int i = b + t; i < e; i += 256) acc += in[i];
+    s[t] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) s[t] += s[t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (loss)
+            atomicAdd(loss, s[0] * scale);
+        else
+            out[blockIdx.x] = s[0];
+    }
+}
+
 RenderArgs make_args(const splat_plan &p, void *ws, unsigned long long *stats) {
     RenderArgs a;
     a.rec = ws_at<float4>(ws, p.off_rec);
@@ -828,6 +856,7 @@ RenderArgs make_args(const splat_plan &p, void *ws, unsigned long long *stats) {
     a.bmask = ws_at<uint8_t>(ws, p.off_bmask);
     a.g2z = ws_at<float4>(ws, p.off_grad2d);
     a.l1 = L1Fuse{nullptr, nullptr, nullptr, nullptr, 0.0};
+    a.l1part = ws_at<double>(ws, p.off_l1part);
     a.lc = (uint32_t)p.split_len;
     a.chk_cap = (uint32_t)p.chk_cap;
     a.stats = stats;
@@ -882,7 +911,16 @@ int fwd_impl(const splat_plan &p, void *ws, float *img, float *T, int32_t *last,
         hipLaunchKernelGGL((render_fwd_kernel<TW, TH, false, 2, NB>), dim3(grid), dim3(64), 0, st, a, img, T, last);
     else
         hipLaunchKernelGGL((render_fwd_kernel<TW, TH, false, 0, NB>), dim3(grid), dim3(64), 0, st, a, img, T, last);
-    return launch_status("render_fwd");
+    if ((rc = launch_status("render_fwd"))) return rc;
+    if (a.l1.target && a.l1.loss) {
+        const int ng = (a.n_items + kL1Span - 1) / kL1Span;
+        double *gsum = a.l1part + a.n_items;
+        hipLaunchKernelGGL(l1_sum_kernel, dim3(ng), dim3(256), 0, st, a.l1part, a.n_items, gsum, 0.0, nullptr);
+        if ((rc = launch_status("render_fwd_l1_groups"))) return rc;
+        hipLaunchKernelGGL(l1_sum_kernel, dim3(1), dim3(256), 0, st, gsum, ng, nullptr, a.l1.inv_n, a.l1.loss);
+        rc = launch_status("render_fwd_l1_total");
+    }
+    return rc;
 }
 
 template <int TW, int TH, int NB>

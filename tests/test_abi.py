@@ -43,7 +43,8 @@ def test_plan_layout_is_aligned_and_disjoint():
     s = B.default_settings()
     p = B.splat_plan_make(s, 3, 1000, 100, 37, 2000, 9000)
     names = [n for n in B._PLAN_OFFS if n != "ws_bytes"] + ["off_bqueue", "off_bqoff", "off_chk", "off_chklast",
-                                                           "off_bmask", "off_dkey", "off_spay", "off_skeys", "off_soff"]
+                                                           "off_bmask", "off_dkey", "off_spay", "off_skeys", "off_soff",
+                                                           "off_l1part"]
     offs = sorted((getattr(p, n), n) for n in names)
     assert all(o % 256 == 0 for o, _ in offs)
     assert len({o for o, _ in offs}) == len(offs)
@@ -56,7 +57,8 @@ def test_plan_layout_is_aligned_and_disjoint():
     assert p.off_bmask - p.off_chklast >= p.chk_cap * 16 * 16 * 4
     assert p.off_dkey - p.off_bmask >= 9000 and p.off_spay - p.off_dkey >= 2000 * 4
     assert p.off_skeys - p.off_spay >= 2000 * 16 and p.off_soff - p.off_skeys >= 2000 * 4
-    assert p.ws_bytes - p.off_soff >= 2001 * 4
+    assert p.off_l1part - p.off_soff >= 2001 * 4
+    assert p.ws_bytes - p.off_l1part >= (63 + 1) * 8   # 63 work-item partials, one group sum
     assert p.tiles_x == 7 and p.tiles_y == 3 and p.tiles_per_view == 21
     # key = (view*T + tile) << depth_bits | depth: 63 items need 6 bits, the 0.2..256 m window 27
     assert p.tile_bits == 6 and p.depth_bits == 27

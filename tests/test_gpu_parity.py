@@ -574,6 +574,37 @@ def test_render_fwd_l1_matches_the_separate_calls(tile, roi, masked):
     assert float(loss.item()) == pytest.approx(float(ref_loss.item()), rel=1e-12)
 
 
+def test_render_fwd_l1_sum_over_many_work_items_is_reproducible():
+    """16,544 work items (8x8 tiles of four 704x376 views): the forward's per-item partial sums of
+    |C - target| are added in a fixed order over five groups, so the loss equals the loss kernel's
+    up to the order of the float64 sum, a second call adds bit for bit the same value, and the
+    loss accumulates into what the caller passed (Eq. 4's L1 term)."""
+    say("case: render_fwd_l1 704x376 8x8, 4 views")
+    scene = synth.small_drive(5, n_points=20000, W=704, H=376, f=276.0, n_frames=2)
+    ds = pl.DeviceScene.from_scene(scene)
+    xi, dl = _dev(scene.xi), _dev(scene.delta)
+    fr = pl.fit_frame(ds, xi, dl, pl.make_settings(tile=(8, 8)))
+    assert fr.V * fr.plan.tiles_per_view > 4 * 4096
+    rng = np.random.default_rng(5)
+    tgt = torch.as_tensor(rng.uniform(size=(fr.V, 3, fr.H, fr.W)).astype(np.float32), device="cuda")
+    img = pl.forward(fr, ds, xi, dl)[0].clone()
+    ref_loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ref_d = torch.empty_like(img)
+    B.splat_l1_loss_grad(img, tgt, None, ref_d, ref_loss, 0, 1.0)
+    losses = []
+    for start in (0.0, 0.0, 2.5):
+        loss = torch.full((1,), start, dtype=torch.float64, device="cuda")
+        d = torch.full_like(img, float("nan"))
+        pl.forward(fr, ds, xi, dl, l1=(tgt, None, d, loss, 1.0))
+        torch.cuda.synchronize()
+        assert torch.equal(d, ref_d)
+        losses.append(float(loss.item()) - start)
+    say(f"  loss {losses} vs {ref_loss.item():.12f}")
+    assert losses[0] == pytest.approx(float(ref_loss.item()), rel=1e-12)
+    assert losses[0] == losses[1]
+    assert losses[2] == pytest.approx(losses[0], rel=1e-14)
+
+
 def _step_for(scene, tile=(16, 16)):
     ds = pl.DeviceScene.from_scene(scene)
     xi, dl = _dev(scene.xi), _dev(scene.delta)
