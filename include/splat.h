@@ -28,7 +28,10 @@
  *   SPLAT_ST_DEGENERATE a Gaussian with |q| < 1e-12 (culled),
  *   SPLAT_ST_EXTRAPOLATED a camera time outside the trajectory (informational),
  *   SPLAT_ST_RANGE     a point outside the voxel grid (voxel downsampling; the
- *                      point was clamped into the grid).
+ *                      point was clamped into the grid),
+ *   SPLAT_ST_SEQUENCE  splat_bin_sort on a projection made for the other bin
+ *                      sort (plan->slot_sort changed in between): nothing was
+ *                      binned, every tile list is empty; project again.
  * The library never clears the status word; the caller zeroes it when it wants.
  *
  * Threading.  Re-entrant; no global mutable state except the thread-local
@@ -60,6 +63,7 @@ extern "C" {
 #define SPLAT_ST_DEGENERATE 4u
 #define SPLAT_ST_EXTRAPOLATED 8u
 #define SPLAT_ST_RANGE 16u
+#define SPLAT_ST_SEQUENCE 32u
 
 /*
  * Renderer constants.  The paper fixes none of them (it defers the splatting
@@ -116,13 +120,14 @@ typedef struct splat_plan {
     size_t ws_bytes;
     size_t off_status;      /* u32                                                      */
     size_t off_counts;      /* u32[8]: 0 slots, 1 instances, 2 work counter, 3 split lists, 4 chunks
-                               of the split lists, 5 render-adjoint items, 6..7 spare        */
+                               of the split lists, 5 render-adjoint items, 6 the bin sort the
+                               last projection prepared for, 7 spare                         */
     size_t off_view_off;    /* u32[V+1] first slot of every view                          */
     size_t off_blockcnt;    /* u32[V*n_blocks_proj*4+1] visible count per (view, wave), scanned in place to slot offsets */
     size_t off_rec;         /* float4[3][slot_cap]: (mx,my,lx,ly) (a,b,c,o) (r,g,b,depth) */
     size_t off_meta;        /* int2[slot_cap]: (Gaussian id, view)                       */
-    size_t off_rect;        /* u16x4[slot_cap]: tile rect (x0,x1,y0,y1) inclusive         */
-    size_t off_ntiles;      /* u32[slot_cap+1]: tiles per slot, scanned to offsets       */
+    size_t off_rect;        /* u16x4[slot_cap]: tile rect (x0,x1,y0,y1) inclusive (slot_sort 0) */
+    size_t off_ntiles;      /* u32[slot_cap+1]: tiles per slot, scanned to offsets (slot_sort 0) */
     size_t off_keys;        /* u64[2][inst_cap] (the sort's last passes keep u32 keys, see key_shift) */
     size_t off_vals;        /* u32[2][inst_cap]                                          */
     size_t off_ranges;      /* u32x2[V*T]: [start,end) of every (view, tile) list         */
@@ -237,8 +242,9 @@ SPLAT_API int splat_pose_interp_bwd(int32_t K, const double *knot_t, const doubl
  * compacted per view in Gaussian order into slots.
  *   g: Gaussians (device planes); w2c[V][12] float64 (device);
  *   intr[V][4] float64 (fx, fy, cx, cy) per view (device).
- * Writes counts, view_off, rec, meta, rect, ntiles (and, with plan->slot_sort,
- * the slot payloads) in the workspace.
+ * Writes counts, view_off, rec, meta, the depth fields and, for the bin sort
+ * the plan selects, the slot payloads (plan->slot_sort = 1) or the tile rects
+ * and counts (0) in the workspace.
  */
 SPLAT_API int splat_project(const splat_plan *plan, void *ws, const splat_gaussians *g, const double *w2c,
                   const double *intr, void *stream);

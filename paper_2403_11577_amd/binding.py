@@ -14,7 +14,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsplat.so")
 
-ST_CAPACITY, ST_NONFINITE, ST_DEGENERATE, ST_EXTRAPOLATED, ST_RANGE = 1, 2, 4, 8, 16
+ST_CAPACITY, ST_NONFINITE, ST_DEGENERATE, ST_EXTRAPOLATED, ST_RANGE, ST_SEQUENCE = 1, 2, 4, 8, 16, 32
 
 
 class SplatError(RuntimeError):

@@ -720,6 +720,15 @@ int launch_radix_sort_u64(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1
                                   nullptr);
 }
 
+// A projection writes the per-slot inputs of one bin sort only: binning for the other one finds
+// no slots (and flags the status word) instead of reading buffers that projection left stale.
+__global__ void prep_check_kernel(uint32_t *counts, uint32_t want, uint32_t *status) {
+    if (counts[CNT_PREP] != want) {
+        counts[CNT_SLOTS] = 0u;
+        atomicOr(status, SPLAT_ST_SEQUENCE);
+    }
+}
+
 int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
     uint32_t *status = ws_at<uint32_t>(ws, p.off_status);
     uint32_t *counts = ws_at<uint32_t>(ws, p.off_counts);
@@ -738,6 +747,9 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
     int eb = (int)((p.slot_cap + 255) / 256);  // about one slot per thread
     if (eb > 65536) eb = 65536;
     int rc = 0, in1 = 0, kshift = -1;
+    hipLaunchKernelGGL(prep_check_kernel, dim3(1), dim3(1), 0, st, counts, p.slot_sort ? kPrepSlotSort : kPrepInstSort,
+                       status);
+    if ((rc = launch_status("prep_check"))) return rc;
     if (p.slot_sort) {
         // slots by depth (the payload travels along), then the instances, emitted in that order,
         // by tile: stable sorts, so a tile's list is in (depth, slot) order as with the 64-bit keys

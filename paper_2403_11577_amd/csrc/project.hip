@@ -313,9 +313,10 @@ __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, sp
         Rect16 rc;
         rc.x0 = (uint16_t)(P.px0 / tw); rc.x1 = (uint16_t)(P.px1 / tw);
         rc.y0 = (uint16_t)(P.py0 / th); rc.y1 = (uint16_t)(P.py1 / th);
-        rect[slot] = rc;
-        ntiles[slot] = (uint32_t)(rc.x1 - rc.x0 + 1) * (uint32_t)(rc.y1 - rc.y0 + 1);
-        if (sp.spay) {
+        if (!sp.spay) {  // the 64-bit instance sort reads the rect and tile count of every slot
+            rect[slot] = rc;
+            ntiles[slot] = (uint32_t)(rc.x1 - rc.x0 + 1) * (uint32_t)(rc.y1 - rc.y0 + 1);
+        } else {
             const uint64_t first = (uint64_t)v * (uint64_t)sp.T + (uint64_t)rc.y0 * (uint64_t)sp.tiles_x + rc.x0;
             // a field of width 0 holds 0 and may sit at bit 64: no shift by 64
             const int s1 = sp.b0 + sp.tb, s2 = s1 + sp.b1;
@@ -328,7 +329,7 @@ __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, sp
 
 // totals after the (view, wave) count scan: slot count (clamped), view offsets, capacity flag
 __global__ void project_finish_kernel(const uint32_t *waveoff, int V, int nw, int64_t slot_cap, uint32_t *counts,
-                                      uint32_t *view_off, uint32_t *status) {
+                                      uint32_t *view_off, uint32_t *status, uint32_t prep) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t total = waveoff[(size_t)V * nw];
     uint32_t cap = (uint32_t)slot_cap;
@@ -338,6 +339,7 @@ __global__ void project_finish_kernel(const uint32_t *waveoff, int V, int nw, in
     }
     if (v == 0) {
         counts[CNT_SLOTS] = total < cap ? total : cap;
+        counts[CNT_PREP] = prep;
         if (total > cap) atomicOr(status, SPLAT_ST_CAPACITY);
     }
 }
@@ -604,7 +606,8 @@ int launch_project(const splat_plan &p, void *ws, const splat_gaussians &g, cons
         if (rc) return rc;
     }
     hipLaunchKernelGGL(project_finish_kernel, dim3((V + 1 + 255) / 256), dim3(256), 0, st, wavecnt, V, nw,
-                       p.slot_cap, counts, ws_at<uint32_t>(ws, p.off_view_off), status);
+                       p.slot_cap, counts, ws_at<uint32_t>(ws, p.off_view_off), status,
+                       p.slot_sort ? kPrepSlotSort : kPrepInstSort);
     rc = launch_status("project_finish");
     if (rc || g.n == 0) return rc;
     hipLaunchKernelGGL(project_write_kernel, dim3(nb), dim3(256), 0, st, p.s, g, w2c, cam, p.width, p.height, V, nb,

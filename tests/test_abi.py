@@ -349,3 +349,12 @@ def test_noalloc_dssim_rejects_oversized_inputs_on_the_host():
                                            None, None) == -1
     assert b"exceed the maximum" in L.splat_last_error()
     assert L.splat_dssim_loss_grad_noalloc(None, None, 1, 8, 8, 0, 0.2, None, None, None) == -1
+
+
+def test_status_bits_and_return_codes_match_the_header():
+    """The binding's copies of the status bits and return codes are the header's values."""
+    text = open(os.path.join(ROOT, "include", "splat.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define SPLAT_(\w+) \(?(-?\d+)u?\)?", text)}
+    for name in ("CAPACITY", "NONFINITE", "DEGENERATE", "EXTRAPOLATED", "RANGE", "SEQUENCE"):
+        assert getattr(B, "ST_" + name) == defs["ST_" + name], name
+    assert len({defs[k] for k in defs if k.startswith("ST_")}) == sum(k.startswith("ST_") for k in defs)

@@ -194,8 +194,15 @@ def test_bin_sort_vs_oracle(tile, path):
     assert nz[0, 0] == 0 and nz[-1, 1] == ni and np.all(nz[1:, 0] == nz[:-1, 1])
     if path == "instance_keys":  # the per-slot tile counts were scanned in place to instance offsets
         per_slot = np.diff(fr.buf("ntiles", torch.int32, ns + 1).cpu().numpy().astype(np.int64))
-    else:
-        per_slot = fr.buf("ntiles", torch.int32, ns).cpu().numpy().astype(np.int64)
+    else:  # every slot payload (slot | first tile | w - 1 | h - 1), in the order a sort pass left
+        pay = fr.buf("spay", torch.int64, ns).cpu().numpy().view(np.uint64)
+        b0, b1, b2 = (int(x) for x in fr.plan.pack_bits)
+        s1 = b0 + int(fr.plan.tile_bits)
+        field = lambda sh, b: (pay >> np.uint64(sh)) & np.uint64((1 << b) - 1) if sh < 64 else np.zeros_like(pay)
+        slot_of = field(0, b0).astype(np.int64)
+        assert np.array_equal(np.sort(slot_of), np.arange(ns))
+        per_slot = np.zeros(ns, np.int64)
+        per_slot[slot_of] = ((field(s1, b1) + np.uint64(1)) * (field(s1 + b1, b2) + np.uint64(1))).astype(np.int64)
     assert per_slot.sum() == ni and np.array_equal(np.bincount(vals, minlength=ns), per_slot)
     # the sorted keys are the (view, tile) of every instance
     keys = fr.sorted_keys(ni).cpu().numpy().astype(np.int64)
@@ -572,6 +579,39 @@ def test_render_fwd_l1_matches_the_separate_calls(tile, roi, masked):
     assert torch.equal(d, ref_d)
     say(f"  loss {loss.item():.12f} vs {ref_loss.item():.12f}")
     assert float(loss.item()) == pytest.approx(float(ref_loss.item()), rel=1e-12)
+
+
+def test_bin_sort_after_a_projection_for_the_other_sort_bins_nothing():
+    """A projection writes the per-slot inputs of the plan's bin sort only; binning with the other
+    sort before projecting again flags SPLAT_ST_SEQUENCE and leaves every tile list empty (the
+    image is the background), and a new projection makes it whole again."""
+    say("case: bin_sort after a projection for the other sort")
+    scene = synth.small_drive(3, n_frames=2)
+    ds = pl.DeviceScene.from_scene(scene)
+    xi, dl = _dev(scene.xi), _dev(scene.delta)
+    fr = pl.fit_frame(ds, xi, dl, pl.make_settings())
+    slot_fields = (int(fr.plan.slot_sort), int(fr.plan.sorted_buf), int(fr.plan.key_shift))
+    assert slot_fields[0] == 1
+    ref = [t.clone() for t in pl.forward(fr, ds, xi, dl)]
+    torch.cuda.synchronize()
+    assert fr.status() == 0 and fr.counts()[1] > 0
+    for switch in ("to_instance_keys", "to_slot_first"):
+        if switch == "to_instance_keys":
+            use_instance_sort(fr)
+        else:
+            pl.forward(fr, ds, xi, dl)   # projected for the instance keys
+            fr.plan.slot_sort, fr.plan.sorted_buf, fr.plan.key_shift = slot_fields
+        fr.clear_status()
+        B.splat_bin_sort(fr.plan, fr.ws)
+        torch.cuda.synchronize()
+        assert fr.status() == B.ST_SEQUENCE, switch
+        assert fr.counts() == (0, 0), switch
+        assert int((fr.ranges()[:, 1] - fr.ranges()[:, 0]).sum()) == 0
+        fr.clear_status()
+        img = pl.forward(fr, ds, xi, dl)[0]
+        torch.cuda.synchronize()
+        assert fr.status() == 0
+        assert torch.equal(img, ref[0]), switch
 
 
 def test_render_fwd_l1_sum_over_many_work_items_is_reproducible():
