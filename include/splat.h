@@ -121,7 +121,7 @@ typedef struct splat_plan {
     size_t off_status;      /* u32                                                      */
     size_t off_counts;      /* u32[8]: 0 slots, 1 instances, 2 work counter, 3 split lists, 4 chunks
                                of the split lists, 5 render-adjoint items, 6 the bin sort the
-                               last projection prepared for, 7 spare                         */
+                               last projection prepared for, 7 runs of 64 depth-sorted slots  */
     size_t off_view_off;    /* u32[V+1] first slot of every view                          */
     size_t off_blockcnt;    /* u32[V*n_blocks_proj*4+1] visible count per (view, wave), scanned in place to slot offsets */
     size_t off_rec;         /* float4[3][slot_cap]: (mx,my,lx,ly) (a,b,c,o) (r,g,b,depth) */
@@ -169,11 +169,11 @@ typedef struct splat_plan {
                                the tile rect being w x h tiles from its first tile (view*T + tile) */
     size_t off_spay;        /* u64[2][slot_cap]: packed payloads of the slot sort (slot_sort)        */
     size_t off_skeys;       /* u32[slot_cap]: the slot sort's second key buffer (slot_sort)          */
-    size_t off_soff;        /* u32[slot_cap+1]: tiles per slot in depth order, scanned to instance
-                               offsets (slot_sort)                                                   */
+    size_t off_soff;        /* u32[ceil(slot_cap/64)+1]: instances of every run of 64 slots in depth
+                               order, scanned to the runs' first instance (slot_sort)               */
     size_t off_l1part;      /* f64[V*T + ceil(V*T / 4096)]: splat_render_fwd_l1's partial sums of
-                               |C - target|, one per (view, tile) work item, then one per group of
-                               4096 items; summed in this fixed order                              */
+                               |C - target|, one per (view, tile), then one per group of 4096 of
+                               them; summed in this fixed order                                    */
 } splat_plan;
 
 /* Fill `s` with the default settings listed above (16x16 tiles, batch 64,

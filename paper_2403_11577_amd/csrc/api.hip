@@ -294,7 +294,7 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     p.off_dkey = take((size_t)slot_cap * 4);
     p.off_spay = take(p.slot_sort ? (size_t)slot_cap * 16 : 0);
     p.off_skeys = take(p.slot_sort ? (size_t)slot_cap * 4 : 0);
-    p.off_soff = take(p.slot_sort ? (size_t)(slot_cap + 1) * 4 : 0);
+    p.off_soff = take(p.slot_sort ? (size_t)((slot_cap + 63) / 64 + 1) * 4 : 0);
     p.off_l1part = take(((size_t)ntiles_all + (ntiles_all + kL1Span - 1) / kL1Span) * 8);
     p.ws_bytes = off;
     *plan = p;

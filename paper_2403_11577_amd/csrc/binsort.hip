@@ -214,24 +214,61 @@ __device__ inline uint64_t field(uint64_t p, int at, int width) {
 }
 
 // tiles of every slot in depth order (scanned afterwards to the instance offsets)
-__global__ __launch_bounds__(256) void slot_tiles_kernel(const uint32_t *__restrict__ counts,
-                                                        const uint64_t *__restrict__ pay, PayBits pb,
-                                                        uint32_t *__restrict__ soff) {
+__device__ inline uint32_t tiles_of(uint64_t p, PayBits pb) {
+    return ((uint32_t)field(p, pb.b0 + pb.tb, pb.b1) + 1u) * ((uint32_t)field(p, pb.b0 + pb.tb + pb.b1, 64) + 1u);
+}
+
+// Instances of every run of 64 consecutive slots in depth order (the runs the emission's waves
+// take), to be scanned to run offsets; counts[CNT_RUNS] = the number of runs.
+__global__ __launch_bounds__(256) void run_tiles_kernel(uint32_t *__restrict__ counts,
+                                                       const uint64_t *__restrict__ pay, PayBits pb,
+                                                       uint32_t *__restrict__ rsum) {
     const uint32_t ns = counts[CNT_SLOTS];
-    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t p = pay[s];
-        const uint32_t w = (uint32_t)field(p, pb.b0 + pb.tb, pb.b1) + 1u;
-        const uint32_t h = (uint32_t)field(p, pb.b0 + pb.tb + pb.b1, 64) + 1u;
-        soff[s] = w * h;
+    const uint32_t nr = (ns + 63u) / 64u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) counts[CNT_RUNS] = nr;
+    const int lane = __lane_id();
+    for (uint64_t q = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < nr; q += (uint64_t)gridDim.x * 4) {
+        const uint64_t s = q * 64 + lane;
+        const uint32_t tot = wave_incl_scan(s < ns ? tiles_of(pay[s], pb) : 0u);
+        if (lane == 63) rsum[q] = tot;
+    }
+}
+
+// Instance count from the scanned run offsets (roff[nr] = the total).  On overflow the count is
+// the end of the longest prefix of slots whose instances all fit: the run in which the capacity
+// is crossed is found by bisection, then the one wave scans that run's tile counts.
+__global__ __launch_bounds__(64) void run_finish_kernel(const uint32_t *roff, const uint64_t *pay, PayBits pb,
+                                                       int64_t inst_cap, uint32_t *counts, uint32_t *status) {
+    const uint32_t nr = counts[CNT_RUNS], ns = counts[CNT_SLOTS];
+    const uint32_t tot = roff[nr];
+    const uint32_t cap = (uint32_t)inst_cap;
+    if (tot <= cap) {
+        if (threadIdx.x == 0) counts[CNT_INST] = tot;
+        return;
+    }
+    uint32_t lo = 0, hi = nr;  // largest run k with roff[k] <= cap (roff[0] = 0 and roff[nr] > cap)
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (roff[mid] <= cap) lo = mid; else hi = mid - 1;
+    }
+    const uint64_t s = (uint64_t)lo * 64 + threadIdx.x;
+    // where each slot of the run ends: nondecreasing, so the slots that fit are a prefix
+    const uint32_t end = roff[lo] + wave_incl_scan(s < ns ? tiles_of(pay[s], pb) : 0u);
+    const int nfit = __popcll(__ballot(end <= cap));
+    const uint32_t cnt = nfit ? (uint32_t)__shfl((int)end, nfit - 1, kWave) : roff[lo];
+    if (threadIdx.x == 0) {
+        counts[CNT_INST] = cnt;
+        atomicOr(status, SPLAT_ST_CAPACITY);
     }
 }
 
 // one instance per (slot, covered tile) in depth order: key view * T + tile (u32), value slot.
-// A wave takes 64 consecutive slots; their instances form one run of the output, which the
-// lanes write in turn (coalesced stores, and no lane waits for a large slot of another): run
-// position q belongs to the last of the 64 slots that starts at or before q.
+// A wave takes a run of 64 consecutive slots; their instances form one run of the output from
+// the run's offset, which the lanes write in turn (coalesced stores, and no lane waits for a
+// large slot of another): run position q belongs to the last of the 64 slots that starts at or
+// before q.
 __global__ __launch_bounds__(256) void emit_sorted_kernel(const uint32_t *__restrict__ counts,
-                                                         const uint32_t *__restrict__ soff,
+                                                         const uint32_t *__restrict__ roff,
                                                          const uint64_t *__restrict__ pay, PayBits pb, int tiles_x,
                                                          uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
     __shared__ uint32_t sbeg[4][64];  // per wave: run position of each slot's first instance
@@ -242,15 +279,12 @@ __global__ __launch_bounds__(256) void emit_sorted_kernel(const uint32_t *__rest
     for (uint64_t s0 = ((uint64_t)blockIdx.x * 4 + w) * 64; s0 < ns; s0 += (uint64_t)gridDim.x * 256) {
         const uint64_t s = s0 + lane;
         const bool valid = s < ns;
-        const uint32_t o = valid ? soff[s] : 0u;
         const uint64_t p = valid ? pay[s] : 0ull;
-        uint32_t nt = 0u;
-        if (valid) {
-            nt = ((uint32_t)field(p, pb.b0 + pb.tb, pb.b1) + 1u) * ((uint32_t)field(p, pb.b0 + pb.tb + pb.b1, 64) + 1u);
-            if ((uint64_t)o + nt > (uint64_t)ni) nt = 0u;  // and so does every later slot
-        }
-        const uint32_t run0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)o);  // lane 0 is valid
-        const uint32_t rel = valid ? o - run0 : 0xFFFFFFFFu;
+        const uint32_t run0 = roff[s0 / 64];
+        uint32_t nt = valid ? tiles_of(p, pb) : 0u;
+        const uint32_t incl = wave_incl_scan(nt);
+        const uint32_t rel = valid ? incl - nt : 0xFFFFFFFFu;
+        if ((uint64_t)run0 + incl > (uint64_t)ni) nt = 0u;  // and so does every later slot
         // the run ends where the last slot with instances ends
         uint32_t end = nt ? rel + nt : 0u;
 #pragma unroll
@@ -762,11 +796,12 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
                                              &sin1);
         if (rc) return rc;
         const uint64_t *pay = sin1 ? pay1 : pay0;
-        hipLaunchKernelGGL(slot_tiles_kernel, dim3(eb), dim3(256), 0, st, counts, pay, pb, soff);
-        if ((rc = launch_status("slot_tiles"))) return rc;
-        if ((rc = launch_scan_u32(soff, soff, counts + CNT_SLOTS, p.slot_cap, partials, nullptr, st))) return rc;
-        hipLaunchKernelGGL(inst_finish_kernel, dim3(1), dim3(64), 0, st, soff, p.inst_cap, counts, status);
-        if ((rc = launch_status("inst_finish"))) return rc;
+        hipLaunchKernelGGL(run_tiles_kernel, dim3((eb + 3) / 4), dim3(256), 0, st, counts, pay, pb, soff);
+        if ((rc = launch_status("run_tiles"))) return rc;
+        if ((rc = launch_scan_u32(soff, soff, counts + CNT_RUNS, (p.slot_cap + 63) / 64, partials, nullptr, st)))
+            return rc;
+        hipLaunchKernelGGL(run_finish_kernel, dim3(1), dim3(64), 0, st, soff, pay, pb, p.inst_cap, counts, status);
+        if ((rc = launch_status("run_finish"))) return rc;
         uint32_t *k32 = reinterpret_cast<uint32_t *>(keys0);
         hipLaunchKernelGGL(emit_sorted_kernel, dim3((eb + 3) / 4), dim3(256), 0, st, counts, soff, pay, pb, p.tiles_x,
                            k32, vals0);

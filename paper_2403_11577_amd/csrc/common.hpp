@@ -31,7 +31,8 @@ struct alignas(8) Rect16 {
 };
 
 // counter indices in off_counts
-enum { CNT_SLOTS = 0, CNT_INST = 1, CNT_WORK = 2, CNT_NSPLIT = 3, CNT_NCHUNK = 4, CNT_BITEMS = 5, CNT_PREP = 6 };
+enum { CNT_SLOTS = 0, CNT_INST = 1, CNT_WORK = 2, CNT_NSPLIT = 3, CNT_NCHUNK = 4, CNT_BITEMS = 5, CNT_PREP = 6,
+       CNT_RUNS = 7 };
 // counts[CNT_PREP]: the bin sort the last projection wrote its per-slot inputs for
 constexpr uint32_t kPrepSlotSort = 0x534C4F54u, kPrepInstSort = 0x494E5354u;
 

@@ -53,7 +53,7 @@ struct RenderArgs {
     uint8_t *bmask;             // per instance: sub-blocks it was blended into (forward writes)
     float4 *g2z;                // the slots' gradient sums, cleared by the forward for the adjoint
     L1Fuse l1;                  // the L1 term at the forward's output stage (l1.target null: off)
-    double *l1part;             // its sum of |C - target| per work item
+    double *l1part;             // its sum of |C - target| per (view, tile)
     unsigned long long *stats;  // pair counters of the instrumented variant
     int n_items, T, tiles_x, W, H, persistent, roi_y0;
     uint32_t lc, chk_cap;       // split length, checkpoint slots
@@ -551,11 +551,12 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a, float *img
             }
         }
         if (a.l1.target && a.l1.loss) {
-            // one partial per work item, summed in item order after the launch (a device-wide
-            // atomic per item on one address serialises at the memory side)
+            // one partial per (view, tile), summed in that order after the launch (the work
+            // queue's order within a cost class varies between calls; a device-wide atomic per
+            // item on one address serialises at the memory side)
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) l1acc += __shfl_xor(l1acc, off, kWave);
-            if (lane == 0) a.l1part[item] = l1acc;
+            if (lane == 0) a.l1part[tid] = l1acc;
         }
     }
     if (STATS) {
@@ -816,9 +817,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void re
 
 __global__ void reset_work_kernel(uint32_t *w) { *w = 0u; }
 
-// Fixed-order sum of the forward's L1 partials: workgroup g adds items [g kL1Span, (g+1) kL1Span)
-// (thread t the items t mod 256, then a tree over the threads) into out[g]; with scale != 0 a
-// single workgroup adds scale times the sum of all n into *loss instead.
+// Fixed-order sum of the forward's L1 partials: workgroup g adds partials [g kL1Span, (g+1) kL1Span)
+// (thread t those at t mod 256, then a tree over the threads) into out[g]; given loss, the one
+// workgroup adds scale times the sum of all n into *loss instead.
 __global__ __launch_bounds__(256) void l1_sum_kernel(const double *in, int n, double *out, double scale,
                                                      double *loss) {
     __shared__ double s[256];

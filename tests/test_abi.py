@@ -57,7 +57,7 @@ def test_plan_layout_is_aligned_and_disjoint():
     assert p.off_bmask - p.off_chklast >= p.chk_cap * 16 * 16 * 4
     assert p.off_dkey - p.off_bmask >= 9000 and p.off_spay - p.off_dkey >= 2000 * 4
     assert p.off_skeys - p.off_spay >= 2000 * 16 and p.off_soff - p.off_skeys >= 2000 * 4
-    assert p.off_l1part - p.off_soff >= 2001 * 4
+    assert p.off_l1part - p.off_soff >= (-(-2000 // 64) + 1) * 4
     assert p.ws_bytes - p.off_l1part >= (63 + 1) * 8   # 63 work-item partials, one group sum
     assert p.tiles_x == 7 and p.tiles_y == 3 and p.tiles_per_view == 21
     # key = (view*T + tile) << depth_bits | depth: 63 items need 6 bits, the 0.2..256 m window 27

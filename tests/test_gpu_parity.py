@@ -521,6 +521,45 @@ def test_capacity_overflow_is_flagged_not_fatal():
     assert ns <= 100 and ni <= 200
 
 
+@pytest.mark.parametrize("path", ["slot_first", "instance_keys"])
+def test_instance_capacity_overflow_keeps_the_longest_prefix(path):
+    """With too few instance slots the bin sort emits exactly the instances of the longest prefix
+    of slots that fits, in emission order (depth order with the slot-first sort, slot order with
+    the 64-bit keys), and flags SPLAT_ST_CAPACITY."""
+    say(f"case: instance capacity overflow path={path}")
+    scene = synth.small_drive(4, n_frames=2)
+    ds = pl.DeviceScene.from_scene(scene)
+    xi, dl = _dev(scene.xi), _dev(scene.delta)
+    ref = pl.fit_frame(ds, xi, dl, pl.make_settings())
+    if path == "instance_keys":
+        use_instance_sort(ref)
+    pl.forward(ref, ds, xi, dl)
+    torch.cuda.synchronize()
+    ns, ni = ref.counts()
+    assert ref.status() == 0 and ni > 3000
+    per_slot = np.bincount(ref.sorted_vals(ni).cpu().numpy().astype(np.int64), minlength=ns)
+    if path == "slot_first":  # emission order: (depth32, slot)
+        depth = ref.records(ns)[:, 11].contiguous().cpu().numpy().view(np.uint32)
+        order = np.lexsort((np.arange(ns), depth))
+    else:
+        order = np.arange(ns)
+    ends = np.cumsum(per_slot[order])
+    for cap in (ni // 3, ni // 2 + 17, ni - 1):
+        fr = pl.Frame(ref.settings, ref.V, ref.G, ref.W, ref.H, int(ref.plan.slot_cap), cap)
+        if path == "instance_keys":
+            use_instance_sort(fr)
+        pl.forward(fr, ds, xi, dl)
+        torch.cuda.synchronize()
+        assert fr.status() == B.ST_CAPACITY
+        ns2, ni2 = fr.counts()
+        k = int(np.searchsorted(ends, cap, side="right"))   # slots order[:k] fit
+        assert ns2 == ns and ni2 == (int(ends[k - 1]) if k else 0), cap
+        got = np.bincount(fr.sorted_vals(ni2).cpu().numpy().astype(np.int64), minlength=ns)
+        want = np.zeros(ns, np.int64)
+        want[order[:k]] = per_slot[order[:k]]
+        assert np.array_equal(got, want), cap
+
+
 def test_invalid_arguments_rejected():
     say("case: invalid args")
     st = pl.make_settings()
