@@ -266,9 +266,10 @@ SPLAT_API int splat_project(const splat_plan *plan, void *ws, const splat_gaussi
  * sorted result (it is a function of the plan only).  With slot_sort = 0 the
  * per-slot tile counts written by splat_project are turned into instance
  * offsets in place; with slot_sort = 1 the slot sort consumes the depth fields.
- * Either way, call this exactly once after each splat_project.  When the
- * instances exceed inst_cap, the longest prefix of whole slots in emission
- * order is kept and SPLAT_ST_CAPACITY is set.
+ * Either way, call this exactly once after each splat_project, with the same
+ * slot_sort as that projection (otherwise nothing is binned and
+ * SPLAT_ST_SEQUENCE is set).  When the instances exceed inst_cap, the longest
+ * prefix of whole slots in emission order is kept and SPLAT_ST_CAPACITY is set.
  */
 SPLAT_API int splat_bin_sort(const splat_plan *plan, void *ws, void *stream);
 
