@@ -280,7 +280,7 @@ int splat_plan_make(const splat_settings *s, int32_t n_views, int64_t n_gauss, i
     p.off_grad2d = take((size_t)slot_cap * 36);
     p.off_visbits = take((size_t)n_views * p.n_blocks_proj * 4 * 8);
     p.off_dwpart = take((size_t)n_views * (p.n_blocks_proj * 4 + kDw2cStages) * 12 * 8);  // + the stage sums
-    p.off_cam = take((size_t)n_views * 8 * 8);
+    p.off_cam = take((size_t)n_views * kCamBytes);
     // render-adjoint work items: a list of L >= split_len instances becomes ceil(L / split_len) <=
     // 2 L / split_len chunks, so the split lists need fewer than 2 inst_cap / split_len chunks
     p.split_len = s->split_len ? s->split_len : 1024;

@@ -19,6 +19,7 @@ constexpr int kRadixBits = SPLAT_RADIX_BITS;
 constexpr int kRadixDigits = 1 << kRadixBits;
 constexpr int kDw2cStages = 32;  // workgroups per view summing the W2C gradient partials
 constexpr int kL1Span = 4096;    // work-item partials of the forward's L1 term summed per workgroup
+constexpr size_t kCamBytes = 144;  // per-view camera constants of the projection (f64[8], f32[20])
 
 // workspace views --------------------------------------------------------------
 template <typename T>

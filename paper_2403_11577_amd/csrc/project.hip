@@ -28,10 +28,15 @@ struct GaussPre {
 };
 
 // Per-view camera constants: focal lengths, principal point and the clamp bounds
-// of the Jacobian's x/z, y/z ratios.
+// of the Jacobian's x/z, y/z ratios; then float32 copies of the world-to-camera matrix and
+// of those constants for the cull bounds and the depth key (converted once per view instead
+// of once per (Gaussian, view) pair).
 struct CamC {
     double fx, fy, cx, cy, gx0, gx1, gy0, gy1;
+    float m[12];
+    float fxf, fyf, cxf, cyf, gx0f, gx1f, gy0f, gy1f;
 };
+static_assert(sizeof(CamC) == kCamBytes, "camera constants");
 
 struct Proj {
     float depth32;
@@ -64,7 +69,8 @@ __device__ inline void gauss_pre(const splat_settings &S, const float *q, float 
     G.k2 = fmax(2.0 * log((double)o / S.alpha_min), 0.0);
 }
 
-__global__ void camconst_kernel(splat_settings S, const double *intr, int V, int W, int H, CamC *cam) {
+__global__ void camconst_kernel(splat_settings S, const double *intr, const double *w2c, int V, int W, int H,
+                                CamC *cam) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
     const double *K4 = intr + 4 * v;
@@ -72,6 +78,9 @@ __global__ void camconst_kernel(splat_settings S, const double *intr, int V, int
     c.fx = K4[0]; c.fy = K4[1]; c.cx = K4[2]; c.cy = K4[3];
     c.gx0 = (-c.cx - S.guard * W) / c.fx; c.gx1 = (W - c.cx + S.guard * W) / c.fx;
     c.gy0 = (-c.cy - S.guard * H) / c.fy; c.gy1 = (H - c.cy + S.guard * H) / c.fy;
+    for (int k = 0; k < 12; ++k) c.m[k] = (float)w2c[12 * v + k];
+    c.fxf = (float)c.fx; c.fyf = (float)c.fy; c.cxf = (float)c.cx; c.cyf = (float)c.cy;
+    c.gx0f = (float)c.gx0; c.gx1f = (float)c.gx1; c.gy0f = (float)c.gy0; c.gy1f = (float)c.gy1;
     cam[v] = c;
 }
 
@@ -129,8 +138,9 @@ __device__ inline int footprint(const splat_settings &S, double k2, int W, int H
 }
 
 // float32 depth key: fma chain on float32-rounded row 2 of W2C
-__device__ inline float depth_key(const double *M, const float *x) {
-    return __fmaf_rn((float)M[8], x[0], __fmaf_rn((float)M[9], x[1], __fmaf_rn((float)M[10], x[2], (float)M[11])));
+// m: the float32 copy of the view's world-to-camera matrix (CamC::m)
+__device__ inline float depth_key(const float *m, const float *x) {
+    return __fmaf_rn(m[8], x[0], __fmaf_rn(m[9], x[1], __fmaf_rn(m[10], x[2], m[11])));
 }
 
 // Conservative float32 frustum test, run before the float64 projection: true
@@ -138,25 +148,25 @@ __device__ inline float depth_key(const double *M, const float *x) {
 // half-width is k sqrt(Sigma2_xx) (1 + pad_rel) + pad_px with Sigma2_xx =
 // |J_x A|^2 + eps2d <= |J_x|^2 max(s)^2 + eps2d (W and R are rotations), where
 // J_x = (fx / z, 0, -fx xh / z) with the clamped ratio xh; likewise for y.  The
-// bound is widened by 0.1% + 1 px + 1e-5 |mu| to cover float32 rounding.
-__device__ inline bool offscreen_bound(const splat_settings &S, const double *M, const CamC &C, int W, int H,
-                                       const float *x, const float *s, float k2f, float z) {
-    float t0 = __fmaf_rn((float)M[0], x[0], __fmaf_rn((float)M[1], x[1], __fmaf_rn((float)M[2], x[2], (float)M[3])));
-    float t1 = __fmaf_rn((float)M[4], x[0], __fmaf_rn((float)M[5], x[1], __fmaf_rn((float)M[6], x[2], (float)M[7])));
-    float iz = 1.f / z;
-    float fx = (float)C.fx, fy = (float)C.fy, cx = (float)C.cx, cy = (float)C.cy;
+// bound is widened by 0.1% + 1 px + 1e-5 |mu| to cover float32 rounding (and the one-ulp
+// hardware reciprocal and square root).  sm2 = max(s)^2, k2f = k^2 in float32.
+__device__ inline bool offscreen_bound(const splat_settings &S, const CamC &C, int W, int H, const float *x,
+                                       float sm2, float k2f, float z) {
+    const float *m = C.m;
+    float t0 = __fmaf_rn(m[0], x[0], __fmaf_rn(m[1], x[1], __fmaf_rn(m[2], x[2], m[3])));
+    float t1 = __fmaf_rn(m[4], x[0], __fmaf_rn(m[5], x[1], __fmaf_rn(m[6], x[2], m[7])));
+    float iz = __builtin_amdgcn_rcpf(z);
     float ux = t0 * iz, uy = t1 * iz;
-    float xh = fminf(fmaxf(ux, (float)C.gx0), (float)C.gx1);
-    float yh = fminf(fmaxf(uy, (float)C.gy0), (float)C.gy1);
-    float sm = fmaxf(fmaxf(s[0], s[1]), s[2]);
+    float xh = fminf(fmaxf(ux, C.gx0f), C.gx1f);
+    float yh = fminf(fmaxf(uy, C.gy0f), C.gy1f);
     float e2 = (float)S.eps2d;
-    float jx = fx * iz, jy = fy * iz;
-    float sx = jx * jx * (1.f + xh * xh) * sm * sm + e2;
-    float sy = jy * jy * (1.f + yh * yh) * sm * sm + e2;
+    float jx = C.fxf * iz, jy = C.fyf * iz;
+    float sx = jx * jx * (1.f + xh * xh) * sm2 + e2;
+    float sy = jy * jy * (1.f + yh * yh) * sm2 + e2;
     float pr = 1.f + (float)S.pad_rel, pp = (float)S.pad_px;
-    float mx = fx * ux + cx, my = fy * uy + cy;
-    float ex = (sqrtf(k2f * sx) * pr + pp) * 1.001f + 1.f + 1e-5f * fabsf(mx);
-    float ey = (sqrtf(k2f * sy) * pr + pp) * 1.001f + 1.f + 1e-5f * fabsf(my);
+    float mx = C.fxf * ux + C.cxf, my = C.fyf * uy + C.cyf;
+    float ex = (__builtin_amdgcn_sqrtf(k2f * sx) * pr + pp) * 1.001f + 1.f + 1e-5f * fabsf(mx);
+    float ey = (__builtin_amdgcn_sqrtf(k2f * sy) * pr + pp) * 1.001f + 1.f + 1e-5f * fabsf(my);
     // NaN anywhere makes every comparison false: not culled here, decided exactly afterwards
     return (mx - 0.5f + ex < 0.f) || (mx - 0.5f - ex > (float)(W - 1)) || (my - 0.5f + ey < (float)S.roi_y0) ||
            (my - 0.5f - ey > (float)(H - 1));
@@ -168,20 +178,22 @@ __device__ inline bool offscreen_bound(const splat_settings &S, const double *M,
 // contains the integer nearest to u, which lies in [0, W - 1] whenever u does (likewise for
 // y and the rows [roi_y0, H - 1]).  u is bounded through the float32 mean: its error in u_x
 // is at most 1e-6 (a0 + |u_x| a2) / z, a0 and a2 being the sums of the magnitudes of the terms
-// of t0 and z (four roundings of 2^-24 each, widened 4x), and 1e-5 |mu| + 1 px are added.
-__device__ inline bool onscreen_bound(const splat_settings &S, const double *M, const CamC &C, int W, int H,
-                                      const float *x, float k2f, float z) {
-    const float h = sqrtf(k2f * (float)S.eps2d) * 0.9999f + (float)S.pad_px;
-    if (!(h >= 0.5001f)) return false;
-    float t0 = __fmaf_rn((float)M[0], x[0], __fmaf_rn((float)M[1], x[1], __fmaf_rn((float)M[2], x[2], (float)M[3])));
-    float t1 = __fmaf_rn((float)M[4], x[0], __fmaf_rn((float)M[5], x[1], __fmaf_rn((float)M[6], x[2], (float)M[7])));
-    float a0 = fabsf((float)M[0] * x[0]) + fabsf((float)M[1] * x[1]) + fabsf((float)M[2] * x[2]) + fabsf((float)M[3]);
-    float a1 = fabsf((float)M[4] * x[0]) + fabsf((float)M[5] * x[1]) + fabsf((float)M[6] * x[2]) + fabsf((float)M[7]);
-    float a2 = fabsf((float)M[8] * x[0]) + fabsf((float)M[9] * x[1]) + fabsf((float)M[10] * x[2]) + fabsf((float)M[11]);
-    float iz = 1.f / z;
+// of t0 and z (four roundings of 2^-24 each, and one ulp of the reciprocal, widened 4x), and
+// 1e-5 |mu| + 1 px are added.  h_ok: h >= 1/2 with h = sqrt(k2 eps2d) 0.9999 + pad_px (per
+// Gaussian).
+__device__ inline bool onscreen_bound(const splat_settings &S, const CamC &C, int W, int H, const float *x,
+                                      bool h_ok, float z) {
+    if (!h_ok) return false;
+    const float *m = C.m;
+    float t0 = __fmaf_rn(m[0], x[0], __fmaf_rn(m[1], x[1], __fmaf_rn(m[2], x[2], m[3])));
+    float t1 = __fmaf_rn(m[4], x[0], __fmaf_rn(m[5], x[1], __fmaf_rn(m[6], x[2], m[7])));
+    float a0 = fabsf(m[0] * x[0]) + fabsf(m[1] * x[1]) + fabsf(m[2] * x[2]) + fabsf(m[3]);
+    float a1 = fabsf(m[4] * x[0]) + fabsf(m[5] * x[1]) + fabsf(m[6] * x[2]) + fabsf(m[7]);
+    float a2 = fabsf(m[8] * x[0]) + fabsf(m[9] * x[1]) + fabsf(m[10] * x[2]) + fabsf(m[11]);
+    float iz = __builtin_amdgcn_rcpf(z);
     float ux = t0 * iz, uy = t1 * iz;
-    float fx = (float)C.fx, fy = (float)C.fy;
-    float mx = fx * ux + (float)C.cx, my = fy * uy + (float)C.cy;
+    float fx = C.fxf, fy = C.fyf;
+    float mx = fx * ux + C.cxf, my = fy * uy + C.cyf;
     float dx = 1.f + 1e-5f * fabsf(mx) + 1e-6f * fabsf(fx) * (a0 + fabsf(ux) * a2) * iz;
     float dy = 1.f + 1e-5f * fabsf(my) + 1e-6f * fabsf(fy) * (a1 + fabsf(uy) * a2) * iz;
     float u = mx - 0.5f, v = my - 0.5f;
@@ -196,6 +208,8 @@ struct GaussIn {
     float x[3], q[4], s[3], o;
     bool fin, opac_ok, quat_ok;
     GaussPre G;
+    float k2f, sm2;  // the cull bounds' per-Gaussian terms: k^2 and max(s)^2 in float32
+    bool h_ok;       // the smallest footprint half-width reaches half a pixel
 };
 
 __device__ inline void gauss_in(const splat_settings &S, const splat_gaussians &g, int64_t i, GaussIn &gi) {
@@ -211,20 +225,25 @@ __device__ inline void gauss_in(const splat_settings &S, const splat_gaussians &
     double n2 = (double)gi.q[0] * gi.q[0] + (double)gi.q[1] * gi.q[1] + (double)gi.q[2] * gi.q[2] +
                 (double)gi.q[3] * gi.q[3];
     gi.quat_ok = n2 >= 1e-24;
-    if (gi.fin && gi.opac_ok && gi.quat_ok) gauss_pre(S, gi.q, gi.o, gi.G);
+    const bool pre = gi.fin && gi.opac_ok && gi.quat_ok;
+    if (pre) gauss_pre(S, gi.q, gi.o, gi.G);
+    gi.k2f = pre ? (float)gi.G.k2 : 0.f;  // read by the bounds only after those three checks
+    const float sm = fmaxf(fmaxf(gi.s[0], gi.s[1]), gi.s[2]);
+    gi.sm2 = sm * sm;
+    gi.h_ok = sqrtf(gi.k2f * (float)S.eps2d) * 0.9999f + (float)S.pad_px >= 0.5001f;
 }
 
 __device__ inline int classify(const splat_settings &S, const double *M, const CamC &C, int W, int H,
                                const GaussIn &gi, Proj &P) {
     if (!gi.fin) return PC_NONFINITE;
-    P.depth32 = depth_key(M, gi.x);
+    P.depth32 = depth_key(C.m, gi.x);
     if (!(P.depth32 > (float)S.near_z)) return PC_NEAR;
     if (P.depth32 > (float)S.far_z) return PC_FAR;
     if (!gi.opac_ok) return PC_OPAC;
     if (!gi.quat_ok) return PC_QUAT;
-    if (offscreen_bound(S, M, C, W, H, gi.x, gi.s, (float)gi.G.k2, P.depth32)) return PC_OFF;
+    if (offscreen_bound(S, C, W, H, gi.x, gi.sm2, gi.k2f, P.depth32)) return PC_OFF;
     // most visible pairs are decided here; the float64 projection is for the ones near an edge
-    if (onscreen_bound(S, M, C, W, H, gi.x, (float)gi.G.k2, P.depth32)) return PC_OK;
+    if (onscreen_bound(S, C, W, H, gi.x, gi.h_ok, P.depth32)) return PC_OK;
     project_view(S, M, C, gi.x, gi.s, gi.G, false, P);
     return footprint(S, gi.G.k2, W, H, P);
 }
@@ -300,7 +319,7 @@ __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, sp
         if (slot >= (uint64_t)slot_cap) continue;  // capacity flagged by the scan finisher
         const double *M = w2c + 12 * v;
         Proj P;
-        P.depth32 = depth_key(M, gi.x);
+        P.depth32 = depth_key(cam[v].m, gi.x);
         project_view(S, M, cam[v], gi.x, gi.s, gi.G, true, P);
         footprint(S, gi.G.k2, W, H, P);  // visible: the count pass found this rectangle non-empty
         float mxh = (float)P.mu[0], myh = (float)P.mu[1];
@@ -590,7 +609,8 @@ int launch_project(const splat_plan &p, void *ws, const splat_gaussians &g, cons
     uint32_t *wavecnt = ws_at<uint32_t>(ws, p.off_blockcnt);
     CamC *cam = ws_at<CamC>(ws, p.off_cam);
     uint64_t *visbits = ws_at<uint64_t>(ws, p.off_visbits);
-    hipLaunchKernelGGL(camconst_kernel, dim3((V + 63) / 64), dim3(64), 0, st, p.s, intr, V, p.width, p.height, cam);
+    hipLaunchKernelGGL(camconst_kernel, dim3((V + 63) / 64), dim3(64), 0, st, p.s, intr, w2c, V, p.width, p.height,
+                       cam);
     int rc = launch_status("camconst");
     if (rc) return rc;
     if (g.n == 0) {
@@ -625,8 +645,8 @@ int launch_project_bwd(const splat_plan &p, void *ws, const splat_gaussians &g, 
     if (g.n == 0) return 0;
     int nb = p.n_blocks_proj;
     double *part = ws_at<double>(ws, p.off_dwpart);
-    hipLaunchKernelGGL(camconst_kernel, dim3((p.n_views + 63) / 64), dim3(64), 0, st, p.s, intr, p.n_views, p.width,
-                       p.height, ws_at<CamC>(ws, p.off_cam));
+    hipLaunchKernelGGL(camconst_kernel, dim3((p.n_views + 63) / 64), dim3(64), 0, st, p.s, intr, w2c, p.n_views,
+                       p.width, p.height, ws_at<CamC>(ws, p.off_cam));
     int rc0 = launch_status("camconst");
     if (rc0) return rc0;
     hipLaunchKernelGGL(project_bwd_kernel, dim3(nb), dim3(256), 0, st, p.s, g, w2c, ws_at<CamC>(ws, p.off_cam),
