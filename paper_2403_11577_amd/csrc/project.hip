@@ -310,7 +310,8 @@ __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, sp
     gauss_in(S, g, i, gi);
     const int64_t n = g.n;
     const float cr = g.color[i], cg = g.color[n + i], cb = g.color[2 * n + i];
-    const int tw = S.tile_w, th = S.tile_h;
+    // tile sizes are powers of two and the footprint bounds are non-negative: shifts divide
+    const int tws = __builtin_ctz((unsigned)S.tile_w), ths = __builtin_ctz((unsigned)S.tile_h);
     for (int v = 0; v < V; ++v) {
         size_t k = ((size_t)v * nb + b) * 4 + w;
         uint64_t m = visbits[k];
@@ -330,8 +331,8 @@ __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, sp
         meta[slot] = make_int2((int)i, v);
         dkey[slot] = __float_as_uint(P.depth32) - __float_as_uint((float)S.near_z);
         Rect16 rc;
-        rc.x0 = (uint16_t)(P.px0 / tw); rc.x1 = (uint16_t)(P.px1 / tw);
-        rc.y0 = (uint16_t)(P.py0 / th); rc.y1 = (uint16_t)(P.py1 / th);
+        rc.x0 = (uint16_t)(P.px0 >> tws); rc.x1 = (uint16_t)(P.px1 >> tws);
+        rc.y0 = (uint16_t)(P.py0 >> ths); rc.y1 = (uint16_t)(P.py1 >> ths);
         if (!sp.spay) {  // the 64-bit instance sort reads the rect and tile count of every slot
             rect[slot] = rc;
             ntiles[slot] = (uint32_t)(rc.x1 - rc.x0 + 1) * (uint32_t)(rc.y1 - rc.y0 + 1);
