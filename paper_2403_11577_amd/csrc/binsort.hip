@@ -556,6 +556,45 @@ __global__ __launch_bounds__(256) void ranges_kernel(const K *__restrict__ keys,
     }
 }
 
+// The same for u32 keys on a 16-byte aligned buffer: lane l of a wave loads its four keys with
+// one vector load; the key before them is lane l - 1's last and the key after them lane l + 1's
+// first (lanes 0 and 63 load theirs).  The walk goes by whole waves, so every lane takes part
+// in the exchanges.
+__global__ __launch_bounds__(256) void ranges_vec_kernel(const uint32_t *__restrict__ keys, const uint32_t *counts,
+                                                        int shift, uint32_t n_tiles, uint2 *__restrict__ ranges) {
+    constexpr uint32_t kNone = 0xFFFFFFFFu;  // past either end; never a tile (n_tiles < 2^31)
+    const uint32_t n = counts[CNT_INST];
+    const uint64_t ng = ((uint64_t)n + 3) / 4;
+    const int lane = __lane_id();
+    const uint4 *keys4 = reinterpret_cast<const uint4 *>(keys);
+    auto tile_at = [&](int64_t i) { return (i >= 0 && i < (int64_t)n) ? keys[i] >> shift : kNone; };
+    for (uint64_t g0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); g0 < ng;
+         g0 += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t g = g0 + (uint64_t)lane;
+        const int64_t i0 = 4 * (int64_t)g;
+        uint32_t t[6];
+        if (i0 + 3 < (int64_t)n) {
+            const uint4 q = keys4[g];
+            t[1] = q.x >> shift; t[2] = q.y >> shift; t[3] = q.z >> shift; t[4] = q.w >> shift;
+        } else {
+#pragma unroll
+            for (int k = 1; k <= 4; ++k) t[k] = tile_at(i0 + k - 1);
+        }
+        t[0] = (uint32_t)__shfl_up((int)t[4], 1, kWave);
+        t[5] = (uint32_t)__shfl_down((int)t[1], 1, kWave);
+        if (lane == 0) t[0] = tile_at(i0 - 1);
+        if (lane == 63) t[5] = tile_at(i0 + 4);
+#pragma unroll
+        for (int k = 1; k <= 4; ++k) {
+            const uint32_t tk = t[k];
+            if (tk >= n_tiles) continue;  // past the end; cannot happen for emitted keys
+            const uint32_t i = (uint32_t)(i0 + k - 1);
+            if (t[k - 1] != tk) ranges[tk].x = i;
+            if (t[k + 1] != tk) ranges[tk].y = i + 1;
+        }
+    }
+}
+
 __device__ inline int cost_bucket(uint2 r) {
     uint32_t c = r.y - r.x;  // empty tiles have x = y = 0
     return c == 0 ? 0 : 32 - __clz(c);  // 1..32
@@ -836,7 +875,10 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
     if ((rc = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, (int64_t)2 * nT, st))) return rc;
     int rb = (int)((p.inst_cap / 4 + 256) / 256);
     if (rb > 8192) rb = 8192;
-    if (kshift >= 0)
+    if (kshift >= 0 && (reinterpret_cast<uintptr_t>(ki) & 15u) == 0)
+        hipLaunchKernelGGL(ranges_vec_kernel, dim3(rb), dim3(256), 0, st, reinterpret_cast<const uint32_t *>(ki), counts,
+                           p.depth_bits - kshift, (uint32_t)nT, ranges);
+    else if (kshift >= 0)
         hipLaunchKernelGGL(ranges_kernel<uint32_t>, dim3(rb), dim3(256), 0, st, reinterpret_cast<const uint32_t *>(ki),
                            counts, p.depth_bits - kshift, (uint64_t)nT, ranges);
     else
