@@ -13,9 +13,10 @@
 //
 // Adjoint: the 11 output gradients are pushed back through the heads and the MLP (on the
 // matrix cores, from the forward's values stored per Gaussian, or evaluated again), and
-// the activations and deltas are stored so that the weight gradients -- sums over all
-// Gaussians of outer products, a tall-skinny A^T B -- are formed by atb_kernel
-// (per-workgroup partials on the matrix cores, then a fixed-order float64 reduction).  The table gradient of a
+// the weight gradients -- sums over all Gaussians of outer products, a tall-skinny A^T B --
+// are contracted on the matrix cores into per-workgroup partials (inside the adjoint that
+// reads the stored values, by wgrad_kernel from the stored deltas otherwise), then reduced
+// in a fixed float64 order.  The table gradient of a
 // row is the sum, over every (Gaussian, vertex) that looked it up, of the
 // trilinear weight times the Gaussian's encoding gradient.  Two ways to form it:
 //  * scatter: hardware float atomics (16 levels x 8 vertices x 2 features), after
@@ -392,14 +393,15 @@ __device__ __forceinline__ void field_block(const NgpArgs &a, const float2 *tabl
     }
 }
 
-// The adjoint of block g0 from the stored rows: output deltas, dL/dh2 and dL/dh1 go to the
-// rows (for the weight gradients), the encoding gradients are returned in tile layout
-// (register v of tile (t, j): feature 16 t + 4 q + v of Gaussian g0 + 16 j + c; zero for
-// lanes past n).
-template <int FJ>
+// The adjoint of block g0 from the stored rows: the output deltas D, dL/dh2 (G) and dL/dh1
+// (H) are returned, and with STORE also written to the rows (for the weight-gradient kernel),
+// the encoding gradients are returned too, all in tile layout (register v of tile (t, j):
+// feature 16 t + 4 q + v of Gaussian g0 + 16 j + c; zero for lanes past n).
+template <int FJ, bool STORE>
 __device__ __forceinline__ void adjoint_block(const NgpArgs &a, const WBwd &W, int64_t n, int64_t g0,
                                               const float *dquat, const float *dscale, const float *dopac,
-                                              const float *dcolor, float *rows, f4 (&dE)[2][FJ]) {
+                                              const float *dcolor, float *rows, f4 (&dE)[2][FJ], f4 (&D)[FJ],
+                                              f4 (&G)[4][FJ], f4 (&H)[4][FJ]) {
     const int lane = __lane_id(), c = lane & 15, q = lane >> 4;
     // the row stride, opaque to the compiler: the offsets of the stores below are then formed
     // where they are used, instead of all of them being hoisted out of the block loop
@@ -415,7 +417,6 @@ __device__ __forceinline__ void adjoint_block(const NgpArgs &a, const WBwd &W, i
         m1[j] = __float_as_uint(mr[0]);
         m2[j] = __float_as_uint(mr[(int64_t)4 * ld]);
     }
-    f4 D[FJ];
 #pragma unroll
     for (int j = 0; j < FJ; ++j) {
         const int64_t g = g0 + 16 * j + c;
@@ -435,11 +436,10 @@ __device__ __forceinline__ void adjoint_block(const NgpArgs &a, const WBwd &W, i
             }
             d = live ? d : 0.f;
             D[j][v] = d;
-            if (k < 12) lr[(int64_t)(R_DOUT + v) * ld + 16 * j] = d;
+            if (STORE && k < 12) lr[(int64_t)(R_DOUT + v) * ld + 16 * j] = d;
         }
     }
     // dL/dh2 = w3^T dOut where h2 > 0
-    f4 G[4][FJ];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
 #pragma unroll
@@ -458,10 +458,9 @@ __device__ __forceinline__ void adjoint_block(const NgpArgs &a, const WBwd &W, i
             for (int v = 0; v < 4; ++v) {
                 const float d = (m2[j] >> (4 * t + v)) & 1u ? G[t][j][v] : 0.f;
                 G[t][j][v] = d;
-                lr[(int64_t)(R_DH2 + 16 * t + v) * ld + 16 * j] = d;
+                if (STORE) lr[(int64_t)(R_DH2 + 16 * t + v) * ld + 16 * j] = d;
             }
     // dL/dh1 = w2^T dL/dh2 where h1 > 0
-    f4 H[4][FJ];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -484,7 +483,7 @@ __device__ __forceinline__ void adjoint_block(const NgpArgs &a, const WBwd &W, i
             for (int v = 0; v < 4; ++v) {
                 const float d = (m1[j] >> (4 * t + v)) & 1u ? H[t][j][v] : 0.f;
                 H[t][j][v] = d;
-                lr[(int64_t)(R_DH1 + 16 * t + v) * ld + 16 * j] = d;
+                if (STORE) lr[(int64_t)(R_DH1 + 16 * t + v) * ld + 16 * j] = d;
             }
     // dL/denc = w1^T dL/dh1
 #pragma unroll
@@ -521,6 +520,146 @@ __global__ __launch_bounds__(256, 2) void ngp_fwd_kernel(NgpArgs a, const float 
         field_block<FJ, SAVE>(a, tables, W, mean, n, FB * b, quat, scale, opac, color, rows);
 }
 
+// ---- weight gradients on the matrix cores, contracted over the Gaussians ----
+// dW3 = dOut^T h2 (dOut padded to 16 rows), dW2 = dh2^T h1, dW1 = dh1^T enc, and the bias
+// gradients, the column sums of the deltas.  A wave adds 16 Gaussians g16 + 0..15 at a time.
+// In an A tile lane (m, kq) (m = lane % 16, kq = lane / 16) holds in register s the delta of
+// feature 16 t + m of Gaussian g16 + 4 kq + s; in a B tile, the activation of column 16 t + m
+// of the same Gaussian; MFMA s then contracts the Gaussians {4 kq + s}.  The adjoint's deltas
+// come in tile layout (Gaussian on the lane's low bits); transpose16 turns such a 16 x 16 tile
+// into the A layout on the matrix cores: four MFMAs against selector matrices, each output
+// element one product by 1.0 plus products by 0.0, so the values pass unchanged (the rows
+// loaded by wgrad_kernel hold the same values, so all adjoint paths sum the same products in
+// the same order).
+constexpr int WG_NE3 = 12 * NH + 12, WG_NE2 = NH * NH + NH, WG_NE1 = NH * ND + NH;  // partial sizes
+constexpr int WG_NE = WG_NE3 + WG_NE2 + WG_NE1;
+constexpr int WG_FJ = 1;  // 16-Gaussian blocks per wave step of the saved adjoint (and of wgrad_kernel)
+
+struct WAcc {
+    f4 w3[4], w2[16], w1[8];  // C tiles (ti, tj): w3[tj], w2[4 ti + tj], w1[2 ti + tj]
+    float b3, b2[4], b1[4];   // per lane: column sums of the deltas of features 16 t + lane % 16
+};
+
+__device__ __forceinline__ void wacc_zero(WAcc &acc) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc.w3[u] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc.w2[u] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc.w1[u] = f4{0.f, 0.f, 0.f, 0.f};
+    acc.b3 = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc.b2[t] = acc.b1[t] = 0.f;
+}
+
+__device__ __forceinline__ f4 transpose16(const f4 x) {
+    const int lane = __lane_id(), c = lane & 15, q = lane >> 4;
+    f4 r = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) r = mma(x[v], c == 4 * q + v ? 1.f : 0.f, r);
+    return r;
+}
+
+// four consecutive Gaussians g.. of feature row `row`; columns at or past n are scratch: zero
+__device__ __forceinline__ f4 load_g4(const float *rows, int64_t ld, int row, int64_t g, int64_t n) {
+    f4 v = *reinterpret_cast<const f4 *>(rows + (int64_t)row * ld + g);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = g + s < n ? v[s] : 0.f;
+    return v;
+}
+
+// adds the 16 Gaussians from g16 (g16 < n); D, G, H: the A tiles of dOut, dh2 and dh1
+__device__ __forceinline__ void wgrad_block(WAcc &acc, const f4 &D, const f4 (&G)[4], const f4 (&H)[4],
+                                            const float *rows, int64_t ld, int64_t g16, int64_t n) {
+    const int lane = __lane_id(), m = lane & 15, kq = lane >> 4;
+    const int64_t g = g16 + 4 * kq;
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) {
+        const f4 h2 = load_g4(rows, ld, R_H2 + 16 * tj + m, g, n);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc.w3[tj] = mma(D[s], h2[s], acc.w3[tj]);
+    }
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) {
+        const f4 h1 = load_g4(rows, ld, R_H1 + 16 * tj + m, g, n);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti) acc.w2[4 * ti + tj] = mma(G[ti][s], h1[s], acc.w2[4 * ti + tj]);
+    }
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) {
+        const f4 en = load_g4(rows, ld, R_ENC + 16 * tj + m, g, n);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti) acc.w1[2 * ti + tj] = mma(H[ti][s], en[s], acc.w1[2 * ti + tj]);
+    }
+    acc.b3 += (D[0] + D[1]) + (D[2] + D[3]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        acc.b2[t] += (G[t][0] + G[t][1]) + (G[t][2] + G[t][3]);
+        acc.b1[t] += (H[t][0] + H[t][1]) + (H[t][2] + H[t][3]);
+    }
+}
+
+// The workgroup's sums, waves added in order in LDS (red: WG_NE floats), written to its slots
+// of the three partial arrays ([group][WG_NE3], then [group][WG_NE2], then [group][WG_NE1]),
+// each laid out as C[row][col] then the column sums of the deltas.  ngroups: the grid size.
+__device__ __forceinline__ void wgrad_finish(WAcc &acc, float *red, float *partial, int ngroups) {
+    const int w = threadIdx.x >> 6, lane = __lane_id(), m = lane & 15, kq = lane >> 4;
+    // the bias sums of the four lane groups
+    acc.b3 += __shfl_xor(acc.b3, 16, kWave);
+    acc.b3 += __shfl_xor(acc.b3, 32, kWave);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        acc.b2[t] += __shfl_xor(acc.b2[t], 16, kWave);
+        acc.b2[t] += __shfl_xor(acc.b2[t], 32, kWave);
+        acc.b1[t] += __shfl_xor(acc.b1[t], 16, kWave);
+        acc.b1[t] += __shfl_xor(acc.b1[t], 32, kWave);
+    }
+    float *r3 = red, *r2 = red + WG_NE3, *r1 = red + WG_NE3 + WG_NE2;
+    for (int wv = 0; wv < 4; ++wv) {
+        if (w == wv) {
+            auto put = [&](float *d, int i, float v) { d[i] = wv == 0 ? v : d[i] + v; };
+#pragma unroll
+            for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 4 * kq + i;
+                    if (row < 12) put(r3, row * NH + 16 * tj + m, acc.w3[tj][i]);
+                }
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) put(r2, (16 * ti + 4 * kq + i) * NH + 16 * tj + m, acc.w2[4 * ti + tj][i]);
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) put(r1, (16 * ti + 4 * kq + i) * ND + 16 * tj + m, acc.w1[2 * ti + tj][i]);
+            if (kq == 0) {
+                if (m < 12) put(r3, 12 * NH + m, acc.b3);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    put(r2, NH * NH + 16 * t + m, acc.b2[t]);
+                    put(r1, NH * ND + 16 * t + m, acc.b1[t]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float *p3 = partial + (int64_t)blockIdx.x * WG_NE3;
+    float *p2 = partial + (int64_t)ngroups * WG_NE3 + (int64_t)blockIdx.x * WG_NE2;
+    float *p1 = partial + (int64_t)ngroups * (WG_NE3 + WG_NE2) + (int64_t)blockIdx.x * WG_NE1;
+    for (int i = threadIdx.x; i < WG_NE3; i += blockDim.x) p3[i] = r3[i];
+    for (int i = threadIdx.x; i < WG_NE2; i += blockDim.x) p2[i] = r2[i];
+    for (int i = threadIdx.x; i < WG_NE1; i += blockDim.x) p1[i] = r1[i];
+}
+
 template <int MODE> struct __align__(16) BwdSmem { WFwd f; WBwd b; };
 template <> struct __align__(16) BwdSmem<2> { WBwd b; };
 
@@ -528,25 +667,45 @@ template <> struct __align__(16) BwdSmem<2> { WBwd b; };
 // dEc[level][Gaussian] for the indexed reduction; MODE 2: as 1, with the forward's values
 // read from the rows stored by the training forward instead of evaluated again (modes 0
 // and 1 evaluate the field of the block and store the rows first).  Blocks of 32 Gaussians
-// per wave in mode 2 (four waves per SIMD), 64 when the field is evaluated too.
-template <int MODE, int FJ = MODE == 2 ? 2 : 4, int FB = 16 * FJ>
+// per wave in mode 2, 64 when the field is evaluated too.  Modes 0 and 1 store the deltas in
+// the rows for wgrad_kernel; mode 2 adds the weight gradients itself from the registers, over
+// the same blocks in the same order, into its workgroup's partial sums (partial).
+template <int MODE, int FJ = MODE == 2 ? WG_FJ : 4, int FB = 16 * FJ>
 __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float *mean, int64_t n, const float2 *tables,
                                                       const float *w1, const float *b1, const float *w2,
                                                       const float *b2, const float *w3, const float *b3,
                                                       const float *dquat, const float *dscale, const float *dopac,
-                                                      const float *dcolor, float *dtables, float *rows, float2 *dEc) {
+                                                      const float *dcolor, float *dtables, float *rows, float2 *dEc,
+                                                      float *partial) {
     __shared__ BwdSmem<MODE> S;
     if constexpr (MODE != 2) load_fwd(S.f, w1, b1, w2, b2, w3, b3, 2 * a.levels);
     load_bwd(S.b, w1, w2, w3, 2 * a.levels);
     __syncthreads();
     const int lane = __lane_id(), c = lane & 15, q = lane >> 4;
     const int64_t nblk = (n + FB - 1) / FB;
+    WAcc acc;
+    if constexpr (MODE == 2) wacc_zero(acc);
     for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nblk; b += (int64_t)gridDim.x * 4) {
         const int64_t g0 = FB * b;
         if constexpr (MODE != 2)
             field_block<FJ, true, false>(a, tables, S.f, mean, n, g0, nullptr, nullptr, nullptr, nullptr, rows);
-        f4 dE[2][FJ];
-        adjoint_block<FJ>(a, S.b, n, g0, dquat, dscale, dopac, dcolor, rows, dE);
+        f4 dE[2][FJ], D[FJ], G[4][FJ], H[4][FJ];
+        adjoint_block<FJ, MODE != 2>(a, S.b, n, g0, dquat, dscale, dopac, dcolor, rows, dE, D, G, H);
+        if constexpr (MODE == 2) {
+            const int64_t ld = row_ld(n);
+#pragma unroll
+            for (int j = 0; j < FJ; ++j) {
+                const int64_t g16 = g0 + 16 * j;
+                if (g16 >= n) continue;  // wave-uniform
+                f4 tg[4], th[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    tg[t] = transpose16(G[t][j]);
+                    th[t] = transpose16(H[t][j]);
+                }
+                wgrad_block(acc, transpose16(D[j]), tg, th, rows, ld, g16, n);
+            }
+        }
         if constexpr (MODE != 0) {
 #pragma unroll
             for (int t = 0; t < 2; ++t)
@@ -591,114 +750,38 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
             }
         }
     }
+    if constexpr (MODE == 2) {
+        __syncthreads();  // the weights in LDS are no longer read: their space takes the sums
+        wgrad_finish(acc, reinterpret_cast<float *>(&S), partial, (int)gridDim.x);
+    }
 }
 
-// C[MA][NB] = sum_r A_r[i] B_r[j] and s[MA] = sum_r A_r[i] over the Gaussians r of a chunk
-// range, A_r[i] = rows[(aoff + i) * ld + r], B_r[j] = rows[(boff + j) * ld + r]: a dense
-// contraction over the Gaussians, run on the matrix cores (v_mfma_f32_16x16x4f32, FP32
-// products and sums).  Each workgroup sums its own range (a multiple of 4 Gaussians long, so
-// every 16-byte load is aligned): 64 Gaussians at a time are staged in LDS, feature-major as
-// in memory, with 16-byte loads of 4 consecutive Gaussians.  C is cut into 16 x 16 tiles
-// (A's rows padded to a multiple of 16 with zeros), each owned by one wave; per step a lane
-// reads the 4 Gaussians (4 (lane / 16) + 0..3 of a group of 16) of its A row lane % 16 and
-// B column lane % 16 with one 16-byte LDS read each, and four MFMAs take them as the k
-// index.  The column sums of A are kept by the loading threads, whose features and Gaussian
-// offsets are the same in every batch.
-constexpr int ATB_AR = 64;
-
-typedef float atb_f4 __attribute__((ext_vector_type(4)));
-
-template <int MA, int NB>
-__global__ __launch_bounds__(256) void atb_kernel(const float *rows, int64_t n, int aoff, int boff, float *partial) {
-    constexpr int MP = (MA + 15) / 16 * 16;       // A rows padded to whole tiles
-    constexpr int TI = MP / 16, TJ = NB / 16;      // tiles of C
-    constexpr int TPW = TI * TJ / 4;               // tiles per wave
-    constexpr int KQ = ATB_AR / 4;                 // 16-byte quads per feature and batch
-    constexpr int SR = ATB_AR + 4;                 // padded LDS feature row (floats)
-    constexpr int LA = (MA * KQ + 255) / 256;      // A quads each thread loads per batch
-    constexpr int LB = (NB * KQ + 255) / 256;
-    static_assert(NB % 16 == 0 && (TI * TJ) % 4 == 0 && 256 % KQ == 0 && ATB_AR % 16 == 0, "atb tile shape");
-    __shared__ __align__(16) float sa[MA * SR], sb[NB * SR];
-    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    const int lk = t % KQ, lf = t / KQ;  // loader: quad lk of features lf + (256 / KQ) m
-    const int64_t ld = row_ld(n);
-    atb_f4 acc[TPW];
+// The weight gradients of modes 0 and 1 from the deltas they stored in the rows: the saved
+// mode's blocks (16 WG_FJ Gaussians per wave step, the same grid), order and arithmetic.
+__global__ __launch_bounds__(256, 2) void wgrad_kernel(const float *rows, int64_t n, float *partial) {
+    __shared__ float red[WG_NE];
+    const int lane = __lane_id(), m = lane & 15, kq = lane >> 4;
+    const int64_t ld = row_ld(n), nblk = (n + 16 * WG_FJ - 1) / (16 * WG_FJ);
+    WAcc acc;
+    wacc_zero(acc);
+    for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nblk; b += (int64_t)gridDim.x * 4) {
 #pragma unroll
-    for (int u = 0; u < TPW; ++u) acc[u] = atb_f4{0.f, 0.f, 0.f, 0.f};
-    float cs[LA];
+        for (int j = 0; j < WG_FJ; ++j) {
+            const int64_t g16 = 16 * WG_FJ * b + 16 * j;
+            if (g16 >= n) continue;  // wave-uniform
+            const int64_t g = g16 + 4 * kq;
+            f4 d = f4{0.f, 0.f, 0.f, 0.f}, tg[4], th[4];
+            if (m < 12) d = load_g4(rows, ld, R_DOUT + m, g, n);
 #pragma unroll
-    for (int m = 0; m < LA; ++m) cs[m] = 0.f;
-    const int64_t per = ((n + gridDim.x - 1) / gridDim.x + 3) & ~(int64_t)3;
-    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = r0 + per < n ? r0 + per : n;
-    for (int64_t base = r0; base < r1; base += ATB_AR) {
-        const int cnt = (int)(r1 - base < ATB_AR ? r1 - base : ATB_AR);
-        const int r = 4 * lk;
-        // a quad that starts at or past cnt is zero; one that straddles it is masked
-        auto quad = [&](int f) {
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (r < cnt) {
-                v = *reinterpret_cast<const float4 *>(rows + (int64_t)f * ld + base + r);
-                if (r + 1 >= cnt) v.y = 0.f;
-                if (r + 2 >= cnt) v.z = 0.f;
-                if (r + 3 >= cnt) v.w = 0.f;
+            for (int t = 0; t < 4; ++t) {
+                tg[t] = load_g4(rows, ld, R_DH2 + 16 * t + m, g, n);
+                th[t] = load_g4(rows, ld, R_DH1 + 16 * t + m, g, n);
             }
-            return v;
-        };
-#pragma unroll
-        for (int m = 0; m < LA; ++m) {
-            const int f = lf + (256 / KQ) * m;
-            if (f < MA) {
-                const float4 v = quad(aoff + f);
-                cs[m] += (v.x + v.y) + (v.z + v.w);
-                *reinterpret_cast<float4 *>(sa + f * SR + r) = v;
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < LB; ++m) {
-            const int f = lf + (256 / KQ) * m;
-            if (f < NB) *reinterpret_cast<float4 *>(sb + f * SR + r) = quad(boff + f);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kg = 0; kg < ATB_AR / 16; ++kg) {
-            const int gr = kg * 16 + 4 * (lane >> 4);  // this lane's 4 Gaussians of the group
-#pragma unroll
-            for (int u = 0; u < TPW; ++u) {
-                const int tile = w * TPW + u, ti = tile / TJ, tj = tile - ti * TJ;
-                const int fa = ti * 16 + (lane & 15), fb = tj * 16 + (lane & 15);
-                float4 av = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (MP == MA || fa < MA) av = *reinterpret_cast<const float4 *>(sa + fa * SR + gr);
-                const float4 bv = *reinterpret_cast<const float4 *>(sb + fb * SR + gr);
-                acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc[u], 0, 0, 0);
-                acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc[u], 0, 0, 0);
-                acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, acc[u], 0, 0, 0);
-                acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, acc[u], 0, 0, 0);
-            }
-        }
-        __syncthreads();
-    }
-    constexpr int NE = MA * NB + MA;
-    float *out = partial + (int64_t)blockIdx.x * NE;
-    // column sums: the KQ loaders of a feature are consecutive lanes of one wave
-#pragma unroll
-    for (int m = 0; m < LA; ++m) {
-        float s = cs[m];
-#pragma unroll
-        for (int o = KQ / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, KQ);
-        const int f = lf + (256 / KQ) * m;
-        if (lk == 0 && f < MA) out[MA * NB + f] = s;
-    }
-    // accumulator element i of a lane is C[16 ti + 4 (lane / 16) + i][16 tj + lane % 16]
-#pragma unroll
-    for (int u = 0; u < TPW; ++u) {
-        const int tile = w * TPW + u, ti = tile / TJ, tj = tile - ti * TJ;
-        const int col = tj * 16 + (lane & 15);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = ti * 16 + 4 * (lane >> 4) + i;
-            if (MP == MA || row < MA) out[row * NB + col] = acc[u][i];
+            wgrad_block(acc, d, tg, th, rows, ld, g16, n);
         }
     }
+    __syncthreads();
+    wgrad_finish(acc, red, partial, (int)gridDim.x);
 }
 
 // out[e] += sum over workgroups of partial[g][e], in float64 and a fixed order (four
@@ -1033,7 +1116,7 @@ WsLayout ws_layout(int64_t n) {
     int64_t ntiles = (int64_t)NL * ((8 * n + GT_TILE - 1) / GT_TILE);
     size_t o = 0;
     W.rows = o; o = al256(o + (size_t)row_ld(n) * R_LEN * sizeof(float));
-    W.partial = o; o = al256(o + (size_t)ATB_GROUPS * (NH * NH + NH) * sizeof(float));
+    W.partial = o; o = al256(o + (size_t)ATB_GROUPS * WG_NE * sizeof(float));
     W.dec = o; o = al256(o + (size_t)NL * n * sizeof(float2));
     W.carry_head = o; o = al256(o + (size_t)ntiles * sizeof(double2));
     W.carry_tail = o; o = al256(o + (size_t)ntiles * sizeof(double2));
@@ -1091,28 +1174,29 @@ int launch_ngp_index_build(const splat_ngp &m, const float *mean, int64_t n, voi
 namespace {
 // weight gradients: dW3 = sum dOut^T h2 (11 x 64, dOut padded to 12), dW2 = sum dh2^T h1,
 // dW1 = sum dh1^T enc (enc padded to 32 columns); biases are the column sums of the deltas
-int launch_atb_jobs(const splat_ngp &m, int64_t n, float *rows, float *partial, float *dw1, float *db1, float *dw2,
-                    float *db2, float *dw3, float *db3, hipStream_t st) {
-    const int din = 2 * m.levels;
-    int rc;
-    auto reduce = [&](int ma, int nb, int mreal, int dinw, float *dw, float *db) {
+// the weight gradients from the partials of the ng workgroups of the saved adjoint or of
+// wgrad_kernel: dW3 (11 x 64), dW2 (64 x 64), dW1 (64 x 2 levels) and the biases
+int launch_wgrad_reduce(const splat_ngp &m, int ng, float *partial, float *dw1, float *db1, float *dw2, float *db2,
+                        float *dw3, float *db3, hipStream_t st) {
+    auto reduce = [&](const float *part, int ma, int nb, int mreal, int dinw, float *dw, float *db) {
         int ne = ma * nb + ma;
-        hipLaunchKernelGGL(atb_reduce_kernel, dim3((unsigned)((ne + 63) / 64)), dim3(256), 0, st, partial, ATB_GROUPS,
-                           ma, nb, mreal, dinw, dw, db);
-        return launch_status("ngp_atb_reduce");
+        hipLaunchKernelGGL(atb_reduce_kernel, dim3((unsigned)((ne + 63) / 64)), dim3(256), 0, st, part, ng, ma, nb,
+                           mreal, dinw, dw, db);
+        return launch_status("ngp_wgrad_reduce");
     };
-    hipLaunchKernelGGL((atb_kernel<12, NH>), dim3(ATB_GROUPS), dim3(256), 0, st, rows, n, (int)R_DOUT, (int)R_H2,
-                       partial);
-    if ((rc = launch_status("ngp_atb"))) return rc;
-    if ((rc = reduce(12, NH, NO, NH, dw3, db3))) return rc;
-    hipLaunchKernelGGL((atb_kernel<NH, NH>), dim3(ATB_GROUPS), dim3(256), 0, st, rows, n, (int)R_DH2, (int)R_H1,
-                       partial);
-    if ((rc = launch_status("ngp_atb"))) return rc;
-    if ((rc = reduce(NH, NH, NH, NH, dw2, db2))) return rc;
-    hipLaunchKernelGGL((atb_kernel<NH, ND>), dim3(ATB_GROUPS), dim3(256), 0, st, rows, n, (int)R_DH1, (int)R_ENC,
-                       partial);
-    if ((rc = launch_status("ngp_atb"))) return rc;
-    return reduce(NH, ND, NH, din, dw1, db1);
+    int rc;
+    if ((rc = reduce(partial, 12, NH, NO, NH, dw3, db3))) return rc;
+    if ((rc = reduce(partial + (int64_t)ng * WG_NE3, NH, NH, NH, NH, dw2, db2))) return rc;
+    return reduce(partial + (int64_t)ng * (WG_NE3 + WG_NE2), NH, ND, NH, 2 * m.levels, dw1, db1);
+}
+
+int launch_wgrad(const splat_ngp &m, int64_t n, float *rows, float *partial, float *dw1, float *db1, float *dw2,
+                 float *db2, float *dw3, float *db3, hipStream_t st) {
+    const int ng = (int)field_groups(n, 16 * WG_FJ);  // the saved adjoint's grid
+    hipLaunchKernelGGL(wgrad_kernel, dim3((unsigned)ng), dim3(256), 0, st, rows, n, partial);
+    int rc = launch_status("ngp_wgrad");
+    if (rc) return rc;
+    return launch_wgrad_reduce(m, ng, partial, dw1, db1, dw2, db2, dw3, db3, st);
 }
 }  // namespace
 
@@ -1129,14 +1213,15 @@ int ngp_bwd_via_index(const splat_ngp &m, const float *mean, int64_t n, const vo
     const IndexLayout I = index_layout(m.levels, m.log2_table, n);
     float *rows = ws_at<float>(ws, W.rows);
     float2 *dEc = ws_at<float2>(ws, W.dec);
-    const int64_t nb = field_groups(n, saved ? 32 : 64);
+    const int64_t nb = field_groups(n, saved ? 16 * WG_FJ : 64);
     const float2 *tab = reinterpret_cast<const float2 *>(m.tables);
+    float *partial = ws_at<float>(ws, W.partial);
     if (saved)
         hipLaunchKernelGGL(ngp_bwd_kernel<2>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n, tab, m.w1, m.b1,
-                           m.w2, m.b2, m.w3, m.b3, dquat, dscale, dopac, dcolor, dtables, rows, dEc);
+                           m.w2, m.b2, m.w3, m.b3, dquat, dscale, dopac, dcolor, dtables, rows, dEc, partial);
     else
         hipLaunchKernelGGL(ngp_bwd_kernel<1>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n, tab, m.w1, m.b1,
-                           m.w2, m.b2, m.w3, m.b3, dquat, dscale, dopac, dcolor, dtables, rows, dEc);
+                           m.w2, m.b2, m.w3, m.b3, dquat, dscale, dopac, dcolor, dtables, rows, dEc, nullptr);
     int rc = launch_status("ngp_bwd");
     if (rc) return rc;
     void *ix = const_cast<void *>(index);
@@ -1150,7 +1235,8 @@ int ngp_bwd_via_index(const splat_ngp &m, const float *mean, int64_t n, const vo
     hipLaunchKernelGGL(ngp_fixup_kernel, dim3((unsigned)fb), dim3(256), 0, st, a.T, I.tpl, I.ntiles, ent_g, seg_row,
                        tile_seg, ws_at<uint32_t>(ix, I.tile_nh), ch, ct, dtables);
     if ((rc = launch_status("ngp_fixup"))) return rc;
-    return launch_atb_jobs(m, n, rows, ws_at<float>(ws, W.partial), dw1, db1, dw2, db2, dw3, db3, st);
+    if (saved) return launch_wgrad_reduce(m, (int)nb, partial, dw1, db1, dw2, db2, dw3, db3, st);
+    return launch_wgrad(m, n, rows, partial, dw1, db1, dw2, db2, dw3, db3, st);
 }
 
 int ngp_fwd(const splat_ngp &m, const float *mean, int64_t n, float *quat, float *scale, float *opac, float *color,
@@ -1203,10 +1289,10 @@ int launch_ngp_bwd(const splat_ngp &m, const float *mean, int64_t n, const float
     const int64_t nb = field_groups(n, 64);
     hipLaunchKernelGGL(ngp_bwd_kernel<0>, dim3((unsigned)nb), dim3(256), 0, st, a, mean, n,
                        reinterpret_cast<const float2 *>(m.tables), m.w1, m.b1, m.w2, m.b2, m.w3, m.b3, dquat, dscale,
-                       dopac, dcolor, dtables, rows, nullptr);
+                       dopac, dcolor, dtables, rows, nullptr, nullptr);
     int rc = launch_status("ngp_bwd");
     if (rc) return rc;
-    return launch_atb_jobs(m, n, rows, ws_at<float>(ws, W.partial), dw1, db1, dw2, db2, dw3, db3, st);
+    return launch_wgrad(m, n, rows, ws_at<float>(ws, W.partial), dw1, db1, dw2, db2, dw3, db3, st);
 }
 
 }  // namespace splat
