@@ -197,9 +197,15 @@ def test_ngp_indexed_backward_at_two_million_gaussians():
     _bwd(model, xs, dd, ws, gw, index)
     torch.cuda.synchronize()
     a = gi["tables"].cpu().numpy()
-    ok, err = rel_close(a, gs["tables"].cpu().numpy(), 1e-4)
-    say(f"  tables vs atomics: {err:.2e}")
+    b = gs["tables"].cpu().numpy()
+    # the atomic path adds up to 9,000 float32 terms per row in an order that varies between runs
+    # (worst case k u = 5.4e-4 of the row's absolute-term sum): element-wise the parity metric,
+    # over the whole tensor 1e-4
+    ok, err = rel_close(a, b, 1e-3)
+    tens = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    say(f"  tables vs atomics: {err:.2e} (tensor {tens:.2e})")
     assert ok, err
+    assert tens <= 1e-4, tens
     assert np.array_equal(gb.cpu().numpy(), base.cpu().numpy() + a)
     for k in ("w1", "b1", "w2", "b2", "w3", "b3"):
         assert torch.equal(gi[k], gs[k]), k
