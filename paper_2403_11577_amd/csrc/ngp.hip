@@ -568,44 +568,53 @@ __device__ __forceinline__ f4 load_g4(const float *rows, int64_t ld, int row, in
     return v;
 }
 
-// adds the 16 Gaussians from g16 (g16 < n); D, G, H: the A tiles of dOut, dh2 and dh1
+// adds the 16 Gaussians from g16 (g16 < n); D, G, H: the A tiles of dOut, dh2 and dh1.
+// MASK selects the products (1: dW3, 2: dW2, 4: dW1); a tile's sum depends only on its own
+// sequence of MFMAs, so any selection gives the same values for the products it forms.
+template <int MASK>
 __device__ __forceinline__ void wgrad_block(WAcc &acc, const f4 &D, const f4 (&G)[4], const f4 (&H)[4],
                                             const float *rows, int64_t ld, int64_t g16, int64_t n) {
     const int lane = __lane_id(), m = lane & 15, kq = lane >> 4;
     const int64_t g = g16 + 4 * kq;
+    if constexpr ((MASK & 1) != 0) {
 #pragma unroll
-    for (int tj = 0; tj < 4; ++tj) {
-        const f4 h2 = load_g4(rows, ld, R_H2 + 16 * tj + m, g, n);
+        for (int tj = 0; tj < 4; ++tj) {
+            const f4 h2 = load_g4(rows, ld, R_H2 + 16 * tj + m, g, n);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc.w3[tj] = mma(D[s], h2[s], acc.w3[tj]);
+            for (int s = 0; s < 4; ++s) acc.w3[tj] = mma(D[s], h2[s], acc.w3[tj]);
+        }
+        acc.b3 += (D[0] + D[1]) + (D[2] + D[3]);
     }
+    if constexpr ((MASK & 2) != 0) {
 #pragma unroll
-    for (int tj = 0; tj < 4; ++tj) {
-        const f4 h1 = load_g4(rows, ld, R_H1 + 16 * tj + m, g, n);
+        for (int tj = 0; tj < 4; ++tj) {
+            const f4 h1 = load_g4(rows, ld, R_H1 + 16 * tj + m, g, n);
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+            for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int ti = 0; ti < 4; ++ti) acc.w2[4 * ti + tj] = mma(G[ti][s], h1[s], acc.w2[4 * ti + tj]);
+                for (int ti = 0; ti < 4; ++ti) acc.w2[4 * ti + tj] = mma(G[ti][s], h1[s], acc.w2[4 * ti + tj]);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc.b2[t] += (G[t][0] + G[t][1]) + (G[t][2] + G[t][3]);
     }
+    if constexpr ((MASK & 4) != 0) {
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj) {
-        const f4 en = load_g4(rows, ld, R_ENC + 16 * tj + m, g, n);
+        for (int tj = 0; tj < 2; ++tj) {
+            const f4 en = load_g4(rows, ld, R_ENC + 16 * tj + m, g, n);
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+            for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int ti = 0; ti < 4; ++ti) acc.w1[2 * ti + tj] = mma(H[ti][s], en[s], acc.w1[2 * ti + tj]);
-    }
-    acc.b3 += (D[0] + D[1]) + (D[2] + D[3]);
+                for (int ti = 0; ti < 4; ++ti) acc.w1[2 * ti + tj] = mma(H[ti][s], en[s], acc.w1[2 * ti + tj]);
+        }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        acc.b2[t] += (G[t][0] + G[t][1]) + (G[t][2] + G[t][3]);
-        acc.b1[t] += (H[t][0] + H[t][1]) + (H[t][2] + H[t][3]);
+        for (int t = 0; t < 4; ++t) acc.b1[t] += (H[t][0] + H[t][1]) + (H[t][2] + H[t][3]);
     }
 }
 
 // The workgroup's sums, waves added in order in LDS (red: WG_NE floats), written to its slots
 // of the three partial arrays ([group][WG_NE3], then [group][WG_NE2], then [group][WG_NE1]),
 // each laid out as C[row][col] then the column sums of the deltas.  ngroups: the grid size.
+template <int MASK>
 __device__ __forceinline__ void wgrad_finish(WAcc &acc, float *red, float *partial, int ngroups) {
     const int w = threadIdx.x >> 6, lane = __lane_id(), m = lane & 15, kq = lane >> 4;
     // the bias sums of the four lane groups
@@ -622,32 +631,39 @@ __device__ __forceinline__ void wgrad_finish(WAcc &acc, float *red, float *parti
     for (int wv = 0; wv < 4; ++wv) {
         if (w == wv) {
             auto put = [&](float *d, int i, float v) { d[i] = wv == 0 ? v : d[i] + v; };
-#pragma unroll
-            for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int row = 4 * kq + i;
-                    if (row < 12) put(r3, row * NH + 16 * tj + m, acc.w3[tj][i]);
-                }
-#pragma unroll
-            for (int ti = 0; ti < 4; ++ti)
+            if constexpr ((MASK & 1) != 0) {
 #pragma unroll
                 for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) put(r2, (16 * ti + 4 * kq + i) * NH + 16 * tj + m, acc.w2[4 * ti + tj][i]);
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = 4 * kq + i;
+                        if (row < 12) put(r3, row * NH + 16 * tj + m, acc.w3[tj][i]);
+                    }
+                if (kq == 0 && m < 12) put(r3, 12 * NH + m, acc.b3);
+            }
+            if constexpr ((MASK & 2) != 0) {
 #pragma unroll
-            for (int ti = 0; ti < 4; ++ti)
+                for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
-                for (int tj = 0; tj < 2; ++tj)
+                    for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) put(r1, (16 * ti + 4 * kq + i) * ND + 16 * tj + m, acc.w1[2 * ti + tj][i]);
-            if (kq == 0) {
-                if (m < 12) put(r3, 12 * NH + m, acc.b3);
+                        for (int i = 0; i < 4; ++i)
+                            put(r2, (16 * ti + 4 * kq + i) * NH + 16 * tj + m, acc.w2[4 * ti + tj][i]);
+                if (kq == 0)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    put(r2, NH * NH + 16 * t + m, acc.b2[t]);
-                    put(r1, NH * ND + 16 * t + m, acc.b1[t]);
-                }
+                    for (int t = 0; t < 4; ++t) put(r2, NH * NH + 16 * t + m, acc.b2[t]);
+            }
+            if constexpr ((MASK & 4) != 0) {
+#pragma unroll
+                for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            put(r1, (16 * ti + 4 * kq + i) * ND + 16 * tj + m, acc.w1[2 * ti + tj][i]);
+                if (kq == 0)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) put(r1, NH * ND + 16 * t + m, acc.b1[t]);
             }
         }
         __syncthreads();
@@ -655,9 +671,12 @@ __device__ __forceinline__ void wgrad_finish(WAcc &acc, float *red, float *parti
     float *p3 = partial + (int64_t)blockIdx.x * WG_NE3;
     float *p2 = partial + (int64_t)ngroups * WG_NE3 + (int64_t)blockIdx.x * WG_NE2;
     float *p1 = partial + (int64_t)ngroups * (WG_NE3 + WG_NE2) + (int64_t)blockIdx.x * WG_NE1;
-    for (int i = threadIdx.x; i < WG_NE3; i += blockDim.x) p3[i] = r3[i];
-    for (int i = threadIdx.x; i < WG_NE2; i += blockDim.x) p2[i] = r2[i];
-    for (int i = threadIdx.x; i < WG_NE1; i += blockDim.x) p1[i] = r1[i];
+    if constexpr ((MASK & 1) != 0)
+        for (int i = threadIdx.x; i < WG_NE3; i += blockDim.x) p3[i] = r3[i];
+    if constexpr ((MASK & 2) != 0)
+        for (int i = threadIdx.x; i < WG_NE2; i += blockDim.x) p2[i] = r2[i];
+    if constexpr ((MASK & 4) != 0)
+        for (int i = threadIdx.x; i < WG_NE1; i += blockDim.x) p1[i] = r1[i];
 }
 
 template <int MODE> struct __align__(16) BwdSmem { WFwd f; WBwd b; };
@@ -703,7 +722,7 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
                     tg[t] = transpose16(G[t][j]);
                     th[t] = transpose16(H[t][j]);
                 }
-                wgrad_block(acc, transpose16(D[j]), tg, th, rows, ld, g16, n);
+                wgrad_block<7>(acc, transpose16(D[j]), tg, th, rows, ld, g16, n);
             }
         }
         if constexpr (MODE != 0) {
@@ -752,13 +771,15 @@ __global__ __launch_bounds__(256, 2) void ngp_bwd_kernel(NgpArgs a, const float 
     }
     if constexpr (MODE == 2) {
         __syncthreads();  // the weights in LDS are no longer read: their space takes the sums
-        wgrad_finish(acc, reinterpret_cast<float *>(&S), partial, (int)gridDim.x);
+        wgrad_finish<7>(acc, reinterpret_cast<float *>(&S), partial, (int)gridDim.x);
     }
 }
 
 // The weight gradients of modes 0 and 1 from the deltas they stored in the rows: the saved
-// mode's blocks (16 WG_FJ Gaussians per wave step, the same grid), order and arithmetic.
-__global__ __launch_bounds__(256, 2) void wgrad_kernel(const float *rows, int64_t n, float *partial) {
+// mode's blocks (16 WG_FJ Gaussians per wave step, the same grid), order and arithmetic, one
+// product per launch (MASK 1, 2 or 4: fewer accumulators, more waves).
+template <int MASK>
+__global__ __launch_bounds__(256, 3) void wgrad_kernel(const float *rows, int64_t n, float *partial) {
     __shared__ float red[WG_NE];
     const int lane = __lane_id(), m = lane & 15, kq = lane >> 4;
     const int64_t ld = row_ld(n), nblk = (n + 16 * WG_FJ - 1) / (16 * WG_FJ);
@@ -771,17 +792,17 @@ __global__ __launch_bounds__(256, 2) void wgrad_kernel(const float *rows, int64_
             if (g16 >= n) continue;  // wave-uniform
             const int64_t g = g16 + 4 * kq;
             f4 d = f4{0.f, 0.f, 0.f, 0.f}, tg[4], th[4];
-            if (m < 12) d = load_g4(rows, ld, R_DOUT + m, g, n);
+            if ((MASK & 1) != 0 && m < 12) d = load_g4(rows, ld, R_DOUT + m, g, n);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                tg[t] = load_g4(rows, ld, R_DH2 + 16 * t + m, g, n);
-                th[t] = load_g4(rows, ld, R_DH1 + 16 * t + m, g, n);
+                tg[t] = (MASK & 2) != 0 ? load_g4(rows, ld, R_DH2 + 16 * t + m, g, n) : f4{0.f, 0.f, 0.f, 0.f};
+                th[t] = (MASK & 4) != 0 ? load_g4(rows, ld, R_DH1 + 16 * t + m, g, n) : f4{0.f, 0.f, 0.f, 0.f};
             }
-            wgrad_block(acc, d, tg, th, rows, ld, g16, n);
+            wgrad_block<MASK>(acc, d, tg, th, rows, ld, g16, n);
         }
     }
     __syncthreads();
-    wgrad_finish(acc, red, partial, (int)gridDim.x);
+    wgrad_finish<MASK>(acc, red, partial, (int)gridDim.x);
 }
 
 // out[e] += sum over workgroups of partial[g][e], in float64 and a fixed order (four
@@ -1193,7 +1214,9 @@ int launch_wgrad_reduce(const splat_ngp &m, int ng, float *partial, float *dw1, 
 int launch_wgrad(const splat_ngp &m, int64_t n, float *rows, float *partial, float *dw1, float *db1, float *dw2,
                  float *db2, float *dw3, float *db3, hipStream_t st) {
     const int ng = (int)field_groups(n, 16 * WG_FJ);  // the saved adjoint's grid
-    hipLaunchKernelGGL(wgrad_kernel, dim3((unsigned)ng), dim3(256), 0, st, rows, n, partial);
+    hipLaunchKernelGGL(wgrad_kernel<1>, dim3((unsigned)ng), dim3(256), 0, st, rows, n, partial);
+    hipLaunchKernelGGL(wgrad_kernel<2>, dim3((unsigned)ng), dim3(256), 0, st, rows, n, partial);
+    hipLaunchKernelGGL(wgrad_kernel<4>, dim3((unsigned)ng), dim3(256), 0, st, rows, n, partial);
     int rc = launch_status("ngp_wgrad");
     if (rc) return rc;
     return launch_wgrad_reduce(m, ng, partial, dw1, db1, dw2, db2, dw3, db3, st);
