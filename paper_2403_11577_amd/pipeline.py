@@ -210,14 +210,36 @@ class Grads:
 
 
 def alloc_grads(ds: DeviceScene, with_mean=False) -> Grads:
+    """Gradient buffers as views of one float32 and one float64 allocation (each view 256-byte
+    aligned), so that zero_grads clears them with two fills."""
     dev = ds.opacity.device
     G, V, Cn = ds.n_gauss, ds.n_views, ds.n_cams
-    z = lambda *s, dt=torch.float32: torch.zeros(s, dtype=dt, device=dev)
-    return Grads(z(4, G), z(3, G), z(G), z(3, G), z(3, G) if with_mean else None,
-                 z(V, 12, dt=torch.float64), z(Cn, 6, dt=torch.float64), z(Cn, dt=torch.float64))
+    pad = lambda k, q: -(-k // q) * q
+    Gp = pad(G, 64)
+    rows32 = [4, 3, 1, 3] + ([3] if with_mean else [])
+    f32 = torch.zeros(Gp * sum(rows32), dtype=torch.float32, device=dev)
+    views, o = [], 0
+    for r in rows32:
+        views.append(f32[o:o + r * G].view(r, G) if r > 1 else f32[o:o + G])
+        o += r * Gp
+    n64 = [V * 12, Cn * 6, Cn]
+    f64 = torch.zeros(sum(pad(k, 32) for k in n64), dtype=torch.float64, device=dev)
+    o, v64 = 0, []
+    for k in n64:
+        v64.append(f64[o:o + k])
+        o += pad(k, 32)
+    gr = Grads(views[0], views[1], views[2], views[3], views[4] if with_mean else None,
+               v64[0].view(V, 12), v64[1].view(Cn, 6), v64[2])
+    gr._flat = (f32, f64)
+    return gr
 
 
 def zero_grads(gr: Grads):
+    flat = getattr(gr, "_flat", None)
+    if flat is not None:
+        for t in flat:
+            t.zero_()
+        return
     for f in dataclasses.fields(gr):
         t = getattr(gr, f.name)
         if t is not None:
