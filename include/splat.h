@@ -137,7 +137,8 @@ typedef struct splat_plan {
     size_t off_grad2d;      /* float[slot_cap][9]: moments of dL/dpower over the pixel offsets
                                (x, y, xx, xy, yy, 1), then dL/d(r,g,b)                      */
     size_t off_visbits;     /* u64[V*n_blocks_proj*4]: visible (view, Gaussian) bit masks  */
-    size_t off_dwpart;      /* f64[V][n_blocks_proj][4][12] per-wave W2C gradient partials, then f64[V][32][12] stage sums */
+    size_t off_dwpart;      /* f64[V][n_blocks_proj][4][12] per-wave W2C gradient partials (written for the
+                               waves with a visible Gaussian in the view), then f64[V][32][12] stage sums */
     size_t off_cam;         /* per view f64[8] + f32[20]: camera constants of the projection, then
                                float32 copies of the view matrix and of those constants        */
     int32_t sorted_buf;     /* which of the two key/value buffers holds the sorted result */

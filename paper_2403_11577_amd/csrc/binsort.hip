@@ -345,11 +345,13 @@ constexpr int RS_UKPT = 16;  // keys per thread per upsweep round
 template <typename K>
 __global__ __launch_bounds__(RS_T) void radix_upsweep_kernel(const K *keys, const uint32_t *counts, int cnt_idx,
                                                             int shift, int nparts, uint32_t *hist) {
-    // one LDS histogram per wave, plain LDS atomics (equal digits in a wave serialise in hardware)
-    __shared__ uint32_t h[RS_T / 64][kRadixDigits];
-    const int w = threadIdx.x >> 6;
+    // four LDS histograms per wave, lane l counting into copy l mod 4 (rows one bank apart): equal
+    // digits within a wave, common in the high digits of coherent keys, serialise four times less
+    constexpr int NH = 4 * (RS_T / 64);
+    __shared__ uint32_t h[NH][kRadixDigits + 1];
+    const int w = 4 * (threadIdx.x >> 6) + (threadIdx.x & 3);
     for (int q = 0; q < RS_DPT; ++q)
-        for (int ww = 0; ww < RS_T / 64; ++ww) h[ww][q * RS_T + threadIdx.x] = 0;
+        for (int ww = 0; ww < NH; ++ww) h[ww][q * RS_T + threadIdx.x] = 0;
     __syncthreads();
     uint32_t n = counts[cnt_idx];
     uint32_t b, e;
@@ -370,7 +372,7 @@ __global__ __launch_bounds__(RS_T) void radix_upsweep_kernel(const K *keys, cons
     for (int q = 0; q < RS_DPT; ++q) {
         int d = q * RS_T + threadIdx.x;
         uint32_t c = 0;
-        for (int ww = 0; ww < RS_T / 64; ++ww) c += h[ww][d];
+        for (int ww = 0; ww < NH; ++ww) c += h[ww][d];
         hist[(size_t)d * nparts + blockIdx.x] = c;
     }
 }

@@ -532,9 +532,8 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
         }
         double *part = dwpart + k0 * 12;
         const bool vis = live && ((mask >> lane) & 1ull);
-        if (mask == 0ull) {  // nothing of this wave visible in view v
-            if (lane < 12) part[lane] = 0.0;
-        } else {
+        if (mask != 0ull) {  // otherwise nothing of this wave is visible in view v: no partial (the
+                             // reduction skips it by the same visibility word)
             double gw[12];
             for (int k = 0; k < 12; ++k) gw[k] = 0.0;
             if (vis) {
@@ -573,13 +572,15 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
 // view in order.  DW_S workgroups per view keep the whole chip reading.
 constexpr int DW_S = kDw2cStages;
 
-__global__ __launch_bounds__(256) void dw2c_reduce_kernel(const double *dwpart, int nparts, double *stage) {
+__global__ __launch_bounds__(256) void dw2c_reduce_kernel(const double *dwpart, const uint64_t *visbits, int nparts,
+                                                          double *stage) {
     __shared__ double red[4][12];
     const int s = blockIdx.x, v = blockIdx.y, wv = threadIdx.x >> 6, lane = __lane_id();
     const LaneClass lc(lane);
     double acc[12];
     for (int k = 0; k < 12; ++k) acc[k] = 0.0;
     for (int q = threadIdx.x + 256 * s; q < nparts; q += 256 * DW_S) {
+        if (visbits[(size_t)v * nparts + q] == 0ull) continue;  // a wave with nothing visible wrote none
         const double *p = dwpart + ((size_t)v * nparts + q) * 12;
         for (int k = 0; k < 12; ++k) acc[k] += p[k];
     }
@@ -657,7 +658,8 @@ int launch_project_bwd(const splat_plan &p, void *ws, const splat_gaussians &g, 
     if (rc) return rc;
     // the stage sums sit after the partials (the plan sizes the region for both)
     double *stage = part + (size_t)p.n_views * 4 * nb * 12;
-    hipLaunchKernelGGL(dw2c_reduce_kernel, dim3(DW_S, p.n_views), dim3(256), 0, st, part, 4 * nb, stage);
+    hipLaunchKernelGGL(dw2c_reduce_kernel, dim3(DW_S, p.n_views), dim3(256), 0, st, part,
+                       ws_at<uint64_t>(ws, p.off_visbits), 4 * nb, stage);
     if ((rc = launch_status("dw2c_reduce"))) return rc;
     hipLaunchKernelGGL(dw2c_finish_kernel, dim3(p.n_views), dim3(64), 0, st, stage, dw2c);
     return launch_status("dw2c_finish");
