@@ -122,12 +122,36 @@ __global__ __launch_bounds__(1024) void scan_partials_kernel(uint32_t *partials,
     }
 }
 
+// SELF: the partials are the blocks' plain sums (no scan_partials_kernel): each workgroup adds
+// up those before its own (at most 4 SCAN_T of them), and the one holding the last element
+// writes the total to out[n] and *total_dst.  Otherwise partials[b] is already block b's
+// exclusive prefix.
+template <bool SELF>
 __global__ __launch_bounds__(SCAN_T) void scan_down_kernel(const uint32_t *in, uint32_t *out, const uint32_t *n_dev,
-                                                          int64_t n_cap, const uint32_t *partials) {
-    __shared__ uint32_t lds[4];
+                                                          int64_t n_cap, const uint32_t *partials,
+                                                          uint32_t *total_dst) {
+    __shared__ uint32_t lds[4], lds2[4];
     uint32_t n = load_n(n_dev, n_cap);
     uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    if (SELF && n == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            out[0] = 0u;
+            if (total_dst) *total_dst = 0u;
+        }
+        return;
+    }
     if (base >= n) return;
+    uint32_t pre;
+    if constexpr (SELF) {
+        uint32_t acc = 0;
+        for (int i = threadIdx.x; i < (int)blockIdx.x; i += SCAN_T) acc += partials[i];
+        uint32_t inc = wave_incl_scan(acc);
+        if (__lane_id() == 63) lds2[threadIdx.x >> 6] = inc;
+        __syncthreads();
+        pre = ((lds2[0] + lds2[1]) + lds2[2]) + lds2[3];
+    } else {
+        pre = partials[blockIdx.x];
+    }
     // each thread owns SCAN_ITEMS consecutive elements
     uint64_t t0 = base + (uint64_t)threadIdx.x * SCAN_ITEMS;
     uint32_t v[SCAN_ITEMS];
@@ -138,11 +162,15 @@ __global__ __launch_bounds__(SCAN_T) void scan_down_kernel(const uint32_t *in, u
         s += v[k];
     }
     uint32_t tot;
-    uint32_t ex = block_excl_scan(s, lds, &tot) + partials[blockIdx.x];
+    uint32_t ex = block_excl_scan(s, lds, &tot) + pre;
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         uint64_t i = t0 + k;
         if (i < n) out[i] = ex;
         ex += v[k];
+    }
+    if (SELF && threadIdx.x == 0 && (uint64_t)n <= base + SCAN_TILE) {  // the block holding element n - 1
+        out[n] = pre + tot;
+        if (total_dst) *total_dst = pre + tot;
     }
 }
 
@@ -227,10 +255,18 @@ __global__ __launch_bounds__(256) void run_tiles_kernel(uint32_t *__restrict__ c
     const uint32_t nr = (ns + 63u) / 64u;
     if (blockIdx.x == 0 && threadIdx.x == 0) counts[CNT_RUNS] = nr;
     const int lane = __lane_id();
-    for (uint64_t q = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < nr; q += (uint64_t)gridDim.x * 4) {
-        const uint64_t s = q * 64 + lane;
-        const uint32_t tot = wave_incl_scan(s < ns ? tiles_of(pay[s], pb) : 0u);
-        if (lane == 63) rsum[q] = tot;
+    const uint64_t stride = (uint64_t)gridDim.x * 4;
+    // two runs per step, both payloads loaded before either is used
+    for (uint64_t q = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < nr; q += 2 * stride) {
+        const uint64_t q2 = q + stride;
+        const uint64_t s = q * 64 + lane, s2 = q2 * 64 + lane;
+        const uint64_t p = s < ns ? pay[s] : 0ull, p2 = s2 < ns ? pay[s2] : 0ull;
+        const uint32_t tot = wave_incl_scan(s < ns ? tiles_of(p, pb) : 0u);
+        const uint32_t tot2 = wave_incl_scan(s2 < ns ? tiles_of(p2, pb) : 0u);
+        if (lane == 63) {
+            rsum[q] = tot;
+            if (q2 < nr) rsum[q2] = tot2;
+        }
     }
 }
 
@@ -706,11 +742,17 @@ int launch_scan_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, in
     hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nparts), dim3(SCAN_T), 0, st, in, n_dev, n_cap, partials);
     int rc = launch_status("scan_reduce");
     if (rc) return rc;
+    if (nparts <= 4 * SCAN_T) {  // the down-sweep adds up the block sums before each block itself
+        hipLaunchKernelGGL(scan_down_kernel<true>, dim3((unsigned)nparts), dim3(SCAN_T), 0, st, in, out, n_dev, n_cap,
+                           partials, total_dst);
+        return launch_status("scan_down");
+    }
     hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, st, partials, (int)nparts, out, n_dev, n_cap,
                        total_dst);
     rc = launch_status("scan_partials");
     if (rc) return rc;
-    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nparts), dim3(SCAN_T), 0, st, in, out, n_dev, n_cap, partials);
+    hipLaunchKernelGGL(scan_down_kernel<false>, dim3((unsigned)nparts), dim3(SCAN_T), 0, st, in, out, n_dev, n_cap,
+                       partials, nullptr);
     return launch_status("scan_down");
 }
 
