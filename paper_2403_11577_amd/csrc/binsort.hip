@@ -572,7 +572,9 @@ __global__ __launch_bounds__(RS_T) void radix_downsweep_kernel(const KI *kin, co
 // writes the bounds of the runs that start or end among its four.
 template <typename K>
 __global__ __launch_bounds__(256) void ranges_kernel(const K *__restrict__ keys, const uint32_t *counts,
-                                                    int depth_bits, uint64_t n_tiles, uint2 *__restrict__ ranges) {
+                                                    int depth_bits, uint64_t n_tiles, uint2 *__restrict__ ranges,
+                                                    uint32_t *qh) {
+    if (blockIdx.x == 0 && threadIdx.x < 66) qh[threadIdx.x] = 0u;  // the work queue's counters
     const uint32_t n = counts[CNT_INST];
     const uint64_t ng = ((uint64_t)n + 3) / 4;
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += (uint64_t)gridDim.x * blockDim.x) {
@@ -599,8 +601,10 @@ __global__ __launch_bounds__(256) void ranges_kernel(const K *__restrict__ keys,
 // first (lanes 0 and 63 load theirs).  The walk goes by whole waves, so every lane takes part
 // in the exchanges.
 __global__ __launch_bounds__(256) void ranges_vec_kernel(const uint32_t *__restrict__ keys, const uint32_t *counts,
-                                                        int shift, uint32_t n_tiles, uint2 *__restrict__ ranges) {
+                                                        int shift, uint32_t n_tiles, uint2 *__restrict__ ranges,
+                                                        uint32_t *qh) {
     constexpr uint32_t kNone = 0xFFFFFFFFu;  // past either end; never a tile (n_tiles < 2^31)
+    if (blockIdx.x == 0 && threadIdx.x < 66) qh[threadIdx.x] = 0u;  // the work queue's counters
     const uint32_t n = counts[CNT_INST];
     const uint64_t ng = ((uint64_t)n + 3) / 4;
     const int lane = __lane_id();
@@ -638,7 +642,8 @@ __device__ inline int cost_bucket(uint2 r) {
     return c == 0 ? 0 : 32 - __clz(c);  // 1..32
 }
 
-// hist[64]: [0..32] bucket counts
+// qh[66]: [0..32] bucket counts, [33..65] the running counts of the scatter (zeroed by the
+// ranges kernel)
 __global__ __launch_bounds__(256) void queue_hist_kernel(const uint2 *ranges, int n, uint32_t *qh) {
     __shared__ uint32_t h[33];
     if (threadIdx.x < 33) h[threadIdx.x] = 0;
@@ -649,23 +654,17 @@ __global__ __launch_bounds__(256) void queue_hist_kernel(const uint2 *ranges, in
     if (threadIdx.x < 33 && h[threadIdx.x]) atomicAdd(&qh[threadIdx.x], h[threadIdx.x]);
 }
 
-// descending buckets: cursor[b] = number of items in buckets > b
-__global__ void queue_scan_kernel(uint32_t *qh) {
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int b = 32; b >= 0; --b) {
-            uint32_t c = qh[b];
-            qh[33 + b] = acc;
-            acc += c;
-        }
-    }
-}
-
-// each workgroup reserves one range per bucket with a single global atomic,
-// then places its items with LDS atomics
+// Descending buckets: bucket b starts after the items of the buckets above it (each workgroup
+// adds those counts up itself); each workgroup reserves one range per bucket with a single
+// global atomic on the bucket's running count, then places its items with LDS atomics.
 __global__ __launch_bounds__(256) void queue_scatter_kernel(const uint2 *ranges, int n, uint32_t *qh,
                                                            uint32_t *queue) {
-    __shared__ uint32_t cnt[33], base[33];
+    __shared__ uint32_t cnt[33], base[33], start[33];
+    if (threadIdx.x < 33) {
+        uint32_t acc = 0;
+        for (int b = threadIdx.x + 1; b < 33; ++b) acc += qh[b];
+        start[threadIdx.x] = acc;
+    }
     for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
         if (threadIdx.x < 33) cnt[threadIdx.x] = 0;
         __syncthreads();
@@ -673,7 +672,8 @@ __global__ __launch_bounds__(256) void queue_scatter_kernel(const uint2 *ranges,
         int bk = i < n ? cost_bucket(ranges[i]) : 0;
         uint32_t local = i < n ? atomicAdd(&cnt[bk], 1u) : 0u;
         __syncthreads();
-        if (threadIdx.x < 33 && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&qh[33 + threadIdx.x], cnt[threadIdx.x]);
+        if (threadIdx.x < 33 && cnt[threadIdx.x])
+            base[threadIdx.x] = start[threadIdx.x] + atomicAdd(&qh[33 + threadIdx.x], cnt[threadIdx.x]);
         __syncthreads();
         if (i < n) queue[base[bk] + local] = (uint32_t)i;
         __syncthreads();
@@ -921,21 +921,18 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
     if (rb > 8192) rb = 8192;
     if (kshift >= 0 && (reinterpret_cast<uintptr_t>(ki) & 15u) == 0)
         hipLaunchKernelGGL(ranges_vec_kernel, dim3(rb), dim3(256), 0, st, reinterpret_cast<const uint32_t *>(ki), counts,
-                           p.depth_bits - kshift, (uint32_t)nT, ranges);
+                           p.depth_bits - kshift, (uint32_t)nT, ranges, qh);
     else if (kshift >= 0)
         hipLaunchKernelGGL(ranges_kernel<uint32_t>, dim3(rb), dim3(256), 0, st, reinterpret_cast<const uint32_t *>(ki),
-                           counts, p.depth_bits - kshift, (uint64_t)nT, ranges);
+                           counts, p.depth_bits - kshift, (uint64_t)nT, ranges, qh);
     else
         hipLaunchKernelGGL(ranges_kernel<uint64_t>, dim3(rb), dim3(256), 0, st, ki, counts, p.depth_bits, (uint64_t)nT,
-                           ranges);
+                           ranges, qh);
     if ((rc = launch_status("ranges"))) return rc;
-    if ((rc = launch_fill_u32(qh, 0u, 66, st))) return rc;
     int qb = (nT + 255) / 256;
     if (qb > 1024) qb = 1024;
     hipLaunchKernelGGL(queue_hist_kernel, dim3(qb), dim3(256), 0, st, ranges, nT, qh);
     if ((rc = launch_status("queue_hist"))) return rc;
-    hipLaunchKernelGGL(queue_scan_kernel, dim3(1), dim3(64), 0, st, qh);
-    if ((rc = launch_status("queue_scan"))) return rc;
     hipLaunchKernelGGL(queue_scatter_kernel, dim3(qb), dim3(256), 0, st, ranges, nT, qh, queue);
     if ((rc = launch_status("queue_scatter"))) return rc;
 

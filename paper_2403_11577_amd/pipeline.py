@@ -209,9 +209,10 @@ class Grads:
     delta: torch.Tensor
 
 
-def alloc_grads(ds: DeviceScene, with_mean=False) -> Grads:
+def alloc_grads(ds: DeviceScene, with_mean=False, n_extra64=0) -> Grads:
     """Gradient buffers as views of one float32 and one float64 allocation (each view 256-byte
-    aligned), so that zero_grads clears them with two fills."""
+    aligned), so that zero_grads clears them with two fills.  n_extra64 float64 values more
+    (gr.extra64, cleared with them) hold what a step accumulates besides the gradients."""
     dev = ds.opacity.device
     G, V, Cn = ds.n_gauss, ds.n_views, ds.n_cams
     pad = lambda k, q: -(-k // q) * q
@@ -222,7 +223,7 @@ def alloc_grads(ds: DeviceScene, with_mean=False) -> Grads:
     for r in rows32:
         views.append(f32[o:o + r * G].view(r, G) if r > 1 else f32[o:o + G])
         o += r * Gp
-    n64 = [V * 12, Cn * 6, Cn]
+    n64 = [V * 12, Cn * 6, Cn] + ([n_extra64] if n_extra64 else [])
     f64 = torch.zeros(sum(pad(k, 32) for k in n64), dtype=torch.float64, device=dev)
     o, v64 = 0, []
     for k in n64:
@@ -231,6 +232,7 @@ def alloc_grads(ds: DeviceScene, with_mean=False) -> Grads:
     gr = Grads(views[0], views[1], views[2], views[3], views[4] if with_mean else None,
                v64[0].view(V, 12), v64[1].view(Cn, 6), v64[2])
     gr._flat = (f32, f64)
+    gr.extra64 = v64[3] if n_extra64 else None
     return gr
 
 
@@ -313,15 +315,14 @@ class BatchedStep:
         self.targets = targets.contiguous()
         self.mask = None if mask is None else mask.to(torch.uint8).contiguous()
         self.fr = fr or fit_frame(ds, xi, delta, settings)
-        self.gr = alloc_grads(ds)
+        self.gr = alloc_grads(ds, n_extra64=1)
         self.dimg = torch.empty_like(self.fr.img)
-        self.loss = torch.zeros(1, dtype=torch.float64, device=ds.opacity.device)
+        self.loss = self.gr.extra64  # cleared with the gradients
         self.graph = None
         self.events = None  # optional list of (start, end) event pairs per stage
 
     def run(self):
         fr, ds = self.fr, self.ds
-        self.loss.zero_()
         zero_grads(self.gr)
         pose_fwd(fr, ds, self.xi, self.delta)
         fr.generation += 1
