@@ -308,7 +308,7 @@ __global__ __launch_bounds__(256) void emit_sorted_kernel(const uint32_t *__rest
                                                          const uint64_t *__restrict__ pay, PayBits pb, int tiles_x,
                                                          uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
     __shared__ uint32_t sbeg[4][64];  // per wave: run position of each slot's first instance
-    __shared__ uint64_t spl[4][64];   // per wave: the slots' payloads
+    __shared__ uint4 sinf[4][64];     // per wave: the slots' first tile, rect width, 1 / width, slot id
     const uint32_t ns = counts[CNT_SLOTS];
     const uint32_t ni = counts[CNT_INST];  // <= capacity; only slots wholly below it emit
     const int lane = __lane_id(), w = threadIdx.x >> 6;
@@ -326,22 +326,24 @@ __global__ __launch_bounds__(256) void emit_sorted_kernel(const uint32_t *__rest
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) end = max(end, (uint32_t)__shfl_xor((int)end, d, kWave));
         sbeg[w][lane] = rel;
-        spl[w][lane] = p;
+        const uint32_t wl = (uint32_t)field(p, pb.b0 + pb.tb, pb.b1) + 1u;
+        sinf[w][lane] = make_uint4((uint32_t)field(p, pb.b0, pb.tb), wl, __float_as_uint(__builtin_amdgcn_rcpf((float)wl)),
+                                   (uint32_t)field(p, 0, pb.b0));
         __builtin_amdgcn_wave_barrier();  // one wave: its LDS writes complete before its reads
         for (uint32_t q = lane; q < end; q += 64) {
             int j = 0;  // the last slot whose first instance is at or before q
 #pragma unroll
             for (int step = 32; step > 0; step >>= 1)
                 if (sbeg[w][j + step] <= q) j += step;
-            const uint64_t pj = spl[w][j];
-            const uint32_t wj = (uint32_t)field(pj, pb.b0 + pb.tb, pb.b1) + 1u;
+            const uint4 fj = sinf[w][j];
+            const uint32_t wj = fj.y;
             const uint32_t r = q - sbeg[w][j];
-            uint32_t dy = (uint32_t)((float)r * __builtin_amdgcn_rcpf((float)wj));
+            uint32_t dy = (uint32_t)((float)r * __uint_as_float(fj.z));
             if (dy * wj > r) --dy;           // the float estimate is within one of r / wj
             if ((dy + 1u) * wj <= r) ++dy;
             const uint32_t dx = r - dy * wj;
-            keys[run0 + q] = (uint32_t)field(pj, pb.b0, pb.tb) + dy * (uint32_t)tiles_x + dx;
-            vals[run0 + q] = (uint32_t)field(pj, 0, pb.b0);
+            keys[run0 + q] = fj.x + dy * (uint32_t)tiles_x + dx;
+            vals[run0 + q] = fj.w;
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -459,7 +461,8 @@ __device__ inline void rs_load(const K *kin, const V *vin, uint32_t base, uint32
 // KI keys in, KO keys out: a pass after which every remaining digit lies at or above bit
 // out_shift can write the keys shifted down by out_shift as 32-bit words (the later passes
 // then move 4 bytes less per key, read and written).  V: the values carried along; the key
-// count is counts[cnt_idx].
+// count is counts[cnt_idx].  A null kout moves the values only (a last pass whose keys nothing
+// reads).
 template <typename KI, typename KO, typename V>
 __global__ __launch_bounds__(RS_T) void radix_downsweep_kernel(const KI *kin, const V *vin, KO *kout, V *vout,
                                                               const uint32_t *counts, int cnt_idx, int shift,
@@ -547,7 +550,7 @@ __global__ __launch_bounds__(RS_T) void radix_downsweep_kernel(const KI *kin, co
                 uint32_t d = (uint32_t)(kk >> shift) & kDigitMask;
                 uint32_t dst = gstart[d] + (i - tstart[d]);
                 if (dst < n) {  // always true when both sweeps saw the same keys
-                    kout[dst] = (KO)(kk >> out_shift);
+                    if (kout) kout[dst] = (KO)(kk >> out_shift);
                     vout[dst] = sv[i];
                 }
             }
@@ -807,9 +810,11 @@ int launch_radix_sort_keys(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v
 
 // Stable LSD sort of counts[cnt_idx] u32 keys on bits [0, bits), carrying V values; the result
 // is in the second buffers when *sorted_in_1 (an odd number of passes).
+// keys_out = false: the last pass writes the values only (the sorted keys are left unwritten)
 template <typename V>
 int launch_radix_sort_u32(uint32_t *k0, uint32_t *k1, V *v0, V *v1, const uint32_t *counts, int cnt_idx, int bits,
-                          int nparts, uint32_t *hist, uint32_t *partials, hipStream_t st, int *sorted_in_1) {
+                          int nparts, uint32_t *hist, uint32_t *partials, hipStream_t st, int *sorted_in_1,
+                          bool keys_out = true) {
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
     const int nh = kRadixDigits * nparts;
     uint32_t *ki = k0, *ko = k1;
@@ -821,8 +826,8 @@ int launch_radix_sort_u32(uint32_t *k0, uint32_t *k1, V *v0, V *v1, const uint32
                            nparts, hist);
         if ((rc = launch_status("radix_upsweep"))) return rc;
         if ((rc = launch_scan_u32(hist, hist, nullptr, nh, partials, nullptr, st))) return rc;
-        hipLaunchKernelGGL((radix_downsweep_kernel<uint32_t, uint32_t, V>), dim3(nparts), dim3(RS_T), 0, st, ki, vi, ko,
-                           vo, counts, cnt_idx, shift, 0, nparts, hist);
+        hipLaunchKernelGGL((radix_downsweep_kernel<uint32_t, uint32_t, V>), dim3(nparts), dim3(RS_T), 0, st, ki, vi,
+                           keys_out || ps + 1 < passes ? ko : nullptr, vo, counts, cnt_idx, shift, 0, nparts, hist);
         if ((rc = launch_status("radix_downsweep"))) return rc;
         uint32_t *tk = ki; ki = ko; ko = tk;
         V *tv = vi; vi = vo; vo = tv;
@@ -876,7 +881,7 @@ int launch_bin_sort(const splat_plan &p, void *ws, hipStream_t st) {
         int sin1 = 0;
         rc = launch_radix_sort_u32<uint64_t>(ws_at<uint32_t>(ws, p.off_dkey), ws_at<uint32_t>(ws, p.off_skeys), pay0,
                                              pay1, counts, CNT_SLOTS, p.depth_bits, p.n_sort_blocks, hist, partials, st,
-                                             &sin1);
+                                             &sin1, false);  // only the payloads are read afterwards
         if (rc) return rc;
         const uint64_t *pay = sin1 ? pay1 : pay0;
         hipLaunchKernelGGL(run_tiles_kernel, dim3((eb + 3) / 4), dim3(256), 0, st, counts, pay, pb, soff);
