@@ -125,7 +125,7 @@ typedef struct splat_plan {
     size_t off_view_off;    /* u32[V+1] first slot of every view                          */
     size_t off_blockcnt;    /* u32[V*n_blocks_proj*4+1] visible count per (view, wave), scanned in place to slot offsets */
     size_t off_rec;         /* float4[3][slot_cap]: (mx,my,lx,ly) (a,b,c,o) (r,g,b,depth) */
-    size_t off_meta;        /* int2[slot_cap]: (Gaussian id, view)                       */
+    size_t off_meta;        /* int2[slot_cap]: (Gaussian id, view); see splat_slot_meta  */
     size_t off_rect;        /* u16x4[slot_cap]: tile rect (x0,x1,y0,y1) inclusive (slot_sort 0) */
     size_t off_ntiles;      /* u32[slot_cap+1]: tiles per slot, scanned to offsets (slot_sort 0) */
     size_t off_keys;        /* u64[2][inst_cap] (the sort's last passes keep u32 keys, see key_shift) */
@@ -244,12 +244,24 @@ SPLAT_API int splat_pose_interp_bwd(int32_t K, const double *knot_t, const doubl
  * compacted per view in Gaussian order into slots.
  *   g: Gaussians (device planes); w2c[V][12] float64 (device);
  *   intr[V][4] float64 (fx, fy, cx, cy) per view (device).
- * Writes counts, view_off, rec, meta, the depth fields and, for the bin sort
- * the plan selects, the slot payloads (plan->slot_sort = 1) or the tile rects
- * and counts (0) in the workspace.
+ * Writes counts, view_off, rec, the depth fields and, for the bin sort the
+ * plan selects, the slot payloads (plan->slot_sort = 1) or meta and the tile
+ * rects and counts (0) in the workspace.
  */
 SPLAT_API int splat_project(const splat_plan *plan, void *ws, const splat_gaussians *g, const double *w2c,
                   const double *intr, void *stream);
+
+/*
+ * The (Gaussian id, view) of every slot of the last splat_project on this
+ * workspace, written to meta (int2[slot_cap] at plan->off_meta), for callers
+ * that map slots back to Gaussians (checks, statistics).  The paper has no
+ * passage for it: slots are this library's compaction of the visible pairs
+ * of the projection (Sec. III-B).  The projection stores meta itself only
+ * for plan->slot_sort = 0, whose binning reads it.  Reads the visibility
+ * words and slot offsets the projection left, so call it after that
+ * splat_project and before the next one.
+ */
+SPLAT_API int splat_slot_meta(const splat_plan *plan, void *ws, void *stream);
 
 /*
  * Tile binning (the paper has no passage for it: it is how Phi of Eq. 5 finds

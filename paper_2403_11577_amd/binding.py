@@ -92,6 +92,7 @@ def lib():
     L.splat_pose_interp_bwd.argtypes = [I32, P, P, P, I32, P, P, P, P, I32, P, P, P, P, P, P]
     L.splat_project.argtypes = [C.POINTER(splat_plan), P, C.POINTER(splat_gaussians), P, P, P]
     L.splat_bin_sort.argtypes = [C.POINTER(splat_plan), P, P]
+    L.splat_slot_meta.argtypes = [C.POINTER(splat_plan), P, P]
     L.splat_render_fwd.argtypes = [C.POINTER(splat_plan), P, P, P, P, P]
     L.splat_render_bwd.argtypes = [C.POINTER(splat_plan), P, P, P, P, P]
     L.splat_project_bwd.argtypes = [C.POINTER(splat_plan), P, C.POINTER(splat_gaussians), P, P,
@@ -250,6 +251,10 @@ def splat_project(plan, ws, gauss: splat_gaussians, w2c, intr, stream=None):
     V = int(plan.n_views)
     _check(lib().splat_project(C.byref(plan), _ws(plan, ws), C.byref(gauss), _arg(w2c, "w2c", "f64", 12 * V),
                                _arg(intr, "intr", "f64", 4 * V), _stream(stream)), "splat_project")
+
+
+def splat_slot_meta(plan, ws, stream=None):
+    _check(lib().splat_slot_meta(C.byref(plan), _ws(plan, ws), _stream(stream)), "splat_slot_meta")
 
 
 def splat_bin_sort(plan, ws, stream=None):

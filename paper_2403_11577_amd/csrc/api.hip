@@ -335,6 +335,13 @@ int splat_project(const splat_plan *plan, void *ws, const splat_gaussians *g, co
     return launch_project(*plan, ws, *g, w2c, intr, (hipStream_t)stream);
 }
 
+int splat_slot_meta(const splat_plan *plan, void *ws, void *stream) {
+    g_err[0] = 0;
+    int rc = check_plan(plan, ws, "slot_meta");
+    if (rc) return rc;
+    return launch_slot_meta(*plan, ws, (hipStream_t)stream);
+}
+
 int splat_bin_sort(const splat_plan *plan, void *ws, void *stream) {
     g_err[0] = 0;
     int rc = check_plan(plan, ws, "bin_sort");

@@ -75,6 +75,7 @@ int launch_pose_bwd(int32_t K, const double *kt, const double *kq, const double 
                     const double *R0, const double *t0, const double *xi, const double *delta,
                     int32_t V, const int32_t *vcam, const double *vt, const double *dw2c,
                     double *dxi, double *ddelta, hipStream_t st);
+int launch_slot_meta(const splat_plan &p, void *ws, hipStream_t st);
 int launch_project(const splat_plan &p, void *ws, const splat_gaussians &g, const double *w2c,
                    const double *intr, hipStream_t st);
 int launch_project_bwd(const splat_plan &p, void *ws, const splat_gaussians &g, const double *w2c,

@@ -328,12 +328,12 @@ __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, sp
         rec[3 * slot + 0] = make_float4(mxh, myh, mxl, myl);
         rec[3 * slot + 1] = make_float4((float)P.Q[0], (float)P.Q[1], (float)P.Q[2], gi.o);
         rec[3 * slot + 2] = make_float4(cr, cg, cb, P.depth32);
-        meta[slot] = make_int2((int)i, v);
         dkey[slot] = __float_as_uint(P.depth32) - __float_as_uint((float)S.near_z);
         Rect16 rc;
         rc.x0 = (uint16_t)(P.px0 >> tws); rc.x1 = (uint16_t)(P.px1 >> tws);
         rc.y0 = (uint16_t)(P.py0 >> ths); rc.y1 = (uint16_t)(P.py1 >> ths);
-        if (!sp.spay) {  // the 64-bit instance sort reads the rect and tile count of every slot
+        if (!sp.spay) {  // the 64-bit instance sort reads the rect, tile count and view of every slot
+            meta[slot] = make_int2((int)i, v);
             rect[slot] = rc;
             ntiles[slot] = (uint32_t)(rc.x1 - rc.x0 + 1) * (uint32_t)(rc.y1 - rc.y0 + 1);
         } else {
@@ -346,6 +346,23 @@ __global__ __launch_bounds__(256) void project_write_kernel(splat_settings S, sp
     }
 }
 
+
+// (Gaussian id, view) of every slot, from the visibility words and slot offsets the last
+// projection left (its write pass stores them only for the 64-bit instance sort)
+__global__ __launch_bounds__(256) void slot_meta_kernel(int64_t n, int V, int nb, const uint32_t *waveoff,
+                                                        const uint64_t *visbits, const uint32_t *counts, int2 *meta) {
+    const int b = blockIdx.x, w = threadIdx.x >> 6, lane = __lane_id();
+    const int64_t i = (int64_t)b * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t ns = counts[CNT_SLOTS];
+    for (int v = 0; v < V; ++v) {
+        const size_t k = ((size_t)v * nb + b) * 4 + w;
+        const uint64_t m = visbits[k];
+        if (!((m >> lane) & 1ull)) continue;
+        const uint64_t slot = (uint64_t)waveoff[k] + rank_in(m);
+        if (slot < ns) meta[slot] = make_int2((int)i, v);
+    }
+}
 
 // totals after the (view, wave) count scan: slot count (clamped), view offsets, capacity flag
 __global__ void project_finish_kernel(const uint32_t *waveoff, int V, int nw, int64_t slot_cap, uint32_t *counts,
@@ -639,6 +656,14 @@ int launch_project(const splat_plan &p, void *ws, const splat_gaussians &g, cons
                        SlotPack{p.slot_sort ? ws_at<uint64_t>(ws, p.off_spay) : nullptr, p.pack_bits[0], p.tile_bits,
                                 p.pack_bits[1], p.tiles_x, p.tiles_per_view});
     return launch_status("project_write");
+}
+
+int launch_slot_meta(const splat_plan &p, void *ws, hipStream_t st) {
+    if (p.n_gauss == 0) return 0;
+    hipLaunchKernelGGL(slot_meta_kernel, dim3(p.n_blocks_proj), dim3(256), 0, st, p.n_gauss, p.n_views,
+                       p.n_blocks_proj, ws_at<uint32_t>(ws, p.off_blockcnt), ws_at<uint64_t>(ws, p.off_visbits),
+                       ws_at<uint32_t>(ws, p.off_counts), ws_at<int2>(ws, p.off_meta));
+    return launch_status("slot_meta");
 }
 
 int launch_project_bwd(const splat_plan &p, void *ws, const splat_gaussians &g, const double *w2c,

@@ -157,6 +157,8 @@ class Frame:
         return self.buf("rec", torch.float32, 12 * n).view(n, 12)
 
     def meta(self, n: int) -> torch.Tensor:
+        # (Gaussian id, view) per slot of the last projection, written on demand
+        B.splat_slot_meta(self.plan, self.ws)
         return self.buf("meta", torch.int32, 2 * n).view(n, 2)
 
     def grad2d(self, n: int) -> torch.Tensor:
