@@ -620,6 +620,39 @@ def test_render_fwd_l1_matches_the_separate_calls(tile, roi, masked):
     assert float(loss.item()) == pytest.approx(float(ref_loss.item()), rel=1e-12)
 
 
+def test_slot_meta_matches_the_projections_own_and_a_host_count():
+    """splat_slot_meta: the (Gaussian id, view) of every slot, formed from the visibility words,
+    equals what the projection writes itself for the 64-bit instance sort, and on the slot-first
+    path (where the projection leaves it out) the slots of each view are its visible Gaussians
+    in increasing order, as many as the view's slot range holds."""
+    say("case: splat_slot_meta against the projection's own meta")
+    scene = synth.small_drive(5, n_frames=2)
+    ds = pl.DeviceScene.from_scene(scene)
+    xi, dl = _dev(scene.xi), _dev(scene.delta)
+    fr = pl.fit_frame(ds, xi, dl, pl.make_settings())
+    pl.forward(fr, ds, xi, dl)
+    torch.cuda.synchronize()
+    ns = int(fr.counts()[0])
+    assert ns > 0 and fr.status() == 0
+    slot_meta = fr.meta(ns).cpu().numpy().copy()
+    view_off = fr.buf("view_off", torch.int32, scene.views.n + 1).cpu().numpy()
+    for v in range(scene.views.n):
+        sl = slot_meta[view_off[v]:view_off[v + 1]]
+        assert np.all(sl[:, 1] == v) and np.all(np.diff(sl[:, 0]) > 0)
+        assert np.all((sl[:, 0] >= 0) & (sl[:, 0] < ds.n_gauss))
+    use_instance_sort(fr)
+    raw = fr.buf("meta", torch.int32, 2 * ns)
+    raw.fill_(-7)
+    pl.forward(fr, ds, xi, dl)   # the projection for the instance keys writes meta itself
+    torch.cuda.synchronize()
+    assert fr.status() == 0 and int(fr.counts()[0]) == ns
+    own = raw.cpu().numpy().reshape(ns, 2).copy()
+    assert np.array_equal(own, slot_meta)
+    B.splat_slot_meta(fr.plan, fr.ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(raw.cpu().numpy().reshape(ns, 2), own)
+
+
 def test_bin_sort_after_a_projection_for_the_other_sort_bins_nothing():
     """A projection writes the per-slot inputs of the plan's bin sort only; binning with the other
     sort before projecting again flags SPLAT_ST_SEQUENCE and leaves every tile list empty (the
