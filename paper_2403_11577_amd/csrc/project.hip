@@ -123,6 +123,37 @@ __device__ inline void project_view(const splat_settings &S, const double *M, co
     P.mu[1] = C.fy * uy + C.cy;
 }
 
+// project_view with the conic, as the adjoint needs it: the clamp decisions are taken as the
+// forward takes them (x/z and y/z by division), the Jacobian's entries by one reciprocal of the
+// depth (returned in iz); R, qh and the screen mean are not copied or formed.
+__device__ inline void project_view_adj(const splat_settings &S, const double *M, const CamC &C, const float *x,
+                                        const float *s, const GaussPre &G, Proj &P, double &iz) {
+    const double *R = G.R;
+    double xd[3] = {x[0], x[1], x[2]};
+    for (int i = 0; i < 3; ++i) P.t[i] = M[4 * i] * xd[0] + M[4 * i + 1] * xd[1] + M[4 * i + 2] * xd[2] + M[4 * i + 3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            P.A[3 * i + j] = (M[4 * i] * R[j] + M[4 * i + 1] * R[3 + j] + M[4 * i + 2] * R[6 + j]) * (double)s[j];
+    const double tz = P.t[2];
+    const double ux = P.t[0] / tz, uy = P.t[1] / tz;
+    P.clx = (ux < C.gx0) || (ux > C.gx1);
+    P.cly = (uy < C.gy0) || (uy > C.gy1);
+    P.xh = fmin(fmax(ux, C.gx0), C.gx1);
+    P.yh = fmin(fmax(uy, C.gy0), C.gy1);
+    iz = 1.0 / tz;
+    double *J = P.J;
+    J[0] = C.fx * iz; J[1] = 0.0; J[2] = -C.fx * P.xh * iz;
+    J[3] = 0.0; J[4] = C.fy * iz; J[5] = -C.fy * P.yh * iz;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j)
+            P.T[3 * i + j] = J[3 * i] * P.A[j] + J[3 * i + 1] * P.A[3 + j] + J[3 * i + 2] * P.A[6 + j];
+    const double sxx = P.T[0] * P.T[0] + P.T[1] * P.T[1] + P.T[2] * P.T[2] + S.eps2d;
+    const double sxy = P.T[0] * P.T[3] + P.T[1] * P.T[4] + P.T[2] * P.T[5];
+    const double syy = P.T[3] * P.T[3] + P.T[4] * P.T[4] + P.T[5] * P.T[5] + S.eps2d;
+    const double idet = 1.0 / (sxx * syy - sxy * sxy);
+    P.Q[0] = syy * idet; P.Q[1] = -sxy * idet; P.Q[2] = sxx * idet;
+}
+
 // Pixel rectangle of the alpha >= alpha_min footprint (exact AABB of the ellipse,
 // padded) inside the rendered rows; PC_OFF if it misses them.
 __device__ inline int footprint(const splat_settings &S, double k2, int W, int H, Proj &P) {
@@ -390,9 +421,12 @@ __global__ void project_finish_kernel(const uint32_t *waveoff, int V, int nw, in
 // the pixels), with power = -(a dx^2 + 2 b dx dy + c dy^2)/2 for the conic
 // (a, b, c), so that dL/dmu = (a Mx + b My, b Mx + c My) and
 // dL/d(a, b, c) = (-Mxx/2, -Mxy, -Myy/2).  Adds the quaternion, scale and mean
-// gradients to gq, gs, gm and returns the W2C gradient in gw[12].
-__device__ void slot_adjoint(const Proj &P, const double *M, const CamC &C, const float *x, const float *s,
-                             const float *gd, double *gq, double *gs, double *gm, double *gw) {
+// gradients to gR (dL/dR of the Gaussian's rotation, turned into the quaternion's gradient once
+// per Gaussian after the views: the map from dR to dq depends on the quaternion only), gs, gm
+// and returns the W2C gradient in gw[12].  iz = 1 / t_z (from project_view_adj).
+__device__ void slot_adjoint(const Proj &P, const double *R, const double *M, const CamC &C, const float *x,
+                             const float *s, const float *gd, double iz, double *gRs, double *gs, double *gm,
+                             double *gw) {
     double a = P.Q[0], b = P.Q[1], c = P.Q[2];
     const double Mx = gd[0], My = gd[1];
     double gmx = a * Mx + b * My, gmy = b * Mx + c * My;
@@ -420,7 +454,7 @@ __device__ void slot_adjoint(const Proj &P, const double *M, const CamC &C, cons
     // J(t), mu(t)
     double fx = C.fx, fy = C.fy;
     double tx = P.t[0], ty = P.t[1], tz = P.t[2];
-    double iz = 1.0 / tz, iz2 = iz * iz;
+    double iz2 = iz * iz;
     double gt0 = gmx * fx * iz, gt1 = gmy * fy * iz;
     double gt2 = -(gmx * fx * tx + gmy * fy * ty) * iz2 - (gJ[0] * fx + gJ[4] * fy) * iz2;
     if (!P.clx) {
@@ -437,34 +471,36 @@ __device__ void slot_adjoint(const Proj &P, const double *M, const CamC &C, cons
     }
     double gt[3] = {gt0, gt1, gt2};
     // A = W R D: dW += gA (R D)^T ; dR = W^T gA D ; ds_k = ((W R)^T gA)_kk
-    double gR[9];
     for (int r = 0; r < 3; ++r)
         for (int k = 0; k < 3; ++k) {
             double acc = 0.0;
             for (int m = 0; m < 3; ++m) acc += M[4 * m + r] * gA[3 * m + k];  // (W^T gA)[r][k]
-            gR[3 * r + k] = acc * (double)s[k];
-            gs[k] += P.R[3 * r + k] * acc;  // ((W R)^T gA)_kk = sum_r R[r][k] (W^T gA)[r][k]
+            gRs[3 * r + k] += acc * (double)s[k];
+            gs[k] += R[3 * r + k] * acc;  // ((W R)^T gA)_kk = sum_r R[r][k] (W^T gA)[r][k]
         }
     for (int r = 0; r < 3; ++r)
         for (int k = 0; k < 3; ++k) {
             double acc = 0.0;
-            for (int m = 0; m < 3; ++m) acc += gA[3 * r + m] * P.R[3 * k + m] * (double)s[m];
+            for (int m = 0; m < 3; ++m) acc += gA[3 * r + m] * R[3 * k + m] * (double)s[m];
             gw[4 * r + k] = acc + gt[r] * (double)x[k];
         }
     for (int r = 0; r < 3; ++r) gw[4 * r + 3] = gt[r];
     for (int k = 0; k < 3; ++k) gm[k] += M[k] * gt[0] + M[4 + k] * gt[1] + M[8 + k] * gt[2];
-    // R(q_hat) -> q_hat -> q
-    double w = P.qh[0], qx = P.qh[1], qy = P.qh[2], qz = P.qh[3];
+}
+
+// R(q_hat) -> q_hat -> q: the quaternion gradient of a Gaussian from its summed dL/dR
+__device__ inline void quat_adjoint(const GaussPre &G, const double *gR, double *gq) {
+    double w = G.qh[0], qx = G.qh[1], qy = G.qh[2], qz = G.qh[3];
     double gq0 = 2.0 * (-qz * gR[1] + qy * gR[2] + qz * gR[3] - qx * gR[5] - qy * gR[6] + qx * gR[7]);
     double gq1 = 2.0 * (qy * gR[1] + qz * gR[2] + qy * gR[3] - 2.0 * qx * gR[4] - w * gR[5] + qz * gR[6] + w * gR[7] - 2.0 * qx * gR[8]);
     double gq2 = 2.0 * (-2.0 * qy * gR[0] + qx * gR[1] + w * gR[2] + qx * gR[3] + qz * gR[5] - w * gR[6] + qz * gR[7] - 2.0 * qy * gR[8]);
     double gq3 = 2.0 * (-2.0 * qz * gR[0] - w * gR[1] + qx * gR[2] + w * gR[3] - 2.0 * qz * gR[4] + qy * gR[5] + qx * gR[6] + qy * gR[7]);
     double dot = w * gq0 + qx * gq1 + qy * gq2 + qz * gq3;
-    double iq = 1.0 / P.qn;
-    gq[0] += (gq0 - w * dot) * iq;
-    gq[1] += (gq1 - qx * dot) * iq;
-    gq[2] += (gq2 - qy * dot) * iq;
-    gq[3] += (gq3 - qz * dot) * iq;
+    double iq = 1.0 / G.qn;
+    gq[0] = (gq0 - w * dot) * iq;
+    gq[1] = (gq1 - qx * dot) * iq;
+    gq[2] = (gq2 - qy * dot) * iq;
+    gq[3] = (gq3 - qz * dot) * iq;
 }
 
 // Transposed FP64 reduction of twelve per-lane values over the wave: four
@@ -535,7 +571,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
     const bool live = i < n;
     GaussIn gi;
     if (live) gauss_in(S, g, i, gi);
-    double gq[4] = {0, 0, 0, 0}, gs[3] = {0, 0, 0}, gm[3] = {0, 0, 0}, go = 0.0, gc[3] = {0, 0, 0};
+    double gR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gs[3] = {0, 0, 0}, gm[3] = {0, 0, 0}, go = 0.0, gc[3] = {0, 0, 0};
     size_t k0 = (size_t)b * 4 + wv;  // (view, block, wave) index of view 0
     const size_t kstep = (size_t)nb * 4;
     uint64_t mask = visbits[k0];
@@ -559,13 +595,14 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
                     const double *M = w2c + 12 * v;
                     const CamC C = cam[v];
                     Proj P;
-                    project_view(S, M, C, gi.x, gi.s, gi.G, true, P);
+                    double iz;
+                    project_view_adj(S, M, C, gi.x, gi.s, gi.G, P, iz);
                     const float *gd = grad2d + 9 * slot;
                     go += (double)gd[5] / (double)gi.o;   // gd[5] = sum of dL/dpower = o dL/do
                     gc[0] += gd[6];
                     gc[1] += gd[7];
                     gc[2] += gd[8];
-                    slot_adjoint(P, M, C, gi.x, gi.s, gd, gq, gs, gm, gw);
+                    slot_adjoint(P, gi.G.R, M, C, gi.x, gi.s, gd, iz, gR, gs, gm, gw);
                 }
             }
             double tot = reduce12(gw, lc.c0, lc.c1, lc.c2, lc.c3);
@@ -575,6 +612,8 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, spla
         base = base_n;
     }
     if (!live) return;
+    double gq[4] = {0, 0, 0, 0};
+    if (gi.fin && gi.opac_ok && gi.quat_ok) quat_adjoint(gi.G, gR, gq);  // G is set for these only
     for (int k = 0; k < 4; ++k) dquat[k * n + i] += (float)gq[k];
     for (int k = 0; k < 3; ++k) dscale[k * n + i] += (float)gs[k];
     dopac[i] += (float)go;
