@@ -150,7 +150,9 @@ class Calibrator:
         self.stage = -1
         self.stage_log = []
         self._set_points(full.mean)
-        self.tgt = torch.empty((Bv, 3, full.H, full.W), dtype=torch.float32, device=device)
+        # the batch's targets: only the rows of the region of interest are gathered each step (the
+        # losses read none above it; those rows stay zero)
+        self.tgt = torch.zeros((Bv, 3, full.H, full.W), dtype=torch.float32, device=device)
         # parameters (raw) and their activations
         if cfg.gauss_init == "scene":
             o = full.opacity.clamp(1e-6, 1 - 1e-6)
@@ -438,7 +440,8 @@ class Calibrator:
         torch.index_select(f.view_cam, 0, idx, out=w.view_cam)
         torch.index_select(f.view_t, 0, idx, out=w.view_t)
         torch.index_select(f.intr, 0, idx, out=w.intr)
-        torch.index_select(self.targets, 0, idx, out=self.tgt)
+        r0 = int(self.settings.roi_y0)
+        torch.index_select(self.targets[:, :, r0:, :], 0, idx, out=self.tgt[:, :, r0:, :])
         native = self._native and not cfg.freeze_gaussians
         with torch.no_grad():
             if self.field is None:
