@@ -345,10 +345,8 @@ SPLAT_API int splat_render_bwd(const splat_plan *plan, void *ws, const float *dL
  * gradients it ADDS d(loss)/d quat,
  * scale, opacity, colour and (if dmean != NULL) mean of every Gaussian
  * (float32 device planes of the parameter shapes; the caller zeroes them), and
- * ADDS d(loss)/d w2c[V][12] (float64; caller zeroes).  The projection of each
- * visible pair is formed in float64 as splat_project forms it, the chain rule
- * in float32; the per-wave W2C partials are reduced in float64 in a fixed
- * order, so the result is deterministic.
+ * ADDS d(loss)/d w2c[V][12] (float64, reduced in float64 in a fixed order, so
+ * the result is deterministic; caller zeroes).  The adjoint runs in float64.
  * g, w2c and intr must be the ones given to splat_project.
  */
 SPLAT_API int splat_project_bwd(const splat_plan *plan, void *ws, const splat_gaussians *g,

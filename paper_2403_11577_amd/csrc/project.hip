@@ -123,44 +123,35 @@ __device__ inline void project_view(const splat_settings &S, const double *M, co
     P.mu[1] = C.fy * uy + C.cy;
 }
 
-// What the float32 adjoint chain takes from the float64 projection of a visible pair.
-struct ProjF {
-    float Q[3], T[6], A[9], J0, J2, J4, J5, tx, ty, iz, xh, yh;
-    bool clx, cly;
-};
-
-// The projection of a visible pair for the adjoint, in float64 as project_view forms it (the
-// clamp decisions by division, as the forward takes them; the Jacobian's entries by one
-// reciprocal of the depth), rounded to float32 once at the end.
+// project_view with the conic, as the adjoint needs it: the clamp decisions are taken as the
+// forward takes them (x/z and y/z by division), the Jacobian's entries by one reciprocal of the
+// depth (returned in iz); R, qh and the screen mean are not copied or formed.
 __device__ inline void project_view_adj(const splat_settings &S, const double *M, const CamC &C, const float *x,
-                                        const float *s, const GaussPre &G, ProjF &F) {
+                                        const float *s, const GaussPre &G, Proj &P, double &iz) {
     const double *R = G.R;
-    double xd[3] = {x[0], x[1], x[2]}, t[3], A[9], T[6];
-    for (int i = 0; i < 3; ++i) t[i] = M[4 * i] * xd[0] + M[4 * i + 1] * xd[1] + M[4 * i + 2] * xd[2] + M[4 * i + 3];
+    double xd[3] = {x[0], x[1], x[2]};
+    for (int i = 0; i < 3; ++i) P.t[i] = M[4 * i] * xd[0] + M[4 * i + 1] * xd[1] + M[4 * i + 2] * xd[2] + M[4 * i + 3];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
-            A[3 * i + j] = (M[4 * i] * R[j] + M[4 * i + 1] * R[3 + j] + M[4 * i + 2] * R[6 + j]) * (double)s[j];
-    const double tz = t[2];
-    const double ux = t[0] / tz, uy = t[1] / tz;
-    F.clx = (ux < C.gx0) || (ux > C.gx1);
-    F.cly = (uy < C.gy0) || (uy > C.gy1);
-    const double xh = fmin(fmax(ux, C.gx0), C.gx1), yh = fmin(fmax(uy, C.gy0), C.gy1);
-    const double iz = 1.0 / tz;
-    const double J0 = C.fx * iz, J2 = -C.fx * xh * iz, J4 = C.fy * iz, J5 = -C.fy * yh * iz;
-    for (int j = 0; j < 3; ++j) {
-        T[j] = J0 * A[j] + J2 * A[6 + j];
-        T[3 + j] = J4 * A[3 + j] + J5 * A[6 + j];
-    }
-    const double sxx = T[0] * T[0] + T[1] * T[1] + T[2] * T[2] + S.eps2d;
-    const double sxy = T[0] * T[3] + T[1] * T[4] + T[2] * T[5];
-    const double syy = T[3] * T[3] + T[4] * T[4] + T[5] * T[5] + S.eps2d;
+            P.A[3 * i + j] = (M[4 * i] * R[j] + M[4 * i + 1] * R[3 + j] + M[4 * i + 2] * R[6 + j]) * (double)s[j];
+    const double tz = P.t[2];
+    const double ux = P.t[0] / tz, uy = P.t[1] / tz;
+    P.clx = (ux < C.gx0) || (ux > C.gx1);
+    P.cly = (uy < C.gy0) || (uy > C.gy1);
+    P.xh = fmin(fmax(ux, C.gx0), C.gx1);
+    P.yh = fmin(fmax(uy, C.gy0), C.gy1);
+    iz = 1.0 / tz;
+    double *J = P.J;
+    J[0] = C.fx * iz; J[1] = 0.0; J[2] = -C.fx * P.xh * iz;
+    J[3] = 0.0; J[4] = C.fy * iz; J[5] = -C.fy * P.yh * iz;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j)
+            P.T[3 * i + j] = J[3 * i] * P.A[j] + J[3 * i + 1] * P.A[3 + j] + J[3 * i + 2] * P.A[6 + j];
+    const double sxx = P.T[0] * P.T[0] + P.T[1] * P.T[1] + P.T[2] * P.T[2] + S.eps2d;
+    const double sxy = P.T[0] * P.T[3] + P.T[1] * P.T[4] + P.T[2] * P.T[5];
+    const double syy = P.T[3] * P.T[3] + P.T[4] * P.T[4] + P.T[5] * P.T[5] + S.eps2d;
     const double idet = 1.0 / (sxx * syy - sxy * sxy);
-    F.Q[0] = (float)(syy * idet); F.Q[1] = (float)(-sxy * idet); F.Q[2] = (float)(sxx * idet);
-    for (int k = 0; k < 6; ++k) F.T[k] = (float)T[k];
-    for (int k = 0; k < 9; ++k) F.A[k] = (float)A[k];
-    F.J0 = (float)J0; F.J2 = (float)J2; F.J4 = (float)J4; F.J5 = (float)J5;
-    F.tx = (float)t[0]; F.ty = (float)t[1]; F.iz = (float)iz;
-    F.xh = (float)xh; F.yh = (float)yh;
+    P.Q[0] = syy * idet; P.Q[1] = -sxy * idet; P.Q[2] = sxx * idet;
 }
 
 // Pixel rectangle of the alpha >= alpha_min footprint (exact AABB of the ellipse,
@@ -429,70 +420,69 @@ __global__ void project_finish_kernel(const uint32_t *waveoff, int V, int nw, in
 // dL/dpower over the pixel offsets d = pixel - mu (M. = sum dL/dpower * d. over
 // the pixels), with power = -(a dx^2 + 2 b dx dy + c dy^2)/2 for the conic
 // (a, b, c), so that dL/dmu = (a Mx + b My, b Mx + c My) and
-// dL/d(a, b, c) = (-Mxx/2, -Mxy, -Myy/2).  Adds the rotation, scale and mean gradients to gR
-// (dL/dR, turned into the quaternion's gradient once per Gaussian after the views: the map
-// from dR to dq depends on the quaternion only), gs and gm, and returns the W2C gradient in
-// gw[12].  In float32, from the float64 projection quantities rounded once (project_view_adj):
-// the chain from the slot's float32 moments is a sequence of products and short sums, whose
-// float32 rounding stays far below that of the moments themselves.  The camera matrix is the
-// float32 copy of the view's.
-__device__ void slot_adjoint_f(const ProjF &P, const double *Rd, const CamC &C, const float *x, const float *s,
-                               const float *gd, float *gR, float *gs, float *gm, float *gw) {
-    const float *M = C.m;
-    const float a = P.Q[0], b = P.Q[1], c = P.Q[2];
-    const float Mx = gd[0], My = gd[1];
-    const float gmx = a * Mx + b * My, gmy = b * Mx + c * My;
-    const float ga = -0.5f * gd[2], gb = -gd[3], gc = -0.5f * gd[4];
-    const float hb = 0.5f * gb;
-    const float m00 = a * ga + b * hb, m01 = a * hb + b * gc;
-    const float m10 = b * ga + c * hb, m11 = b * hb + c * gc;
-    const float g2xx = -(m00 * a + m01 * b);
-    const float g2xy = -(m00 * b + m01 * c);
-    const float g2yy = -(m10 * b + m11 * c);
-    const float *T = P.T, *A = P.A;
-    float gT[6], gJ[6], gA[9], R[9];
-    for (int k = 0; k < 9; ++k) R[k] = (float)Rd[k];
+// dL/d(a, b, c) = (-Mxx/2, -Mxy, -Myy/2).  Adds the quaternion, scale and mean
+// gradients to gR (dL/dR of the Gaussian's rotation, turned into the quaternion's gradient once
+// per Gaussian after the views: the map from dR to dq depends on the quaternion only), gs, gm
+// and returns the W2C gradient in gw[12].  iz = 1 / t_z (from project_view_adj).
+__device__ void slot_adjoint(const Proj &P, const double *R, const double *M, const CamC &C, const float *x,
+                             const float *s, const float *gd, double iz, double *gRs, double *gs, double *gm,
+                             double *gw) {
+    double a = P.Q[0], b = P.Q[1], c = P.Q[2];
+    const double Mx = gd[0], My = gd[1];
+    double gmx = a * Mx + b * My, gmy = b * Mx + c * My;
+    double ga = -0.5 * (double)gd[2], gb = -(double)gd[3], gc = -0.5 * (double)gd[4];
+    // conic -> Sigma2: G2 = -Q GQ Q with GQ = [[ga, gb/2], [gb/2, gc]]
+    double hb = 0.5 * gb;
+    double m00 = a * ga + b * hb, m01 = a * hb + b * gc;
+    double m10 = b * ga + c * hb, m11 = b * hb + c * gc;
+    double g2xx = -(m00 * a + m01 * b);
+    double g2xy = -(m00 * b + m01 * c);
+    double g2yy = -(m10 * b + m11 * c);
+    // Sigma2 = T T^T + eps I -> dT = 2 G2 T
+    double gT[6];
     for (int j = 0; j < 3; ++j) {
-        gT[j] = 2.f * (g2xx * T[j] + g2xy * T[3 + j]);
-        gT[3 + j] = 2.f * (g2xy * T[j] + g2yy * T[3 + j]);
+        gT[j] = 2.0 * (g2xx * P.T[j] + g2xy * P.T[3 + j]);
+        gT[3 + j] = 2.0 * (g2xy * P.T[j] + g2yy * P.T[3 + j]);
     }
+    // T = J A -> dJ = gT A^T, dA = J^T gT
+    double gJ[6], gA[9];
     for (int r = 0; r < 2; ++r)
-        for (int k = 0; k < 3; ++k) gJ[3 * r + k] = gT[3 * r] * A[3 * k] + gT[3 * r + 1] * A[3 * k + 1] + gT[3 * r + 2] * A[3 * k + 2];
-    const float J0 = P.J0, J2 = P.J2, J4 = P.J4, J5 = P.J5;
-    for (int r = 0; r < 3; ++r) {
-        const float jx = r == 0 ? J0 : (r == 2 ? J2 : 0.f), jy = r == 1 ? J4 : (r == 2 ? J5 : 0.f);
-        for (int k = 0; k < 3; ++k) gA[3 * r + k] = jx * gT[k] + jy * gT[3 + k];
-    }
-    const float fx = C.fxf, fy = C.fyf;
-    const float tx = P.tx, ty = P.ty;
-    const float iz = P.iz, iz2 = iz * iz;
-    float gt0 = gmx * fx * iz, gt1 = gmy * fy * iz;
-    float gt2 = -(gmx * fx * tx + gmy * fy * ty) * iz2 - (gJ[0] * fx + gJ[4] * fy) * iz2;
+        for (int k = 0; k < 3; ++k)
+            gJ[3 * r + k] = gT[3 * r] * P.A[3 * k] + gT[3 * r + 1] * P.A[3 * k + 1] + gT[3 * r + 2] * P.A[3 * k + 2];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) gA[3 * r + k] = P.J[r] * gT[k] + P.J[3 + r] * gT[3 + k];
+    // J(t), mu(t)
+    double fx = C.fx, fy = C.fy;
+    double tx = P.t[0], ty = P.t[1], tz = P.t[2];
+    double iz2 = iz * iz;
+    double gt0 = gmx * fx * iz, gt1 = gmy * fy * iz;
+    double gt2 = -(gmx * fx * tx + gmy * fy * ty) * iz2 - (gJ[0] * fx + gJ[4] * fy) * iz2;
     if (!P.clx) {
         gt0 += -gJ[2] * fx * iz2;
-        gt2 += 2.f * gJ[2] * fx * tx * iz2 * iz;
+        gt2 += 2.0 * gJ[2] * fx * tx * iz2 * iz;
     } else {
         gt2 += gJ[2] * fx * P.xh * iz2;
     }
     if (!P.cly) {
         gt1 += -gJ[5] * fy * iz2;
-        gt2 += 2.f * gJ[5] * fy * ty * iz2 * iz;
+        gt2 += 2.0 * gJ[5] * fy * ty * iz2 * iz;
     } else {
         gt2 += gJ[5] * fy * P.yh * iz2;
     }
-    const float gt[3] = {gt0, gt1, gt2};
+    double gt[3] = {gt0, gt1, gt2};
+    // A = W R D: dW += gA (R D)^T ; dR = W^T gA D ; ds_k = ((W R)^T gA)_kk
     for (int r = 0; r < 3; ++r)
         for (int k = 0; k < 3; ++k) {
-            float acc = 0.f;
+            double acc = 0.0;
             for (int m = 0; m < 3; ++m) acc += M[4 * m + r] * gA[3 * m + k];  // (W^T gA)[r][k]
-            gR[3 * r + k] += acc * s[k];
-            gs[k] += R[3 * r + k] * acc;
+            gRs[3 * r + k] += acc * (double)s[k];
+            gs[k] += R[3 * r + k] * acc;  // ((W R)^T gA)_kk = sum_r R[r][k] (W^T gA)[r][k]
         }
     for (int r = 0; r < 3; ++r)
         for (int k = 0; k < 3; ++k) {
-            float acc = 0.f;
-            for (int m = 0; m < 3; ++m) acc += gA[3 * r + m] * R[3 * k + m] * s[m];
-            gw[4 * r + k] = acc + gt[r] * x[k];
+            double acc = 0.0;
+            for (int m = 0; m < 3; ++m) acc += gA[3 * r + m] * R[3 * k + m] * (double)s[m];
+            gw[4 * r + k] = acc + gt[r] * (double)x[k];
         }
     for (int r = 0; r < 3; ++r) gw[4 * r + 3] = gt[r];
     for (int k = 0; k < 3; ++k) gm[k] += M[k] * gt[0] + M[4 + k] * gt[1] + M[8 + k] * gt[2];
@@ -548,33 +538,6 @@ __device__ inline double reduce12(const double (&v)[12], bool c0, bool c1, bool 
     return e;
 }
 
-// reduce12 on float32 values
-template <int CTRL>
-__device__ __forceinline__ float dpp_fl(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
-}
-
-template <int CTRL>
-__device__ __forceinline__ float xpair_fl(float lo, float hi, bool c) {
-    float keep = c ? hi : lo, send = c ? lo : hi;
-    return keep + dpp_fl<CTRL>(send);
-}
-
-template <int CTRL>
-__device__ __forceinline__ float xpad_fl(float v) { return v + dpp_fl<CTRL>(v); }
-
-__device__ inline float reduce12f(const float (&v)[12], bool c0, bool c1, bool c2, bool c3) {
-    float a0 = xpair_fl<0xB1>(v[0], v[1], c0), a1 = xpair_fl<0xB1>(v[2], v[3], c0);
-    float a2 = xpair_fl<0xB1>(v[4], v[5], c0), a3 = xpair_fl<0xB1>(v[6], v[7], c0);
-    float a4 = xpair_fl<0xB1>(v[8], v[9], c0), a5 = xpair_fl<0xB1>(v[10], v[11], c0);
-    float b0 = xpair_fl<0x4E>(a0, a1, c1), b1 = xpair_fl<0x4E>(a2, a3, c1), b2 = xpair_fl<0x4E>(a4, a5, c1);
-    float d0 = xpair_fl<0x141>(b0, b1, c2), d1 = xpad_fl<0x141>(b2);
-    float e = xpair_fl<0x140>(d0, d1, c3);
-    e += __shfl_xor(e, 16, kWave);
-    e += __shfl_xor(e, 32, kWave);
-    return e;
-}
-
 struct LaneClass {
     bool c0, c1, c2, c3;
     int cls;
@@ -592,15 +555,14 @@ struct LaneClass {
 // The W2C gradient of each view is reduced over the workgroup in float64 and
 // stored as the workgroup's partial; dw2c_reduce_kernel sums the partials of a
 // view in a fixed order (deterministic, no contended float64 atomics).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void project_bwd_kernel(splat_settings S, splat_gaussians g, const double *w2c,
+__global__ __launch_bounds__(256) void project_bwd_kernel(splat_settings S, splat_gaussians g, const double *w2c,
                                                          const CamC *cam, int V, int nb, const uint32_t *waveoff,
                                                          const uint64_t *visbits, int64_t slot_cap,
                                                          const float *grad2d, float *dquat, float *dscale,
                                                          float *dopac, float *dcolor, float *dmean, double *dwpart) {
     // Every wave walks the views on its own (no workgroup barrier in the loop), writing its
-    // W2C partial per view (the wave's float32 sum, stored in float64 for the fixed-order
-    // reduction); the next view's visibility word and slot base are loaded while the current
-    // view is processed.  Three waves per SIMD (168 VGPRs, a few spilled) beat two.
+    // FP64 W2C partial per view; the next view's visibility word and slot base are loaded
+    // while the current view is processed.
     const int b = blockIdx.x, wv = threadIdx.x >> 6, lane = __lane_id();
     const LaneClass lc(lane);
     const bool writer = lane < 16 && lc.cls < 12;
@@ -609,7 +571,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
     const bool live = i < n;
     GaussIn gi;
     if (live) gauss_in(S, g, i, gi);
-    float gR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gs[3] = {0, 0, 0}, gm[3] = {0, 0, 0}, go = 0.f, gc[3] = {0, 0, 0};
+    double gR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gs[3] = {0, 0, 0}, gm[3] = {0, 0, 0}, go = 0.0, gc[3] = {0, 0, 0};
     size_t k0 = (size_t)b * 4 + wv;  // (view, block, wave) index of view 0
     const size_t kstep = (size_t)nb * 4;
     uint64_t mask = visbits[k0];
@@ -625,36 +587,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
         const bool vis = live && ((mask >> lane) & 1ull);
         if (mask != 0ull) {  // otherwise nothing of this wave is visible in view v: no partial (the
                              // reduction skips it by the same visibility word)
-            float gw[12];
-            for (int k = 0; k < 12; ++k) gw[k] = 0.f;
+            double gw[12];
+            for (int k = 0; k < 12; ++k) gw[k] = 0.0;
             if (vis) {
                 uint64_t slot = (uint64_t)base + rank_in(mask);
                 if (slot < (uint64_t)slot_cap) {
                     const double *M = w2c + 12 * v;
                     const CamC C = cam[v];
-                    ProjF P;
-                    project_view_adj(S, M, C, gi.x, gi.s, gi.G, P);
+                    Proj P;
+                    double iz;
+                    project_view_adj(S, M, C, gi.x, gi.s, gi.G, P, iz);
                     const float *gd = grad2d + 9 * slot;
-                    go += gd[5] / gi.o;   // gd[5] = sum of dL/dpower = o dL/do
+                    go += (double)gd[5] / (double)gi.o;   // gd[5] = sum of dL/dpower = o dL/do
                     gc[0] += gd[6];
                     gc[1] += gd[7];
                     gc[2] += gd[8];
-                    slot_adjoint_f(P, gi.G.R, C, gi.x, gi.s, gd, gR, gs, gm, gw);
+                    slot_adjoint(P, gi.G.R, M, C, gi.x, gi.s, gd, iz, gR, gs, gm, gw);
                 }
             }
-            float tot = reduce12f(gw, lc.c0, lc.c1, lc.c2, lc.c3);
-            if (writer) part[lc.cls] = (double)tot;
+            double tot = reduce12(gw, lc.c0, lc.c1, lc.c2, lc.c3);
+            if (writer) part[lc.cls] = tot;
         }
         mask = mask_n;
         base = base_n;
     }
     if (!live) return;
     double gq[4] = {0, 0, 0, 0};
-    if (gi.fin && gi.opac_ok && gi.quat_ok) {  // G is set for these only
-        double gRd[9];
-        for (int k = 0; k < 9; ++k) gRd[k] = gR[k];
-        quat_adjoint(gi.G, gRd, gq);
-    }
+    if (gi.fin && gi.opac_ok && gi.quat_ok) quat_adjoint(gi.G, gR, gq);  // G is set for these only
     for (int k = 0; k < 4; ++k) dquat[k * n + i] += (float)gq[k];
     for (int k = 0; k < 3; ++k) dscale[k * n + i] += (float)gs[k];
     dopac[i] += (float)go;
