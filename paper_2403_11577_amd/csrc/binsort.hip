@@ -41,6 +41,22 @@ __device__ inline uint32_t dpp_add(uint32_t x) {
     return x + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, BC);
 }
 
+// inclusive prefix maximum over the wave, same pattern (lanes without a source see 0)
+template <int CTRL, int ROWS, bool BC>
+__device__ inline uint32_t dpp_max(uint32_t x) {
+    return max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, BC));
+}
+
+__device__ inline uint32_t wave_incl_max(uint32_t x) {
+    x = dpp_max<0x111, 0xF, true>(x);
+    x = dpp_max<0x112, 0xF, true>(x);
+    x = dpp_max<0x114, 0xF, true>(x);
+    x = dpp_max<0x118, 0xF, true>(x);
+    x = dpp_max<0x142, 0xA, false>(x);
+    x = dpp_max<0x143, 0xC, false>(x);
+    return x;
+}
+
 __device__ inline uint32_t wave_incl_scan(uint32_t x) {
     x = dpp_add<0x111, 0xF, true>(x);  // row_shr:1
     x = dpp_add<0x112, 0xF, true>(x);  // row_shr:2
@@ -300,14 +316,17 @@ __global__ __launch_bounds__(64) void run_finish_kernel(const uint32_t *roff, co
 
 // one instance per (slot, covered tile) in depth order: key view * T + tile (u32), value slot.
 // A wave takes a run of 64 consecutive slots; their instances form one run of the output from
-// the run's offset, which the lanes write in turn (coalesced stores, and no lane waits for a
-// large slot of another): run position q belongs to the last of the 64 slots that starts at or
-// before q.
+// the run's offset, which the lanes write in turn, 64 positions at a time (coalesced stores,
+// and no lane waits for a large slot of another): run position q belongs to the last slot with
+// instances that starts at or before q.  Per window of 64 positions, each such slot that starts
+// inside it marks its start, and a prefix maximum over the wave (carried from the window
+// before) names every position's slot.
 __global__ __launch_bounds__(256) void emit_sorted_kernel(const uint32_t *__restrict__ counts,
                                                          const uint32_t *__restrict__ roff,
                                                          const uint64_t *__restrict__ pay, PayBits pb, int tiles_x,
                                                          uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
     __shared__ uint32_t sbeg[4][64];  // per wave: run position of each slot's first instance
+    __shared__ uint32_t smark[4][64];  // per wave and window: 1 + the slot starting at each position
     __shared__ uint4 sinf[4][64];     // per wave: the slots' first tile, rect width, 1 / width, slot id
     const uint32_t ns = counts[CNT_SLOTS];
     const uint32_t ni = counts[CNT_INST];  // <= capacity; only slots wholly below it emit
@@ -330,11 +349,18 @@ __global__ __launch_bounds__(256) void emit_sorted_kernel(const uint32_t *__rest
         sinf[w][lane] = make_uint4((uint32_t)field(p, pb.b0, pb.tb), wl, __float_as_uint(__builtin_amdgcn_rcpf((float)wl)),
                                    (uint32_t)field(p, 0, pb.b0));
         __builtin_amdgcn_wave_barrier();  // one wave: its LDS writes complete before its reads
-        for (uint32_t q = lane; q < end; q += 64) {
-            int j = 0;  // the last slot whose first instance is at or before q
-#pragma unroll
-            for (int step = 32; step > 0; step >>= 1)
-                if (sbeg[w][j + step] <= q) j += step;
+        uint32_t carry = 0;  // 1 + the slot of the position before the window
+        for (uint32_t q0 = 0; q0 < end; q0 += 64) {
+            smark[w][lane] = 0u;
+            __builtin_amdgcn_wave_barrier();
+            if (nt && rel - q0 < 64u) smark[w][rel - q0] = (uint32_t)lane + 1u;  // unsigned: earlier starts fail
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t own = max(wave_incl_max(smark[w][lane]), carry);
+            carry = (uint32_t)__builtin_amdgcn_readlane((int)own, 63);
+            __builtin_amdgcn_wave_barrier();  // every mark read before the next window clears them
+            const uint32_t q = q0 + lane;
+            if (q >= end) continue;
+            const int j = (int)own - 1;
             const uint4 fj = sinf[w][j];
             const uint32_t wj = fj.y;
             const uint32_t r = q - sbeg[w][j];
